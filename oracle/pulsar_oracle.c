@@ -1,0 +1,356 @@
+/*
+ * FP64 brute-force oracle for the sphere renderer of Pulsar (Lassner and
+ * Zollhoefer, "Pulsar: Efficient Sphere-based Neural Rendering").
+ *
+ * TEST INFRASTRUCTURE. Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark load this library. It shares no code, header, table or
+ * constant with the HIP renderer, and the renderer never calls it.
+ *
+ * What it computes (paper Sec. 3.1, Sec. 3.2 Eq. 1, App. A):
+ *   scene S = {(p_i, f_i, r_i, o_i)}; camera x_cam = R x_world + t, pinhole with
+ *   focal length f and sensor width s, principal point at the sensor centre.
+ *   For every pixel ray and EVERY sphere (no binning, no culling structure):
+ *     w_i = o_i d_i exp(o_i z_i / gamma) / (exp(eps/gamma) + sum_k o_k d_k exp(o_k z_k / gamma))
+ *     F   = sum_i w_i f_i + exp(eps/gamma) / (...) * background
+ *   The sum runs over all spheres the ray intersects.
+ *
+ * Readings of points the paper leaves open:
+ *   - pixel (row i, col j) centre on the plane z = f at
+ *       x_s = (j + 1/2) s/W - s/2,  y_s = (i + 1/2) s/W - (s H/W)/2,
+ *     camera axes x right, y down, z forward; unit ray u = (x_s, y_s, f)/|.|.
+ *   - the intersection depth is the distance along u to the FRONT intersection,
+ *     t = b - sqrt(R^2 - q^2) with b = u.c, d = c - b u, q = |d|;
+ *     a hit needs q < R and t <= far.
+ *   - z = (far - t)/(far - near) in [0, 1], 0 at the far plane (Sec. 3.2).
+ *   - d_i is used as delta = 1 - min(1, q/R): the weight is largest on the
+ *     ray through the centre and falls continuously to 0 at the silhouette.
+ *   - a sphere takes part iff its inputs are finite, r > 0 and c_z - R >= near.
+ *   - optional minimum size (App. B, Step 0): R = max(r, rho c_z / f), with
+ *     rho = min_radius_px * pitch; off when min_radius_px = 0.
+ *   - gradients flow through the first min(K, #hits) hits of a pixel in
+ *     ascending (t, sphere index) order (App. B, Step 2 and backward prep);
+ *     the image blends every hit (Sec. 2, point-based representations: an
+ *     unlimited number of spheres colour a pixel, the first few get gradients).
+ *   - the sums are shifted by m = max(eps/gamma, max_i o_i z_i / gamma), which
+ *     leaves Eq. 1 unchanged and keeps exp() finite down to gamma = 1e-5.
+ *
+ * All arithmetic is IEEE double. Threads split work over pixels in the
+ * forward; the backward accumulates serially in pixel order, so it is
+ * deterministic.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORACLE_OK 0
+#define ORACLE_BAD_ARG -1
+#define ORACLE_NEG_OPACITY -2
+
+/* cam[16] = R (row-major 9), t (3), f, s, near, far */
+typedef struct {
+  double R[9], t[3];
+  double f, s, znear, zfar;
+  int W, H;
+  double pitch, sh;
+} camera_t;
+
+typedef struct {
+  double c[3];  /* camera-space centre */
+  double R;     /* effective radius */
+  int take_part;
+  int clamped;  /* effective radius comes from the minimum size */
+} sphere_cam_t;
+
+typedef struct {
+  double t;
+  int k;
+} hit_key_t;
+
+static void make_camera(camera_t* cam, const double* c16, int W, int H) {
+  memcpy(cam->R, c16, 9 * sizeof(double));
+  memcpy(cam->t, c16 + 9, 3 * sizeof(double));
+  cam->f = c16[12];
+  cam->s = c16[13];
+  cam->znear = c16[14];
+  cam->zfar = c16[15];
+  cam->W = W;
+  cam->H = H;
+  cam->pitch = cam->s / (double)W;
+  cam->sh = cam->s * (double)H / (double)W;
+}
+
+/* unit ray through the centre of pixel (i, j) */
+static void pixel_ray(const camera_t* cam, int i, int j, double u[3]) {
+  double xs = (j + 0.5) * cam->pitch - 0.5 * cam->s;
+  double ys = (i + 0.5) * cam->pitch - 0.5 * cam->sh;
+  double len = sqrt(xs * xs + ys * ys + cam->f * cam->f);
+  u[0] = xs / len;
+  u[1] = ys / len;
+  u[2] = cam->f / len;
+}
+
+static void sphere_to_camera(const camera_t* cam, const double* pos, double r, double o,
+                             double min_radius_px, sphere_cam_t* sc) {
+  for (int a = 0; a < 3; ++a)
+    sc->c[a] = cam->R[3 * a + 0] * pos[0] + cam->R[3 * a + 1] * pos[1] +
+               cam->R[3 * a + 2] * pos[2] + cam->t[a];
+  double rmin = min_radius_px * cam->pitch * sc->c[2] / cam->f;
+  sc->clamped = (min_radius_px > 0.0) && (rmin > r);
+  sc->R = sc->clamped ? rmin : r;
+  int finite = isfinite(pos[0]) && isfinite(pos[1]) && isfinite(pos[2]) && isfinite(r) &&
+               isfinite(o);
+  sc->take_part = finite && r > 0.0 && (sc->c[2] - sc->R >= cam->znear);
+}
+
+/* Ray-sphere test along unit direction u. Returns 1 on a hit and fills
+ * t (front intersection distance), q (distance of the centre from the ray),
+ * b (projection of the centre on the ray) and d (vector from the ray to the centre). */
+static int ray_sphere(const camera_t* cam, const double u[3], const sphere_cam_t* sc,
+                      double* t, double* q, double* b, double d[3]) {
+  if (!sc->take_part) return 0;
+  double bb = u[0] * sc->c[0] + u[1] * sc->c[1] + u[2] * sc->c[2];
+  double dd[3] = {sc->c[0] - bb * u[0], sc->c[1] - bb * u[1], sc->c[2] - bb * u[2]};
+  double qq = sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+  if (!(qq < sc->R)) return 0;
+  double tt = bb - sqrt(sc->R * sc->R - qq * qq);
+  if (!(tt <= cam->zfar)) return 0;
+  *t = tt;
+  *q = qq;
+  *b = bb;
+  d[0] = dd[0];
+  d[1] = dd[1];
+  d[2] = dd[2];
+  return 1;
+}
+
+static int cmp_hit(const void* pa, const void* pb) {
+  const hit_key_t* a = (const hit_key_t*)pa;
+  const hit_key_t* b = (const hit_key_t*)pb;
+  if (a->t < b->t) return -1;
+  if (a->t > b->t) return 1;
+  return (a->k > b->k) - (a->k < b->k);
+}
+
+static sphere_cam_t* transform_all(const camera_t* cam, int n, const double* pos,
+                                   const double* radius, const double* opacity,
+                                   double min_radius_px) {
+  sphere_cam_t* sc = (sphere_cam_t*)malloc(sizeof(sphere_cam_t) * (size_t)(n > 0 ? n : 1));
+  if (!sc) return NULL;
+  for (int k = 0; k < n; ++k)
+    sphere_to_camera(cam, pos + 3 * (size_t)k, radius[k], opacity ? opacity[k] : 1.0,
+                     min_radius_px, &sc[k]);
+  return sc;
+}
+
+/*
+ * Forward pass over the pixels of the listed rows (all rows when rows == NULL).
+ *   F [H,W,C], L [H,W] (log of the Eq. 1 denominator, L = m + ln D),
+ *   nhits [H,W], klist_t / klist_id [H,W,K] (ascending (t, index); id -1 and
+ *   t = +inf where a pixel has fewer than K hits), t_next [H,W] (distance of
+ *   hit K+1, +inf if none), ambiguous [H,W] (1 when hit K and hit K+1 are
+ *   closer than amb_rel * t_K, which makes the K-set sensitive to rounding).
+ * Entries of rows that are not listed are left untouched.
+ */
+int oracle_forward(int n, int C, const double* pos, const double* radius, const double* opacity,
+                   const double* payload, const double* bg, const double* cam16, int W, int H,
+                   double gamma, double eps, double min_radius_px, int K, double amb_rel,
+                   int n_rows, const int* rows, double* F, double* L, int* nhits,
+                   double* klist_t, int* klist_id, double* t_next, uint8_t* ambiguous,
+                   int n_threads) {
+  if (n < 0 || C < 1 || W < 1 || H < 1 || K < 1 || !(gamma > 0.0)) return ORACLE_BAD_ARG;
+  if (n > 0 && (!pos || !radius || !payload)) return ORACLE_BAD_ARG;
+  if (opacity)
+    for (int k = 0; k < n; ++k)
+      if (opacity[k] < 0.0) return ORACLE_NEG_OPACITY;
+  camera_t cam;
+  make_camera(&cam, cam16, W, H);
+  sphere_cam_t* sc = transform_all(&cam, n, pos, radius, opacity, min_radius_px);
+  if (!sc) return ORACLE_BAD_ARG;
+  int nr = rows ? n_rows : H;
+  long long npix = (long long)nr * W;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+#pragma omp parallel
+  {
+    hit_key_t* hits = (hit_key_t*)malloc(sizeof(hit_key_t) * (size_t)(n > 0 ? n : 1));
+    double* acc = (double*)malloc(sizeof(double) * (size_t)C);
+#pragma omp for schedule(dynamic, 16)
+    for (long long pix = 0; pix < npix; ++pix) {
+      int i = rows ? rows[pix / W] : (int)(pix / W);
+      int j = (int)(pix % W);
+      size_t p = (size_t)i * W + j;
+      double u[3];
+      pixel_ray(&cam, i, j, u);
+      /* collect every intersected sphere */
+      int nh = 0;
+      double m = eps / gamma;
+      for (int k = 0; k < n; ++k) {
+        double t, q, b, d[3];
+        if (ray_sphere(&cam, u, &sc[k], &t, &q, &b, d)) {
+          hits[nh].t = t;
+          hits[nh].k = k;
+          ++nh;
+          double o = opacity ? opacity[k] : 1.0;
+          double z = (cam.zfar - t) / (cam.zfar - cam.znear);
+          double s = o * z / gamma;
+          if (s > m) m = s;
+        }
+      }
+      /* Eq. 1 with all hits, shifted by m */
+      double wbg = exp(eps / gamma - m);
+      double D = wbg;
+      for (int c = 0; c < C; ++c) acc[c] = wbg * bg[c];
+      for (int h = 0; h < nh; ++h) {
+        int k = hits[h].k;
+        double t = 0.0, q = 0.0, b = 0.0, d[3];
+        ray_sphere(&cam, u, &sc[k], &t, &q, &b, d);
+        double o = opacity ? opacity[k] : 1.0;
+        double z = (cam.zfar - t) / (cam.zfar - cam.znear);
+        double delta = 1.0 - q / sc[k].R;
+        double a = o * delta * exp(o * z / gamma - m);
+        D += a;
+        for (int c = 0; c < C; ++c) acc[c] += a * payload[(size_t)k * C + c];
+      }
+      for (int c = 0; c < C; ++c) F[p * C + c] = acc[c] / D;
+      L[p] = m + log(D);
+      /* the K nearest hits in ascending (t, index) */
+      qsort(hits, (size_t)nh, sizeof(hit_key_t), cmp_hit);
+      nhits[p] = nh;
+      for (int r = 0; r < K; ++r) {
+        klist_t[p * K + r] = r < nh ? hits[r].t : INFINITY;
+        klist_id[p * K + r] = r < nh ? hits[r].k : -1;
+      }
+      t_next[p] = nh > K ? hits[K].t : INFINITY;
+      ambiguous[p] = (nh > K) && (hits[K].t - hits[K - 1].t < amb_rel * hits[K - 1].t);
+    }
+    free(hits);
+    free(acc);
+  }
+  free(sc);
+  return ORACLE_OK;
+}
+
+/*
+ * Backward pass for upstream dLoss/dF = G [H,W,C] over the listed rows, using
+ * F, L and the K-lists of oracle_forward. Derivatives of Eq. 1 (in the
+ * readings above) with respect to the camera-space centre c, the effective
+ * radius, opacity and features of each sphere in a pixel's K-list, then chained
+ * to world position (dLoss/dp = R^T dLoss/dc) and radius. Outputs are overwritten.
+ * grad_opacity may be NULL (no opacity input).
+ */
+int oracle_backward(int n, int C, const double* pos, const double* radius, const double* opacity,
+                    const double* payload, const double* bg, const double* cam16, int W, int H,
+                    double gamma, double eps, double min_radius_px, int K, int n_rows,
+                    const int* rows, const double* G, const double* F, const double* L,
+                    const int* klist_id, double* grad_pos, double* grad_radius,
+                    double* grad_opacity, double* grad_payload, double* grad_bg) {
+  (void)bg;
+  if (n < 0 || C < 1 || W < 1 || H < 1 || K < 1 || !(gamma > 0.0)) return ORACLE_BAD_ARG;
+  camera_t cam;
+  make_camera(&cam, cam16, W, H);
+  sphere_cam_t* sc = transform_all(&cam, n, pos, radius, opacity, min_radius_px);
+  double* gc = (double*)calloc((size_t)(n > 0 ? n : 1) * 3, sizeof(double));
+  double* gR = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+  if (!sc || !gc || !gR) return ORACLE_BAD_ARG;
+  memset(grad_pos, 0, sizeof(double) * 3 * (size_t)n);
+  memset(grad_radius, 0, sizeof(double) * (size_t)n);
+  if (grad_opacity) memset(grad_opacity, 0, sizeof(double) * (size_t)n);
+  memset(grad_payload, 0, sizeof(double) * (size_t)n * C);
+  memset(grad_bg, 0, sizeof(double) * (size_t)C);
+  int nr = rows ? n_rows : H;
+  const double span = cam.zfar - cam.znear;
+  for (int ri = 0; ri < nr; ++ri) {
+    int i = rows ? rows[ri] : ri;
+    for (int j = 0; j < W; ++j) {
+      size_t p = (size_t)i * W + j;
+      const double* Gp = G + p * C;
+      const double* Fp = F + p * C;
+      /* background weight exp(eps/gamma) / denominator */
+      double wbg = exp(eps / gamma - L[p]);
+      for (int c = 0; c < C; ++c) grad_bg[c] += wbg * Gp[c];
+      double u[3];
+      pixel_ray(&cam, i, j, u);
+      for (int r = 0; r < K; ++r) {
+        int k = klist_id[p * K + r];
+        if (k < 0) break;
+        double t = 0.0, q = 0.0, b = 0.0, d[3];
+        if (!ray_sphere(&cam, u, &sc[k], &t, &q, &b, d)) continue; /* cannot happen */
+        double o = opacity ? opacity[k] : 1.0;
+        double Rk = sc[k].R;
+        double z = (cam.zfar - t) / span;
+        double delta = 1.0 - q / Rk;
+        double ex = exp(o * z / gamma - L[p]); /* exp(s) / denominator */
+        double e = delta * ex;                 /* d w / d o-linear factor */
+        double w = o * e;                      /* blending weight w_k of Eq. 1 */
+        double h = 0.0;                        /* G . (f_k - F) */
+        for (int c = 0; c < C; ++c) h += Gp[c] * (payload[(size_t)k * C + c] - Fp[c]);
+        for (int c = 0; c < C; ++c) grad_payload[(size_t)k * C + c] += w * Gp[c];
+        if (grad_opacity) grad_opacity[k] += e * h * (1.0 + o * z / gamma);
+        double g_t = -(w * h * o / gamma) / span; /* dLoss/dt */
+        double g_delta = o * ex * h;              /* dLoss/d delta */
+        double root = sqrt(Rk * Rk - q * q);
+        for (int a = 0; a < 3; ++a) {
+          double dt_dc = u[a] + d[a] / root;               /* t = b - sqrt(R^2 - q^2) */
+          double ddelta_dc = q > 0.0 ? -d[a] / (q * Rk) : 0.0; /* delta = 1 - q/R */
+          gc[3 * (size_t)k + a] += g_t * dt_dc + g_delta * ddelta_dc;
+        }
+        gR[k] += g_t * (-Rk / root) + g_delta * (q / (Rk * Rk));
+      }
+    }
+  }
+  for (int k = 0; k < n; ++k) {
+    double g[3] = {gc[3 * (size_t)k], gc[3 * (size_t)k + 1], gc[3 * (size_t)k + 2]};
+    if (sc[k].clamped) {
+      /* R = rho c_z / f depends on the depth, not on r */
+      g[2] += gR[k] * min_radius_px * cam.pitch / cam.f;
+      grad_radius[k] = 0.0;
+    } else {
+      grad_radius[k] = gR[k];
+    }
+    /* c = R p + t  =>  dLoss/dp = R^T dLoss/dc */
+    for (int a = 0; a < 3; ++a)
+      grad_pos[3 * (size_t)k + a] =
+          cam.R[0 * 3 + a] * g[0] + cam.R[1 * 3 + a] * g[1] + cam.R[2 * 3 + a] * g[2];
+  }
+  free(sc);
+  free(gc);
+  free(gR);
+  return ORACLE_OK;
+}
+
+/*
+ * Per-sphere intersection dump for one pixel: hit [n] (0/1), t, q, b [n]
+ * (valid where hit), and the camera-space centre c [n,3] and effective radius
+ * [n] of every sphere.
+ */
+int oracle_pixel_hits(int n, const double* pos, const double* radius, const double* opacity,
+                      const double* cam16, int W, int H, double min_radius_px, int i, int j,
+                      uint8_t* hit, double* t_out, double* q_out, double* b_out, double* c_out,
+                      double* reff_out, double* u_out) {
+  if (n < 0 || W < 1 || H < 1 || i < 0 || i >= H || j < 0 || j >= W) return ORACLE_BAD_ARG;
+  camera_t cam;
+  make_camera(&cam, cam16, W, H);
+  double u[3];
+  pixel_ray(&cam, i, j, u);
+  for (int a = 0; a < 3; ++a) u_out[a] = u[a];
+  for (int k = 0; k < n; ++k) {
+    sphere_cam_t sc;
+    sphere_to_camera(&cam, pos + 3 * (size_t)k, radius[k], opacity ? opacity[k] : 1.0,
+                     min_radius_px, &sc);
+    double t = NAN, q = NAN, b = NAN, d[3];
+    hit[k] = (uint8_t)ray_sphere(&cam, u, &sc, &t, &q, &b, d);
+    t_out[k] = t;
+    q_out[k] = q;
+    b_out[k] = b;
+    for (int a = 0; a < 3; ++a) c_out[3 * (size_t)k + a] = sc.c[a];
+    reff_out[k] = sc.R;
+  }
+  return ORACLE_OK;
+}
+
+int oracle_version(void) { return 1; }
