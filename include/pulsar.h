@@ -1,0 +1,168 @@
+/*
+ * pulsar.h - C ABI of the MI355X (gfx950) sphere renderer.
+ *
+ * The renderer implements the differentiable sphere-based projection step of
+ * Pulsar (Lassner and Zollhoefer): a scene of spheres (position p_i, payload
+ * f_i of C channels, radius r_i, opacity o_i; paper Sec. 3.1) is rendered by a
+ * pinhole camera (R, t and the intrinsics focal length and sensor width;
+ * Sec. 3.2) into a C-channel feature image F whose pixels blend every
+ * intersected sphere with the weights of Eq. 1 (Sec. 3.2). The backward pass
+ * returns the gradients of a scalar loss with respect to position, radius,
+ * opacity, payload and background, given dLoss/dF; gradients flow through the
+ * K nearest hits of each pixel (App. B, Step 2 and "Preparing for the backward
+ * pass"; Sec. 2 on blending all spheres but differentiating the first few).
+ *
+ * Conventions shared by every entry point:
+ *   - Camera frame: x right, y down, z forward; x_cam = R x_world + t.
+ *     Pixel (row i, column j) looks through the sensor point
+ *     ((j + 1/2) s/W - s/2, (i + 1/2) s/W - (s H/W)/2, f): square pixels of
+ *     pitch s/W, principal point at the sensor centre.
+ *   - The depth of a hit is the distance along the unit pixel ray to the
+ *     front intersection, t in [znear, zfar]; z = (zfar - t)/(zfar - znear) is
+ *     the [0, 1] depth of Eq. 1 with 0 at the far plane (Sec. 3.2).
+ *   - The normalised distance d_i of Eq. 1 enters as 1 - q/R, q the distance
+ *     of the sphere centre from the ray: 1 on the central ray, 0 at the
+ *     silhouette.
+ *   - A sphere takes part iff its inputs are finite, r > 0 and its camera-space
+ *     depth satisfies c_z - R >= znear. A hit needs q < R and t <= zfar.
+ *   - The background is blended with weight exp(eps/gamma) (Sec. 3.2).
+ *   - Array pointers are DEVICE pointers to row-major, densely packed float32
+ *     data owned by the caller. The library never allocates device memory and
+ *     never synchronises the stream, except pulsar_query_status.
+ *   - All work is enqueued on `stream` (a hipStream_t, NULL = null stream).
+ *     Inputs must stay valid and unmodified until the work has finished.
+ *   - Every return value is PULSAR_OK (0) or a negative PULSAR_ERR_* code. All
+ *     argument checks run on the host before anything is enqueued.
+ */
+#ifndef PULSAR_H_
+#define PULSAR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PULSAR_OK 0
+/* a required pointer is NULL, a size or parameter is out of range */
+#define PULSAR_ERR_INVALID_ARGUMENT (-1)
+/* ws_bytes is smaller than pulsar_workspace_size() */
+#define PULSAR_ERR_WORKSPACE (-2)
+/* a flag or size this build does not implement */
+#define PULSAR_ERR_UNSUPPORTED (-3)
+/* a HIP launch or runtime call failed */
+#define PULSAR_ERR_HIP (-4)
+/* reported by pulsar_query_status only: the (tile, sphere) pairs of the last
+ * forward did not fit into max_pairs; its outputs are invalid */
+#define PULSAR_ERR_CAPACITY (-5)
+
+/* Pinhole camera (Sec. 3.2, Lst. 1: focal length f and sensor width s share
+ * one unit). Host struct, passed by pointer. */
+typedef struct pulsar_camera {
+  float R[9];          /* row-major world-to-camera rotation */
+  float t[3];          /* translation: x_cam = R x_world + t */
+  float focal;         /* f > 0 */
+  float sensor_width;  /* s > 0; pitch = s / width */
+  float znear;         /* > 0; spheres must lie beyond it (c_z - R >= znear) */
+  float zfar;          /* > znear; hits beyond it are ignored */
+  int32_t width;       /* W in [1, 65535] */
+  int32_t height;      /* H in [1, 65535] */
+} pulsar_camera_t;
+
+/* Render parameters (host struct). */
+typedef struct pulsar_params {
+  float gamma;          /* blending softness of Eq. 1, in [1e-5, 1] (Sec. 3.2) */
+  float eps;            /* background offset of Eq. 1, >= 0, typically 1e-5 */
+  float min_radius_px;  /* >= 0. When > 0 a sphere is drawn at least this many
+                           pixels wide in radius: R = max(r, min_radius_px * pitch * c_z / f)
+                           (App. B, Step 0). 0 = off. */
+  int32_t K;            /* nearest hits per pixel that receive gradients, 1..32 */
+  uint32_t flags;       /* reserved, must be 0 */
+  int32_t max_pairs;    /* capacity of (screen tile, sphere) pairs; 0 = default
+                           (4 n + number of tiles + 65536) */
+  int32_t depth_bits;   /* depth quantisation of the sort key; 0 = automatic.
+                           Changes only the summation order, not the result. */
+  int32_t reserved;     /* must be 0 */
+} pulsar_params_t;
+
+/* Bytes of device workspace one pulsar_fwd / pulsar_bwd pair needs for n
+ * spheres, a width x height image and C channels. Host-only arithmetic.
+ * Returns 0 for invalid arguments. A workspace sized for n works for any
+ * smaller sphere count with the same image size and parameters. */
+size_t pulsar_workspace_size(int32_t n, int32_t width, int32_t height, int32_t C,
+                             const pulsar_params_t* params);
+
+/* Forward pass (Eq. 1 over all hits; App. B, Steps 0-2).
+ *   pos [n,3], radius [n]      sphere centres (world) and radii
+ *   opacity [n] or NULL        NULL means o = 1 for every sphere; o >= 0 is a
+ *                              precondition and is not checked on the device
+ *   payload [n,C]              feature vector f_i of every sphere, C >= 1
+ *   background [C]             background feature
+ *   image [H,W,C]  (out)       F, channels last
+ *   aux [H,W]      (out)       per-pixel L = log of the Eq. 1 denominator,
+ *                              needed by pulsar_bwd; may be NULL if no backward
+ *                              pass follows
+ *   ws, ws_bytes               caller-owned device workspace; after the call it
+ *                              holds the sorted tile lists that pulsar_bwd reuses
+ * n = 0 is valid and renders the background. Outputs must not alias inputs. */
+int pulsar_fwd(const float* pos, const float* radius, const float* opacity,
+               const float* payload, int32_t n, int32_t C, const float* background,
+               const pulsar_camera_t* cam, const pulsar_params_t* params, float* image,
+               float* aux, void* ws, size_t ws_bytes, void* stream);
+
+/* Backward pass (App. B, "The Backward Pass"): given grad_image = dLoss/dF
+ * [H,W,C], writes (overwrites, never accumulates)
+ *   grad_pos [n,3], grad_radius [n], grad_opacity [n], grad_payload [n,C],
+ *   grad_background [C].
+ * Any output may be NULL when that gradient is not needed (Sec. App. B: only
+ * required gradients are computed); grad_opacity must be NULL when opacity is.
+ * Scene, camera, params, image and aux must be exactly those of the preceding
+ * pulsar_fwd on the same workspace, with no other call on that workspace in
+ * between. The per-pixel hits are recomputed from the workspace's sorted tile
+ * lists; nothing per pixel beyond image and aux is stored. */
+int pulsar_bwd(const float* pos, const float* radius, const float* opacity,
+               const float* payload, int32_t n, int32_t C, const float* background,
+               const pulsar_camera_t* cam, const pulsar_params_t* params, const float* image,
+               const float* aux, const float* grad_image, float* grad_pos, float* grad_radius,
+               float* grad_opacity, float* grad_payload, float* grad_background, void* ws,
+               size_t ws_bytes, void* stream);
+
+/* Synchronises `stream` and reports the status the device wrote into the
+ * workspace during the last pulsar_fwd: PULSAR_OK or PULSAR_ERR_CAPACITY.
+ * If pairs is not NULL it receives the number of (tile, sphere) pairs that
+ * forward produced. */
+int pulsar_query_status(const void* ws, size_t ws_bytes, void* stream, int64_t* pairs);
+
+/* Static English description of a status code. Never NULL. */
+const char* pulsar_status_string(int code);
+
+/* Message of the last PULSAR_ERR_HIP raised by this thread, or "". */
+const char* pulsar_last_hip_error(void);
+
+/* Stage timing, a profiling aid. While enabled (process-wide), every
+ * pulsar_fwd / pulsar_bwd records a pair of HIP events on its stream around
+ * each stage below; pulsar_timing_read waits for the recorded events and adds
+ * their elapsed times per stage into total_ms[PULSAR_NUM_STAGES] and the
+ * number of timed launches into counts[PULSAR_NUM_STAGES] (either may be
+ * NULL), then forgets them. Enabling costs one event pair per stage and call;
+ * it never changes results. pulsar_timing_enable returns the previous state. */
+#define PULSAR_STAGE_PROJECT 0    /* K1: projection, culling, sphere records */
+#define PULSAR_STAGE_BINNING 1    /* K2-K5: pair scan, emission, radix sort, tile ranges */
+#define PULSAR_STAGE_RASTER_FWD 2 /* K6: per-tile forward blend */
+#define PULSAR_STAGE_ZERO 3       /* clearing of the gradient outputs */
+#define PULSAR_STAGE_RASTER_BWD 4 /* K7: per-tile backward with recomputed hits */
+#define PULSAR_STAGE_FINALIZE 5   /* K8: world-space gradients, background sum */
+#define PULSAR_NUM_STAGES 6
+int pulsar_timing_enable(int on);
+int pulsar_timing_read(double* total_ms, int64_t* counts);
+const char* pulsar_stage_name(int stage);
+
+/* ABI version of this header, currently 1. */
+int pulsar_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PULSAR_H_ */

@@ -68,6 +68,8 @@ typedef struct {
 typedef struct {
   double t;
   int k;
+  int is_hit;     /* 1: a hit; 0: a near miss kept only for the ambiguity flag */
+  int uncertain;  /* within rounding distance of the silhouette or the far plane */
 } hit_key_t;
 
 static void make_camera(camera_t* cam, const double* c16, int W, int H) {
@@ -127,6 +129,21 @@ static int ray_sphere(const camera_t* cam, const double u[3], const sphere_cam_t
   return 1;
 }
 
+/* Distance along u to the point of closest approach when the ray misses the
+ * sphere by less than rel * R (q in [R, R (1 + rel))); used only to flag
+ * pixels whose K nearest hits could change under float32 rounding. */
+static int near_miss(const camera_t* cam, const double u[3], const sphere_cam_t* sc, double rel,
+                     double* t) {
+  if (!sc->take_part) return 0;
+  double bb = u[0] * sc->c[0] + u[1] * sc->c[1] + u[2] * sc->c[2];
+  double dd[3] = {sc->c[0] - bb * u[0], sc->c[1] - bb * u[1], sc->c[2] - bb * u[2]};
+  double qq = sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+  if (!(qq >= sc->R && qq < sc->R * (1.0 + rel))) return 0;
+  if (!(bb <= cam->zfar * (1.0 + rel))) return 0;
+  *t = bb;
+  return 1;
+}
+
 static int cmp_hit(const void* pa, const void* pb) {
   const hit_key_t* a = (const hit_key_t*)pa;
   const hit_key_t* b = (const hit_key_t*)pb;
@@ -151,8 +168,12 @@ static sphere_cam_t* transform_all(const camera_t* cam, int n, const double* pos
  *   F [H,W,C], L [H,W] (log of the Eq. 1 denominator, L = m + ln D),
  *   nhits [H,W], klist_t / klist_id [H,W,K] (ascending (t, index); id -1 and
  *   t = +inf where a pixel has fewer than K hits), t_next [H,W] (distance of
- *   hit K+1, +inf if none), ambiguous [H,W] (1 when hit K and hit K+1 are
- *   closer than amb_rel * t_K, which makes the K-set sensitive to rounding).
+ *   hit K+1, +inf if none), ambiguous [H,W].
+ * A pixel is ambiguous when float32 rounding could change its K nearest hits:
+ * hit K and hit K+1 lie closer than amb_rel * t_K, or, among the first K+1
+ * entries of the depth-sorted list of hits and near misses, one lies within
+ * amb_rel of the silhouette (1 - q/R < amb_rel or a miss by less than
+ * amb_rel R) or of the far plane. It only serves the parity harness.
  * Entries of rows that are not listed are left untouched.
  */
 int oracle_forward(int n, int C, const double* pos, const double* radius, const double* opacity,
@@ -194,11 +215,25 @@ int oracle_forward(int n, int C, const double* pos, const double* radius, const 
         if (ray_sphere(&cam, u, &sc[k], &t, &q, &b, d)) {
           hits[nh].t = t;
           hits[nh].k = k;
+          hits[nh].is_hit = 1;
+          hits[nh].uncertain = (1.0 - q / sc[k].R < amb_rel) || (t > cam.zfar * (1.0 - amb_rel));
           ++nh;
           double o = opacity ? opacity[k] : 1.0;
           double z = (cam.zfar - t) / (cam.zfar - cam.znear);
           double s = o * z / gamma;
           if (s > m) m = s;
+        }
+      }
+      /* near misses go after the hits; the blend below reads only hits[0 .. nh) */
+      int nall = nh;
+      for (int k = 0; k < n; ++k) {
+        double t;
+        if (near_miss(&cam, u, &sc[k], amb_rel, &t)) {
+          hits[nall].t = t;
+          hits[nall].k = k;
+          hits[nall].is_hit = 0;
+          hits[nall].uncertain = 1;
+          ++nall;
         }
       }
       /* Eq. 1 with all hits, shifted by m */
@@ -219,14 +254,30 @@ int oracle_forward(int n, int C, const double* pos, const double* radius, const 
       for (int c = 0; c < C; ++c) F[p * C + c] = acc[c] / D;
       L[p] = m + log(D);
       /* the K nearest hits in ascending (t, index) */
-      qsort(hits, (size_t)nh, sizeof(hit_key_t), cmp_hit);
+      qsort(hits, (size_t)nall, sizeof(hit_key_t), cmp_hit);
       nhits[p] = nh;
-      for (int r = 0; r < K; ++r) {
-        klist_t[p * K + r] = r < nh ? hits[r].t : INFINITY;
-        klist_id[p * K + r] = r < nh ? hits[r].k : -1;
+      int r = 0;
+      double tk = INFINITY, tk1 = INFINITY;
+      for (int h = 0; h < nall; ++h) {
+        if (!hits[h].is_hit) continue;
+        if (r < K) {
+          klist_t[p * K + r] = hits[h].t;
+          klist_id[p * K + r] = hits[h].k;
+          tk = hits[h].t;
+        } else if (r == K) {
+          tk1 = hits[h].t;
+        }
+        ++r;
       }
-      t_next[p] = nh > K ? hits[K].t : INFINITY;
-      ambiguous[p] = (nh > K) && (hits[K].t - hits[K - 1].t < amb_rel * hits[K - 1].t);
+      for (; r < K; ++r) {
+        klist_t[p * K + r] = INFINITY;
+        klist_id[p * K + r] = -1;
+      }
+      t_next[p] = tk1;
+      int amb = (nh > K) && (tk1 - tk < amb_rel * tk);
+      if (nall > K)
+        for (int h = 0; h <= K && h < nall; ++h) amb |= hits[h].uncertain;
+      ambiguous[p] = (uint8_t)amb;
     }
     free(hits);
     free(acc);

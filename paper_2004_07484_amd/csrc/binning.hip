@@ -1,0 +1,247 @@
+// Tile binning: K2 scan of per-sphere tile counts, K3 emission of
+// (tile, depth) keys, K4 LSD radix sort, K5 per-tile ranges.
+//
+// The paper sorts all spheres by their earliest possible hit depth and then
+// filters them per image region (App. B, Step 0 and Step 1). Here the same
+// order is reached in one structure: every (tile, sphere) pair gets the key
+// tile << depth_bits | quantised depth, and a stable radix sort leaves each
+// tile's spheres contiguous and in near-to-far order.
+#include "device_common.h"
+#include "pulsar_internal.h"
+
+namespace pulsar {
+
+// ---------------------------------------------------------------- K2 scan
+// Single block: exclusive scan of the per-block sums in place; writes the
+// total pair count and the capacity status.
+__global__ __launch_bounds__(kScanThreads) void k_scan_partials(
+    unsigned long long* __restrict__ partials, int nblk, long long cap,
+    Status* __restrict__ status) {
+  __shared__ unsigned long long s_wave[kScanThreads / kWave];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  unsigned long long carry = 0;
+  for (int base = 0; base < nblk; base += kScanThreads) {
+    const int i = base + tid;
+    const unsigned long long v = i < nblk ? partials[i] : 0ull;
+    const unsigned long long incl = wave_incl_scan_u64(v, lane);
+    if (lane == kWave - 1) s_wave[wid] = incl;
+    __syncthreads();
+    unsigned long long before = 0, total = 0;
+    for (int w = 0; w < kScanThreads / kWave; ++w) {
+      const unsigned long long x = s_wave[w];
+      if (w < wid) before += x;
+      total += x;
+    }
+    if (i < nblk) partials[i] = carry + before + incl - v;
+    carry += total;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    status->pairs = carry;
+    status->used = uint32_t(carry < (unsigned long long)cap ? carry : (unsigned long long)cap);
+    status->code = carry > (unsigned long long)cap ? uint32_t(-PULSAR_ERR_CAPACITY) : 0u;
+  }
+}
+
+// ---------------------------------------------------------------- K3 emit
+// Block b re-scans the tile counts of its spheres and writes one
+// (key, sphere id) pair per touched tile, dropping pairs beyond capacity.
+__global__ __launch_bounds__(kProjectBlock) void k_emit(
+    int n, const uint32_t* __restrict__ counts, const ushort4* __restrict__ trect,
+    const uint32_t* __restrict__ qdepth, const unsigned long long* __restrict__ partials,
+    int tiles_x, int depth_bits, long long cap, uint32_t* __restrict__ keys,
+    uint32_t* __restrict__ vals) {
+  __shared__ unsigned long long s_wave[kProjectBlock / kWave];
+  const int i = blockIdx.x * kProjectBlock + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const uint32_t c = i < n ? counts[i] : 0u;
+  const unsigned long long incl = wave_incl_scan_u64(c, lane);
+  if (lane == kWave - 1) s_wave[wid] = incl;
+  __syncthreads();
+  unsigned long long before = partials[blockIdx.x];
+  for (int w = 0; w < wid; ++w) before += s_wave[w];
+  if (c == 0) return;
+  unsigned long long at = before + incl - c;
+  const ushort4 tr = trect[i];
+  const uint32_t q = qdepth[i];
+  for (int ty = tr.y; ty <= tr.w; ++ty) {
+    for (int tx = tr.x; tx <= tr.z; ++tx, ++at) {
+      if (at >= (unsigned long long)cap) return;
+      const uint32_t tile = uint32_t(ty) * uint32_t(tiles_x) + uint32_t(tx);
+      keys[at] = (tile << depth_bits) | q;
+      vals[at] = uint32_t(i);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- K4 sort
+// LSD radix sort, 8-bit digits, three kernels per pass:
+//   hist:    per-block digit counts, digit-major [digit][block]
+//   scan:    one block per digit, exclusive scan over blocks + digit total
+//   scatter: stable rank inside the block, then write to the global slot
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(
+    const uint32_t* __restrict__ keys, const Status* __restrict__ status, int shift,
+    int nblk_cap, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t s_h[kSortRadix];
+  const int tid = threadIdx.x;
+  s_h[tid] = 0;
+  __syncthreads();
+  const uint32_t used = status->used;
+  const size_t base = size_t(blockIdx.x) * kSortBlock;
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const size_t idx = base + size_t(r) * kSortThreads + tid;
+    if (idx < used) atomicAdd(&s_h[(keys[idx] >> shift) & (kSortRadix - 1)], 1u);
+  }
+  __syncthreads();
+  hist[size_t(tid) * nblk_cap + blockIdx.x] = s_h[tid];
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_scan(uint32_t* __restrict__ hist,
+                                                            const Status* __restrict__ status,
+                                                            int nblk_cap,
+                                                            uint32_t* __restrict__ dtot) {
+  __shared__ uint32_t s_wave[kSortThreads / kWave];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  const uint32_t used = status->used;
+  const int nblk = int((used + kSortBlock - 1) / kSortBlock);
+  uint32_t* row = hist + size_t(blockIdx.x) * nblk_cap;
+  uint32_t carry = 0;
+  for (int base = 0; base < nblk; base += kSortThreads) {
+    const int i = base + tid;
+    const uint32_t v = i < nblk ? row[i] : 0u;
+    const uint32_t incl = wave_incl_scan_u32(v, lane);
+    if (lane == kWave - 1) s_wave[wid] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int w = 0; w < kSortThreads / kWave; ++w) {
+      const uint32_t x = s_wave[w];
+      if (w < wid) before += x;
+      total += x;
+    }
+    if (i < nblk) row[i] = carry + before + incl - v;
+    carry += total;
+    __syncthreads();
+  }
+  if (tid == 0) dtot[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
+    const uint32_t* __restrict__ keys_in, const uint32_t* __restrict__ vals_in,
+    const Status* __restrict__ status, int shift, int nblk_cap,
+    const uint32_t* __restrict__ hist, const uint32_t* __restrict__ dtot,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+  __shared__ uint32_t s_base[kSortRadix];                      // next free slot per digit
+  __shared__ uint32_t s_cnt[kSortThreads / kWave][kSortRadix];  // per-wave digit counts
+  __shared__ uint32_t s_wave[kSortThreads / kWave];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  const uint32_t used = status->used;
+  const size_t base = size_t(blockIdx.x) * kSortBlock;
+  if (base >= used) return;  // whole block is past the end (uniform)
+  // exclusive scan of the digit totals gives each digit's global start
+  {
+    const uint32_t v = dtot[tid];
+    const uint32_t incl = wave_incl_scan_u32(v, lane);
+    if (lane == kWave - 1) s_wave[wid] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int w = 0; w < wid; ++w) before += s_wave[w];
+    s_base[tid] = before + incl - v + hist[size_t(tid) * nblk_cap + blockIdx.x];
+#pragma unroll
+    for (int w = 0; w < kSortThreads / kWave; ++w) s_cnt[w][tid] = 0;
+  }
+  __syncthreads();
+  for (int r = 0; r < kSortRounds; ++r) {
+    const size_t idx = base + size_t(r) * kSortThreads + tid;
+    const bool valid = idx < used;
+    const uint32_t key = valid ? keys_in[idx] : 0u;
+    const uint32_t val = valid ? vals_in[idx] : 0u;
+    const uint32_t d = (key >> shift) & (kSortRadix - 1);
+    // lanes of this wave holding the same digit (valid lanes only)
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t m = __ballot((d >> b) & 1u);
+      peers &= ((d >> b) & 1u) ? m : ~m;
+    }
+    const uint32_t below = uint32_t(__popcll(peers & lanemask_lt(lane)));
+    if (valid && below == 0) s_cnt[wid][d] = uint32_t(__popcll(peers));
+    __syncthreads();
+    if (valid) {
+      uint32_t rank = s_base[d] + below;
+      for (int w = 0; w < wid; ++w) rank += s_cnt[w][d];
+      keys_out[rank] = key;
+      vals_out[rank] = val;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int w = 0; w < kSortThreads / kWave; ++w) {
+      add += s_cnt[w][tid];
+      s_cnt[w][tid] = 0;
+    }
+    s_base[tid] += add;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- K5 ranges
+// ranges[t] = first sorted position whose tile is >= t (binary search);
+// ranges[T] = number of stored pairs.
+__global__ void k_tile_ranges(const uint32_t* __restrict__ keys,
+                              const Status* __restrict__ status, int T, int depth_bits,
+                              uint32_t* __restrict__ ranges) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > T) return;
+  const uint32_t used = status->used;
+  if (t == T) {
+    ranges[t] = used;
+    return;
+  }
+  uint32_t lo = 0, hi = used;
+  while (lo < hi) {
+    const uint32_t mid = lo + (hi - lo) / 2;
+    if ((keys[mid] >> depth_bits) < uint32_t(t))
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  ranges[t] = lo;
+}
+
+void launch_binning(const Plan& q, char* ws, hipStream_t stream) {
+  Status* status = ws_ptr<Status>(ws, q.off_status);
+  auto* partials = ws_ptr<unsigned long long>(ws, q.off_partials);
+  uint32_t* kA = ws_ptr<uint32_t>(ws, q.off_keysA);
+  uint32_t* vA = ws_ptr<uint32_t>(ws, q.off_valsA);
+  uint32_t* kB = ws_ptr<uint32_t>(ws, q.off_keysB);
+  uint32_t* vB = ws_ptr<uint32_t>(ws, q.off_valsB);
+  uint32_t* hist = ws_ptr<uint32_t>(ws, q.off_hist);
+  uint32_t* dtot = ws_ptr<uint32_t>(ws, q.off_dtot);
+  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, stream, partials,
+                     q.nblk_proj, (long long)q.cap, status);
+  if (q.n > 0)
+    hipLaunchKernelGGL(k_emit, dim3(q.nblk_proj), dim3(kProjectBlock), 0, stream, int(q.n),
+                       ws_ptr<uint32_t>(ws, q.off_counts), ws_ptr<ushort4>(ws, q.off_trect),
+                       ws_ptr<uint32_t>(ws, q.off_qdepth), partials, int(q.tiles_x),
+                       q.depth_bits, (long long)q.cap, kA, vA);
+  for (int p = 0; p < q.passes; ++p) {
+    const int shift = 8 * p;
+    const uint32_t* kin = (p % 2 == 0) ? kA : kB;
+    const uint32_t* vin = (p % 2 == 0) ? vA : vB;
+    uint32_t* kout = (p % 2 == 0) ? kB : kA;
+    uint32_t* vout = (p % 2 == 0) ? vB : vA;
+    hipLaunchKernelGGL(k_sort_hist, dim3(q.nblk_sort), dim3(kSortThreads), 0, stream, kin,
+                       status, shift, q.nblk_sort, hist);
+    hipLaunchKernelGGL(k_sort_scan, dim3(kSortRadix), dim3(kSortThreads), 0, stream, hist,
+                       status, q.nblk_sort, dtot);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(q.nblk_sort), dim3(kSortThreads), 0, stream, kin,
+                       vin, status, shift, q.nblk_sort, hist, dtot, kout, vout);
+  }
+  const uint32_t* ksorted = sorted_in_a(q) ? kA : kB;
+  const int T = int(q.T);
+  hipLaunchKernelGGL(k_tile_ranges, dim3((T + 1 + 255) / 256), dim3(256), 0, stream, ksorted,
+                     status, T, q.depth_bits, ws_ptr<uint32_t>(ws, q.off_ranges));
+}
+
+}  // namespace pulsar

@@ -1,0 +1,335 @@
+// C ABI of the sphere renderer: host-side validation, workspace planning and
+// the entry points declared in include/pulsar.h. Every check runs before any
+// work is enqueued, so a failing call leaves the stream untouched.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "pulsar_internal.h"
+
+namespace pulsar {
+namespace {
+
+thread_local std::string g_last_hip_error;
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int ceil_log2(int64_t v) {
+  int b = 0;
+  while ((int64_t(1) << b) < v) ++b;
+  return b;
+}
+
+bool finite_all(const float* v, int k) {
+  for (int i = 0; i < k; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+int check_camera(const pulsar_camera_t* c) {
+  if (!c) return PULSAR_ERR_INVALID_ARGUMENT;
+  if (!finite_all(c->R, 9) || !finite_all(c->t, 3)) return PULSAR_ERR_INVALID_ARGUMENT;
+  if (!std::isfinite(c->focal) || !(c->focal > 0.f)) return PULSAR_ERR_INVALID_ARGUMENT;
+  if (!std::isfinite(c->sensor_width) || !(c->sensor_width > 0.f))
+    return PULSAR_ERR_INVALID_ARGUMENT;
+  if (!std::isfinite(c->znear) || !(c->znear > 0.f)) return PULSAR_ERR_INVALID_ARGUMENT;
+  if (!std::isfinite(c->zfar) || !(c->zfar > c->znear)) return PULSAR_ERR_INVALID_ARGUMENT;
+  if (c->width < 1 || c->width > 65535 || c->height < 1 || c->height > 65535)
+    return PULSAR_ERR_INVALID_ARGUMENT;
+  return PULSAR_OK;
+}
+
+int check_params(const pulsar_params_t* p) {
+  if (!p) return PULSAR_ERR_INVALID_ARGUMENT;
+  // gamma in [1e-5, 1] (Sec. 3.2); a relative slack of 1e-6 admits float rounding of 1e-5
+  if (!std::isfinite(p->gamma) || p->gamma < 1e-5f * (1.f - 1e-6f) || p->gamma > 1.f)
+    return PULSAR_ERR_INVALID_ARGUMENT;
+  if (!std::isfinite(p->eps) || p->eps < 0.f) return PULSAR_ERR_INVALID_ARGUMENT;
+  if (!std::isfinite(p->min_radius_px) || p->min_radius_px < 0.f)
+    return PULSAR_ERR_INVALID_ARGUMENT;
+  if (p->K < 1 || p->K > kMaxK) return PULSAR_ERR_INVALID_ARGUMENT;
+  if (p->max_pairs < 0) return PULSAR_ERR_INVALID_ARGUMENT;
+  if (p->depth_bits < 0 || p->depth_bits > 16) return PULSAR_ERR_INVALID_ARGUMENT;
+  if (p->flags != 0u || p->reserved != 0) return PULSAR_ERR_UNSUPPORTED;
+  return PULSAR_OK;
+}
+
+int fail_hip(hipError_t e) {
+  g_last_hip_error = hipGetErrorString(e);
+  return PULSAR_ERR_HIP;
+}
+
+// ---- stage timing
+std::atomic<int> g_timing{0};
+std::mutex g_timing_mu;
+struct Mark {
+  int stage;
+  hipEvent_t begin, end;
+};
+std::vector<Mark> g_marks;        // completed begin/end pairs awaiting read-out
+hipEvent_t g_open[PULSAR_NUM_STAGES] = {};  // begin events without their end yet
+
+}  // namespace
+
+void stage_begin(int stage, hipStream_t stream) {
+  if (!g_timing.load(std::memory_order_relaxed)) return;
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return;
+  hipEventRecord(e, stream);
+  if (g_open[stage]) hipEventDestroy(g_open[stage]);
+  g_open[stage] = e;
+}
+
+void stage_end(int stage, hipStream_t stream) {
+  if (!g_timing.load(std::memory_order_relaxed)) return;
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  if (!g_open[stage]) return;
+  hipEvent_t e;
+  if (hipEventCreate(&e) != hipSuccess) return;
+  hipEventRecord(e, stream);
+  g_marks.push_back(Mark{stage, g_open[stage], e});
+  g_open[stage] = nullptr;
+}
+
+int make_plan(int64_t n, int W, int H, int C, const pulsar_params_t* p, Plan* out) {
+  if (n < 0 || n > INT32_MAX || C < 1 || W < 1 || W > 65535 || H < 1 || H > 65535)
+    return PULSAR_ERR_INVALID_ARGUMENT;
+  int rc = check_params(p);
+  if (rc != PULSAR_OK) return rc;
+  Plan q;
+  std::memset(&q, 0, sizeof(q));
+  q.n = n;
+  q.C = C;
+  q.W = W;
+  q.H = H;
+  q.tiles_x = (W + kTileW - 1) / kTileW;
+  q.tiles_y = (H + kTileH - 1) / kTileH;
+  q.T = q.tiles_x * q.tiles_y;
+  q.tile_bits = ceil_log2(q.T);
+  if (q.tile_bits < 1) q.tile_bits = 1;
+  if (p->depth_bits > 0) {
+    q.depth_bits = p->depth_bits;
+  } else {
+    // fill the key to a whole number of 8-bit digits with at least 8 depth bits
+    int total = (q.tile_bits + 8 + 7) / 8 * 8;
+    q.depth_bits = total - q.tile_bits;
+    if (q.depth_bits > 16) q.depth_bits = 16;
+  }
+  if (q.tile_bits + q.depth_bits > 32) return PULSAR_ERR_UNSUPPORTED;
+  q.passes = (q.tile_bits + q.depth_bits + 7) / 8;
+  int64_t cap = p->max_pairs > 0 ? int64_t(p->max_pairs) : 4 * n + q.T + 65536;
+  if (cap > (int64_t(1) << 31) - 1) cap = (int64_t(1) << 31) - 1;
+  q.cap = cap;
+  q.nblk_proj = int((n + kProjectBlock - 1) / kProjectBlock);
+  q.nblk_sort = int((cap + kSortBlock - 1) / kSortBlock);
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o += align_up(bytes);
+    return at;
+  };
+  const size_t nn = size_t(n > 0 ? n : 1);
+  q.off_status = take(sizeof(Status));
+  q.off_counts = take(nn * 4);
+  q.off_trect = take(nn * 8);
+  q.off_qdepth = take(nn * 4);
+  q.off_recA = take(nn * 16);
+  q.off_recB = take(nn * 16);
+  q.off_gacc = take(nn * 16);
+  q.off_partials = take(size_t(q.nblk_proj + 1) * 8);
+  q.off_keysA = take(size_t(cap) * 4);
+  q.off_valsA = take(size_t(cap) * 4);
+  q.off_keysB = take(size_t(cap) * 4);
+  q.off_valsB = take(size_t(cap) * 4);
+  q.off_hist = take(size_t(kSortRadix) * size_t(q.nblk_sort) * 4);
+  q.off_dtot = take(size_t(kSortRadix) * 4);
+  q.off_ranges = take(size_t(q.T + 1) * 4);
+  q.off_bgpart = take(size_t(q.T) * size_t(C) * 4);
+  q.total = o;
+  *out = q;
+  return PULSAR_OK;
+}
+
+CamDev make_cam(const pulsar_camera_t* c) {
+  CamDev d;
+  for (int i = 0; i < 9; ++i) d.R[i] = c->R[i];
+  for (int i = 0; i < 3; ++i) d.t[i] = c->t[i];
+  d.f = c->focal;
+  d.s = c->sensor_width;
+  d.znear = c->znear;
+  d.zfar = c->zfar;
+  d.W = c->width;
+  d.H = c->height;
+  d.pitch = float(double(c->sensor_width) / double(c->width));
+  d.sh = float(double(c->sensor_width) * double(c->height) / double(c->width));
+  d.tiles_x = (c->width + kTileW - 1) / kTileW;
+  d.tiles_y = (c->height + kTileH - 1) / kTileH;
+  return d;
+}
+
+BlendConst make_blend(const pulsar_camera_t* c, const pulsar_params_t* p) {
+  const double log2e = 1.4426950408889634;
+  const double span = double(c->zfar) - double(c->znear);
+  BlendConst b;
+  b.kz = float(log2e / (double(p->gamma) * span));
+  b.eps2 = float(double(p->eps) / double(p->gamma) * log2e);
+  b.zfar = c->zfar;
+  b.inv_gamma = float(1.0 / double(p->gamma));
+  b.inv_span = float(1.0 / span);
+  return b;
+}
+
+}  // namespace pulsar
+
+using namespace pulsar;
+
+extern "C" {
+
+size_t pulsar_workspace_size(int32_t n, int32_t width, int32_t height, int32_t C,
+                             const pulsar_params_t* params) {
+  Plan q;
+  if (make_plan(n, width, height, C, params, &q) != PULSAR_OK) return 0;
+  return q.total;
+}
+
+int pulsar_fwd(const float* pos, const float* radius, const float* opacity,
+               const float* payload, int32_t n, int32_t C, const float* background,
+               const pulsar_camera_t* cam, const pulsar_params_t* params, float* image,
+               float* aux, void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_camera(cam);
+  if (rc != PULSAR_OK) return rc;
+  if (n < 0 || C < 1) return PULSAR_ERR_INVALID_ARGUMENT;
+  if (n > 0 && (!pos || !radius || !payload)) return PULSAR_ERR_INVALID_ARGUMENT;
+  if (!background || !image || !ws) return PULSAR_ERR_INVALID_ARGUMENT;
+  Plan q;
+  rc = make_plan(n, cam->width, cam->height, C, params, &q);
+  if (rc != PULSAR_OK) return rc;
+  if (ws_bytes < q.total) return PULSAR_ERR_WORKSPACE;
+  FwdArgs a;
+  a.pos = pos;
+  a.radius = radius;
+  a.opacity = opacity;
+  a.payload = payload;
+  a.bg = background;
+  a.n = n;
+  a.C = C;
+  a.image = image;
+  a.aux = aux;
+  a.min_radius_px = params->min_radius_px;
+  hipError_t e = launch_forward(q, make_cam(cam), make_blend(cam, params), a,
+                                static_cast<char*>(ws), static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail_hip(e);
+  return PULSAR_OK;
+}
+
+int pulsar_bwd(const float* pos, const float* radius, const float* opacity,
+               const float* payload, int32_t n, int32_t C, const float* background,
+               const pulsar_camera_t* cam, const pulsar_params_t* params, const float* image,
+               const float* aux, const float* grad_image, float* grad_pos, float* grad_radius,
+               float* grad_opacity, float* grad_payload, float* grad_background, void* ws,
+               size_t ws_bytes, void* stream) {
+  int rc = check_camera(cam);
+  if (rc != PULSAR_OK) return rc;
+  if (n < 0 || C < 1) return PULSAR_ERR_INVALID_ARGUMENT;
+  if (n > 0 && (!pos || !radius || !payload)) return PULSAR_ERR_INVALID_ARGUMENT;
+  if (!background || !image || !aux || !grad_image || !ws) return PULSAR_ERR_INVALID_ARGUMENT;
+  if (grad_opacity && !opacity) return PULSAR_ERR_INVALID_ARGUMENT;
+  Plan q;
+  rc = make_plan(n, cam->width, cam->height, C, params, &q);
+  if (rc != PULSAR_OK) return rc;
+  if (ws_bytes < q.total) return PULSAR_ERR_WORKSPACE;
+  BwdArgs a;
+  a.pos = pos;
+  a.radius = radius;
+  a.opacity = opacity;
+  a.payload = payload;
+  a.n = n;
+  a.C = C;
+  a.K = params->K;
+  a.image = image;
+  a.aux = aux;
+  a.grad_image = grad_image;
+  a.grad_pos = grad_pos;
+  a.grad_radius = grad_radius;
+  a.grad_opacity = grad_opacity;
+  a.grad_payload = grad_payload;
+  a.grad_bg = grad_background;
+  a.min_radius_px = params->min_radius_px;
+  hipError_t e = launch_backward(q, make_cam(cam), make_blend(cam, params), a,
+                                 static_cast<char*>(ws), static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return fail_hip(e);
+  return PULSAR_OK;
+}
+
+int pulsar_query_status(const void* ws, size_t ws_bytes, void* stream, int64_t* pairs) {
+  if (!ws || ws_bytes < sizeof(Status)) return PULSAR_ERR_INVALID_ARGUMENT;
+  Status st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipMemcpyAsync(&st, ws, sizeof(Status), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return fail_hip(e);
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail_hip(e);
+  if (pairs) *pairs = int64_t(st.pairs);
+  return st.code == 0u ? PULSAR_OK : PULSAR_ERR_CAPACITY;
+}
+
+const char* pulsar_status_string(int code) {
+  switch (code) {
+    case PULSAR_OK:
+      return "success";
+    case PULSAR_ERR_INVALID_ARGUMENT:
+      return "invalid argument: a required pointer is NULL or a size or parameter is out of range";
+    case PULSAR_ERR_WORKSPACE:
+      return "workspace too small: allocate pulsar_workspace_size() bytes";
+    case PULSAR_ERR_UNSUPPORTED:
+      return "unsupported flag or size in this build";
+    case PULSAR_ERR_HIP:
+      return "HIP launch or runtime error (see pulsar_last_hip_error)";
+    case PULSAR_ERR_CAPACITY:
+      return "tile-pair capacity exceeded: raise params.max_pairs and render again";
+    default:
+      return "unknown status code";
+  }
+}
+
+const char* pulsar_last_hip_error(void) { return g_last_hip_error.c_str(); }
+
+int pulsar_timing_enable(int on) { return g_timing.exchange(on ? 1 : 0); }
+
+int pulsar_timing_read(double* total_ms, int64_t* counts) {
+  std::lock_guard<std::mutex> lk(g_timing_mu);
+  int rc = PULSAR_OK;
+  for (const Mark& m : g_marks) {
+    float ms = 0.f;
+    hipError_t e = hipEventSynchronize(m.end);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, m.begin, m.end);
+    if (e != hipSuccess) {
+      rc = fail_hip(e);
+    } else {
+      if (total_ms) total_ms[m.stage] += double(ms);
+      if (counts) counts[m.stage] += 1;
+    }
+    hipEventDestroy(m.begin);
+    hipEventDestroy(m.end);
+  }
+  g_marks.clear();
+  return rc;
+}
+
+const char* pulsar_stage_name(int stage) {
+  static const char* names[PULSAR_NUM_STAGES] = {"project", "binning", "raster_fwd",
+                                                 "zero", "raster_bwd", "finalize"};
+  return (stage >= 0 && stage < PULSAR_NUM_STAGES) ? names[stage] : "unknown";
+}
+
+int pulsar_version(void) { return 1; }
+
+}  // extern "C"

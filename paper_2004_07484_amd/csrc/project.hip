@@ -1,0 +1,117 @@
+// K1: per-sphere projection and culling (paper App. B, Step 0).
+//
+// One lane per sphere. The camera transform and the projected bounds run in
+// FP64 (the kernel is memory bound, FP64 costs nothing here and keeps the
+// screen-space record exact enough for sub-pixel spheres). Outputs per sphere:
+//   counts  number of 8x8 tiles its pixel rectangle touches (0 = culled)
+//   trect   tile rectangle (tx0, ty0, tx1, ty1)
+//   qdepth  floor-quantised lower bound of its nearest possible hit distance
+//   recA    (X_c - x0, Y_c - y0, kappa, x0 | y0 << 16): projected centre in
+//           pixel units relative to the first pixel of its rectangle, and
+//           kappa = (c_z pitch / R)^2
+//   recB    (c_x / c_z, c_y / c_z, c_z, R)
+// and the per-block sum of counts for the tile-pair scan.
+#include "device_common.h"
+#include "pulsar_internal.h"
+
+namespace pulsar {
+
+__global__ __launch_bounds__(kProjectBlock) void k_project(
+    int n, const float* __restrict__ pos, const float* __restrict__ radius,
+    const float* __restrict__ opacity, CamDev cam, float min_radius_px, int depth_bits,
+    uint32_t* __restrict__ counts, ushort4* __restrict__ trect, uint32_t* __restrict__ qdepth,
+    float4* __restrict__ recA, float4* __restrict__ recB,
+    unsigned long long* __restrict__ partials) {
+  const int i = blockIdx.x * kProjectBlock + threadIdx.x;
+  uint32_t count = 0;
+  if (i < n) {
+    const float px = pos[3 * i + 0], py = pos[3 * i + 1], pz = pos[3 * i + 2];
+    const float r = radius[i];
+    const float o = opacity ? opacity[i] : 1.f;
+    bool ok = isfinite(px) && isfinite(py) && isfinite(pz) && isfinite(r) && isfinite(o) &&
+              r > 0.f;
+    const double cx = double(cam.R[0]) * px + double(cam.R[1]) * py + double(cam.R[2]) * pz +
+                      double(cam.t[0]);
+    const double cy = double(cam.R[3]) * px + double(cam.R[4]) * py + double(cam.R[5]) * pz +
+                      double(cam.t[1]);
+    const double cz = double(cam.R[6]) * px + double(cam.R[7]) * py + double(cam.R[8]) * pz +
+                      double(cam.t[2]);
+    const double f = cam.f;
+    const double pitch = double(cam.s) / double(cam.W);
+    const double sh = double(cam.s) * double(cam.H) / double(cam.W);
+    double R = r;
+    if (min_radius_px > 0.f) {
+      const double rmin = double(min_radius_px) * pitch * cz / f;
+      if (rmin > R) R = rmin;
+    }
+    ok = ok && (cz - R >= double(cam.znear));
+    const double tmin = sqrt(cx * cx + cy * cy + cz * cz) - R;
+    ok = ok && (tmin <= double(cam.zfar));
+    if (ok) {
+      // The cone of rays through the sphere lies between the two planes through
+      // the camera centre tangent to it; on the plane z = f they bound
+      // x in f (c_x c_z -+ R sqrt(c_x^2 + c_z^2 - R^2)) / (c_z^2 - R^2), same for y.
+      const double den = cz * cz - R * R;
+      const double sx = R * sqrt(cx * cx + cz * cz - R * R);
+      const double sy = R * sqrt(cy * cy + cz * cz - R * R);
+      const double xlo = f * (cx * cz - sx) / den, xhi = f * (cx * cz + sx) / den;
+      const double ylo = f * (cy * cz - sy) / den, yhi = f * (cy * cz + sy) / den;
+      // pixel j has its centre at sensor x (j + 1/2) pitch - s/2; widen by a
+      // small margin so rounding never drops a pixel the exact cone covers
+      const double margin = 1e-3;
+      double jlo = ceil((xlo + 0.5 * double(cam.s)) / pitch - 0.5 - margin);
+      double jhi = floor((xhi + 0.5 * double(cam.s)) / pitch - 0.5 + margin);
+      double ilo = ceil((ylo + 0.5 * sh) / pitch - 0.5 - margin);
+      double ihi = floor((yhi + 0.5 * sh) / pitch - 0.5 + margin);
+      jlo = fmax(jlo, 0.0);
+      ilo = fmax(ilo, 0.0);
+      jhi = fmin(jhi, double(cam.W - 1));
+      ihi = fmin(ihi, double(cam.H - 1));
+      if (jlo <= jhi && ilo <= ihi) {
+        const int j0 = int(jlo), j1 = int(jhi), i0 = int(ilo), i1 = int(ihi);
+        const int tx0 = j0 / kTileW, tx1 = j1 / kTileW, ty0 = i0 / kTileH, ty1 = i1 / kTileH;
+        count = uint32_t(tx1 - tx0 + 1) * uint32_t(ty1 - ty0 + 1);
+        trect[i] = make_ushort4(uint16_t(tx0), uint16_t(ty0), uint16_t(tx1), uint16_t(ty1));
+        const double Xc = (f * cx / cz + 0.5 * double(cam.s)) / pitch - 0.5;
+        const double Yc = (f * cy / cz + 0.5 * sh) / pitch - 0.5;
+        const double kap = cz * pitch / R;
+        const uint32_t packed = uint32_t(j0) | (uint32_t(i0) << 16);
+        recA[i] = make_float4(float(Xc - j0), float(Yc - i0), float(kap * kap),
+                              __uint_as_float(packed));
+        recB[i] = make_float4(float(cx / cz), float(cy / cz), float(cz), float(R));
+        // floor quantisation of (tmin - znear) / span, minus one step of margin,
+        // so the decoded value never exceeds any float32 hit distance
+        const double span = double(cam.zfar) - double(cam.znear);
+        const double levels = double(1u << depth_bits);
+        double qd = floor((tmin - double(cam.znear)) / span * levels) - 1.0;
+        qd = fmin(fmax(qd, 0.0), levels - 1.0);
+        qdepth[i] = uint32_t(qd);
+      }
+    }
+    counts[i] = count;
+  }
+  // per-block sum of tile counts
+  __shared__ unsigned long long s_sum[kProjectBlock / kWave];
+  const unsigned long long w = wave_sum_u64(count);
+  if ((threadIdx.x & (kWave - 1)) == 0) s_sum[threadIdx.x / kWave] = w;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+#pragma unroll
+    for (int k = 0; k < kProjectBlock / kWave; ++k) t += s_sum[k];
+    partials[blockIdx.x] = t;
+  }
+}
+
+void launch_project(const Plan& q, const CamDev& cam, const FwdArgs& a, char* ws,
+                    hipStream_t stream) {
+  if (q.n == 0) return;
+  hipLaunchKernelGGL(k_project, dim3(q.nblk_proj), dim3(kProjectBlock), 0, stream, int(q.n),
+                     a.pos, a.radius, a.opacity, cam, a.min_radius_px, q.depth_bits,
+                     ws_ptr<uint32_t>(ws, q.off_counts), ws_ptr<ushort4>(ws, q.off_trect),
+                     ws_ptr<uint32_t>(ws, q.off_qdepth), ws_ptr<float4>(ws, q.off_recA),
+                     ws_ptr<float4>(ws, q.off_recB),
+                     ws_ptr<unsigned long long>(ws, q.off_partials));
+}
+
+}  // namespace pulsar

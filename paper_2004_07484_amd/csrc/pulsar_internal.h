@@ -1,0 +1,115 @@
+// Internal declarations shared by the C ABI (capi.cpp) and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "pulsar.h"
+
+namespace pulsar {
+
+// One wave64 renders one 8x8 screen tile: lane l owns pixel (l / 8, l % 8).
+constexpr int kTileW = 8;
+constexpr int kTileH = 8;
+constexpr int kWave = 64;
+constexpr int kProjectBlock = 256;           // spheres per projection block
+constexpr int kScanThreads = 1024;           // single-block scan of block sums
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 8;
+constexpr int kSortBlock = kSortThreads * kSortRounds;  // keys per sort block
+constexpr int kSortRadix = 256;              // 8-bit digits
+constexpr int kMaxK = 32;
+constexpr int kFwdChannels = 32;             // channels per forward pass (more: several passes)
+
+// Device status block at the start of the workspace.
+struct Status {
+  uint32_t code;                // PULSAR_OK or PULSAR_ERR_CAPACITY
+  uint32_t used;                // pairs actually stored: min(pairs, capacity)
+  unsigned long long pairs;     // pairs the scene produced
+  uint32_t pad[60];
+};
+
+// Camera constants in the form the kernels use.
+struct CamDev {
+  float R[9];
+  float t[3];
+  float f, s, znear, zfar;
+  float pitch;  // s / W
+  float sh;     // sensor height s H / W
+  int W, H, tiles_x, tiles_y;
+};
+
+// Blend constants of Eq. 1 in base-2 exponent units.
+struct BlendConst {
+  float kz;         // log2(e) / (gamma (zfar - znear)): o z / gamma * log2(e) = o (zfar - t) kz
+  float eps2;       // eps / gamma * log2(e): exponent of the background weight
+  float zfar;
+  float inv_gamma;  // 1 / gamma
+  float inv_span;   // 1 / (zfar - znear)
+};
+
+// Workspace layout: byte offsets of every buffer, all 256-byte aligned.
+struct Plan {
+  int64_t n, C, W, H, T, tiles_x, tiles_y, cap;
+  int tile_bits, depth_bits, passes, nblk_proj, nblk_sort;
+  size_t off_status, off_counts, off_trect, off_qdepth, off_recA, off_recB, off_gacc;
+  size_t off_partials, off_keysA, off_valsA, off_keysB, off_valsB, off_hist, off_dtot;
+  size_t off_ranges, off_bgpart, total;
+};
+
+// Fills `out` and returns PULSAR_OK, or returns an error code.
+int make_plan(int64_t n, int W, int H, int C, const pulsar_params_t* p, Plan* out);
+CamDev make_cam(const pulsar_camera_t* c);
+BlendConst make_blend(const pulsar_camera_t* c, const pulsar_params_t* p);
+
+struct FwdArgs {
+  const float* pos;
+  const float* radius;
+  const float* opacity;
+  const float* payload;
+  const float* bg;
+  int n, C;
+  float* image;
+  float* aux;
+  float min_radius_px;
+};
+
+struct BwdArgs {
+  const float* pos;
+  const float* radius;
+  const float* opacity;
+  const float* payload;
+  int n, C, K;
+  const float* image;
+  const float* aux;
+  const float* grad_image;
+  float* grad_pos;
+  float* grad_radius;
+  float* grad_opacity;
+  float* grad_payload;
+  float* grad_bg;
+  float min_radius_px;
+};
+
+// Enqueue the forward / backward pipelines. They return the first launch error.
+hipError_t launch_forward(const Plan& plan, const CamDev& cam, const BlendConst& bc,
+                          const FwdArgs& a, char* ws, hipStream_t stream);
+hipError_t launch_backward(const Plan& plan, const CamDev& cam, const BlendConst& bc,
+                           const BwdArgs& a, char* ws, hipStream_t stream);
+
+// Stage timing hooks (no-ops unless pulsar_timing_enable(1) was called).
+void stage_begin(int stage, hipStream_t stream);
+void stage_end(int stage, hipStream_t stream);
+
+// Pointers into the workspace.
+template <typename T>
+inline T* ws_ptr(char* ws, size_t off) {
+  return reinterpret_cast<T*>(ws + off);
+}
+
+// Result of the LSD sort lands in the A buffers after an even number of passes.
+inline bool sorted_in_a(const Plan& p) { return (p.passes % 2) == 0; }
+
+}  // namespace pulsar

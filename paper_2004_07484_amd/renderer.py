@@ -1,0 +1,136 @@
+"""PyTorch front end: torch.autograd.Function and a Renderer module (paper Sec. 4, Lst. 1).
+
+PyTorch only provides device memory, the stream and autograd bookkeeping;
+every step of the rendering pass runs in the HIP kernels of libpulsar.so.
+The backward recomputes per-pixel hits from the workspace the forward filled
+(nothing per pixel is stored beyond the image and its log-normaliser).
+"""
+from __future__ import annotations
+
+import math
+from typing import Optional
+
+import torch
+
+from . import _capi
+
+
+def axis_angle_to_matrix(r) -> list:
+    """Rodrigues' formula on the host; returns a row-major 3x3 list."""
+    rx, ry, rz = (float(v) for v in r)
+    th = math.sqrt(rx * rx + ry * ry + rz * rz)
+    if th < 1e-12:
+        return [1.0, 0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 0.0, 1.0]
+    kx, ky, kz = rx / th, ry / th, rz / th
+    c, s, v = math.cos(th), math.sin(th), 1.0 - math.cos(th)
+    return [c + kx * kx * v, kx * ky * v - kz * s, kx * kz * v + ky * s,
+            ky * kx * v + kz * s, c + ky * ky * v, ky * kz * v - kx * s,
+            kz * kx * v - ky * s, kz * ky * v + kx * s, c + kz * kz * v]
+
+
+def camera_struct(cam, width: int, height: int, znear: float, zfar: float):
+    """Accepts a pulsar_camera_t, an object with R, t, focal, sensor_width
+    (znear/zfar/width/height optional), or the 8-vector [t (3), axis-angle (3),
+    focal, sensor_width] of Lst. 1, read as x_cam = R(axis-angle) x_world + t."""
+    if isinstance(cam, _capi.pulsar_camera_t):
+        return cam
+    if hasattr(cam, "R"):
+        return _capi.make_camera(cam.R, cam.t, cam.focal, cam.sensor_width,
+                                 getattr(cam, "znear", znear), getattr(cam, "zfar", zfar),
+                                 getattr(cam, "width", width), getattr(cam, "height", height))
+    v = cam.detach().cpu().reshape(-1).tolist() if hasattr(cam, "detach") else list(cam)
+    if len(v) != 8:
+        raise ValueError("camera vector must be [t(3), axis-angle(3), focal, sensor_width]")
+    return _capi.make_camera(axis_angle_to_matrix(v[3:6]), v[0:3], v[6], v[7], znear, zfar,
+                             width, height)
+
+
+def _forward_into(pos, radius, opacity, payload, bg, cam, params, check: bool):
+    """Run pulsar_fwd into fresh outputs; grow the pair capacity and re-run
+    if the device reports an overflow (only when check is set)."""
+    n, C = payload.shape
+    dev = payload.device
+    image = torch.empty((cam.height, cam.width, C), device=dev, dtype=torch.float32)
+    aux = torch.empty((cam.height, cam.width), device=dev, dtype=torch.float32)
+    while True:
+        ws = torch.empty(_capi.pulsar_workspace_size(n, cam.width, cam.height, C, params),
+                         device=dev, dtype=torch.uint8)
+        _capi.pulsar_fwd(pos, radius, opacity, payload, bg, cam, params, image, aux, ws)
+        if not check:
+            return image, aux, ws, params
+        code, pairs = _capi.pulsar_query_status(ws)
+        if code == _capi.PULSAR_OK:
+            return image, aux, ws, params
+        grown = _capi.make_params(params.gamma, params.eps, params.min_radius_px, params.K,
+                                  int(min(2**31 - 1, pairs * 5 // 4 + 1024)), params.depth_bits)
+        if grown.max_pairs <= params.max_pairs:
+            raise _capi.PulsarError(code, "pulsar_fwd")
+        params = grown
+
+
+class PulsarFunction(torch.autograd.Function):
+    """F = R(S, camera) with the hand-written backward of libpulsar.so."""
+
+    @staticmethod
+    def forward(ctx, pos, radius, opacity, payload, bg, cam, params, check=True):
+        pos, radius, payload, bg = (t.contiguous() for t in (pos, radius, payload, bg))
+        opacity = opacity.contiguous() if opacity is not None else None
+        image, aux, ws, params = _forward_into(pos, radius, opacity, payload, bg, cam, params,
+                                               check)
+        ctx.save_for_backward(pos, radius, opacity, payload, bg, image, aux, ws)
+        ctx.cam, ctx.params = cam, params
+        ctx.mark_non_differentiable(aux)
+        return image, aux
+
+    @staticmethod
+    def backward(ctx, grad_image, grad_aux):
+        pos, radius, opacity, payload, bg, image, aux, ws = ctx.saved_tensors
+        need = ctx.needs_input_grad
+        n, C = payload.shape
+
+        def out(flag, shape):
+            return torch.empty(shape, device=payload.device, dtype=torch.float32) if flag \
+                else None
+
+        gp, gr = out(need[0], (n, 3)), out(need[1], (n,))
+        go = out(need[2] and opacity is not None, (n,))
+        gf, gb = out(need[3], (n, C)), out(need[4], (C,))
+        if grad_image is None:
+            grad_image = torch.zeros_like(image)
+        _capi.pulsar_bwd(pos, radius, opacity, payload, bg, ctx.cam, ctx.params, image, aux,
+                         grad_image.contiguous(), gp, gr, go, gf, gb, ws)
+        return gp, gr, go, gf, gb, None, None, None
+
+
+class Renderer(torch.nn.Module):
+    """Lst. 1 style renderer: Renderer(width, height, max_num_spheres)(pos, payload, radius, cam).
+
+    The camera is an 8-vector [t, axis-angle, focal, sensor_width] or an
+    object with R, t, focal and sensor_width. ``max_depth`` is the far clip
+    zfar and ``min_depth`` the near clip znear of the depth mapping.
+    """
+
+    def __init__(self, width: int, height: int, max_num_spheres: int, n_channels: int = 3,
+                 K: int = 5, max_pairs: int = 0, check_capacity: bool = True):
+        super().__init__()
+        self.width, self.height = int(width), int(height)
+        self.max_num_spheres, self.n_channels, self.K = int(max_num_spheres), int(n_channels), \
+            int(K)
+        self.max_pairs = int(max_pairs)
+        self.check_capacity = bool(check_capacity)
+        _capi.load()
+
+    def forward(self, pos, payload, radius, cam, opacity: Optional[torch.Tensor] = None,
+                gamma: float = 0.1, max_depth: float = 10.0, min_depth: float = 1.0,
+                bg: Optional[torch.Tensor] = None, eps: float = 1e-5,
+                min_radius_px: float = 0.0, return_aux: bool = False):
+        if pos.shape[0] > self.max_num_spheres:
+            raise ValueError("more spheres than the renderer was built for")
+        C = payload.shape[1]
+        if bg is None:
+            bg = torch.zeros(C, device=payload.device, dtype=torch.float32)
+        cs = camera_struct(cam, self.width, self.height, min_depth, max_depth)
+        params = _capi.make_params(gamma, eps, min_radius_px, self.K, self.max_pairs)
+        image, aux = PulsarFunction.apply(pos, radius, opacity, payload, bg, cs, params,
+                                          self.check_capacity)
+        return (image, aux) if return_aux else image

@@ -1,0 +1,166 @@
+"""Host-side checks of the C ABI: the library loads, exports every declared
+entry point, plans workspaces and rejects bad arguments before any launch.
+None of these calls touches a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import pytest
+
+from paper_2004_07484_amd import _capi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pulsar.h")
+
+FAKE = ctypes.c_void_p(0x10000)  # never dereferenced: validation fails first
+
+
+def _lib():
+    if not os.path.exists(_capi.LIB_PATH):
+        from paper_2004_07484_amd import build
+        build.build()
+    return _capi.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w]+\**\s+\**(pulsar_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declarations_are_exported():
+    lib = _lib()
+    names = declared_functions()
+    assert set(_capi.EXPORTED) <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", _capi.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (pulsar_\w+)", out))
+    assert set(names) <= exported
+
+
+def test_version_and_status_strings():
+    _lib()
+    assert _capi.pulsar_version() == 1
+    for code in [0, -1, -2, -3, -4, -5, -99]:
+        assert len(_capi.pulsar_status_string(code)) > 5
+    assert "capacity" in _capi.pulsar_status_string(_capi.PULSAR_ERR_CAPACITY)
+
+
+def test_workspace_size_plan():
+    _lib()
+    p = _capi.make_params(K=8)
+    s1 = _capi.pulsar_workspace_size(1000, 64, 64, 3, p)
+    s2 = _capi.pulsar_workspace_size(100_000, 64, 64, 3, p)
+    s0 = _capi.pulsar_workspace_size(0, 64, 64, 3, p)
+    assert 0 < s0 < s1 < s2
+    assert s1 % 256 == 0
+    # explicit pair capacity grows the workspace by 16 bytes per pair
+    big = _capi.pulsar_workspace_size(1000, 64, 64, 3, _capi.make_params(K=8, max_pairs=10**6))
+    small = _capi.pulsar_workspace_size(1000, 64, 64, 3, _capi.make_params(K=8, max_pairs=10**5))
+    assert big - small >= 16 * 9 * 10**5
+    # invalid requests plan nothing
+    assert _capi.pulsar_workspace_size(-1, 64, 64, 3, p) == 0
+    assert _capi.pulsar_workspace_size(10, 0, 64, 3, p) == 0
+    assert _capi.pulsar_workspace_size(10, 64, 70000, 3, p) == 0
+    assert _capi.pulsar_workspace_size(10, 64, 64, 0, p) == 0
+    assert _capi.pulsar_workspace_size(10, 64, 64, 3, _capi.make_params(K=0)) == 0
+    assert _capi.pulsar_workspace_size(10, 64, 64, 3, _capi.make_params(K=33)) == 0
+
+
+def _call_fwd(cam, params, n=10, C=3, ws_bytes=1 << 30, image=FAKE, bg=FAKE, pos=FAKE):
+    lib = _lib()
+    return lib.pulsar_fwd(pos, FAKE, None, FAKE, n, C, bg, ctypes.byref(cam),
+                          ctypes.byref(params), image, None, FAKE, ws_bytes, None)
+
+
+def _cam(**kw):
+    d = dict(R=[1, 0, 0, 0, 1, 0, 0, 0, 1], t=[0, 0, 0], focal=1.0, sensor_width=2.0, znear=1.0,
+             zfar=10.0, width=64, height=64)
+    d.update(kw)
+    return _capi.make_camera(**d)
+
+
+@pytest.mark.parametrize("cam_kw", [dict(focal=0.0), dict(focal=-1.0),
+                                    dict(sensor_width=0.0), dict(znear=0.0),
+                                    dict(znear=5.0, zfar=5.0), dict(width=0),
+                                    dict(height=65536), dict(t=[0, float("nan"), 0]),
+                                    dict(focal=float("inf"))])
+def test_bad_camera_is_rejected(cam_kw):
+    assert _call_fwd(_cam(**cam_kw), _capi.make_params()) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+
+
+@pytest.mark.parametrize("par_kw,code", [
+    (dict(gamma=0.0), _capi.PULSAR_ERR_INVALID_ARGUMENT),
+    (dict(gamma=2.0), _capi.PULSAR_ERR_INVALID_ARGUMENT),
+    (dict(gamma=1e-6), _capi.PULSAR_ERR_INVALID_ARGUMENT),
+    (dict(eps=-1.0), _capi.PULSAR_ERR_INVALID_ARGUMENT),
+    (dict(min_radius_px=-0.5), _capi.PULSAR_ERR_INVALID_ARGUMENT),
+    (dict(K=0), _capi.PULSAR_ERR_INVALID_ARGUMENT),
+    (dict(K=33), _capi.PULSAR_ERR_INVALID_ARGUMENT),
+    (dict(max_pairs=-5), _capi.PULSAR_ERR_INVALID_ARGUMENT),
+    (dict(depth_bits=17), _capi.PULSAR_ERR_INVALID_ARGUMENT),
+])
+def test_bad_params_are_rejected(par_kw, code):
+    assert _call_fwd(_cam(), _capi.make_params(**par_kw)) == code
+
+
+def test_reserved_flags_are_unsupported():
+    p = _capi.make_params()
+    p.flags = 1
+    assert _call_fwd(_cam(), p) == _capi.PULSAR_ERR_UNSUPPORTED
+
+
+def test_missing_pointers_and_small_workspace():
+    p = _capi.make_params()
+    assert _call_fwd(_cam(), p, image=None) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    assert _call_fwd(_cam(), p, bg=None) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    assert _call_fwd(_cam(), p, pos=None) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    assert _call_fwd(_cam(), p, n=-1) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    assert _call_fwd(_cam(), p, C=0) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    need = _capi.pulsar_workspace_size(10, 64, 64, 3, p)
+    assert _call_fwd(_cam(), p, ws_bytes=need - 1) == _capi.PULSAR_ERR_WORKSPACE
+
+
+def test_backward_argument_checks():
+    lib = _lib()
+    cam, p = _cam(), _capi.make_params()
+    args = [FAKE, FAKE, None, FAKE, 10, 3, FAKE, ctypes.byref(cam), ctypes.byref(p), FAKE, FAKE,
+            FAKE, FAKE, FAKE, None, FAKE, FAKE, FAKE, 1 << 30, None]
+    bad_aux = list(args)
+    bad_aux[10] = None
+    assert lib.pulsar_bwd(*bad_aux) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    op_grad_without_opacity = list(args)
+    op_grad_without_opacity[14] = FAKE
+    assert lib.pulsar_bwd(*op_grad_without_opacity) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    small = list(args)
+    small[18] = 1024
+    assert lib.pulsar_bwd(*small) == _capi.PULSAR_ERR_WORKSPACE
+
+
+def test_launch_without_device_reports_hip_error():
+    """With no GPU present a well-formed call fails cleanly with PULSAR_ERR_HIP.
+    Runs in a child process so HIP runtime state stays out of this one."""
+    code = r"""
+import ctypes, sys
+sys.path.insert(0, %r)
+from paper_2004_07484_amd import _capi
+lib = _capi.load()
+cnt = ctypes.c_int(0)
+ctypes.CDLL("libamdhip64.so").hipGetDeviceCount(ctypes.byref(cnt))
+if cnt.value > 0:
+    print("HAS_GPU")
+    sys.exit(0)
+cam = _capi.make_camera([1,0,0,0,1,0,0,0,1], [0,0,0], 1.0, 2.0, 1.0, 10.0, 16, 16)
+p = _capi.make_params()
+f = ctypes.c_void_p(0x10000)
+rc = lib.pulsar_fwd(f, f, None, f, 4, 3, f, ctypes.byref(cam), ctypes.byref(p), f, None, f,
+                    1 << 30, None)
+print("RC", rc, lib.pulsar_last_hip_error().decode())
+""" % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    if "HAS_GPU" in out.stdout:
+        pytest.skip("a GPU is present; this checks the no-device path")
+    assert f"RC {_capi.PULSAR_ERR_HIP}" in out.stdout, out.stdout + out.stderr

@@ -1,0 +1,197 @@
+"""Parity of the HIP renderer (through the C ABI) with the FP64 oracle.
+
+Images: |d| <= 1e-4 max(|ref|, 1e-2 max|ref|). Gradients: 1e-3 on the same
+scale. Upstream gradients are zero on pixels whose K nearest hits the oracle
+flags as rounding-sensitive, and off the evaluated rows for large workloads.
+"""
+import sys
+import types
+
+import numpy as np
+import pytest
+
+from oracle import reference as ref
+from paper_2004_07484_amd import _capi
+from paper_2004_07484_amd import scenegen as sg
+from tests.gpu_helpers import (GRAD_REL, IMAGE_REL, assert_close, compare_grads, gpu_render,
+                               masked_G)
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _parity(wl, rows=None, G_seed=1000, what="", grads=True, max_pairs=0):
+    sc, cam, par = wl.scene, wl.camera, wl.params
+    _say(f"[parity] {what} n={sc.n} {cam.width}x{cam.height} C={sc.C} K={par.K} rows="
+         f"{None if rows is None else len(rows)}")
+    fwd = ref.forward(sc, cam, par, rows=rows)
+    G = sg.upstream_grad(wl.seed + G_seed, cam.height, cam.width, sc.C)
+    Gm = masked_G(G, rows, fwd["ambiguous"])
+    out = gpu_render(sc, cam, par, Gm if grads else None, max_pairs=max_pairs)
+    assert out["status"] == _capi.PULSAR_OK
+    sel = slice(None) if rows is None else rows
+    assert_close(out["F"][sel], fwd["F"][sel], IMAGE_REL, f"{what} image")
+    assert_close(out["L"][sel], fwd["L"][sel], IMAGE_REL, f"{what} log-normaliser")
+    if grads:
+        g = ref.backward(sc, cam, par, Gm, fwd, rows=rows)
+        compare_grads(out, g, what)
+    return fwd, out
+
+
+def test_config1_full_frame():
+    _parity(sg.config1(), what="1k spheres 64x64")
+
+
+def test_config2_row_subset():
+    wl = sg.config2()
+    rows = sorted(np.random.default_rng(77).choice(512, 12, replace=False).tolist())
+    _parity(wl, rows=rows, what="100k spheres 512x512")
+
+
+def test_config3_full_size_row_subset():
+    """1M spheres at 1024x1024, C=8, K=8: the benchmark workload and launch
+    configuration, checked on 6 seeded rows (G zero elsewhere)."""
+    wl = sg.config3()
+    rows = sorted(np.random.default_rng(78).choice(1024, 6, replace=False).tolist())
+    fwd, out = _parity(wl, rows=rows, what="1M blobs 1024x1024")
+    assert np.isfinite(out["F"]).all()
+
+
+@pytest.mark.parametrize("case", ["truncated_K2", "K1", "K32", "no_opacity", "rotated",
+                                  "ragged", "one_channel", "forty_channels", "min_radius"])
+def test_small_scene_variants(case):
+    kw = dict(n=12, C=3, W=40, H=32, r_lo=0.2, r_hi=0.6)
+    if case == "ragged":
+        kw.update(W=37, H=29)
+    if case == "one_channel":
+        kw.update(C=1)
+    if case == "forty_channels":
+        kw.update(C=40)
+    if case == "no_opacity":
+        kw.update(with_opacity=False)
+    if case == "min_radius":
+        kw.update(r_lo=0.01, r_hi=0.05, n=30)
+    wl = sg.tiny_scene(101 + len(case), **kw)
+    wl.params = sg.Params(gamma=0.2, eps=1e-5, K={"truncated_K2": 2, "K1": 1, "K32": 32}.get(
+        case, 5), min_radius_px=2.0 if case == "min_radius" else 0.0)
+    if case == "rotated":
+        rng = np.random.default_rng(5)
+        q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+        q = q * np.sign(np.diag(r))
+        if np.linalg.det(q) < 0:
+            q[:, 0] = -q[:, 0]
+        tq = rng.uniform(-1, 1, 3)
+        sc = wl.scene
+        sc.pos = ((sc.pos.astype(np.float64) - tq) @ q).astype(np.float32)
+        wl.camera.R = q.astype(np.float32)
+        wl.camera.t = tq.astype(np.float32)
+    fwd, _ = _parity(wl, what=case)
+    if case in ("truncated_K2", "K1"):
+        assert fwd["nhits"].max() > wl.params.K  # the truncation is exercised
+
+
+def test_many_tiles_per_sphere():
+    """Spheres covering dozens of tiles, deep pixels, several sort blocks."""
+    wl = sg.tiny_scene(55, n=300, C=4, W=160, H=120, r_lo=0.05, r_hi=0.4)
+    wl.params = sg.Params(gamma=0.1, K=6)
+    fwd, out = _parity(wl, what="large spheres 160x120")
+    assert out["pairs"] > 3000
+
+
+def test_hard_blend_limit():
+    """gamma = 1e-5: pixels with a clear winner in o z show its payload."""
+    wl = sg.tiny_scene(7, n=10, C=3, W=32, H=32, r_lo=0.3, r_hi=0.6)
+    wl.params = sg.Params(gamma=1e-5, eps=1e-5, K=4)
+    fwd = ref.forward(wl.scene, wl.camera, wl.params)
+    out = gpu_render(wl.scene, wl.camera, wl.params)
+    checked = 0
+    for i in range(32):
+        for j in range(32):
+            h = ref.pixel_hits(wl.scene, wl.camera, wl.params, i, j)
+            ks = np.nonzero(h["hit"])[0]
+            if len(ks) == 0:
+                continue
+            z = (wl.camera.zfar - h["t"][ks]) / (wl.camera.zfar - wl.camera.znear)
+            oz = np.sort(wl.scene.opacity[ks].astype(np.float64) * z)[::-1]
+            if len(ks) > 1 and (oz[0] - oz[1]) / 1e-5 < 200:
+                continue
+            np.testing.assert_allclose(out["F"][i, j], fwd["F"][i, j], rtol=1e-4, atol=1e-5)
+            checked += 1
+    assert checked > 100
+
+
+def test_empty_scene_is_background():
+    cam = sg.identity_camera(24, 20)
+    sc = sg.Scene(pos=np.zeros((0, 3), np.float32), radius=np.zeros(0, np.float32),
+                  opacity=np.zeros(0, np.float32), payload=np.zeros((0, 2), np.float32),
+                  bg=np.array([0.5, -2.0], np.float32))
+    par = sg.Params(gamma=0.1, K=3)
+    G = sg.upstream_grad(3, 20, 24, 2)
+    out = gpu_render(sc, cam, par, G)
+    assert np.array_equal(out["F"], np.broadcast_to(sc.bg, (20, 24, 2)))
+    np.testing.assert_allclose(out["L"], 1e-4, rtol=1e-6)
+    np.testing.assert_allclose(out["grad_bg"], G.astype(np.float64).sum((0, 1)), rtol=1e-5)
+
+
+def test_invisible_spheres_change_nothing():
+    wl = sg.config1()
+    base = gpu_render(wl.scene, wl.camera, wl.params, sg.upstream_grad(5, 64, 64, 3))
+    sc = wl.scene
+    extra = np.array([[0, 0, -3], [50, 0, 4], [0.1, 0, 1.1], [0, 0.1, 12.0]], np.float32)
+    ext = sg.Scene(pos=np.concatenate([sc.pos, extra]),
+                   radius=np.concatenate([sc.radius, np.array([0.5, 0.5, 0.3, 0.5], np.float32)]),
+                   opacity=np.concatenate([sc.opacity, np.full(4, 0.9, np.float32)]),
+                   payload=np.concatenate([sc.payload, np.ones((4, 3), np.float32)]), bg=sc.bg)
+    nan_sphere = sg.Scene(pos=np.concatenate([ext.pos, np.array([[np.nan, 0, 4]], np.float32)]),
+                          radius=np.concatenate([ext.radius, np.array([0.5], np.float32)]),
+                          opacity=np.concatenate([ext.opacity, np.array([0.5], np.float32)]),
+                          payload=np.concatenate([ext.payload, np.ones((1, 3), np.float32)]),
+                          bg=sc.bg)
+    got = gpu_render(nan_sphere, wl.camera, wl.params, sg.upstream_grad(5, 64, 64, 3))
+    assert np.array_equal(got["F"], base["F"]) and np.array_equal(got["L"], base["L"])
+    assert got["pairs"] == base["pairs"]
+    for key in ["grad_pos", "grad_radius", "grad_opacity", "grad_payload"]:
+        assert np.all(got[key][1000:] == 0.0)
+
+
+def test_forward_is_deterministic_and_permutation_invariant():
+    wl = sg.config1()
+    a = gpu_render(wl.scene, wl.camera, wl.params)
+    b = gpu_render(wl.scene, wl.camera, wl.params)
+    assert np.array_equal(a["F"], b["F"]) and np.array_equal(a["L"], b["L"])
+    perm = np.random.default_rng(9).permutation(wl.scene.n)
+    sc = wl.scene
+    sp = sg.Scene(pos=sc.pos[perm], radius=sc.radius[perm], opacity=sc.opacity[perm],
+                  payload=sc.payload[perm], bg=sc.bg)
+    c = gpu_render(sp, wl.camera, wl.params)
+    assert_close(c["F"], a["F"], 1e-5, "permuted image")
+
+
+def test_capacity_overflow_is_reported_then_recovers():
+    wl = sg.config1()
+    small = gpu_render(wl.scene, wl.camera, wl.params, max_pairs=100)
+    assert small["status"] == _capi.PULSAR_ERR_CAPACITY and small["pairs"] > 100
+    _parity(wl, what="1k spheres, exact capacity", max_pairs=small["pairs"])
+
+
+def test_depth_key_width_only_changes_rounding():
+    wl = sg.config1()
+    a = gpu_render(wl.scene, wl.camera, wl.params, sg.upstream_grad(4, 64, 64, 3), depth_bits=10)
+    b = gpu_render(wl.scene, wl.camera, wl.params, sg.upstream_grad(4, 64, 64, 3), depth_bits=3)
+    assert_close(b["F"], a["F"], 1e-5, "image")
+    for key in ["grad_pos", "grad_radius", "grad_opacity", "grad_payload", "grad_bg"]:
+        assert_close(b[key], a[key], 1e-4, key)
+
+
+def test_only_requested_gradients_are_written():
+    wl = sg.config1()
+    G = sg.upstream_grad(8, 64, 64, 3)
+    full = gpu_render(wl.scene, wl.camera, wl.params, G)
+    part = gpu_render(wl.scene, wl.camera, wl.params, G, need={"payload", "bg"})
+    assert part["grad_pos"] is None and part["grad_radius"] is None
+    assert_close(part["grad_payload"], full["grad_payload"], 1e-5, "payload")
+    assert_close(part["grad_bg"], full["grad_bg"], 1e-5, "bg")
