@@ -80,7 +80,7 @@ typedef struct pulsar_params {
   int32_t K;            /* nearest hits per pixel that receive gradients, 1..32 */
   uint32_t flags;       /* reserved, must be 0 */
   int32_t max_pairs;    /* capacity of (screen tile, sphere) pairs; 0 = default
-                           (4 n + number of tiles + 65536) */
+                           (2 n + number of tiles + 65536) */
   int32_t depth_bits;   /* depth quantisation of the sort key; 0 = automatic.
                            Changes only the summation order, not the result. */
   int32_t reserved;     /* must be 0 */

@@ -209,6 +209,107 @@ __global__ void k_tile_ranges(const uint32_t* __restrict__ keys,
   ranges[t] = lo;
 }
 
+// ---------------------------------------------------------------- work items
+// Each tile's list is cut into chunks of at most kChunk records; an empty tile
+// still gets one chunk (it renders the background). Tiles with several chunks
+// need one partial blend state per chunk, merged afterwards.
+__device__ __forceinline__ void tile_chunks(const uint32_t* __restrict__ ranges, int t, int T,
+                                            uint32_t& n, uint32_t& m) {
+  n = 0;
+  m = 0;
+  if (t < T) {
+    const uint32_t L = ranges[t + 1] - ranges[t];
+    n = L == 0 ? 1u : (L + kChunk - 1) / kChunk;
+    m = n >= 2 ? n : 0u;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_chunk_count(const uint32_t* __restrict__ ranges, int T,
+                                                     uint2* __restrict__ cpart) {
+  __shared__ uint32_t s_n[256 / kWave], s_m[256 / kWave];
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  uint32_t n, m;
+  tile_chunks(ranges, t, T, n, m);
+  n = wave_sum_u32(n);
+  m = wave_sum_u32(m);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    s_n[threadIdx.x / kWave] = n;
+    s_m[threadIdx.x / kWave] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t a = 0, b = 0;
+    for (int w = 0; w < 256 / kWave; ++w) {
+      a += s_n[w];
+      b += s_m[w];
+    }
+    cpart[blockIdx.x] = make_uint2(a, b);
+  }
+}
+
+// Single block: exclusive scan of the per-block (chunks, partials) sums.
+__global__ __launch_bounds__(kScanThreads) void k_chunk_scan(uint2* __restrict__ cpart,
+                                                             int nblk, long long pcap,
+                                                             Status* __restrict__ status) {
+  __shared__ uint32_t s_n[kScanThreads / kWave], s_m[kScanThreads / kWave];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  uint32_t cn = 0, cm = 0;
+  for (int base = 0; base < nblk; base += kScanThreads) {
+    const int i = base + tid;
+    const uint2 v = i < nblk ? cpart[i] : make_uint2(0u, 0u);
+    const uint32_t in = wave_incl_scan_u32(v.x, lane), im = wave_incl_scan_u32(v.y, lane);
+    if (lane == kWave - 1) {
+      s_n[wid] = in;
+      s_m[wid] = im;
+    }
+    __syncthreads();
+    uint32_t bn = 0, bm = 0, tn = 0, tm = 0;
+    for (int w = 0; w < kScanThreads / kWave; ++w) {
+      if (w < wid) {
+        bn += s_n[w];
+        bm += s_m[w];
+      }
+      tn += s_n[w];
+      tm += s_m[w];
+    }
+    if (i < nblk) cpart[i] = make_uint2(cn + bn + in - v.x, cm + bm + im - v.y);
+    cn += tn;
+    cm += tm;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    status->nchunks = cn;
+    status->npartials = cm;
+    if ((long long)cm > pcap) status->code = uint32_t(-PULSAR_ERR_CAPACITY);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_chunk_emit(const uint32_t* __restrict__ ranges, int T,
+                                                    const uint2* __restrict__ cpart,
+                                                    uint4* __restrict__ tinfo,
+                                                    uint2* __restrict__ desc) {
+  __shared__ uint32_t s_n[256 / kWave], s_m[256 / kWave];
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  uint32_t n, m;
+  tile_chunks(ranges, t, T, n, m);
+  const uint32_t in = wave_incl_scan_u32(n, lane), im = wave_incl_scan_u32(m, lane);
+  if (lane == kWave - 1) {
+    s_n[wid] = in;
+    s_m[wid] = im;
+  }
+  __syncthreads();
+  uint32_t bn = cpart[blockIdx.x].x, bm = cpart[blockIdx.x].y;
+  for (int w = 0; w < wid; ++w) {
+    bn += s_n[w];
+    bm += s_m[w];
+  }
+  if (t >= T) return;
+  const uint32_t coff = bn + in - n, poff = bm + im - m;
+  tinfo[t] = make_uint4(coff, n, poff, 0u);
+  for (uint32_t ci = 0; ci < n; ++ci) desc[coff + ci] = make_uint2(uint32_t(t), ci);
+}
+
 void launch_binning(const Plan& q, char* ws, hipStream_t stream) {
   Status* status = ws_ptr<Status>(ws, q.off_status);
   auto* partials = ws_ptr<unsigned long long>(ws, q.off_partials);
@@ -240,8 +341,15 @@ void launch_binning(const Plan& q, char* ws, hipStream_t stream) {
   }
   const uint32_t* ksorted = sorted_in_a(q) ? kA : kB;
   const int T = int(q.T);
+  uint32_t* ranges = ws_ptr<uint32_t>(ws, q.off_ranges);
   hipLaunchKernelGGL(k_tile_ranges, dim3((T + 1 + 255) / 256), dim3(256), 0, stream, ksorted,
-                     status, T, q.depth_bits, ws_ptr<uint32_t>(ws, q.off_ranges));
+                     status, T, q.depth_bits, ranges);
+  uint2* cpart = ws_ptr<uint2>(ws, q.off_cpart);
+  hipLaunchKernelGGL(k_chunk_count, dim3(q.nblk_tiles), dim3(256), 0, stream, ranges, T, cpart);
+  hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kScanThreads), 0, stream, cpart, q.nblk_tiles,
+                     (long long)q.pcap, status);
+  hipLaunchKernelGGL(k_chunk_emit, dim3(q.nblk_tiles), dim3(256), 0, stream, ranges, T, cpart,
+                     ws_ptr<uint4>(ws, q.off_tinfo), ws_ptr<uint2>(ws, q.off_desc));
 }
 
 }  // namespace pulsar

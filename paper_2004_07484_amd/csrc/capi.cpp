@@ -83,8 +83,8 @@ void stage_begin(int stage, hipStream_t stream) {
   std::lock_guard<std::mutex> lk(g_timing_mu);
   hipEvent_t e;
   if (hipEventCreate(&e) != hipSuccess) return;
-  hipEventRecord(e, stream);
-  if (g_open[stage]) hipEventDestroy(g_open[stage]);
+  (void)hipEventRecord(e, stream);
+  if (g_open[stage]) (void)hipEventDestroy(g_open[stage]);
   g_open[stage] = e;
 }
 
@@ -94,7 +94,7 @@ void stage_end(int stage, hipStream_t stream) {
   if (!g_open[stage]) return;
   hipEvent_t e;
   if (hipEventCreate(&e) != hipSuccess) return;
-  hipEventRecord(e, stream);
+  (void)hipEventRecord(e, stream);
   g_marks.push_back(Mark{stage, g_open[stage], e});
   g_open[stage] = nullptr;
 }
@@ -125,7 +125,7 @@ int make_plan(int64_t n, int W, int H, int C, const pulsar_params_t* p, Plan* ou
   }
   if (q.tile_bits + q.depth_bits > 32) return PULSAR_ERR_UNSUPPORTED;
   q.passes = (q.tile_bits + q.depth_bits + 7) / 8;
-  int64_t cap = p->max_pairs > 0 ? int64_t(p->max_pairs) : 4 * n + q.T + 65536;
+  int64_t cap = p->max_pairs > 0 ? int64_t(p->max_pairs) : 2 * n + q.T + 65536;
   if (cap > (int64_t(1) << 31) - 1) cap = (int64_t(1) << 31) - 1;
   q.cap = cap;
   q.nblk_proj = int((n + kProjectBlock - 1) / kProjectBlock);
@@ -143,6 +143,8 @@ int make_plan(int64_t n, int W, int H, int C, const pulsar_params_t* p, Plan* ou
   q.off_qdepth = take(nn * 4);
   q.off_recA = take(nn * 16);
   q.off_recB = take(nn * 16);
+  q.off_recC = take(nn * 16);
+  q.off_recD = take(nn * 16);
   q.off_gacc = take(nn * 16);
   q.off_partials = take(size_t(q.nblk_proj + 1) * 8);
   q.off_keysA = take(size_t(cap) * 4);
@@ -153,6 +155,19 @@ int make_plan(int64_t n, int W, int H, int C, const pulsar_params_t* p, Plan* ou
   q.off_dtot = take(size_t(kSortRadix) * 4);
   q.off_ranges = take(size_t(q.T + 1) * 4);
   q.off_bgpart = take(size_t(q.T) * size_t(C) * 4);
+  q.max_chunks = (cap + kChunk - 1) / kChunk + q.T;
+  q.pcap = (cap + kChunk - 1) / kChunk + 1024;
+  q.nblk_tiles = int((q.T + 255) / 256);
+  q.fwd_cm = C < kFwdChannels ? C : kFwdChannels;
+  int km = 4;  // register K-list slots: a power of two >= K, at least 4
+  while (km < p->K) km *= 2;
+  q.klist_slots = km;
+  q.pstride = 2 + q.fwd_cm + 2 * km;  // m, D, numerator[cm], K-list (t, id)
+  q.off_tinfo = take(size_t(q.T) * 16);
+  q.off_desc = take(size_t(q.max_chunks) * 8);
+  q.off_cpart = take(size_t(q.nblk_tiles + 1) * 8);
+  q.off_pstate = take(size_t(q.pcap) * kWave * size_t(q.pstride) * 4);
+  q.off_thr = take(size_t(W) * size_t(H) * 8);
   q.total = o;
   *out = q;
   return PULSAR_OK;
@@ -221,6 +236,7 @@ int pulsar_fwd(const float* pos, const float* radius, const float* opacity,
   a.bg = background;
   a.n = n;
   a.C = C;
+  a.K = params->K;
   a.image = image;
   a.aux = aux;
   a.min_radius_px = params->min_radius_px;
@@ -317,8 +333,8 @@ int pulsar_timing_read(double* total_ms, int64_t* counts) {
       if (total_ms) total_ms[m.stage] += double(ms);
       if (counts) counts[m.stage] += 1;
     }
-    hipEventDestroy(m.begin);
-    hipEventDestroy(m.end);
+    (void)hipEventDestroy(m.begin);
+    (void)hipEventDestroy(m.end);
   }
   g_marks.clear();
   return rc;

@@ -1,0 +1,173 @@
+// Ray-sphere geometry shared by the raster kernels.
+//
+// A pixel ray is v = (x_s, y_s, f) through the pixel centre on the sensor
+// plane z = f. With D = pixel - projected sphere centre in pixel units and
+// (a_x, a_y) = (c_x, c_y) / c_z, the squared normalised distance of the centre
+// from the ray is
+//     r2 = q^2 / R^2 = kappa (D_x^2 + D_y^2 + (a_x D_y - a_y D_x)^2) / |v|^2,
+//     kappa = (c_z pitch / R)^2,
+// because |c x v| = c_z pitch |(-D_y, D_x, a_x D_y - a_y D_x)| (no cancellation).
+//
+// Near the silhouette the image depends on e = 1 - r2 with a gain of up to
+// o exp(o z / gamma), far beyond what FP32 rounding of r2 allows. So a cheap
+// FP32 test only rejects clear misses, and every candidate is decided and
+// measured in FP64 from double-float records (hi + lo FP32 pairs), after which
+// d = 1 - q/R = e / (1 + sqrt(1 - e)) keeps full relative accuracy.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "device_common.h"
+#include "pulsar_internal.h"
+
+namespace pulsar {
+
+// FP32 rejection threshold on r2: generous against FP32 rounding of the
+// record's high parts, so no hit of the exact test is ever rejected.
+constexpr float kRejectR2 = 1.015625f;
+
+struct PixelRay {
+  int px, py;
+  float xs, ys;       // sensor-plane coordinates of the pixel centre
+  float ux, uy, uz;   // unit ray
+  float inv_v2;       // 1 / |v|^2
+  double inv_v2_d;    // the same in FP64
+};
+
+__device__ __forceinline__ PixelRay make_ray(const CamDev& cam, int px, int py) {
+#pragma clang fp contract(off)
+  PixelRay r;
+  r.px = px;
+  r.py = py;
+  r.xs = (float(px) + 0.5f) * cam.pitch - 0.5f * cam.s;
+  r.ys = (float(py) + 0.5f) * cam.pitch - 0.5f * cam.sh;
+  const float v2 = r.xs * r.xs + r.ys * r.ys + cam.f * cam.f;
+  r.inv_v2 = 1.f / v2;
+  const float inv_len = 1.f / sqrtf(v2);
+  r.ux = r.xs * inv_len;
+  r.uy = r.ys * inv_len;
+  r.uz = cam.f * inv_len;
+  const double pitch = double(cam.s) / double(cam.W);
+  const double xs = (double(px) + 0.5) * pitch - 0.5 * double(cam.s);
+  const double ys = (double(py) + 0.5) * pitch - 0.5 * double(cam.s) * double(cam.H) / double(cam.W);
+  r.inv_v2_d = 1.0 / (xs * xs + ys * ys + double(cam.f) * double(cam.f));
+  return r;
+}
+
+// One sphere record in registers (uniform across the wave when broadcast).
+struct SphereRec {
+  int x0, y0;           // first pixel of its rectangle
+  float xh, yh, kh;     // high parts: centre offset from (x0, y0), kappa
+  float axh, ayh;       // high parts of c_x / c_z, c_y / c_z
+  float cz, R, o;
+  float xl, yl, kl, axl, ayl;  // low parts
+};
+
+// Cheap FP32 rejection. Returns r2 (only meaningful when < kRejectR2).
+__device__ __forceinline__ float coarse_r2(const PixelRay& ray, int x0, int y0, float xh,
+                                           float yh, float kh, float axh, float ayh) {
+  const float dx = float(ray.px - x0) - xh;
+  const float dy = float(ray.py - y0) - yh;
+  const float cr = axh * dy - ayh * dx;
+  return kh * (dx * dx + dy * dy + cr * cr) * ray.inv_v2;
+}
+
+struct Hit {
+  float e;      // 1 - q^2/R^2, accurate to FP64 rounding
+  float delta;  // 1 - q/R
+  float sq;     // sqrt(1 - q^2/R^2) = sqrt(R^2 - q^2) / R
+  float ratio;  // q / R
+  float t;      // distance to the front intersection
+  float dx, dy, cr;  // D and the cross term (pixel units), for the gradient direction
+};
+
+// Exact test. Returns true on a hit (q < R and t <= zfar) and fills h.
+__device__ __forceinline__ bool exact_hit(const PixelRay& ray, const SphereRec& s, float zfar,
+                                          Hit& h) {
+  // every kernel must see bitwise the same t for the same (pixel, sphere)
+#pragma clang fp contract(off)
+  const double X = double(s.xh) + double(s.xl);
+  const double Y = double(s.yh) + double(s.yl);
+  const double dx = double(ray.px - s.x0) - X;
+  const double dy = double(ray.py - s.y0) - Y;
+  const double ax = double(s.axh) + double(s.axl);
+  const double ay = double(s.ayh) + double(s.ayl);
+  const double cr = ax * dy - ay * dx;
+  const double S = dx * dx + dy * dy + cr * cr;
+  const double r2 = (double(s.kh) + double(s.kl)) * S * ray.inv_v2_d;
+  if (!(r2 < 1.0)) return false;
+  const float e = float(1.0 - r2);
+  const float sq = fast_sqrt(e);
+  const float ratio = fast_sqrt(float(r2));
+  const float t = s.cz * (ray.ux * s.axh + ray.uy * s.ayh + ray.uz) - s.R * sq;
+  if (!(t <= zfar)) return false;
+  h.e = e;
+  h.sq = sq;
+  h.ratio = ratio;
+  h.delta = e / (1.f + ratio);
+  h.t = t;
+  h.dx = float(dx);
+  h.dy = float(dy);
+  h.cr = float(cr);
+  return true;
+}
+
+// The same ray as make_ray, from per-tile LDS copies of its fields.
+struct TileRays {
+  float xs[kWave], ys[kWave], ux[kWave], uy[kWave], uz[kWave], iv2[kWave];
+  double iv2d[kWave];
+};
+
+__device__ __forceinline__ void store_ray(TileRays& tr, int pl, const PixelRay& r) {
+  tr.xs[pl] = r.xs;
+  tr.ys[pl] = r.ys;
+  tr.ux[pl] = r.ux;
+  tr.uy[pl] = r.uy;
+  tr.uz[pl] = r.uz;
+  tr.iv2[pl] = r.inv_v2;
+  tr.iv2d[pl] = r.inv_v2_d;
+}
+
+__device__ __forceinline__ PixelRay load_ray(const TileRays& tr, int pl, int px, int py) {
+  PixelRay r;
+  r.px = px;
+  r.py = py;
+  r.xs = tr.xs[pl];
+  r.ys = tr.ys[pl];
+  r.ux = tr.ux[pl];
+  r.uy = tr.uy[pl];
+  r.uz = tr.uz[pl];
+  r.inv_v2 = tr.iv2[pl];
+  r.inv_v2_d = tr.iv2d[pl];
+  return r;
+}
+
+// Record loads: four float4 per sphere (see k_project for the layout).
+__device__ __forceinline__ SphereRec load_rec(const float4* __restrict__ recA,
+                                              const float4* __restrict__ recB,
+                                              const float4* __restrict__ recC,
+                                              const float4* __restrict__ recD, uint32_t id) {
+  const float4 a = recA[id], b = recB[id], c = recC[id], d = recD[id];
+  SphereRec s;
+  const uint32_t pk = __float_as_uint(a.w);
+  s.x0 = int(pk & 0xffffu);
+  s.y0 = int(pk >> 16);
+  s.xh = a.x;
+  s.yh = a.y;
+  s.kh = a.z;
+  s.axh = b.x;
+  s.ayh = b.y;
+  s.cz = b.z;
+  s.R = b.w;
+  s.xl = c.x;
+  s.yl = c.y;
+  s.kl = c.z;
+  s.axl = c.w;
+  s.ayl = d.x;
+  s.o = d.y;
+  return s;
+}
+
+}  // namespace pulsar

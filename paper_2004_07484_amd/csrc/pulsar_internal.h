@@ -22,13 +22,18 @@ constexpr int kSortBlock = kSortThreads * kSortRounds;  // keys per sort block
 constexpr int kSortRadix = 256;              // 8-bit digits
 constexpr int kMaxK = 32;
 constexpr int kFwdChannels = 32;             // channels per forward pass (more: several passes)
+constexpr int kBwdChannels = 32;             // channels kept in registers by the backward
+constexpr int kChunk = 128;                  // sphere records per raster work item
+constexpr int kRasterGrid = 4096;            // persistent raster grid (one wave per block)
 
 // Device status block at the start of the workspace.
 struct Status {
   uint32_t code;                // PULSAR_OK or PULSAR_ERR_CAPACITY
   uint32_t used;                // pairs actually stored: min(pairs, capacity)
   unsigned long long pairs;     // pairs the scene produced
-  uint32_t pad[60];
+  uint32_t nchunks;             // raster work items (chunks of <= kChunk records of one tile)
+  uint32_t npartials;           // partial blend states needed by tiles with several chunks
+  uint32_t pad[58];
 };
 
 // Camera constants in the form the kernels use.
@@ -54,9 +59,17 @@ struct BlendConst {
 struct Plan {
   int64_t n, C, W, H, T, tiles_x, tiles_y, cap;
   int tile_bits, depth_bits, passes, nblk_proj, nblk_sort;
-  size_t off_status, off_counts, off_trect, off_qdepth, off_recA, off_recB, off_gacc;
+  size_t off_status, off_counts, off_trect, off_qdepth, off_recA, off_recB, off_recC, off_recD;
+  size_t off_gacc;
   size_t off_partials, off_keysA, off_valsA, off_keysB, off_valsB, off_hist, off_dtot;
-  size_t off_ranges, off_bgpart, total;
+  size_t off_ranges, off_bgpart;
+  // raster work items: per-tile (first chunk, chunks, first partial slot), the
+  // chunk list (tile, index within tile), block sums of the chunk scan, the
+  // partial blend states and the per-pixel K-th nearest hit (t, sphere id)
+  size_t off_tinfo, off_desc, off_cpart, off_pstate, off_thr;
+  int64_t max_chunks, pcap;
+  int nblk_tiles, fwd_cm, klist_slots, pstride;
+  size_t total;
 };
 
 // Fills `out` and returns PULSAR_OK, or returns an error code.
@@ -70,7 +83,7 @@ struct FwdArgs {
   const float* opacity;
   const float* payload;
   const float* bg;
-  int n, C;
+  int n, C, K;
   float* image;
   float* aux;
   float min_radius_px;

@@ -1,19 +1,22 @@
 // K7/K8: backward pass (paper App. B, "The Backward Pass").
 //
-// K7, one wave64 per 8x8 tile, reuses the forward's sorted tile lists and
-// recomputes each pixel's K nearest hits (ascending (t, sphere index)) into a
-// register list instead of reading stored per-pixel hit lists. The walk stops
-// as soon as the next sphere's depth lower bound exceeds the K-th distance of
-// every lane. For each list entry it evaluates the derivatives of Eq. 1 and
-// accumulates per sphere, in camera space, dL/dc (3), dL/dR, plus dL/do and
-// dL/df straight into the caller's buffers, with float atomics (many pixels
-// of one tile and of neighbouring tiles update the same sphere).
-// The background gradient is reduced per tile into a partial buffer.
+// The forward left, per pixel, the K-th nearest hit (t_K, sphere index) and
+// the log-normaliser L. A hit (t, k) of pixel p receives gradients iff it is
+// among the K nearest, i.e. k is the K-th one or (t, k) < (t_K, k_K); nothing
+// else per pixel is stored, every intersection is recomputed here.
+//
+// K7 runs over the same chunks as the forward with the roles turned around:
+// lane l owns record l and walks the pixels of its rectangle inside the tile,
+// so each lane accumulates its own sphere's derivatives of Eq. 1 in registers
+// (camera-space dL/dc, dL/dR, dL/do, dL/df) and flushes them once per chunk
+// with float atomics (a sphere meets several chunks only when its rectangle
+// spans tiles or its tile list is split). The tile's G, F, L, thresholds and
+// rays are staged once per chunk in LDS. The first chunk of each tile also
+// writes the tile's background-gradient partial.
 //
 // K8 turns the camera-space accumulators into world-space position and
 // radius gradients; K8b sums the per-tile background partials.
-#include "device_common.h"
-#include "pulsar_internal.h"
+#include "hit_geometry.h"
 
 namespace pulsar {
 
@@ -23,147 +26,242 @@ __global__ void k_zero(float* __restrict__ p, size_t count) {
     p[i] = 0.f;
 }
 
-template <int KM>
-__global__ __launch_bounds__(kWave) void k_raster_bwd(
-    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ skeys,
-    const uint32_t* __restrict__ svals, const float4* __restrict__ recA,
-    const float4* __restrict__ recB, const float* __restrict__ opacity,
-    const float* __restrict__ payload, int C, int K, int depth_bits, float depth_step,
-    CamDev cam, BlendConst bc, const float* __restrict__ image, const float* __restrict__ aux,
-    const float* __restrict__ grad_image, float* __restrict__ gacc,
-    float* __restrict__ grad_opacity, float* __restrict__ grad_payload,
-    float* __restrict__ bgpart) {
-  const int tile = blockIdx.x;
+struct BwdKernelArgs {
+  const Status* status;
+  const uint2* desc;
+  const uint32_t* ranges;
+  const uint32_t* svals;
+  const float4* recA;
+  const float4* recB;
+  const float4* recC;
+  const float4* recD;
+  const float* payload;
+  const float* image;
+  const float* aux;
+  const float* grad_image;
+  const float2* thr;
+  float* gacc;
+  float* grad_opacity;
+  float* grad_payload;
+  float* bgpart;
+  int C;
+};
+
+// CM >= C: channels kept in LDS and registers.
+template <int CM>
+__global__ __launch_bounds__(kWave) void k_bwd_chunks(BwdKernelArgs A, CamDev cam,
+                                                      BlendConst bc) {
+  __shared__ TileRays s_ray;
+  __shared__ float s_G[CM][kWave], s_F[CM][kWave];
+  __shared__ float s_L2[kWave], s_tk[kWave];
+  __shared__ uint32_t s_ik[kWave];
   const int lane = threadIdx.x;
-  const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
-  const int px = tx * kTileW + (lane % kTileW);
-  const int py = ty * kTileH + (lane / kTileW);
-  const bool inside = px < cam.W && py < cam.H;
-  const size_t p = inside ? size_t(py) * size_t(cam.W) + size_t(px) : 0;
-  const float xs = (float(px) + 0.5f) * cam.pitch - 0.5f * cam.s;
-  const float ys = (float(py) + 0.5f) * cam.pitch - 0.5f * cam.sh;
-  const float v2 = xs * xs + ys * ys + cam.f * cam.f;
-  const float inv_v2 = 1.f / v2;
-  const float inv_len = 1.f / sqrtf(v2);
-  const float ux = xs * inv_len, uy = ys * inv_len, uz = cam.f * inv_len;
-  const float L2 = inside ? aux[p] * 1.4426950408889634f : 0.f;
-
-  // Background: dL/dbg = sum_p exp(eps/gamma - L_p) G_p, one partial per tile.
-  if (bgpart) {
-    const float wbg = inside ? fast_exp2(bc.eps2 - L2) : 0.f;
-    for (int c = 0; c < C; ++c) {
-      const float g = inside ? grad_image[p * size_t(C) + c] : 0.f;
-      const float s = wave_sum(wbg * g);
-      if (lane == 0) bgpart[size_t(tile) * size_t(C) + c] = s;
+  const int C = A.C;
+  const uint32_t nchunks = A.status->nchunks;
+  for (uint32_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+    const uint2 dsc = A.desc[chunk];
+    const int tile = int(dsc.x), ci = int(dsc.y);
+    const uint32_t beg = A.ranges[tile] + uint32_t(ci) * kChunk;
+    const uint32_t end = min(A.ranges[tile + 1], beg + kChunk);
+    const int tx0 = (tile % cam.tiles_x) * kTileW, ty0 = (tile / cam.tiles_x) * kTileH;
+    if (beg >= end && !(ci == 0 && A.bgpart)) continue;  // empty tile, nothing to do
+    // stage the tile's pixels (lane = pixel)
+    const int px = tx0 + (lane % kTileW), py = ty0 + (lane / kTileW);
+    const bool inside = px < cam.W && py < cam.H;
+    const size_t p = inside ? size_t(py) * size_t(cam.W) + size_t(px) : 0;
+    const float L2 = inside ? A.aux[p] * 1.4426950408889634f : 0.f;
+    __syncthreads();  // the previous chunk's LDS reads are done
+    store_ray(s_ray, lane, make_ray(cam, px, py));
+    s_L2[lane] = L2;
+    const float2 th = inside ? A.thr[p] : make_float2(-INFINITY, 0.f);
+    s_tk[lane] = th.x;
+    s_ik[lane] = __float_as_uint(th.y);
+#pragma unroll
+    for (int c = 0; c < CM; ++c) {
+      s_G[c][lane] = (inside && c < C) ? A.grad_image[p * size_t(C) + c] : 0.f;
+      s_F[c][lane] = (inside && c < C) ? A.image[p * size_t(C) + c] : 0.f;
     }
-  }
-
-  // K nearest hits. The list lives in the last K of KM slots, ascending; the
-  // unused leading slots hold -inf and never move, so the K-th distance is
-  // always kt[KM - 1].
-  float kt[KM];
-  uint32_t kid[KM];
+    if (ci == 0 && A.bgpart) {
+      // dL/dbg = sum_p exp(eps/gamma - L_p) G_p
+      const float wbg = inside ? fast_exp2(bc.eps2 - L2) : 0.f;
 #pragma unroll
-  for (int i = 0; i < KM; ++i) {
-    kt[i] = i < KM - K ? -INFINITY : INFINITY;
-    kid[i] = 0xffffffffu;
-  }
-  const uint32_t beg = ranges[tile], end = ranges[tile + 1];
-  const uint32_t qmask = (1u << depth_bits) - 1u;
-  bool done = false;
-  for (uint32_t base = beg; base < end && !done; base += kWave) {
-    const uint32_t j = base + uint32_t(lane);
-    const bool valid = j < end;
-    const uint32_t id = valid ? svals[j] : 0u;
-    const float lbv = valid ? cam.znear + float(skeys[j] & qmask) * depth_step : INFINITY;
-    const float4 a = valid ? recA[id] : make_float4(0.f, 0.f, 0.f, 0.f);
-    const float4 b = valid ? recB[id] : make_float4(0.f, 0.f, 1.f, 1.f);
-    const int cnt = int(min(uint32_t(kWave), end - base));
-    for (int k = 0; k < cnt; ++k) {
-      // every lane already holds K hits nearer than anything left in the list
-      if (__all(!inside || kt[KM - 1] < rl(lbv, k))) {
-        done = true;
-        break;
+      for (int c = 0; c < CM; ++c) {
+        if (c < C) {
+          const float sum = wave_sum(wbg * s_G[c][lane]);
+          if (lane == 0) A.bgpart[size_t(tile) * size_t(C) + c] = sum;
+        }
       }
-      const uint32_t pk = rlu(__float_as_uint(a.w), k);
-      const float dx = float(px - int(pk & 0xffffu)) - rl(a.x, k);
-      const float dy = float(py - int(pk >> 16)) - rl(a.y, k);
-      const float axf = rl(b.x, k), ayf = rl(b.y, k);
-      const float cr = axf * dy - ayf * dx;
-      const float S = dx * dx + dy * dy + cr * cr;
-      const float r2 = rl(a.z, k) * S * inv_v2;
-      if (r2 < 1.f) {
-        const float cz = rl(b.z, k), R = rl(b.w, k);
-        float t = cz * (ux * axf + uy * ayf + uz) - R * fast_sqrt(1.f - r2);
-        uint32_t idk = rlu(id, k);
-        if (t <= bc.zfar && (t < kt[KM - 1] || (t == kt[KM - 1] && idk < kid[KM - 1]))) {
-          // insertion: carry the new entry up the ascending list
+    }
+    __syncthreads();
+    for (uint32_t b0 = beg; b0 < end; b0 += kWave) {
+      const uint32_t j = b0 + uint32_t(lane);
+      if (j >= end) continue;
+      const uint32_t id = A.svals[j];
+      const SphereRec s = load_rec(A.recA, A.recB, A.recC, A.recD, id);
+      const uint32_t p1 = __float_as_uint(A.recD[id].z);
+      float fk[CM];
+      const float* fp = A.payload + size_t(id) * size_t(C);
 #pragma unroll
-          for (int i = 0; i < KM; ++i) {
-            const bool lt = t < kt[i] || (t == kt[i] && idk < kid[i]);
-            const float tt = kt[i];
-            const uint32_t ti = kid[i];
-            kt[i] = lt ? t : tt;
-            kid[i] = lt ? idk : ti;
-            t = lt ? tt : t;
-            idk = lt ? ti : idk;
-          }
+      for (int c = 0; c < CM; ++c) fk[c] = c < C ? fp[c] : 0.f;
+      float gcx = 0.f, gcy = 0.f, gcz = 0.f, gR = 0.f, go = 0.f, gf[CM];
+#pragma unroll
+      for (int c = 0; c < CM; ++c) gf[c] = 0.f;
+      bool any = false;
+      const int xa = max(s.x0, tx0), xb = min(int(p1 & 0xffffu), tx0 + kTileW - 1);
+      const int ya = max(s.y0, ty0), yb = min(int(p1 >> 16), ty0 + kTileH - 1);
+      for (int iy = ya; iy <= yb; ++iy) {
+        for (int ix = xa; ix <= xb; ++ix) {
+          const int pl = (iy - ty0) * kTileW + (ix - tx0);
+          const PixelRay ray = load_ray(s_ray, pl, ix, iy);
+          if (!(coarse_r2(ray, s.x0, s.y0, s.xh, s.yh, s.kh, s.axh, s.ayh) < kRejectR2)) continue;
+          Hit h;
+          if (!exact_hit(ray, s, bc.zfar, h)) continue;
+          // among the pixel's K nearest hits?
+          const float tk = s_tk[pl];
+          const uint32_t ik = s_ik[pl];
+          if (!(id == ik || h.t < tk || (h.t == tk && id < ik))) continue;
+          any = true;
+          const float o = s.o;
+          const float s2 = o * (bc.zfar - h.t) * bc.kz;  // o z / gamma in base 2
+          const float ex = fast_exp2(s2 - s_L2[pl]);      // exp(o z / gamma) / denominator
+          const float e = h.delta * ex;                   // dw/do without the exponent term
+          const float w = o * e;                          // blending weight of Eq. 1
+          float hs = 0.f;                                 // G . (f_k - F)
+#pragma unroll
+          for (int c = 0; c < CM; ++c) hs += s_G[c][pl] * (fk[c] - s_F[c][pl]);
+#pragma unroll
+          for (int c = 0; c < CM; ++c) gf[c] += w * s_G[c][pl];
+          go += e * hs * (1.f + o * (bc.zfar - h.t) * bc.inv_span * bc.inv_gamma);
+          const float gt = -w * hs * o * bc.inv_gamma * bc.inv_span;  // dL/dt
+          const float gd = o * ex * hs;                               // dL/d(1 - q/R)
+          // (c - (u.c) u) / R = sqrt(kappa) (v x (-D_y, D_x, cr)) / |v|^2
+          const float sk = fast_sqrt(s.kh) * ray.inv_v2;
+          const float dnx = (ray.ys * h.cr - cam.f * h.dx) * sk;
+          const float dny = (-cam.f * h.dy - ray.xs * h.cr) * sk;
+          const float dnz = (ray.xs * h.dx + ray.ys * h.dy) * sk;
+          const float coef = gt / h.sq - (h.ratio > 0.f ? gd / (s.R * h.ratio) : 0.f);
+          gcx += gt * ray.ux + coef * dnx;
+          gcy += gt * ray.uy + coef * dny;
+          gcz += gt * ray.uz + coef * dnz;
+          gR += -gt / h.sq + gd * h.ratio / s.R;
+        }
+      }
+      if (any) {
+        if (A.grad_payload) {
+          float* g = A.grad_payload + size_t(id) * size_t(C);
+#pragma unroll
+          for (int c = 0; c < CM; ++c)
+            if (c < C) atomicAdd(g + c, gf[c]);
+        }
+        if (A.grad_opacity) atomicAdd(A.grad_opacity + id, go);
+        if (A.gacc) {
+          float* g = A.gacc + size_t(id) * 4;
+          atomicAdd(g + 0, gcx);
+          atomicAdd(g + 1, gcy);
+          atomicAdd(g + 2, gcz);
+          atomicAdd(g + 3, gR);
         }
       }
     }
   }
+}
 
-  // Gradients of Eq. 1 for each of the K entries.
-  const float* Gp = grad_image + p * size_t(C);
-  const float* Fp = image + p * size_t(C);
-#pragma unroll
-  for (int i = 0; i < KM; ++i) {
-    if (i < KM - K) continue;
-    if (!(inside && kt[i] < INFINITY)) continue;
-    const uint32_t id = kid[i];
-    const float4 a = recA[id];
-    const float4 b = recB[id];
-    const float o = opacity ? opacity[id] : 1.f;
-    const uint32_t pk = __float_as_uint(a.w);
-    const float dx = float(px - int(pk & 0xffffu)) - a.x;
-    const float dy = float(py - int(pk >> 16)) - a.y;
-    const float axf = b.x, ayf = b.y, cz = b.z, R = b.w;
-    const float cr = axf * dy - ayf * dx;
-    const float S = dx * dx + dy * dy + cr * cr;
-    // the list walk saw r2 < 1; keep it below 1 if this recomputation rounds differently
-    const float r2 = fminf(a.z * S * inv_v2, 0.99999994f);
-    const float sq = fast_sqrt(1.f - r2);  // sqrt(R^2 - q^2) / R
-    const float ratio = fast_sqrt(r2);    // q / R
-    const float t = cz * (ux * axf + uy * ayf + uz) - R * sq;
-    const float s2 = o * (bc.zfar - t) * bc.kz;   // o z / gamma in base 2
-    const float ex = fast_exp2(s2 - L2);          // exp(o z / gamma) / denominator
-    const float e = (1.f - ratio) * ex;           // dw/do without the exponent term
-    const float w = o * e;                        // blending weight of Eq. 1
-    const float* fk = payload + size_t(id) * size_t(C);
-    float h = 0.f;                                // G . (f_k - F)
-    for (int c = 0; c < C; ++c) h += Gp[c] * (fk[c] - Fp[c]);
-    if (grad_payload) {
-      float* gf = grad_payload + size_t(id) * size_t(C);
-      for (int c = 0; c < C; ++c) atomicAdd(gf + c, w * Gp[c]);
+// Channels beyond the register budget: same walk, the pixel terms read from
+// global memory and payload gradients go out per hit.
+__global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A, CamDev cam,
+                                                           BlendConst bc) {
+  __shared__ TileRays s_ray;
+  __shared__ float s_L2[kWave], s_tk[kWave];
+  __shared__ uint32_t s_ik[kWave];
+  const int lane = threadIdx.x;
+  const int C = A.C;
+  const uint32_t nchunks = A.status->nchunks;
+  for (uint32_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+    const uint2 dsc = A.desc[chunk];
+    const int tile = int(dsc.x), ci = int(dsc.y);
+    const uint32_t beg = A.ranges[tile] + uint32_t(ci) * kChunk;
+    const uint32_t end = min(A.ranges[tile + 1], beg + kChunk);
+    const int tx0 = (tile % cam.tiles_x) * kTileW, ty0 = (tile / cam.tiles_x) * kTileH;
+    if (beg >= end && !(ci == 0 && A.bgpart)) continue;
+    const int px = tx0 + (lane % kTileW), py = ty0 + (lane / kTileW);
+    const bool inside = px < cam.W && py < cam.H;
+    const size_t p = inside ? size_t(py) * size_t(cam.W) + size_t(px) : 0;
+    const float L2 = inside ? A.aux[p] * 1.4426950408889634f : 0.f;
+    __syncthreads();
+    store_ray(s_ray, lane, make_ray(cam, px, py));
+    s_L2[lane] = L2;
+    const float2 th = inside ? A.thr[p] : make_float2(-INFINITY, 0.f);
+    s_tk[lane] = th.x;
+    s_ik[lane] = __float_as_uint(th.y);
+    if (ci == 0 && A.bgpart) {
+      const float wbg = inside ? fast_exp2(bc.eps2 - L2) : 0.f;
+      for (int c = 0; c < C; ++c) {
+        const float g = inside ? A.grad_image[p * size_t(C) + c] : 0.f;
+        const float sum = wave_sum(wbg * g);
+        if (lane == 0) A.bgpart[size_t(tile) * size_t(C) + c] = sum;
+      }
     }
-    if (grad_opacity) {
-      const float oz_g = o * (bc.zfar - t) * bc.inv_span * bc.inv_gamma;
-      atomicAdd(grad_opacity + id, e * h * (1.f + oz_g));
-    }
-    if (gacc) {
-      const float gt = -w * h * o * bc.inv_gamma * bc.inv_span;  // dL/dt
-      const float gd = o * ex * h;                                // dL/d(1 - q/R)
-      // d = c - (u.c) u = sqrt(kappa) (v x (-D_y, D_x, cr)) / |v|^2 * R
-      const float sk = fast_sqrt(a.z) * inv_v2;
-      const float dnx = (ys * cr - cam.f * dx) * sk;
-      const float dny = (-cam.f * dy - xs * cr) * sk;
-      const float dnz = (xs * dx + ys * dy) * sk;
-      const float coef = gt / sq - (ratio > 0.f ? gd / (R * ratio) : 0.f);
-      float* g = gacc + size_t(id) * 4;
-      atomicAdd(g + 0, gt * ux + coef * dnx);
-      atomicAdd(g + 1, gt * uy + coef * dny);
-      atomicAdd(g + 2, gt * uz + coef * dnz);
-      atomicAdd(g + 3, -gt / sq + gd * ratio / R);
+    __syncthreads();
+    for (uint32_t b0 = beg; b0 < end; b0 += kWave) {
+      const uint32_t j = b0 + uint32_t(lane);
+      if (j >= end) continue;
+      const uint32_t id = A.svals[j];
+      const SphereRec s = load_rec(A.recA, A.recB, A.recC, A.recD, id);
+      const uint32_t p1 = __float_as_uint(A.recD[id].z);
+      const float* fk = A.payload + size_t(id) * size_t(C);
+      float gcx = 0.f, gcy = 0.f, gcz = 0.f, gR = 0.f, go = 0.f;
+      bool any = false;
+      const int xa = max(s.x0, tx0), xb = min(int(p1 & 0xffffu), tx0 + kTileW - 1);
+      const int ya = max(s.y0, ty0), yb = min(int(p1 >> 16), ty0 + kTileH - 1);
+      for (int iy = ya; iy <= yb; ++iy) {
+        for (int ix = xa; ix <= xb; ++ix) {
+          const int pl = (iy - ty0) * kTileW + (ix - tx0);
+          const PixelRay ray = load_ray(s_ray, pl, ix, iy);
+          if (!(coarse_r2(ray, s.x0, s.y0, s.xh, s.yh, s.kh, s.axh, s.ayh) < kRejectR2)) continue;
+          Hit h;
+          if (!exact_hit(ray, s, bc.zfar, h)) continue;
+          const float tk = s_tk[pl];
+          const uint32_t ik = s_ik[pl];
+          if (!(id == ik || h.t < tk || (h.t == tk && id < ik))) continue;
+          any = true;
+          const size_t pp = size_t(iy) * size_t(cam.W) + size_t(ix);
+          const float* Gp = A.grad_image + pp * size_t(C);
+          const float* Fp = A.image + pp * size_t(C);
+          const float o = s.o;
+          const float s2 = o * (bc.zfar - h.t) * bc.kz;
+          const float ex = fast_exp2(s2 - s_L2[pl]);
+          const float e = h.delta * ex;
+          const float w = o * e;
+          float hs = 0.f;
+          for (int c = 0; c < C; ++c) hs += Gp[c] * (fk[c] - Fp[c]);
+          if (A.grad_payload) {
+            float* g = A.grad_payload + size_t(id) * size_t(C);
+            for (int c = 0; c < C; ++c) atomicAdd(g + c, w * Gp[c]);
+          }
+          go += e * hs * (1.f + o * (bc.zfar - h.t) * bc.inv_span * bc.inv_gamma);
+          const float gt = -w * hs * o * bc.inv_gamma * bc.inv_span;
+          const float gd = o * ex * hs;
+          const float sk = fast_sqrt(s.kh) * ray.inv_v2;
+          const float dnx = (ray.ys * h.cr - cam.f * h.dx) * sk;
+          const float dny = (-cam.f * h.dy - ray.xs * h.cr) * sk;
+          const float dnz = (ray.xs * h.dx + ray.ys * h.dy) * sk;
+          const float coef = gt / h.sq - (h.ratio > 0.f ? gd / (s.R * h.ratio) : 0.f);
+          gcx += gt * ray.ux + coef * dnx;
+          gcy += gt * ray.uy + coef * dny;
+          gcz += gt * ray.uz + coef * dnz;
+          gR += -gt / h.sq + gd * h.ratio / s.R;
+        }
+      }
+      if (any) {
+        if (A.grad_opacity) atomicAdd(A.grad_opacity + id, go);
+        if (A.gacc) {
+          float* g = A.gacc + size_t(id) * 4;
+          atomicAdd(g + 0, gcx);
+          atomicAdd(g + 1, gcy);
+          atomicAdd(g + 2, gcz);
+          atomicAdd(g + 3, gR);
+        }
+      }
     }
   }
 }
@@ -219,53 +317,57 @@ static void zero_async(float* p, size_t count, hipStream_t stream) {
   hipLaunchKernelGGL(k_zero, dim3(unsigned(blocks)), dim3(256), 0, stream, p, count);
 }
 
-template <int KM>
-static void launch_raster_bwd_km(const Plan& q, const CamDev& cam, const BlendConst& bc,
-                                 const BwdArgs& a, char* ws, float* gacc, float* bgpart,
-                                 hipStream_t stream) {
-  const bool in_a = sorted_in_a(q);
-  const float depth_step =
-      float((double(cam.zfar) - double(cam.znear)) / double(1u << q.depth_bits));
-  hipLaunchKernelGGL(k_raster_bwd<KM>, dim3(unsigned(q.T)), dim3(kWave), 0, stream,
-                     ws_ptr<uint32_t>(ws, q.off_ranges),
-                     ws_ptr<uint32_t>(ws, in_a ? q.off_keysA : q.off_keysB),
-                     ws_ptr<uint32_t>(ws, in_a ? q.off_valsA : q.off_valsB),
-                     ws_ptr<float4>(ws, q.off_recA), ws_ptr<float4>(ws, q.off_recB), a.opacity,
-                     a.payload, a.C, a.K, q.depth_bits, depth_step, cam, bc, a.image, a.aux,
-                     a.grad_image, gacc, a.grad_opacity, a.grad_payload, bgpart);
-}
-
 hipError_t launch_backward(const Plan& q, const CamDev& cam, const BlendConst& bc,
                            const BwdArgs& a, char* ws, hipStream_t stream) {
   const bool need_geo = a.grad_pos || a.grad_radius;
-  float* gacc = need_geo ? ws_ptr<float>(ws, q.off_gacc) : nullptr;
-  float* bgpart = a.grad_bg ? ws_ptr<float>(ws, q.off_bgpart) : nullptr;
+  BwdKernelArgs A;
+  A.status = ws_ptr<Status>(ws, q.off_status);
+  A.desc = ws_ptr<uint2>(ws, q.off_desc);
+  A.ranges = ws_ptr<uint32_t>(ws, q.off_ranges);
+  A.svals = ws_ptr<uint32_t>(ws, sorted_in_a(q) ? q.off_valsA : q.off_valsB);
+  A.recA = ws_ptr<float4>(ws, q.off_recA);
+  A.recB = ws_ptr<float4>(ws, q.off_recB);
+  A.recC = ws_ptr<float4>(ws, q.off_recC);
+  A.recD = ws_ptr<float4>(ws, q.off_recD);
+  A.payload = a.payload;
+  A.image = a.image;
+  A.aux = a.aux;
+  A.grad_image = a.grad_image;
+  A.thr = ws_ptr<float2>(ws, q.off_thr);
+  A.gacc = need_geo ? ws_ptr<float>(ws, q.off_gacc) : nullptr;
+  A.grad_opacity = a.grad_opacity;
+  A.grad_payload = a.grad_payload;
+  A.bgpart = a.grad_bg ? ws_ptr<float>(ws, q.off_bgpart) : nullptr;
+  A.C = a.C;
   stage_begin(PULSAR_STAGE_ZERO, stream);
-  zero_async(gacc, size_t(q.n) * 4, stream);
+  zero_async(A.gacc, size_t(q.n) * 4, stream);
   zero_async(a.grad_opacity, size_t(q.n), stream);
   zero_async(a.grad_payload, size_t(q.n) * size_t(q.C), stream);
   stage_end(PULSAR_STAGE_ZERO, stream);
   stage_begin(PULSAR_STAGE_RASTER_BWD, stream);
-  if (a.K <= 1)
-    launch_raster_bwd_km<1>(q, cam, bc, a, ws, gacc, bgpart, stream);
-  else if (a.K <= 2)
-    launch_raster_bwd_km<2>(q, cam, bc, a, ws, gacc, bgpart, stream);
-  else if (a.K <= 4)
-    launch_raster_bwd_km<4>(q, cam, bc, a, ws, gacc, bgpart, stream);
-  else if (a.K <= 8)
-    launch_raster_bwd_km<8>(q, cam, bc, a, ws, gacc, bgpart, stream);
-  else if (a.K <= 16)
-    launch_raster_bwd_km<16>(q, cam, bc, a, ws, gacc, bgpart, stream);
+  const dim3 grid(kRasterGrid), block(kWave);
+  if (a.C <= 1)
+    hipLaunchKernelGGL(k_bwd_chunks<1>, grid, block, 0, stream, A, cam, bc);
+  else if (a.C <= 2)
+    hipLaunchKernelGGL(k_bwd_chunks<2>, grid, block, 0, stream, A, cam, bc);
+  else if (a.C <= 4)
+    hipLaunchKernelGGL(k_bwd_chunks<4>, grid, block, 0, stream, A, cam, bc);
+  else if (a.C <= 8)
+    hipLaunchKernelGGL(k_bwd_chunks<8>, grid, block, 0, stream, A, cam, bc);
+  else if (a.C <= 16)
+    hipLaunchKernelGGL(k_bwd_chunks<16>, grid, block, 0, stream, A, cam, bc);
+  else if (a.C <= kBwdChannels)
+    hipLaunchKernelGGL(k_bwd_chunks<32>, grid, block, 0, stream, A, cam, bc);
   else
-    launch_raster_bwd_km<32>(q, cam, bc, a, ws, gacc, bgpart, stream);
+    hipLaunchKernelGGL(k_bwd_chunks_wide, grid, block, 0, stream, A, cam, bc);
   stage_end(PULSAR_STAGE_RASTER_BWD, stream);
   stage_begin(PULSAR_STAGE_FINALIZE, stream);
   if (need_geo && q.n > 0)
     hipLaunchKernelGGL(k_finalize, dim3(unsigned((q.n + 255) / 256)), dim3(256), 0, stream,
                        int(q.n), a.pos, a.radius, cam, a.min_radius_px,
-                       reinterpret_cast<const float4*>(gacc), a.grad_pos, a.grad_radius);
+                       reinterpret_cast<const float4*>(A.gacc), a.grad_pos, a.grad_radius);
   if (a.grad_bg)
-    hipLaunchKernelGGL(k_reduce_bg, dim3(unsigned(q.C)), dim3(256), 0, stream, bgpart,
+    hipLaunchKernelGGL(k_reduce_bg, dim3(unsigned(q.C)), dim3(256), 0, stream, A.bgpart,
                        int(q.T), int(q.C), a.grad_bg);
   stage_end(PULSAR_STAGE_FINALIZE, stream);
   return hipGetLastError();

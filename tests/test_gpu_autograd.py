@@ -51,32 +51,44 @@ def test_autograd_respects_needs_input_grad():
 
 
 def test_fp32_finite_differences_smoke():
-    """Loose FP32 central differences through the GPU forward (large steps,
-    large spheres): catches sign and scale errors in the chained gradients."""
+    """FP32 central differences through the GPU forward. The loss is smooth in
+    payload and opacity, which are checked at 1 %; along positions the weight
+    1 - q/R has a kink at every silhouette, so finite steps only check sign and
+    scale there (the FP64 oracle pins the exact derivative)."""
     import torch
     from paper_2004_07484_amd.renderer import Renderer
     wl = sg.tiny_scene(21, n=4, C=2, W=32, H=32, r_lo=0.4, r_hi=0.7)
     r = Renderer(32, 32, 4, n_channels=2, K=8)
     G = torch.from_numpy(sg.upstream_grad(1, 32, 32, 2)).cuda()
     pos = torch.from_numpy(wl.scene.pos).cuda().requires_grad_(True)
-    pay = torch.from_numpy(wl.scene.payload).cuda()
-    rad = torch.from_numpy(wl.scene.radius).cuda().requires_grad_(True)
-    opa = torch.from_numpy(wl.scene.opacity).cuda()
+    pay = torch.from_numpy(wl.scene.payload).cuda().requires_grad_(True)
+    rad = torch.from_numpy(wl.scene.radius).cuda()
+    opa = torch.from_numpy(wl.scene.opacity).cuda().requires_grad_(True)
 
-    def loss(p, rr):
-        return float((r(p, pay, rr, wl.camera, opacity=opa, gamma=0.5) * G).sum())
+    def loss(p, f, o):
+        img = r(p, f, rad, wl.camera, opacity=o, gamma=0.5)
+        return float((img.double() * G.double()).sum())
 
     (r(pos, pay, rad, wl.camera, opacity=opa, gamma=0.5) * G).sum().backward()
-    h = 1e-3
+
+    def fd(which, idx, h):
+        args = [pos.detach().clone(), pay.detach().clone(), opa.detach().clone()]
+        plus, minus = [a.clone() for a in args], [a.clone() for a in args]
+        plus[which][idx] += h
+        minus[which][idx] -= h
+        return (loss(*plus) - loss(*minus)) / (2 * h)
+
+    for k in range(4):
+        for c in range(2):
+            an = float(pay.grad[k, c])
+            assert abs(fd(1, (k, c), 1e-2) - an) <= 0.01 * abs(an) + 1e-3, (k, c)
+        an = float(opa.grad[k])
+        assert abs(fd(2, k, 1e-3) - an) <= 0.01 * abs(an) + 1e-2 * float(opa.grad.abs().max())
+    gmax = float(pos.grad.abs().max())
     for k in range(4):
         for a in range(3):
-            pp, pm = pos.detach().clone(), pos.detach().clone()
-            pp[k, a] += h
-            pm[k, a] -= h
-            fd = (loss(pp, rad.detach()) - loss(pm, rad.detach())) / (2 * h)
             an = float(pos.grad[k, a])
-            assert abs(fd - an) <= 0.05 * max(abs(an), 0.05 * float(pos.grad.abs().max())), \
-                (k, a, fd, an)
+            assert abs(fd(0, (k, a), 2e-3) - an) <= 0.15 * abs(an) + 0.03 * gmax, (k, a)
 
 
 def test_listing1_example_renders_like_the_oracle():
