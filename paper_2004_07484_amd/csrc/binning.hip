@@ -210,104 +210,134 @@ __global__ void k_tile_ranges(const uint32_t* __restrict__ keys,
 }
 
 // ---------------------------------------------------------------- work items
-// Each tile's list is cut into chunks of at most kChunk records; an empty tile
-// still gets one chunk (it renders the background). Tiles with several chunks
-// need one partial blend state per chunk, merged afterwards.
-__device__ __forceinline__ void tile_chunks(const uint32_t* __restrict__ ranges, int t, int T,
-                                            uint32_t& n, uint32_t& m) {
-  n = 0;
-  m = 0;
+// Each non-empty tile's list is cut into chunks of at most kChunk records:
+// L / kChunk full chunks and one shorter chunk for the rest. Full chunks of
+// all tiles come first in the work list (the costlier items start first),
+// then the short ones. A tile with several chunks needs one partial blend
+// state per chunk (slots soff .. soff + n - 1), merged afterwards. Empty
+// tiles get no work item at all.
+struct TileChunks {
+  uint32_t nf, np, ns;  // full chunks, short chunks (0/1), partial-state slots
+};
+
+__device__ __forceinline__ TileChunks tile_chunks(const uint32_t* __restrict__ ranges, int t,
+                                                  int T) {
+  TileChunks c{0u, 0u, 0u};
   if (t < T) {
     const uint32_t L = ranges[t + 1] - ranges[t];
-    n = L == 0 ? 1u : (L + kChunk - 1) / kChunk;
-    m = n >= 2 ? n : 0u;
+    c.nf = L / kChunk;
+    c.np = (L % kChunk) != 0u ? 1u : 0u;
+    const uint32_t n = c.nf + c.np;
+    c.ns = n >= 2 ? n : 0u;
   }
+  return c;
 }
 
 __global__ __launch_bounds__(256) void k_chunk_count(const uint32_t* __restrict__ ranges, int T,
-                                                     uint2* __restrict__ cpart) {
-  __shared__ uint32_t s_n[256 / kWave], s_m[256 / kWave];
+                                                     uint4* __restrict__ cpart) {
+  __shared__ uint32_t s_f[256 / kWave], s_p[256 / kWave], s_s[256 / kWave];
   const int t = blockIdx.x * 256 + threadIdx.x;
-  uint32_t n, m;
-  tile_chunks(ranges, t, T, n, m);
-  n = wave_sum_u32(n);
-  m = wave_sum_u32(m);
+  const TileChunks c = tile_chunks(ranges, t, T);
+  const uint32_t f = wave_sum_u32(c.nf), pp = wave_sum_u32(c.np), ss = wave_sum_u32(c.ns);
   if ((threadIdx.x & (kWave - 1)) == 0) {
-    s_n[threadIdx.x / kWave] = n;
-    s_m[threadIdx.x / kWave] = m;
+    s_f[threadIdx.x / kWave] = f;
+    s_p[threadIdx.x / kWave] = pp;
+    s_s[threadIdx.x / kWave] = ss;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t a = 0, b = 0;
+    uint32_t a = 0, b = 0, d = 0;
     for (int w = 0; w < 256 / kWave; ++w) {
-      a += s_n[w];
-      b += s_m[w];
+      a += s_f[w];
+      b += s_p[w];
+      d += s_s[w];
     }
-    cpart[blockIdx.x] = make_uint2(a, b);
+    cpart[blockIdx.x] = make_uint4(a, b, d, 0u);
   }
 }
 
-// Single block: exclusive scan of the per-block (chunks, partials) sums.
-__global__ __launch_bounds__(kScanThreads) void k_chunk_scan(uint2* __restrict__ cpart,
+// Single block: exclusive scan of the per-block (full, short, slots) sums.
+__global__ __launch_bounds__(kScanThreads) void k_chunk_scan(uint4* __restrict__ cpart,
                                                              int nblk, long long pcap,
                                                              Status* __restrict__ status) {
-  __shared__ uint32_t s_n[kScanThreads / kWave], s_m[kScanThreads / kWave];
+  __shared__ uint32_t s_f[kScanThreads / kWave], s_p[kScanThreads / kWave],
+      s_s[kScanThreads / kWave];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-  uint32_t cn = 0, cm = 0;
+  uint32_t cf = 0, cp = 0, cs = 0;
   for (int base = 0; base < nblk; base += kScanThreads) {
     const int i = base + tid;
-    const uint2 v = i < nblk ? cpart[i] : make_uint2(0u, 0u);
-    const uint32_t in = wave_incl_scan_u32(v.x, lane), im = wave_incl_scan_u32(v.y, lane);
+    const uint4 v = i < nblk ? cpart[i] : make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t inf = wave_incl_scan_u32(v.x, lane), inp = wave_incl_scan_u32(v.y, lane),
+                   ins = wave_incl_scan_u32(v.z, lane);
     if (lane == kWave - 1) {
-      s_n[wid] = in;
-      s_m[wid] = im;
+      s_f[wid] = inf;
+      s_p[wid] = inp;
+      s_s[wid] = ins;
     }
     __syncthreads();
-    uint32_t bn = 0, bm = 0, tn = 0, tm = 0;
+    uint32_t bf = 0, bp = 0, bs = 0, tf = 0, tp = 0, ts = 0;
     for (int w = 0; w < kScanThreads / kWave; ++w) {
       if (w < wid) {
-        bn += s_n[w];
-        bm += s_m[w];
+        bf += s_f[w];
+        bp += s_p[w];
+        bs += s_s[w];
       }
-      tn += s_n[w];
-      tm += s_m[w];
+      tf += s_f[w];
+      tp += s_p[w];
+      ts += s_s[w];
     }
-    if (i < nblk) cpart[i] = make_uint2(cn + bn + in - v.x, cm + bm + im - v.y);
-    cn += tn;
-    cm += tm;
+    if (i < nblk)
+      cpart[i] = make_uint4(cf + bf + inf - v.x, cp + bp + inp - v.y, cs + bs + ins - v.z, 0u);
+    cf += tf;
+    cp += tp;
+    cs += ts;
     __syncthreads();
   }
   if (tid == 0) {
-    status->nchunks = cn;
-    status->npartials = cm;
-    if ((long long)cm > pcap) status->code = uint32_t(-PULSAR_ERR_CAPACITY);
+    status->nfull = cf;
+    status->nchunks = cf + cp;
+    status->npartials = cs;
+    if ((long long)cs > pcap) status->code = uint32_t(-PULSAR_ERR_CAPACITY);
   }
 }
 
 __global__ __launch_bounds__(256) void k_chunk_emit(const uint32_t* __restrict__ ranges, int T,
-                                                    const uint2* __restrict__ cpart,
+                                                    const uint4* __restrict__ cpart,
+                                                    const Status* __restrict__ status,
                                                     uint4* __restrict__ tinfo,
-                                                    uint2* __restrict__ desc) {
-  __shared__ uint32_t s_n[256 / kWave], s_m[256 / kWave];
+                                                    uint4* __restrict__ desc) {
+  __shared__ uint32_t s_f[256 / kWave], s_p[256 / kWave], s_s[256 / kWave];
   const int t = blockIdx.x * 256 + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  uint32_t n, m;
-  tile_chunks(ranges, t, T, n, m);
-  const uint32_t in = wave_incl_scan_u32(n, lane), im = wave_incl_scan_u32(m, lane);
+  const TileChunks c = tile_chunks(ranges, t, T);
+  const uint32_t inf = wave_incl_scan_u32(c.nf, lane), inp = wave_incl_scan_u32(c.np, lane),
+                 ins = wave_incl_scan_u32(c.ns, lane);
   if (lane == kWave - 1) {
-    s_n[wid] = in;
-    s_m[wid] = im;
+    s_f[wid] = inf;
+    s_p[wid] = inp;
+    s_s[wid] = ins;
   }
   __syncthreads();
-  uint32_t bn = cpart[blockIdx.x].x, bm = cpart[blockIdx.x].y;
+  const uint4 base = cpart[blockIdx.x];
+  uint32_t bf = base.x, bp = base.y, bs = base.z;
   for (int w = 0; w < wid; ++w) {
-    bn += s_n[w];
-    bm += s_m[w];
+    bf += s_f[w];
+    bp += s_p[w];
+    bs += s_s[w];
   }
   if (t >= T) return;
-  const uint32_t coff = bn + in - n, poff = bm + im - m;
-  tinfo[t] = make_uint4(coff, n, poff, 0u);
-  for (uint32_t ci = 0; ci < n; ++ci) desc[coff + ci] = make_uint2(uint32_t(t), ci);
+  const uint32_t foff = bf + inf - c.nf, poff = status->nfull + bp + inp - c.np;
+  const uint32_t soff = bs + ins - c.ns;
+  const uint32_t n = c.nf + c.np;
+  tinfo[t] = make_uint4(soff, n, 0u, 0u);
+  const uint32_t rb = ranges[t], re = ranges[t + 1];
+  for (uint32_t ci = 0; ci < n; ++ci) {
+    const uint32_t beg = rb + ci * kChunk;
+    const uint32_t end = min(re, beg + kChunk);
+    const uint32_t slot = n >= 2 ? soff + ci : kNoSlot;
+    const uint32_t at = ci < c.nf ? foff + ci : poff;
+    desc[at] = make_uint4(uint32_t(t) | (ci == 0 ? kFirstChunk : 0u), beg, end, slot);
+  }
 }
 
 void launch_binning(const Plan& q, char* ws, hipStream_t stream) {
@@ -344,12 +374,12 @@ void launch_binning(const Plan& q, char* ws, hipStream_t stream) {
   uint32_t* ranges = ws_ptr<uint32_t>(ws, q.off_ranges);
   hipLaunchKernelGGL(k_tile_ranges, dim3((T + 1 + 255) / 256), dim3(256), 0, stream, ksorted,
                      status, T, q.depth_bits, ranges);
-  uint2* cpart = ws_ptr<uint2>(ws, q.off_cpart);
+  uint4* cpart = ws_ptr<uint4>(ws, q.off_cpart);
   hipLaunchKernelGGL(k_chunk_count, dim3(q.nblk_tiles), dim3(256), 0, stream, ranges, T, cpart);
   hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kScanThreads), 0, stream, cpart, q.nblk_tiles,
                      (long long)q.pcap, status);
   hipLaunchKernelGGL(k_chunk_emit, dim3(q.nblk_tiles), dim3(256), 0, stream, ranges, T, cpart,
-                     ws_ptr<uint4>(ws, q.off_tinfo), ws_ptr<uint2>(ws, q.off_desc));
+                     status, ws_ptr<uint4>(ws, q.off_tinfo), ws_ptr<uint4>(ws, q.off_desc));
 }
 
 }  // namespace pulsar

@@ -164,8 +164,9 @@ int make_plan(int64_t n, int W, int H, int C, const pulsar_params_t* p, Plan* ou
   q.klist_slots = km;
   q.pstride = 2 + q.fwd_cm + 2 * km;  // m, D, numerator[cm], K-list (t, id)
   q.off_tinfo = take(size_t(q.T) * 16);
-  q.off_desc = take(size_t(q.max_chunks) * 8);
-  q.off_cpart = take(size_t(q.nblk_tiles + 1) * 8);
+  q.off_desc = take(size_t(q.max_chunks) * 16);
+  q.off_cpart = take(size_t(q.nblk_tiles + 1) * 16);
+  q.off_bgsum = take(size_t(kBgBlocks) * size_t(C) * 4);
   q.off_pstate = take(size_t(q.pcap) * kWave * size_t(q.pstride) * 4);
   q.off_thr = take(size_t(W) * size_t(H) * 8);
   q.total = o;

@@ -27,6 +27,9 @@ namespace pulsar {
 // FP32 rejection threshold on r2: generous against FP32 rounding of the
 // record's high parts, so no hit of the exact test is ever rejected.
 constexpr float kRejectR2 = 1.015625f;
+// Below this FP32 r2 the pixel is well inside the disc: e = 1 - r2 >= 0.1 is
+// then known to about 1e-5 relative in FP32 and the FP64 evaluation is skipped.
+constexpr float kFastR2 = 0.9f;
 
 struct PixelRay {
   int px, py;
@@ -68,6 +71,7 @@ struct SphereRec {
 // Cheap FP32 rejection. Returns r2 (only meaningful when < kRejectR2).
 __device__ __forceinline__ float coarse_r2(const PixelRay& ray, int x0, int y0, float xh,
                                            float yh, float kh, float axh, float ayh) {
+#pragma clang fp contract(off)
   const float dx = float(ray.px - x0) - xh;
   const float dy = float(ray.py - y0) - yh;
   const float cr = axh * dy - ayh * dx;
@@ -84,33 +88,48 @@ struct Hit {
 };
 
 // Exact test. Returns true on a hit (q < R and t <= zfar) and fills h.
+// Deterministic: every kernel gets bitwise the same result for the same
+// (pixel, sphere), which the K-th-nearest threshold relies on.
 __device__ __forceinline__ bool exact_hit(const PixelRay& ray, const SphereRec& s, float zfar,
                                           Hit& h) {
-  // every kernel must see bitwise the same t for the same (pixel, sphere)
 #pragma clang fp contract(off)
-  const double X = double(s.xh) + double(s.xl);
-  const double Y = double(s.yh) + double(s.yl);
-  const double dx = double(ray.px - s.x0) - X;
-  const double dy = double(ray.py - s.y0) - Y;
-  const double ax = double(s.axh) + double(s.axl);
-  const double ay = double(s.ayh) + double(s.ayl);
-  const double cr = ax * dy - ay * dx;
-  const double S = dx * dx + dy * dy + cr * cr;
-  const double r2 = (double(s.kh) + double(s.kl)) * S * ray.inv_v2_d;
-  if (!(r2 < 1.0)) return false;
-  const float e = float(1.0 - r2);
+  const float dx32 = float(ray.px - s.x0) - s.xh;
+  const float dy32 = float(ray.py - s.y0) - s.yh;
+  const float cr32 = s.axh * dy32 - s.ayh * dx32;
+  const float r2c = s.kh * (dx32 * dx32 + dy32 * dy32 + cr32 * cr32) * ray.inv_v2;
+  if (!(r2c < kRejectR2)) return false;
+  float e, ratio;
+  if (r2c < kFastR2) {
+    e = 1.f - r2c;
+    ratio = fast_sqrt(r2c);
+    h.dx = dx32;
+    h.dy = dy32;
+    h.cr = cr32;
+  } else {
+    const double X = double(s.xh) + double(s.xl);
+    const double Y = double(s.yh) + double(s.yl);
+    const double dx = double(ray.px - s.x0) - X;
+    const double dy = double(ray.py - s.y0) - Y;
+    const double ax = double(s.axh) + double(s.axl);
+    const double ay = double(s.ayh) + double(s.ayl);
+    const double cr = ax * dy - ay * dx;
+    const double S = dx * dx + dy * dy + cr * cr;
+    const double r2 = (double(s.kh) + double(s.kl)) * S * ray.inv_v2_d;
+    if (!(r2 < 1.0)) return false;
+    e = float(1.0 - r2);
+    ratio = fast_sqrt(float(r2));
+    h.dx = float(dx);
+    h.dy = float(dy);
+    h.cr = float(cr);
+  }
   const float sq = fast_sqrt(e);
-  const float ratio = fast_sqrt(float(r2));
   const float t = s.cz * (ray.ux * s.axh + ray.uy * s.ayh + ray.uz) - s.R * sq;
   if (!(t <= zfar)) return false;
   h.e = e;
   h.sq = sq;
   h.ratio = ratio;
-  h.delta = e / (1.f + ratio);
+  h.delta = e * fast_rcp(1.f + ratio);
   h.t = t;
-  h.dx = float(dx);
-  h.dy = float(dy);
-  h.cr = float(cr);
   return true;
 }
 
@@ -144,12 +163,9 @@ __device__ __forceinline__ PixelRay load_ray(const TileRays& tr, int pl, int px,
   return r;
 }
 
-// Record loads: four float4 per sphere (see k_project for the layout).
-__device__ __forceinline__ SphereRec load_rec(const float4* __restrict__ recA,
-                                              const float4* __restrict__ recB,
-                                              const float4* __restrict__ recC,
-                                              const float4* __restrict__ recD, uint32_t id) {
-  const float4 a = recA[id], b = recB[id], c = recC[id], d = recD[id];
+// A sphere record is four float4 (see k_project for the layout).
+__device__ __forceinline__ SphereRec unpack_rec(const float4& a, const float4& b,
+                                                const float4& c, const float4& d) {
   SphereRec s;
   const uint32_t pk = __float_as_uint(a.w);
   s.x0 = int(pk & 0xffffu);
@@ -168,6 +184,13 @@ __device__ __forceinline__ SphereRec load_rec(const float4* __restrict__ recA,
   s.ayl = d.x;
   s.o = d.y;
   return s;
+}
+
+__device__ __forceinline__ SphereRec load_rec(const float4* __restrict__ recA,
+                                              const float4* __restrict__ recB,
+                                              const float4* __restrict__ recC,
+                                              const float4* __restrict__ recD, uint32_t id) {
+  return unpack_rec(recA[id], recB[id], recC[id], recD[id]);
 }
 
 }  // namespace pulsar

@@ -25,6 +25,9 @@ constexpr int kFwdChannels = 32;             // channels per forward pass (more:
 constexpr int kBwdChannels = 32;             // channels kept in registers by the backward
 constexpr int kChunk = 128;                  // sphere records per raster work item
 constexpr int kRasterGrid = 4096;            // persistent raster grid (one wave per block)
+constexpr int kBgBlocks = 1024;              // blocks of the background-gradient reduction
+constexpr uint32_t kFirstChunk = 0x80000000u;  // work item flag: first chunk of its tile
+constexpr uint32_t kNoSlot = 0xffffffffu;      // work item writes final pixels, no partial state
 
 // Device status block at the start of the workspace.
 struct Status {
@@ -33,7 +36,8 @@ struct Status {
   unsigned long long pairs;     // pairs the scene produced
   uint32_t nchunks;             // raster work items (chunks of <= kChunk records of one tile)
   uint32_t npartials;           // partial blend states needed by tiles with several chunks
-  uint32_t pad[58];
+  uint32_t nfull;               // work items with exactly kChunk records (listed first)
+  uint32_t pad[57];
 };
 
 // Camera constants in the form the kernels use.
@@ -63,10 +67,11 @@ struct Plan {
   size_t off_gacc;
   size_t off_partials, off_keysA, off_valsA, off_keysB, off_valsB, off_hist, off_dtot;
   size_t off_ranges, off_bgpart;
-  // raster work items: per-tile (first chunk, chunks, first partial slot), the
-  // chunk list (tile, index within tile), block sums of the chunk scan, the
-  // partial blend states and the per-pixel K-th nearest hit (t, sphere id)
-  size_t off_tinfo, off_desc, off_cpart, off_pstate, off_thr;
+  // raster work items: per tile uint4 (first partial-state slot, chunks, 0, 0);
+  // the work list uint4 (tile | kFirstChunk, begin, end, slot or kNoSlot);
+  // block sums of the chunk scan; the partial blend states; the per-pixel
+  // K-th nearest hit (t, sphere id); background-gradient block sums
+  size_t off_tinfo, off_desc, off_cpart, off_pstate, off_thr, off_bgsum;
   int64_t max_chunks, pcap;
   int nblk_tiles, fwd_cm, klist_slots, pstride;
   size_t total;

@@ -11,24 +11,19 @@
 // (camera-space dL/dc, dL/dR, dL/do, dL/df) and flushes them once per chunk
 // with float atomics (a sphere meets several chunks only when its rectangle
 // spans tiles or its tile list is split). The tile's G, F, L, thresholds and
-// rays are staged once per chunk in LDS. The first chunk of each tile also
-// writes the tile's background-gradient partial.
+// rays are staged once per chunk in LDS. Blocks take work items round-robin,
+// full chunks first.
 //
 // K8 turns the camera-space accumulators into world-space position and
-// radius gradients; K8b sums the per-tile background partials.
+// radius gradients; the background gradient is a plain reduction over all
+// pixels (k_bg_partial, k_reduce_bg).
 #include "hit_geometry.h"
 
 namespace pulsar {
 
-__global__ void k_zero(float* __restrict__ p, size_t count) {
-  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count;
-       i += size_t(gridDim.x) * blockDim.x)
-    p[i] = 0.f;
-}
-
 struct BwdKernelArgs {
-  const Status* status;
-  const uint2* desc;
+  Status* status;
+  const uint4* desc;
   const uint32_t* ranges;
   const uint32_t* svals;
   const float4* recA;
@@ -40,126 +35,209 @@ struct BwdKernelArgs {
   const float* aux;
   const float* grad_image;
   const float2* thr;
+  const uint32_t* counts;  // tiles per sphere (from the forward projection)
   float* gacc;
   float* grad_opacity;
   float* grad_payload;
-  float* bgpart;
   int C;
 };
 
-// CM >= C: channels kept in LDS and registers.
+// Gradient terms of one hit (pixel ray, sphere s) that belongs to the K
+// nearest: derivatives of Eq. 1 through t (depth), 1 - q/R (distance), o and f.
+struct HitGrad {
+  float gcx, gcy, gcz, gR, go, w;
+};
+
+__device__ __forceinline__ HitGrad hit_grad(const PixelRay& ray, const SphereRec& s,
+                                            const Hit& h, const CamDev& cam, const BlendConst& bc,
+                                            float L2, float hs) {
+  HitGrad g;
+  const float o = s.o;
+  const float zg = o * (bc.zfar - h.t);             // o z (zfar - znear)
+  const float ex = fast_exp2(zg * bc.kz - L2);      // exp(o z / gamma) / denominator
+  const float e = h.delta * ex;                     // dw/do without the exponent term
+  g.w = o * e;                                      // blending weight of Eq. 1
+  g.go = e * hs * (1.f + zg * bc.inv_span * bc.inv_gamma);
+  const float gt = -g.w * hs * o * bc.inv_gamma * bc.inv_span;  // dL/dt
+  const float gd = o * ex * hs;                                 // dL/d(1 - q/R)
+  // (c - (u.c) u) / R = sqrt(kappa) (v x (-D_y, D_x, cr)) / |v|^2
+  const float sk = fast_sqrt(s.kh) * ray.inv_v2;
+  const float dnx = (ray.ys * h.cr - cam.f * h.dx) * sk;
+  const float dny = (-cam.f * h.dy - ray.xs * h.cr) * sk;
+  const float dnz = (ray.xs * h.dx + ray.ys * h.dy) * sk;
+  const float isq = fast_rcp(h.sq);
+  const float coef = gt * isq - (h.ratio > 0.f ? gd * fast_rcp(s.R * h.ratio) : 0.f);
+  g.gcx = gt * ray.ux + coef * dnx;
+  g.gcy = gt * ray.uy + coef * dny;
+  g.gcz = gt * ray.uz + coef * dnz;
+  g.gR = -gt * isq + gd * h.ratio * fast_rcp(s.R);
+  return g;
+}
+
+// CM >= C: channels kept in LDS. The (sphere, pixel) pairs of a batch (each
+// sphere's rectangle inside the tile) are flattened by a wave prefix sum over
+// rectangle sizes, so all 64 lanes stay busy whatever the sphere sizes; lane
+// j handles pair j + 64 i and adds its terms to its sphere's LDS accumulator.
 template <int CM>
 __global__ __launch_bounds__(kWave) void k_bwd_chunks(BwdKernelArgs A, CamDev cam,
                                                       BlendConst bc) {
+  constexpr int CQ = (CM + 3) / 4;
+  constexpr int NA = 6 + CM;  // dL/dc (3), dL/dR, dL/do, hit count, dL/df (CM)
   __shared__ TileRays s_ray;
-  __shared__ float s_G[CM][kWave], s_F[CM][kWave];
-  __shared__ float s_L2[kWave], s_tk[kWave];
+  __shared__ float s_G[CM][kWave];
+  __shared__ float s_L2[kWave], s_GF[kWave], s_tk[kWave];
   __shared__ uint32_t s_ik[kWave];
+  __shared__ float4 s_rec[kWave][4];
+  __shared__ float4 s_pay[kWave][CQ];
+  __shared__ uint32_t s_off[kWave], s_box[kWave], s_id[kWave];
+  __shared__ float s_acc[kWave][NA + 1];
   const int lane = threadIdx.x;
   const int C = A.C;
   const uint32_t nchunks = A.status->nchunks;
   for (uint32_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
-    const uint2 dsc = A.desc[chunk];
-    const int tile = int(dsc.x), ci = int(dsc.y);
-    const uint32_t beg = A.ranges[tile] + uint32_t(ci) * kChunk;
-    const uint32_t end = min(A.ranges[tile + 1], beg + kChunk);
+    const uint4 dsc = A.desc[chunk];
+    const int tile = int(dsc.x & ~kFirstChunk);
+    const uint32_t beg = dsc.y, end = dsc.z;
     const int tx0 = (tile % cam.tiles_x) * kTileW, ty0 = (tile / cam.tiles_x) * kTileH;
-    if (beg >= end && !(ci == 0 && A.bgpart)) continue;  // empty tile, nothing to do
-    // stage the tile's pixels (lane = pixel)
-    const int px = tx0 + (lane % kTileW), py = ty0 + (lane / kTileW);
-    const bool inside = px < cam.W && py < cam.H;
-    const size_t p = inside ? size_t(py) * size_t(cam.W) + size_t(px) : 0;
-    const float L2 = inside ? A.aux[p] * 1.4426950408889634f : 0.f;
-    __syncthreads();  // the previous chunk's LDS reads are done
-    store_ray(s_ray, lane, make_ray(cam, px, py));
-    s_L2[lane] = L2;
-    const float2 th = inside ? A.thr[p] : make_float2(-INFINITY, 0.f);
-    s_tk[lane] = th.x;
-    s_ik[lane] = __float_as_uint(th.y);
-#pragma unroll
-    for (int c = 0; c < CM; ++c) {
-      s_G[c][lane] = (inside && c < C) ? A.grad_image[p * size_t(C) + c] : 0.f;
-      s_F[c][lane] = (inside && c < C) ? A.image[p * size_t(C) + c] : 0.f;
-    }
-    if (ci == 0 && A.bgpart) {
-      // dL/dbg = sum_p exp(eps/gamma - L_p) G_p
-      const float wbg = inside ? fast_exp2(bc.eps2 - L2) : 0.f;
+    // stage the tile's pixels (lane = pixel): ray, L, threshold, G and G . F
+    {
+      const int px = tx0 + (lane % kTileW), py = ty0 + (lane / kTileW);
+      const bool inside = px < cam.W && py < cam.H;
+      const size_t p = inside ? size_t(py) * size_t(cam.W) + size_t(px) : 0;
+      __syncthreads();  // the previous chunk's LDS reads are done
+      store_ray(s_ray, lane, make_ray(cam, px, py));
+      s_L2[lane] = inside ? A.aux[p] * 1.4426950408889634f : 0.f;
+      const float2 th = inside ? A.thr[p] : make_float2(-INFINITY, 0.f);
+      s_tk[lane] = th.x;
+      s_ik[lane] = __float_as_uint(th.y);
+      float gf = 0.f;
 #pragma unroll
       for (int c = 0; c < CM; ++c) {
-        if (c < C) {
-          const float sum = wave_sum(wbg * s_G[c][lane]);
-          if (lane == 0) A.bgpart[size_t(tile) * size_t(C) + c] = sum;
-        }
+        const float g = (inside && c < C) ? A.grad_image[p * size_t(C) + c] : 0.f;
+        const float f = (inside && c < C) ? A.image[p * size_t(C) + c] : 0.f;
+        s_G[c][lane] = g;
+        gf += g * f;
       }
+      s_GF[lane] = gf;
     }
-    __syncthreads();
     for (uint32_t b0 = beg; b0 < end; b0 += kWave) {
       const uint32_t j = b0 + uint32_t(lane);
-      if (j >= end) continue;
-      const uint32_t id = A.svals[j];
-      const SphereRec s = load_rec(A.recA, A.recB, A.recC, A.recD, id);
-      const uint32_t p1 = __float_as_uint(A.recD[id].z);
-      float fk[CM];
-      const float* fp = A.payload + size_t(id) * size_t(C);
-#pragma unroll
-      for (int c = 0; c < CM; ++c) fk[c] = c < C ? fp[c] : 0.f;
-      float gcx = 0.f, gcy = 0.f, gcz = 0.f, gR = 0.f, go = 0.f, gf[CM];
-#pragma unroll
-      for (int c = 0; c < CM; ++c) gf[c] = 0.f;
-      bool any = false;
-      const int xa = max(s.x0, tx0), xb = min(int(p1 & 0xffffu), tx0 + kTileW - 1);
-      const int ya = max(s.y0, ty0), yb = min(int(p1 >> 16), ty0 + kTileH - 1);
-      for (int iy = ya; iy <= yb; ++iy) {
-        for (int ix = xa; ix <= xb; ++ix) {
-          const int pl = (iy - ty0) * kTileW + (ix - tx0);
-          const PixelRay ray = load_ray(s_ray, pl, ix, iy);
-          if (!(coarse_r2(ray, s.x0, s.y0, s.xh, s.yh, s.kh, s.axh, s.ayh) < kRejectR2)) continue;
-          Hit h;
-          if (!exact_hit(ray, s, bc.zfar, h)) continue;
-          // among the pixel's K nearest hits?
-          const float tk = s_tk[pl];
-          const uint32_t ik = s_ik[pl];
-          if (!(id == ik || h.t < tk || (h.t == tk && id < ik))) continue;
-          any = true;
-          const float o = s.o;
-          const float s2 = o * (bc.zfar - h.t) * bc.kz;  // o z / gamma in base 2
-          const float ex = fast_exp2(s2 - s_L2[pl]);      // exp(o z / gamma) / denominator
-          const float e = h.delta * ex;                   // dw/do without the exponent term
-          const float w = o * e;                          // blending weight of Eq. 1
-          float hs = 0.f;                                 // G . (f_k - F)
-#pragma unroll
-          for (int c = 0; c < CM; ++c) hs += s_G[c][pl] * (fk[c] - s_F[c][pl]);
-#pragma unroll
-          for (int c = 0; c < CM; ++c) gf[c] += w * s_G[c][pl];
-          go += e * hs * (1.f + o * (bc.zfar - h.t) * bc.inv_span * bc.inv_gamma);
-          const float gt = -w * hs * o * bc.inv_gamma * bc.inv_span;  // dL/dt
-          const float gd = o * ex * hs;                               // dL/d(1 - q/R)
-          // (c - (u.c) u) / R = sqrt(kappa) (v x (-D_y, D_x, cr)) / |v|^2
-          const float sk = fast_sqrt(s.kh) * ray.inv_v2;
-          const float dnx = (ray.ys * h.cr - cam.f * h.dx) * sk;
-          const float dny = (-cam.f * h.dy - ray.xs * h.cr) * sk;
-          const float dnz = (ray.xs * h.dx + ray.ys * h.dy) * sk;
-          const float coef = gt / h.sq - (h.ratio > 0.f ? gd / (s.R * h.ratio) : 0.f);
-          gcx += gt * ray.ux + coef * dnx;
-          gcy += gt * ray.uy + coef * dny;
-          gcz += gt * ray.uz + coef * dnz;
-          gR += -gt / h.sq + gd * h.ratio / s.R;
-        }
+      const bool valid = j < end;
+      uint32_t id = 0;
+      float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a, d = a;
+      bool single = false;
+      if (valid) {
+        id = A.svals[j];
+        a = A.recA[id];
+        b = A.recB[id];
+        c = A.recC[id];
+        d = A.recD[id];
+        single = A.counts[id] == 1u;
       }
-      if (any) {
-        if (A.grad_payload) {
-          float* g = A.grad_payload + size_t(id) * size_t(C);
+      // the sphere's rectangle inside this tile, in tile coordinates
+      const uint32_t p0 = __float_as_uint(a.w), p1 = __float_as_uint(d.z);
+      const int xa = max(int(p0 & 0xffffu), tx0) - tx0;
+      const int xb = min(int(p1 & 0xffffu), tx0 + kTileW - 1) - tx0;
+      const int ya = max(int(p0 >> 16), ty0) - ty0;
+      const int yb = min(int(p1 >> 16), ty0 + kTileH - 1) - ty0;
+      const uint32_t w = valid ? uint32_t(xb - xa + 1) : 1u;
+      const uint32_t n = valid ? w * uint32_t(yb - ya + 1) : 0u;
+      const uint32_t incl = wave_incl_scan_u32(n, lane);
+      const uint32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
+      const uint32_t magic = (65536u + w - 1u) / w;  // i / w = (i * magic) >> 16 for i < 64
+      const float* fp = A.payload + size_t(id) * size_t(C);
+      __syncthreads();  // the previous batch is done with the LDS below
+      s_rec[lane][0] = a;
+      s_rec[lane][1] = b;
+      s_rec[lane][2] = c;
+      s_rec[lane][3] = d;
 #pragma unroll
-          for (int c = 0; c < CM; ++c)
-            if (c < C) atomicAdd(g + c, gf[c]);
+      for (int q = 0; q < CQ; ++q) {
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = (valid && 4 * q + u < C) ? fp[4 * q + u] : 0.f;
+        s_pay[lane][q] = make_float4(v[0], v[1], v[2], v[3]);
+      }
+      s_id[lane] = id;
+      s_off[lane] = incl - n;
+      s_box[lane] = uint32_t(xa) | (uint32_t(ya) << 3) | (w << 6) | (magic << 10);
+#pragma unroll
+      for (int v = 0; v < NA; ++v) s_acc[lane][v] = 0.f;
+      __syncthreads();
+      for (uint32_t pb = 0; pb < total; pb += kWave) {
+        const uint32_t pair = pb + uint32_t(lane);
+        if (pair >= total) continue;
+        // owner: the last sphere whose first pair is <= pair
+        int lo = 0, hi = kWave - 1;
+#pragma unroll
+        for (int step = 0; step < 6; ++step) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_off[mid] <= pair)
+            lo = mid;
+          else
+            hi = mid - 1;
         }
-        if (A.grad_opacity) atomicAdd(A.grad_opacity + id, go);
+        const int r = lo;
+        const uint32_t i = pair - s_off[r], box = s_box[r];
+        const uint32_t bw = (box >> 6) & 15u, yy = (i * (box >> 10)) >> 16;
+        const int x = int(box & 7u) + int(i - yy * bw), y = int((box >> 3) & 7u) + int(yy);
+        const int pl = y * kTileW + x;
+        const SphereRec s = unpack_rec(s_rec[r][0], s_rec[r][1], s_rec[r][2], s_rec[r][3]);
+        const PixelRay ray = load_ray(s_ray, pl, tx0 + x, ty0 + y);
+        Hit h;
+        if (!exact_hit(ray, s, bc.zfar, h)) continue;
+        // among the pixel's K nearest hits?
+        const uint32_t sid = s_id[r];
+        const float tk = s_tk[pl];
+        const uint32_t ik = s_ik[pl];
+        if (!(sid == ik || h.t < tk || (h.t == tk && sid < ik))) continue;
+        float hs = -s_GF[pl];  // G . (f_k - F)
+#pragma unroll
+        for (int q = 0; q < CQ; ++q) {
+          const float4 f = s_pay[r][q];
+          const float fv[4] = {f.x, f.y, f.z, f.w};
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (4 * q + u < CM) hs += s_G[4 * q + u][pl] * fv[u];
+        }
+        const HitGrad g = hit_grad(ray, s, h, cam, bc, s_L2[pl], hs);
+        atomicAdd(&s_acc[r][0], g.gcx);
+        atomicAdd(&s_acc[r][1], g.gcy);
+        atomicAdd(&s_acc[r][2], g.gcz);
+        atomicAdd(&s_acc[r][3], g.gR);
+        atomicAdd(&s_acc[r][4], g.go);
+        atomicAdd(&s_acc[r][5], 1.f);
+#pragma unroll
+        for (int cc = 0; cc < CM; ++cc) atomicAdd(&s_acc[r][6 + cc], g.w * s_G[cc][pl]);
+      }
+      __syncthreads();
+      // A sphere that touches one tile appears in exactly one work item: it
+      // stores its sums (zeros included). Others add into zeroed sums.
+      if (valid && single) {
+        if (A.grad_payload) {
+          float* gp = A.grad_payload + size_t(id) * size_t(C);
+#pragma unroll
+          for (int cc = 0; cc < CM; ++cc)
+            if (cc < C) gp[cc] = s_acc[lane][6 + cc];
+        }
+        if (A.grad_opacity) A.grad_opacity[id] = s_acc[lane][4];
+        if (A.gacc)
+          reinterpret_cast<float4*>(A.gacc)[id] =
+              make_float4(s_acc[lane][0], s_acc[lane][1], s_acc[lane][2], s_acc[lane][3]);
+      } else if (valid && s_acc[lane][5] > 0.f) {
+        if (A.grad_payload) {
+          float* gp = A.grad_payload + size_t(id) * size_t(C);
+#pragma unroll
+          for (int cc = 0; cc < CM; ++cc)
+            if (cc < C) atomicAdd(gp + cc, s_acc[lane][6 + cc]);
+        }
+        if (A.grad_opacity) atomicAdd(A.grad_opacity + id, s_acc[lane][4]);
         if (A.gacc) {
-          float* g = A.gacc + size_t(id) * 4;
-          atomicAdd(g + 0, gcx);
-          atomicAdd(g + 1, gcy);
-          atomicAdd(g + 2, gcz);
-          atomicAdd(g + 3, gR);
+          float* gg = A.gacc + size_t(id) * 4;
+          atomicAdd(gg + 0, s_acc[lane][0]);
+          atomicAdd(gg + 1, s_acc[lane][1]);
+          atomicAdd(gg + 2, s_acc[lane][2]);
+          atomicAdd(gg + 3, s_acc[lane][3]);
         }
       }
     }
@@ -177,12 +255,10 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A, CamD
   const int C = A.C;
   const uint32_t nchunks = A.status->nchunks;
   for (uint32_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
-    const uint2 dsc = A.desc[chunk];
-    const int tile = int(dsc.x), ci = int(dsc.y);
-    const uint32_t beg = A.ranges[tile] + uint32_t(ci) * kChunk;
-    const uint32_t end = min(A.ranges[tile + 1], beg + kChunk);
+    const uint4 dsc = A.desc[chunk];
+    const int tile = int(dsc.x & ~kFirstChunk);
+    const uint32_t beg = dsc.y, end = dsc.z;
     const int tx0 = (tile % cam.tiles_x) * kTileW, ty0 = (tile / cam.tiles_x) * kTileH;
-    if (beg >= end && !(ci == 0 && A.bgpart)) continue;
     const int px = tx0 + (lane % kTileW), py = ty0 + (lane / kTileW);
     const bool inside = px < cam.W && py < cam.H;
     const size_t p = inside ? size_t(py) * size_t(cam.W) + size_t(px) : 0;
@@ -193,14 +269,6 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A, CamD
     const float2 th = inside ? A.thr[p] : make_float2(-INFINITY, 0.f);
     s_tk[lane] = th.x;
     s_ik[lane] = __float_as_uint(th.y);
-    if (ci == 0 && A.bgpart) {
-      const float wbg = inside ? fast_exp2(bc.eps2 - L2) : 0.f;
-      for (int c = 0; c < C; ++c) {
-        const float g = inside ? A.grad_image[p * size_t(C) + c] : 0.f;
-        const float sum = wave_sum(wbg * g);
-        if (lane == 0) A.bgpart[size_t(tile) * size_t(C) + c] = sum;
-      }
-    }
     __syncthreads();
     for (uint32_t b0 = beg; b0 < end; b0 += kWave) {
       const uint32_t j = b0 + uint32_t(lane);
@@ -217,7 +285,6 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A, CamD
         for (int ix = xa; ix <= xb; ++ix) {
           const int pl = (iy - ty0) * kTileW + (ix - tx0);
           const PixelRay ray = load_ray(s_ray, pl, ix, iy);
-          if (!(coarse_r2(ray, s.x0, s.y0, s.xh, s.yh, s.kh, s.axh, s.ayh) < kRejectR2)) continue;
           Hit h;
           if (!exact_hit(ray, s, bc.zfar, h)) continue;
           const float tk = s_tk[pl];
@@ -266,12 +333,41 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A, CamD
   }
 }
 
-// K8: camera-space (dL/dc, dL/dR) -> world-space position and radius gradients.
-__global__ void k_finalize(int n, const float* __restrict__ pos, const float* __restrict__ radius,
-                           CamDev cam, float min_radius_px, const float4* __restrict__ gacc,
-                           float* __restrict__ grad_pos, float* __restrict__ grad_radius) {
+// Before K7: zero the sums of the spheres that K7 will add into (those that
+// touch several tiles, or every visible one when K7 adds per hit).
+__global__ void k_bwd_prep(int n, const uint32_t* __restrict__ counts, uint32_t min_count,
+                           int C, float4* __restrict__ gacc, float* __restrict__ grad_opacity,
+                           float* __restrict__ grad_payload) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || counts[i] < min_count) return;
+  if (gacc) gacc[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (grad_opacity) grad_opacity[i] = 0.f;
+  if (grad_payload)
+    for (int c = 0; c < C; ++c) grad_payload[size_t(i) * size_t(C) + c] = 0.f;
+}
+
+// K8: camera-space (dL/dc, dL/dR) -> world-space position and radius
+// gradients; spheres that touch no tile get zeros everywhere.
+__global__ void k_finalize(int n, const uint32_t* __restrict__ counts,
+                           const float* __restrict__ pos, const float* __restrict__ radius,
+                           CamDev cam, float min_radius_px, int C, const float4* __restrict__ gacc,
+                           float* __restrict__ grad_pos, float* __restrict__ grad_radius,
+                           float* __restrict__ grad_opacity, float* __restrict__ grad_payload) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (counts[i] == 0u) {
+    if (grad_pos) {
+      grad_pos[3 * i + 0] = 0.f;
+      grad_pos[3 * i + 1] = 0.f;
+      grad_pos[3 * i + 2] = 0.f;
+    }
+    if (grad_radius) grad_radius[i] = 0.f;
+    if (grad_opacity) grad_opacity[i] = 0.f;
+    if (grad_payload)
+      for (int c = 0; c < C; ++c) grad_payload[size_t(i) * size_t(C) + c] = 0.f;
+    return;
+  }
+  if (!gacc) return;
   const float4 g = gacc[i];
   float gx = g.x, gy = g.y, gz = g.z, gR = g.w;
   bool clamped = false;
@@ -293,7 +389,42 @@ __global__ void k_finalize(int n, const float* __restrict__ pos, const float* __
   }
 }
 
-// K8b: grad_bg[c] = sum over tiles of the partials (one block per channel).
+// Background gradient, dL/dbg = sum_p exp(eps/gamma - L_p) G_p: per-block
+// partial sums over a grid-stride walk of the pixels, [kBgBlocks][C].
+__global__ __launch_bounds__(256) void k_bg_partial(const float* __restrict__ aux,
+                                                    const float* __restrict__ grad_image,
+                                                    long long npix, int C, float eps2,
+                                                    float* __restrict__ bgsum) {
+  __shared__ float s[256 / kWave];
+  for (int c0 = 0; c0 < C; c0 += 8) {
+    float acc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0.f;
+    for (long long p = (long long)blockIdx.x * 256 + threadIdx.x; p < npix;
+         p += (long long)gridDim.x * 256) {
+      const float w = fast_exp2(eps2 - aux[p] * 1.4426950408889634f);
+      const float* g = grad_image + p * C + c0;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c0 + c < C) acc[c] += w * g[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      if (c0 + c >= C) break;
+      const float v = wave_sum(acc[c]);
+      __syncthreads();
+      if ((threadIdx.x & (kWave - 1)) == 0) s[threadIdx.x / kWave] = v;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        float tsum = 0.f;
+        for (int w = 0; w < 256 / kWave; ++w) tsum += s[w];
+        bgsum[size_t(blockIdx.x) * size_t(C) + c0 + c] = tsum;
+      }
+    }
+  }
+}
+
+// K8b: grad_bg[c] = sum of the per-block partials (one block per channel).
 __global__ __launch_bounds__(256) void k_reduce_bg(const float* __restrict__ bgpart, int T, int C,
                                                    float* __restrict__ grad_bg) {
   __shared__ float s[256 / kWave];
@@ -310,19 +441,12 @@ __global__ __launch_bounds__(256) void k_reduce_bg(const float* __restrict__ bgp
   }
 }
 
-static void zero_async(float* p, size_t count, hipStream_t stream) {
-  if (!p || count == 0) return;
-  size_t blocks = (count + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_zero, dim3(unsigned(blocks)), dim3(256), 0, stream, p, count);
-}
-
 hipError_t launch_backward(const Plan& q, const CamDev& cam, const BlendConst& bc,
                            const BwdArgs& a, char* ws, hipStream_t stream) {
   const bool need_geo = a.grad_pos || a.grad_radius;
   BwdKernelArgs A;
   A.status = ws_ptr<Status>(ws, q.off_status);
-  A.desc = ws_ptr<uint2>(ws, q.off_desc);
+  A.desc = ws_ptr<uint4>(ws, q.off_desc);
   A.ranges = ws_ptr<uint32_t>(ws, q.off_ranges);
   A.svals = ws_ptr<uint32_t>(ws, sorted_in_a(q) ? q.off_valsA : q.off_valsB);
   A.recA = ws_ptr<float4>(ws, q.off_recA);
@@ -334,15 +458,19 @@ hipError_t launch_backward(const Plan& q, const CamDev& cam, const BlendConst& b
   A.aux = a.aux;
   A.grad_image = a.grad_image;
   A.thr = ws_ptr<float2>(ws, q.off_thr);
+  A.counts = ws_ptr<uint32_t>(ws, q.off_counts);
   A.gacc = need_geo ? ws_ptr<float>(ws, q.off_gacc) : nullptr;
   A.grad_opacity = a.grad_opacity;
   A.grad_payload = a.grad_payload;
-  A.bgpart = a.grad_bg ? ws_ptr<float>(ws, q.off_bgpart) : nullptr;
   A.C = a.C;
+  float* bgsum = ws_ptr<float>(ws, q.off_bgsum);
   stage_begin(PULSAR_STAGE_ZERO, stream);
-  zero_async(A.gacc, size_t(q.n) * 4, stream);
-  zero_async(a.grad_opacity, size_t(q.n), stream);
-  zero_async(a.grad_payload, size_t(q.n) * size_t(q.C), stream);
+  // the narrow kernels store single-tile spheres directly, the wide one adds per hit
+  const uint32_t min_count = a.C <= kBwdChannels ? 2u : 1u;
+  if (q.n > 0)
+    hipLaunchKernelGGL(k_bwd_prep, dim3(unsigned((q.n + 255) / 256)), dim3(256), 0, stream,
+                       int(q.n), A.counts, min_count, a.C, reinterpret_cast<float4*>(A.gacc),
+                       a.grad_opacity, a.grad_payload);
   stage_end(PULSAR_STAGE_ZERO, stream);
   stage_begin(PULSAR_STAGE_RASTER_BWD, stream);
   const dim3 grid(kRasterGrid), block(kWave);
@@ -362,13 +490,17 @@ hipError_t launch_backward(const Plan& q, const CamDev& cam, const BlendConst& b
     hipLaunchKernelGGL(k_bwd_chunks_wide, grid, block, 0, stream, A, cam, bc);
   stage_end(PULSAR_STAGE_RASTER_BWD, stream);
   stage_begin(PULSAR_STAGE_FINALIZE, stream);
-  if (need_geo && q.n > 0)
+  if (q.n > 0)
     hipLaunchKernelGGL(k_finalize, dim3(unsigned((q.n + 255) / 256)), dim3(256), 0, stream,
-                       int(q.n), a.pos, a.radius, cam, a.min_radius_px,
-                       reinterpret_cast<const float4*>(A.gacc), a.grad_pos, a.grad_radius);
-  if (a.grad_bg)
-    hipLaunchKernelGGL(k_reduce_bg, dim3(unsigned(q.C)), dim3(256), 0, stream, A.bgpart,
-                       int(q.T), int(q.C), a.grad_bg);
+                       int(q.n), A.counts, a.pos, a.radius, cam, a.min_radius_px, a.C,
+                       reinterpret_cast<const float4*>(A.gacc), a.grad_pos, a.grad_radius,
+                       a.grad_opacity, a.grad_payload);
+  if (a.grad_bg) {
+    hipLaunchKernelGGL(k_bg_partial, dim3(kBgBlocks), dim3(256), 0, stream, a.aux, a.grad_image,
+                       (long long)(q.W * q.H), int(q.C), bc.eps2, bgsum);
+    hipLaunchKernelGGL(k_reduce_bg, dim3(unsigned(q.C)), dim3(256), 0, stream, bgsum,
+                       kBgBlocks, int(q.C), a.grad_bg);
+  }
   stage_end(PULSAR_STAGE_FINALIZE, stream);
   return hipGetLastError();
 }

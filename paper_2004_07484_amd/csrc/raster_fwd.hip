@@ -1,12 +1,13 @@
 // K6: forward raster (paper App. B, Steps 1-2; Eq. 1).
 //
-// Work item = a chunk of at most kChunk depth-sorted records of one 8x8 tile
-// (long tile lists are split, so no wave walks thousands of spheres alone);
-// a persistent grid of one-wave blocks takes chunks round-robin. Per batch of
-// 64 records:
-//   A. sphere-parallel: lane l tests record l against the pixels of its own
-//      rectangle inside the tile (cheap FP32 test) and sets bit l of each
-//      candidate pixel's hit mask in LDS;
+// Work item = a chunk of at most kChunk depth-sorted records of one non-empty
+// 8x8 tile (long tile lists are split, so no wave walks thousands of spheres
+// alone); a persistent grid of one-wave blocks takes work items round-robin,
+// full chunks first. Per batch of 64 records:
+//   A. sphere-parallel: the (record, pixel of its rectangle inside the tile)
+//      pairs are flattened over the lanes by a prefix sum over rectangle
+//      sizes; each pair runs the cheap FP32 test and a candidate sets bit l
+//      of the pixel's hit mask in LDS;
 //   B. pixel-parallel: lane p walks the set bits of its mask in ascending
 //      order (the tile list is sorted near to far), decides each hit exactly
 //      (hit_geometry.h) and blends it.
@@ -17,7 +18,8 @@
 // index), and the K-th one becomes the pixel's gradient threshold.
 // A tile with one chunk writes its pixels directly; otherwise every chunk
 // leaves a partial state (m, D, numerator, K-list) and k_fwd_merge combines
-// them in chunk order, so the result is deterministic.
+// them in chunk order, so the result is deterministic. k_fwd_merge also
+// fills the empty tiles with the background.
 #include "hit_geometry.h"
 
 namespace pulsar {
@@ -50,8 +52,8 @@ __device__ __forceinline__ void klist_init(float (&kt)[KM], uint32_t (&kid)[KM],
 }
 
 struct FwdKernelArgs {
-  const Status* status;
-  const uint2* desc;
+  Status* status;
+  const uint4* desc;
   const uint4* tinfo;
   const uint32_t* ranges;
   const uint32_t* svals;
@@ -68,6 +70,7 @@ struct FwdKernelArgs {
   long long pcap;
   int C, c0, cn, K, pstride, kfield;  // kfield: first K-list field of a partial state
   int track;                          // keep K-lists (first channel pass with aux)
+  float eps2;                         // background exponent (base 2)
 };
 
 template <int CM, int KM>
@@ -88,29 +91,32 @@ __device__ __forceinline__ void write_pixel(const FwdKernelArgs& A, const CamDev
 template <int CM, int KM>
 __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A, CamDev cam,
                                                       BlendConst bc) {
-  __shared__ float s_rec[14][kWave];  // the batch's records, one field per row
+  // the batch's records and payloads, padded rows so that lanes reading
+  // different records mostly hit different banks
+  constexpr int CQ = (CM + 3) / 4;
+  __shared__ float4 s_rec[kWave][5];
+  __shared__ float4 s_pay[kWave][CQ + 1];
   __shared__ uint32_t s_id[kWave];
-  __shared__ float s_pay[CM][kWave];
   __shared__ unsigned long long s_mask[kWave];
   __shared__ float s_iv2[kWave];
+  __shared__ uint32_t s_off[kWave], s_box[kWave];
   const int lane = threadIdx.x;
   const uint32_t nchunks = A.status->nchunks;
   for (uint32_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
-    const uint2 dsc = A.desc[chunk];
-    const int tile = int(dsc.x), ci = int(dsc.y);
-    const uint4 ti = A.tinfo[tile];
-    const uint32_t beg = A.ranges[tile] + uint32_t(ci) * kChunk;
-    const uint32_t end = min(A.ranges[tile + 1], beg + kChunk);
+    const uint4 dsc = A.desc[chunk];
+    const int tile = int(dsc.x & ~kFirstChunk);
+    const bool first = (dsc.x & kFirstChunk) != 0u;
+    const uint32_t beg = dsc.y, end = dsc.z, slot = dsc.w;
     const int tx0 = (tile % cam.tiles_x) * kTileW, ty0 = (tile / cam.tiles_x) * kTileH;
     const PixelRay ray = make_ray(cam, tx0 + (lane % kTileW), ty0 + (lane / kTileW));
     __syncthreads();  // the previous chunk's LDS reads are done
     s_iv2[lane] = ray.inv_v2;
     // the background enters only through the tile's first chunk
-    float m2 = ci == 0 ? bc.eps2 : -INFINITY;
-    float D = ci == 0 ? 1.f : 0.f;
+    float m2 = first ? bc.eps2 : -INFINITY;
+    float D = first ? 1.f : 0.f;
     float N[CM];
 #pragma unroll
-    for (int c = 0; c < CM; ++c) N[c] = (ci == 0 && c < A.cn) ? A.bg[A.c0 + c] : 0.f;
+    for (int c = 0; c < CM; ++c) N[c] = (first && c < A.cn) ? A.bg[A.c0 + c] : 0.f;
     float kt[KM];
     uint32_t kid[KM];
     klist_init(kt, kid, A.K);
@@ -127,44 +133,64 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A, CamDev ca
         c = A.recC[id];
         d = A.recD[id];
       }
+      // the sphere's rectangle inside this tile, in tile coordinates; the
+      // (sphere, pixel) pairs are flattened over the wave by a prefix sum
+      const uint32_t p0 = __float_as_uint(a.w), p1 = __float_as_uint(d.z);
+      const int xa = max(int(p0 & 0xffffu), tx0) - tx0;
+      const int xb = min(int(p1 & 0xffffu), tx0 + kTileW - 1) - tx0;
+      const int ya = max(int(p0 >> 16), ty0) - ty0;
+      const int yb = min(int(p1 >> 16), ty0 + kTileH - 1) - ty0;
+      const uint32_t w = valid ? uint32_t(xb - xa + 1) : 1u;
+      const uint32_t n = valid ? w * uint32_t(yb - ya + 1) : 0u;
+      const uint32_t incl = wave_incl_scan_u32(n, lane);
+      const uint32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
+      const uint32_t magic = (65536u + w - 1u) / w;  // i / w = (i * magic) >> 16 for i < 64
       __syncthreads();  // previous batch done with s_rec / s_pay / s_mask
+      s_off[lane] = incl - n;
+      s_box[lane] = uint32_t(xa) | (uint32_t(ya) << 3) | (w << 6) | (magic << 10);
       s_mask[lane] = 0ull;
       s_id[lane] = id;
-      s_rec[0][lane] = a.x;
-      s_rec[1][lane] = a.y;
-      s_rec[2][lane] = a.z;
-      s_rec[3][lane] = a.w;
-      s_rec[4][lane] = b.x;
-      s_rec[5][lane] = b.y;
-      s_rec[6][lane] = b.z;
-      s_rec[7][lane] = b.w;
-      s_rec[8][lane] = c.x;
-      s_rec[9][lane] = c.y;
-      s_rec[10][lane] = c.z;
-      s_rec[11][lane] = c.w;
-      s_rec[12][lane] = d.x;
-      s_rec[13][lane] = d.y;
+      s_rec[lane][0] = a;
+      s_rec[lane][1] = b;
+      s_rec[lane][2] = c;
+      s_rec[lane][3] = d;
       const float* fp = A.payload + size_t(id) * size_t(A.C) + A.c0;
 #pragma unroll
-      for (int ch = 0; ch < CM; ++ch) s_pay[ch][lane] = (valid && ch < A.cn) ? fp[ch] : 0.f;
-      __syncthreads();
-      // A. record l against the pixels of its rectangle inside this tile
-      if (valid) {
-        const uint32_t p0 = __float_as_uint(a.w), p1 = __float_as_uint(d.z);
-        const int x0 = int(p0 & 0xffffu), y0 = int(p0 >> 16);
-        const int xa = max(x0, tx0), xb = min(int(p1 & 0xffffu), tx0 + kTileW - 1);
-        const int ya = max(y0, ty0), yb = min(int(p1 >> 16), ty0 + kTileH - 1);
-        const unsigned long long bit = 1ull << lane;
-        for (int iy = ya; iy <= yb; ++iy) {
-          const float dy = float(iy - y0) - a.y;
-          for (int ix = xa; ix <= xb; ++ix) {
-            const float dx = float(ix - x0) - a.x;
-            const float cr = b.x * dy - b.y * dx;
-            const int pl = (iy - ty0) * kTileW + (ix - tx0);
-            const float r2 = a.z * (dx * dx + dy * dy + cr * cr) * s_iv2[pl];
-            if (r2 < kRejectR2) atomicOr(&s_mask[pl], bit);
-          }
+      for (int q = 0; q < CQ; ++q) {
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ch = 4 * q + u;
+          v[u] = (valid && ch < A.cn) ? fp[ch] : 0.f;
         }
+        s_pay[lane][q] = make_float4(v[0], v[1], v[2], v[3]);
+      }
+      __syncthreads();
+      // A. every (record, pixel of its rectangle) pair, 64 at a time
+      for (uint32_t pb = 0; pb < total; pb += kWave) {
+        const uint32_t pair = pb + uint32_t(lane);
+        if (pair >= total) continue;
+        int lo = 0, hi = kWave - 1;  // owner: the last record whose first pair is <= pair
+#pragma unroll
+        for (int step = 0; step < 6; ++step) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_off[mid] <= pair)
+            lo = mid;
+          else
+            hi = mid - 1;
+        }
+        const int r = lo;
+        const uint32_t i = pair - s_off[r], box = s_box[r];
+        const uint32_t bw = (box >> 6) & 15u, yy = (i * (box >> 10)) >> 16;
+        const int x = int(box & 7u) + int(i - yy * bw), y = int((box >> 3) & 7u) + int(yy);
+        const int pl = y * kTileW + x;
+        const float4 ra = s_rec[r][0], rb = s_rec[r][1];
+        const uint32_t pk = __float_as_uint(ra.w);
+        const float dx = float(tx0 + x - int(pk & 0xffffu)) - ra.x;
+        const float dy = float(ty0 + y - int(pk >> 16)) - ra.y;
+        const float cr = rb.x * dy - rb.y * dx;
+        const float r2 = ra.z * (dx * dx + dy * dy + cr * cr) * s_iv2[pl];
+        if (r2 < kRejectR2) atomicOr(&s_mask[pl], 1ull << r);
       }
       __syncthreads();
       // B. pixel p over its candidates, near to far
@@ -173,23 +199,7 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A, CamDev ca
         if (hits != 0ull) {
           const int k = __builtin_ctzll(hits);
           hits &= hits - 1ull;
-          SphereRec s;
-          const uint32_t pk = __float_as_uint(s_rec[3][k]);
-          s.x0 = int(pk & 0xffffu);
-          s.y0 = int(pk >> 16);
-          s.xh = s_rec[0][k];
-          s.yh = s_rec[1][k];
-          s.kh = s_rec[2][k];
-          s.axh = s_rec[4][k];
-          s.ayh = s_rec[5][k];
-          s.cz = s_rec[6][k];
-          s.R = s_rec[7][k];
-          s.xl = s_rec[8][k];
-          s.yl = s_rec[9][k];
-          s.kl = s_rec[10][k];
-          s.axl = s_rec[11][k];
-          s.ayl = s_rec[12][k];
-          s.o = s_rec[13][k];
+          const SphereRec s = unpack_rec(s_rec[k][0], s_rec[k][1], s_rec[k][2], s_rec[k][3]);
           Hit h;
           if (exact_hit(ray, s, bc.zfar, h)) {
             const float s2 = s.o * (bc.zfar - h.t) * bc.kz;
@@ -203,18 +213,23 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A, CamDev ca
             const float wgt = s.o * h.delta * fast_exp2(s2 - m2);
             D += wgt;
 #pragma unroll
-            for (int ch = 0; ch < CM; ++ch) N[ch] += wgt * s_pay[ch][k];
+            for (int q = 0; q < CQ; ++q) {
+              const float4 f = s_pay[k][q];
+              const float fv[4] = {f.x, f.y, f.z, f.w};
+#pragma unroll
+              for (int u = 0; u < 4; ++u)
+                if (4 * q + u < CM) N[4 * q + u] += wgt * fv[u];
+            }
             if (A.track) klist_insert(kt, kid, h.t, s_id[k]);
           }
         }
       }
     }
 
-    if (ti.y == 1) {
+    if (slot == kNoSlot) {
       write_pixel(A, cam, ray.px, ray.py, m2, D, N, kt, kid);
     } else {
-      const long long slot = (long long)ti.z + ci;
-      if (slot < A.pcap) {
+      if ((long long)slot < A.pcap) {
         float* ps = A.pstate + size_t(slot) * size_t(kWave) * size_t(A.pstride);
         ps[0 * kWave + lane] = m2;
         ps[1 * kWave + lane] = D;
@@ -233,40 +248,64 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A, CamDev ca
   }
 }
 
-// Combines the partial states of tiles with several chunks, in chunk order.
+// Per tile: empty tiles show the background; tiles with several chunks
+// combine their partial states in chunk order (the next state is loaded
+// while the current one is folded in).
 template <int CM, int KM>
 __global__ __launch_bounds__(kWave) void k_fwd_merge(FwdKernelArgs A, CamDev cam) {
   const int tile = blockIdx.x;
   const int lane = threadIdx.x;
   const uint4 ti = A.tinfo[tile];
-  if (ti.y < 2 || (long long)ti.z + ti.y > A.pcap) return;
   const int px = (tile % cam.tiles_x) * kTileW + (lane % kTileW);
   const int py = (tile / cam.tiles_x) * kTileH + (lane / kTileW);
-  float m2 = -INFINITY, D = 0.f, N[CM];
+  float m2 = A.eps2, D = 1.f, N[CM];
   float kt[KM];
   uint32_t kid[KM];
   klist_init(kt, kid, A.K);
+  if (ti.y == 0) {
 #pragma unroll
-  for (int c = 0; c < CM; ++c) N[c] = 0.f;
+    for (int c = 0; c < CM; ++c) N[c] = c < A.cn ? A.bg[A.c0 + c] : 0.f;
+    write_pixel(A, cam, px, py, m2, D, N, kt, kid);
+    return;
+  }
+  if (ti.y < 2 || (long long)ti.x + ti.y > A.pcap) return;
+  // fields folded per state: m, D, numerator[CM], then K-list t[KM], id[KM]
+  constexpr int NF = 2 + CM + 2 * KM;
+  float cur[NF], nxt[NF];
+  auto load_state = [&](float (&dst)[NF], uint32_t slot) {
+    const float* ps = A.pstate + size_t(slot) * size_t(kWave) * size_t(A.pstride);
+#pragma unroll
+    for (int f = 0; f < 2 + CM; ++f) dst[f] = (f < 2 + A.cn) ? ps[f * kWave + lane] : 0.f;
+#pragma unroll
+    for (int f = 0; f < 2 * KM; ++f)
+      dst[2 + CM + f] = A.track ? ps[(A.kfield + f) * kWave + lane] : INFINITY;
+  };
+  load_state(cur, ti.x);
+  m2 = cur[0];
+  D = cur[1];
+#pragma unroll
+  for (int c = 0; c < CM; ++c) N[c] = cur[2 + c];
   for (uint32_t ci = 0; ci < ti.y; ++ci) {
-    const float* ps = A.pstate + size_t(ti.z + ci) * size_t(kWave) * size_t(A.pstride);
-    const float pm = ps[0 * kWave + lane], pD = ps[1 * kWave + lane];
-    // the first chunk holds the background, so m2 is finite from there on
-    const float mm = ci == 0 ? pm : fmaxf(m2, pm);
-    const float sa = ci == 0 ? 0.f : fast_exp2(m2 - mm), sb = fast_exp2(pm - mm);
-    D = D * sa + pD * sb;
+    if (ci + 1 < ti.y) load_state(nxt, ti.x + ci + 1);
+    if (ci > 0) {
+      // the first chunk holds the background, so m2 is finite from there on
+      const float mm = fmaxf(m2, cur[0]);
+      const float sa = fast_exp2(m2 - mm), sb = fast_exp2(cur[0] - mm);
+      D = D * sa + cur[1] * sb;
 #pragma unroll
-    for (int c = 0; c < CM; ++c)
-      if (c < A.cn) N[c] = N[c] * sa + ps[(2 + c) * kWave + lane] * sb;
-    m2 = mm;
+      for (int c = 0; c < CM; ++c) N[c] = N[c] * sa + cur[2 + c] * sb;
+      m2 = mm;
+    }
     if (A.track) {
 #pragma unroll
       for (int i = 0; i < KM; ++i) {
-        const float t = ps[(A.kfield + i) * kWave + lane];
+        const float t = cur[2 + CM + i];
         if (t < INFINITY && t > -INFINITY)
-          klist_insert(kt, kid, t, __float_as_uint(ps[(A.kfield + KM + i) * kWave + lane]));
+          klist_insert(kt, kid, t, __float_as_uint(cur[2 + CM + KM + i]));
       }
     }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) cur[f] = nxt[f];
   }
   write_pixel(A, cam, px, py, m2, D, N, kt, kid);
 }
@@ -311,7 +350,7 @@ hipError_t launch_forward(const Plan& q, const CamDev& cam, const BlendConst& bc
   stage_begin(PULSAR_STAGE_RASTER_FWD, stream);
   FwdKernelArgs A;
   A.status = ws_ptr<Status>(ws, q.off_status);
-  A.desc = ws_ptr<uint2>(ws, q.off_desc);
+  A.desc = ws_ptr<uint4>(ws, q.off_desc);
   A.tinfo = ws_ptr<uint4>(ws, q.off_tinfo);
   A.ranges = ws_ptr<uint32_t>(ws, q.off_ranges);
   A.svals = ws_ptr<uint32_t>(ws, sorted_in_a(q) ? q.off_valsA : q.off_valsB);
@@ -330,6 +369,7 @@ hipError_t launch_forward(const Plan& q, const CamDev& cam, const BlendConst& bc
   A.K = a.K;
   A.pstride = q.pstride;
   A.kfield = 2 + q.fwd_cm;
+  A.eps2 = bc.eps2;
   for (int c0 = 0; c0 < a.C; c0 += kFwdChannels) {
     A.c0 = c0;
     A.cn = a.C - c0 < kFwdChannels ? a.C - c0 : kFwdChannels;
