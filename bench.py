@@ -70,8 +70,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rows", type=int, default=8)
+    ap.add_argument("--cpu-rows", type=int, default=64)
     ap.add_argument("--spheres", type=int, default=1_000_000)
+    ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times) and exit; "
                          "calibrates the FETCH_SIZE / WRITE_SIZE counters")
@@ -122,10 +123,10 @@ def main() -> int:
     gf, gb = torch.empty((n, C), device=dev), torch.empty(C, device=dev)
     stream = torch.cuda.current_stream()
 
-    def step():
-        _capi.pulsar_fwd(pos, rad, opa, pay, bg, cs, ps, image, aux, ws, stream)
-        _capi.pulsar_bwd(pos, rad, opa, pay, bg, cs, ps, image, aux, G, gp, gr, go, gf, gb, ws,
-                         stream)
+    def step(s=None):
+        s = stream if s is None else s
+        _capi.pulsar_fwd(pos, rad, opa, pay, bg, cs, ps, image, aux, ws, s)
+        _capi.pulsar_bwd(pos, rad, opa, pay, bg, cs, ps, image, aux, G, gp, gr, go, gf, gb, ws, s)
 
     log("[bench] first step")
     step()
@@ -166,28 +167,54 @@ def main() -> int:
     assert code == _capi.PULSAR_OK
     fwd_ms = float(np.median([a.elapsed_time(b) for a, b, _ in ev]))
     bwd_ms = float(np.median([b.elapsed_time(c) for _, b, c in ev]))
-    step_ms = float(np.median([a.elapsed_time(c) for a, _, c in ev]))
+    eager_ms = float(np.median([a.elapsed_time(c) for a, _, c in ev]))
     wall_ms = wall * 1e3 / args.steps
-    log(f"[bench] median fwd {fwd_ms:.3f} ms, bwd {bwd_ms:.3f} ms, step {step_ms:.3f} ms, "
+    log(f"[bench] eager: median fwd {fwd_ms:.3f} ms, bwd {bwd_ms:.3f} ms, step {eager_ms:.3f} ms, "
         f"wall/step {wall_ms:.3f} ms")
+
+    # the same step captured once in a HIP graph and replayed (no host work, no launch gaps)
+    graph_ms = None
+    if not args.no_graph:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step(torch.cuda.current_stream())
+        for _ in range(args.warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        gev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        for e0, e1 in gev:
+            e0.record(stream)
+            graph.replay()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        code, _ = _capi.pulsar_query_status(ws, stream)
+        assert code == _capi.PULSAR_OK
+        graph_ms = float(np.median([a.elapsed_time(b) for a, b in gev]))
+        log(f"[bench] graph replay: median step {graph_ms:.3f} ms")
+    step_ms = graph_ms if graph_ms is not None else eager_ms
 
     fwd_b, bwd_b = io_bytes(n, H, W, C)
     stage_avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
-    dominant = max(stage_avg, key=stage_avg.get)
-    # algorithmic bytes the dominant stage must move ("Roofline")
+    # Compulsory bytes per launch of each stage ("Roofline"):
+    #   raster_bwd (one kernel, k_bwd_chunks): read G, F and L, read the payload,
+    #     write dL/df, dL/do and the camera-space position/radius sums
+    #   raster_fwd (k_fwd_chunks + k_fwd_merge): read the payload, write F and L
+    #   project: read pos, radius, opacity
     per_stage_bytes = {
-        "project": n * 20 + n * 4,
-        "binning": 0,
-        "raster_fwd": H * W * (4 * C + 4) + n * (4 * C + 4),
-        "zero": n * 4 * (C + 5),
-        "raster_bwd": bwd_b,
-        "finalize": n * (12 + 16 + 16),
+        "raster_bwd": H * W * (8 * C + 4) + n * 4 * C + n * 4 * (C + 5),
+        "raster_fwd": n * 4 * C + H * W * (4 * C + 4),
+        "project": n * 20,
     }
+    dominant = max(per_stage_bytes, key=lambda k: stage_avg.get(k, 0.0))
     dom_ms = stage_avg[dominant]
-    achieved = per_stage_bytes.get(dominant, 0) / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
-    roofline = {"kernel": dominant, "bound": "hbm", "achieved": round(achieved, 1),
+    achieved = per_stage_bytes[dominant] / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
+    kernel_name = {"raster_bwd": "k_bwd_chunks", "raster_fwd": "k_fwd_chunks+k_fwd_merge",
+                   "project": "k_project"}[dominant]
+    roofline = {"kernel": kernel_name, "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "avg_ms": round(dom_ms, 4)}
+                "traffic": None, "avg_ms": round(dom_ms, 4),
+                "bytes_per_launch": per_stage_bytes[dominant]}
     io_frac = (fwd_b + bwd_b) / (step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
 
     cpu = None
@@ -212,6 +239,8 @@ def main() -> int:
         "config": {"workload": wl.name, "spheres": int(n), "width": W, "height": H,
                    "channels": int(C), "K": int(par.K), "gamma": par.gamma,
                    "tile_pairs": int(pairs)},
+        "eager_ms_per_step": round(eager_ms, 4),
+        "graph_ms_per_step": None if graph_ms is None else round(graph_ms, 4),
         "fwd_ms": round(fwd_ms, 4),
         "bwd_ms": round(bwd_ms, 4),
         "frames_per_s": round(1e3 / step_ms, 2),
