@@ -38,6 +38,31 @@ def io_bytes(n: int, H: int, W: int, C: int):
     return fwd, bwd
 
 
+TRAFFIC_SOURCES = ["paper_2004_07484_amd/csrc/raster_bwd.hip",
+                   "paper_2004_07484_amd/csrc/hit_geometry.h",
+                   "paper_2004_07484_amd/csrc/device_common.h",
+                   "paper_2004_07484_amd/csrc/pulsar_internal.h"]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per dispatch from the committed rocprofv3 summary (FETCH_SIZE
+    and WRITE_SIZE scaled by the copy calibration), or None when the summary
+    is missing or the kernel's sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    rec = None
+    for line in open(path):
+        if line.strip().startswith("TRAFFIC "):
+            rec = json.loads(line.strip()[len("TRAFFIC "):])
+    if rec is None:
+        return None
+    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read()
+                                for p in TRAFFIC_SOURCES)).hexdigest()[:16]
+    return int(rec["bytes"]) if h == rec.get("sources_sha256_16") else None
+
+
 def cpu_baseline(wl, G, rows_n: int) -> dict:
     """FP64 brute-force oracle on a seeded row subset of the same workload,
     extrapolated linearly to the full frame."""
@@ -213,7 +238,8 @@ def main() -> int:
                    "project": "k_project"}[dominant]
     roofline = {"kernel": kernel_name, "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "avg_ms": round(dom_ms, 4),
+                "traffic": measured_traffic(kernel_name, wl.name) if dominant == "raster_bwd"
+                else None, "avg_ms": round(dom_ms, 4),
                 "bytes_per_launch": per_stage_bytes[dominant]}
     io_frac = (fwd_b + bwd_b) / (step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
 
