@@ -81,8 +81,9 @@ typedef struct pulsar_params {
   uint32_t flags;       /* reserved, must be 0 */
   int32_t max_pairs;    /* capacity of (screen tile, sphere) pairs; 0 = default
                            (2 n + number of tiles + 65536) */
-  int32_t depth_bits;   /* depth quantisation of the sort key; 0 = automatic.
-                           Changes only the summation order, not the result. */
+  int32_t depth_bits;   /* bits of quantised depth in the sort key (tile lists
+                           near to far); 0 = automatic (fills the last radix
+                           digit). Changes only the summation order. */
   int32_t reserved;     /* must be 0 */
 } pulsar_params_t;
 

@@ -214,45 +214,49 @@ __global__ void k_tile_ranges(const uint32_t* __restrict__ keys,
 // L / kChunk full chunks and one shorter chunk for the rest. Full chunks of
 // all tiles come first in the work list (the costlier items start first),
 // then the short ones. A tile with several chunks needs one partial blend
-// state per chunk (slots soff .. soff + n - 1), merged afterwards. Empty
-// tiles get no work item at all.
+// state per chunk (slots soff .. soff + n - 1), merged afterwards; such tiles
+// are also listed for the merge kernel. Empty tiles get no work item at all.
 struct TileChunks {
-  uint32_t nf, np, ns;  // full chunks, short chunks (0/1), partial-state slots
+  uint32_t nf, np, ns, nm;  // full chunks, short chunks (0/1), partial-state slots, merges (0/1)
 };
 
 __device__ __forceinline__ TileChunks tile_chunks(const uint32_t* __restrict__ ranges, int t,
                                                   int T) {
-  TileChunks c{0u, 0u, 0u};
+  TileChunks c{0u, 0u, 0u, 0u};
   if (t < T) {
     const uint32_t L = ranges[t + 1] - ranges[t];
     c.nf = L / kChunk;
     c.np = (L % kChunk) != 0u ? 1u : 0u;
     const uint32_t n = c.nf + c.np;
     c.ns = n >= 2 ? n : 0u;
+    c.nm = n >= 2 ? 1u : 0u;
   }
   return c;
 }
 
 __global__ __launch_bounds__(256) void k_chunk_count(const uint32_t* __restrict__ ranges, int T,
                                                      uint4* __restrict__ cpart) {
-  __shared__ uint32_t s_f[256 / kWave], s_p[256 / kWave], s_s[256 / kWave];
+  __shared__ uint32_t s_f[256 / kWave], s_p[256 / kWave], s_s[256 / kWave], s_m[256 / kWave];
   const int t = blockIdx.x * 256 + threadIdx.x;
   const TileChunks c = tile_chunks(ranges, t, T);
-  const uint32_t f = wave_sum_u32(c.nf), pp = wave_sum_u32(c.np), ss = wave_sum_u32(c.ns);
+  const uint32_t f = wave_sum_u32(c.nf), pp = wave_sum_u32(c.np), ss = wave_sum_u32(c.ns),
+                 mm = wave_sum_u32(c.nm);
   if ((threadIdx.x & (kWave - 1)) == 0) {
     s_f[threadIdx.x / kWave] = f;
     s_p[threadIdx.x / kWave] = pp;
     s_s[threadIdx.x / kWave] = ss;
+    s_m[threadIdx.x / kWave] = mm;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    uint32_t a = 0, b = 0, d = 0;
+    uint32_t a = 0, b = 0, d = 0, e = 0;
     for (int w = 0; w < 256 / kWave; ++w) {
       a += s_f[w];
       b += s_p[w];
       d += s_s[w];
+      e += s_m[w];
     }
-    cpart[blockIdx.x] = make_uint4(a, b, d, 0u);
+    cpart[blockIdx.x] = make_uint4(a, b, d, e);
   }
 }
 
@@ -261,42 +265,48 @@ __global__ __launch_bounds__(kScanThreads) void k_chunk_scan(uint4* __restrict__
                                                              int nblk, long long pcap,
                                                              Status* __restrict__ status) {
   __shared__ uint32_t s_f[kScanThreads / kWave], s_p[kScanThreads / kWave],
-      s_s[kScanThreads / kWave];
+      s_s[kScanThreads / kWave], s_m[kScanThreads / kWave];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-  uint32_t cf = 0, cp = 0, cs = 0;
+  uint32_t cf = 0, cp = 0, cs = 0, cm = 0;
   for (int base = 0; base < nblk; base += kScanThreads) {
     const int i = base + tid;
     const uint4 v = i < nblk ? cpart[i] : make_uint4(0u, 0u, 0u, 0u);
     const uint32_t inf = wave_incl_scan_u32(v.x, lane), inp = wave_incl_scan_u32(v.y, lane),
-                   ins = wave_incl_scan_u32(v.z, lane);
+                   ins = wave_incl_scan_u32(v.z, lane), inm = wave_incl_scan_u32(v.w, lane);
     if (lane == kWave - 1) {
       s_f[wid] = inf;
       s_p[wid] = inp;
       s_s[wid] = ins;
+      s_m[wid] = inm;
     }
     __syncthreads();
-    uint32_t bf = 0, bp = 0, bs = 0, tf = 0, tp = 0, ts = 0;
+    uint32_t bf = 0, bp = 0, bs = 0, bm = 0, tf = 0, tp = 0, ts = 0, tm = 0;
     for (int w = 0; w < kScanThreads / kWave; ++w) {
       if (w < wid) {
         bf += s_f[w];
         bp += s_p[w];
         bs += s_s[w];
+        bm += s_m[w];
       }
       tf += s_f[w];
       tp += s_p[w];
       ts += s_s[w];
+      tm += s_m[w];
     }
     if (i < nblk)
-      cpart[i] = make_uint4(cf + bf + inf - v.x, cp + bp + inp - v.y, cs + bs + ins - v.z, 0u);
+      cpart[i] = make_uint4(cf + bf + inf - v.x, cp + bp + inp - v.y, cs + bs + ins - v.z,
+                            cm + bm + inm - v.w);
     cf += tf;
     cp += tp;
     cs += ts;
+    cm += tm;
     __syncthreads();
   }
   if (tid == 0) {
     status->nfull = cf;
     status->nchunks = cf + cp;
     status->npartials = cs;
+    status->nmerge = cm;
     if ((long long)cs > pcap) status->code = uint32_t(-PULSAR_ERR_CAPACITY);
   }
 }
@@ -305,27 +315,31 @@ __global__ __launch_bounds__(256) void k_chunk_emit(const uint32_t* __restrict__
                                                     const uint4* __restrict__ cpart,
                                                     const Status* __restrict__ status,
                                                     uint4* __restrict__ tinfo,
-                                                    uint4* __restrict__ desc) {
-  __shared__ uint32_t s_f[256 / kWave], s_p[256 / kWave], s_s[256 / kWave];
+                                                    uint4* __restrict__ desc,
+                                                    uint32_t* __restrict__ mlist) {
+  __shared__ uint32_t s_f[256 / kWave], s_p[256 / kWave], s_s[256 / kWave], s_m[256 / kWave];
   const int t = blockIdx.x * 256 + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const TileChunks c = tile_chunks(ranges, t, T);
   const uint32_t inf = wave_incl_scan_u32(c.nf, lane), inp = wave_incl_scan_u32(c.np, lane),
-                 ins = wave_incl_scan_u32(c.ns, lane);
+                 ins = wave_incl_scan_u32(c.ns, lane), inm = wave_incl_scan_u32(c.nm, lane);
   if (lane == kWave - 1) {
     s_f[wid] = inf;
     s_p[wid] = inp;
     s_s[wid] = ins;
+    s_m[wid] = inm;
   }
   __syncthreads();
   const uint4 base = cpart[blockIdx.x];
-  uint32_t bf = base.x, bp = base.y, bs = base.z;
+  uint32_t bf = base.x, bp = base.y, bs = base.z, bm = base.w;
   for (int w = 0; w < wid; ++w) {
     bf += s_f[w];
     bp += s_p[w];
     bs += s_s[w];
+    bm += s_m[w];
   }
   if (t >= T) return;
+  if (c.nm) mlist[bm + inm - 1u] = uint32_t(t);
   const uint32_t foff = bf + inf - c.nf, poff = status->nfull + bp + inp - c.np;
   const uint32_t soff = bs + ins - c.ns;
   const uint32_t n = c.nf + c.np;
@@ -338,6 +352,59 @@ __global__ __launch_bounds__(256) void k_chunk_emit(const uint32_t* __restrict__
     const uint32_t at = ci < c.nf ? foff + ci : poff;
     desc[at] = make_uint4(uint32_t(t) | (ci == 0 ? kFirstChunk : 0u), beg, end, slot);
   }
+}
+
+// ---------------------------------------------------------------- K5b records
+// Copies every sphere record and payload row into sorted pair order, so the
+// raster kernels read their lists contiguously (coalesced, one dependent load
+// less). The fourth word of the copy holds the sphere index, with bit 31 set
+// when the sphere touches exactly one tile.
+__global__ __launch_bounds__(256) void k_gather_records(
+    const uint32_t* __restrict__ svals, const Status* __restrict__ status,
+    const float4* __restrict__ recA, const float4* __restrict__ recB,
+    const float4* __restrict__ recC, const float4* __restrict__ recD,
+    const float* __restrict__ payload, int C, float4* __restrict__ srec,
+    float* __restrict__ spay) {
+  // one thread per 16-byte unit: four record units, then the payload row in
+  // float4 units (C % 4 == 0) or single floats
+  const bool vec = (C & 3) == 0;
+  const uint32_t pu = vec ? uint32_t(C) / 4u : uint32_t(C);
+  const uint32_t units = 4u + pu;
+  const unsigned long long total = (unsigned long long)status->used * units;
+  for (unsigned long long t = (unsigned long long)blockIdx.x * 256 + threadIdx.x; t < total;
+       t += (unsigned long long)gridDim.x * 256) {
+    const uint32_t j = uint32_t(t / units), u = uint32_t(t % units);
+    const uint32_t id = svals[j];
+    if (u < 4u) {
+      const float4* src = u == 0u ? recA : u == 1u ? recB : u == 2u ? recC : recD;
+      float4 v = src[id];
+      if (u == 3u) {
+        const uint32_t single = __float_as_uint(v.w) == 1u ? kFirstChunk : 0u;
+        v.w = __uint_as_float(id | single);
+      }
+      srec[4 * size_t(j) + u] = v;
+    } else if (vec) {
+      const uint32_t q = u - 4u;
+      const float4 v = reinterpret_cast<const float4*>(payload + size_t(id) * size_t(C))[q];
+      reinterpret_cast<float4*>(spay + size_t(j) * size_t(C))[q] = v;
+    } else {
+      const uint32_t c = u - 4u;
+      const float v = payload[size_t(id) * size_t(C) + c];
+      spay[size_t(j) * size_t(C) + c] = v;
+    }
+  }
+}
+
+void launch_gather_records(const Plan& q, const float* payload, char* ws, hipStream_t stream) {
+  const uint32_t* svals = ws_ptr<uint32_t>(ws, sorted_in_a(q) ? q.off_valsA : q.off_valsB);
+  const long long units = 4 + ((q.C & 3) == 0 ? q.C / 4 : q.C);
+  long long blocks = (q.cap * units + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_gather_records, dim3(unsigned(blocks)), dim3(256), 0, stream, svals,
+                     ws_ptr<Status>(ws, q.off_status), ws_ptr<float4>(ws, q.off_recA),
+                     ws_ptr<float4>(ws, q.off_recB), ws_ptr<float4>(ws, q.off_recC),
+                     ws_ptr<float4>(ws, q.off_recD), payload, int(q.C),
+                     ws_ptr<float4>(ws, q.off_srec), ws_ptr<float>(ws, q.off_spay));
 }
 
 void launch_binning(const Plan& q, char* ws, hipStream_t stream) {
@@ -379,7 +446,8 @@ void launch_binning(const Plan& q, char* ws, hipStream_t stream) {
   hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kScanThreads), 0, stream, cpart, q.nblk_tiles,
                      (long long)q.pcap, status);
   hipLaunchKernelGGL(k_chunk_emit, dim3(q.nblk_tiles), dim3(256), 0, stream, ranges, T, cpart,
-                     status, ws_ptr<uint4>(ws, q.off_tinfo), ws_ptr<uint4>(ws, q.off_desc));
+                     status, ws_ptr<uint4>(ws, q.off_tinfo), ws_ptr<uint4>(ws, q.off_desc),
+                     ws_ptr<uint32_t>(ws, q.off_mlist));
 }
 
 }  // namespace pulsar

@@ -118,10 +118,9 @@ int make_plan(int64_t n, int W, int H, int C, const pulsar_params_t* p, Plan* ou
   if (p->depth_bits > 0) {
     q.depth_bits = p->depth_bits;
   } else {
-    // fill the key to a whole number of 8-bit digits with at least 8 depth bits
-    int total = (q.tile_bits + 8 + 7) / 8 * 8;
+    // the exact blend needs no depth order: only fill the last 8-bit digit
+    int total = (q.tile_bits + 7) / 8 * 8;
     q.depth_bits = total - q.tile_bits;
-    if (q.depth_bits > 16) q.depth_bits = 16;
   }
   if (q.tile_bits + q.depth_bits > 32) return PULSAR_ERR_UNSUPPORTED;
   q.passes = (q.tile_bits + q.depth_bits + 7) / 8;
@@ -166,9 +165,12 @@ int make_plan(int64_t n, int W, int H, int C, const pulsar_params_t* p, Plan* ou
   q.off_tinfo = take(size_t(q.T) * 16);
   q.off_desc = take(size_t(q.max_chunks) * 16);
   q.off_cpart = take(size_t(q.nblk_tiles + 1) * 16);
-  q.off_bgsum = take(size_t(kBgBlocks) * size_t(C) * 4);
+  q.off_bgsum = take(size_t((int64_t(W) * H + 1023) / 1024) * size_t(C) * 4);
   q.off_pstate = take(size_t(q.pcap) * kWave * size_t(q.pstride) * 4);
   q.off_thr = take(size_t(W) * size_t(H) * 8);
+  q.off_srec = take(size_t(cap) * 64);
+  q.off_spay = take(size_t(cap) * size_t(C) * 4);
+  q.off_mlist = take(size_t(q.T) * 4);
   q.total = o;
   *out = q;
   return PULSAR_OK;

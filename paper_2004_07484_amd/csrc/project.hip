@@ -11,8 +11,8 @@
 //           kappa = (c_z pitch / R)^2 (high FP32 parts)
 //   recB    (c_x / c_z, c_y / c_z, c_z, R) (ratios as high parts)
 //   recC    low parts of X_c - x0, Y_c - y0, kappa, c_x / c_z
-//   recD    (low part of c_y / c_z, opacity, x1 | y1 << 16, 0): x1, y1 is the
-//           last pixel of its rectangle
+//   recD    (low part of c_y / c_z, opacity, x1 | y1 << 16, tile count): x1,
+//           y1 is the last pixel of its rectangle
 // and the per-block sum of counts for the tile-pair scan. High + low FP32
 // parts carry the FP64 values to about 48 bits for the exact hit test.
 #include "device_common.h"
@@ -87,7 +87,8 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
         recB[i] = make_float4(axh, ayh, float(cz), float(R));
         recC[i] = make_float4(float(X - Xh), float(Y - Yh), float(kap - kh), float(ax - axh));
         const uint32_t packed_end = uint32_t(j1) | (uint32_t(i1) << 16);
-        recD[i] = make_float4(float(ay - ayh), o, __uint_as_float(packed_end), 0.f);
+        recD[i] = make_float4(float(ay - ayh), o, __uint_as_float(packed_end),
+                              __uint_as_float(count));
         // floor quantisation of (tmin - znear) / span, minus one step of margin,
         // so the decoded value never exceeds any float32 hit distance
         const double span = double(cam.zfar) - double(cam.znear);

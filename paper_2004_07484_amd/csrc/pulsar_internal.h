@@ -25,7 +25,6 @@ constexpr int kFwdChannels = 32;             // channels per forward pass (more:
 constexpr int kBwdChannels = 32;             // channels kept in registers by the backward
 constexpr int kChunk = 128;                  // sphere records per raster work item
 constexpr int kRasterGrid = 4096;            // persistent raster grid (one wave per block)
-constexpr int kBgBlocks = 1024;              // blocks of the background-gradient reduction
 constexpr uint32_t kFirstChunk = 0x80000000u;  // work item flag: first chunk of its tile
 constexpr uint32_t kNoSlot = 0xffffffffu;      // work item writes final pixels, no partial state
 
@@ -37,7 +36,8 @@ struct Status {
   uint32_t nchunks;             // raster work items (chunks of <= kChunk records of one tile)
   uint32_t npartials;           // partial blend states needed by tiles with several chunks
   uint32_t nfull;               // work items with exactly kChunk records (listed first)
-  uint32_t pad[57];
+  uint32_t nmerge;              // tiles with several work items
+  uint32_t pad[56];
 };
 
 // Camera constants in the form the kernels use.
@@ -72,6 +72,9 @@ struct Plan {
   // block sums of the chunk scan; the partial blend states; the per-pixel
   // K-th nearest hit (t, sphere id); background-gradient block sums
   size_t off_tinfo, off_desc, off_cpart, off_pstate, off_thr, off_bgsum;
+  // sphere records and payload rows copied into sorted pair order
+  size_t off_srec, off_spay;
+  size_t off_mlist;  // tiles with several work items, for the merge kernel
   int64_t max_chunks, pcap;
   int nblk_tiles, fwd_cm, klist_slots, pstride;
   size_t total;

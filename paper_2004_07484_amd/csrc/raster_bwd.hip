@@ -24,18 +24,12 @@ namespace pulsar {
 struct BwdKernelArgs {
   Status* status;
   const uint4* desc;
-  const uint32_t* ranges;
-  const uint32_t* svals;
-  const float4* recA;
-  const float4* recB;
-  const float4* recC;
-  const float4* recD;
-  const float* payload;
+  const float4* srec;   // sphere records in sorted pair order (index | single-tile flag in .w)
+  const float* spay;    // payload rows in sorted pair order
   const float* image;
   const float* aux;
   const float* grad_image;
   const float2* thr;
-  const uint32_t* counts;  // tiles per sphere (from the forward projection)
   float* gacc;
   float* grad_opacity;
   float* grad_payload;
@@ -127,12 +121,13 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks(BwdKernelArgs A, CamDev ca
       float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a, d = a;
       bool single = false;
       if (valid) {
-        id = A.svals[j];
-        a = A.recA[id];
-        b = A.recB[id];
-        c = A.recC[id];
-        d = A.recD[id];
-        single = A.counts[id] == 1u;
+        const float4* rp = A.srec + 4 * size_t(j);
+        a = rp[0];
+        b = rp[1];
+        c = rp[2];
+        d = rp[3];
+        id = __float_as_uint(d.w) & ~kFirstChunk;
+        single = (__float_as_uint(d.w) & kFirstChunk) != 0u;
       }
       // the sphere's rectangle inside this tile, in tile coordinates
       const uint32_t p0 = __float_as_uint(a.w), p1 = __float_as_uint(d.z);
@@ -145,7 +140,7 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks(BwdKernelArgs A, CamDev ca
       const uint32_t incl = wave_incl_scan_u32(n, lane);
       const uint32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
       const uint32_t magic = (65536u + w - 1u) / w;  // i / w = (i * magic) >> 16 for i < 64
-      const float* fp = A.payload + size_t(id) * size_t(C);
+      const float* fp = A.spay + size_t(valid ? j : 0u) * size_t(C);
       __syncthreads();  // the previous batch is done with the LDS below
       s_rec[lane][0] = a;
       s_rec[lane][1] = b;
@@ -273,10 +268,12 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A, CamD
     for (uint32_t b0 = beg; b0 < end; b0 += kWave) {
       const uint32_t j = b0 + uint32_t(lane);
       if (j >= end) continue;
-      const uint32_t id = A.svals[j];
-      const SphereRec s = load_rec(A.recA, A.recB, A.recC, A.recD, id);
-      const uint32_t p1 = __float_as_uint(A.recD[id].z);
-      const float* fk = A.payload + size_t(id) * size_t(C);
+      const float4* rp = A.srec + 4 * size_t(j);
+      const float4 d = rp[3];
+      const SphereRec s = unpack_rec(rp[0], rp[1], rp[2], d);
+      const uint32_t id = __float_as_uint(d.w) & ~kFirstChunk;
+      const uint32_t p1 = __float_as_uint(d.z);
+      const float* fk = A.spay + size_t(j) * size_t(C);
       float gcx = 0.f, gcy = 0.f, gcz = 0.f, gR = 0.f, go = 0.f;
       bool any = false;
       const int xa = max(s.x0, tx0), xb = min(int(p1 & 0xffffu), tx0 + kTileW - 1);
@@ -363,8 +360,15 @@ __global__ void k_finalize(int n, const uint32_t* __restrict__ counts,
     }
     if (grad_radius) grad_radius[i] = 0.f;
     if (grad_opacity) grad_opacity[i] = 0.f;
-    if (grad_payload)
-      for (int c = 0; c < C; ++c) grad_payload[size_t(i) * size_t(C) + c] = 0.f;
+    if (grad_payload) {
+      float* row = grad_payload + size_t(i) * size_t(C);
+      if ((C & 3) == 0 && (reinterpret_cast<uintptr_t>(grad_payload) & 15u) == 0u) {
+        for (int c = 0; c < C; c += 4)
+          *reinterpret_cast<float4*>(row + c) = make_float4(0.f, 0.f, 0.f, 0.f);
+      } else {
+        for (int c = 0; c < C; ++c) row[c] = 0.f;
+      }
+    }
     return;
   }
   if (!gacc) return;
@@ -390,36 +394,45 @@ __global__ void k_finalize(int n, const uint32_t* __restrict__ counts,
 }
 
 // Background gradient, dL/dbg = sum_p exp(eps/gamma - L_p) G_p: per-block
-// partial sums over a grid-stride walk of the pixels, [kBgBlocks][C].
+// partial sums, [blocks][C]; each block covers 256 x kBgPixels pixels.
+constexpr int kBgPixels = 4;
 __global__ __launch_bounds__(256) void k_bg_partial(const float* __restrict__ aux,
                                                     const float* __restrict__ grad_image,
                                                     long long npix, int C, float eps2,
                                                     float* __restrict__ bgsum) {
-  __shared__ float s[256 / kWave];
+  __shared__ float s[256 / kWave][8];
+  const long long p0 = (long long)blockIdx.x * 256 * kBgPixels + threadIdx.x;
+  float w[kBgPixels];
+#pragma unroll
+  for (int k = 0; k < kBgPixels; ++k) {
+    const long long p = p0 + k * 256;
+    w[k] = p < npix ? fast_exp2(eps2 - aux[p] * 1.4426950408889634f) : 0.f;
+  }
   for (int c0 = 0; c0 < C; c0 += 8) {
     float acc[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) acc[c] = 0.f;
-    for (long long p = (long long)blockIdx.x * 256 + threadIdx.x; p < npix;
-         p += (long long)gridDim.x * 256) {
-      const float w = fast_exp2(eps2 - aux[p] * 1.4426950408889634f);
-      const float* g = grad_image + p * C + c0;
 #pragma unroll
-      for (int c = 0; c < 8; ++c)
-        if (c0 + c < C) acc[c] += w * g[c];
+    for (int k = 0; k < kBgPixels; ++k) {
+      const long long p = p0 + k * 256;
+      if (p < npix) {
+        const float* g = grad_image + size_t(p) * size_t(C) + c0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          if (c0 + c < C) acc[c] += w[k] * g[c];
+      }
     }
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      if (c0 + c >= C) break;
-      const float v = wave_sum(acc[c]);
-      __syncthreads();
-      if ((threadIdx.x & (kWave - 1)) == 0) s[threadIdx.x / kWave] = v;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        float tsum = 0.f;
-        for (int w = 0; w < 256 / kWave; ++w) tsum += s[w];
-        bgsum[size_t(blockIdx.x) * size_t(C) + c0 + c] = tsum;
-      }
+    for (int c = 0; c < 8; ++c) acc[c] = wave_sum(acc[c]);
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) s[threadIdx.x / kWave][c] = acc[c];
+    __syncthreads();
+    if (threadIdx.x < 8 && c0 + int(threadIdx.x) < C) {
+      float tsum = 0.f;
+      for (int w2 = 0; w2 < 256 / kWave; ++w2) tsum += s[w2][threadIdx.x];
+      bgsum[size_t(blockIdx.x) * size_t(C) + c0 + threadIdx.x] = tsum;
     }
   }
 }
@@ -447,18 +460,13 @@ hipError_t launch_backward(const Plan& q, const CamDev& cam, const BlendConst& b
   BwdKernelArgs A;
   A.status = ws_ptr<Status>(ws, q.off_status);
   A.desc = ws_ptr<uint4>(ws, q.off_desc);
-  A.ranges = ws_ptr<uint32_t>(ws, q.off_ranges);
-  A.svals = ws_ptr<uint32_t>(ws, sorted_in_a(q) ? q.off_valsA : q.off_valsB);
-  A.recA = ws_ptr<float4>(ws, q.off_recA);
-  A.recB = ws_ptr<float4>(ws, q.off_recB);
-  A.recC = ws_ptr<float4>(ws, q.off_recC);
-  A.recD = ws_ptr<float4>(ws, q.off_recD);
-  A.payload = a.payload;
+  A.srec = ws_ptr<float4>(ws, q.off_srec);
+  A.spay = ws_ptr<float>(ws, q.off_spay);
   A.image = a.image;
   A.aux = a.aux;
   A.grad_image = a.grad_image;
   A.thr = ws_ptr<float2>(ws, q.off_thr);
-  A.counts = ws_ptr<uint32_t>(ws, q.off_counts);
+  const uint32_t* counts = ws_ptr<uint32_t>(ws, q.off_counts);
   A.gacc = need_geo ? ws_ptr<float>(ws, q.off_gacc) : nullptr;
   A.grad_opacity = a.grad_opacity;
   A.grad_payload = a.grad_payload;
@@ -469,7 +477,7 @@ hipError_t launch_backward(const Plan& q, const CamDev& cam, const BlendConst& b
   const uint32_t min_count = a.C <= kBwdChannels ? 2u : 1u;
   if (q.n > 0)
     hipLaunchKernelGGL(k_bwd_prep, dim3(unsigned((q.n + 255) / 256)), dim3(256), 0, stream,
-                       int(q.n), A.counts, min_count, a.C, reinterpret_cast<float4*>(A.gacc),
+                       int(q.n), counts, min_count, a.C, reinterpret_cast<float4*>(A.gacc),
                        a.grad_opacity, a.grad_payload);
   stage_end(PULSAR_STAGE_ZERO, stream);
   stage_begin(PULSAR_STAGE_RASTER_BWD, stream);
@@ -492,14 +500,16 @@ hipError_t launch_backward(const Plan& q, const CamDev& cam, const BlendConst& b
   stage_begin(PULSAR_STAGE_FINALIZE, stream);
   if (q.n > 0)
     hipLaunchKernelGGL(k_finalize, dim3(unsigned((q.n + 255) / 256)), dim3(256), 0, stream,
-                       int(q.n), A.counts, a.pos, a.radius, cam, a.min_radius_px, a.C,
+                       int(q.n), counts, a.pos, a.radius, cam, a.min_radius_px, a.C,
                        reinterpret_cast<const float4*>(A.gacc), a.grad_pos, a.grad_radius,
                        a.grad_opacity, a.grad_payload);
   if (a.grad_bg) {
-    hipLaunchKernelGGL(k_bg_partial, dim3(kBgBlocks), dim3(256), 0, stream, a.aux, a.grad_image,
-                       (long long)(q.W * q.H), int(q.C), bc.eps2, bgsum);
-    hipLaunchKernelGGL(k_reduce_bg, dim3(unsigned(q.C)), dim3(256), 0, stream, bgsum,
-                       kBgBlocks, int(q.C), a.grad_bg);
+    const long long npix = q.W * q.H;
+    const int nb = int((npix + 256 * kBgPixels - 1) / (256 * kBgPixels));
+    hipLaunchKernelGGL(k_bg_partial, dim3(unsigned(nb)), dim3(256), 0, stream, a.aux,
+                       a.grad_image, npix, int(q.C), bc.eps2, bgsum);
+    hipLaunchKernelGGL(k_reduce_bg, dim3(unsigned(q.C)), dim3(256), 0, stream, bgsum, nb,
+                       int(q.C), a.grad_bg);
   }
   stage_end(PULSAR_STAGE_FINALIZE, stream);
   return hipGetLastError();

@@ -3,7 +3,8 @@
 // Work item = a chunk of at most kChunk depth-sorted records of one non-empty
 // 8x8 tile (long tile lists are split, so no wave walks thousands of spheres
 // alone); a persistent grid of one-wave blocks takes work items round-robin,
-// full chunks first. Per batch of 64 records:
+// full chunks first. Records and payloads were copied into sorted pair order
+// after the sort, so a batch is one contiguous read. Per batch of 64 records:
 //   A. sphere-parallel: the (record, pixel of its rectangle inside the tile)
 //      pairs are flattened over the lanes by a prefix sum over rectangle
 //      sizes; each pair runs the cheap FP32 test and a candidate sets bit l
@@ -18,8 +19,8 @@
 // index), and the K-th one becomes the pixel's gradient threshold.
 // A tile with one chunk writes its pixels directly; otherwise every chunk
 // leaves a partial state (m, D, numerator, K-list) and k_fwd_merge combines
-// them in chunk order, so the result is deterministic. k_fwd_merge also
-// fills the empty tiles with the background.
+// them in chunk order, so the result is deterministic. k_fwd_background
+// fills the tiles that no sphere touches.
 #include "hit_geometry.h"
 
 namespace pulsar {
@@ -55,13 +56,9 @@ struct FwdKernelArgs {
   Status* status;
   const uint4* desc;
   const uint4* tinfo;
-  const uint32_t* ranges;
-  const uint32_t* svals;
-  const float4* recA;
-  const float4* recB;
-  const float4* recC;
-  const float4* recD;
-  const float* payload;
+  const uint32_t* mlist;
+  const float4* srec;   // sphere records in sorted pair order, 4 float4 each
+  const float* spay;    // payload rows in sorted pair order
   const float* bg;
   float* image;
   float* aux;
@@ -127,11 +124,12 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A, CamDev ca
       float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a, d = a;
       uint32_t id = 0;
       if (valid) {
-        id = A.svals[j];
-        a = A.recA[id];
-        b = A.recB[id];
-        c = A.recC[id];
-        d = A.recD[id];
+        const float4* rp = A.srec + 4 * size_t(j);
+        a = rp[0];
+        b = rp[1];
+        c = rp[2];
+        d = rp[3];
+        id = __float_as_uint(d.w) & ~kFirstChunk;
       }
       // the sphere's rectangle inside this tile, in tile coordinates; the
       // (sphere, pixel) pairs are flattened over the wave by a prefix sum
@@ -154,7 +152,7 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A, CamDev ca
       s_rec[lane][1] = b;
       s_rec[lane][2] = c;
       s_rec[lane][3] = d;
-      const float* fp = A.payload + size_t(id) * size_t(A.C) + A.c0;
+      const float* fp = A.spay + size_t(valid ? j : 0u) * size_t(A.C) + A.c0;
 #pragma unroll
       for (int q = 0; q < CQ; ++q) {
         float v[4];
@@ -248,78 +246,127 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A, CamDev ca
   }
 }
 
-// Per tile: empty tiles show the background; tiles with several chunks
-// combine their partial states in chunk order (the next state is loaded
-// while the current one is folded in).
+// Tiles with several work items combine their partial states: four waves per
+// tile each fold every fourth state (loading the next one while folding the
+// current), then wave 0 folds the other three in wave order. The order is
+// fixed, so the result is deterministic. A persistent grid walks the list of
+// such tiles.
+constexpr int kMergeWaves = 4;
+
 template <int CM, int KM>
-__global__ __launch_bounds__(kWave) void k_fwd_merge(FwdKernelArgs A, CamDev cam) {
-  const int tile = blockIdx.x;
-  const int lane = threadIdx.x;
-  const uint4 ti = A.tinfo[tile];
-  const int px = (tile % cam.tiles_x) * kTileW + (lane % kTileW);
-  const int py = (tile / cam.tiles_x) * kTileH + (lane / kTileW);
-  float m2 = A.eps2, D = 1.f, N[CM];
-  float kt[KM];
-  uint32_t kid[KM];
-  klist_init(kt, kid, A.K);
-  if (ti.y == 0) {
+__global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(FwdKernelArgs A, CamDev cam) {
+  constexpr int NF = 2 + CM + 2 * KM;  // m, D, numerator[CM], K-list t[KM], id[KM]
+  __shared__ float s_state[kMergeWaves - 1][NF][kWave];
+  const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  const uint32_t nmerge = A.status->nmerge;
+  for (uint32_t mi = blockIdx.x; mi < nmerge; mi += gridDim.x) {
+    const int tile = int(A.mlist[mi]);
+    const uint4 ti = A.tinfo[tile];
+    if ((long long)ti.x + ti.y > A.pcap) continue;  // capacity exceeded (reported)
+    float m2 = -INFINITY, D = 0.f, N[CM];
+    float kt[KM];
+    uint32_t kid[KM];
+    klist_init(kt, kid, A.K);
 #pragma unroll
-    for (int c = 0; c < CM; ++c) N[c] = c < A.cn ? A.bg[A.c0 + c] : 0.f;
-    write_pixel(A, cam, px, py, m2, D, N, kt, kid);
-    return;
-  }
-  if (ti.y < 2 || (long long)ti.x + ti.y > A.pcap) return;
-  // fields folded per state: m, D, numerator[CM], then K-list t[KM], id[KM]
-  constexpr int NF = 2 + CM + 2 * KM;
-  float cur[NF], nxt[NF];
-  auto load_state = [&](float (&dst)[NF], uint32_t slot) {
-    const float* ps = A.pstate + size_t(slot) * size_t(kWave) * size_t(A.pstride);
+    for (int c = 0; c < CM; ++c) N[c] = 0.f;
+    float cur[NF], nxt[NF];
+    auto load_state = [&](float (&dst)[NF], uint32_t slot) {
+      const float* ps = A.pstate + size_t(slot) * size_t(kWave) * size_t(A.pstride);
 #pragma unroll
-    for (int f = 0; f < 2 + CM; ++f) dst[f] = (f < 2 + A.cn) ? ps[f * kWave + lane] : 0.f;
+      for (int f = 0; f < 2 + CM; ++f) dst[f] = (f < 2 + A.cn) ? ps[f * kWave + lane] : 0.f;
 #pragma unroll
-    for (int f = 0; f < 2 * KM; ++f)
-      dst[2 + CM + f] = A.track ? ps[(A.kfield + f) * kWave + lane] : INFINITY;
-  };
-  load_state(cur, ti.x);
-  m2 = cur[0];
-  D = cur[1];
+      for (int f = 0; f < 2 * KM; ++f)
+        dst[2 + CM + f] = A.track ? ps[(A.kfield + f) * kWave + lane] : INFINITY;
+    };
+    auto fold = [&](const float (&st)[NF]) {
+      const float mm = fmaxf(m2, st[0]);
+      if (mm > -INFINITY) {
+        const float sa = fast_exp2(m2 - mm), sb = fast_exp2(st[0] - mm);
+        D = D * sa + st[1] * sb;
 #pragma unroll
-  for (int c = 0; c < CM; ++c) N[c] = cur[2 + c];
-  for (uint32_t ci = 0; ci < ti.y; ++ci) {
-    if (ci + 1 < ti.y) load_state(nxt, ti.x + ci + 1);
-    if (ci > 0) {
-      // the first chunk holds the background, so m2 is finite from there on
-      const float mm = fmaxf(m2, cur[0]);
-      const float sa = fast_exp2(m2 - mm), sb = fast_exp2(cur[0] - mm);
-      D = D * sa + cur[1] * sb;
+        for (int c = 0; c < CM; ++c) N[c] = N[c] * sa + st[2 + c] * sb;
+        m2 = mm;
+      }
+      if (A.track) {
 #pragma unroll
-      for (int c = 0; c < CM; ++c) N[c] = N[c] * sa + cur[2 + c] * sb;
-      m2 = mm;
+        for (int i = 0; i < KM; ++i) {
+          const float t = st[2 + CM + i];
+          if (t < INFINITY && t > -INFINITY)
+            klist_insert(kt, kid, t, __float_as_uint(st[2 + CM + KM + i]));
+        }
+      }
+    };
+    uint32_t ci = uint32_t(wv);
+    if (ci < ti.y) load_state(cur, ti.x + ci);
+    for (; ci < ti.y; ci += kMergeWaves) {
+      if (ci + kMergeWaves < ti.y) load_state(nxt, ti.x + ci + kMergeWaves);
+      fold(cur);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) cur[f] = nxt[f];
     }
-    if (A.track) {
+    __syncthreads();  // the previous tile's readers are done with s_state
+    if (wv > 0) {
+      s_state[wv - 1][0][lane] = m2;
+      s_state[wv - 1][1][lane] = D;
+#pragma unroll
+      for (int c = 0; c < CM; ++c) s_state[wv - 1][2 + c][lane] = N[c];
 #pragma unroll
       for (int i = 0; i < KM; ++i) {
-        const float t = cur[2 + CM + i];
-        if (t < INFINITY && t > -INFINITY)
-          klist_insert(kt, kid, t, __float_as_uint(cur[2 + CM + KM + i]));
+        s_state[wv - 1][2 + CM + i][lane] = kt[i];
+        s_state[wv - 1][2 + CM + KM + i][lane] = __uint_as_float(kid[i]);
       }
     }
+    __syncthreads();
+    if (wv == 0) {
+      for (int w = 0; w < kMergeWaves - 1; ++w) {
+        float st[NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) cur[f] = nxt[f];
+        for (int f = 0; f < NF; ++f) st[f] = s_state[w][f][lane];
+        fold(st);
+      }
+      const int px = (tile % cam.tiles_x) * kTileW + lane % kTileW;
+      const int py = (tile / cam.tiles_x) * kTileH + lane / kTileW;
+      write_pixel(A, cam, px, py, m2, D, N, kt, kid);
+    }
   }
-  write_pixel(A, cam, px, py, m2, D, N, kt, kid);
+}
+
+// Pixels of tiles without any sphere: F = background, L = eps / gamma, and
+// no hit for the gradient threshold. One thread per pixel.
+template <int CM>
+__global__ __launch_bounds__(256) void k_fwd_background(FwdKernelArgs A, CamDev cam) {
+  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
+  float bgv[CM];
+#pragma unroll
+  for (int c = 0; c < CM; ++c) bgv[c] = c < A.cn ? A.bg[A.c0 + c] : 0.f;
+  if (p >= (long long)cam.W * cam.H) return;
+  const int py = int(p / cam.W), px = int(p % cam.W);
+  const int tile = (py / kTileH) * cam.tiles_x + px / kTileW;
+  if (A.tinfo[tile].y != 0u) return;
+  float* out = A.image + size_t(p) * size_t(A.C) + A.c0;
+#pragma unroll
+  for (int c = 0; c < CM; ++c)
+    if (c < A.cn) out[c] = bgv[c];
+  if (A.c0 == 0 && A.aux) A.aux[p] = A.eps2 * 0.69314718055994531f;
+  if (A.track) A.thr[p] = make_float2(INFINITY, __uint_as_float(0xffffffffu));
 }
 
 void launch_project(const Plan& q, const CamDev& cam, const FwdArgs& a, char* ws,
                     hipStream_t stream);
 void launch_binning(const Plan& q, char* ws, hipStream_t stream);
+void launch_gather_records(const Plan& q, const float* payload, char* ws, hipStream_t stream);
 
 template <int CM, int KM>
 static void launch_raster_fwd_cm(const Plan& q, const CamDev& cam, const BlendConst& bc,
                                  const FwdKernelArgs& A, hipStream_t stream) {
   hipLaunchKernelGGL((k_fwd_chunks<CM, KM>), dim3(kRasterGrid), dim3(kWave), 0, stream, A, cam,
                      bc);
-  hipLaunchKernelGGL((k_fwd_merge<CM, KM>), dim3(unsigned(q.T)), dim3(kWave), 0, stream, A, cam);
+  const unsigned mgrid = unsigned(q.T < kRasterGrid ? q.T : kRasterGrid);
+  hipLaunchKernelGGL((k_fwd_merge<CM, KM>), dim3(mgrid), dim3(kWave * kMergeWaves), 0, stream,
+                     A, cam);
+  const long long npix = q.W * q.H;
+  hipLaunchKernelGGL((k_fwd_background<CM>), dim3(unsigned((npix + 255) / 256)), dim3(256), 0,
+                     stream, A, cam);
 }
 
 template <int KM>
@@ -346,19 +393,16 @@ hipError_t launch_forward(const Plan& q, const CamDev& cam, const BlendConst& bc
   stage_end(PULSAR_STAGE_PROJECT, stream);
   stage_begin(PULSAR_STAGE_BINNING, stream);
   launch_binning(q, ws, stream);
+  if (q.n > 0) launch_gather_records(q, a.payload, ws, stream);
   stage_end(PULSAR_STAGE_BINNING, stream);
   stage_begin(PULSAR_STAGE_RASTER_FWD, stream);
   FwdKernelArgs A;
   A.status = ws_ptr<Status>(ws, q.off_status);
   A.desc = ws_ptr<uint4>(ws, q.off_desc);
   A.tinfo = ws_ptr<uint4>(ws, q.off_tinfo);
-  A.ranges = ws_ptr<uint32_t>(ws, q.off_ranges);
-  A.svals = ws_ptr<uint32_t>(ws, sorted_in_a(q) ? q.off_valsA : q.off_valsB);
-  A.recA = ws_ptr<float4>(ws, q.off_recA);
-  A.recB = ws_ptr<float4>(ws, q.off_recB);
-  A.recC = ws_ptr<float4>(ws, q.off_recC);
-  A.recD = ws_ptr<float4>(ws, q.off_recD);
-  A.payload = a.payload;
+  A.mlist = ws_ptr<uint32_t>(ws, q.off_mlist);
+  A.srec = ws_ptr<float4>(ws, q.off_srec);
+  A.spay = ws_ptr<float>(ws, q.off_spay);
   A.bg = a.bg;
   A.image = a.image;
   A.aux = a.aux;
