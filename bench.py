@@ -89,6 +89,151 @@ def cpu_baseline(wl, G, rows_n: int) -> dict:
             "fwd_ms": round((t1 - t0) * 1e3 * scale, 1), "bwd_ms": round((t2 - t1) * 1e3 * scale, 1)}
 
 
+def bench_batch(args, dev) -> dict:
+    """Uneven batch of 32 scenes (1k-500k spheres, 256^2-1024^2, random
+    cameras; C = 3, K = 5): one batched fwd+bwd per step against a loop of
+    single-scene fwd+bwd calls on the same stream, both eager and replayed
+    from a HIP graph."""
+    import torch
+
+    from paper_2004_07484_amd import _capi
+    from paper_2004_07484_amd import scenegen as sg
+
+    wls = sg.config4_scenes()
+    par = wls[0].params
+    C = wls[0].scene.C
+    B = len(wls)
+    cams = [_capi.make_camera(w.camera.R, w.camera.t, w.camera.focal, w.camera.sensor_width,
+                              w.camera.znear, w.camera.zfar, w.camera.width, w.camera.height)
+            for w in wls]
+    counts = [w.scene.n for w in wls]
+    scenes = _capi.make_scenes(cams, counts)
+    N, P = _capi.batch_sizes(scenes)
+    log(f"[batch] {B} scenes, {N} spheres, {P} pixels")
+
+    def t(a):
+        return torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
+
+    pos = t(np.concatenate([w.scene.pos for w in wls]))
+    rad = t(np.concatenate([w.scene.radius for w in wls]))
+    opa = t(np.concatenate([w.scene.opacity for w in wls]))
+    pay = t(np.concatenate([w.scene.payload for w in wls]))
+    bg = t(np.stack([w.scene.bg for w in wls]))
+    G = t(np.concatenate([sg.upstream_grad(w.seed + 1000 + b, w.camera.height, w.camera.width, C)
+                          .reshape(-1, C) for b, w in enumerate(wls)]))
+    image = torch.empty((P, C), device=dev)
+    aux = torch.empty((P,), device=dev)
+    gp, gr, go = torch.empty((N, 3), device=dev), torch.empty(N, device=dev), \
+        torch.empty(N, device=dev)
+    gf, gb = torch.empty((N, C), device=dev), torch.empty((B, C), device=dev)
+    ps = _capi.make_params(par.gamma, par.eps, par.min_radius_px, par.K)
+    ws = torch.empty(_capi.pulsar_batch_workspace_size(scenes, C, ps), dtype=torch.uint8,
+                     device=dev)
+    stream = torch.cuda.current_stream()
+
+    def batched(s):
+        _capi.pulsar_fwd_batched(scenes, pos, rad, opa, pay, bg, ps, image, aux, ws, s)
+        _capi.pulsar_bwd_batched(scenes, pos, rad, opa, pay, bg, ps, image, aux, G, gp, gr, go,
+                                 gf, gb, ws, s)
+
+    # per-scene views into the same packed buffers; one workspace serves every
+    # scene because the calls run one after another on one stream
+    views, n0, p0 = [], 0, 0
+    for b, (w, c) in enumerate(zip(wls, cams)):
+        n, hw = w.scene.n, w.camera.height * w.camera.width
+        H, W = w.camera.height, w.camera.width
+        views.append((c, pos[n0:n0 + n], rad[n0:n0 + n], opa[n0:n0 + n], pay[n0:n0 + n], bg[b],
+                      image[p0:p0 + hw].view(H, W, C), aux[p0:p0 + hw].view(H, W),
+                      G[p0:p0 + hw].view(H, W, C), gp[n0:n0 + n], gr[n0:n0 + n], go[n0:n0 + n],
+                      gf[n0:n0 + n], gb[b]))
+        n0 += n
+        p0 += hw
+    ws1 = torch.empty(max(_capi.pulsar_workspace_size(w.scene.n, w.camera.width,
+                                                      w.camera.height, C, ps) for w in wls),
+                      dtype=torch.uint8, device=dev)
+
+    def looped(s):
+        for (c, p_, r_, o_, f_, b_, im, ax, g_, gp_, gr_, go_, gf_, gb_) in views:
+            _capi.pulsar_fwd(p_, r_, o_, f_, b_, c, ps, im, ax, ws1, s)
+            _capi.pulsar_bwd(p_, r_, o_, f_, b_, c, ps, im, ax, g_, gp_, gr_, go_, gf_, gb_, ws1, s)
+
+    def time_eager(fn):
+        for _ in range(args.warmup):
+            fn(stream)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        for e0, e1 in evs:
+            e0.record(stream)
+            fn(stream)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+    def time_graph(fn):
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            fn(torch.cuda.current_stream())
+        for _ in range(args.warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        for e0, e1 in evs:
+            e0.record(stream)
+            graph.replay()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+    batched(stream)
+    code, pairs = _capi.pulsar_query_status(ws, stream)
+    assert code == _capi.PULSAR_OK, "batched tile-pair capacity"
+    knobs = None
+    if not args.no_tune:
+        from paper_2004_07484_amd import autotune as at
+        wss = {}
+
+        def run(p):
+            key = (p.chunk, p.raster_blocks, p.depth_bits)
+            if key not in wss:
+                wss[key] = torch.empty(_capi.pulsar_batch_workspace_size(scenes, C, p),
+                                       dtype=torch.uint8, device=dev)
+            w = wss[key]
+            _capi.pulsar_fwd_batched(scenes, pos, rad, opa, pay, bg, p, image, aux, w, stream)
+            _capi.pulsar_bwd_batched(scenes, pos, rad, opa, pay, bg, p, image, aux, G, gp, gr, go,
+                                     gf, gb, w, stream)
+
+        tuned, info = at.tune(run, ps, reps=5, warmup=2)
+        ps.chunk, ps.raster_blocks, ps.depth_bits = tuned.chunk, tuned.raster_blocks, \
+            tuned.depth_bits
+        ws = wss[(ps.chunk, ps.raster_blocks, ps.depth_bits)]
+        wss.clear()
+        knobs = info["knobs"]
+        log(f"[batch] tuned knobs {knobs}")
+        # the looped calls use the same knobs; their workspace may grow with them
+        ws1 = torch.empty(max(_capi.pulsar_workspace_size(w.scene.n, w.camera.width,
+                                                          w.camera.height, C, ps) for w in wls),
+                          dtype=torch.uint8, device=dev)
+    looped(stream)
+    torch.cuda.synchronize()
+    res = {"batched_eager_ms": time_eager(batched), "looped_eager_ms": time_eager(looped)}
+    if not args.no_graph:
+        res["batched_graph_ms"] = time_graph(batched)
+        res["looped_graph_ms"] = time_graph(looped)
+    code, _ = _capi.pulsar_query_status(ws, stream)
+    assert code == _capi.PULSAR_OK
+    bt = res.get("batched_graph_ms", res["batched_eager_ms"])
+    lt = min(res.get("looped_graph_ms", np.inf), res["looped_eager_ms"])
+    log(f"[batch] batched {bt:.3f} ms, looped {lt:.3f} ms per batch of {B}")
+    out = {"workload": "uneven32_c3_k5", "scenes": B, "spheres": int(N), "pixels": int(P),
+           "tile_pairs": int(pairs), "batched_frames_per_s": round(B / (bt * 1e-3), 1),
+           "looped_frames_per_s": round(B / (lt * 1e-3), 1),
+           "speedup": round(lt / bt, 3), "tuned_knobs": knobs}
+    out.update({k: round(v, 4) for k, v in res.items()})
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -98,6 +243,10 @@ def main() -> int:
     ap.add_argument("--cpu-rows", type=int, default=64)
     ap.add_argument("--spheres", type=int, default=1_000_000)
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched-vs-looped measurement of 32 uneven scenes")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the default launch knobs instead of autotuning them first")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times) and exit; "
                          "calibrates the FETCH_SIZE / WRITE_SIZE counters")
@@ -164,6 +313,26 @@ def main() -> int:
         step()
         code, pairs = _capi.pulsar_query_status(ws, stream)
         assert code == _capi.PULSAR_OK
+    tune_info = None
+    if not args.no_tune:
+        from paper_2004_07484_amd import autotune as at
+        wss = {}
+
+        def run(p):
+            key = (p.chunk, p.raster_blocks, p.depth_bits)
+            if key not in wss:
+                wss[key] = torch.empty(_capi.pulsar_workspace_size(n, W, H, C, p),
+                                       dtype=torch.uint8, device=dev)
+            w = wss[key]
+            _capi.pulsar_fwd(pos, rad, opa, pay, bg, cs, p, image, aux, w, stream)
+            _capi.pulsar_bwd(pos, rad, opa, pay, bg, cs, p, image, aux, G, gp, gr, go, gf, gb, w,
+                             stream)
+
+        ps, tune_info = at.tune(run, ps, reps=5, warmup=2)
+        ws = wss[(ps.chunk, ps.raster_blocks, ps.depth_bits)]
+        wss.clear()
+        torch.cuda.synchronize()
+        log(f"[bench] tuned knobs {tune_info['knobs']} ({tune_info['ms']:.3f} ms eager)")
     log(f"[bench] {pairs} tile pairs; warmup {args.warmup}")
     for _ in range(args.warmup):
         step()
@@ -243,6 +412,10 @@ def main() -> int:
                 "bytes_per_launch": per_stage_bytes[dominant]}
     io_frac = (fwd_b + bwd_b) / (step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
 
+    batch = None
+    if not args.no_batch:
+        batch = bench_batch(args, dev)
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline on {args.cpu_rows} rows")
@@ -250,7 +423,7 @@ def main() -> int:
         log(f"[bench] oracle {cpu['value']} ms/frame on {cpu['cores']} threads")
 
     out = {
-        "metric": "fwd+bwd ms/frame at 1M spheres 1024^2 FP32",
+        "metric": "fwd+bwd ms/frame at 1M spheres 1024^2 FP32; batched vs looped frames/s",
         "value": round(step_ms, 4),
         "unit": "ms/frame",
         "n_gpus": 1,
@@ -275,6 +448,8 @@ def main() -> int:
         "io_roofline_frac": round(io_frac, 4),
         "stages_ms": {k: round(v, 4) for k, v in stage_avg.items()},
         "roofline": roofline,
+        "tuned_knobs": None if tune_info is None else tune_info["knobs"],
+        "batched": batch,
         "cpu_baseline": cpu,
         "paper_context": "RTX 2080, 1M spheres at 1000^2: fwd 19 ms, bwd 4.7 ms (CUDA only)",
     }

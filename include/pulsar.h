@@ -84,6 +84,14 @@ typedef struct pulsar_params {
   int32_t depth_bits;   /* bits of quantised depth in the sort key (tile lists
                            near to far); 0 = automatic (fills the last radix
                            digit). Changes only the summation order. */
+  int32_t chunk;        /* sphere records per raster work item: 0 = automatic
+                           (128), else a multiple of 64 in [64, 1024]. Long tile
+                           lists are split into work items of this size and
+                           their partial blends merged. Changes only the
+                           summation order. */
+  int32_t raster_blocks;/* blocks of the persistent raster kernels: 0 = automatic
+                           (4096), else in [256, 65536]. Never changes the image;
+                           gradients only within float atomic reordering. */
   int32_t reserved;     /* must be 0 */
 } pulsar_params_t;
 
@@ -129,6 +137,59 @@ int pulsar_bwd(const float* pos, const float* radius, const float* opacity,
                float* grad_opacity, float* grad_payload, float* grad_background, void* ws,
                size_t ws_bytes, void* stream);
 
+/* ---- Batched rendering: several independent scenes in one call.
+ *
+ * Each scene is the problem of Sec. 3.1-3.2 on its own: a sphere set, a
+ * camera and an image size. A batched call renders all of them with one
+ * launch per pipeline stage (all scenes' tiles share the persistent raster
+ * grid), which is what a loop of single-scene calls cannot do for small
+ * scenes. The results equal those of pulsar_fwd / pulsar_bwd per scene up to
+ * float summation order.
+ *
+ * Packing (B scenes, N = sum of n_b spheres, P = sum of H_b W_b pixels):
+ *   pos [N,3], radius [N], opacity [N] or NULL, payload [N,C]
+ *       scene b owns rows n_0 + ... + n_{b-1} onwards, in scene order;
+ *   background [B,C]                 one background feature per scene;
+ *   image [P,C], aux [P], grad_image [P,C]
+ *       scene b owns the H_b x W_b row-major block of pixels that starts after
+ *       the pixels of scenes 0 .. b-1;
+ *   grad_pos [N,3], grad_radius [N], grad_opacity [N], grad_payload [N,C],
+ *   grad_background [B,C]            packed like their inputs.
+ * C, K, gamma and every other parameter are shared. The scene array is read
+ * on the host during the call only; its cameras are copied into the launch
+ * arguments, so a captured graph replays with the cameras of capture time
+ * while reading the sphere and image buffers afresh at every replay. */
+#define PULSAR_MAX_SCENES 4096
+
+typedef struct pulsar_scene {
+  pulsar_camera_t camera;  /* camera and image size of this scene */
+  int32_t n;               /* its number of spheres, >= 0 */
+  int32_t reserved;        /* must be 0 */
+} pulsar_scene_t;
+
+/* Workspace bytes of a batched pair of calls on these B scenes (1 <= B <=
+ * PULSAR_MAX_SCENES). Returns 0 for invalid arguments. For B = 1 it equals
+ * pulsar_workspace_size of that scene. */
+size_t pulsar_batch_workspace_size(const pulsar_scene_t* scenes, int32_t B, int32_t C,
+                                   const pulsar_params_t* params);
+
+/* Batched forward: pulsar_fwd for every scene, packed as described above.
+ * Totals must satisfy N < 2^31 and fewer than 2^31 8x8 tiles. */
+int pulsar_fwd_batched(const pulsar_scene_t* scenes, int32_t B, const float* pos,
+                       const float* radius, const float* opacity, const float* payload,
+                       int32_t C, const float* background, const pulsar_params_t* params,
+                       float* image, float* aux, void* ws, size_t ws_bytes, void* stream);
+
+/* Batched backward: pulsar_bwd for every scene; the same rules on NULL
+ * outputs and on pairing with the preceding forward apply. */
+int pulsar_bwd_batched(const pulsar_scene_t* scenes, int32_t B, const float* pos,
+                       const float* radius, const float* opacity, const float* payload,
+                       int32_t C, const float* background, const pulsar_params_t* params,
+                       const float* image, const float* aux, const float* grad_image,
+                       float* grad_pos, float* grad_radius, float* grad_opacity,
+                       float* grad_payload, float* grad_background, void* ws,
+                       size_t ws_bytes, void* stream);
+
 /* Synchronises `stream` and reports the status the device wrote into the
  * workspace during the last pulsar_fwd: PULSAR_OK or PULSAR_ERR_CAPACITY.
  * If pairs is not NULL it receives the number of (tile, sphere) pairs that
@@ -159,7 +220,7 @@ int pulsar_timing_enable(int on);
 int pulsar_timing_read(double* total_ms, int64_t* counts);
 const char* pulsar_stage_name(int stage);
 
-/* ABI version of this header, currently 1. */
+/* ABI version of this header, currently 2. */
 int pulsar_version(void);
 
 #ifdef __cplusplus

@@ -22,11 +22,13 @@ PULSAR_ERR_UNSUPPORTED = -3
 PULSAR_ERR_HIP = -4
 PULSAR_ERR_CAPACITY = -5
 
-EXPORTED = ("pulsar_workspace_size", "pulsar_fwd", "pulsar_bwd", "pulsar_query_status",
+EXPORTED = ("pulsar_workspace_size", "pulsar_fwd", "pulsar_bwd", "pulsar_batch_workspace_size",
+            "pulsar_fwd_batched", "pulsar_bwd_batched", "pulsar_query_status",
             "pulsar_status_string", "pulsar_last_hip_error", "pulsar_timing_enable",
             "pulsar_timing_read", "pulsar_stage_name", "pulsar_version")
 
 PULSAR_NUM_STAGES = 6
+PULSAR_MAX_SCENES = 4096
 
 
 class PulsarLibraryMissing(RuntimeError):
@@ -52,7 +54,13 @@ class pulsar_params_t(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_float), ("eps", ctypes.c_float),
                 ("min_radius_px", ctypes.c_float), ("K", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("max_pairs", ctypes.c_int32),
-                ("depth_bits", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("depth_bits", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("raster_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class pulsar_scene_t(ctypes.Structure):
+    _fields_ = [("camera", pulsar_camera_t), ("n", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -78,6 +86,19 @@ def load():
     lib.pulsar_bwd.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp,
                                ctypes.POINTER(pulsar_camera_t), ctypes.POINTER(pulsar_params_t),
                                _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    lib.pulsar_batch_workspace_size.restype = ctypes.c_size_t
+    lib.pulsar_batch_workspace_size.argtypes = [ctypes.POINTER(pulsar_scene_t), ctypes.c_int32,
+                                                ctypes.c_int32, ctypes.POINTER(pulsar_params_t)]
+    lib.pulsar_fwd_batched.restype = ctypes.c_int
+    lib.pulsar_fwd_batched.argtypes = [ctypes.POINTER(pulsar_scene_t), ctypes.c_int32, _vp, _vp,
+                                       _vp, _vp, ctypes.c_int32, _vp,
+                                       ctypes.POINTER(pulsar_params_t), _vp, _vp, _vp,
+                                       ctypes.c_size_t, _vp]
+    lib.pulsar_bwd_batched.restype = ctypes.c_int
+    lib.pulsar_bwd_batched.argtypes = [ctypes.POINTER(pulsar_scene_t), ctypes.c_int32, _vp, _vp,
+                                       _vp, _vp, ctypes.c_int32, _vp,
+                                       ctypes.POINTER(pulsar_params_t), _vp, _vp, _vp, _vp, _vp,
+                                       _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
     lib.pulsar_query_status.restype = ctypes.c_int
     lib.pulsar_query_status.argtypes = [_vp, ctypes.c_size_t, _vp,
                                         ctypes.POINTER(ctypes.c_int64)]
@@ -113,12 +134,33 @@ def make_camera(R, t, focal, sensor_width, znear, zfar, width, height) -> pulsar
 
 
 def make_params(gamma=0.1, eps=1e-5, min_radius_px=0.0, K=8, max_pairs=0,
-                depth_bits=0) -> pulsar_params_t:
+                depth_bits=0, chunk=0, raster_blocks=0) -> pulsar_params_t:
     p = pulsar_params_t()
     p.gamma, p.eps, p.min_radius_px = float(gamma), float(eps), float(min_radius_px)
     p.K, p.flags, p.max_pairs, p.depth_bits, p.reserved = int(K), 0, int(max_pairs), \
         int(depth_bits), 0
+    p.chunk, p.raster_blocks = int(chunk), int(raster_blocks)
     return p
+
+
+def make_scenes(cameras, counts):
+    """ctypes array of pulsar_scene_t from cameras (pulsar_camera_t) and sphere counts."""
+    cameras, counts = list(cameras), [int(c) for c in counts]
+    if len(cameras) != len(counts):
+        raise ValueError("one sphere count per camera")
+    arr = (pulsar_scene_t * len(cameras))()
+    for b, (c, n) in enumerate(zip(cameras, counts)):
+        arr[b].camera = c
+        arr[b].n = n
+        arr[b].reserved = 0
+    return arr
+
+
+def batch_sizes(scenes) -> Tuple[int, int]:
+    """(total spheres, total pixels) of a scene array."""
+    N = sum(int(s.n) for s in scenes)
+    P = sum(int(s.camera.width) * int(s.camera.height) for s in scenes)
+    return N, P
 
 
 def _flat(x):
@@ -205,6 +247,48 @@ def pulsar_bwd(pos, radius, opacity, payload, background, cam: pulsar_camera_t,
         _ws_ptr(ws), int(ws.numel()), _stream(stream))
     if rc != PULSAR_OK:
         raise PulsarError(rc, "pulsar_bwd")
+
+
+def pulsar_batch_workspace_size(scenes, C: int, params: pulsar_params_t) -> int:
+    return int(load().pulsar_batch_workspace_size(scenes, len(scenes), int(C),
+                                                  ctypes.byref(params)))
+
+
+def pulsar_fwd_batched(scenes, pos, radius, opacity, payload, background,
+                       params: pulsar_params_t, image, aux, ws, stream=None) -> None:
+    """Packed batch (include/pulsar.h): pos [N,3], background [B,C], image [P,C], aux [P]."""
+    B = len(scenes)
+    N, P = batch_sizes(scenes)
+    C = int(payload.shape[1])
+    rc = load().pulsar_fwd_batched(
+        scenes, B, _ptr(pos, "pos", N > 0, (N, 3)), _ptr(radius, "radius", N > 0, (N,)),
+        _ptr(opacity, "opacity", False, (N,)), _ptr(payload, "payload", N > 0, (N, C)), C,
+        _ptr(background, "background", True, (B, C)), ctypes.byref(params),
+        _ptr(image, "image", True, (P, C)), _ptr(aux, "aux", False, (P,)),
+        _ws_ptr(ws), int(ws.numel()), _stream(stream))
+    if rc != PULSAR_OK:
+        raise PulsarError(rc, "pulsar_fwd_batched")
+
+
+def pulsar_bwd_batched(scenes, pos, radius, opacity, payload, background,
+                       params: pulsar_params_t, image, aux, grad_image, grad_pos, grad_radius,
+                       grad_opacity, grad_payload, grad_background, ws, stream=None) -> None:
+    B = len(scenes)
+    N, P = batch_sizes(scenes)
+    C = int(payload.shape[1])
+    rc = load().pulsar_bwd_batched(
+        scenes, B, _ptr(pos, "pos", N > 0, (N, 3)), _ptr(radius, "radius", N > 0, (N,)),
+        _ptr(opacity, "opacity", False, (N,)), _ptr(payload, "payload", N > 0, (N, C)), C,
+        _ptr(background, "background", True, (B, C)), ctypes.byref(params),
+        _ptr(image, "image", True, (P, C)), _ptr(aux, "aux", True, (P,)),
+        _ptr(grad_image, "grad_image", True, (P, C)),
+        _ptr(grad_pos, "grad_pos", False, (N, 3)), _ptr(grad_radius, "grad_radius", False, (N,)),
+        _ptr(grad_opacity, "grad_opacity", False, (N,)),
+        _ptr(grad_payload, "grad_payload", False, (N, C)),
+        _ptr(grad_background, "grad_background", False, (B, C)),
+        _ws_ptr(ws), int(ws.numel()), _stream(stream))
+    if rc != PULSAR_OK:
+        raise PulsarError(rc, "pulsar_bwd_batched")
 
 
 def pulsar_query_status(ws, stream=None) -> Tuple[int, int]:

@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partials(
 __global__ __launch_bounds__(kProjectBlock) void k_emit(
     int n, const uint32_t* __restrict__ counts, const ushort4* __restrict__ trect,
     const uint32_t* __restrict__ qdepth, const unsigned long long* __restrict__ partials,
-    int tiles_x, int depth_bits, long long cap, uint32_t* __restrict__ keys,
+    SceneTable tab, int depth_bits, long long cap, uint32_t* __restrict__ keys,
     uint32_t* __restrict__ vals) {
   __shared__ unsigned long long s_wave[kProjectBlock / kWave];
   const int i = blockIdx.x * kProjectBlock + threadIdx.x;
@@ -64,10 +64,13 @@ __global__ __launch_bounds__(kProjectBlock) void k_emit(
   unsigned long long at = before + incl - c;
   const ushort4 tr = trect[i];
   const uint32_t q = qdepth[i];
+  // tiles are numbered scene by scene, row-major inside each scene
+  const SceneDev& sc = tab.scenes[find_scene(tab.sph_start, tab.B, uint32_t(i))];
+  const uint32_t tiles_x = uint32_t(sc.cam.tiles_x), tile0 = sc.tile_off;
   for (int ty = tr.y; ty <= tr.w; ++ty) {
     for (int tx = tr.x; tx <= tr.z; ++tx, ++at) {
       if (at >= (unsigned long long)cap) return;
-      const uint32_t tile = uint32_t(ty) * uint32_t(tiles_x) + uint32_t(tx);
+      const uint32_t tile = tile0 + uint32_t(ty) * tiles_x + uint32_t(tx);
       keys[at] = (tile << depth_bits) | q;
       vals[at] = uint32_t(i);
     }
@@ -210,8 +213,8 @@ __global__ void k_tile_ranges(const uint32_t* __restrict__ keys,
 }
 
 // ---------------------------------------------------------------- work items
-// Each non-empty tile's list is cut into chunks of at most kChunk records:
-// L / kChunk full chunks and one shorter chunk for the rest. Full chunks of
+// Each non-empty tile's list is cut into chunks of at most `chunk` records:
+// L / chunk full chunks and one shorter chunk for the rest. Full chunks of
 // all tiles come first in the work list (the costlier items start first),
 // then the short ones. A tile with several chunks needs one partial blend
 // state per chunk (slots soff .. soff + n - 1), merged afterwards; such tiles
@@ -221,12 +224,12 @@ struct TileChunks {
 };
 
 __device__ __forceinline__ TileChunks tile_chunks(const uint32_t* __restrict__ ranges, int t,
-                                                  int T) {
+                                                  int T, uint32_t chunk) {
   TileChunks c{0u, 0u, 0u, 0u};
   if (t < T) {
     const uint32_t L = ranges[t + 1] - ranges[t];
-    c.nf = L / kChunk;
-    c.np = (L % kChunk) != 0u ? 1u : 0u;
+    c.nf = L / chunk;
+    c.np = (L % chunk) != 0u ? 1u : 0u;
     const uint32_t n = c.nf + c.np;
     c.ns = n >= 2 ? n : 0u;
     c.nm = n >= 2 ? 1u : 0u;
@@ -235,10 +238,10 @@ __device__ __forceinline__ TileChunks tile_chunks(const uint32_t* __restrict__ r
 }
 
 __global__ __launch_bounds__(256) void k_chunk_count(const uint32_t* __restrict__ ranges, int T,
-                                                     uint4* __restrict__ cpart) {
+                                                     uint32_t chunk, uint4* __restrict__ cpart) {
   __shared__ uint32_t s_f[256 / kWave], s_p[256 / kWave], s_s[256 / kWave], s_m[256 / kWave];
   const int t = blockIdx.x * 256 + threadIdx.x;
-  const TileChunks c = tile_chunks(ranges, t, T);
+  const TileChunks c = tile_chunks(ranges, t, T, chunk);
   const uint32_t f = wave_sum_u32(c.nf), pp = wave_sum_u32(c.np), ss = wave_sum_u32(c.ns),
                  mm = wave_sum_u32(c.nm);
   if ((threadIdx.x & (kWave - 1)) == 0) {
@@ -312,6 +315,7 @@ __global__ __launch_bounds__(kScanThreads) void k_chunk_scan(uint4* __restrict__
 }
 
 __global__ __launch_bounds__(256) void k_chunk_emit(const uint32_t* __restrict__ ranges, int T,
+                                                    uint32_t chunk,
                                                     const uint4* __restrict__ cpart,
                                                     const Status* __restrict__ status,
                                                     uint4* __restrict__ tinfo,
@@ -320,7 +324,7 @@ __global__ __launch_bounds__(256) void k_chunk_emit(const uint32_t* __restrict__
   __shared__ uint32_t s_f[256 / kWave], s_p[256 / kWave], s_s[256 / kWave], s_m[256 / kWave];
   const int t = blockIdx.x * 256 + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  const TileChunks c = tile_chunks(ranges, t, T);
+  const TileChunks c = tile_chunks(ranges, t, T, chunk);
   const uint32_t inf = wave_incl_scan_u32(c.nf, lane), inp = wave_incl_scan_u32(c.np, lane),
                  ins = wave_incl_scan_u32(c.ns, lane), inm = wave_incl_scan_u32(c.nm, lane);
   if (lane == kWave - 1) {
@@ -346,8 +350,8 @@ __global__ __launch_bounds__(256) void k_chunk_emit(const uint32_t* __restrict__
   tinfo[t] = make_uint4(soff, n, 0u, 0u);
   const uint32_t rb = ranges[t], re = ranges[t + 1];
   for (uint32_t ci = 0; ci < n; ++ci) {
-    const uint32_t beg = rb + ci * kChunk;
-    const uint32_t end = min(re, beg + kChunk);
+    const uint32_t beg = rb + ci * chunk;
+    const uint32_t end = min(re, beg + chunk);
     const uint32_t slot = n >= 2 ? soff + ci : kNoSlot;
     const uint32_t at = ci < c.nf ? foff + ci : poff;
     desc[at] = make_uint4(uint32_t(t) | (ci == 0 ? kFirstChunk : 0u), beg, end, slot);
@@ -421,7 +425,7 @@ void launch_binning(const Plan& q, char* ws, hipStream_t stream) {
   if (q.n > 0)
     hipLaunchKernelGGL(k_emit, dim3(q.nblk_proj), dim3(kProjectBlock), 0, stream, int(q.n),
                        ws_ptr<uint32_t>(ws, q.off_counts), ws_ptr<ushort4>(ws, q.off_trect),
-                       ws_ptr<uint32_t>(ws, q.off_qdepth), partials, int(q.tiles_x),
+                       ws_ptr<uint32_t>(ws, q.off_qdepth), partials, scene_table(q, ws),
                        q.depth_bits, (long long)q.cap, kA, vA);
   for (int p = 0; p < q.passes; ++p) {
     const int shift = 8 * p;
@@ -442,11 +446,13 @@ void launch_binning(const Plan& q, char* ws, hipStream_t stream) {
   hipLaunchKernelGGL(k_tile_ranges, dim3((T + 1 + 255) / 256), dim3(256), 0, stream, ksorted,
                      status, T, q.depth_bits, ranges);
   uint4* cpart = ws_ptr<uint4>(ws, q.off_cpart);
-  hipLaunchKernelGGL(k_chunk_count, dim3(q.nblk_tiles), dim3(256), 0, stream, ranges, T, cpart);
+  const uint32_t chunk = uint32_t(q.chunk);
+  hipLaunchKernelGGL(k_chunk_count, dim3(q.nblk_tiles), dim3(256), 0, stream, ranges, T, chunk,
+                     cpart);
   hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kScanThreads), 0, stream, cpart, q.nblk_tiles,
                      (long long)q.pcap, status);
-  hipLaunchKernelGGL(k_chunk_emit, dim3(q.nblk_tiles), dim3(256), 0, stream, ranges, T, cpart,
-                     status, ws_ptr<uint4>(ws, q.off_tinfo), ws_ptr<uint4>(ws, q.off_desc),
+  hipLaunchKernelGGL(k_chunk_emit, dim3(q.nblk_tiles), dim3(256), 0, stream, ranges, T, chunk,
+                     cpart, status, ws_ptr<uint4>(ws, q.off_tinfo), ws_ptr<uint4>(ws, q.off_desc),
                      ws_ptr<uint32_t>(ws, q.off_mlist));
 }
 

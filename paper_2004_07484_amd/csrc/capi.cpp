@@ -57,6 +57,10 @@ int check_params(const pulsar_params_t* p) {
   if (p->K < 1 || p->K > kMaxK) return PULSAR_ERR_INVALID_ARGUMENT;
   if (p->max_pairs < 0) return PULSAR_ERR_INVALID_ARGUMENT;
   if (p->depth_bits < 0 || p->depth_bits > 16) return PULSAR_ERR_INVALID_ARGUMENT;
+  if (p->chunk != 0 && (p->chunk < 64 || p->chunk > 1024 || p->chunk % 64 != 0))
+    return PULSAR_ERR_INVALID_ARGUMENT;
+  if (p->raster_blocks != 0 && (p->raster_blocks < 256 || p->raster_blocks > 65536))
+    return PULSAR_ERR_INVALID_ARGUMENT;
   if (p->flags != 0u || p->reserved != 0) return PULSAR_ERR_UNSUPPORTED;
   return PULSAR_OK;
 }
@@ -99,20 +103,59 @@ void stage_end(int stage, hipStream_t stream) {
   g_open[stage] = nullptr;
 }
 
-int make_plan(int64_t n, int W, int H, int C, const pulsar_params_t* p, Plan* out) {
-  if (n < 0 || n > INT32_MAX || C < 1 || W < 1 || W > 65535 || H < 1 || H > 65535)
-    return PULSAR_ERR_INVALID_ARGUMENT;
+int make_scenes(const pulsar_scene_t* scenes, int B, const pulsar_params_t* p,
+                std::vector<SceneDev>* out) {
+  if (!scenes || B < 1 || B > PULSAR_MAX_SCENES) return PULSAR_ERR_INVALID_ARGUMENT;
   int rc = check_params(p);
   if (rc != PULSAR_OK) return rc;
+  out->clear();
+  out->reserve(size_t(B));
+  int64_t sph = 0, tiles = 0, blk = 0;
+  unsigned long long pix = 0;
+  for (int b = 0; b < B; ++b) {
+    const pulsar_scene_t& sc = scenes[b];
+    rc = check_camera(&sc.camera);
+    if (rc != PULSAR_OK) return rc;
+    if (sc.n < 0) return PULSAR_ERR_INVALID_ARGUMENT;
+    if (sc.reserved != 0) return PULSAR_ERR_UNSUPPORTED;
+    SceneDev d;
+    std::memset(&d, 0, sizeof(d));
+    d.cam = make_cam(&sc.camera);
+    d.bc = make_blend(&sc.camera, p);
+    d.sph_off = uint32_t(sph);
+    d.n = uint32_t(sc.n);
+    d.tile_off = uint32_t(tiles);
+    d.bgblk_off = uint32_t(blk);
+    d.pix_off = pix;
+    const int64_t npix = int64_t(sc.camera.width) * sc.camera.height;
+    sph += sc.n;
+    tiles += int64_t(d.cam.tiles_x) * d.cam.tiles_y;
+    blk += (npix + kBgBlockPixels - 1) / kBgBlockPixels;
+    pix += (unsigned long long)npix;
+    // sphere indices and tile numbers carry a flag in bit 31
+    if (sph > INT32_MAX || tiles > INT32_MAX || blk > INT32_MAX)
+      return PULSAR_ERR_INVALID_ARGUMENT;
+    out->push_back(d);
+  }
+  return PULSAR_OK;
+}
+
+int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, Plan* out) {
+  if (sc.empty() || C < 1) return PULSAR_ERR_INVALID_ARGUMENT;
+  int rc = check_params(p);
+  if (rc != PULSAR_OK) return rc;
+  const SceneDev& last = sc.back();
+  const int64_t lastpix = int64_t(last.cam.W) * last.cam.H;
   Plan q;
   std::memset(&q, 0, sizeof(q));
-  q.n = n;
+  q.B = int(sc.size());
+  q.n = int64_t(last.sph_off) + last.n;
   q.C = C;
-  q.W = W;
-  q.H = H;
-  q.tiles_x = (W + kTileW - 1) / kTileW;
-  q.tiles_y = (H + kTileH - 1) / kTileH;
-  q.T = q.tiles_x * q.tiles_y;
+  q.T = int64_t(last.tile_off) + int64_t(last.cam.tiles_x) * last.cam.tiles_y;
+  q.npix = int64_t(last.pix_off) + lastpix;
+  q.nbgblk = int64_t(last.bgblk_off) + (lastpix + kBgBlockPixels - 1) / kBgBlockPixels;
+  q.chunk = p->chunk > 0 ? p->chunk : kChunkDefault;
+  q.raster_grid = p->raster_blocks > 0 ? p->raster_blocks : kRasterGridDefault;
   q.tile_bits = ceil_log2(q.T);
   if (q.tile_bits < 1) q.tile_bits = 1;
   if (p->depth_bits > 0) {
@@ -124,6 +167,7 @@ int make_plan(int64_t n, int W, int H, int C, const pulsar_params_t* p, Plan* ou
   }
   if (q.tile_bits + q.depth_bits > 32) return PULSAR_ERR_UNSUPPORTED;
   q.passes = (q.tile_bits + q.depth_bits + 7) / 8;
+  const int64_t n = q.n;
   int64_t cap = p->max_pairs > 0 ? int64_t(p->max_pairs) : 2 * n + q.T + 65536;
   if (cap > (int64_t(1) << 31) - 1) cap = (int64_t(1) << 31) - 1;
   q.cap = cap;
@@ -137,6 +181,8 @@ int make_plan(int64_t n, int W, int H, int C, const pulsar_params_t* p, Plan* ou
   };
   const size_t nn = size_t(n > 0 ? n : 1);
   q.off_status = take(sizeof(Status));
+  q.off_scenes = take(size_t(q.B) * sizeof(SceneDev));
+  q.off_starts = take(size_t(3) * size_t(q.B + 1) * 4);
   q.off_counts = take(nn * 4);
   q.off_trect = take(nn * 8);
   q.off_qdepth = take(nn * 4);
@@ -153,9 +199,8 @@ int make_plan(int64_t n, int W, int H, int C, const pulsar_params_t* p, Plan* ou
   q.off_hist = take(size_t(kSortRadix) * size_t(q.nblk_sort) * 4);
   q.off_dtot = take(size_t(kSortRadix) * 4);
   q.off_ranges = take(size_t(q.T + 1) * 4);
-  q.off_bgpart = take(size_t(q.T) * size_t(C) * 4);
-  q.max_chunks = (cap + kChunk - 1) / kChunk + q.T;
-  q.pcap = (cap + kChunk - 1) / kChunk + 1024;
+  q.max_chunks = (cap + q.chunk - 1) / q.chunk + q.T;
+  q.pcap = (cap + q.chunk - 1) / q.chunk + 1024;
   q.nblk_tiles = int((q.T + 255) / 256);
   q.fwd_cm = C < kFwdChannels ? C : kFwdChannels;
   int km = 4;  // register K-list slots: a power of two >= K, at least 4
@@ -165,9 +210,9 @@ int make_plan(int64_t n, int W, int H, int C, const pulsar_params_t* p, Plan* ou
   q.off_tinfo = take(size_t(q.T) * 16);
   q.off_desc = take(size_t(q.max_chunks) * 16);
   q.off_cpart = take(size_t(q.nblk_tiles + 1) * 16);
-  q.off_bgsum = take(size_t((int64_t(W) * H + 1023) / 1024) * size_t(C) * 4);
+  q.off_bgsum = take(size_t(q.nbgblk) * size_t(C) * 4);
   q.off_pstate = take(size_t(q.pcap) * kWave * size_t(q.pstride) * 4);
-  q.off_thr = take(size_t(W) * size_t(H) * 8);
+  q.off_thr = take(size_t(q.npix) * 8);
   q.off_srec = take(size_t(cap) * 64);
   q.off_spay = take(size_t(cap) * size_t(C) * 4);
   q.off_mlist = take(size_t(q.T) * 4);
@@ -211,25 +256,43 @@ using namespace pulsar;
 
 extern "C" {
 
-size_t pulsar_workspace_size(int32_t n, int32_t width, int32_t height, int32_t C,
-                             const pulsar_params_t* params) {
+size_t pulsar_batch_workspace_size(const pulsar_scene_t* scenes, int32_t B, int32_t C,
+                                   const pulsar_params_t* params) {
+  std::vector<SceneDev> sc;
+  if (make_scenes(scenes, B, params, &sc) != PULSAR_OK) return 0;
   Plan q;
-  if (make_plan(n, width, height, C, params, &q) != PULSAR_OK) return 0;
+  if (make_plan(sc, C, params, &q) != PULSAR_OK) return 0;
   return q.total;
 }
 
-int pulsar_fwd(const float* pos, const float* radius, const float* opacity,
-               const float* payload, int32_t n, int32_t C, const float* background,
-               const pulsar_camera_t* cam, const pulsar_params_t* params, float* image,
-               float* aux, void* ws, size_t ws_bytes, void* stream) {
-  int rc = check_camera(cam);
+size_t pulsar_workspace_size(int32_t n, int32_t width, int32_t height, int32_t C,
+                             const pulsar_params_t* params) {
+  pulsar_scene_t sc;
+  std::memset(&sc, 0, sizeof(sc));
+  // any valid camera: the workspace depends on the image size only
+  sc.camera.R[0] = sc.camera.R[4] = sc.camera.R[8] = 1.f;
+  sc.camera.focal = sc.camera.sensor_width = 1.f;
+  sc.camera.znear = 1.f;
+  sc.camera.zfar = 2.f;
+  sc.camera.width = width;
+  sc.camera.height = height;
+  sc.n = n;
+  return pulsar_batch_workspace_size(&sc, 1, C, params);
+}
+
+int pulsar_fwd_batched(const pulsar_scene_t* scenes, int32_t B, const float* pos,
+                       const float* radius, const float* opacity, const float* payload,
+                       int32_t C, const float* background, const pulsar_params_t* params,
+                       float* image, float* aux, void* ws, size_t ws_bytes, void* stream) {
+  std::vector<SceneDev> sc;
+  int rc = make_scenes(scenes, B, params, &sc);
   if (rc != PULSAR_OK) return rc;
-  if (n < 0 || C < 1) return PULSAR_ERR_INVALID_ARGUMENT;
-  if (n > 0 && (!pos || !radius || !payload)) return PULSAR_ERR_INVALID_ARGUMENT;
-  if (!background || !image || !ws) return PULSAR_ERR_INVALID_ARGUMENT;
+  if (C < 1) return PULSAR_ERR_INVALID_ARGUMENT;
   Plan q;
-  rc = make_plan(n, cam->width, cam->height, C, params, &q);
+  rc = make_plan(sc, C, params, &q);
   if (rc != PULSAR_OK) return rc;
+  if (q.n > 0 && (!pos || !radius || !payload)) return PULSAR_ERR_INVALID_ARGUMENT;
+  if (!background || !image || !ws) return PULSAR_ERR_INVALID_ARGUMENT;
   if (ws_bytes < q.total) return PULSAR_ERR_WORKSPACE;
   FwdArgs a;
   a.pos = pos;
@@ -237,40 +300,42 @@ int pulsar_fwd(const float* pos, const float* radius, const float* opacity,
   a.opacity = opacity;
   a.payload = payload;
   a.bg = background;
-  a.n = n;
+  a.n = int(q.n);
   a.C = C;
   a.K = params->K;
   a.image = image;
   a.aux = aux;
   a.min_radius_px = params->min_radius_px;
-  hipError_t e = launch_forward(q, make_cam(cam), make_blend(cam, params), a,
-                                static_cast<char*>(ws), static_cast<hipStream_t>(stream));
+  hipError_t e = launch_forward(q, sc, a, static_cast<char*>(ws),
+                                static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail_hip(e);
   return PULSAR_OK;
 }
 
-int pulsar_bwd(const float* pos, const float* radius, const float* opacity,
-               const float* payload, int32_t n, int32_t C, const float* background,
-               const pulsar_camera_t* cam, const pulsar_params_t* params, const float* image,
-               const float* aux, const float* grad_image, float* grad_pos, float* grad_radius,
-               float* grad_opacity, float* grad_payload, float* grad_background, void* ws,
-               size_t ws_bytes, void* stream) {
-  int rc = check_camera(cam);
+int pulsar_bwd_batched(const pulsar_scene_t* scenes, int32_t B, const float* pos,
+                       const float* radius, const float* opacity, const float* payload,
+                       int32_t C, const float* background, const pulsar_params_t* params,
+                       const float* image, const float* aux, const float* grad_image,
+                       float* grad_pos, float* grad_radius, float* grad_opacity,
+                       float* grad_payload, float* grad_background, void* ws,
+                       size_t ws_bytes, void* stream) {
+  std::vector<SceneDev> sc;
+  int rc = make_scenes(scenes, B, params, &sc);
   if (rc != PULSAR_OK) return rc;
-  if (n < 0 || C < 1) return PULSAR_ERR_INVALID_ARGUMENT;
-  if (n > 0 && (!pos || !radius || !payload)) return PULSAR_ERR_INVALID_ARGUMENT;
+  if (C < 1) return PULSAR_ERR_INVALID_ARGUMENT;
+  Plan q;
+  rc = make_plan(sc, C, params, &q);
+  if (rc != PULSAR_OK) return rc;
+  if (q.n > 0 && (!pos || !radius || !payload)) return PULSAR_ERR_INVALID_ARGUMENT;
   if (!background || !image || !aux || !grad_image || !ws) return PULSAR_ERR_INVALID_ARGUMENT;
   if (grad_opacity && !opacity) return PULSAR_ERR_INVALID_ARGUMENT;
-  Plan q;
-  rc = make_plan(n, cam->width, cam->height, C, params, &q);
-  if (rc != PULSAR_OK) return rc;
   if (ws_bytes < q.total) return PULSAR_ERR_WORKSPACE;
   BwdArgs a;
   a.pos = pos;
   a.radius = radius;
   a.opacity = opacity;
   a.payload = payload;
-  a.n = n;
+  a.n = int(q.n);
   a.C = C;
   a.K = params->K;
   a.image = image;
@@ -282,10 +347,41 @@ int pulsar_bwd(const float* pos, const float* radius, const float* opacity,
   a.grad_payload = grad_payload;
   a.grad_bg = grad_background;
   a.min_radius_px = params->min_radius_px;
-  hipError_t e = launch_backward(q, make_cam(cam), make_blend(cam, params), a,
-                                 static_cast<char*>(ws), static_cast<hipStream_t>(stream));
+  a.eps2 = sc[0].bc.eps2;
+  hipError_t e = launch_backward(q, a, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail_hip(e);
   return PULSAR_OK;
+}
+
+static pulsar_scene_t single_scene(const pulsar_camera_t* cam, int32_t n) {
+  pulsar_scene_t sc;
+  std::memset(&sc, 0, sizeof(sc));
+  sc.camera = *cam;
+  sc.n = n;
+  return sc;
+}
+
+int pulsar_fwd(const float* pos, const float* radius, const float* opacity,
+               const float* payload, int32_t n, int32_t C, const float* background,
+               const pulsar_camera_t* cam, const pulsar_params_t* params, float* image,
+               float* aux, void* ws, size_t ws_bytes, void* stream) {
+  if (!cam) return PULSAR_ERR_INVALID_ARGUMENT;
+  const pulsar_scene_t sc = single_scene(cam, n);
+  return pulsar_fwd_batched(&sc, 1, pos, radius, opacity, payload, C, background, params,
+                            image, aux, ws, ws_bytes, stream);
+}
+
+int pulsar_bwd(const float* pos, const float* radius, const float* opacity,
+               const float* payload, int32_t n, int32_t C, const float* background,
+               const pulsar_camera_t* cam, const pulsar_params_t* params, const float* image,
+               const float* aux, const float* grad_image, float* grad_pos, float* grad_radius,
+               float* grad_opacity, float* grad_payload, float* grad_background, void* ws,
+               size_t ws_bytes, void* stream) {
+  if (!cam) return PULSAR_ERR_INVALID_ARGUMENT;
+  const pulsar_scene_t sc = single_scene(cam, n);
+  return pulsar_bwd_batched(&sc, 1, pos, radius, opacity, payload, C, background, params,
+                            image, aux, grad_image, grad_pos, grad_radius, grad_opacity,
+                            grad_payload, grad_background, ws, ws_bytes, stream);
 }
 
 int pulsar_query_status(const void* ws, size_t ws_bytes, void* stream, int64_t* pairs) {
@@ -349,6 +445,6 @@ const char* pulsar_stage_name(int stage) {
   return (stage >= 0 && stage < PULSAR_NUM_STAGES) ? names[stage] : "unknown";
 }
 
-int pulsar_version(void) { return 1; }
+int pulsar_version(void) { return 2; }
 
 }  // extern "C"

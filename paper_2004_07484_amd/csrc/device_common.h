@@ -58,6 +58,21 @@ __device__ __forceinline__ uint32_t wave_incl_scan_u32(uint32_t v, int lane) {
   return v;
 }
 
+// Scene of element x: the largest b in [0, B) with start[b] <= x, for an
+// ascending start array with start[0] = 0 (empty scenes are skipped because
+// a later scene with the same start wins).
+__device__ __forceinline__ int find_scene(const uint32_t* __restrict__ start, int B, uint32_t x) {
+  int lo = 0, hi = B - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 __device__ __forceinline__ uint64_t lanemask_lt(int lane) {
   return (uint64_t(1) << lane) - 1u;
 }

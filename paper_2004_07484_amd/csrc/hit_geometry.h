@@ -163,6 +163,22 @@ __device__ __forceinline__ PixelRay load_ray(const TileRays& tr, int pl, int px,
   return r;
 }
 
+// The scene of a (global) tile, its camera and the tile's first pixel.
+struct TileScene {
+  int b;
+  int tx0, ty0;
+};
+
+__device__ __forceinline__ TileScene tile_scene(const SceneTable& tab, uint32_t tile) {
+  TileScene ts;
+  ts.b = find_scene(tab.tile_start, tab.B, tile);
+  const int lt = int(tile - tab.scenes[ts.b].tile_off);
+  const int tiles_x = tab.scenes[ts.b].cam.tiles_x;
+  ts.tx0 = (lt % tiles_x) * kTileW;
+  ts.ty0 = (lt / tiles_x) * kTileH;
+  return ts;
+}
+
 // A sphere record is four float4 (see k_project for the layout).
 __device__ __forceinline__ SphereRec unpack_rec(const float4& a, const float4& b,
                                                 const float4& c, const float4& d) {

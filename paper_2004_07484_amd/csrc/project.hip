@@ -15,20 +15,68 @@
 //           y1 is the last pixel of its rectangle
 // and the per-block sum of counts for the tile-pair scan. High + low FP32
 // parts carry the FP64 values to about 48 bits for the exact hit test.
+#include <cstring>
+
 #include "device_common.h"
 #include "pulsar_internal.h"
 
 namespace pulsar {
 
+// Copies up to kUploadScenes scene descriptors from the launch arguments into
+// the workspace table and its start arrays; the launch covering the last
+// scene also writes the B-th (total) entry of each start array.
+struct SceneUpload {
+  int first, count, B;
+  uint32_t total_spheres, total_tiles, total_blocks;
+  SceneDev s[kUploadScenes];
+};
+
+__global__ __launch_bounds__(64) void k_upload_scenes(SceneUpload u, SceneDev* __restrict__ scenes,
+                                                      uint32_t* __restrict__ starts) {
+  const int k = threadIdx.x;
+  const int B1 = u.B + 1;
+  if (k < u.count) {
+    const int b = u.first + k;
+    scenes[b] = u.s[k];
+    starts[b] = u.s[k].sph_off;
+    starts[B1 + b] = u.s[k].tile_off;
+    starts[2 * B1 + b] = u.s[k].bgblk_off;
+  }
+  if (k == 0 && u.first + u.count == u.B) {
+    starts[u.B] = u.total_spheres;
+    starts[B1 + u.B] = u.total_tiles;
+    starts[2 * B1 + u.B] = u.total_blocks;
+  }
+}
+
+void launch_upload_scenes(const Plan& q, const std::vector<SceneDev>& sc, char* ws,
+                          hipStream_t stream) {
+  SceneDev* scenes = ws_ptr<SceneDev>(ws, q.off_scenes);
+  uint32_t* starts = ws_ptr<uint32_t>(ws, q.off_starts);
+  for (int first = 0; first < q.B; first += kUploadScenes) {
+    SceneUpload u;
+    std::memset(&u, 0, sizeof(u));
+    u.first = first;
+    u.count = q.B - first < kUploadScenes ? q.B - first : kUploadScenes;
+    u.B = q.B;
+    u.total_spheres = uint32_t(q.n);
+    u.total_tiles = uint32_t(q.T);
+    u.total_blocks = uint32_t(q.nbgblk);
+    for (int k = 0; k < u.count; ++k) u.s[k] = sc[size_t(first + k)];
+    hipLaunchKernelGGL(k_upload_scenes, dim3(1), dim3(64), 0, stream, u, scenes, starts);
+  }
+}
+
 __global__ __launch_bounds__(kProjectBlock) void k_project(
     int n, const float* __restrict__ pos, const float* __restrict__ radius,
-    const float* __restrict__ opacity, CamDev cam, float min_radius_px, int depth_bits,
+    const float* __restrict__ opacity, SceneTable tab, float min_radius_px, int depth_bits,
     uint32_t* __restrict__ counts, ushort4* __restrict__ trect, uint32_t* __restrict__ qdepth,
     float4* __restrict__ recA, float4* __restrict__ recB, float4* __restrict__ recC,
     float4* __restrict__ recD, unsigned long long* __restrict__ partials) {
   const int i = blockIdx.x * kProjectBlock + threadIdx.x;
   uint32_t count = 0;
   if (i < n) {
+    const CamDev cam = tab.scenes[find_scene(tab.sph_start, tab.B, uint32_t(i))].cam;
     const float px = pos[3 * i + 0], py = pos[3 * i + 1], pz = pos[3 * i + 2];
     const float r = radius[i];
     const float o = opacity ? opacity[i] : 1.f;
@@ -113,11 +161,11 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
   }
 }
 
-void launch_project(const Plan& q, const CamDev& cam, const FwdArgs& a, char* ws,
-                    hipStream_t stream) {
+void launch_project(const Plan& q, const FwdArgs& a, char* ws, hipStream_t stream) {
   if (q.n == 0) return;
   hipLaunchKernelGGL(k_project, dim3(q.nblk_proj), dim3(kProjectBlock), 0, stream, int(q.n),
-                     a.pos, a.radius, a.opacity, cam, a.min_radius_px, q.depth_bits,
+                     a.pos, a.radius, a.opacity, scene_table(q, ws), a.min_radius_px,
+                     q.depth_bits,
                      ws_ptr<uint32_t>(ws, q.off_counts), ws_ptr<ushort4>(ws, q.off_trect),
                      ws_ptr<uint32_t>(ws, q.off_qdepth), ws_ptr<float4>(ws, q.off_recA),
                      ws_ptr<float4>(ws, q.off_recB), ws_ptr<float4>(ws, q.off_recC),

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "pulsar.h"
 
@@ -23,8 +24,10 @@ constexpr int kSortRadix = 256;              // 8-bit digits
 constexpr int kMaxK = 32;
 constexpr int kFwdChannels = 32;             // channels per forward pass (more: several passes)
 constexpr int kBwdChannels = 32;             // channels kept in registers by the backward
-constexpr int kChunk = 128;                  // sphere records per raster work item
-constexpr int kRasterGrid = 4096;            // persistent raster grid (one wave per block)
+constexpr int kChunkDefault = 128;           // sphere records per raster work item
+constexpr int kRasterGridDefault = 4096;     // persistent raster grid (one wave per block)
+constexpr int kUploadScenes = 12;            // scene descriptors per upload launch
+constexpr int kBgBlockPixels = 1024;         // pixels per background-gradient block
 constexpr uint32_t kFirstChunk = 0x80000000u;  // work item flag: first chunk of its tile
 constexpr uint32_t kNoSlot = 0xffffffffu;      // work item writes final pixels, no partial state
 
@@ -33,9 +36,9 @@ struct Status {
   uint32_t code;                // PULSAR_OK or PULSAR_ERR_CAPACITY
   uint32_t used;                // pairs actually stored: min(pairs, capacity)
   unsigned long long pairs;     // pairs the scene produced
-  uint32_t nchunks;             // raster work items (chunks of <= kChunk records of one tile)
+  uint32_t nchunks;             // raster work items (chunks of <= chunk records of one tile)
   uint32_t npartials;           // partial blend states needed by tiles with several chunks
-  uint32_t nfull;               // work items with exactly kChunk records (listed first)
+  uint32_t nfull;               // work items with exactly chunk records (listed first)
   uint32_t nmerge;              // tiles with several work items
   uint32_t pad[56];
 };
@@ -59,14 +62,38 @@ struct BlendConst {
   float inv_span;   // 1 / (zfar - znear)
 };
 
+// One scene of a call: its camera and blend constants and where its spheres,
+// tiles, pixels and background-gradient blocks start in the packed arrays.
+// A single-scene call is a batch of one.
+struct SceneDev {
+  CamDev cam;
+  BlendConst bc;
+  uint32_t sph_off;    // first sphere
+  uint32_t n;          // spheres
+  uint32_t tile_off;   // first tile in the global tile numbering
+  uint32_t bgblk_off;  // first background-gradient block
+  unsigned long long pix_off;  // first pixel (index into the packed [P] planes)
+};
+
+// Device copy of the scene table plus three ascending start arrays of B + 1
+// entries each (spheres, tiles, background blocks) for scene lookup.
+struct SceneTable {
+  const SceneDev* scenes;
+  const uint32_t* sph_start;
+  const uint32_t* tile_start;
+  const uint32_t* blk_start;
+  int B;
+};
+
 // Workspace layout: byte offsets of every buffer, all 256-byte aligned.
 struct Plan {
-  int64_t n, C, W, H, T, tiles_x, tiles_y, cap;
+  int64_t n, C, T, npix, cap, nbgblk;
+  int B, chunk, raster_grid;
   int tile_bits, depth_bits, passes, nblk_proj, nblk_sort;
   size_t off_status, off_counts, off_trect, off_qdepth, off_recA, off_recB, off_recC, off_recD;
   size_t off_gacc;
   size_t off_partials, off_keysA, off_valsA, off_keysB, off_valsB, off_hist, off_dtot;
-  size_t off_ranges, off_bgpart;
+  size_t off_ranges;
   // raster work items: per tile uint4 (first partial-state slot, chunks, 0, 0);
   // the work list uint4 (tile | kFirstChunk, begin, end, slot or kNoSlot);
   // block sums of the chunk scan; the partial blend states; the per-pixel
@@ -75,13 +102,19 @@ struct Plan {
   // sphere records and payload rows copied into sorted pair order
   size_t off_srec, off_spay;
   size_t off_mlist;  // tiles with several work items, for the merge kernel
+  size_t off_scenes, off_starts;  // scene table and its start arrays
   int64_t max_chunks, pcap;
   int nblk_tiles, fwd_cm, klist_slots, pstride;
   size_t total;
 };
 
-// Fills `out` and returns PULSAR_OK, or returns an error code.
-int make_plan(int64_t n, int W, int H, int C, const pulsar_params_t* p, Plan* out);
+// Validates the scenes and fills the host copy of the scene table (offsets in
+// scene order). Returns PULSAR_OK or an error code.
+int make_scenes(const pulsar_scene_t* scenes, int B, const pulsar_params_t* p,
+                std::vector<SceneDev>* out);
+// Fills `out` from a validated scene table and returns PULSAR_OK, or returns
+// an error code.
+int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, Plan* out);
 CamDev make_cam(const pulsar_camera_t* c);
 BlendConst make_blend(const pulsar_camera_t* c, const pulsar_params_t* p);
 
@@ -112,13 +145,15 @@ struct BwdArgs {
   float* grad_payload;
   float* grad_bg;
   float min_radius_px;
+  float eps2;  // eps / gamma * log2(e), the background exponent (camera independent)
 };
 
-// Enqueue the forward / backward pipelines. They return the first launch error.
-hipError_t launch_forward(const Plan& plan, const CamDev& cam, const BlendConst& bc,
+// Enqueue the forward / backward pipelines. The forward first copies the
+// host scene table into the workspace; the backward uses that copy. They
+// return the first launch error.
+hipError_t launch_forward(const Plan& plan, const std::vector<SceneDev>& scenes,
                           const FwdArgs& a, char* ws, hipStream_t stream);
-hipError_t launch_backward(const Plan& plan, const CamDev& cam, const BlendConst& bc,
-                           const BwdArgs& a, char* ws, hipStream_t stream);
+hipError_t launch_backward(const Plan& plan, const BwdArgs& a, char* ws, hipStream_t stream);
 
 // Stage timing hooks (no-ops unless pulsar_timing_enable(1) was called).
 void stage_begin(int stage, hipStream_t stream);
@@ -132,5 +167,16 @@ inline T* ws_ptr(char* ws, size_t off) {
 
 // Result of the LSD sort lands in the A buffers after an even number of passes.
 inline bool sorted_in_a(const Plan& p) { return (p.passes % 2) == 0; }
+
+inline SceneTable scene_table(const Plan& q, char* ws) {
+  SceneTable t;
+  t.scenes = ws_ptr<SceneDev>(ws, q.off_scenes);
+  const uint32_t* st = ws_ptr<uint32_t>(ws, q.off_starts);
+  t.sph_start = st;
+  t.tile_start = st + (q.B + 1);
+  t.blk_start = st + 2 * (q.B + 1);
+  t.B = q.B;
+  return t;
+}
 
 }  // namespace pulsar

@@ -22,6 +22,7 @@
 namespace pulsar {
 
 struct BwdKernelArgs {
+  SceneTable tab;
   Status* status;
   const uint4* desc;
   const float4* srec;   // sphere records in sorted pair order (index | single-tile flag in .w)
@@ -73,8 +74,7 @@ __device__ __forceinline__ HitGrad hit_grad(const PixelRay& ray, const SphereRec
 // rectangle sizes, so all 64 lanes stay busy whatever the sphere sizes; lane
 // j handles pair j + 64 i and adds its terms to its sphere's LDS accumulator.
 template <int CM>
-__global__ __launch_bounds__(kWave) void k_bwd_chunks(BwdKernelArgs A, CamDev cam,
-                                                      BlendConst bc) {
+__global__ __launch_bounds__(kWave) void k_bwd_chunks(BwdKernelArgs A) {
   constexpr int CQ = (CM + 3) / 4;
   constexpr int NA = 6 + CM;  // dL/dc (3), dL/dR, dL/do, hit count, dL/df (CM)
   __shared__ TileRays s_ray;
@@ -90,14 +90,19 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks(BwdKernelArgs A, CamDev ca
   const uint32_t nchunks = A.status->nchunks;
   for (uint32_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
     const uint4 dsc = A.desc[chunk];
-    const int tile = int(dsc.x & ~kFirstChunk);
+    const uint32_t tile = dsc.x & ~kFirstChunk;
     const uint32_t beg = dsc.y, end = dsc.z;
-    const int tx0 = (tile % cam.tiles_x) * kTileW, ty0 = (tile / cam.tiles_x) * kTileH;
+    const TileScene ts = tile_scene(A.tab, tile);
+    const SceneDev& sc = A.tab.scenes[ts.b];
+    const CamDev cam = sc.cam;
+    const BlendConst bc = sc.bc;
+    const int tx0 = ts.tx0, ty0 = ts.ty0;
     // stage the tile's pixels (lane = pixel): ray, L, threshold, G and G . F
     {
       const int px = tx0 + (lane % kTileW), py = ty0 + (lane / kTileW);
       const bool inside = px < cam.W && py < cam.H;
-      const size_t p = inside ? size_t(py) * size_t(cam.W) + size_t(px) : 0;
+      const size_t p =
+          inside ? size_t(sc.pix_off) + size_t(py) * size_t(cam.W) + size_t(px) : 0;
       __syncthreads();  // the previous chunk's LDS reads are done
       store_ray(s_ray, lane, make_ray(cam, px, py));
       s_L2[lane] = inside ? A.aux[p] * 1.4426950408889634f : 0.f;
@@ -241,8 +246,7 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks(BwdKernelArgs A, CamDev ca
 
 // Channels beyond the register budget: same walk, the pixel terms read from
 // global memory and payload gradients go out per hit.
-__global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A, CamDev cam,
-                                                           BlendConst bc) {
+__global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A) {
   __shared__ TileRays s_ray;
   __shared__ float s_L2[kWave], s_tk[kWave];
   __shared__ uint32_t s_ik[kWave];
@@ -251,12 +255,16 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A, CamD
   const uint32_t nchunks = A.status->nchunks;
   for (uint32_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
     const uint4 dsc = A.desc[chunk];
-    const int tile = int(dsc.x & ~kFirstChunk);
+    const uint32_t tile = dsc.x & ~kFirstChunk;
     const uint32_t beg = dsc.y, end = dsc.z;
-    const int tx0 = (tile % cam.tiles_x) * kTileW, ty0 = (tile / cam.tiles_x) * kTileH;
+    const TileScene ts = tile_scene(A.tab, tile);
+    const SceneDev& sc = A.tab.scenes[ts.b];
+    const CamDev cam = sc.cam;
+    const BlendConst bc = sc.bc;
+    const int tx0 = ts.tx0, ty0 = ts.ty0;
     const int px = tx0 + (lane % kTileW), py = ty0 + (lane / kTileW);
     const bool inside = px < cam.W && py < cam.H;
-    const size_t p = inside ? size_t(py) * size_t(cam.W) + size_t(px) : 0;
+    const size_t p = inside ? size_t(sc.pix_off) + size_t(py) * size_t(cam.W) + size_t(px) : 0;
     const float L2 = inside ? A.aux[p] * 1.4426950408889634f : 0.f;
     __syncthreads();
     store_ray(s_ray, lane, make_ray(cam, px, py));
@@ -288,7 +296,7 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A, CamD
           const uint32_t ik = s_ik[pl];
           if (!(id == ik || h.t < tk || (h.t == tk && id < ik))) continue;
           any = true;
-          const size_t pp = size_t(iy) * size_t(cam.W) + size_t(ix);
+          const size_t pp = size_t(sc.pix_off) + size_t(iy) * size_t(cam.W) + size_t(ix);
           const float* Gp = A.grad_image + pp * size_t(C);
           const float* Fp = A.image + pp * size_t(C);
           const float o = s.o;
@@ -347,7 +355,8 @@ __global__ void k_bwd_prep(int n, const uint32_t* __restrict__ counts, uint32_t 
 // gradients; spheres that touch no tile get zeros everywhere.
 __global__ void k_finalize(int n, const uint32_t* __restrict__ counts,
                            const float* __restrict__ pos, const float* __restrict__ radius,
-                           CamDev cam, float min_radius_px, int C, const float4* __restrict__ gacc,
+                           SceneTable tab, float min_radius_px, int C,
+                           const float4* __restrict__ gacc,
                            float* __restrict__ grad_pos, float* __restrict__ grad_radius,
                            float* __restrict__ grad_opacity, float* __restrict__ grad_payload) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -372,6 +381,7 @@ __global__ void k_finalize(int n, const uint32_t* __restrict__ counts,
     return;
   }
   if (!gacc) return;
+  const CamDev cam = tab.scenes[find_scene(tab.sph_start, tab.B, uint32_t(i))].cam;
   const float4 g = gacc[i];
   float gx = g.x, gy = g.y, gz = g.z, gR = g.w;
   bool clamped = false;
@@ -393,20 +403,26 @@ __global__ void k_finalize(int n, const uint32_t* __restrict__ counts,
   }
 }
 
-// Background gradient, dL/dbg = sum_p exp(eps/gamma - L_p) G_p: per-block
-// partial sums, [blocks][C]; each block covers 256 x kBgPixels pixels.
-constexpr int kBgPixels = 4;
-__global__ __launch_bounds__(256) void k_bg_partial(const float* __restrict__ aux,
-                                                    const float* __restrict__ grad_image,
-                                                    long long npix, int C, float eps2,
-                                                    float* __restrict__ bgsum) {
+// Background gradient, dL/dbg = sum_p exp(eps/gamma - L_p) G_p per scene:
+// per-block partial sums [blocks][C]; every block covers kBgBlockPixels
+// pixels of one scene (256 threads x kBgPixels).
+constexpr int kBgPixels = kBgBlockPixels / 256;
+__global__ __launch_bounds__(256) void k_bg_partial(SceneTable tab, const float* __restrict__ aux,
+                                                    const float* __restrict__ grad_image, int C,
+                                                    float eps2, float* __restrict__ bgsum) {
   __shared__ float s[256 / kWave][8];
-  const long long p0 = (long long)blockIdx.x * 256 * kBgPixels + threadIdx.x;
+  const int b = find_scene(tab.blk_start, tab.B, blockIdx.x);
+  const SceneDev& sc = tab.scenes[b];
+  const long long npix = (long long)sc.cam.W * sc.cam.H;
+  const long long p0 =
+      (long long)(blockIdx.x - sc.bgblk_off) * kBgBlockPixels + (long long)threadIdx.x;
+  const float* auxs = aux + sc.pix_off;
+  const float* gs = grad_image + size_t(sc.pix_off) * size_t(C);
   float w[kBgPixels];
 #pragma unroll
   for (int k = 0; k < kBgPixels; ++k) {
     const long long p = p0 + k * 256;
-    w[k] = p < npix ? fast_exp2(eps2 - aux[p] * 1.4426950408889634f) : 0.f;
+    w[k] = p < npix ? fast_exp2(eps2 - auxs[p] * 1.4426950408889634f) : 0.f;
   }
   for (int c0 = 0; c0 < C; c0 += 8) {
     float acc[8];
@@ -416,7 +432,7 @@ __global__ __launch_bounds__(256) void k_bg_partial(const float* __restrict__ au
     for (int k = 0; k < kBgPixels; ++k) {
       const long long p = p0 + k * 256;
       if (p < npix) {
-        const float* g = grad_image + size_t(p) * size_t(C) + c0;
+        const float* g = gs + size_t(p) * size_t(C) + c0;
 #pragma unroll
         for (int c = 0; c < 8; ++c)
           if (c0 + c < C) acc[c] += w[k] * g[c];
@@ -437,27 +453,29 @@ __global__ __launch_bounds__(256) void k_bg_partial(const float* __restrict__ au
   }
 }
 
-// K8b: grad_bg[c] = sum of the per-block partials (one block per channel).
-__global__ __launch_bounds__(256) void k_reduce_bg(const float* __restrict__ bgpart, int T, int C,
-                                                   float* __restrict__ grad_bg) {
+// K8b: grad_bg[b][c] = sum of scene b's block partials (one block per (c, b)).
+__global__ __launch_bounds__(256) void k_reduce_bg(SceneTable tab, const float* __restrict__ bgpart,
+                                                   int C, float* __restrict__ grad_bg) {
   __shared__ float s[256 / kWave];
-  const int c = blockIdx.x;
+  const int c = blockIdx.x, b = blockIdx.y;
+  const uint32_t k0 = tab.blk_start[b], k1 = tab.blk_start[b + 1];
   float acc = 0.f;
-  for (int t = threadIdx.x; t < T; t += 256) acc += bgpart[size_t(t) * size_t(C) + c];
+  for (uint32_t k = k0 + threadIdx.x; k < k1; k += 256) acc += bgpart[size_t(k) * size_t(C) + c];
   acc = wave_sum(acc);
   if ((threadIdx.x & (kWave - 1)) == 0) s[threadIdx.x / kWave] = acc;
   __syncthreads();
   if (threadIdx.x == 0) {
     float tsum = 0.f;
     for (int w = 0; w < 256 / kWave; ++w) tsum += s[w];
-    grad_bg[c] = tsum;
+    grad_bg[size_t(b) * size_t(C) + c] = tsum;
   }
 }
 
-hipError_t launch_backward(const Plan& q, const CamDev& cam, const BlendConst& bc,
-                           const BwdArgs& a, char* ws, hipStream_t stream) {
+hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_t stream) {
   const bool need_geo = a.grad_pos || a.grad_radius;
+  const SceneTable tab = scene_table(q, ws);
   BwdKernelArgs A;
+  A.tab = tab;
   A.status = ws_ptr<Status>(ws, q.off_status);
   A.desc = ws_ptr<uint4>(ws, q.off_desc);
   A.srec = ws_ptr<float4>(ws, q.off_srec);
@@ -481,35 +499,33 @@ hipError_t launch_backward(const Plan& q, const CamDev& cam, const BlendConst& b
                        a.grad_opacity, a.grad_payload);
   stage_end(PULSAR_STAGE_ZERO, stream);
   stage_begin(PULSAR_STAGE_RASTER_BWD, stream);
-  const dim3 grid(kRasterGrid), block(kWave);
+  const dim3 grid(unsigned(q.raster_grid)), block(kWave);
   if (a.C <= 1)
-    hipLaunchKernelGGL(k_bwd_chunks<1>, grid, block, 0, stream, A, cam, bc);
+    hipLaunchKernelGGL(k_bwd_chunks<1>, grid, block, 0, stream, A);
   else if (a.C <= 2)
-    hipLaunchKernelGGL(k_bwd_chunks<2>, grid, block, 0, stream, A, cam, bc);
+    hipLaunchKernelGGL(k_bwd_chunks<2>, grid, block, 0, stream, A);
   else if (a.C <= 4)
-    hipLaunchKernelGGL(k_bwd_chunks<4>, grid, block, 0, stream, A, cam, bc);
+    hipLaunchKernelGGL(k_bwd_chunks<4>, grid, block, 0, stream, A);
   else if (a.C <= 8)
-    hipLaunchKernelGGL(k_bwd_chunks<8>, grid, block, 0, stream, A, cam, bc);
+    hipLaunchKernelGGL(k_bwd_chunks<8>, grid, block, 0, stream, A);
   else if (a.C <= 16)
-    hipLaunchKernelGGL(k_bwd_chunks<16>, grid, block, 0, stream, A, cam, bc);
+    hipLaunchKernelGGL(k_bwd_chunks<16>, grid, block, 0, stream, A);
   else if (a.C <= kBwdChannels)
-    hipLaunchKernelGGL(k_bwd_chunks<32>, grid, block, 0, stream, A, cam, bc);
+    hipLaunchKernelGGL(k_bwd_chunks<32>, grid, block, 0, stream, A);
   else
-    hipLaunchKernelGGL(k_bwd_chunks_wide, grid, block, 0, stream, A, cam, bc);
+    hipLaunchKernelGGL(k_bwd_chunks_wide, grid, block, 0, stream, A);
   stage_end(PULSAR_STAGE_RASTER_BWD, stream);
   stage_begin(PULSAR_STAGE_FINALIZE, stream);
   if (q.n > 0)
     hipLaunchKernelGGL(k_finalize, dim3(unsigned((q.n + 255) / 256)), dim3(256), 0, stream,
-                       int(q.n), counts, a.pos, a.radius, cam, a.min_radius_px, a.C,
+                       int(q.n), counts, a.pos, a.radius, tab, a.min_radius_px, a.C,
                        reinterpret_cast<const float4*>(A.gacc), a.grad_pos, a.grad_radius,
                        a.grad_opacity, a.grad_payload);
   if (a.grad_bg) {
-    const long long npix = q.W * q.H;
-    const int nb = int((npix + 256 * kBgPixels - 1) / (256 * kBgPixels));
-    hipLaunchKernelGGL(k_bg_partial, dim3(unsigned(nb)), dim3(256), 0, stream, a.aux,
-                       a.grad_image, npix, int(q.C), bc.eps2, bgsum);
-    hipLaunchKernelGGL(k_reduce_bg, dim3(unsigned(q.C)), dim3(256), 0, stream, bgsum, nb,
-                       int(q.C), a.grad_bg);
+    hipLaunchKernelGGL(k_bg_partial, dim3(unsigned(q.nbgblk)), dim3(256), 0, stream, tab, a.aux,
+                       a.grad_image, int(q.C), a.eps2, bgsum);
+    hipLaunchKernelGGL(k_reduce_bg, dim3(unsigned(q.C), unsigned(q.B)), dim3(256), 0, stream, tab,
+                       bgsum, int(q.C), a.grad_bg);
   }
   stage_end(PULSAR_STAGE_FINALIZE, stream);
   return hipGetLastError();

@@ -1,6 +1,6 @@
 // K6: forward raster (paper App. B, Steps 1-2; Eq. 1).
 //
-// Work item = a chunk of at most kChunk depth-sorted records of one non-empty
+// Work item = a chunk of at most `chunk` depth-sorted records of one non-empty
 // 8x8 tile (long tile lists are split, so no wave walks thousands of spheres
 // alone); a persistent grid of one-wave blocks takes work items round-robin,
 // full chunks first. Records and payloads were copied into sorted pair order
@@ -53,13 +53,14 @@ __device__ __forceinline__ void klist_init(float (&kt)[KM], uint32_t (&kid)[KM],
 }
 
 struct FwdKernelArgs {
+  SceneTable tab;
   Status* status;
   const uint4* desc;
   const uint4* tinfo;
   const uint32_t* mlist;
   const float4* srec;   // sphere records in sorted pair order, 4 float4 each
   const float* spay;    // payload rows in sorted pair order
-  const float* bg;
+  const float* bg;      // [B, C]
   float* image;
   float* aux;
   float2* thr;
@@ -72,11 +73,11 @@ struct FwdKernelArgs {
 
 template <int CM, int KM>
 __device__ __forceinline__ void write_pixel(const FwdKernelArgs& A, const CamDev& cam,
-                                            int px, int py, float m2, float D,
-                                            const float (&N)[CM], const float (&kt)[KM],
-                                            const uint32_t (&kid)[KM]) {
+                                            unsigned long long pix_off, int px, int py,
+                                            float m2, float D, const float (&N)[CM],
+                                            const float (&kt)[KM], const uint32_t (&kid)[KM]) {
   if (px >= cam.W || py >= cam.H) return;
-  const size_t p = size_t(py) * size_t(cam.W) + size_t(px);
+  const size_t p = size_t(pix_off) + size_t(py) * size_t(cam.W) + size_t(px);
   const float invD = 1.f / D;
 #pragma unroll
   for (int c = 0; c < CM; ++c)
@@ -86,8 +87,7 @@ __device__ __forceinline__ void write_pixel(const FwdKernelArgs& A, const CamDev
 }
 
 template <int CM, int KM>
-__global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A, CamDev cam,
-                                                      BlendConst bc) {
+__global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A) {
   // the batch's records and payloads, padded rows so that lanes reading
   // different records mostly hit different banks
   constexpr int CQ = (CM + 3) / 4;
@@ -101,10 +101,15 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A, CamDev ca
   const uint32_t nchunks = A.status->nchunks;
   for (uint32_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
     const uint4 dsc = A.desc[chunk];
-    const int tile = int(dsc.x & ~kFirstChunk);
+    const uint32_t tile = dsc.x & ~kFirstChunk;
     const bool first = (dsc.x & kFirstChunk) != 0u;
     const uint32_t beg = dsc.y, end = dsc.z, slot = dsc.w;
-    const int tx0 = (tile % cam.tiles_x) * kTileW, ty0 = (tile / cam.tiles_x) * kTileH;
+    const TileScene ts = tile_scene(A.tab, tile);
+    const SceneDev& sc = A.tab.scenes[ts.b];
+    const CamDev cam = sc.cam;
+    const BlendConst bc = sc.bc;
+    const int tx0 = ts.tx0, ty0 = ts.ty0;
+    const float* bg = A.bg + size_t(ts.b) * size_t(A.C);
     const PixelRay ray = make_ray(cam, tx0 + (lane % kTileW), ty0 + (lane / kTileW));
     __syncthreads();  // the previous chunk's LDS reads are done
     s_iv2[lane] = ray.inv_v2;
@@ -113,7 +118,7 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A, CamDev ca
     float D = first ? 1.f : 0.f;
     float N[CM];
 #pragma unroll
-    for (int c = 0; c < CM; ++c) N[c] = (first && c < A.cn) ? A.bg[A.c0 + c] : 0.f;
+    for (int c = 0; c < CM; ++c) N[c] = (first && c < A.cn) ? bg[A.c0 + c] : 0.f;
     float kt[KM];
     uint32_t kid[KM];
     klist_init(kt, kid, A.K);
@@ -225,7 +230,7 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A, CamDev ca
     }
 
     if (slot == kNoSlot) {
-      write_pixel(A, cam, ray.px, ray.py, m2, D, N, kt, kid);
+      write_pixel(A, cam, sc.pix_off, ray.px, ray.py, m2, D, N, kt, kid);
     } else {
       if ((long long)slot < A.pcap) {
         float* ps = A.pstate + size_t(slot) * size_t(kWave) * size_t(A.pstride);
@@ -254,7 +259,7 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A, CamDev ca
 constexpr int kMergeWaves = 4;
 
 template <int CM, int KM>
-__global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(FwdKernelArgs A, CamDev cam) {
+__global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(FwdKernelArgs A) {
   constexpr int NF = 2 + CM + 2 * KM;  // m, D, numerator[CM], K-list t[KM], id[KM]
   __shared__ float s_state[kMergeWaves - 1][NF][kWave];
   const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
@@ -324,72 +329,74 @@ __global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(FwdKernelArgs
         for (int f = 0; f < NF; ++f) st[f] = s_state[w][f][lane];
         fold(st);
       }
-      const int px = (tile % cam.tiles_x) * kTileW + lane % kTileW;
-      const int py = (tile / cam.tiles_x) * kTileH + lane / kTileW;
-      write_pixel(A, cam, px, py, m2, D, N, kt, kid);
+      const TileScene ts = tile_scene(A.tab, uint32_t(tile));
+      const SceneDev& sc = A.tab.scenes[ts.b];
+      write_pixel(A, sc.cam, sc.pix_off, ts.tx0 + lane % kTileW, ts.ty0 + lane / kTileW, m2, D,
+                  N, kt, kid);
     }
   }
 }
 
 // Pixels of tiles without any sphere: F = background, L = eps / gamma, and
-// no hit for the gradient threshold. One thread per pixel.
+// no hit for the gradient threshold. One wave per tile, lane = pixel.
 template <int CM>
-__global__ __launch_bounds__(256) void k_fwd_background(FwdKernelArgs A, CamDev cam) {
-  const long long p = (long long)blockIdx.x * 256 + threadIdx.x;
-  float bgv[CM];
-#pragma unroll
-  for (int c = 0; c < CM; ++c) bgv[c] = c < A.cn ? A.bg[A.c0 + c] : 0.f;
-  if (p >= (long long)cam.W * cam.H) return;
-  const int py = int(p / cam.W), px = int(p % cam.W);
-  const int tile = (py / kTileH) * cam.tiles_x + px / kTileW;
-  if (A.tinfo[tile].y != 0u) return;
-  float* out = A.image + size_t(p) * size_t(A.C) + A.c0;
+__global__ __launch_bounds__(256) void k_fwd_background(FwdKernelArgs A, uint32_t T) {
+  const uint32_t tile = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  if (tile >= T || A.tinfo[tile].y != 0u) return;
+  const TileScene ts = tile_scene(A.tab, tile);
+  const SceneDev& sc = A.tab.scenes[ts.b];
+  const int px = ts.tx0 + lane % kTileW, py = ts.ty0 + lane / kTileW;
+  if (px >= sc.cam.W || py >= sc.cam.H) return;
+  const size_t p = size_t(sc.pix_off) + size_t(py) * size_t(sc.cam.W) + size_t(px);
+  const float* bg = A.bg + size_t(ts.b) * size_t(A.C) + A.c0;
+  float* out = A.image + p * size_t(A.C) + A.c0;
 #pragma unroll
   for (int c = 0; c < CM; ++c)
-    if (c < A.cn) out[c] = bgv[c];
+    if (c < A.cn) out[c] = bg[c];
   if (A.c0 == 0 && A.aux) A.aux[p] = A.eps2 * 0.69314718055994531f;
   if (A.track) A.thr[p] = make_float2(INFINITY, __uint_as_float(0xffffffffu));
 }
 
-void launch_project(const Plan& q, const CamDev& cam, const FwdArgs& a, char* ws,
-                    hipStream_t stream);
+void launch_upload_scenes(const Plan& q, const std::vector<SceneDev>& sc, char* ws,
+                          hipStream_t stream);
+void launch_project(const Plan& q, const FwdArgs& a, char* ws, hipStream_t stream);
 void launch_binning(const Plan& q, char* ws, hipStream_t stream);
 void launch_gather_records(const Plan& q, const float* payload, char* ws, hipStream_t stream);
 
 template <int CM, int KM>
-static void launch_raster_fwd_cm(const Plan& q, const CamDev& cam, const BlendConst& bc,
-                                 const FwdKernelArgs& A, hipStream_t stream) {
-  hipLaunchKernelGGL((k_fwd_chunks<CM, KM>), dim3(kRasterGrid), dim3(kWave), 0, stream, A, cam,
-                     bc);
-  const unsigned mgrid = unsigned(q.T < kRasterGrid ? q.T : kRasterGrid);
-  hipLaunchKernelGGL((k_fwd_merge<CM, KM>), dim3(mgrid), dim3(kWave * kMergeWaves), 0, stream,
-                     A, cam);
-  const long long npix = q.W * q.H;
-  hipLaunchKernelGGL((k_fwd_background<CM>), dim3(unsigned((npix + 255) / 256)), dim3(256), 0,
-                     stream, A, cam);
+static void launch_raster_fwd_cm(const Plan& q, const FwdKernelArgs& A, hipStream_t stream) {
+  hipLaunchKernelGGL((k_fwd_chunks<CM, KM>), dim3(unsigned(q.raster_grid)), dim3(kWave), 0,
+                     stream, A);
+  const long long mg = q.T < q.raster_grid ? q.T : q.raster_grid;
+  hipLaunchKernelGGL((k_fwd_merge<CM, KM>), dim3(unsigned(mg)), dim3(kWave * kMergeWaves), 0,
+                     stream, A);
+  const long long nb = (q.T + 256 / kWave - 1) / (256 / kWave);
+  hipLaunchKernelGGL((k_fwd_background<CM>), dim3(unsigned(nb)), dim3(256), 0, stream, A,
+                     uint32_t(q.T));
 }
 
 template <int KM>
-static void dispatch_cm(const Plan& q, const CamDev& cam, const BlendConst& bc,
-                        const FwdKernelArgs& A, hipStream_t stream) {
+static void dispatch_cm(const Plan& q, const FwdKernelArgs& A, hipStream_t stream) {
   if (A.cn <= 1)
-    launch_raster_fwd_cm<1, KM>(q, cam, bc, A, stream);
+    launch_raster_fwd_cm<1, KM>(q, A, stream);
   else if (A.cn <= 2)
-    launch_raster_fwd_cm<2, KM>(q, cam, bc, A, stream);
+    launch_raster_fwd_cm<2, KM>(q, A, stream);
   else if (A.cn <= 4)
-    launch_raster_fwd_cm<4, KM>(q, cam, bc, A, stream);
+    launch_raster_fwd_cm<4, KM>(q, A, stream);
   else if (A.cn <= 8)
-    launch_raster_fwd_cm<8, KM>(q, cam, bc, A, stream);
+    launch_raster_fwd_cm<8, KM>(q, A, stream);
   else if (A.cn <= 16)
-    launch_raster_fwd_cm<16, KM>(q, cam, bc, A, stream);
+    launch_raster_fwd_cm<16, KM>(q, A, stream);
   else
-    launch_raster_fwd_cm<32, KM>(q, cam, bc, A, stream);
+    launch_raster_fwd_cm<32, KM>(q, A, stream);
 }
 
-hipError_t launch_forward(const Plan& q, const CamDev& cam, const BlendConst& bc,
-                          const FwdArgs& a, char* ws, hipStream_t stream) {
+hipError_t launch_forward(const Plan& q, const std::vector<SceneDev>& scenes, const FwdArgs& a,
+                          char* ws, hipStream_t stream) {
   stage_begin(PULSAR_STAGE_PROJECT, stream);
-  launch_project(q, cam, a, ws, stream);
+  launch_upload_scenes(q, scenes, ws, stream);
+  launch_project(q, a, ws, stream);
   stage_end(PULSAR_STAGE_PROJECT, stream);
   stage_begin(PULSAR_STAGE_BINNING, stream);
   launch_binning(q, ws, stream);
@@ -397,6 +404,7 @@ hipError_t launch_forward(const Plan& q, const CamDev& cam, const BlendConst& bc
   stage_end(PULSAR_STAGE_BINNING, stream);
   stage_begin(PULSAR_STAGE_RASTER_FWD, stream);
   FwdKernelArgs A;
+  A.tab = scene_table(q, ws);
   A.status = ws_ptr<Status>(ws, q.off_status);
   A.desc = ws_ptr<uint4>(ws, q.off_desc);
   A.tinfo = ws_ptr<uint4>(ws, q.off_tinfo);
@@ -413,19 +421,19 @@ hipError_t launch_forward(const Plan& q, const CamDev& cam, const BlendConst& bc
   A.K = a.K;
   A.pstride = q.pstride;
   A.kfield = 2 + q.fwd_cm;
-  A.eps2 = bc.eps2;
+  A.eps2 = scenes[0].bc.eps2;  // eps / gamma does not depend on the camera
   for (int c0 = 0; c0 < a.C; c0 += kFwdChannels) {
     A.c0 = c0;
     A.cn = a.C - c0 < kFwdChannels ? a.C - c0 : kFwdChannels;
     A.track = (c0 == 0 && a.aux != nullptr) ? 1 : 0;
     if (q.klist_slots <= 4)
-      dispatch_cm<4>(q, cam, bc, A, stream);
+      dispatch_cm<4>(q, A, stream);
     else if (q.klist_slots <= 8)
-      dispatch_cm<8>(q, cam, bc, A, stream);
+      dispatch_cm<8>(q, A, stream);
     else if (q.klist_slots <= 16)
-      dispatch_cm<16>(q, cam, bc, A, stream);
+      dispatch_cm<16>(q, A, stream);
     else
-      dispatch_cm<32>(q, cam, bc, A, stream);
+      dispatch_cm<32>(q, A, stream);
   }
   stage_end(PULSAR_STAGE_RASTER_FWD, stream);
   return hipGetLastError();

@@ -62,7 +62,8 @@ def _forward_into(pos, radius, opacity, payload, bg, cam, params, check: bool):
         if code == _capi.PULSAR_OK:
             return image, aux, ws, params
         grown = _capi.make_params(params.gamma, params.eps, params.min_radius_px, params.K,
-                                  int(min(2**31 - 1, pairs * 5 // 4 + 1024)), params.depth_bits)
+                                  int(min(2**31 - 1, pairs * 5 // 4 + 1024)), params.depth_bits,
+                                  params.chunk, params.raster_blocks)
         if grown.max_pairs <= params.max_pairs:
             raise _capi.PulsarError(code, "pulsar_fwd")
         params = grown
@@ -102,6 +103,83 @@ class PulsarFunction(torch.autograd.Function):
         return gp, gr, go, gf, gb, None, None, None
 
 
+class PulsarBatchFunction(torch.autograd.Function):
+    """Batched F = R(S_b, camera_b) for b = 1..B in one call (packed layout of
+    pulsar_fwd_batched), with the batched hand-written backward."""
+
+    @staticmethod
+    def forward(ctx, pos, radius, opacity, payload, bg, scenes, params):
+        pos, radius, payload, bg = (t.contiguous() for t in (pos, radius, payload, bg))
+        opacity = opacity.contiguous() if opacity is not None else None
+        N, P = _capi.batch_sizes(scenes)
+        C = payload.shape[1]
+        dev = payload.device
+        image = torch.empty((P, C), device=dev, dtype=torch.float32)
+        aux = torch.empty((P,), device=dev, dtype=torch.float32)
+        ws = torch.empty(_capi.pulsar_batch_workspace_size(scenes, C, params), device=dev,
+                         dtype=torch.uint8)
+        _capi.pulsar_fwd_batched(scenes, pos, radius, opacity, payload, bg, params, image, aux,
+                                 ws)
+        code, _ = _capi.pulsar_query_status(ws)
+        if code != _capi.PULSAR_OK:
+            raise _capi.PulsarError(code, "pulsar_fwd_batched")
+        ctx.save_for_backward(pos, radius, opacity, payload, bg, image, aux, ws)
+        ctx.scenes, ctx.params = scenes, params
+        ctx.mark_non_differentiable(aux)
+        return image, aux
+
+    @staticmethod
+    def backward(ctx, grad_image, grad_aux):
+        pos, radius, opacity, payload, bg, image, aux, ws = ctx.saved_tensors
+        need = ctx.needs_input_grad
+        N, C = payload.shape
+        B = bg.shape[0]
+
+        def out(flag, shape):
+            return torch.empty(shape, device=payload.device, dtype=torch.float32) if flag \
+                else None
+
+        gp, gr = out(need[0], (N, 3)), out(need[1], (N,))
+        go = out(need[2] and opacity is not None, (N,))
+        gf, gb = out(need[3], (N, C)), out(need[4], (B, C))
+        if grad_image is None:
+            grad_image = torch.zeros_like(image)
+        _capi.pulsar_bwd_batched(ctx.scenes, pos, radius, opacity, payload, bg, ctx.params,
+                                 image, aux, grad_image.contiguous(), gp, gr, go, gf, gb, ws)
+        return gp, gr, go, gf, gb, None, None
+
+
+def render_batch(cams, counts, pos, radius, payload, opacity=None, bg=None, gamma=0.1,
+                 K: int = 5, eps: float = 1e-5, min_radius_px: float = 0.0, widths=None,
+                 heights=None, min_depth: float = 1.0, max_depth: float = 10.0,
+                 params=None):
+    """Renders B scenes in one batched call. cams: B cameras (pulsar_camera_t,
+    objects with R/t or 8-vectors, the latter two with widths/heights given);
+    counts: spheres per scene, the sphere tensors packed in scene order.
+    Returns a list of B images [H_b, W_b, C] (views into one packed tensor)."""
+    B = len(cams)
+    C = payload.shape[1]
+    structs = []
+    for b, c in enumerate(cams):
+        if isinstance(c, _capi.pulsar_camera_t):
+            structs.append(c)
+        else:
+            structs.append(camera_struct(c, int(widths[b]), int(heights[b]), min_depth,
+                                         max_depth))
+    scenes = _capi.make_scenes(structs, counts)
+    if bg is None:
+        bg = torch.zeros((B, C), device=payload.device, dtype=torch.float32)
+    if params is None:
+        params = _capi.make_params(gamma, eps, min_radius_px, K)
+    image, _ = PulsarBatchFunction.apply(pos, radius, opacity, payload, bg, scenes, params)
+    out, p0 = [], 0
+    for s in structs:
+        hw = int(s.width) * int(s.height)
+        out.append(image[p0:p0 + hw].view(int(s.height), int(s.width), C))
+        p0 += hw
+    return out
+
+
 class Renderer(torch.nn.Module):
     """Lst. 1 style renderer: Renderer(width, height, max_num_spheres)(pos, payload, radius, cam).
 
@@ -111,14 +189,45 @@ class Renderer(torch.nn.Module):
     """
 
     def __init__(self, width: int, height: int, max_num_spheres: int, n_channels: int = 3,
-                 K: int = 5, max_pairs: int = 0, check_capacity: bool = True):
+                 K: int = 5, max_pairs: int = 0, check_capacity: bool = True,
+                 autotune: bool = False, tune_cache: Optional[str] = None):
         super().__init__()
         self.width, self.height = int(width), int(height)
         self.max_num_spheres, self.n_channels, self.K = int(max_num_spheres), int(n_channels), \
             int(K)
         self.max_pairs = int(max_pairs)
         self.check_capacity = bool(check_capacity)
+        self.autotune = bool(autotune)
+        self._tune_cache = None
+        self._tune_path = tune_cache
+        self._knobs = {}
         _capi.load()
+
+    def _tuned(self, params, pos, radius, opacity, payload, bg, cs):
+        """Knobs for this workload from the tuning cache, or measured now on
+        these inputs (one forward + backward per candidate)."""
+        from . import autotune as at
+        if self._tune_cache is None:
+            self._tune_cache = at.TuneCache(self._tune_path)
+        n, C = payload.shape
+        key = at.cache_key(at.arch_name(), n, self.width * self.height, C, self.K)
+        knobs = self._knobs.get(key)
+        if knobs is None:
+            with torch.no_grad():
+                G = torch.ones((self.height, self.width, C), device=payload.device)
+                state = {}
+
+                def run(p):
+                    img, aux, ws, _ = _forward_into(pos, radius, opacity, payload, bg, cs, p,
+                                                    False)
+                    _capi.pulsar_bwd(pos, radius, opacity, payload, bg, cs, p, img, aux, G,
+                                     None, None, None, None, None, ws)
+                    state["ws"] = ws
+
+                tuned, _ = at.tune(run, params, key=key, cache=self._tune_cache)
+            knobs = at.knobs_of(tuned)
+            self._knobs[key] = knobs
+        return at.with_knobs(params, knobs)
 
     def forward(self, pos, payload, radius, cam, opacity: Optional[torch.Tensor] = None,
                 gamma: float = 0.1, max_depth: float = 10.0, min_depth: float = 1.0,
@@ -131,6 +240,10 @@ class Renderer(torch.nn.Module):
             bg = torch.zeros(C, device=payload.device, dtype=torch.float32)
         cs = camera_struct(cam, self.width, self.height, min_depth, max_depth)
         params = _capi.make_params(gamma, eps, min_radius_px, self.K, self.max_pairs)
+        if self.autotune:
+            params = self._tuned(params, pos.detach().contiguous(), radius.detach().contiguous(),
+                                 None if opacity is None else opacity.detach().contiguous(),
+                                 payload.detach().contiguous(), bg.detach().contiguous(), cs)
         image, aux = PulsarFunction.apply(pos, radius, opacity, payload, bg, cs, params,
                                           self.check_capacity)
         return (image, aux) if return_aux else image

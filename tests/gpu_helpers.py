@@ -24,12 +24,12 @@ def to_dev(a):
 
 
 def gpu_render(scene, cam, params, G=None, max_pairs=0, depth_bits=0, need=None,
-               stream=None):
+               stream=None, chunk=0, raster_blocks=0):
     """Forward (and backward when G is given) on cuda:0; numpy results."""
     import torch
     cs = cam_struct(cam)
     ps = _capi.make_params(params.gamma, params.eps, params.min_radius_px, params.K,
-                           max_pairs, depth_bits)
+                           max_pairs, depth_bits, chunk, raster_blocks)
     n, C = scene.payload.shape
     pos, rad, opa = to_dev(scene.pos), to_dev(scene.radius), to_dev(scene.opacity)
     pay, bg = to_dev(scene.payload), to_dev(scene.bg)
@@ -96,3 +96,54 @@ def compare_grads(gpu, ref, what=""):
         if ref.get(key) is None or gpu.get(key) is None:
             continue
         assert_close(gpu[key], ref[key], GRAD_REL, f"{what} {key}")
+
+
+def gpu_render_batch(workloads, params, Gs=None, depth_bits=0, chunk=0, raster_blocks=0,
+                     bgs=None, stream=None):
+    """One batched forward (and backward when Gs is given) over several
+    workloads sharing C and params; returns one result dict per scene."""
+    import torch
+    B = len(workloads)
+    C = workloads[0].scene.payload.shape[1]
+    ps = _capi.make_params(params.gamma, params.eps, params.min_radius_px, params.K, 0,
+                           depth_bits, chunk, raster_blocks)
+    scenes = _capi.make_scenes([cam_struct(w.camera) for w in workloads],
+                               [w.scene.n for w in workloads])
+    cat = lambda xs, shape: np.concatenate([np.asarray(x, np.float32).reshape(shape) for x in xs])
+    pos = to_dev(cat([w.scene.pos for w in workloads], (-1, 3)))
+    rad = to_dev(cat([w.scene.radius for w in workloads], (-1,)))
+    opa = to_dev(cat([w.scene.opacity for w in workloads], (-1,)))
+    pay = to_dev(cat([w.scene.payload for w in workloads], (-1, C)))
+    bg = to_dev(np.stack([w.scene.bg if bgs is None else bgs[b]
+                          for b, w in enumerate(workloads)]).astype(np.float32))
+    N, P = _capi.batch_sizes(scenes)
+    ws = torch.empty(_capi.pulsar_batch_workspace_size(scenes, C, ps), dtype=torch.uint8,
+                     device="cuda:0")
+    image = torch.empty((P, C), device="cuda:0")
+    aux = torch.empty((P,), device="cuda:0")
+    _capi.pulsar_fwd_batched(scenes, pos, rad, opa, pay, bg, ps, image, aux, ws, stream)
+    code, pairs = _capi.pulsar_query_status(ws, stream)
+    F, L = image.cpu().numpy(), aux.cpu().numpy()
+    outs, p0, n0 = [], 0, 0
+    for w in workloads:
+        H, W, n = w.camera.height, w.camera.width, w.scene.n
+        outs.append(dict(F=F[p0:p0 + H * W].reshape(H, W, C), L=L[p0:p0 + H * W].reshape(H, W),
+                         status=code, pairs=pairs, sl=(p0, n0)))
+        p0 += H * W
+        n0 += n
+    if Gs is not None and code == _capi.PULSAR_OK:
+        G = to_dev(np.concatenate([np.asarray(g, np.float32).reshape(-1, C) for g in Gs]))
+        gp = torch.full((N, 3), float("nan"), device="cuda:0")
+        gr = torch.full((N,), float("nan"), device="cuda:0")
+        go = torch.full((N,), float("nan"), device="cuda:0")
+        gf = torch.full((N, C), float("nan"), device="cuda:0")
+        gb = torch.full((B, C), float("nan"), device="cuda:0")
+        _capi.pulsar_bwd_batched(scenes, pos, rad, opa, pay, bg, ps, image, aux, G, gp, gr, go,
+                                 gf, gb, ws, stream)
+        torch.cuda.synchronize()
+        gp, gr, go, gf, gb = (t.cpu().numpy() for t in (gp, gr, go, gf, gb))
+        for b, (w, o) in enumerate(zip(workloads, outs)):
+            n0, n = o["sl"][1], w.scene.n
+            o.update(grad_pos=gp[n0:n0 + n], grad_radius=gr[n0:n0 + n],
+                     grad_opacity=go[n0:n0 + n], grad_payload=gf[n0:n0 + n], grad_bg=gb[b])
+    return outs

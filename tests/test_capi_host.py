@@ -43,7 +43,7 @@ def test_header_declarations_are_exported():
 
 def test_version_and_status_strings():
     _lib()
-    assert _capi.pulsar_version() == 1
+    assert _capi.pulsar_version() == 2
     for code in [0, -1, -2, -3, -4, -5, -99]:
         assert len(_capi.pulsar_status_string(code)) > 5
     assert "capacity" in _capi.pulsar_status_string(_capi.PULSAR_ERR_CAPACITY)
@@ -102,6 +102,11 @@ def test_bad_camera_is_rejected(cam_kw):
     (dict(K=33), _capi.PULSAR_ERR_INVALID_ARGUMENT),
     (dict(max_pairs=-5), _capi.PULSAR_ERR_INVALID_ARGUMENT),
     (dict(depth_bits=17), _capi.PULSAR_ERR_INVALID_ARGUMENT),
+    (dict(chunk=32), _capi.PULSAR_ERR_INVALID_ARGUMENT),
+    (dict(chunk=100), _capi.PULSAR_ERR_INVALID_ARGUMENT),
+    (dict(chunk=2048), _capi.PULSAR_ERR_INVALID_ARGUMENT),
+    (dict(raster_blocks=100), _capi.PULSAR_ERR_INVALID_ARGUMENT),
+    (dict(raster_blocks=70000), _capi.PULSAR_ERR_INVALID_ARGUMENT),
 ])
 def test_bad_params_are_rejected(par_kw, code):
     assert _call_fwd(_cam(), _capi.make_params(**par_kw)) == code
@@ -164,3 +169,88 @@ print("RC", rc, lib.pulsar_last_hip_error().decode())
     if "HAS_GPU" in out.stdout:
         pytest.skip("a GPU is present; this checks the no-device path")
     assert f"RC {_capi.PULSAR_ERR_HIP}" in out.stdout, out.stdout + out.stderr
+
+
+# ---------------------------------------------------------------- batched calls
+
+def _scenes(specs):
+    """specs: list of (width, height, n)."""
+    return _capi.make_scenes([_cam(width=w, height=h) for w, h, _ in specs],
+                             [n for _, _, n in specs])
+
+
+def _call_fwd_batched(scenes, params, C=3, ws_bytes=1 << 34, pos=FAKE, image=FAKE, B=None):
+    lib = _lib()
+    return lib.pulsar_fwd_batched(scenes, len(scenes) if B is None else B, pos, FAKE, None, FAKE,
+                                  C, FAKE, ctypes.byref(params), image, None, FAKE, ws_bytes,
+                                  None)
+
+
+def test_batch_workspace_matches_single_scene_and_grows():
+    _lib()
+    p = _capi.make_params(K=5)
+    one = _scenes([(256, 256, 5000)])
+    assert _capi.pulsar_batch_workspace_size(one, 3, p) == \
+        _capi.pulsar_workspace_size(5000, 256, 256, 3, p)
+    two = _scenes([(256, 256, 5000), (512, 384, 20000)])
+    three = _scenes([(256, 256, 5000), (512, 384, 20000), (1024, 1024, 0)])
+    s1 = _capi.pulsar_batch_workspace_size(one, 3, p)
+    s2 = _capi.pulsar_batch_workspace_size(two, 3, p)
+    s3 = _capi.pulsar_batch_workspace_size(three, 3, p)
+    assert 0 < s1 < s2 < s3
+    # the same scenes in another order need the same space
+    rev = _scenes([(512, 384, 20000), (256, 256, 5000)])
+    assert _capi.pulsar_batch_workspace_size(rev, 3, p) == s2
+    # the tuning knobs only resize work-item buffers
+    assert _capi.pulsar_batch_workspace_size(two, 3, _capi.make_params(K=5, chunk=64)) > s2
+    assert _capi.pulsar_batch_workspace_size(two, 3, _capi.make_params(K=5, raster_blocks=512)) \
+        == s2
+
+
+def test_batched_argument_checks():
+    _lib()
+    p = _capi.make_params(K=5)
+    good = _scenes([(64, 64, 10), (32, 48, 7)])
+    assert _capi.pulsar_batch_workspace_size(good, 3, p) > 0
+    # B out of range
+    assert _call_fwd_batched(good, p, B=0) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    many = _scenes([(8, 8, 1)] * (_capi.PULSAR_MAX_SCENES + 1))
+    assert _call_fwd_batched(many, p) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    assert _capi.pulsar_batch_workspace_size(many, 3, p) == 0
+    # a bad camera or count anywhere in the batch
+    bad = _scenes([(64, 64, 10), (0, 48, 7)])
+    assert _call_fwd_batched(bad, p) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    neg = _scenes([(64, 64, 10), (32, 48, -1)])
+    assert _call_fwd_batched(neg, p) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    res = _scenes([(64, 64, 10), (32, 48, 7)])
+    res[1].reserved = 3
+    assert _call_fwd_batched(res, p) == _capi.PULSAR_ERR_UNSUPPORTED
+    # more than 2^31 - 1 spheres in total
+    huge = _scenes([(64, 64, 2**30), (64, 64, 2**30)])
+    assert _call_fwd_batched(huge, p) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    # pointers and workspace
+    assert _call_fwd_batched(good, p, pos=None) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    assert _call_fwd_batched(good, p, image=None) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    need = _capi.pulsar_batch_workspace_size(good, 3, p)
+    assert _call_fwd_batched(good, p, ws_bytes=need - 1) == _capi.PULSAR_ERR_WORKSPACE
+    # all-empty batches need no sphere pointers
+    empty = _scenes([(64, 64, 0), (32, 48, 0)])
+    need0 = _capi.pulsar_batch_workspace_size(empty, 3, p)
+    assert _call_fwd_batched(empty, p, pos=None, ws_bytes=need0 - 1) == _capi.PULSAR_ERR_WORKSPACE
+
+
+def test_batched_backward_argument_checks():
+    lib = _lib()
+    p = _capi.make_params(K=5)
+    sc = _scenes([(64, 64, 10), (32, 48, 7)])
+    args = [sc, 2, FAKE, FAKE, None, FAKE, 3, FAKE, ctypes.byref(p), FAKE, FAKE, FAKE, FAKE,
+            FAKE, None, FAKE, FAKE, FAKE, 1 << 34, None]
+    no_grad_image = list(args)
+    no_grad_image[11] = None
+    assert lib.pulsar_bwd_batched(*no_grad_image) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    op_grad_without_opacity = list(args)
+    op_grad_without_opacity[14] = FAKE
+    assert lib.pulsar_bwd_batched(*op_grad_without_opacity) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    small = list(args)
+    small[18] = 4096
+    assert lib.pulsar_bwd_batched(*small) == _capi.PULSAR_ERR_WORKSPACE
