@@ -247,6 +247,9 @@ def main() -> int:
                     help="skip the batched-vs-looped measurement of 32 uneven scenes")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the default launch knobs instead of autotuning them first")
+    ap.add_argument("--knobs", default="", metavar="K=V,...",
+                    help="fixed launch knobs for the single-scene workload, e.g. "
+                         "raster_blocks=4096,chunk=128,depth_bits=0 (implies no tuning)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times) and exit; "
                          "calibrates the FETCH_SIZE / WRITE_SIZE counters")
@@ -314,7 +317,19 @@ def main() -> int:
         code, pairs = _capi.pulsar_query_status(ws, stream)
         assert code == _capi.PULSAR_OK
     tune_info = None
-    if not args.no_tune:
+    if args.knobs:
+        for kv in args.knobs.split(","):
+            k, v = kv.split("=")
+            if k not in ("raster_blocks", "chunk", "depth_bits"):
+                raise SystemExit(f"unknown knob {k}")
+            setattr(ps, k, int(v))
+        ws = torch.empty(_capi.pulsar_workspace_size(n, W, H, C, ps), dtype=torch.uint8,
+                         device=dev)
+        step()
+        tune_info = {"knobs": {k: int(getattr(ps, k)) for k in ("raster_blocks", "chunk",
+                                                                 "depth_bits")}}
+        log(f"[bench] fixed knobs {tune_info['knobs']}")
+    elif not args.no_tune:
         from paper_2004_07484_amd import autotune as at
         wss = {}
 

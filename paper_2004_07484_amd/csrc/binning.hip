@@ -365,13 +365,10 @@ __global__ __launch_bounds__(256) void k_chunk_emit(const uint32_t* __restrict__
 // when the sphere touches exactly one tile.
 __global__ __launch_bounds__(256) void k_gather_records(
     const uint32_t* __restrict__ svals, const Status* __restrict__ status,
-    const float4* __restrict__ recA, const float4* __restrict__ recB,
-    const float4* __restrict__ recC, const float4* __restrict__ recD,
-    const float* __restrict__ payload, int C, float4* __restrict__ srec,
-    float* __restrict__ spay) {
+    const float4* __restrict__ rec, const float* __restrict__ payload, int C, int vec,
+    float4* __restrict__ srec, float* __restrict__ spay) {
   // one thread per 16-byte unit: four record units, then the payload row in
-  // float4 units (C % 4 == 0) or single floats
-  const bool vec = (C & 3) == 0;
+  // float4 units (vec: C % 4 == 0 and a 16-byte aligned payload) or floats
   const uint32_t pu = vec ? uint32_t(C) / 4u : uint32_t(C);
   const uint32_t units = 4u + pu;
   const unsigned long long total = (unsigned long long)status->used * units;
@@ -380,8 +377,7 @@ __global__ __launch_bounds__(256) void k_gather_records(
     const uint32_t j = uint32_t(t / units), u = uint32_t(t % units);
     const uint32_t id = svals[j];
     if (u < 4u) {
-      const float4* src = u == 0u ? recA : u == 1u ? recB : u == 2u ? recC : recD;
-      float4 v = src[id];
+      float4 v = rec[4 * size_t(id) + u];
       if (u == 3u) {
         const uint32_t single = __float_as_uint(v.w) == 1u ? kFirstChunk : 0u;
         v.w = __uint_as_float(id | single);
@@ -401,14 +397,14 @@ __global__ __launch_bounds__(256) void k_gather_records(
 
 void launch_gather_records(const Plan& q, const float* payload, char* ws, hipStream_t stream) {
   const uint32_t* svals = ws_ptr<uint32_t>(ws, sorted_in_a(q) ? q.off_valsA : q.off_valsB);
-  const long long units = 4 + ((q.C & 3) == 0 ? q.C / 4 : q.C);
+  const int vec = (q.C & 3) == 0 && (reinterpret_cast<uintptr_t>(payload) & 15u) == 0u;
+  const long long units = 4 + (vec ? q.C / 4 : q.C);
   long long blocks = (q.cap * units + 255) / 256;
   if (blocks > 16384) blocks = 16384;
   hipLaunchKernelGGL(k_gather_records, dim3(unsigned(blocks)), dim3(256), 0, stream, svals,
-                     ws_ptr<Status>(ws, q.off_status), ws_ptr<float4>(ws, q.off_recA),
-                     ws_ptr<float4>(ws, q.off_recB), ws_ptr<float4>(ws, q.off_recC),
-                     ws_ptr<float4>(ws, q.off_recD), payload, int(q.C),
-                     ws_ptr<float4>(ws, q.off_srec), ws_ptr<float>(ws, q.off_spay));
+                     ws_ptr<Status>(ws, q.off_status), ws_ptr<float4>(ws, q.off_rec), payload,
+                     int(q.C), vec, ws_ptr<float4>(ws, q.off_srec),
+                     ws_ptr<float>(ws, q.off_spay));
 }
 
 void launch_binning(const Plan& q, char* ws, hipStream_t stream) {

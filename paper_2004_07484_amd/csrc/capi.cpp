@@ -186,10 +186,7 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   q.off_counts = take(nn * 4);
   q.off_trect = take(nn * 8);
   q.off_qdepth = take(nn * 4);
-  q.off_recA = take(nn * 16);
-  q.off_recB = take(nn * 16);
-  q.off_recC = take(nn * 16);
-  q.off_recD = take(nn * 16);
+  q.off_rec = take(nn * 64);
   q.off_gacc = take(nn * 16);
   q.off_partials = take(size_t(q.nblk_proj + 1) * 8);
   q.off_keysA = take(size_t(cap) * 4);

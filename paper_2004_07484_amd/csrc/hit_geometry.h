@@ -202,11 +202,5 @@ __device__ __forceinline__ SphereRec unpack_rec(const float4& a, const float4& b
   return s;
 }
 
-__device__ __forceinline__ SphereRec load_rec(const float4* __restrict__ recA,
-                                              const float4* __restrict__ recB,
-                                              const float4* __restrict__ recC,
-                                              const float4* __restrict__ recD, uint32_t id) {
-  return unpack_rec(recA[id], recB[id], recC[id], recD[id]);
-}
 
 }  // namespace pulsar

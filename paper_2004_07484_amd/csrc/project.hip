@@ -6,12 +6,13 @@
 //   counts  number of 8x8 tiles its pixel rectangle touches (0 = culled)
 //   trect   tile rectangle (tx0, ty0, tx1, ty1)
 //   qdepth  floor-quantised lower bound of its nearest possible hit distance
-//   recA    (X_c - x0, Y_c - y0, kappa, x0 | y0 << 16): projected centre in
+//   rec     four float4 per sphere, one 64-byte line:
+//     [0]   (X_c - x0, Y_c - y0, kappa, x0 | y0 << 16): projected centre in
 //           pixel units relative to the first pixel of its rectangle, and
 //           kappa = (c_z pitch / R)^2 (high FP32 parts)
-//   recB    (c_x / c_z, c_y / c_z, c_z, R) (ratios as high parts)
-//   recC    low parts of X_c - x0, Y_c - y0, kappa, c_x / c_z
-//   recD    (low part of c_y / c_z, opacity, x1 | y1 << 16, tile count): x1,
+//     [1]   (c_x / c_z, c_y / c_z, c_z, R) (ratios as high parts)
+//     [2]   low parts of X_c - x0, Y_c - y0, kappa, c_x / c_z
+//     [3]   (low part of c_y / c_z, opacity, x1 | y1 << 16, tile count): x1,
 //           y1 is the last pixel of its rectangle
 // and the per-block sum of counts for the tile-pair scan. High + low FP32
 // parts carry the FP64 values to about 48 bits for the exact hit test.
@@ -71,8 +72,7 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
     int n, const float* __restrict__ pos, const float* __restrict__ radius,
     const float* __restrict__ opacity, SceneTable tab, float min_radius_px, int depth_bits,
     uint32_t* __restrict__ counts, ushort4* __restrict__ trect, uint32_t* __restrict__ qdepth,
-    float4* __restrict__ recA, float4* __restrict__ recB, float4* __restrict__ recC,
-    float4* __restrict__ recD, unsigned long long* __restrict__ partials) {
+    float4* __restrict__ rec, unsigned long long* __restrict__ partials) {
   const int i = blockIdx.x * kProjectBlock + threadIdx.x;
   uint32_t count = 0;
   if (i < n) {
@@ -131,12 +131,13 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
         const float Xh = float(X), Yh = float(Y), kh = float(kap), axh = float(ax),
                     ayh = float(ay);
         const uint32_t packed = uint32_t(j0) | (uint32_t(i0) << 16);
-        recA[i] = make_float4(Xh, Yh, kh, __uint_as_float(packed));
-        recB[i] = make_float4(axh, ayh, float(cz), float(R));
-        recC[i] = make_float4(float(X - Xh), float(Y - Yh), float(kap - kh), float(ax - axh));
+        float4* r4 = rec + 4 * size_t(i);
+        r4[0] = make_float4(Xh, Yh, kh, __uint_as_float(packed));
+        r4[1] = make_float4(axh, ayh, float(cz), float(R));
+        r4[2] = make_float4(float(X - Xh), float(Y - Yh), float(kap - kh), float(ax - axh));
         const uint32_t packed_end = uint32_t(j1) | (uint32_t(i1) << 16);
-        recD[i] = make_float4(float(ay - ayh), o, __uint_as_float(packed_end),
-                              __uint_as_float(count));
+        r4[3] = make_float4(float(ay - ayh), o, __uint_as_float(packed_end),
+                            __uint_as_float(count));
         // floor quantisation of (tmin - znear) / span, minus one step of margin,
         // so the decoded value never exceeds any float32 hit distance
         const double span = double(cam.zfar) - double(cam.znear);
@@ -167,9 +168,7 @@ void launch_project(const Plan& q, const FwdArgs& a, char* ws, hipStream_t strea
                      a.pos, a.radius, a.opacity, scene_table(q, ws), a.min_radius_px,
                      q.depth_bits,
                      ws_ptr<uint32_t>(ws, q.off_counts), ws_ptr<ushort4>(ws, q.off_trect),
-                     ws_ptr<uint32_t>(ws, q.off_qdepth), ws_ptr<float4>(ws, q.off_recA),
-                     ws_ptr<float4>(ws, q.off_recB), ws_ptr<float4>(ws, q.off_recC),
-                     ws_ptr<float4>(ws, q.off_recD),
+                     ws_ptr<uint32_t>(ws, q.off_qdepth), ws_ptr<float4>(ws, q.off_rec),
                      ws_ptr<unsigned long long>(ws, q.off_partials));
 }
 

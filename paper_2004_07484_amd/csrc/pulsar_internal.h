@@ -90,7 +90,7 @@ struct Plan {
   int64_t n, C, T, npix, cap, nbgblk;
   int B, chunk, raster_grid;
   int tile_bits, depth_bits, passes, nblk_proj, nblk_sort;
-  size_t off_status, off_counts, off_trect, off_qdepth, off_recA, off_recB, off_recC, off_recD;
+  size_t off_status, off_counts, off_trect, off_qdepth, off_rec;
   size_t off_gacc;
   size_t off_partials, off_keysA, off_valsA, off_keysB, off_valsB, off_hist, off_dtot;
   size_t off_ranges;

@@ -21,6 +21,9 @@
 
 namespace pulsar {
 
+// Backward raster by (tile, sphere) pair instead of by tile work item.
+constexpr bool kPairBackward = false;
+
 struct BwdKernelArgs {
   SceneTable tab;
   Status* status;
@@ -244,6 +247,121 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks(BwdKernelArgs A) {
   }
 }
 
+// Pair-parallel variant of K7: lane = one (tile, sphere) pair of the sorted
+// lists. The lane walks its sphere's rectangle inside the tile, recomputes
+// each hit from the pixel's ray, keeps those among the pixel's K nearest and
+// adds their terms in registers; the pixel data (G, F, L, threshold) come
+// straight from memory, where neighbouring lanes (pairs of the same tile)
+// share them through the caches. No LDS, no barriers, so occupancy is set by
+// registers alone and global-memory latency overlaps across many waves.
+struct BwdPairArgs {
+  SceneTable tab;
+  const Status* status;
+  const uint32_t* keys;  // sorted pair keys: tile << depth_bits | quantised depth
+  int depth_bits;
+  const float4* srec;
+  const float* spay;
+  const float* image;
+  const float* aux;
+  const float* grad_image;
+  const float2* thr;
+  float* gacc;
+  float* grad_opacity;
+  float* grad_payload;
+  int C;
+};
+
+constexpr int kPairThreads = 256;
+
+template <int CM>
+__global__ __launch_bounds__(kPairThreads) void k_bwd_pairs(BwdPairArgs A) {
+  const uint32_t used = A.status->used;
+  const int C = A.C;
+  for (uint32_t j = blockIdx.x * kPairThreads + threadIdx.x; j < used;
+       j += gridDim.x * kPairThreads) {
+    const uint32_t tile = A.keys[j] >> A.depth_bits;
+    const TileScene ts = tile_scene(A.tab, tile);
+    const SceneDev& sc = A.tab.scenes[ts.b];
+    const CamDev cam = sc.cam;
+    const BlendConst bc = sc.bc;
+    const float4* rp = A.srec + 4 * size_t(j);
+    const float4 rd = rp[3];
+    const SphereRec s = unpack_rec(rp[0], rp[1], rp[2], rd);
+    const uint32_t id = __float_as_uint(rd.w) & ~kFirstChunk;
+    const bool single = (__float_as_uint(rd.w) & kFirstChunk) != 0u;
+    const uint32_t p1 = __float_as_uint(rd.z);
+    const int xa = max(s.x0, ts.tx0), xb = min(int(p1 & 0xffffu), ts.tx0 + kTileW - 1);
+    const int ya = max(s.y0, ts.ty0), yb = min(int(p1 >> 16), ts.ty0 + kTileH - 1);
+    float f[CM], gf[CM];
+    const float* fp = A.spay + size_t(j) * size_t(C);
+#pragma unroll
+    for (int c = 0; c < CM; ++c) {
+      f[c] = c < C ? fp[c] : 0.f;
+      gf[c] = 0.f;
+    }
+    float gcx = 0.f, gcy = 0.f, gcz = 0.f, gR = 0.f, go = 0.f;
+    uint32_t nh = 0;
+    for (int py = ya; py <= yb; ++py) {
+      for (int px = xa; px <= xb; ++px) {
+        const PixelRay ray = make_ray(cam, px, py);
+        Hit h;
+        if (!exact_hit(ray, s, bc.zfar, h)) continue;
+        const size_t p = size_t(sc.pix_off) + size_t(py) * size_t(cam.W) + size_t(px);
+        const float2 th = A.thr[p];
+        const float tk = th.x;
+        const uint32_t ik = __float_as_uint(th.y);
+        if (!(id == ik || h.t < tk || (h.t == tk && id < ik))) continue;
+        float G[CM];
+        float hs = 0.f;  // G . (f_k - F)
+        const float* Gp = A.grad_image + p * size_t(C);
+        const float* Fp = A.image + p * size_t(C);
+#pragma unroll
+        for (int c = 0; c < CM; ++c) {
+          G[c] = c < C ? Gp[c] : 0.f;
+          const float F = c < C ? Fp[c] : 0.f;
+          hs += G[c] * (f[c] - F);
+        }
+        const HitGrad g = hit_grad(ray, s, h, cam, bc, A.aux[p] * 1.4426950408889634f, hs);
+        gcx += g.gcx;
+        gcy += g.gcy;
+        gcz += g.gcz;
+        gR += g.gR;
+        go += g.go;
+#pragma unroll
+        for (int c = 0; c < CM; ++c) gf[c] += g.w * G[c];
+        ++nh;
+      }
+    }
+    // A sphere that touches one tile has exactly one pair: it stores its sums
+    // (zeros included). Others add into zeroed sums.
+    if (single) {
+      if (A.grad_payload) {
+        float* gp = A.grad_payload + size_t(id) * size_t(C);
+#pragma unroll
+        for (int c = 0; c < CM; ++c)
+          if (c < C) gp[c] = gf[c];
+      }
+      if (A.grad_opacity) A.grad_opacity[id] = go;
+      if (A.gacc) reinterpret_cast<float4*>(A.gacc)[id] = make_float4(gcx, gcy, gcz, gR);
+    } else if (nh > 0) {
+      if (A.grad_payload) {
+        float* gp = A.grad_payload + size_t(id) * size_t(C);
+#pragma unroll
+        for (int c = 0; c < CM; ++c)
+          if (c < C) atomicAdd(gp + c, gf[c]);
+      }
+      if (A.grad_opacity) atomicAdd(A.grad_opacity + id, go);
+      if (A.gacc) {
+        float* gg = A.gacc + size_t(id) * 4;
+        atomicAdd(gg + 0, gcx);
+        atomicAdd(gg + 1, gcy);
+        atomicAdd(gg + 2, gcz);
+        atomicAdd(gg + 3, gR);
+      }
+    }
+  }
+}
+
 // Channels beyond the register budget: same walk, the pixel terms read from
 // global memory and payload gradients go out per hit.
 __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A) {
@@ -405,50 +523,74 @@ __global__ void k_finalize(int n, const uint32_t* __restrict__ counts,
 
 // Background gradient, dL/dbg = sum_p exp(eps/gamma - L_p) G_p per scene:
 // per-block partial sums [blocks][C]; every block covers kBgBlockPixels
-// pixels of one scene (256 threads x kBgPixels).
-constexpr int kBgPixels = kBgBlockPixels / 256;
-__global__ __launch_bounds__(256) void k_bg_partial(SceneTable tab, const float* __restrict__ aux,
-                                                    const float* __restrict__ grad_image, int C,
-                                                    float eps2, float* __restrict__ bgsum) {
-  __shared__ float s[256 / kWave][8];
+// consecutive pixels of one scene. The block's pixel weights go to LDS, then
+// the block reads its G rows as one flat run of floats: thread t takes
+// elements t, t + S, t + 2S, ... with S the largest multiple of C <= 256, so
+// its channel is always t % C and consecutive threads read consecutive floats.
+constexpr int kBgThreads = 256;
+constexpr int kBgMaxC = kBgThreads;  // wider images use k_bg_partial_wide
+__global__ __launch_bounds__(kBgThreads) void k_bg_partial(SceneTable tab,
+                                                           const float* __restrict__ aux,
+                                                           const float* __restrict__ grad_image,
+                                                           int C, float eps2,
+                                                           float* __restrict__ bgsum) {
+  __shared__ float s_w[kBgBlockPixels];
+  __shared__ float s_acc[kBgThreads];
+  const int tid = threadIdx.x;
   const int b = find_scene(tab.blk_start, tab.B, blockIdx.x);
   const SceneDev& sc = tab.scenes[b];
   const long long npix = (long long)sc.cam.W * sc.cam.H;
-  const long long p0 =
-      (long long)(blockIdx.x - sc.bgblk_off) * kBgBlockPixels + (long long)threadIdx.x;
+  const long long p0 = (long long)(blockIdx.x - sc.bgblk_off) * kBgBlockPixels;
+  const int np = int(min((long long)kBgBlockPixels, npix - p0));
+  const float* auxs = aux + sc.pix_off + p0;
+  const float* gs = grad_image + (size_t(sc.pix_off) + size_t(p0)) * size_t(C);
+  for (int k = tid; k < kBgBlockPixels; k += kBgThreads)
+    s_w[k] = k < np ? fast_exp2(eps2 - auxs[k] * 1.4426950408889634f) : 0.f;
+  __syncthreads();
+  const int S = (kBgThreads / C) * C;  // threads in use, a multiple of C
+  const int step = S / C;               // pixels advanced per round
+  float acc = 0.f;
+  if (tid < S) {
+    const int total = np * C;
+    int pix = tid / C;
+    for (int f = tid; f < total; f += S, pix += step) acc += s_w[pix] * gs[f];
+  }
+  s_acc[tid] = acc;
+  __syncthreads();
+  if (tid < C) {
+    float t = 0.f;
+    for (int k = tid; k < S; k += C) t += s_acc[k];
+    bgsum[size_t(blockIdx.x) * size_t(C) + tid] = t;
+  }
+}
+
+// The same sums for C > kBgMaxC: one pixel per thread and a loop over channels.
+__global__ __launch_bounds__(kBgThreads) void k_bg_partial_wide(SceneTable tab,
+                                                                const float* __restrict__ aux,
+                                                                const float* __restrict__ grad_image,
+                                                                int C, float eps2,
+                                                                float* __restrict__ bgsum) {
+  __shared__ float s[kBgThreads / kWave];
+  const int b = find_scene(tab.blk_start, tab.B, blockIdx.x);
+  const SceneDev& sc = tab.scenes[b];
+  const long long npix = (long long)sc.cam.W * sc.cam.H;
+  const long long p0 = (long long)(blockIdx.x - sc.bgblk_off) * kBgBlockPixels;
   const float* auxs = aux + sc.pix_off;
   const float* gs = grad_image + size_t(sc.pix_off) * size_t(C);
-  float w[kBgPixels];
-#pragma unroll
-  for (int k = 0; k < kBgPixels; ++k) {
-    const long long p = p0 + k * 256;
-    w[k] = p < npix ? fast_exp2(eps2 - auxs[p] * 1.4426950408889634f) : 0.f;
-  }
-  for (int c0 = 0; c0 < C; c0 += 8) {
-    float acc[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) acc[c] = 0.f;
-#pragma unroll
-    for (int k = 0; k < kBgPixels; ++k) {
-      const long long p = p0 + k * 256;
-      if (p < npix) {
-        const float* g = gs + size_t(p) * size_t(C) + c0;
-#pragma unroll
-        for (int c = 0; c < 8; ++c)
-          if (c0 + c < C) acc[c] += w[k] * g[c];
-      }
+  for (int c = 0; c < C; ++c) {
+    float acc = 0.f;
+    for (int k = threadIdx.x; k < kBgBlockPixels; k += kBgThreads) {
+      const long long p = p0 + k;
+      if (p < npix) acc += fast_exp2(eps2 - auxs[p] * 1.4426950408889634f) * gs[size_t(p) * C + c];
     }
-#pragma unroll
-    for (int c = 0; c < 8; ++c) acc[c] = wave_sum(acc[c]);
+    acc = wave_sum(acc);
     __syncthreads();
-    if ((threadIdx.x & (kWave - 1)) == 0)
-#pragma unroll
-      for (int c = 0; c < 8; ++c) s[threadIdx.x / kWave][c] = acc[c];
+    if ((threadIdx.x & (kWave - 1)) == 0) s[threadIdx.x / kWave] = acc;
     __syncthreads();
-    if (threadIdx.x < 8 && c0 + int(threadIdx.x) < C) {
-      float tsum = 0.f;
-      for (int w2 = 0; w2 < 256 / kWave; ++w2) tsum += s[w2][threadIdx.x];
-      bgsum[size_t(blockIdx.x) * size_t(C) + c0 + threadIdx.x] = tsum;
+    if (threadIdx.x == 0) {
+      float t = 0.f;
+      for (int w = 0; w < kBgThreads / kWave; ++w) t += s[w];
+      bgsum[size_t(blockIdx.x) * size_t(C) + c] = t;
     }
   }
 }
@@ -500,7 +642,38 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
   stage_end(PULSAR_STAGE_ZERO, stream);
   stage_begin(PULSAR_STAGE_RASTER_BWD, stream);
   const dim3 grid(unsigned(q.raster_grid)), block(kWave);
-  if (a.C <= 1)
+  if (kPairBackward && a.C <= kBwdChannels) {
+    BwdPairArgs P;
+    P.tab = tab;
+    P.status = A.status;
+    P.keys = ws_ptr<uint32_t>(ws, sorted_in_a(q) ? q.off_keysA : q.off_keysB);
+    P.depth_bits = q.depth_bits;
+    P.srec = A.srec;
+    P.spay = A.spay;
+    P.image = A.image;
+    P.aux = A.aux;
+    P.grad_image = A.grad_image;
+    P.thr = A.thr;
+    P.gacc = A.gacc;
+    P.grad_opacity = A.grad_opacity;
+    P.grad_payload = A.grad_payload;
+    P.C = A.C;
+    long long pb = (q.cap + kPairThreads - 1) / kPairThreads;
+    if (pb > 8192) pb = 8192;
+    const dim3 pg{unsigned(pb), 1u, 1u}, pt{unsigned(kPairThreads), 1u, 1u};
+    if (a.C <= 1)
+      hipLaunchKernelGGL(k_bwd_pairs<1>, pg, pt, 0, stream, P);
+    else if (a.C <= 2)
+      hipLaunchKernelGGL(k_bwd_pairs<2>, pg, pt, 0, stream, P);
+    else if (a.C <= 4)
+      hipLaunchKernelGGL(k_bwd_pairs<4>, pg, pt, 0, stream, P);
+    else if (a.C <= 8)
+      hipLaunchKernelGGL(k_bwd_pairs<8>, pg, pt, 0, stream, P);
+    else if (a.C <= 16)
+      hipLaunchKernelGGL(k_bwd_pairs<16>, pg, pt, 0, stream, P);
+    else
+      hipLaunchKernelGGL(k_bwd_pairs<32>, pg, pt, 0, stream, P);
+  } else if (a.C <= 1)
     hipLaunchKernelGGL(k_bwd_chunks<1>, grid, block, 0, stream, A);
   else if (a.C <= 2)
     hipLaunchKernelGGL(k_bwd_chunks<2>, grid, block, 0, stream, A);
@@ -522,8 +695,12 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
                        reinterpret_cast<const float4*>(A.gacc), a.grad_pos, a.grad_radius,
                        a.grad_opacity, a.grad_payload);
   if (a.grad_bg) {
-    hipLaunchKernelGGL(k_bg_partial, dim3(unsigned(q.nbgblk)), dim3(256), 0, stream, tab, a.aux,
-                       a.grad_image, int(q.C), a.eps2, bgsum);
+    if (q.C <= kBgMaxC)
+      hipLaunchKernelGGL(k_bg_partial, dim3(unsigned(q.nbgblk)), dim3(kBgThreads), 0, stream,
+                         tab, a.aux, a.grad_image, int(q.C), a.eps2, bgsum);
+    else
+      hipLaunchKernelGGL(k_bg_partial_wide, dim3(unsigned(q.nbgblk)), dim3(kBgThreads), 0,
+                         stream, tab, a.aux, a.grad_image, int(q.C), a.eps2, bgsum);
     hipLaunchKernelGGL(k_reduce_bg, dim3(unsigned(q.C), unsigned(q.B)), dim3(256), 0, stream, tab,
                        bgsum, int(q.C), a.grad_bg);
   }

@@ -338,7 +338,9 @@ __global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(FwdKernelArgs
 }
 
 // Pixels of tiles without any sphere: F = background, L = eps / gamma, and
-// no hit for the gradient threshold. One wave per tile, lane = pixel.
+// no hit for the gradient threshold. One wave per tile; the image is written
+// row by row as contiguous runs of (pixels in the row) x C floats, so each
+// store instruction covers consecutive addresses.
 template <int CM>
 __global__ __launch_bounds__(256) void k_fwd_background(FwdKernelArgs A, uint32_t T) {
   const uint32_t tile = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
@@ -346,14 +348,22 @@ __global__ __launch_bounds__(256) void k_fwd_background(FwdKernelArgs A, uint32_
   if (tile >= T || A.tinfo[tile].y != 0u) return;
   const TileScene ts = tile_scene(A.tab, tile);
   const SceneDev& sc = A.tab.scenes[ts.b];
+  const int W = sc.cam.W, H = sc.cam.H, C = A.C;
+  const int npx = min(kTileW, W - ts.tx0);    // pixels of the tile inside each row
+  const int nrows = min(kTileH, H - ts.ty0);
+  const float* bg = A.bg + size_t(ts.b) * size_t(C);
+  const int run = npx * C;
+  for (int r = 0; r < nrows; ++r) {
+    float* row = A.image + (size_t(sc.pix_off) + size_t(ts.ty0 + r) * size_t(W) +
+                            size_t(ts.tx0)) * size_t(C);
+    for (int f = lane; f < run; f += kWave) {
+      const int ch = f % C;
+      if (ch >= A.c0 && ch < A.c0 + A.cn) row[f] = bg[ch];
+    }
+  }
   const int px = ts.tx0 + lane % kTileW, py = ts.ty0 + lane / kTileW;
-  if (px >= sc.cam.W || py >= sc.cam.H) return;
-  const size_t p = size_t(sc.pix_off) + size_t(py) * size_t(sc.cam.W) + size_t(px);
-  const float* bg = A.bg + size_t(ts.b) * size_t(A.C) + A.c0;
-  float* out = A.image + p * size_t(A.C) + A.c0;
-#pragma unroll
-  for (int c = 0; c < CM; ++c)
-    if (c < A.cn) out[c] = bg[c];
+  if (px >= W || py >= H) return;
+  const size_t p = size_t(sc.pix_off) + size_t(py) * size_t(W) + size_t(px);
   if (A.c0 == 0 && A.aux) A.aux[p] = A.eps2 * 0.69314718055994531f;
   if (A.track) A.thr[p] = make_float2(INFINITY, __uint_as_float(0xffffffffu));
 }

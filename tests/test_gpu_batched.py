@@ -211,5 +211,9 @@ def test_tuning_knobs_keep_results(knob):
     else:
         assert_close(got["F"], base["F"], 2e-6, "image", floor=1e-2)
         assert_close(got["L"], base["L"], 2e-6, "log-normaliser", floor=1e-2)
+    # a bitwise-equal forward leaves only float atomic order to the gradients;
+    # a changed summation order moves F in its last bits, which h = G . (f - F)
+    # amplifies where f is close to F, so those are held to the parity bar
+    rel = 1e-4 if "raster_blocks" in knob else GRAD_REL
     for key in ["grad_pos", "grad_radius", "grad_opacity", "grad_payload", "grad_bg"]:
-        assert_close(got[key], base[key], 1e-4, key, floor=1e-3)
+        assert_close(got[key], base[key], rel, key, floor=1e-2)
