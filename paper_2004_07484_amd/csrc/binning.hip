@@ -13,17 +13,26 @@ namespace pulsar {
 
 // ---------------------------------------------------------------- K2 scan
 // Single block: exclusive scan of the per-block sums in place; writes the
-// total pair count and the capacity status.
+// total pair count and the capacity status. Thread t owns a run of
+// consecutive entries, loaded together, so one pass over the block suffices
+// for up to kScanThreads * kScanRun entries (more take further passes).
+constexpr int kScanRun = 8;
 __global__ __launch_bounds__(kScanThreads) void k_scan_partials(
     unsigned long long* __restrict__ partials, int nblk, long long cap,
     Status* __restrict__ status) {
   __shared__ unsigned long long s_wave[kScanThreads / kWave];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   unsigned long long carry = 0;
-  for (int base = 0; base < nblk; base += kScanThreads) {
-    const int i = base + tid;
-    const unsigned long long v = i < nblk ? partials[i] : 0ull;
-    const unsigned long long incl = wave_incl_scan_u64(v, lane);
+  for (int base = 0; base < nblk; base += kScanThreads * kScanRun) {
+    const int i0 = base + tid * kScanRun;
+    unsigned long long v[kScanRun];
+    unsigned long long run = 0;
+#pragma unroll
+    for (int k = 0; k < kScanRun; ++k) {
+      v[k] = i0 + k < nblk ? partials[i0 + k] : 0ull;
+      run += v[k];
+    }
+    const unsigned long long incl = wave_incl_scan_u64(run, lane);
     if (lane == kWave - 1) s_wave[wid] = incl;
     __syncthreads();
     unsigned long long before = 0, total = 0;
@@ -32,7 +41,12 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_partials(
       if (w < wid) before += x;
       total += x;
     }
-    if (i < nblk) partials[i] = carry + before + incl - v;
+    unsigned long long at = carry + before + incl - run;
+#pragma unroll
+    for (int k = 0; k < kScanRun; ++k) {
+      if (i0 + k < nblk) partials[i0 + k] = at;
+      at += v[k];
+    }
     carry += total;
     __syncthreads();
   }

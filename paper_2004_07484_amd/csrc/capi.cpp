@@ -187,7 +187,6 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   q.off_trect = take(nn * 8);
   q.off_qdepth = take(nn * 4);
   q.off_rec = take(nn * 64);
-  q.off_gacc = take(nn * 16);
   q.off_partials = take(size_t(q.nblk_proj + 1) * 8);
   q.off_keysA = take(size_t(cap) * 4);
   q.off_valsA = take(size_t(cap) * 4);
@@ -213,6 +212,12 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   q.off_srec = take(size_t(cap) * 64);
   q.off_spay = take(size_t(cap) * size_t(C) * 4);
   q.off_mlist = take(size_t(q.T) * 4);
+  // the backward kernel instance keeps cm >= C channels, a power of two up to
+  // 32; wider payloads keep only dL/dc, dL/dR | dL/do in the record
+  int bcm = 1;
+  while (bcm < C && bcm < kBwdChannels) bcm *= 2;
+  q.bwd_ps4 = C <= kBwdChannels ? 1 + (bcm + 4) / 4 : 2;
+  q.off_sres = take(nn * size_t(q.bwd_ps4) * 16);
   q.total = o;
   *out = q;
   return PULSAR_OK;

@@ -18,7 +18,7 @@ constexpr int kWave = 64;
 constexpr int kProjectBlock = 256;           // spheres per projection block
 constexpr int kScanThreads = 1024;           // single-block scan of block sums
 constexpr int kSortThreads = 256;
-constexpr int kSortRounds = 8;
+constexpr int kSortRounds = 4;
 constexpr int kSortBlock = kSortThreads * kSortRounds;  // keys per sort block
 constexpr int kSortRadix = 256;              // 8-bit digits
 constexpr int kMaxK = 32;
@@ -91,7 +91,6 @@ struct Plan {
   int B, chunk, raster_grid;
   int tile_bits, depth_bits, passes, nblk_proj, nblk_sort;
   size_t off_status, off_counts, off_trect, off_qdepth, off_rec;
-  size_t off_gacc;
   size_t off_partials, off_keysA, off_valsA, off_keysB, off_valsB, off_hist, off_dtot;
   size_t off_ranges;
   // raster work items: per tile uint4 (first partial-state slot, chunks, 0, 0);
@@ -103,6 +102,10 @@ struct Plan {
   size_t off_srec, off_spay;
   size_t off_mlist;  // tiles with several work items, for the merge kernel
   size_t off_scenes, off_starts;  // scene table and its start arrays
+  // backward: one sum record per sphere, bwd_ps4 float4 each
+  // (dL/dc, dL/dR | dL/do, dL/df[cm], padding)
+  size_t off_sres;
+  int bwd_ps4;
   int64_t max_chunks, pcap;
   int nblk_tiles, fwd_cm, klist_slots, pstride;
   size_t total;

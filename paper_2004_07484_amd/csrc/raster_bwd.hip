@@ -5,24 +5,24 @@
 // among the K nearest, i.e. k is the K-th one or (t, k) < (t_K, k_K); nothing
 // else per pixel is stored, every intersection is recomputed here.
 //
-// K7 runs over the same chunks as the forward with the roles turned around:
-// lane l owns record l and walks the pixels of its rectangle inside the tile,
-// so each lane accumulates its own sphere's derivatives of Eq. 1 in registers
-// (camera-space dL/dc, dL/dR, dL/do, dL/df) and flushes them once per chunk
-// with float atomics (a sphere meets several chunks only when its rectangle
-// spans tiles or its tile list is split). The tile's G, F, L, thresholds and
-// rays are staged once per chunk in LDS. Blocks take work items round-robin,
-// full chunks first.
+// K7 (k_bwd_items) runs over the forward's work items: a block takes one
+// chunk of one tile's sorted list, stages the tile's 64 pixels in LDS and
+// gives each thread one record. The thread walks its sphere's rectangle
+// inside the tile and sums its sphere's derivatives of Eq. 1 (camera-space
+// dL/dc, dL/dR, dL/do, dL/df) in registers, then hands them to the sphere's
+// sum record in the workspace: one aligned record per sphere (ps4 float4:
+// dL/dc, dL/dR | dL/do, dL/df[cm]), so a sphere that touches one tile (it has
+// exactly one record in all work items) writes it whole with plain stores,
+// one scattered line instead of three partial ones; spheres that touch several
+// tiles add into their zeroed record with float atomics.
 //
-// K8 turns the camera-space accumulators into world-space position and
-// radius gradients; the background gradient is a plain reduction over all
-// pixels (k_bg_partial, k_reduce_bg).
+// K8 (k_finalize) runs in sphere order over those records (coalesced): it
+// turns the camera-space sums into world-space position and radius gradients
+// and writes every requested output contiguously. The background gradient is a
+// plain reduction over all pixels (k_bg_partial, k_reduce_bg).
 #include "hit_geometry.h"
 
 namespace pulsar {
-
-// Backward raster by (tile, sphere) pair instead of by tile work item.
-constexpr bool kPairBackward = false;
 
 struct BwdKernelArgs {
   SceneTable tab;
@@ -34,10 +34,11 @@ struct BwdKernelArgs {
   const float* aux;
   const float* grad_image;
   const float2* thr;
-  float* gacc;
-  float* grad_opacity;
-  float* grad_payload;
+  float4* sres;         // per-sphere sum records, ps4 float4 each
+  int ps4;
+  float* grad_payload;  // caller's output, added per hit by the wide path only
   int C;
+  int need_geo, need_op, need_pay;
 };
 
 // Gradient terms of one hit (pixel ray, sphere s) that belongs to the K
@@ -72,23 +73,22 @@ __device__ __forceinline__ HitGrad hit_grad(const PixelRay& ray, const SphereRec
   return g;
 }
 
-// CM >= C: channels kept in LDS. The (sphere, pixel) pairs of a batch (each
-// sphere's rectangle inside the tile) are flattened by a wave prefix sum over
-// rectangle sizes, so all 64 lanes stay busy whatever the sphere sizes; lane
-// j handles pair j + 64 i and adds its terms to its sphere's LDS accumulator.
+// K7 by work item: a block of kBwdWaves waves takes one work item (a chunk of
+// one tile's sorted list), so tile, scene and camera are uniform. The tile's
+// 64 pixels are staged once in LDS (ray, L, K-th nearest threshold, G and
+// G . F); then each thread owns one record of the chunk, walks the sphere's
+// rectangle inside the tile, recomputes each hit, keeps those among the
+// pixel's K nearest and adds their terms in registers. No global load sits
+// inside the pixel loop and no barrier inside the record loop. CM >= C.
+constexpr int kBwdWaves = 4;
+
 template <int CM>
-__global__ __launch_bounds__(kWave) void k_bwd_chunks(BwdKernelArgs A) {
-  constexpr int CQ = (CM + 3) / 4;
-  constexpr int NA = 6 + CM;  // dL/dc (3), dL/dR, dL/do, hit count, dL/df (CM)
+__global__ __launch_bounds__(kWave * kBwdWaves) void k_bwd_items(BwdKernelArgs A) {
   __shared__ TileRays s_ray;
   __shared__ float s_G[CM][kWave];
   __shared__ float s_L2[kWave], s_GF[kWave], s_tk[kWave];
   __shared__ uint32_t s_ik[kWave];
-  __shared__ float4 s_rec[kWave][4];
-  __shared__ float4 s_pay[kWave][CQ];
-  __shared__ uint32_t s_off[kWave], s_box[kWave], s_id[kWave];
-  __shared__ float s_acc[kWave][NA + 1];
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x;
   const int C = A.C;
   const uint32_t nchunks = A.status->nchunks;
   for (uint32_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
@@ -99,264 +99,113 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks(BwdKernelArgs A) {
     const SceneDev& sc = A.tab.scenes[ts.b];
     const CamDev cam = sc.cam;
     const BlendConst bc = sc.bc;
-    const int tx0 = ts.tx0, ty0 = ts.ty0;
-    // stage the tile's pixels (lane = pixel): ray, L, threshold, G and G . F
-    {
-      const int px = tx0 + (lane % kTileW), py = ty0 + (lane / kTileW);
+    // the thread's first record and payload row are requested before the
+    // staging below, so the two global round trips overlap
+    uint32_t j = beg + uint32_t(tid);
+    float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra, rc = ra, rd = ra;
+    float f[CM];
+#pragma unroll
+    for (int c = 0; c < CM; ++c) f[c] = 0.f;
+    auto load_record = [&](uint32_t jj) {
+      const float4* rp = A.srec + 4 * size_t(jj);
+      ra = rp[0];
+      rb = rp[1];
+      rc = rp[2];
+      rd = rp[3];
+      const float* fp = A.spay + size_t(jj) * size_t(C);
+#pragma unroll
+      for (int c = 0; c < CM; ++c) f[c] = c < C ? fp[c] : 0.f;
+    };
+    if (j < end) load_record(j);
+    __syncthreads();  // the previous item's readers are done with the LDS
+    if (tid < kWave) {
+      const int px = ts.tx0 + (tid % kTileW), py = ts.ty0 + (tid / kTileW);
       const bool inside = px < cam.W && py < cam.H;
       const size_t p =
           inside ? size_t(sc.pix_off) + size_t(py) * size_t(cam.W) + size_t(px) : 0;
-      __syncthreads();  // the previous chunk's LDS reads are done
-      store_ray(s_ray, lane, make_ray(cam, px, py));
-      s_L2[lane] = inside ? A.aux[p] * 1.4426950408889634f : 0.f;
+      store_ray(s_ray, tid, make_ray(cam, px, py));
+      s_L2[tid] = inside ? A.aux[p] * 1.4426950408889634f : 0.f;
       const float2 th = inside ? A.thr[p] : make_float2(-INFINITY, 0.f);
-      s_tk[lane] = th.x;
-      s_ik[lane] = __float_as_uint(th.y);
+      s_tk[tid] = th.x;
+      s_ik[tid] = __float_as_uint(th.y);
       float gf = 0.f;
 #pragma unroll
       for (int c = 0; c < CM; ++c) {
         const float g = (inside && c < C) ? A.grad_image[p * size_t(C) + c] : 0.f;
         const float f = (inside && c < C) ? A.image[p * size_t(C) + c] : 0.f;
-        s_G[c][lane] = g;
+        s_G[c][tid] = g;
         gf += g * f;
       }
-      s_GF[lane] = gf;
+      s_GF[tid] = gf;
     }
-    for (uint32_t b0 = beg; b0 < end; b0 += kWave) {
-      const uint32_t j = b0 + uint32_t(lane);
-      const bool valid = j < end;
-      uint32_t id = 0;
-      float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a, d = a;
-      bool single = false;
-      if (valid) {
-        const float4* rp = A.srec + 4 * size_t(j);
-        a = rp[0];
-        b = rp[1];
-        c = rp[2];
-        d = rp[3];
-        id = __float_as_uint(d.w) & ~kFirstChunk;
-        single = (__float_as_uint(d.w) & kFirstChunk) != 0u;
-      }
-      // the sphere's rectangle inside this tile, in tile coordinates
-      const uint32_t p0 = __float_as_uint(a.w), p1 = __float_as_uint(d.z);
-      const int xa = max(int(p0 & 0xffffu), tx0) - tx0;
-      const int xb = min(int(p1 & 0xffffu), tx0 + kTileW - 1) - tx0;
-      const int ya = max(int(p0 >> 16), ty0) - ty0;
-      const int yb = min(int(p1 >> 16), ty0 + kTileH - 1) - ty0;
-      const uint32_t w = valid ? uint32_t(xb - xa + 1) : 1u;
-      const uint32_t n = valid ? w * uint32_t(yb - ya + 1) : 0u;
-      const uint32_t incl = wave_incl_scan_u32(n, lane);
-      const uint32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
-      const uint32_t magic = (65536u + w - 1u) / w;  // i / w = (i * magic) >> 16 for i < 64
-      const float* fp = A.spay + size_t(valid ? j : 0u) * size_t(C);
-      __syncthreads();  // the previous batch is done with the LDS below
-      s_rec[lane][0] = a;
-      s_rec[lane][1] = b;
-      s_rec[lane][2] = c;
-      s_rec[lane][3] = d;
+    __syncthreads();
+    for (; j < end; j += kWave * kBwdWaves) {
+      if (j != beg + uint32_t(tid)) load_record(j);
+      const SphereRec s = unpack_rec(ra, rb, rc, rd);
+      const uint32_t id = __float_as_uint(rd.w) & ~kFirstChunk;
+      const bool single = (__float_as_uint(rd.w) & kFirstChunk) != 0u;
+      const uint32_t p1 = __float_as_uint(rd.z);
+      const int xa = max(s.x0, ts.tx0), xb = min(int(p1 & 0xffffu), ts.tx0 + kTileW - 1);
+      const int ya = max(s.y0, ts.ty0), yb = min(int(p1 >> 16), ts.ty0 + kTileH - 1);
+      float gf[CM];
 #pragma unroll
-      for (int q = 0; q < CQ; ++q) {
-        float v[4];
+      for (int c = 0; c < CM; ++c) gf[c] = 0.f;
+      float gcx = 0.f, gcy = 0.f, gcz = 0.f, gR = 0.f, go = 0.f;
+      uint32_t nh = 0;
+      for (int py = ya; py <= yb; ++py) {
+        for (int px = xa; px <= xb; ++px) {
+          const int pl = (py - ts.ty0) * kTileW + (px - ts.tx0);
+          const PixelRay ray = load_ray(s_ray, pl, px, py);
+          Hit h;
+          if (!exact_hit(ray, s, bc.zfar, h)) continue;
+          const float tk = s_tk[pl];
+          const uint32_t ik = s_ik[pl];
+          if (!(id == ik || h.t < tk || (h.t == tk && id < ik))) continue;
+          float hs = -s_GF[pl];  // G . (f_k - F)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = (valid && 4 * q + u < C) ? fp[4 * q + u] : 0.f;
-        s_pay[lane][q] = make_float4(v[0], v[1], v[2], v[3]);
-      }
-      s_id[lane] = id;
-      s_off[lane] = incl - n;
-      s_box[lane] = uint32_t(xa) | (uint32_t(ya) << 3) | (w << 6) | (magic << 10);
+          for (int c = 0; c < CM; ++c) hs += s_G[c][pl] * f[c];
+          const HitGrad g = hit_grad(ray, s, h, cam, bc, s_L2[pl], hs);
+          gcx += g.gcx;
+          gcy += g.gcy;
+          gcz += g.gcz;
+          gR += g.gR;
+          go += g.go;
 #pragma unroll
-      for (int v = 0; v < NA; ++v) s_acc[lane][v] = 0.f;
-      __syncthreads();
-      for (uint32_t pb = 0; pb < total; pb += kWave) {
-        const uint32_t pair = pb + uint32_t(lane);
-        if (pair >= total) continue;
-        // owner: the last sphere whose first pair is <= pair
-        int lo = 0, hi = kWave - 1;
-#pragma unroll
-        for (int step = 0; step < 6; ++step) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (s_off[mid] <= pair)
-            lo = mid;
-          else
-            hi = mid - 1;
-        }
-        const int r = lo;
-        const uint32_t i = pair - s_off[r], box = s_box[r];
-        const uint32_t bw = (box >> 6) & 15u, yy = (i * (box >> 10)) >> 16;
-        const int x = int(box & 7u) + int(i - yy * bw), y = int((box >> 3) & 7u) + int(yy);
-        const int pl = y * kTileW + x;
-        const SphereRec s = unpack_rec(s_rec[r][0], s_rec[r][1], s_rec[r][2], s_rec[r][3]);
-        const PixelRay ray = load_ray(s_ray, pl, tx0 + x, ty0 + y);
-        Hit h;
-        if (!exact_hit(ray, s, bc.zfar, h)) continue;
-        // among the pixel's K nearest hits?
-        const uint32_t sid = s_id[r];
-        const float tk = s_tk[pl];
-        const uint32_t ik = s_ik[pl];
-        if (!(sid == ik || h.t < tk || (h.t == tk && sid < ik))) continue;
-        float hs = -s_GF[pl];  // G . (f_k - F)
-#pragma unroll
-        for (int q = 0; q < CQ; ++q) {
-          const float4 f = s_pay[r][q];
-          const float fv[4] = {f.x, f.y, f.z, f.w};
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (4 * q + u < CM) hs += s_G[4 * q + u][pl] * fv[u];
-        }
-        const HitGrad g = hit_grad(ray, s, h, cam, bc, s_L2[pl], hs);
-        atomicAdd(&s_acc[r][0], g.gcx);
-        atomicAdd(&s_acc[r][1], g.gcy);
-        atomicAdd(&s_acc[r][2], g.gcz);
-        atomicAdd(&s_acc[r][3], g.gR);
-        atomicAdd(&s_acc[r][4], g.go);
-        atomicAdd(&s_acc[r][5], 1.f);
-#pragma unroll
-        for (int cc = 0; cc < CM; ++cc) atomicAdd(&s_acc[r][6 + cc], g.w * s_G[cc][pl]);
-      }
-      __syncthreads();
-      // A sphere that touches one tile appears in exactly one work item: it
-      // stores its sums (zeros included). Others add into zeroed sums.
-      if (valid && single) {
-        if (A.grad_payload) {
-          float* gp = A.grad_payload + size_t(id) * size_t(C);
-#pragma unroll
-          for (int cc = 0; cc < CM; ++cc)
-            if (cc < C) gp[cc] = s_acc[lane][6 + cc];
-        }
-        if (A.grad_opacity) A.grad_opacity[id] = s_acc[lane][4];
-        if (A.gacc)
-          reinterpret_cast<float4*>(A.gacc)[id] =
-              make_float4(s_acc[lane][0], s_acc[lane][1], s_acc[lane][2], s_acc[lane][3]);
-      } else if (valid && s_acc[lane][5] > 0.f) {
-        if (A.grad_payload) {
-          float* gp = A.grad_payload + size_t(id) * size_t(C);
-#pragma unroll
-          for (int cc = 0; cc < CM; ++cc)
-            if (cc < C) atomicAdd(gp + cc, s_acc[lane][6 + cc]);
-        }
-        if (A.grad_opacity) atomicAdd(A.grad_opacity + id, s_acc[lane][4]);
-        if (A.gacc) {
-          float* gg = A.gacc + size_t(id) * 4;
-          atomicAdd(gg + 0, s_acc[lane][0]);
-          atomicAdd(gg + 1, s_acc[lane][1]);
-          atomicAdd(gg + 2, s_acc[lane][2]);
-          atomicAdd(gg + 3, s_acc[lane][3]);
+          for (int c = 0; c < CM; ++c) gf[c] += g.w * s_G[c][pl];
+          ++nh;
         }
       }
-    }
-  }
-}
-
-// Pair-parallel variant of K7: lane = one (tile, sphere) pair of the sorted
-// lists. The lane walks its sphere's rectangle inside the tile, recomputes
-// each hit from the pixel's ray, keeps those among the pixel's K nearest and
-// adds their terms in registers; the pixel data (G, F, L, threshold) come
-// straight from memory, where neighbouring lanes (pairs of the same tile)
-// share them through the caches. No LDS, no barriers, so occupancy is set by
-// registers alone and global-memory latency overlaps across many waves.
-struct BwdPairArgs {
-  SceneTable tab;
-  const Status* status;
-  const uint32_t* keys;  // sorted pair keys: tile << depth_bits | quantised depth
-  int depth_bits;
-  const float4* srec;
-  const float* spay;
-  const float* image;
-  const float* aux;
-  const float* grad_image;
-  const float2* thr;
-  float* gacc;
-  float* grad_opacity;
-  float* grad_payload;
-  int C;
-};
-
-constexpr int kPairThreads = 256;
-
-template <int CM>
-__global__ __launch_bounds__(kPairThreads) void k_bwd_pairs(BwdPairArgs A) {
-  const uint32_t used = A.status->used;
-  const int C = A.C;
-  for (uint32_t j = blockIdx.x * kPairThreads + threadIdx.x; j < used;
-       j += gridDim.x * kPairThreads) {
-    const uint32_t tile = A.keys[j] >> A.depth_bits;
-    const TileScene ts = tile_scene(A.tab, tile);
-    const SceneDev& sc = A.tab.scenes[ts.b];
-    const CamDev cam = sc.cam;
-    const BlendConst bc = sc.bc;
-    const float4* rp = A.srec + 4 * size_t(j);
-    const float4 rd = rp[3];
-    const SphereRec s = unpack_rec(rp[0], rp[1], rp[2], rd);
-    const uint32_t id = __float_as_uint(rd.w) & ~kFirstChunk;
-    const bool single = (__float_as_uint(rd.w) & kFirstChunk) != 0u;
-    const uint32_t p1 = __float_as_uint(rd.z);
-    const int xa = max(s.x0, ts.tx0), xb = min(int(p1 & 0xffffu), ts.tx0 + kTileW - 1);
-    const int ya = max(s.y0, ts.ty0), yb = min(int(p1 >> 16), ts.ty0 + kTileH - 1);
-    float f[CM], gf[CM];
-    const float* fp = A.spay + size_t(j) * size_t(C);
+      // A sphere that touches one tile has exactly one record in all work
+      // items: it writes its whole sum record (zeros included). Others add
+      // into their zeroed record.
+      float4* sr = A.sres + size_t(id) * size_t(A.ps4);
+      constexpr int NT = (CM + 4) / 4;  // float4 holding dL/do, dL/df[CM]
+      if (single) {
+        sr[0] = make_float4(gcx, gcy, gcz, gR);
 #pragma unroll
-    for (int c = 0; c < CM; ++c) {
-      f[c] = c < C ? fp[c] : 0.f;
-      gf[c] = 0.f;
-    }
-    float gcx = 0.f, gcy = 0.f, gcz = 0.f, gR = 0.f, go = 0.f;
-    uint32_t nh = 0;
-    for (int py = ya; py <= yb; ++py) {
-      for (int px = xa; px <= xb; ++px) {
-        const PixelRay ray = make_ray(cam, px, py);
-        Hit h;
-        if (!exact_hit(ray, s, bc.zfar, h)) continue;
-        const size_t p = size_t(sc.pix_off) + size_t(py) * size_t(cam.W) + size_t(px);
-        const float2 th = A.thr[p];
-        const float tk = th.x;
-        const uint32_t ik = __float_as_uint(th.y);
-        if (!(id == ik || h.t < tk || (h.t == tk && id < ik))) continue;
-        float G[CM];
-        float hs = 0.f;  // G . (f_k - F)
-        const float* Gp = A.grad_image + p * size_t(C);
-        const float* Fp = A.image + p * size_t(C);
+        for (int q = 0; q < NT; ++q) {
+          float v[4];
 #pragma unroll
-        for (int c = 0; c < CM; ++c) {
-          G[c] = c < C ? Gp[c] : 0.f;
-          const float F = c < C ? Fp[c] : 0.f;
-          hs += G[c] * (f[c] - F);
+          for (int u = 0; u < 4; ++u) {
+            const int k = 4 * q + u;
+            v[u] = k == 0 ? go : (k - 1 < CM ? gf[k - 1 < CM ? k - 1 : 0] : 0.f);
+          }
+          sr[1 + q] = make_float4(v[0], v[1], v[2], v[3]);
         }
-        const HitGrad g = hit_grad(ray, s, h, cam, bc, A.aux[p] * 1.4426950408889634f, hs);
-        gcx += g.gcx;
-        gcy += g.gcy;
-        gcz += g.gcz;
-        gR += g.gR;
-        go += g.go;
+      } else if (nh > 0) {
+        float* f0 = reinterpret_cast<float*>(sr);
+        if (A.need_geo) {
+          atomicAdd(f0 + 0, gcx);
+          atomicAdd(f0 + 1, gcy);
+          atomicAdd(f0 + 2, gcz);
+          atomicAdd(f0 + 3, gR);
+        }
+        if (A.need_op) atomicAdd(f0 + 4, go);
+        if (A.need_pay) {
 #pragma unroll
-        for (int c = 0; c < CM; ++c) gf[c] += g.w * G[c];
-        ++nh;
-      }
-    }
-    // A sphere that touches one tile has exactly one pair: it stores its sums
-    // (zeros included). Others add into zeroed sums.
-    if (single) {
-      if (A.grad_payload) {
-        float* gp = A.grad_payload + size_t(id) * size_t(C);
-#pragma unroll
-        for (int c = 0; c < CM; ++c)
-          if (c < C) gp[c] = gf[c];
-      }
-      if (A.grad_opacity) A.grad_opacity[id] = go;
-      if (A.gacc) reinterpret_cast<float4*>(A.gacc)[id] = make_float4(gcx, gcy, gcz, gR);
-    } else if (nh > 0) {
-      if (A.grad_payload) {
-        float* gp = A.grad_payload + size_t(id) * size_t(C);
-#pragma unroll
-        for (int c = 0; c < CM; ++c)
-          if (c < C) atomicAdd(gp + c, gf[c]);
-      }
-      if (A.grad_opacity) atomicAdd(A.grad_opacity + id, go);
-      if (A.gacc) {
-        float* gg = A.gacc + size_t(id) * 4;
-        atomicAdd(gg + 0, gcx);
-        atomicAdd(gg + 1, gcy);
-        atomicAdd(gg + 2, gcz);
-        atomicAdd(gg + 3, gR);
+          for (int c = 0; c < CM; ++c)
+            if (c < C) atomicAdd(f0 + 5 + c, gf[c]);
+        }
       }
     }
   }
@@ -424,7 +273,7 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A) {
           const float w = o * e;
           float hs = 0.f;
           for (int c = 0; c < C; ++c) hs += Gp[c] * (fk[c] - Fp[c]);
-          if (A.grad_payload) {
+          if (A.need_pay) {
             float* g = A.grad_payload + size_t(id) * size_t(C);
             for (int c = 0; c < C; ++c) atomicAdd(g + c, w * Gp[c]);
           }
@@ -443,81 +292,110 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A) {
         }
       }
       if (any) {
-        if (A.grad_opacity) atomicAdd(A.grad_opacity + id, go);
-        if (A.gacc) {
-          float* g = A.gacc + size_t(id) * 4;
-          atomicAdd(g + 0, gcx);
-          atomicAdd(g + 1, gcy);
-          atomicAdd(g + 2, gcz);
-          atomicAdd(g + 3, gR);
+        float* f0 = reinterpret_cast<float*>(A.sres + size_t(id) * size_t(A.ps4));
+        if (A.need_geo) {
+          atomicAdd(f0 + 0, gcx);
+          atomicAdd(f0 + 1, gcy);
+          atomicAdd(f0 + 2, gcz);
+          atomicAdd(f0 + 3, gR);
         }
+        if (A.need_op) atomicAdd(f0 + 4, go);
       }
     }
   }
 }
 
-// Before K7: zero the sums of the spheres that K7 will add into (those that
-// touch several tiles, or every visible one when K7 adds per hit).
-__global__ void k_bwd_prep(int n, const uint32_t* __restrict__ counts, uint32_t min_count,
-                           int C, float4* __restrict__ gacc, float* __restrict__ grad_opacity,
-                           float* __restrict__ grad_payload) {
+// Before K7: zero the sum records K7 adds into: those of spheres that touch
+// several tiles (the narrow path writes one-tile spheres whole), or of every
+// visible sphere together with its row of the caller's payload gradient (the
+// wide path adds per hit).
+__global__ void k_bwd_prep(int n, const uint32_t* __restrict__ counts, int wide, int C, int ps4,
+                           float4* __restrict__ sres, float* __restrict__ grad_payload) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || counts[i] < min_count) return;
-  if (gacc) gacc[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (grad_opacity) grad_opacity[i] = 0.f;
-  if (grad_payload)
+  if (i >= n || counts[i] < (wide ? 1u : 2u)) return;
+  for (int q = 0; q < ps4; ++q) sres[size_t(i) * size_t(ps4) + q] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (wide && grad_payload)
     for (int c = 0; c < C; ++c) grad_payload[size_t(i) * size_t(C) + c] = 0.f;
 }
 
-// K8: camera-space (dL/dc, dL/dR) -> world-space position and radius
-// gradients; spheres that touch no tile get zeros everywhere.
-__global__ void k_finalize(int n, const uint32_t* __restrict__ counts,
-                           const float* __restrict__ pos, const float* __restrict__ radius,
-                           SceneTable tab, float min_radius_px, int C,
-                           const float4* __restrict__ gacc,
-                           float* __restrict__ grad_pos, float* __restrict__ grad_radius,
-                           float* __restrict__ grad_opacity, float* __restrict__ grad_payload) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (counts[i] == 0u) {
-    if (grad_pos) {
-      grad_pos[3 * i + 0] = 0.f;
-      grad_pos[3 * i + 1] = 0.f;
-      grad_pos[3 * i + 2] = 0.f;
+// K8: per sphere, in sphere order, kFinThreads spheres per block. The
+// camera-space sums come from the sphere's record (zero when it touches no
+// tile). Position and radius gradients follow c = R p + t and the min-size
+// clamp; opacity and payload gradients are copied out (narrow path; the wide
+// path added the payload gradient in place). Rows wider than one float
+// (positions, payloads) are staged per block and written as one contiguous
+// run, so every store instruction covers consecutive addresses.
+constexpr int kFinThreads = 256;
+__global__ __launch_bounds__(kFinThreads) void k_finalize(
+    int n, const uint32_t* __restrict__ counts, const float* __restrict__ pos,
+    const float* __restrict__ radius, SceneTable tab, float min_radius_px, int C, int wide,
+    const float4* __restrict__ sres, int ps4, float* __restrict__ grad_pos,
+    float* __restrict__ grad_radius, float* __restrict__ grad_opacity,
+    float* __restrict__ grad_payload) {
+  __shared__ uint32_t s_cnt[kFinThreads];
+  __shared__ float s_gp[3 * kFinThreads];
+  const int t = threadIdx.x;
+  const int i0 = blockIdx.x * kFinThreads;
+  const int nloc = min(kFinThreads, n - i0);
+  const int i = i0 + t;
+  const uint32_t count = t < nloc ? counts[i] : 0u;
+  s_cnt[t] = count;
+  if (t < nloc) {
+    float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+    float go = 0.f;
+    if (count != 0u) {
+      const float4* sr = sres + size_t(i) * size_t(ps4);
+      g = sr[0];
+      go = sr[1].x;
     }
-    if (grad_radius) grad_radius[i] = 0.f;
-    if (grad_opacity) grad_opacity[i] = 0.f;
-    if (grad_payload) {
-      float* row = grad_payload + size_t(i) * size_t(C);
-      if ((C & 3) == 0 && (reinterpret_cast<uintptr_t>(grad_payload) & 15u) == 0u) {
-        for (int c = 0; c < C; c += 4)
-          *reinterpret_cast<float4*>(row + c) = make_float4(0.f, 0.f, 0.f, 0.f);
-      } else {
-        for (int c = 0; c < C; ++c) row[c] = 0.f;
+    if (grad_opacity) grad_opacity[i] = go;
+    if (grad_pos || grad_radius) {
+      float gx = g.x, gy = g.y, gz = g.z, gR = g.w;
+      bool clamped = false;
+      const CamDev cam = tab.scenes[find_scene(tab.sph_start, tab.B, uint32_t(i))].cam;
+      if (count != 0u && min_radius_px > 0.f) {
+        const float px = pos[3 * i + 0], py = pos[3 * i + 1], pz = pos[3 * i + 2];
+        const double cz = double(cam.R[6]) * px + double(cam.R[7]) * py +
+                          double(cam.R[8]) * pz + double(cam.t[2]);
+        const double pitch = double(cam.s) / double(cam.W);
+        const double k = double(min_radius_px) * pitch / double(cam.f);
+        clamped = k * cz > double(radius[i]);
+        if (clamped) gz += float(double(gR) * k);  // R = k c_z depends on depth only
+      }
+      if (grad_radius) grad_radius[i] = clamped ? 0.f : gR;
+      // c = R p + t  =>  dL/dp = R^T dL/dc
+      s_gp[3 * t + 0] = cam.R[0] * gx + cam.R[3] * gy + cam.R[6] * gz;
+      s_gp[3 * t + 1] = cam.R[1] * gx + cam.R[4] * gy + cam.R[7] * gz;
+      s_gp[3 * t + 2] = cam.R[2] * gx + cam.R[5] * gy + cam.R[8] * gz;
+    }
+  }
+  __syncthreads();
+  if (grad_pos) {
+    float* dst = grad_pos + size_t(i0) * 3;
+    for (int f = t; f < 3 * nloc; f += kFinThreads) dst[f] = s_gp[f];
+  }
+  if (grad_payload && !wide) {
+    // element f of the block's [nloc, C] rows: sphere f / C, channel f % C
+    float* dst = grad_payload + size_t(i0) * size_t(C);
+    const int total = nloc * C;
+    const int dsph = kFinThreads / C, dch = kFinThreads % C;
+    int sph = t / C, ch = t % C;
+    for (int f = t; f < total; f += kFinThreads) {
+      float v = 0.f;
+      if (s_cnt[sph] != 0u)
+        v = reinterpret_cast<const float*>(sres + size_t(i0 + sph) * size_t(ps4))[5 + ch];
+      dst[f] = v;
+      sph += dsph;
+      ch += dch;
+      if (ch >= C) {
+        ch -= C;
+        ++sph;
       }
     }
-    return;
-  }
-  if (!gacc) return;
-  const CamDev cam = tab.scenes[find_scene(tab.sph_start, tab.B, uint32_t(i))].cam;
-  const float4 g = gacc[i];
-  float gx = g.x, gy = g.y, gz = g.z, gR = g.w;
-  bool clamped = false;
-  if (min_radius_px > 0.f) {
-    const float px = pos[3 * i + 0], py = pos[3 * i + 1], pz = pos[3 * i + 2];
-    const double cz = double(cam.R[6]) * px + double(cam.R[7]) * py + double(cam.R[8]) * pz +
-                      double(cam.t[2]);
-    const double pitch = double(cam.s) / double(cam.W);
-    const double k = double(min_radius_px) * pitch / double(cam.f);
-    clamped = k * cz > double(radius[i]);
-    if (clamped) gz += float(double(gR) * k);  // R = k c_z depends on depth only
-  }
-  if (grad_radius) grad_radius[i] = clamped ? 0.f : gR;
-  if (grad_pos) {
-    // c = R p + t  =>  dL/dp = R^T dL/dc
-    grad_pos[3 * i + 0] = cam.R[0] * gx + cam.R[3] * gy + cam.R[6] * gz;
-    grad_pos[3 * i + 1] = cam.R[1] * gx + cam.R[4] * gy + cam.R[7] * gz;
-    grad_pos[3 * i + 2] = cam.R[2] * gx + cam.R[5] * gy + cam.R[8] * gz;
+  } else if (grad_payload && wide) {
+    // the wide path added into the caller's rows; spheres without a tile get zeros
+    if (t < nloc && count == 0u)
+      for (int c = 0; c < C; ++c) grad_payload[size_t(i) * size_t(C) + c] = 0.f;
   }
 }
 
@@ -553,7 +431,16 @@ __global__ __launch_bounds__(kBgThreads) void k_bg_partial(SceneTable tab,
   if (tid < S) {
     const int total = np * C;
     int pix = tid / C;
-    for (int f = tid; f < total; f += S, pix += step) acc += s_w[pix] * gs[f];
+    int f = tid;
+    // eight independent loads in flight per round
+    for (; f + 7 * S < total; f += 8 * S, pix += 8 * step) {
+      float g[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) g[u] = gs[f + u * S];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += s_w[pix + u * step] * g[u];
+    }
+    for (; f < total; f += S, pix += step) acc += s_w[pix] * gs[f];
   }
   s_acc[tid] = acc;
   __syncthreads();
@@ -615,6 +502,7 @@ __global__ __launch_bounds__(256) void k_reduce_bg(SceneTable tab, const float* 
 
 hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_t stream) {
   const bool need_geo = a.grad_pos || a.grad_radius;
+  const bool wide = a.C > kBwdChannels;
   const SceneTable tab = scene_table(q, ws);
   BwdKernelArgs A;
   A.tab = tab;
@@ -626,73 +514,44 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
   A.aux = a.aux;
   A.grad_image = a.grad_image;
   A.thr = ws_ptr<float2>(ws, q.off_thr);
-  const uint32_t* counts = ws_ptr<uint32_t>(ws, q.off_counts);
-  A.gacc = need_geo ? ws_ptr<float>(ws, q.off_gacc) : nullptr;
-  A.grad_opacity = a.grad_opacity;
+  A.sres = ws_ptr<float4>(ws, q.off_sres);
+  A.ps4 = q.bwd_ps4;
   A.grad_payload = a.grad_payload;
   A.C = a.C;
+  A.need_geo = need_geo ? 1 : 0;
+  A.need_op = a.grad_opacity ? 1 : 0;
+  A.need_pay = a.grad_payload ? 1 : 0;
+  const uint32_t* counts = ws_ptr<uint32_t>(ws, q.off_counts);
   float* bgsum = ws_ptr<float>(ws, q.off_bgsum);
   stage_begin(PULSAR_STAGE_ZERO, stream);
-  // the narrow kernels store single-tile spheres directly, the wide one adds per hit
-  const uint32_t min_count = a.C <= kBwdChannels ? 2u : 1u;
   if (q.n > 0)
     hipLaunchKernelGGL(k_bwd_prep, dim3(unsigned((q.n + 255) / 256)), dim3(256), 0, stream,
-                       int(q.n), counts, min_count, a.C, reinterpret_cast<float4*>(A.gacc),
-                       a.grad_opacity, a.grad_payload);
+                       int(q.n), counts, wide ? 1 : 0, a.C, q.bwd_ps4, A.sres, a.grad_payload);
   stage_end(PULSAR_STAGE_ZERO, stream);
   stage_begin(PULSAR_STAGE_RASTER_BWD, stream);
-  const dim3 grid(unsigned(q.raster_grid)), block(kWave);
-  if (kPairBackward && a.C <= kBwdChannels) {
-    BwdPairArgs P;
-    P.tab = tab;
-    P.status = A.status;
-    P.keys = ws_ptr<uint32_t>(ws, sorted_in_a(q) ? q.off_keysA : q.off_keysB);
-    P.depth_bits = q.depth_bits;
-    P.srec = A.srec;
-    P.spay = A.spay;
-    P.image = A.image;
-    P.aux = A.aux;
-    P.grad_image = A.grad_image;
-    P.thr = A.thr;
-    P.gacc = A.gacc;
-    P.grad_opacity = A.grad_opacity;
-    P.grad_payload = A.grad_payload;
-    P.C = A.C;
-    long long pb = (q.cap + kPairThreads - 1) / kPairThreads;
-    if (pb > 8192) pb = 8192;
-    const dim3 pg{unsigned(pb), 1u, 1u}, pt{unsigned(kPairThreads), 1u, 1u};
-    if (a.C <= 1)
-      hipLaunchKernelGGL(k_bwd_pairs<1>, pg, pt, 0, stream, P);
-    else if (a.C <= 2)
-      hipLaunchKernelGGL(k_bwd_pairs<2>, pg, pt, 0, stream, P);
-    else if (a.C <= 4)
-      hipLaunchKernelGGL(k_bwd_pairs<4>, pg, pt, 0, stream, P);
-    else if (a.C <= 8)
-      hipLaunchKernelGGL(k_bwd_pairs<8>, pg, pt, 0, stream, P);
-    else if (a.C <= 16)
-      hipLaunchKernelGGL(k_bwd_pairs<16>, pg, pt, 0, stream, P);
-    else
-      hipLaunchKernelGGL(k_bwd_pairs<32>, pg, pt, 0, stream, P);
-  } else if (a.C <= 1)
-    hipLaunchKernelGGL(k_bwd_chunks<1>, grid, block, 0, stream, A);
+  const dim3 ig{unsigned(q.raster_grid), 1u, 1u}, it{unsigned(kWave * kBwdWaves), 1u, 1u};
+  if (a.C <= 1)
+    hipLaunchKernelGGL(k_bwd_items<1>, ig, it, 0, stream, A);
   else if (a.C <= 2)
-    hipLaunchKernelGGL(k_bwd_chunks<2>, grid, block, 0, stream, A);
+    hipLaunchKernelGGL(k_bwd_items<2>, ig, it, 0, stream, A);
   else if (a.C <= 4)
-    hipLaunchKernelGGL(k_bwd_chunks<4>, grid, block, 0, stream, A);
+    hipLaunchKernelGGL(k_bwd_items<4>, ig, it, 0, stream, A);
   else if (a.C <= 8)
-    hipLaunchKernelGGL(k_bwd_chunks<8>, grid, block, 0, stream, A);
+    hipLaunchKernelGGL(k_bwd_items<8>, ig, it, 0, stream, A);
   else if (a.C <= 16)
-    hipLaunchKernelGGL(k_bwd_chunks<16>, grid, block, 0, stream, A);
-  else if (a.C <= kBwdChannels)
-    hipLaunchKernelGGL(k_bwd_chunks<32>, grid, block, 0, stream, A);
+    hipLaunchKernelGGL(k_bwd_items<16>, ig, it, 0, stream, A);
+  else if (!wide)
+    hipLaunchKernelGGL(k_bwd_items<32>, ig, it, 0, stream, A);
   else
-    hipLaunchKernelGGL(k_bwd_chunks_wide, grid, block, 0, stream, A);
+    hipLaunchKernelGGL(k_bwd_chunks_wide, dim3(unsigned(q.raster_grid)), dim3(kWave), 0, stream,
+                       A);
   stage_end(PULSAR_STAGE_RASTER_BWD, stream);
   stage_begin(PULSAR_STAGE_FINALIZE, stream);
   if (q.n > 0)
-    hipLaunchKernelGGL(k_finalize, dim3(unsigned((q.n + 255) / 256)), dim3(256), 0, stream,
+    hipLaunchKernelGGL(k_finalize, dim3(unsigned((q.n + kFinThreads - 1) / kFinThreads)),
+                       dim3(kFinThreads), 0, stream,
                        int(q.n), counts, a.pos, a.radius, tab, a.min_radius_px, a.C,
-                       reinterpret_cast<const float4*>(A.gacc), a.grad_pos, a.grad_radius,
+                       wide ? 1 : 0, A.sres, q.bwd_ps4, a.grad_pos, a.grad_radius,
                        a.grad_opacity, a.grad_payload);
   if (a.grad_bg) {
     if (q.C <= kBgMaxC)
