@@ -90,6 +90,7 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
                       double(cam.t[2]);
     const double f = cam.f;
     const double pitch = double(cam.s) / double(cam.W);
+    const double inv_pitch = double(cam.W) / double(cam.s);
     const double sh = double(cam.s) * double(cam.H) / double(cam.W);
     double R = r;
     if (min_radius_px > 0.f) {
@@ -103,18 +104,18 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
       // The cone of rays through the sphere lies between the two planes through
       // the camera centre tangent to it; on the plane z = f they bound
       // x in f (c_x c_z -+ R sqrt(c_x^2 + c_z^2 - R^2)) / (c_z^2 - R^2), same for y.
-      const double den = cz * cz - R * R;
+      const double fden = f / (cz * cz - R * R);
       const double sx = R * sqrt(cx * cx + cz * cz - R * R);
       const double sy = R * sqrt(cy * cy + cz * cz - R * R);
-      const double xlo = f * (cx * cz - sx) / den, xhi = f * (cx * cz + sx) / den;
-      const double ylo = f * (cy * cz - sy) / den, yhi = f * (cy * cz + sy) / den;
+      const double xlo = (cx * cz - sx) * fden, xhi = (cx * cz + sx) * fden;
+      const double ylo = (cy * cz - sy) * fden, yhi = (cy * cz + sy) * fden;
       // pixel j has its centre at sensor x (j + 1/2) pitch - s/2; widen by a
       // small margin so rounding never drops a pixel the exact cone covers
       const double margin = 1e-3;
-      double jlo = ceil((xlo + 0.5 * double(cam.s)) / pitch - 0.5 - margin);
-      double jhi = floor((xhi + 0.5 * double(cam.s)) / pitch - 0.5 + margin);
-      double ilo = ceil((ylo + 0.5 * sh) / pitch - 0.5 - margin);
-      double ihi = floor((yhi + 0.5 * sh) / pitch - 0.5 + margin);
+      double jlo = ceil((xlo + 0.5 * double(cam.s)) * inv_pitch - 0.5 - margin);
+      double jhi = floor((xhi + 0.5 * double(cam.s)) * inv_pitch - 0.5 + margin);
+      double ilo = ceil((ylo + 0.5 * sh) * inv_pitch - 0.5 - margin);
+      double ihi = floor((yhi + 0.5 * sh) * inv_pitch - 0.5 + margin);
       jlo = fmax(jlo, 0.0);
       ilo = fmax(ilo, 0.0);
       jhi = fmin(jhi, double(cam.W - 1));
@@ -124,10 +125,12 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
         const int tx0 = j0 / kTileW, tx1 = j1 / kTileW, ty0 = i0 / kTileH, ty1 = i1 / kTileH;
         count = uint32_t(tx1 - tx0 + 1) * uint32_t(ty1 - ty0 + 1);
         trect[i] = make_ushort4(uint16_t(tx0), uint16_t(ty0), uint16_t(tx1), uint16_t(ty1));
-        const double Xc = (f * cx / cz + 0.5 * double(cam.s)) / pitch - 0.5;
-        const double Yc = (f * cy / cz + 0.5 * sh) / pitch - 0.5;
+        const double inv_cz = 1.0 / cz;
+        const double ax = cx * inv_cz, ay = cy * inv_cz;
+        const double Xc = (f * ax + 0.5 * double(cam.s)) * inv_pitch - 0.5;
+        const double Yc = (f * ay + 0.5 * sh) * inv_pitch - 0.5;
         const double kr = cz * pitch / R;
-        const double X = Xc - j0, Y = Yc - i0, kap = kr * kr, ax = cx / cz, ay = cy / cz;
+        const double X = Xc - j0, Y = Yc - i0, kap = kr * kr;
         const float Xh = float(X), Yh = float(Y), kh = float(kap), axh = float(ax),
                     ayh = float(ay);
         const uint32_t packed = uint32_t(j0) | (uint32_t(i0) << 16);

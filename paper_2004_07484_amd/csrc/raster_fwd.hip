@@ -25,31 +25,32 @@
 
 namespace pulsar {
 
+// A hit's place in the K-nearest order: (t, sphere index) as one 64-bit key.
+// Hit distances are positive, so their float bits order like unsigned
+// integers, and the index breaks ties.
+__device__ __forceinline__ uint64_t hit_key(float t, uint32_t id) {
+  return (uint64_t(__float_as_uint(t)) << 32) | uint64_t(id);
+}
+constexpr uint64_t kKeyNone = ~uint64_t(0);  // empty slot (no hit)
+
+// K-list in the last K of KM slots, ascending; the leading KM - K slots hold
+// key 0 and never move, so the K-th nearest is always slot KM - 1. Insertion
+// compares the new key with every slot at once and shifts the larger ones up.
 template <int KM>
-__device__ __forceinline__ void klist_insert(float (&kt)[KM], uint32_t (&kid)[KM], float t,
-                                             uint32_t id) {
-  if (!(t < kt[KM - 1] || (t == kt[KM - 1] && id < kid[KM - 1]))) return;
+__device__ __forceinline__ void klist_insert(uint64_t (&kk)[KM], uint64_t key) {
+  if (!(key < kk[KM - 1])) return;
+  bool lt[KM];
 #pragma unroll
-  for (int i = 0; i < KM; ++i) {
-    const bool lt = t < kt[i] || (t == kt[i] && id < kid[i]);
-    const float tt = kt[i];
-    const uint32_t ti = kid[i];
-    kt[i] = lt ? t : tt;
-    kid[i] = lt ? id : ti;
-    t = lt ? tt : t;
-    id = lt ? ti : id;
-  }
+  for (int i = 0; i < KM; ++i) lt[i] = key < kk[i];
+#pragma unroll
+  for (int i = KM - 1; i > 0; --i) kk[i] = lt[i] ? (lt[i - 1] ? kk[i - 1] : key) : kk[i];
+  kk[0] = lt[0] ? key : kk[0];
 }
 
-// K-list of the last K of KM slots, ascending; leading slots hold -inf and
-// never move, so the K-th nearest is always slot KM - 1.
 template <int KM>
-__device__ __forceinline__ void klist_init(float (&kt)[KM], uint32_t (&kid)[KM], int K) {
+__device__ __forceinline__ void klist_init(uint64_t (&kk)[KM], int K) {
 #pragma unroll
-  for (int i = 0; i < KM; ++i) {
-    kt[i] = i < KM - K ? -INFINITY : INFINITY;
-    kid[i] = 0xffffffffu;
-  }
+  for (int i = 0; i < KM; ++i) kk[i] = i < KM - K ? uint64_t(0) : kKeyNone;
 }
 
 struct FwdKernelArgs {
@@ -75,7 +76,7 @@ template <int CM, int KM>
 __device__ __forceinline__ void write_pixel(const FwdKernelArgs& A, const CamDev& cam,
                                             unsigned long long pix_off, int px, int py,
                                             float m2, float D, const float (&N)[CM],
-                                            const float (&kt)[KM], const uint32_t (&kid)[KM]) {
+                                            const uint64_t (&kk)[KM]) {
   if (px >= cam.W || py >= cam.H) return;
   const size_t p = size_t(pix_off) + size_t(py) * size_t(cam.W) + size_t(px);
   const float invD = 1.f / D;
@@ -83,7 +84,13 @@ __device__ __forceinline__ void write_pixel(const FwdKernelArgs& A, const CamDev
   for (int c = 0; c < CM; ++c)
     if (c < A.cn) A.image[p * size_t(A.C) + A.c0 + c] = N[c] * invD;
   if (A.c0 == 0 && A.aux) A.aux[p] = (m2 + fast_log2(D)) * 0.69314718055994531f;
-  if (A.track) A.thr[p] = make_float2(kt[KM - 1], __uint_as_float(kid[KM - 1]));
+  if (A.track) {
+    // the K-th nearest hit, or (+inf, none) when the pixel has fewer than K
+    const uint64_t k = kk[KM - 1];
+    A.thr[p] = k == kKeyNone ? make_float2(INFINITY, __uint_as_float(0xffffffffu))
+                             : make_float2(__uint_as_float(uint32_t(k >> 32)),
+                                           __uint_as_float(uint32_t(k)));
+  }
 }
 
 template <int CM, int KM>
@@ -119,9 +126,8 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A) {
     float N[CM];
 #pragma unroll
     for (int c = 0; c < CM; ++c) N[c] = (first && c < A.cn) ? bg[A.c0 + c] : 0.f;
-    float kt[KM];
-    uint32_t kid[KM];
-    klist_init(kt, kid, A.K);
+    uint64_t kk[KM];
+    klist_init(kk, A.K);
 
     for (uint32_t b0 = beg; b0 < end; b0 += kWave) {
       const uint32_t j = b0 + uint32_t(lane);
@@ -223,14 +229,14 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A) {
               for (int u = 0; u < 4; ++u)
                 if (4 * q + u < CM) N[4 * q + u] += wgt * fv[u];
             }
-            if (A.track) klist_insert(kt, kid, h.t, s_id[k]);
+            if (A.track) klist_insert(kk, hit_key(h.t, s_id[k]));
           }
         }
       }
     }
 
     if (slot == kNoSlot) {
-      write_pixel(A, cam, sc.pix_off, ray.px, ray.py, m2, D, N, kt, kid);
+      write_pixel(A, cam, sc.pix_off, ray.px, ray.py, m2, D, N, kk);
     } else {
       if ((long long)slot < A.pcap) {
         float* ps = A.pstate + size_t(slot) * size_t(kWave) * size_t(A.pstride);
@@ -242,8 +248,8 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A) {
         if (A.track) {
 #pragma unroll
           for (int i = 0; i < KM; ++i) {
-            ps[(A.kfield + i) * kWave + lane] = kt[i];
-            ps[(A.kfield + KM + i) * kWave + lane] = __uint_as_float(kid[i]);
+            ps[(A.kfield + i) * kWave + lane] = __uint_as_float(uint32_t(kk[i] >> 32));
+            ps[(A.kfield + KM + i) * kWave + lane] = __uint_as_float(uint32_t(kk[i]));
           }
         }
       }
@@ -269,9 +275,8 @@ __global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(FwdKernelArgs
     const uint4 ti = A.tinfo[tile];
     if ((long long)ti.x + ti.y > A.pcap) continue;  // capacity exceeded (reported)
     float m2 = -INFINITY, D = 0.f, N[CM];
-    float kt[KM];
-    uint32_t kid[KM];
-    klist_init(kt, kid, A.K);
+    uint64_t kk[KM];
+    klist_init(kk, A.K);
 #pragma unroll
     for (int c = 0; c < CM; ++c) N[c] = 0.f;
     float cur[NF], nxt[NF];
@@ -281,7 +286,7 @@ __global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(FwdKernelArgs
       for (int f = 0; f < 2 + CM; ++f) dst[f] = (f < 2 + A.cn) ? ps[f * kWave + lane] : 0.f;
 #pragma unroll
       for (int f = 0; f < 2 * KM; ++f)
-        dst[2 + CM + f] = A.track ? ps[(A.kfield + f) * kWave + lane] : INFINITY;
+        dst[2 + CM + f] = A.track ? ps[(A.kfield + f) * kWave + lane] : 0.f;
     };
     auto fold = [&](const float (&st)[NF]) {
       const float mm = fmaxf(m2, st[0]);
@@ -295,9 +300,9 @@ __global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(FwdKernelArgs
       if (A.track) {
 #pragma unroll
         for (int i = 0; i < KM; ++i) {
-          const float t = st[2 + CM + i];
-          if (t < INFINITY && t > -INFINITY)
-            klist_insert(kt, kid, t, __float_as_uint(st[2 + CM + KM + i]));
+          const uint64_t key = (uint64_t(__float_as_uint(st[2 + CM + i])) << 32) |
+                               uint64_t(__float_as_uint(st[2 + CM + KM + i]));
+          if (key != 0u && key != kKeyNone) klist_insert(kk, key);
         }
       }
     };
@@ -317,8 +322,8 @@ __global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(FwdKernelArgs
       for (int c = 0; c < CM; ++c) s_state[wv - 1][2 + c][lane] = N[c];
 #pragma unroll
       for (int i = 0; i < KM; ++i) {
-        s_state[wv - 1][2 + CM + i][lane] = kt[i];
-        s_state[wv - 1][2 + CM + KM + i][lane] = __uint_as_float(kid[i]);
+        s_state[wv - 1][2 + CM + i][lane] = __uint_as_float(uint32_t(kk[i] >> 32));
+        s_state[wv - 1][2 + CM + KM + i][lane] = __uint_as_float(uint32_t(kk[i]));
       }
     }
     __syncthreads();
@@ -332,13 +337,13 @@ __global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(FwdKernelArgs
       const TileScene ts = tile_scene(A.tab, uint32_t(tile));
       const SceneDev& sc = A.tab.scenes[ts.b];
       write_pixel(A, sc.cam, sc.pix_off, ts.tx0 + lane % kTileW, ts.ty0 + lane / kTileW, m2, D,
-                  N, kt, kid);
+                  N, kk);
     }
   }
 }
 
-// Pixels of tiles without any sphere: F = background, L = eps / gamma, and
-// no hit for the gradient threshold. One wave per tile; the image is written
+// Pixels of tiles without any sphere: F = background and L = eps / gamma.
+// One wave per tile; the image is written
 // row by row as contiguous runs of (pixels in the row) x C floats, so each
 // store instruction covers consecutive addresses.
 template <int CM>
@@ -365,7 +370,7 @@ __global__ __launch_bounds__(256) void k_fwd_background(FwdKernelArgs A, uint32_
   if (px >= W || py >= H) return;
   const size_t p = size_t(sc.pix_off) + size_t(py) * size_t(W) + size_t(px);
   if (A.c0 == 0 && A.aux) A.aux[p] = A.eps2 * 0.69314718055994531f;
-  if (A.track) A.thr[p] = make_float2(INFINITY, __uint_as_float(0xffffffffu));
+  // no gradient threshold: the backward only visits tiles that have work items
 }
 
 void launch_upload_scenes(const Plan& q, const std::vector<SceneDev>& sc, char* ws,
