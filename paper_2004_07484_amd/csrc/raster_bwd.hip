@@ -11,7 +11,7 @@
 // inside the tile and sums its sphere's derivatives of Eq. 1 (camera-space
 // dL/dc, dL/dR, dL/do, dL/df) in registers, then hands them to the sphere's
 // sum record in the workspace: one aligned record per sphere (ps4 float4:
-// dL/dc, dL/dR | dL/do, dL/df[cm]), so a sphere that touches one tile (it has
+// dL/dc, dL/dR | dL/df[cm] | dL/do), so a sphere that touches one tile (it has
 // exactly one record in all work items) writes it whole with plain stores,
 // one scattered line instead of three partial ones; spheres that touch several
 // tiles add into their zeroed record with float atomics.
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(kWave * kBwdWaves) void k_bwd_items(BwdKernelArgs A
       // items: it writes its whole sum record (zeros included). Others add
       // into their zeroed record.
       float4* sr = A.sres + size_t(id) * size_t(A.ps4);
-      constexpr int NT = (CM + 4) / 4;  // float4 holding dL/do, dL/df[CM]
+      constexpr int NT = (CM + 4) / 4;  // float4 holding dL/df[CM], then dL/do
       if (single) {
         sr[0] = make_float4(gcx, gcy, gcz, gR);
 #pragma unroll
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(kWave * kBwdWaves) void k_bwd_items(BwdKernelArgs A
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int k = 4 * q + u;
-            v[u] = k == 0 ? go : (k - 1 < CM ? gf[k - 1 < CM ? k - 1 : 0] : 0.f);
+            v[u] = k < CM ? gf[k < CM ? k : 0] : (k == CM ? go : 0.f);
           }
           sr[1 + q] = make_float4(v[0], v[1], v[2], v[3]);
         }
@@ -200,12 +200,12 @@ __global__ __launch_bounds__(kWave * kBwdWaves) void k_bwd_items(BwdKernelArgs A
           atomicAdd(f0 + 2, gcz);
           atomicAdd(f0 + 3, gR);
         }
-        if (A.need_op) atomicAdd(f0 + 4, go);
         if (A.need_pay) {
 #pragma unroll
           for (int c = 0; c < CM; ++c)
-            if (c < C) atomicAdd(f0 + 5 + c, gf[c]);
+            if (c < C) atomicAdd(f0 + 4 + c, gf[c]);
         }
+        if (A.need_op) atomicAdd(f0 + 4 + CM, go);
       }
     }
   }
@@ -329,7 +329,7 @@ constexpr int kFinThreads = 256;
 __global__ __launch_bounds__(kFinThreads) void k_finalize(
     int n, const uint32_t* __restrict__ counts, const float* __restrict__ pos,
     const float* __restrict__ radius, SceneTable tab, float min_radius_px, int C, int wide,
-    const float4* __restrict__ sres, int ps4, float* __restrict__ grad_pos,
+    const float4* __restrict__ sres, int ps4, int go_off, float* __restrict__ grad_pos,
     float* __restrict__ grad_radius, float* __restrict__ grad_opacity,
     float* __restrict__ grad_payload) {
   __shared__ uint32_t s_cnt[kFinThreads];
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
     if (count != 0u) {
       const float4* sr = sres + size_t(i) * size_t(ps4);
       g = sr[0];
-      go = sr[1].x;
+      go = reinterpret_cast<const float*>(sr)[go_off];
     }
     if (grad_opacity) grad_opacity[i] = go;
     if (grad_pos || grad_radius) {
@@ -374,7 +374,26 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
     float* dst = grad_pos + size_t(i0) * 3;
     for (int f = t; f < 3 * nloc; f += kFinThreads) dst[f] = s_gp[f];
   }
-  if (grad_payload && !wide) {
+  if (grad_payload && !wide && (C & 3) == 0 &&
+      (reinterpret_cast<uintptr_t>(grad_payload) & 15u) == 0u) {
+    // float4 unit f of the block's [nloc, C] rows: sphere f / (C/4), group f % (C/4)
+    float4* dst = reinterpret_cast<float4*>(grad_payload + size_t(i0) * size_t(C));
+    const int cq = C / 4;
+    const int total = nloc * cq;
+    const int dsph = kFinThreads / cq, dq = kFinThreads % cq;
+    int sph = t / cq, q = t % cq;
+    for (int f = t; f < total; f += kFinThreads) {
+      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (s_cnt[sph] != 0u) v = sres[size_t(i0 + sph) * size_t(ps4) + 1 + q];
+      dst[f] = v;
+      sph += dsph;
+      q += dq;
+      if (q >= cq) {
+        q -= cq;
+        ++sph;
+      }
+    }
+  } else if (grad_payload && !wide) {
     // element f of the block's [nloc, C] rows: sphere f / C, channel f % C
     float* dst = grad_payload + size_t(i0) * size_t(C);
     const int total = nloc * C;
@@ -383,7 +402,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
     for (int f = t; f < total; f += kFinThreads) {
       float v = 0.f;
       if (s_cnt[sph] != 0u)
-        v = reinterpret_cast<const float*>(sres + size_t(i0 + sph) * size_t(ps4))[5 + ch];
+        v = reinterpret_cast<const float*>(sres + size_t(i0 + sph) * size_t(ps4))[4 + ch];
       dst[f] = v;
       sph += dsph;
       ch += dch;
@@ -414,6 +433,7 @@ __global__ __launch_bounds__(kBgThreads) void k_bg_partial(SceneTable tab,
                                                            float* __restrict__ bgsum) {
   __shared__ float s_w[kBgBlockPixels];
   __shared__ float s_acc[kBgThreads];
+  __shared__ float s_acc4_buf[4 * kBgThreads];
   const int tid = threadIdx.x;
   const int b = find_scene(tab.blk_start, tab.B, blockIdx.x);
   const SceneDev& sc = tab.scenes[b];
@@ -425,6 +445,65 @@ __global__ __launch_bounds__(kBgThreads) void k_bg_partial(SceneTable tab,
   for (int k = tid; k < kBgBlockPixels; k += kBgThreads)
     s_w[k] = k < np ? fast_exp2(eps2 - auxs[k] * 1.4426950408889634f) : 0.f;
   __syncthreads();
+  const int cq = C / 4;
+  if ((C & 3) == 0 && cq <= kWave && (cq & (cq - 1)) == 0 &&
+      (reinterpret_cast<uintptr_t>(gs) & 15u) == 0u) {
+    // the same in float4 units: thread t always sees channels 4 (t mod C/4) ..
+    // 4 (t mod C/4) + 3; C/4 is a power of two, so lanes of one channel group
+    // stay together under xor shuffles by multiples of C/4
+    const int S4 = (kBgThreads / cq) * cq;
+    const int step4 = S4 / cq;
+    float4 acc4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (tid < S4) {
+      const float4* g4 = reinterpret_cast<const float4*>(gs);
+      const int total4 = np * cq;
+      int pix = tid / cq;
+      int f = tid;
+      for (; f + 3 * S4 < total4; f += 4 * S4, pix += 4 * step4) {
+        float4 g[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) g[u] = g4[f + u * S4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float w = s_w[pix + u * step4];
+          acc4.x += w * g[u].x;
+          acc4.y += w * g[u].y;
+          acc4.z += w * g[u].z;
+          acc4.w += w * g[u].w;
+        }
+      }
+      for (; f < total4; f += S4, pix += step4) {
+        const float4 g = g4[f];
+        const float w = s_w[pix];
+        acc4.x += w * g.x;
+        acc4.y += w * g.y;
+        acc4.z += w * g.z;
+        acc4.w += w * g.w;
+      }
+    }
+    for (int off = kWave / 2; off >= cq; off >>= 1) {
+      acc4.x += __shfl_xor(acc4.x, off, kWave);
+      acc4.y += __shfl_xor(acc4.y, off, kWave);
+      acc4.z += __shfl_xor(acc4.z, off, kWave);
+      acc4.w += __shfl_xor(acc4.w, off, kWave);
+    }
+    // lane l < C/4 of each wave now holds its wave's sums for group l
+    const int lane = tid % kWave, wv = tid / kWave;
+    if (lane < cq) {
+      float* dst = s_acc4_buf + (wv * cq + lane) * 4;
+      dst[0] = acc4.x;
+      dst[1] = acc4.y;
+      dst[2] = acc4.z;
+      dst[3] = acc4.w;
+    }
+    __syncthreads();
+    if (tid < C) {
+      float t = 0.f;
+      for (int w = 0; w < kBgThreads / kWave; ++w) t += s_acc4_buf[(w * cq + tid / 4) * 4 + (tid & 3)];
+      bgsum[size_t(blockIdx.x) * size_t(C) + tid] = t;
+    }
+    return;
+  }
   const int S = (kBgThreads / C) * C;  // threads in use, a multiple of C
   const int step = S / C;               // pixels advanced per round
   float acc = 0.f;
@@ -444,9 +523,20 @@ __global__ __launch_bounds__(kBgThreads) void k_bg_partial(SceneTable tab,
   }
   s_acc[tid] = acc;
   __syncthreads();
+  // two-stage per-channel sum of the S partials: `split` runs per channel
+  // (split * C <= kBgThreads), then one thread per channel adds its runs
+  const int split = min(16, kBgThreads / C);
+  float part = 0.f;
+  if (tid < C * split) {
+    const int c = tid % C, r = tid / C;
+    for (int k = c + C * r; k < S; k += C * split) part += s_acc[k];
+  }
+  __syncthreads();
+  if (tid < C * split) s_acc[tid] = part;
+  __syncthreads();
   if (tid < C) {
     float t = 0.f;
-    for (int k = tid; k < S; k += C) t += s_acc[k];
+    for (int r = 0; r < split; ++r) t += s_acc[tid + C * r];
     bgsum[size_t(blockIdx.x) * size_t(C) + tid] = t;
   }
 }
@@ -551,7 +641,7 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
     hipLaunchKernelGGL(k_finalize, dim3(unsigned((q.n + kFinThreads - 1) / kFinThreads)),
                        dim3(kFinThreads), 0, stream,
                        int(q.n), counts, a.pos, a.radius, tab, a.min_radius_px, a.C,
-                       wide ? 1 : 0, A.sres, q.bwd_ps4, a.grad_pos, a.grad_radius,
+                       wide ? 1 : 0, A.sres, q.bwd_ps4, q.bwd_go, a.grad_pos, a.grad_radius,
                        a.grad_opacity, a.grad_payload);
   if (a.grad_bg) {
     if (q.C <= kBgMaxC)

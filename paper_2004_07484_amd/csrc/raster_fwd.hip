@@ -69,6 +69,7 @@ struct FwdKernelArgs {
   long long pcap;
   int C, c0, cn, K, pstride, kfield;  // kfield: first K-list field of a partial state
   int track;                          // keep K-lists (first channel pass with aux)
+  int vec4;                           // one channel pass, C % 4 == 0, 16-byte aligned image
   float eps2;                         // background exponent (base 2)
 };
 
@@ -358,12 +359,27 @@ __global__ __launch_bounds__(256) void k_fwd_background(FwdKernelArgs A, uint32_
   const int nrows = min(kTileH, H - ts.ty0);
   const float* bg = A.bg + size_t(ts.b) * size_t(C);
   const int run = npx * C;
-  for (int r = 0; r < nrows; ++r) {
-    float* row = A.image + (size_t(sc.pix_off) + size_t(ts.ty0 + r) * size_t(W) +
-                            size_t(ts.tx0)) * size_t(C);
-    for (int f = lane; f < run; f += kWave) {
-      const int ch = f % C;
-      if (ch >= A.c0 && ch < A.c0 + A.cn) row[f] = bg[ch];
+  if (A.vec4) {
+    // whole channel range in this pass and 16-byte aligned rows: float4 units,
+    // so each store instruction writes four rows of the tile at once
+    const int run4 = run / 4, cq = C / 4;
+    const int units = nrows * run4;
+    for (int u = lane; u < units; u += kWave) {
+      const int r = u / run4, k = u - r * run4;
+      const int q = k % cq;
+      float4* row = reinterpret_cast<float4*>(
+          A.image + (size_t(sc.pix_off) + size_t(ts.ty0 + r) * size_t(W) + size_t(ts.tx0)) *
+                        size_t(C));
+      row[k] = make_float4(bg[4 * q], bg[4 * q + 1], bg[4 * q + 2], bg[4 * q + 3]);
+    }
+  } else {
+    for (int r = 0; r < nrows; ++r) {
+      float* row = A.image + (size_t(sc.pix_off) + size_t(ts.ty0 + r) * size_t(W) +
+                              size_t(ts.tx0)) * size_t(C);
+      for (int f = lane; f < run; f += kWave) {
+        const int ch = f % C;
+        if (ch >= A.c0 && ch < A.c0 + A.cn) row[f] = bg[ch];
+      }
     }
   }
   const int px = ts.tx0 + lane % kTileW, py = ts.ty0 + lane / kTileW;
@@ -441,6 +457,10 @@ hipError_t launch_forward(const Plan& q, const std::vector<SceneDev>& scenes, co
     A.c0 = c0;
     A.cn = a.C - c0 < kFwdChannels ? a.C - c0 : kFwdChannels;
     A.track = (c0 == 0 && a.aux != nullptr) ? 1 : 0;
+    A.vec4 = (a.C <= kFwdChannels && (a.C & 3) == 0 &&
+              (reinterpret_cast<uintptr_t>(a.image) & 15u) == 0u)
+                 ? 1
+                 : 0;
     if (q.klist_slots <= 4)
       dispatch_cm<4>(q, A, stream);
     else if (q.klist_slots <= 8)
