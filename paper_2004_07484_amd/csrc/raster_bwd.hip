@@ -19,7 +19,8 @@
 // K8 (k_finalize) runs in sphere order over those records (coalesced): it
 // turns the camera-space sums into world-space position and radius gradients
 // and writes every requested output contiguously. The background gradient is a
-// plain reduction over all pixels (k_bg_partial, k_reduce_bg).
+// plain reduction over all pixels: block sums at the end of K7 (k_bg_partial
+// for the wide path), summed per scene by extra blocks of K8.
 #include "hit_geometry.h"
 
 namespace pulsar {
@@ -39,7 +40,16 @@ struct BwdKernelArgs {
   float* grad_payload;  // caller's output, added per hit by the wide path only
   int C;
   int need_geo, need_op, need_pay;
+  float* bgsum;       // background-gradient block sums, or null
+  uint32_t nbgblk;
+  float eps2;
 };
+
+constexpr int kBgThreads = 256;
+constexpr int kBgMaxC = kBgThreads;  // wider images use k_bg_partial_wide
+__device__ void bg_partial_block(const SceneTable& tab, const float* __restrict__ aux,
+                                 const float* __restrict__ grad_image, int C, float eps2,
+                                 float* __restrict__ bgsum, uint32_t blk);
 
 // Gradient terms of one hit (pixel ray, sphere s) that belongs to the K
 // nearest: derivatives of Eq. 1 through t (depth), 1 - q/R (distance), o and f.
@@ -209,6 +219,11 @@ __global__ __launch_bounds__(kWave * kBwdWaves) void k_bwd_items(BwdKernelArgs A
       }
     }
   }
+  // then the background-gradient block sums on the same grid (their reads
+  // overlap the uneven end of the work-item loop)
+  if (A.bgsum)
+    for (uint32_t blk = blockIdx.x; blk < A.nbgblk; blk += gridDim.x)
+      bg_partial_block(A.tab, A.aux, A.grad_image, C, A.eps2, A.bgsum, blk);
 }
 
 // Channels beyond the register budget: same walk, the pixel terms read from
@@ -331,10 +346,30 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
     const float* __restrict__ radius, SceneTable tab, float min_radius_px, int C, int wide,
     const float4* __restrict__ sres, int ps4, int go_off, float* __restrict__ grad_pos,
     float* __restrict__ grad_radius, float* __restrict__ grad_opacity,
-    float* __restrict__ grad_payload) {
+    float* __restrict__ grad_payload, uint32_t nfin, const float* __restrict__ bgsum,
+    float* __restrict__ grad_bg) {
   __shared__ uint32_t s_cnt[kFinThreads];
   __shared__ float s_gp[3 * kFinThreads];
   const int t = threadIdx.x;
+  if (blockIdx.x >= nfin) {
+    // K8b: grad_bg[b][c] = sum of scene b's background block sums, one block
+    // per (scene, channel) after the sphere blocks
+    const uint32_t k = blockIdx.x - nfin;
+    const int c = int(k % uint32_t(C)), b = int(k / uint32_t(C));
+    const uint32_t k0 = tab.blk_start[b], k1 = tab.blk_start[b + 1];
+    float acc = 0.f;
+    for (uint32_t j = k0 + t; j < k1; j += kFinThreads) acc += bgsum[size_t(j) * size_t(C) + c];
+    acc = wave_sum(acc);
+    __shared__ float s_red[kFinThreads / kWave];
+    if ((t & (kWave - 1)) == 0) s_red[t / kWave] = acc;
+    __syncthreads();
+    if (t == 0) {
+      float tsum = 0.f;
+      for (int w = 0; w < kFinThreads / kWave; ++w) tsum += s_red[w];
+      grad_bg[size_t(b) * size_t(C) + c] = tsum;
+    }
+    return;
+  }
   const int i0 = blockIdx.x * kFinThreads;
   const int nloc = min(kFinThreads, n - i0);
   const int i = i0 + t;
@@ -424,21 +459,21 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
 // the block reads its G rows as one flat run of floats: thread t takes
 // elements t, t + S, t + 2S, ... with S the largest multiple of C <= 256, so
 // its channel is always t % C and consecutive threads read consecutive floats.
-constexpr int kBgThreads = 256;
-constexpr int kBgMaxC = kBgThreads;  // wider images use k_bg_partial_wide
-__global__ __launch_bounds__(kBgThreads) void k_bg_partial(SceneTable tab,
-                                                           const float* __restrict__ aux,
-                                                           const float* __restrict__ grad_image,
-                                                           int C, float eps2,
-                                                           float* __restrict__ bgsum) {
+// The block sum for background block `blk`, by a whole block of kBgThreads
+// threads (called uniformly; it starts with a barrier so a block can run it
+// for several blocks in a row).
+__device__ void bg_partial_block(const SceneTable& tab, const float* __restrict__ aux,
+                                 const float* __restrict__ grad_image, int C, float eps2,
+                                 float* __restrict__ bgsum, uint32_t blk) {
   __shared__ float s_w[kBgBlockPixels];
   __shared__ float s_acc[kBgThreads];
   __shared__ float s_acc4_buf[4 * kBgThreads];
   const int tid = threadIdx.x;
-  const int b = find_scene(tab.blk_start, tab.B, blockIdx.x);
+  __syncthreads();  // the previous call's readers are done with the LDS
+  const int b = find_scene(tab.blk_start, tab.B, blk);
   const SceneDev& sc = tab.scenes[b];
   const long long npix = (long long)sc.cam.W * sc.cam.H;
-  const long long p0 = (long long)(blockIdx.x - sc.bgblk_off) * kBgBlockPixels;
+  const long long p0 = (long long)(blk - sc.bgblk_off) * kBgBlockPixels;
   const int np = int(min((long long)kBgBlockPixels, npix - p0));
   const float* auxs = aux + sc.pix_off + p0;
   const float* gs = grad_image + (size_t(sc.pix_off) + size_t(p0)) * size_t(C);
@@ -500,7 +535,7 @@ __global__ __launch_bounds__(kBgThreads) void k_bg_partial(SceneTable tab,
     if (tid < C) {
       float t = 0.f;
       for (int w = 0; w < kBgThreads / kWave; ++w) t += s_acc4_buf[(w * cq + tid / 4) * 4 + (tid & 3)];
-      bgsum[size_t(blockIdx.x) * size_t(C) + tid] = t;
+      bgsum[size_t(blk) * size_t(C) + tid] = t;
     }
     return;
   }
@@ -537,8 +572,16 @@ __global__ __launch_bounds__(kBgThreads) void k_bg_partial(SceneTable tab,
   if (tid < C) {
     float t = 0.f;
     for (int r = 0; r < split; ++r) t += s_acc[tid + C * r];
-    bgsum[size_t(blockIdx.x) * size_t(C) + tid] = t;
+    bgsum[size_t(blk) * size_t(C) + tid] = t;
   }
+}
+
+__global__ __launch_bounds__(kBgThreads) void k_bg_partial(SceneTable tab,
+                                                           const float* __restrict__ aux,
+                                                           const float* __restrict__ grad_image,
+                                                           int C, float eps2,
+                                                           float* __restrict__ bgsum) {
+  bg_partial_block(tab, aux, grad_image, C, eps2, bgsum, blockIdx.x);
 }
 
 // The same sums for C > kBgMaxC: one pixel per thread and a loop over channels.
@@ -572,24 +615,6 @@ __global__ __launch_bounds__(kBgThreads) void k_bg_partial_wide(SceneTable tab,
   }
 }
 
-// K8b: grad_bg[b][c] = sum of scene b's block partials (one block per (c, b)).
-__global__ __launch_bounds__(256) void k_reduce_bg(SceneTable tab, const float* __restrict__ bgpart,
-                                                   int C, float* __restrict__ grad_bg) {
-  __shared__ float s[256 / kWave];
-  const int c = blockIdx.x, b = blockIdx.y;
-  const uint32_t k0 = tab.blk_start[b], k1 = tab.blk_start[b + 1];
-  float acc = 0.f;
-  for (uint32_t k = k0 + threadIdx.x; k < k1; k += 256) acc += bgpart[size_t(k) * size_t(C) + c];
-  acc = wave_sum(acc);
-  if ((threadIdx.x & (kWave - 1)) == 0) s[threadIdx.x / kWave] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    float tsum = 0.f;
-    for (int w = 0; w < 256 / kWave; ++w) tsum += s[w];
-    grad_bg[size_t(b) * size_t(C) + c] = tsum;
-  }
-}
-
 hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_t stream) {
   const bool need_geo = a.grad_pos || a.grad_radius;
   const bool wide = a.C > kBwdChannels;
@@ -611,6 +636,10 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
   A.need_geo = need_geo ? 1 : 0;
   A.need_op = a.grad_opacity ? 1 : 0;
   A.need_pay = a.grad_payload ? 1 : 0;
+  // the narrow raster kernel also computes the background block sums
+  A.bgsum = (a.grad_bg && !wide) ? ws_ptr<float>(ws, q.off_bgsum) : nullptr;
+  A.nbgblk = uint32_t(q.nbgblk);
+  A.eps2 = a.eps2;
   const uint32_t* counts = ws_ptr<uint32_t>(ws, q.off_counts);
   float* bgsum = ws_ptr<float>(ws, q.off_bgsum);
   stage_begin(PULSAR_STAGE_ZERO, stream);
@@ -637,22 +666,21 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
                        A);
   stage_end(PULSAR_STAGE_RASTER_BWD, stream);
   stage_begin(PULSAR_STAGE_FINALIZE, stream);
-  if (q.n > 0)
-    hipLaunchKernelGGL(k_finalize, dim3(unsigned((q.n + kFinThreads - 1) / kFinThreads)),
-                       dim3(kFinThreads), 0, stream,
-                       int(q.n), counts, a.pos, a.radius, tab, a.min_radius_px, a.C,
-                       wide ? 1 : 0, A.sres, q.bwd_ps4, q.bwd_go, a.grad_pos, a.grad_radius,
-                       a.grad_opacity, a.grad_payload);
-  if (a.grad_bg) {
+  if (a.grad_bg && wide) {
     if (q.C <= kBgMaxC)
       hipLaunchKernelGGL(k_bg_partial, dim3(unsigned(q.nbgblk)), dim3(kBgThreads), 0, stream,
                          tab, a.aux, a.grad_image, int(q.C), a.eps2, bgsum);
     else
       hipLaunchKernelGGL(k_bg_partial_wide, dim3(unsigned(q.nbgblk)), dim3(kBgThreads), 0,
                          stream, tab, a.aux, a.grad_image, int(q.C), a.eps2, bgsum);
-    hipLaunchKernelGGL(k_reduce_bg, dim3(unsigned(q.C), unsigned(q.B)), dim3(256), 0, stream, tab,
-                       bgsum, int(q.C), a.grad_bg);
   }
+  const uint32_t nfin = uint32_t((q.n + kFinThreads - 1) / kFinThreads);
+  const uint32_t nred = a.grad_bg ? uint32_t(q.C) * uint32_t(q.B) : 0u;
+  if (nfin + nred > 0)
+    hipLaunchKernelGGL(k_finalize, dim3(nfin + nred), dim3(kFinThreads), 0, stream, int(q.n),
+                       counts, a.pos, a.radius, tab, a.min_radius_px, a.C, wide ? 1 : 0, A.sres,
+                       q.bwd_ps4, q.bwd_go, a.grad_pos, a.grad_radius, a.grad_opacity,
+                       a.grad_payload, nfin, bgsum, a.grad_bg);
   stage_end(PULSAR_STAGE_FINALIZE, stream);
   return hipGetLastError();
 }

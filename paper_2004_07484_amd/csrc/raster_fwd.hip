@@ -19,8 +19,8 @@
 // index), and the K-th one becomes the pixel's gradient threshold.
 // A tile with one chunk writes its pixels directly; otherwise every chunk
 // leaves a partial state (m, D, numerator, K-list) and k_fwd_merge combines
-// them in chunk order, so the result is deterministic. k_fwd_background
-// fills the tiles that no sphere touches.
+// them in chunk order, so the result is deterministic. After its work items
+// the same grid fills the tiles that no sphere touches.
 #include "hit_geometry.h"
 
 namespace pulsar {
@@ -70,6 +70,8 @@ struct FwdKernelArgs {
   int C, c0, cn, K, pstride, kfield;  // kfield: first K-list field of a partial state
   int track;                          // keep K-lists (first channel pass with aux)
   int vec4;                           // one channel pass, C % 4 == 0, 16-byte aligned image
+  uint32_t T;                         // tiles of all scenes
+  int fill_in_tail;                   // empty tiles filled by the work-item kernel
   float eps2;                         // background exponent (base 2)
 };
 
@@ -92,6 +94,55 @@ __device__ __forceinline__ void write_pixel(const FwdKernelArgs& A, const CamDev
                              : make_float2(__uint_as_float(uint32_t(k >> 32)),
                                            __uint_as_float(uint32_t(k)));
   }
+}
+
+// Pixels of a tile without any sphere: F = background and L = eps / gamma
+// (no gradient threshold: the backward only visits tiles that have work
+// items). One wave; the image is written row by row as contiguous runs of
+// (pixels in the row) x C floats, so each store instruction covers
+// consecutive addresses.
+__device__ __forceinline__ void fill_background_tile(const FwdKernelArgs& A, uint32_t tile,
+                                                     int lane) {
+  const TileScene ts = tile_scene(A.tab, tile);
+  const SceneDev& sc = A.tab.scenes[ts.b];
+  const int W = sc.cam.W, H = sc.cam.H, C = A.C;
+  const int npx = min(kTileW, W - ts.tx0);    // pixels of the tile inside each row
+  const int nrows = min(kTileH, H - ts.ty0);
+  const float* bg = A.bg + size_t(ts.b) * size_t(C);
+  const int run = npx * C;
+  if (A.vec4) {
+    // whole channel range in this pass and 16-byte aligned rows: float4 units,
+    // so each store instruction writes four rows of the tile at once
+    const int run4 = run / 4, cq = C / 4;
+    const int units = nrows * run4;
+    for (int u = lane; u < units; u += kWave) {
+      const int r = u / run4, k = u - r * run4;
+      const int q = k % cq;
+      float4* row = reinterpret_cast<float4*>(
+          A.image + (size_t(sc.pix_off) + size_t(ts.ty0 + r) * size_t(W) + size_t(ts.tx0)) *
+                        size_t(C));
+      row[k] = make_float4(bg[4 * q], bg[4 * q + 1], bg[4 * q + 2], bg[4 * q + 3]);
+    }
+  } else {
+    for (int r = 0; r < nrows; ++r) {
+      float* row = A.image + (size_t(sc.pix_off) + size_t(ts.ty0 + r) * size_t(W) +
+                              size_t(ts.tx0)) * size_t(C);
+      for (int f = lane; f < run; f += kWave) {
+        const int ch = f % C;
+        if (ch >= A.c0 && ch < A.c0 + A.cn) row[f] = bg[ch];
+      }
+    }
+  }
+  const int px = ts.tx0 + lane % kTileW, py = ts.ty0 + lane / kTileW;
+  if (A.c0 == 0 && A.aux && px < W && py < H)
+    A.aux[size_t(sc.pix_off) + size_t(py) * size_t(W) + size_t(px)] =
+        A.eps2 * 0.69314718055994531f;
+}
+
+// Empty-tile fill as a launch of its own: one wave per tile.
+__global__ __launch_bounds__(256) void k_fwd_background(FwdKernelArgs A) {
+  const uint32_t tile = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+  if (tile < A.T && A.tinfo[tile].y == 0u) fill_background_tile(A, tile, threadIdx.x % kWave);
 }
 
 template <int CM, int KM>
@@ -256,6 +307,20 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A) {
       }
     }
   }
+  // then the tiles that no sphere touches, on the same persistent grid (their
+  // fill overlaps the uneven end of the work-item loop). This block owns tiles
+  // blockIdx.x + i gridDim.x; the wave tests 64 of them at once and fills the
+  // empty ones.
+  if (!A.fill_in_tail) return;
+  for (uint32_t i0 = 0; blockIdx.x + i0 * gridDim.x < A.T; i0 += kWave) {
+    const uint32_t t = blockIdx.x + (i0 + uint32_t(lane)) * gridDim.x;
+    uint64_t empty = __ballot(t < A.T && A.tinfo[t].y == 0u);
+    while (empty != 0ull) {
+      const uint32_t k = uint32_t(__builtin_ctzll(empty));
+      empty &= empty - 1ull;
+      fill_background_tile(A, blockIdx.x + (i0 + k) * gridDim.x, lane);
+    }
+  }
 }
 
 // Tiles with several work items combine their partial states: four waves per
@@ -343,52 +408,6 @@ __global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(FwdKernelArgs
   }
 }
 
-// Pixels of tiles without any sphere: F = background and L = eps / gamma.
-// One wave per tile; the image is written
-// row by row as contiguous runs of (pixels in the row) x C floats, so each
-// store instruction covers consecutive addresses.
-template <int CM>
-__global__ __launch_bounds__(256) void k_fwd_background(FwdKernelArgs A, uint32_t T) {
-  const uint32_t tile = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
-  const int lane = threadIdx.x % kWave;
-  if (tile >= T || A.tinfo[tile].y != 0u) return;
-  const TileScene ts = tile_scene(A.tab, tile);
-  const SceneDev& sc = A.tab.scenes[ts.b];
-  const int W = sc.cam.W, H = sc.cam.H, C = A.C;
-  const int npx = min(kTileW, W - ts.tx0);    // pixels of the tile inside each row
-  const int nrows = min(kTileH, H - ts.ty0);
-  const float* bg = A.bg + size_t(ts.b) * size_t(C);
-  const int run = npx * C;
-  if (A.vec4) {
-    // whole channel range in this pass and 16-byte aligned rows: float4 units,
-    // so each store instruction writes four rows of the tile at once
-    const int run4 = run / 4, cq = C / 4;
-    const int units = nrows * run4;
-    for (int u = lane; u < units; u += kWave) {
-      const int r = u / run4, k = u - r * run4;
-      const int q = k % cq;
-      float4* row = reinterpret_cast<float4*>(
-          A.image + (size_t(sc.pix_off) + size_t(ts.ty0 + r) * size_t(W) + size_t(ts.tx0)) *
-                        size_t(C));
-      row[k] = make_float4(bg[4 * q], bg[4 * q + 1], bg[4 * q + 2], bg[4 * q + 3]);
-    }
-  } else {
-    for (int r = 0; r < nrows; ++r) {
-      float* row = A.image + (size_t(sc.pix_off) + size_t(ts.ty0 + r) * size_t(W) +
-                              size_t(ts.tx0)) * size_t(C);
-      for (int f = lane; f < run; f += kWave) {
-        const int ch = f % C;
-        if (ch >= A.c0 && ch < A.c0 + A.cn) row[f] = bg[ch];
-      }
-    }
-  }
-  const int px = ts.tx0 + lane % kTileW, py = ts.ty0 + lane / kTileW;
-  if (px >= W || py >= H) return;
-  const size_t p = size_t(sc.pix_off) + size_t(py) * size_t(W) + size_t(px);
-  if (A.c0 == 0 && A.aux) A.aux[p] = A.eps2 * 0.69314718055994531f;
-  // no gradient threshold: the backward only visits tiles that have work items
-}
-
 void launch_upload_scenes(const Plan& q, const std::vector<SceneDev>& sc, char* ws,
                           hipStream_t stream);
 void launch_project(const Plan& q, const FwdArgs& a, char* ws, hipStream_t stream);
@@ -402,9 +421,8 @@ static void launch_raster_fwd_cm(const Plan& q, const FwdKernelArgs& A, hipStrea
   const long long mg = q.T < q.raster_grid ? q.T : q.raster_grid;
   hipLaunchKernelGGL((k_fwd_merge<CM, KM>), dim3(unsigned(mg)), dim3(kWave * kMergeWaves), 0,
                      stream, A);
-  const long long nb = (q.T + 256 / kWave - 1) / (256 / kWave);
-  hipLaunchKernelGGL((k_fwd_background<CM>), dim3(unsigned(nb)), dim3(256), 0, stream, A,
-                     uint32_t(q.T));
+  if (!A.fill_in_tail)
+    hipLaunchKernelGGL(k_fwd_background, dim3(unsigned((q.T + 3) / 4)), dim3(256), 0, stream, A);
 }
 
 template <int KM>
@@ -453,6 +471,10 @@ hipError_t launch_forward(const Plan& q, const std::vector<SceneDev>& scenes, co
   A.pstride = q.pstride;
   A.kfield = 2 + q.fwd_cm;
   A.eps2 = scenes[0].bc.eps2;  // eps / gamma does not depend on the camera
+  A.T = uint32_t(q.T);
+  // a few tiles per block fill well in the tail of the work-item kernel; many
+  // more (large batches) get a launch of their own with one wave per tile
+  A.fill_in_tail = q.T <= 4LL * q.raster_grid ? 1 : 0;
   for (int c0 = 0; c0 < a.C; c0 += kFwdChannels) {
     A.c0 = c0;
     A.cn = a.C - c0 < kFwdChannels ? a.C - c0 : kFwdChannels;
