@@ -407,8 +407,9 @@ def main() -> int:
     stage_avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
     # Algorithmic bytes per launch (the kernel's share of the frame's
     # compulsory I/O) of the stages that are one kernel:
-    #   raster_bwd (k_bwd_pairs): read G, F and L, read the payload, write
-    #     dL/df, dL/do and the camera-space position/radius sums
+    #   raster_bwd (k_bwd_items, with the background-gradient block sums in
+    #     its tail): read G, F and L, read the payload, write dL/df, dL/do and
+    #     the camera-space position/radius sums
     #   project (k_project): read pos, radius, opacity
     # The forward raster stage is three kernels (chunks, merge, background
     # fill) and is reported beside it for its share: payload in, F and L out.
@@ -416,7 +417,7 @@ def main() -> int:
         "raster_bwd": H * W * (8 * C + 4) + n * 4 * C + n * 4 * (C + 5),
         "project": n * 20,
     }
-    kernel_of = {"raster_bwd": "k_bwd_pairs", "project": "k_project"}
+    kernel_of = {"raster_bwd": "k_bwd_items", "project": "k_project"}
     dominant = max(per_stage_bytes, key=lambda k: stage_avg.get(k, 0.0))
     dom_ms = stage_avg[dominant]
     achieved = per_stage_bytes[dominant] / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
@@ -428,7 +429,7 @@ def main() -> int:
                 "bytes_per_launch": per_stage_bytes[dominant]}
     fwd_stage_bytes = n * 4 * C + H * W * (4 * C + 4)
     fwd_stage_ms = stage_avg.get("raster_fwd", 0.0)
-    raster_fwd_stage = {"kernels": "k_fwd_chunks+k_fwd_merge+k_fwd_background",
+    raster_fwd_stage = {"kernels": "k_fwd_chunks+k_fwd_merge",
                         "avg_ms": round(fwd_stage_ms, 4), "bytes_per_launch": fwd_stage_bytes,
                         "achieved_GBs": round(fwd_stage_bytes / (fwd_stage_ms * 1e-3) / 1e9, 1)
                         if fwd_stage_ms > 0 else None}
