@@ -202,30 +202,6 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
   }
 }
 
-// ---------------------------------------------------------------- K5 ranges
-// ranges[t] = first sorted position whose tile is >= t (binary search);
-// ranges[T] = number of stored pairs.
-__global__ void k_tile_ranges(const uint32_t* __restrict__ keys,
-                              const Status* __restrict__ status, int T, int depth_bits,
-                              uint32_t* __restrict__ ranges) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t > T) return;
-  const uint32_t used = status->used;
-  if (t == T) {
-    ranges[t] = used;
-    return;
-  }
-  uint32_t lo = 0, hi = used;
-  while (lo < hi) {
-    const uint32_t mid = lo + (hi - lo) / 2;
-    if ((keys[mid] >> depth_bits) < uint32_t(t))
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  ranges[t] = lo;
-}
-
 // ---------------------------------------------------------------- work items
 // Each non-empty tile's list is cut into chunks of at most `chunk` records:
 // L / chunk full chunks and one shorter chunk for the rest. Full chunks of
@@ -237,25 +213,52 @@ struct TileChunks {
   uint32_t nf, np, ns, nm;  // full chunks, short chunks (0/1), partial-state slots, merges (0/1)
 };
 
-__device__ __forceinline__ TileChunks tile_chunks(const uint32_t* __restrict__ ranges, int t,
-                                                  int T, uint32_t chunk) {
-  TileChunks c{0u, 0u, 0u, 0u};
-  if (t < T) {
-    const uint32_t L = ranges[t + 1] - ranges[t];
-    c.nf = L / chunk;
-    c.np = (L % chunk) != 0u ? 1u : 0u;
-    const uint32_t n = c.nf + c.np;
-    c.ns = n >= 2 ? n : 0u;
-    c.nm = n >= 2 ? 1u : 0u;
-  }
+__device__ __forceinline__ TileChunks chunks_of(uint32_t L, uint32_t chunk) {
+  TileChunks c;
+  c.nf = L / chunk;
+  c.np = (L % chunk) != 0u ? 1u : 0u;
+  const uint32_t n = c.nf + c.np;
+  c.ns = n >= 2 ? n : 0u;
+  c.nm = n >= 2 ? 1u : 0u;
   return c;
 }
 
-__global__ __launch_bounds__(256) void k_chunk_count(const uint32_t* __restrict__ ranges, int T,
-                                                     uint32_t chunk, uint4* __restrict__ cpart) {
+// K5: ranges[t] = first sorted position whose tile is >= t (binary search
+// over the sorted keys), ranges[T] = number of stored pairs; and per block of
+// 256 tiles the sums of full chunks, short chunks, partial-state slots and
+// merge tiles.
+__device__ __forceinline__ uint32_t first_of_tile(const uint32_t* __restrict__ keys,
+                                                  uint32_t used, int depth_bits, uint32_t t) {
+  uint32_t lo = 0, hi = used;
+  while (lo < hi) {
+    const uint32_t mid = lo + (hi - lo) / 2;
+    if ((keys[mid] >> depth_bits) < t)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void k_tile_plan(const uint32_t* __restrict__ keys,
+                                                   const Status* __restrict__ status, int T,
+                                                   int depth_bits, uint32_t chunk,
+                                                   uint32_t* __restrict__ ranges,
+                                                   uint4* __restrict__ cpart) {
+  __shared__ uint32_t s_lo[257];
   __shared__ uint32_t s_f[256 / kWave], s_p[256 / kWave], s_s[256 / kWave], s_m[256 / kWave];
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  const TileChunks c = tile_chunks(ranges, t, T, chunk);
+  const uint32_t used = status->used;
+  const int t0 = blockIdx.x * 256;
+  const int t = t0 + threadIdx.x;
+  const uint32_t lo = t < T ? first_of_tile(keys, used, depth_bits, uint32_t(t)) : used;
+  s_lo[threadIdx.x] = lo;
+  if (threadIdx.x == 0)
+    s_lo[256] = t0 + 256 < T ? first_of_tile(keys, used, depth_bits, uint32_t(t0 + 256)) : used;
+  if (t < T) ranges[t] = lo;
+  if (t == T - 1) ranges[T] = used;
+  __syncthreads();
+  const TileChunks c = t < T ? chunks_of(s_lo[threadIdx.x + 1] - lo, chunk)
+                             : TileChunks{0u, 0u, 0u, 0u};
   const uint32_t f = wave_sum_u32(c.nf), pp = wave_sum_u32(c.np), ss = wave_sum_u32(c.ns),
                  mm = wave_sum_u32(c.nm);
   if ((threadIdx.x & (kWave - 1)) == 0) {
@@ -277,68 +280,74 @@ __global__ __launch_bounds__(256) void k_chunk_count(const uint32_t* __restrict_
   }
 }
 
-// Single block: exclusive scan of the per-block (full, short, slots) sums.
-__global__ __launch_bounds__(kScanThreads) void k_chunk_scan(uint4* __restrict__ cpart,
-                                                             int nblk, long long pcap,
-                                                             Status* __restrict__ status) {
-  __shared__ uint32_t s_f[kScanThreads / kWave], s_p[kScanThreads / kWave],
-      s_s[kScanThreads / kWave], s_m[kScanThreads / kWave];
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-  uint32_t cf = 0, cp = 0, cs = 0, cm = 0;
-  for (int base = 0; base < nblk; base += kScanThreads) {
-    const int i = base + tid;
-    const uint4 v = i < nblk ? cpart[i] : make_uint4(0u, 0u, 0u, 0u);
-    const uint32_t inf = wave_incl_scan_u32(v.x, lane), inp = wave_incl_scan_u32(v.y, lane),
-                   ins = wave_incl_scan_u32(v.z, lane), inm = wave_incl_scan_u32(v.w, lane);
-    if (lane == kWave - 1) {
-      s_f[wid] = inf;
-      s_p[wid] = inp;
-      s_s[wid] = ins;
-      s_m[wid] = inm;
-    }
-    __syncthreads();
-    uint32_t bf = 0, bp = 0, bs = 0, bm = 0, tf = 0, tp = 0, ts = 0, tm = 0;
-    for (int w = 0; w < kScanThreads / kWave; ++w) {
-      if (w < wid) {
-        bf += s_f[w];
-        bp += s_p[w];
-        bs += s_s[w];
-        bm += s_m[w];
-      }
-      tf += s_f[w];
-      tp += s_p[w];
-      ts += s_s[w];
-      tm += s_m[w];
-    }
-    if (i < nblk)
-      cpart[i] = make_uint4(cf + bf + inf - v.x, cp + bp + inp - v.y, cs + bs + ins - v.z,
-                            cm + bm + inm - v.w);
-    cf += tf;
-    cp += tp;
-    cs += ts;
-    cm += tm;
-    __syncthreads();
-  }
-  if (tid == 0) {
-    status->nfull = cf;
-    status->nchunks = cf + cp;
-    status->npartials = cs;
-    status->nmerge = cm;
-    if ((long long)cs > pcap) status->code = uint32_t(-PULSAR_ERR_CAPACITY);
-  }
-}
-
 __global__ __launch_bounds__(256) void k_chunk_emit(const uint32_t* __restrict__ ranges, int T,
                                                     uint32_t chunk,
-                                                    const uint4* __restrict__ cpart,
-                                                    const Status* __restrict__ status,
+                                                    const uint4* __restrict__ cpart, int nblk,
+                                                    long long pcap, Status* __restrict__ status,
                                                     uint4* __restrict__ tinfo,
                                                     uint4* __restrict__ desc,
                                                     uint32_t* __restrict__ mlist) {
   __shared__ uint32_t s_f[256 / kWave], s_p[256 / kWave], s_s[256 / kWave], s_m[256 / kWave];
+  __shared__ uint4 s_before, s_total;
   const int t = blockIdx.x * 256 + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
-  const TileChunks c = tile_chunks(ranges, t, T, chunk);
+  // this block's offsets and the grand totals: sums over the few block sums
+  // (one block per 256 tiles), so no separate scan launch is needed
+  {
+    uint32_t bf = 0, bp = 0, bs = 0, bm = 0, tf = 0, tp = 0, ts = 0, tm = 0;
+    for (int k = threadIdx.x; k < nblk; k += 256) {
+      const uint4 v = cpart[k];
+      if (k < int(blockIdx.x)) {
+        bf += v.x;
+        bp += v.y;
+        bs += v.z;
+        bm += v.w;
+      }
+      tf += v.x;
+      tp += v.y;
+      ts += v.z;
+      tm += v.w;
+    }
+    bf = wave_sum_u32(bf);
+    bp = wave_sum_u32(bp);
+    bs = wave_sum_u32(bs);
+    bm = wave_sum_u32(bm);
+    tf = wave_sum_u32(tf);
+    tp = wave_sum_u32(tp);
+    ts = wave_sum_u32(ts);
+    tm = wave_sum_u32(tm);
+    __shared__ uint4 s_b[256 / kWave], s_t[256 / kWave];
+    if (lane == 0) {
+      s_b[wid] = make_uint4(bf, bp, bs, bm);
+      s_t[wid] = make_uint4(tf, tp, ts, tm);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint4 b = make_uint4(0u, 0u, 0u, 0u), tt = b;
+      for (int w = 0; w < 256 / kWave; ++w) {
+        b.x += s_b[w].x;
+        b.y += s_b[w].y;
+        b.z += s_b[w].z;
+        b.w += s_b[w].w;
+        tt.x += s_t[w].x;
+        tt.y += s_t[w].y;
+        tt.z += s_t[w].z;
+        tt.w += s_t[w].w;
+      }
+      s_before = b;
+      s_total = tt;
+      if (blockIdx.x == 0) {
+        status->nfull = tt.x;
+        status->nchunks = tt.x + tt.y;
+        status->npartials = tt.z;
+        status->nmerge = tt.w;
+        if ((long long)tt.z > pcap) status->code = uint32_t(-PULSAR_ERR_CAPACITY);
+      }
+    }
+    __syncthreads();
+  }
+  const TileChunks c = t < T ? chunks_of(ranges[t + 1] - ranges[t], chunk)
+                             : TileChunks{0u, 0u, 0u, 0u};
   const uint32_t inf = wave_incl_scan_u32(c.nf, lane), inp = wave_incl_scan_u32(c.np, lane),
                  ins = wave_incl_scan_u32(c.ns, lane), inm = wave_incl_scan_u32(c.nm, lane);
   if (lane == kWave - 1) {
@@ -348,7 +357,8 @@ __global__ __launch_bounds__(256) void k_chunk_emit(const uint32_t* __restrict__
     s_m[wid] = inm;
   }
   __syncthreads();
-  const uint4 base = cpart[blockIdx.x];
+  const uint4 base = s_before;
+  const uint32_t nfull = s_total.x;
   uint32_t bf = base.x, bp = base.y, bs = base.z, bm = base.w;
   for (int w = 0; w < wid; ++w) {
     bf += s_f[w];
@@ -358,7 +368,7 @@ __global__ __launch_bounds__(256) void k_chunk_emit(const uint32_t* __restrict__
   }
   if (t >= T) return;
   if (c.nm) mlist[bm + inm - 1u] = uint32_t(t);
-  const uint32_t foff = bf + inf - c.nf, poff = status->nfull + bp + inp - c.np;
+  const uint32_t foff = bf + inf - c.nf, poff = nfull + bp + inp - c.np;
   const uint32_t soff = bs + ins - c.ns;
   const uint32_t n = c.nf + c.np;
   tinfo[t] = make_uint4(soff, n, 0u, 0u);
@@ -453,16 +463,13 @@ void launch_binning(const Plan& q, char* ws, hipStream_t stream) {
   const uint32_t* ksorted = sorted_in_a(q) ? kA : kB;
   const int T = int(q.T);
   uint32_t* ranges = ws_ptr<uint32_t>(ws, q.off_ranges);
-  hipLaunchKernelGGL(k_tile_ranges, dim3((T + 1 + 255) / 256), dim3(256), 0, stream, ksorted,
-                     status, T, q.depth_bits, ranges);
   uint4* cpart = ws_ptr<uint4>(ws, q.off_cpart);
   const uint32_t chunk = uint32_t(q.chunk);
-  hipLaunchKernelGGL(k_chunk_count, dim3(q.nblk_tiles), dim3(256), 0, stream, ranges, T, chunk,
-                     cpart);
-  hipLaunchKernelGGL(k_chunk_scan, dim3(1), dim3(kScanThreads), 0, stream, cpart, q.nblk_tiles,
-                     (long long)q.pcap, status);
+  hipLaunchKernelGGL(k_tile_plan, dim3(q.nblk_tiles), dim3(256), 0, stream, ksorted, status, T,
+                     q.depth_bits, chunk, ranges, cpart);
   hipLaunchKernelGGL(k_chunk_emit, dim3(q.nblk_tiles), dim3(256), 0, stream, ranges, T, chunk,
-                     cpart, status, ws_ptr<uint4>(ws, q.off_tinfo), ws_ptr<uint4>(ws, q.off_desc),
+                     cpart, q.nblk_tiles, (long long)q.pcap, status,
+                     ws_ptr<uint4>(ws, q.off_tinfo), ws_ptr<uint4>(ws, q.off_desc),
                      ws_ptr<uint32_t>(ws, q.off_mlist));
 }
 

@@ -50,33 +50,67 @@ __global__ __launch_bounds__(64) void k_upload_scenes(SceneUpload u, SceneDev* _
   }
 }
 
+// Fills a SceneUpload with scenes first .. first + count - 1 of the table.
+static SceneUpload make_upload(const Plan& q, const std::vector<SceneDev>& sc, int first) {
+  SceneUpload u;
+  std::memset(&u, 0, sizeof(u));
+  u.first = first;
+  u.count = q.B - first < kUploadScenes ? q.B - first : kUploadScenes;
+  u.B = q.B;
+  u.total_spheres = uint32_t(q.n);
+  u.total_tiles = uint32_t(q.T);
+  u.total_blocks = uint32_t(q.nbgblk);
+  for (int k = 0; k < u.count; ++k) u.s[k] = sc[size_t(first + k)];
+  return u;
+}
+
 void launch_upload_scenes(const Plan& q, const std::vector<SceneDev>& sc, char* ws,
                           hipStream_t stream) {
   SceneDev* scenes = ws_ptr<SceneDev>(ws, q.off_scenes);
   uint32_t* starts = ws_ptr<uint32_t>(ws, q.off_starts);
   for (int first = 0; first < q.B; first += kUploadScenes) {
-    SceneUpload u;
-    std::memset(&u, 0, sizeof(u));
-    u.first = first;
-    u.count = q.B - first < kUploadScenes ? q.B - first : kUploadScenes;
-    u.B = q.B;
-    u.total_spheres = uint32_t(q.n);
-    u.total_tiles = uint32_t(q.T);
-    u.total_blocks = uint32_t(q.nbgblk);
-    for (int k = 0; k < u.count; ++k) u.s[k] = sc[size_t(first + k)];
+    const SceneUpload u = make_upload(q, sc, first);
     hipLaunchKernelGGL(k_upload_scenes, dim3(1), dim3(64), 0, stream, u, scenes, starts);
   }
 }
 
+// When the whole scene table fits in the launch arguments (`inline_scenes`),
+// the projection reads its cameras from there and its first block also
+// writes the workspace copy the later kernels use; otherwise the table was
+// uploaded before and is read from the workspace.
 __global__ __launch_bounds__(kProjectBlock) void k_project(
     int n, const float* __restrict__ pos, const float* __restrict__ radius,
-    const float* __restrict__ opacity, SceneTable tab, float min_radius_px, int depth_bits,
+    const float* __restrict__ opacity, SceneTable tab, SceneUpload u, int inline_scenes,
+    SceneDev* __restrict__ tab_out, uint32_t* __restrict__ starts_out, float min_radius_px,
+    int depth_bits,
     uint32_t* __restrict__ counts, ushort4* __restrict__ trect, uint32_t* __restrict__ qdepth,
     float4* __restrict__ rec, unsigned long long* __restrict__ partials) {
   const int i = blockIdx.x * kProjectBlock + threadIdx.x;
+  if (inline_scenes && blockIdx.x == 0 && threadIdx.x < kWave) {
+    const int k = threadIdx.x;
+    const int B1 = u.B + 1;
+    if (k < u.count) {
+      tab_out[k] = u.s[k];
+      starts_out[k] = u.s[k].sph_off;
+      starts_out[B1 + k] = u.s[k].tile_off;
+      starts_out[2 * B1 + k] = u.s[k].bgblk_off;
+    }
+    if (k == 0) {
+      starts_out[u.B] = u.total_spheres;
+      starts_out[B1 + u.B] = u.total_tiles;
+      starts_out[2 * B1 + u.B] = u.total_blocks;
+    }
+  }
   uint32_t count = 0;
   if (i < n) {
-    const CamDev cam = tab.scenes[find_scene(tab.sph_start, tab.B, uint32_t(i))].cam;
+    int b = 0;
+    if (inline_scenes) {
+      for (int k = 1; k < u.count; ++k)
+        if (u.s[k].sph_off <= uint32_t(i)) b = k;
+    } else {
+      b = find_scene(tab.sph_start, tab.B, uint32_t(i));
+    }
+    const CamDev cam = inline_scenes ? u.s[b].cam : tab.scenes[b].cam;
     const float px = pos[3 * i + 0], py = pos[3 * i + 1], pz = pos[3 * i + 2];
     const float r = radius[i];
     const float o = opacity ? opacity[i] : 1.f;
@@ -165,11 +199,17 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
   }
 }
 
-void launch_project(const Plan& q, const FwdArgs& a, char* ws, hipStream_t stream) {
+// Uploads the scene table (unless the projection carries it) and projects.
+void launch_project(const Plan& q, const std::vector<SceneDev>& sc, const FwdArgs& a, char* ws,
+                    hipStream_t stream) {
+  const bool inline_scenes = q.B <= kUploadScenes && q.n > 0;
+  if (!inline_scenes) launch_upload_scenes(q, sc, ws, stream);
   if (q.n == 0) return;
+  const SceneUpload u = make_upload(q, sc, 0);
   hipLaunchKernelGGL(k_project, dim3(q.nblk_proj), dim3(kProjectBlock), 0, stream, int(q.n),
-                     a.pos, a.radius, a.opacity, scene_table(q, ws), a.min_radius_px,
-                     q.depth_bits,
+                     a.pos, a.radius, a.opacity, scene_table(q, ws), u, inline_scenes ? 1 : 0,
+                     ws_ptr<SceneDev>(ws, q.off_scenes), ws_ptr<uint32_t>(ws, q.off_starts),
+                     a.min_radius_px, q.depth_bits,
                      ws_ptr<uint32_t>(ws, q.off_counts), ws_ptr<ushort4>(ws, q.off_trect),
                      ws_ptr<uint32_t>(ws, q.off_qdepth), ws_ptr<float4>(ws, q.off_rec),
                      ws_ptr<unsigned long long>(ws, q.off_partials));

@@ -408,9 +408,8 @@ __global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(FwdKernelArgs
   }
 }
 
-void launch_upload_scenes(const Plan& q, const std::vector<SceneDev>& sc, char* ws,
-                          hipStream_t stream);
-void launch_project(const Plan& q, const FwdArgs& a, char* ws, hipStream_t stream);
+void launch_project(const Plan& q, const std::vector<SceneDev>& sc, const FwdArgs& a, char* ws,
+                    hipStream_t stream);
 void launch_binning(const Plan& q, char* ws, hipStream_t stream);
 void launch_gather_records(const Plan& q, const float* payload, char* ws, hipStream_t stream);
 
@@ -444,8 +443,7 @@ static void dispatch_cm(const Plan& q, const FwdKernelArgs& A, hipStream_t strea
 hipError_t launch_forward(const Plan& q, const std::vector<SceneDev>& scenes, const FwdArgs& a,
                           char* ws, hipStream_t stream) {
   stage_begin(PULSAR_STAGE_PROJECT, stream);
-  launch_upload_scenes(q, scenes, ws, stream);
-  launch_project(q, a, ws, stream);
+  launch_project(q, scenes, a, ws, stream);
   stage_end(PULSAR_STAGE_PROJECT, stream);
   stage_begin(PULSAR_STAGE_BINNING, stream);
   launch_binning(q, ws, stream);
