@@ -217,8 +217,8 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   int bcm = 1;
   while (bcm < C && bcm < kBwdChannels) bcm *= 2;
   q.bwd_ps4 = C <= kBwdChannels ? 1 + (bcm + 4) / 4 : 2;
-  q.bwd_go = C <= kBwdChannels ? 4 + bcm : 4;
-  q.off_sres = take(nn * size_t(q.bwd_ps4) * 16);
+  q.off_pslot = take(size_t(cap) * size_t(q.bwd_ps4) * 16);
+  q.off_sfirst = take(nn * 4);
   q.total = o;
   *out = q;
   return PULSAR_OK;

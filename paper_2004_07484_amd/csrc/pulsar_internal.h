@@ -102,10 +102,11 @@ struct Plan {
   size_t off_srec, off_spay;
   size_t off_mlist;  // tiles with several work items, for the merge kernel
   size_t off_scenes, off_starts;  // scene table and its start arrays
-  // backward: one sum record per sphere, bwd_ps4 float4 each
-  // (dL/dc, dL/dR | dL/df[cm] | dL/do at float bwd_go, padding)
-  size_t off_sres;
-  int bwd_ps4, bwd_go;
+  // backward: one sum slot per (tile, sphere) pair at its emission position,
+  // bwd_ps4 float4 each (dL/dc, dL/dR | dL/df[cm] | dL/do, padding), and each
+  // sphere's first emission position
+  size_t off_pslot, off_sfirst;
+  int bwd_ps4;
   int64_t max_chunks, pcap;
   int nblk_tiles, fwd_cm, klist_slots, pstride;
   size_t total;

@@ -9,16 +9,16 @@
 // chunk of one tile's sorted list, stages the tile's 64 pixels in LDS and
 // gives each thread one record. The thread walks its sphere's rectangle
 // inside the tile and sums its sphere's derivatives of Eq. 1 (camera-space
-// dL/dc, dL/dR, dL/do, dL/df) in registers, then hands them to the sphere's
-// sum record in the workspace: one aligned record per sphere (ps4 float4:
-// dL/dc, dL/dR | dL/df[cm] | dL/do), so a sphere that touches one tile (it has
-// exactly one record in all work items) writes it whole with plain stores,
-// one scattered line instead of three partial ones; spheres that touch several
-// tiles add into their zeroed record with float atomics.
+// dL/dc, dL/dR, dL/do, dL/df) in registers, then writes them whole into the
+// pair's slot (ps4 float4: dL/dc, dL/dR | dL/df[cm] | dL/do) with plain
+// stores. A pair's slot is its emission position, so a sphere's slots are
+// contiguous and in sphere order: no atomics and no zeroing pass, and the
+// result does not depend on scheduling.
 //
-// K8 (k_finalize) runs in sphere order over those records (coalesced): it
-// turns the camera-space sums into world-space position and radius gradients
-// and writes every requested output contiguously. The background gradient is a
+// K8 (k_finalize) runs in sphere order: it adds each sphere's slots (one per
+// tile it touches, read sequentially), turns the camera-space sums into
+// world-space position and radius gradients and writes every requested
+// output contiguously. The background gradient is a
 // plain reduction over all pixels: block sums at the end of K7 (k_bg_partial
 // for the wide path), summed per scene by extra blocks of K8.
 #include "hit_geometry.h"
@@ -29,14 +29,15 @@ struct BwdKernelArgs {
   SceneTable tab;
   Status* status;
   const uint4* desc;
-  const float4* srec;   // sphere records in sorted pair order (index | single-tile flag in .w)
+  const float4* srec;   // sphere records in sorted pair order (pair position in .w)
   const float* spay;    // payload rows in sorted pair order
   const float* image;
   const float* aux;
   const float* grad_image;
   const float2* thr;
-  float4* sres;         // per-sphere sum records, ps4 float4 each
+  float4* pslot;        // per-pair sum slots at emission positions, ps4 float4 each
   int ps4;
+  const uint32_t* svals;  // sphere index of every sorted pair
   float* grad_payload;  // caller's output, added per hit by the wide path only
   int C;
   int need_geo, need_op, need_pay;
@@ -152,8 +153,7 @@ __global__ __launch_bounds__(kWave * kBwdWaves) void k_bwd_items(BwdKernelArgs A
     for (; j < end; j += kWave * kBwdWaves) {
       if (j != beg + uint32_t(tid)) load_record(j);
       const SphereRec s = unpack_rec(ra, rb, rc, rd);
-      const uint32_t id = __float_as_uint(rd.w) & ~kFirstChunk;
-      const bool single = (__float_as_uint(rd.w) & kFirstChunk) != 0u;
+      const uint32_t id = __float_as_uint(rd.w);  // pair position (tie-break and slot)
       const uint32_t p1 = __float_as_uint(rd.z);
       const int xa = max(s.x0, ts.tx0), xb = min(int(p1 & 0xffffu), ts.tx0 + kTileW - 1);
       const int ya = max(s.y0, ts.ty0), yb = min(int(p1 >> 16), ts.ty0 + kTileH - 1);
@@ -185,38 +185,21 @@ __global__ __launch_bounds__(kWave * kBwdWaves) void k_bwd_items(BwdKernelArgs A
           ++nh;
         }
       }
-      // A sphere that touches one tile has exactly one record in all work
-      // items: it writes its whole sum record (zeros included). Others add
-      // into their zeroed record.
-      float4* sr = A.sres + size_t(id) * size_t(A.ps4);
+      // the pair's sums go whole into its slot
+      float4* sr = A.pslot + size_t(id) * size_t(A.ps4);
       constexpr int NT = (CM + 4) / 4;  // float4 holding dL/df[CM], then dL/do
-      if (single) {
-        sr[0] = make_float4(gcx, gcy, gcz, gR);
+      sr[0] = make_float4(gcx, gcy, gcz, gR);
 #pragma unroll
-        for (int q = 0; q < NT; ++q) {
-          float v[4];
+      for (int q = 0; q < NT; ++q) {
+        float v[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int k = 4 * q + u;
-            v[u] = k < CM ? gf[k < CM ? k : 0] : (k == CM ? go : 0.f);
-          }
-          sr[1 + q] = make_float4(v[0], v[1], v[2], v[3]);
+        for (int u = 0; u < 4; ++u) {
+          const int k = 4 * q + u;
+          v[u] = k < CM ? gf[k < CM ? k : 0] : (k == CM ? go : 0.f);
         }
-      } else if (nh > 0) {
-        float* f0 = reinterpret_cast<float*>(sr);
-        if (A.need_geo) {
-          atomicAdd(f0 + 0, gcx);
-          atomicAdd(f0 + 1, gcy);
-          atomicAdd(f0 + 2, gcz);
-          atomicAdd(f0 + 3, gR);
-        }
-        if (A.need_pay) {
-#pragma unroll
-          for (int c = 0; c < CM; ++c)
-            if (c < C) atomicAdd(f0 + 4 + c, gf[c]);
-        }
-        if (A.need_op) atomicAdd(f0 + 4 + CM, go);
+        sr[1 + q] = make_float4(v[0], v[1], v[2], v[3]);
       }
+      (void)nh;
     }
   }
   // then the background-gradient block sums on the same grid (their reads
@@ -261,11 +244,11 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A) {
       const float4* rp = A.srec + 4 * size_t(j);
       const float4 d = rp[3];
       const SphereRec s = unpack_rec(rp[0], rp[1], rp[2], d);
-      const uint32_t id = __float_as_uint(d.w) & ~kFirstChunk;
+      const uint32_t slot = __float_as_uint(d.w);  // pair position (tie-break and slot)
+      const uint32_t id = A.svals[j];              // sphere index
       const uint32_t p1 = __float_as_uint(d.z);
       const float* fk = A.spay + size_t(j) * size_t(C);
       float gcx = 0.f, gcy = 0.f, gcz = 0.f, gR = 0.f, go = 0.f;
-      bool any = false;
       const int xa = max(s.x0, tx0), xb = min(int(p1 & 0xffffu), tx0 + kTileW - 1);
       const int ya = max(s.y0, ty0), yb = min(int(p1 >> 16), ty0 + kTileH - 1);
       for (int iy = ya; iy <= yb; ++iy) {
@@ -276,8 +259,7 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A) {
           if (!exact_hit(ray, s, bc.zfar, h)) continue;
           const float tk = s_tk[pl];
           const uint32_t ik = s_ik[pl];
-          if (!(id == ik || h.t < tk || (h.t == tk && id < ik))) continue;
-          any = true;
+          if (!(slot == ik || h.t < tk || (h.t == tk && slot < ik))) continue;
           const size_t pp = size_t(sc.pix_off) + size_t(iy) * size_t(cam.W) + size_t(ix);
           const float* Gp = A.grad_image + pp * size_t(C);
           const float* Fp = A.image + pp * size_t(C);
@@ -306,54 +288,49 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A) {
           gR += -gt / h.sq + gd * h.ratio / s.R;
         }
       }
-      if (any) {
-        float* f0 = reinterpret_cast<float*>(A.sres + size_t(id) * size_t(A.ps4));
-        if (A.need_geo) {
-          atomicAdd(f0 + 0, gcx);
-          atomicAdd(f0 + 1, gcy);
-          atomicAdd(f0 + 2, gcz);
-          atomicAdd(f0 + 3, gR);
-        }
-        if (A.need_op) atomicAdd(f0 + 4, go);
-      }
+      // dL/dc, dL/dR, dL/do whole into the pair's slot (the payload terms
+      // went out per hit)
+      float4* sr = A.pslot + size_t(slot) * size_t(A.ps4);
+      sr[0] = make_float4(gcx, gcy, gcz, gR);
+      sr[1] = make_float4(go, 0.f, 0.f, 0.f);
     }
   }
 }
 
-// Before K7: zero the sum records K7 adds into: those of spheres that touch
-// several tiles (the narrow path writes one-tile spheres whole), or of every
-// visible sphere together with its row of the caller's payload gradient (the
-// wide path adds per hit).
-__global__ void k_bwd_prep(int n, const uint32_t* __restrict__ counts, int wide, int C, int ps4,
-                           float4* __restrict__ sres, float* __restrict__ grad_payload) {
+// Before the wide K7: zero the caller's payload-gradient rows it adds into
+// per hit (every visible sphere).
+__global__ void k_bwd_prep(int n, const uint32_t* __restrict__ counts, int C,
+                           float* __restrict__ grad_payload) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || counts[i] < (wide ? 1u : 2u)) return;
-  for (int q = 0; q < ps4; ++q) sres[size_t(i) * size_t(ps4) + q] = make_float4(0.f, 0.f, 0.f, 0.f);
-  if (wide && grad_payload)
-    for (int c = 0; c < C; ++c) grad_payload[size_t(i) * size_t(C) + c] = 0.f;
+  if (i >= n || counts[i] == 0u) return;
+  for (int c = 0; c < C; ++c) grad_payload[size_t(i) * size_t(C) + c] = 0.f;
 }
 
 // K8: per sphere, in sphere order, kFinThreads spheres per block. The
-// camera-space sums come from the sphere's record (zero when it touches no
-// tile). Position and radius gradients follow c = R p + t and the min-size
-// clamp; opacity and payload gradients are copied out (narrow path; the wide
-// path added the payload gradient in place). Rows wider than one float
-// (positions, payloads) are staged per block and written as one contiguous
-// run, so every store instruction covers consecutive addresses.
+// camera-space sums are the sum of the sphere's pair slots sfirst ..
+// sfirst + count - 1 (in that order; none when it touches no tile). Position
+// and radius gradients follow c = R p + t and the min-size clamp; opacity and
+// payload gradients are copied out (CM > 0; with CM = 0, the wide path, the
+// payload gradient was added in place). Rows wider than one float (positions,
+// payloads) are staged per block and written as one contiguous run, so every
+// store instruction covers consecutive addresses. Blocks past the spheres sum
+// the background block sums, one block per (scene, channel).
 constexpr int kFinThreads = 256;
+template <int CM>
 __global__ __launch_bounds__(kFinThreads) void k_finalize(
-    int n, const uint32_t* __restrict__ counts, const float* __restrict__ pos,
-    const float* __restrict__ radius, SceneTable tab, float min_radius_px, int C, int wide,
-    const float4* __restrict__ sres, int ps4, int go_off, float* __restrict__ grad_pos,
+    int n, const uint32_t* __restrict__ counts, const uint32_t* __restrict__ sfirst,
+    const Status* __restrict__ status, const float* __restrict__ pos,
+    const float* __restrict__ radius, SceneTable tab, float min_radius_px, int C,
+    const float4* __restrict__ pslot, int ps4, float* __restrict__ grad_pos,
     float* __restrict__ grad_radius, float* __restrict__ grad_opacity,
     float* __restrict__ grad_payload, uint32_t nfin, const float* __restrict__ bgsum,
     float* __restrict__ grad_bg) {
+  constexpr int CS = CM > 0 ? CM : 1;
   __shared__ uint32_t s_cnt[kFinThreads];
   __shared__ float s_gp[3 * kFinThreads];
+  __shared__ float s_pay[kFinThreads * CS];
   const int t = threadIdx.x;
   if (blockIdx.x >= nfin) {
-    // K8b: grad_bg[b][c] = sum of scene b's background block sums, one block
-    // per (scene, channel) after the sphere blocks
     const uint32_t k = blockIdx.x - nfin;
     const int c = int(k % uint32_t(C)), b = int(k / uint32_t(C));
     const uint32_t k0 = tab.blk_start[b], k1 = tab.blk_start[b + 1];
@@ -375,14 +352,44 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
   const int i = i0 + t;
   const uint32_t count = t < nloc ? counts[i] : 0u;
   s_cnt[t] = count;
-  if (t < nloc) {
-    float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
-    float go = 0.f;
-    if (count != 0u) {
-      const float4* sr = sres + size_t(i) * size_t(ps4);
-      g = sr[0];
-      go = reinterpret_cast<const float*>(sr)[go_off];
+  float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+  float go = 0.f;
+  float gf[CS];
+#pragma unroll
+  for (int c = 0; c < CS; ++c) gf[c] = 0.f;
+  if (count != 0u) {
+    const uint32_t base = sfirst[i];
+    // after a capacity overflow (outputs invalid) the slots may be missing
+    if (size_t(base) + count <= size_t(status->used)) {
+      for (uint32_t k = 0; k < count; ++k) {
+        const float4* sr = pslot + size_t(base + k) * size_t(ps4);
+        const float4 a = sr[0];
+        g.x += a.x;
+        g.y += a.y;
+        g.z += a.z;
+        g.w += a.w;
+        if (CM > 0) {
+          constexpr int NT = (CM + 4) / 4;
+#pragma unroll
+          for (int q = 0; q < NT; ++q) {
+            const float4 v = sr[1 + q];
+            const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int kk = 4 * q + u;
+              if (kk < CM)
+                gf[kk < CS ? kk : 0] += vv[u];
+              else if (kk == CM)
+                go += vv[u];
+            }
+          }
+        } else {
+          go += sr[1].x;
+        }
+      }
     }
+  }
+  if (t < nloc) {
     if (grad_opacity) grad_opacity[i] = go;
     if (grad_pos || grad_radius) {
       float gx = g.x, gy = g.y, gz = g.z, gR = g.w;
@@ -404,41 +411,24 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
       s_gp[3 * t + 2] = cam.R[2] * gx + cam.R[5] * gy + cam.R[8] * gz;
     }
   }
+  if (CM > 0) {
+#pragma unroll
+    for (int c = 0; c < CS; ++c) s_pay[t * CS + c] = gf[c];
+  }
   __syncthreads();
   if (grad_pos) {
     float* dst = grad_pos + size_t(i0) * 3;
     for (int f = t; f < 3 * nloc; f += kFinThreads) dst[f] = s_gp[f];
   }
-  if (grad_payload && !wide && (C & 3) == 0 &&
-      (reinterpret_cast<uintptr_t>(grad_payload) & 15u) == 0u) {
-    // float4 unit f of the block's [nloc, C] rows: sphere f / (C/4), group f % (C/4)
-    float4* dst = reinterpret_cast<float4*>(grad_payload + size_t(i0) * size_t(C));
-    const int cq = C / 4;
-    const int total = nloc * cq;
-    const int dsph = kFinThreads / cq, dq = kFinThreads % cq;
-    int sph = t / cq, q = t % cq;
-    for (int f = t; f < total; f += kFinThreads) {
-      float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (s_cnt[sph] != 0u) v = sres[size_t(i0 + sph) * size_t(ps4) + 1 + q];
-      dst[f] = v;
-      sph += dsph;
-      q += dq;
-      if (q >= cq) {
-        q -= cq;
-        ++sph;
-      }
-    }
-  } else if (grad_payload && !wide) {
+  if (!grad_payload) return;
+  if (CM > 0) {
     // element f of the block's [nloc, C] rows: sphere f / C, channel f % C
     float* dst = grad_payload + size_t(i0) * size_t(C);
     const int total = nloc * C;
     const int dsph = kFinThreads / C, dch = kFinThreads % C;
     int sph = t / C, ch = t % C;
     for (int f = t; f < total; f += kFinThreads) {
-      float v = 0.f;
-      if (s_cnt[sph] != 0u)
-        v = reinterpret_cast<const float*>(sres + size_t(i0 + sph) * size_t(ps4))[4 + ch];
-      dst[f] = v;
+      dst[f] = s_pay[sph * CS + ch];
       sph += dsph;
       ch += dch;
       if (ch >= C) {
@@ -446,19 +436,12 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
         ++sph;
       }
     }
-  } else if (grad_payload && wide) {
+  } else if (t < nloc && count == 0u) {
     // the wide path added into the caller's rows; spheres without a tile get zeros
-    if (t < nloc && count == 0u)
-      for (int c = 0; c < C; ++c) grad_payload[size_t(i) * size_t(C) + c] = 0.f;
+    for (int c = 0; c < C; ++c) grad_payload[size_t(i) * size_t(C) + c] = 0.f;
   }
 }
 
-// Background gradient, dL/dbg = sum_p exp(eps/gamma - L_p) G_p per scene:
-// per-block partial sums [blocks][C]; every block covers kBgBlockPixels
-// consecutive pixels of one scene. The block's pixel weights go to LDS, then
-// the block reads its G rows as one flat run of floats: thread t takes
-// elements t, t + S, t + 2S, ... with S the largest multiple of C <= 256, so
-// its channel is always t % C and consecutive threads read consecutive floats.
 // The block sum for background block `blk`, by a whole block of kBgThreads
 // threads (called uniformly; it starts with a barrier so a block can run it
 // for several blocks in a row).
@@ -615,8 +598,18 @@ __global__ __launch_bounds__(kBgThreads) void k_bg_partial_wide(SceneTable tab,
   }
 }
 
+template <int CM>
+static void launch_finalize(const Plan& q, const BwdArgs& a, char* ws, hipStream_t stream,
+                            uint32_t nfin, uint32_t nred) {
+  hipLaunchKernelGGL((k_finalize<CM>), dim3(nfin + nred), dim3(kFinThreads), 0, stream, int(q.n),
+                     ws_ptr<uint32_t>(ws, q.off_counts), ws_ptr<uint32_t>(ws, q.off_sfirst),
+                     ws_ptr<Status>(ws, q.off_status), a.pos, a.radius, scene_table(q, ws),
+                     a.min_radius_px, a.C, ws_ptr<float4>(ws, q.off_pslot), q.bwd_ps4, a.grad_pos,
+                     a.grad_radius, a.grad_opacity, a.grad_payload, nfin,
+                     ws_ptr<float>(ws, q.off_bgsum), a.grad_bg);
+}
+
 hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_t stream) {
-  const bool need_geo = a.grad_pos || a.grad_radius;
   const bool wide = a.C > kBwdChannels;
   const SceneTable tab = scene_table(q, ws);
   BwdKernelArgs A;
@@ -629,23 +622,24 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
   A.aux = a.aux;
   A.grad_image = a.grad_image;
   A.thr = ws_ptr<float2>(ws, q.off_thr);
-  A.sres = ws_ptr<float4>(ws, q.off_sres);
+  A.pslot = ws_ptr<float4>(ws, q.off_pslot);
   A.ps4 = q.bwd_ps4;
+  A.svals = ws_ptr<uint32_t>(ws, sorted_in_a(q) ? q.off_valsA : q.off_valsB);
   A.grad_payload = a.grad_payload;
   A.C = a.C;
-  A.need_geo = need_geo ? 1 : 0;
+  A.need_geo = (a.grad_pos || a.grad_radius) ? 1 : 0;
   A.need_op = a.grad_opacity ? 1 : 0;
   A.need_pay = a.grad_payload ? 1 : 0;
   // the narrow raster kernel also computes the background block sums
   A.bgsum = (a.grad_bg && !wide) ? ws_ptr<float>(ws, q.off_bgsum) : nullptr;
   A.nbgblk = uint32_t(q.nbgblk);
   A.eps2 = a.eps2;
-  const uint32_t* counts = ws_ptr<uint32_t>(ws, q.off_counts);
   float* bgsum = ws_ptr<float>(ws, q.off_bgsum);
+  const uint32_t* counts = ws_ptr<uint32_t>(ws, q.off_counts);
   stage_begin(PULSAR_STAGE_ZERO, stream);
-  if (q.n > 0)
+  if (wide && a.grad_payload && q.n > 0)
     hipLaunchKernelGGL(k_bwd_prep, dim3(unsigned((q.n + 255) / 256)), dim3(256), 0, stream,
-                       int(q.n), counts, wide ? 1 : 0, a.C, q.bwd_ps4, A.sres, a.grad_payload);
+                       int(q.n), counts, a.C, a.grad_payload);
   stage_end(PULSAR_STAGE_ZERO, stream);
   stage_begin(PULSAR_STAGE_RASTER_BWD, stream);
   const dim3 ig{unsigned(q.raster_grid), 1u, 1u}, it{unsigned(kWave * kBwdWaves), 1u, 1u};
@@ -676,11 +670,22 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
   }
   const uint32_t nfin = uint32_t((q.n + kFinThreads - 1) / kFinThreads);
   const uint32_t nred = a.grad_bg ? uint32_t(q.C) * uint32_t(q.B) : 0u;
-  if (nfin + nred > 0)
-    hipLaunchKernelGGL(k_finalize, dim3(nfin + nred), dim3(kFinThreads), 0, stream, int(q.n),
-                       counts, a.pos, a.radius, tab, a.min_radius_px, a.C, wide ? 1 : 0, A.sres,
-                       q.bwd_ps4, q.bwd_go, a.grad_pos, a.grad_radius, a.grad_opacity,
-                       a.grad_payload, nfin, bgsum, a.grad_bg);
+  if (nfin + nred > 0) {
+    if (a.C <= 1)
+      launch_finalize<1>(q, a, ws, stream, nfin, nred);
+    else if (a.C <= 2)
+      launch_finalize<2>(q, a, ws, stream, nfin, nred);
+    else if (a.C <= 4)
+      launch_finalize<4>(q, a, ws, stream, nfin, nred);
+    else if (a.C <= 8)
+      launch_finalize<8>(q, a, ws, stream, nfin, nred);
+    else if (a.C <= 16)
+      launch_finalize<16>(q, a, ws, stream, nfin, nred);
+    else if (!wide)
+      launch_finalize<32>(q, a, ws, stream, nfin, nred);
+    else
+      launch_finalize<0>(q, a, ws, stream, nfin, nred);
+  }
   stage_end(PULSAR_STAGE_FINALIZE, stream);
   return hipGetLastError();
 }

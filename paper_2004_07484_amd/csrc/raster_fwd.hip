@@ -15,8 +15,10 @@
 // Lane p owns pixel p, so no two lanes write the same pixel. Blending keeps a
 // running maximum m of the base-2 exponents and rescales when it grows, so
 // exp never overflows down to gamma = 1e-5; every hit enters the sum. When
-// a backward pass follows, lane p also keeps its K nearest hits (t, sphere
-// index), and the K-th one becomes the pixel's gradient threshold.
+// a backward pass follows, lane p also keeps its K nearest hits, ordered by
+// (t, sphere index); the index is represented by the pair's emission
+// position, which orders spheres the same way. The K-th one becomes the
+// pixel's gradient threshold.
 // A tile with one chunk writes its pixels directly; otherwise every chunk
 // leaves a partial state (m, D, numerator, K-list) and k_fwd_merge combines
 // them in chunk order, so the result is deterministic. After its work items
@@ -192,7 +194,7 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A) {
         b = rp[1];
         c = rp[2];
         d = rp[3];
-        id = __float_as_uint(d.w) & ~kFirstChunk;
+        id = __float_as_uint(d.w);  // pair position: orders spheres like their index
       }
       // the sphere's rectangle inside this tile, in tile coordinates; the
       // (sphere, pixel) pairs are flattened over the wave by a prefix sum
