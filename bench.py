@@ -38,29 +38,38 @@ def io_bytes(n: int, H: int, W: int, C: int):
     return fwd, bwd
 
 
-TRAFFIC_SOURCES = ["paper_2004_07484_amd/csrc/raster_bwd.hip",
-                   "paper_2004_07484_amd/csrc/hit_geometry.h",
-                   "paper_2004_07484_amd/csrc/device_common.h",
-                   "paper_2004_07484_amd/csrc/pulsar_internal.h"]
+COMMON_SOURCES = ["paper_2004_07484_amd/csrc/hit_geometry.h",
+                  "paper_2004_07484_amd/csrc/device_common.h",
+                  "paper_2004_07484_amd/csrc/pulsar_internal.h"]
+TRAFFIC_SOURCES = {
+    "k_bwd_items": ["paper_2004_07484_amd/csrc/raster_bwd.hip"] + COMMON_SOURCES,
+    "k_fwd_chunks": ["paper_2004_07484_amd/csrc/raster_fwd.hip"] + COMMON_SOURCES,
+    "k_project": ["paper_2004_07484_amd/csrc/project.hip"] + COMMON_SOURCES,
+}
+
+
+def sources_hash(kernel: str) -> str:
+    import hashlib
+    return hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read()
+                                   for p in TRAFFIC_SOURCES[kernel])).hexdigest()[:16]
 
 
 def measured_traffic(kernel: str, workload: str):
     """HBM bytes per dispatch from the committed rocprofv3 summary (FETCH_SIZE
     and WRITE_SIZE scaled by the copy calibration), or None when the summary
     is missing or the kernel's sources changed since it was taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
-    if not os.path.exists(path):
+    if kernel not in TRAFFIC_SOURCES or not os.path.exists(path):
         return None
     rec = None
     for line in open(path):
         if line.strip().startswith("TRAFFIC "):
-            rec = json.loads(line.strip()[len("TRAFFIC "):])
+            r = json.loads(line.strip()[len("TRAFFIC "):])
+            if r.get("kernel") == kernel:
+                rec = r
     if rec is None:
         return None
-    h = hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read()
-                                for p in TRAFFIC_SOURCES)).hexdigest()[:16]
-    return int(rec["bytes"]) if h == rec.get("sources_sha256_16") else None
+    return int(rec["bytes"]) if sources_hash(kernel) == rec.get("sources_sha256_16") else None
 
 
 def cpu_baseline(wl, G, rows_n: int) -> dict:
@@ -405,19 +414,24 @@ def main() -> int:
 
     fwd_b, bwd_b = io_bytes(n, H, W, C)
     stage_avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
-    # Algorithmic bytes per launch (the kernel's share of the frame's
-    # compulsory I/O) of the stages that are one kernel:
+    # Algorithmic bytes per launch: each kernel's share of the frame's
+    # compulsory I/O, for the three stages that time a
+    # single kernel:
     #   raster_bwd (k_bwd_items, with the background-gradient block sums in
     #     its tail): read G, F and L, read the payload, write dL/df, dL/do and
     #     the camera-space position/radius sums
+    #   raster_fwd (k_fwd_chunks, with the empty-tile fill in its tail): read
+    #     the payload, write F and L (split tiles' pixels are written by the
+    #     merge, timed as its own stage)
     #   project (k_project): read pos, radius, opacity
-    # The forward raster stage is three kernels (chunks, merge, background
-    # fill) and is reported beside it for its share: payload in, F and L out.
+    # The dominant kernel is the one of these with the longest time.
     per_stage_bytes = {
         "raster_bwd": H * W * (8 * C + 4) + n * 4 * C + n * 4 * (C + 5),
+        "raster_fwd": n * 4 * C + H * W * (4 * C + 4),
         "project": n * 20,
     }
-    kernel_of = {"raster_bwd": "k_bwd_items", "project": "k_project"}
+    kernel_of = {"raster_bwd": "k_bwd_items", "raster_fwd": "k_fwd_chunks",
+                 "project": "k_project"}
     dominant = max(per_stage_bytes, key=lambda k: stage_avg.get(k, 0.0))
     dom_ms = stage_avg[dominant]
     achieved = per_stage_bytes[dominant] / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
@@ -427,12 +441,11 @@ def main() -> int:
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "avg_ms": round(dom_ms, 4),
                 "bytes_per_launch": per_stage_bytes[dominant]}
-    fwd_stage_bytes = n * 4 * C + H * W * (4 * C + 4)
-    fwd_stage_ms = stage_avg.get("raster_fwd", 0.0)
-    raster_fwd_stage = {"kernels": "k_fwd_chunks+k_fwd_merge",
-                        "avg_ms": round(fwd_stage_ms, 4), "bytes_per_launch": fwd_stage_bytes,
-                        "achieved_GBs": round(fwd_stage_bytes / (fwd_stage_ms * 1e-3) / 1e9, 1)
-                        if fwd_stage_ms > 0 else None}
+    kernels = {kernel_of[k]: {"avg_ms": round(stage_avg.get(k, 0.0), 4),
+                              "bytes_per_launch": v,
+                              "achieved_GBs": round(v / (stage_avg[k] * 1e-3) / 1e9, 1)
+                              if stage_avg.get(k, 0.0) > 0 else None}
+               for k, v in per_stage_bytes.items()}
     io_frac = (fwd_b + bwd_b) / (step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
 
     batch = None
@@ -471,7 +484,7 @@ def main() -> int:
         "io_roofline_frac": round(io_frac, 4),
         "stages_ms": {k: round(v, 4) for k, v in stage_avg.items()},
         "roofline": roofline,
-        "raster_fwd_stage": raster_fwd_stage,
+        "kernels": kernels,
         "tuned_knobs": None if tune_info is None else tune_info["knobs"],
         "batched": batch,
         "cpu_baseline": cpu,

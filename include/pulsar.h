@@ -211,11 +211,12 @@ const char* pulsar_last_hip_error(void);
  * it never changes results. pulsar_timing_enable returns the previous state. */
 #define PULSAR_STAGE_PROJECT 0    /* K1: projection, culling, sphere records */
 #define PULSAR_STAGE_BINNING 1    /* K2-K5: pair scan, emission, radix sort, tile ranges */
-#define PULSAR_STAGE_RASTER_FWD 2 /* K6: per-tile forward blend */
+#define PULSAR_STAGE_RASTER_FWD 2 /* K6: per-tile forward blend (and empty-tile fill) */
 #define PULSAR_STAGE_ZERO 3       /* clearing of the gradient outputs */
 #define PULSAR_STAGE_RASTER_BWD 4 /* K7: per-tile backward with recomputed hits */
 #define PULSAR_STAGE_FINALIZE 5   /* K8: world-space gradients, background sum */
-#define PULSAR_NUM_STAGES 6
+#define PULSAR_STAGE_MERGE 6      /* K6b: merge of split tiles' partial blends */
+#define PULSAR_NUM_STAGES 7
 int pulsar_timing_enable(int on);
 int pulsar_timing_read(double* total_ms, int64_t* counts);
 const char* pulsar_stage_name(int stage);

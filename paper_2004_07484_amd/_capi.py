@@ -27,7 +27,7 @@ EXPORTED = ("pulsar_workspace_size", "pulsar_fwd", "pulsar_bwd", "pulsar_batch_w
             "pulsar_status_string", "pulsar_last_hip_error", "pulsar_timing_enable",
             "pulsar_timing_read", "pulsar_stage_name", "pulsar_version")
 
-PULSAR_NUM_STAGES = 6
+PULSAR_NUM_STAGES = 7
 PULSAR_MAX_SCENES = 4096
 
 

@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kProjectBlock) void k_emit(
     int n, const uint32_t* __restrict__ counts, const ushort4* __restrict__ trect,
     const uint32_t* __restrict__ qdepth, const unsigned long long* __restrict__ partials,
     SceneTable tab, int depth_bits, long long cap, uint32_t* __restrict__ keys,
-    uint32_t* __restrict__ vals, uint32_t* __restrict__ sfirst, float4* __restrict__ rec) {
+    uint32_t* __restrict__ vals, uint32_t* __restrict__ sfirst) {
   __shared__ unsigned long long s_wave[kProjectBlock / kWave];
   const int i = blockIdx.x * kProjectBlock + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -78,11 +78,7 @@ __global__ __launch_bounds__(kProjectBlock) void k_emit(
   unsigned long long at = before + incl - c;
   // the sphere's pairs occupy emission positions sfirst .. sfirst + count - 1,
   // in row-major order over its tile rectangle
-  const uint32_t first = uint32_t(at < (unsigned long long)cap ? at : (unsigned long long)cap);
-  sfirst[i] = first;
-  // also into the last word of the sphere's record (it held the tile count),
-  // where the record gather reads it
-  reinterpret_cast<float*>(rec + 4 * size_t(i))[15] = __uint_as_float(first);
+  sfirst[i] = uint32_t(at < (unsigned long long)cap ? at : (unsigned long long)cap);
   const ushort4 tr = trect[i];
   const uint32_t q = qdepth[i];
   // tiles are numbered scene by scene, row-major inside each scene
@@ -392,16 +388,15 @@ __global__ __launch_bounds__(256) void k_chunk_emit(const uint32_t* __restrict__
 // ---------------------------------------------------------------- K5b records
 // Copies every sphere record and payload row into sorted pair order, so the
 // raster kernels read their lists contiguously (coalesced, one dependent load
-// less). The fourth word of the copy holds the pair's emission position: the
-// sphere's first position (left in that word of its record by the emission)
-// plus its tile's row-major index in the sphere's tile rectangle. It is
-// unique per pair, ordered like the sphere index across spheres (so it serves
-// as the K-nearest tie-break), and the slot of the pair's gradient sums in
-// the backward.
+// less). The fourth word of the copy holds the pair's emission position
+// sfirst[sphere] + (its tile's row-major index in the sphere's tile
+// rectangle): unique per pair, ordered like the sphere index across spheres
+// (so it serves as the K-nearest tie-break), and the slot of the pair's
+// gradient sums in the backward.
 __global__ __launch_bounds__(256) void k_gather_records(
     const uint32_t* __restrict__ skeys, const uint32_t* __restrict__ svals,
     const Status* __restrict__ status, SceneTable tab, int depth_bits,
-    const float4* __restrict__ rec,
+    const uint32_t* __restrict__ sfirst, const float4* __restrict__ rec,
     const float* __restrict__ payload, int C, int vec, float4* __restrict__ srec,
     float* __restrict__ spay) {
   // one thread per 16-byte unit: four record units, then the payload row in
@@ -426,7 +421,7 @@ __global__ __launch_bounds__(256) void k_gather_records(
         const uint32_t p0 = __float_as_uint(rec[4 * size_t(id)].w), p1 = __float_as_uint(v.z);
         const int tx0 = int(p0 & 0xffffu) / kTileW, ty0 = int(p0 >> 16) / kTileH;
         const int tw = int(p1 & 0xffffu) / kTileW - tx0 + 1;
-        v.w = __uint_as_float(__float_as_uint(v.w) + uint32_t((ty - ty0) * tw + (tx - tx0)));
+        v.w = __uint_as_float(sfirst[id] + uint32_t((ty - ty0) * tw + (tx - tx0)));
       }
       srec[4 * size_t(j) + u] = v;
     } else if (vec) {
@@ -450,7 +445,7 @@ void launch_gather_records(const Plan& q, const float* payload, char* ws, hipStr
   const uint32_t* skeys = ws_ptr<uint32_t>(ws, sorted_in_a(q) ? q.off_keysA : q.off_keysB);
   hipLaunchKernelGGL(k_gather_records, dim3(unsigned(blocks)), dim3(256), 0, stream, skeys, svals,
                      ws_ptr<Status>(ws, q.off_status), scene_table(q, ws), q.depth_bits,
-                     ws_ptr<float4>(ws, q.off_rec), payload,
+                     ws_ptr<uint32_t>(ws, q.off_sfirst), ws_ptr<float4>(ws, q.off_rec), payload,
                      int(q.C), vec, ws_ptr<float4>(ws, q.off_srec),
                      ws_ptr<float>(ws, q.off_spay));
 }
@@ -471,7 +466,7 @@ void launch_binning(const Plan& q, char* ws, hipStream_t stream) {
                        ws_ptr<uint32_t>(ws, q.off_counts), ws_ptr<ushort4>(ws, q.off_trect),
                        ws_ptr<uint32_t>(ws, q.off_qdepth), partials, scene_table(q, ws),
                        q.depth_bits, (long long)q.cap, kA, vA,
-                       ws_ptr<uint32_t>(ws, q.off_sfirst), ws_ptr<float4>(ws, q.off_rec));
+                       ws_ptr<uint32_t>(ws, q.off_sfirst));
   for (int p = 0; p < q.passes; ++p) {
     const int shift = 8 * p;
     const uint32_t* kin = (p % 2 == 0) ? kA : kB;

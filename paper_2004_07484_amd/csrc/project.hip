@@ -13,8 +13,7 @@
 //     [1]   (c_x / c_z, c_y / c_z, c_z, R) (ratios as high parts)
 //     [2]   low parts of X_c - x0, Y_c - y0, kappa, c_x / c_z
 //     [3]   (low part of c_y / c_z, opacity, x1 | y1 << 16, tile count): x1,
-//           y1 is the last pixel of its rectangle; the pair emission later
-//           replaces the tile count by the sphere's first pair position
+//           y1 is the last pixel of its rectangle
 // and the per-block sum of counts for the tile-pair scan. High + low FP32
 // parts carry the FP64 values to about 48 bits for the exact hit test.
 #include <cstring>

@@ -417,13 +417,17 @@ void launch_gather_records(const Plan& q, const float* payload, char* ws, hipStr
 
 template <int CM, int KM>
 static void launch_raster_fwd_cm(const Plan& q, const FwdKernelArgs& A, hipStream_t stream) {
+  stage_begin(PULSAR_STAGE_RASTER_FWD, stream);
   hipLaunchKernelGGL((k_fwd_chunks<CM, KM>), dim3(unsigned(q.raster_grid)), dim3(kWave), 0,
-                     stream, A);
-  const long long mg = q.T < q.raster_grid ? q.T : q.raster_grid;
-  hipLaunchKernelGGL((k_fwd_merge<CM, KM>), dim3(unsigned(mg)), dim3(kWave * kMergeWaves), 0,
                      stream, A);
   if (!A.fill_in_tail)
     hipLaunchKernelGGL(k_fwd_background, dim3(unsigned((q.T + 3) / 4)), dim3(256), 0, stream, A);
+  stage_end(PULSAR_STAGE_RASTER_FWD, stream);
+  stage_begin(PULSAR_STAGE_MERGE, stream);
+  const long long mg = q.T < q.raster_grid ? q.T : q.raster_grid;
+  hipLaunchKernelGGL((k_fwd_merge<CM, KM>), dim3(unsigned(mg)), dim3(kWave * kMergeWaves), 0,
+                     stream, A);
+  stage_end(PULSAR_STAGE_MERGE, stream);
 }
 
 template <int KM>
@@ -451,7 +455,6 @@ hipError_t launch_forward(const Plan& q, const std::vector<SceneDev>& scenes, co
   launch_binning(q, ws, stream);
   if (q.n > 0) launch_gather_records(q, a.payload, ws, stream);
   stage_end(PULSAR_STAGE_BINNING, stream);
-  stage_begin(PULSAR_STAGE_RASTER_FWD, stream);
   FwdKernelArgs A;
   A.tab = scene_table(q, ws);
   A.status = ws_ptr<Status>(ws, q.off_status);
@@ -492,7 +495,6 @@ hipError_t launch_forward(const Plan& q, const std::vector<SceneDev>& scenes, co
     else
       dispatch_cm<32>(q, A, stream);
   }
-  stage_end(PULSAR_STAGE_RASTER_FWD, stream);
   return hipGetLastError();
 }
 
