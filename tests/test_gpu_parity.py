@@ -171,6 +171,18 @@ def test_forward_is_deterministic_and_permutation_invariant():
     assert_close(c["F"], a["F"], 1e-5, "permuted image")
 
 
+def test_backward_is_bitwise_reproducible():
+    """With C <= 32 every gradient is summed in a fixed order (per-pair slots
+    added per sphere in emission order, background block sums in block
+    order), so two runs agree bit for bit."""
+    wl = sg.config1()
+    G = sg.upstream_grad(4, 64, 64, 3)
+    a = gpu_render(wl.scene, wl.camera, wl.params, G)
+    b = gpu_render(wl.scene, wl.camera, wl.params, G, raster_blocks=1024)
+    for key in ["F", "L", "grad_pos", "grad_radius", "grad_opacity", "grad_payload", "grad_bg"]:
+        assert np.array_equal(a[key], b[key], equal_nan=False), key
+
+
 def test_capacity_overflow_is_reported_then_recovers():
     wl = sg.config1()
     small = gpu_render(wl.scene, wl.camera, wl.params, max_pairs=100)
