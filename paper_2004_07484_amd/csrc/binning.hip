@@ -96,7 +96,9 @@ __global__ __launch_bounds__(kProjectBlock) void k_emit(
 
 // ---------------------------------------------------------------- K4 sort
 // LSD radix sort, 8-bit digits, three kernels per pass:
-//   hist:    per-block digit counts, digit-major [digit][block]
+//   hist:    per-block digit counts, digit-major [digit][block]; blocks are
+//            taken in XCD-contiguous runs (xcd_block) so the counts of
+//            neighbouring blocks, which share cache lines, meet in one L2
 //   scan:    one block per digit, exclusive scan over blocks + digit total
 //   scatter: stable rank inside the block, then write to the global slot
 __global__ __launch_bounds__(kSortThreads) void k_sort_hist(
@@ -104,17 +106,20 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(
     int nblk_cap, uint32_t* __restrict__ hist) {
   __shared__ uint32_t s_h[kSortRadix];
   const int tid = threadIdx.x;
+  const uint32_t used = status->used;
+  const uint32_t nb = (used + kSortBlock - 1) / kSortBlock;
+  if (blockIdx.x >= nb) return;  // past the stored pairs (uniform)
+  const uint32_t lb = xcd_block(blockIdx.x, nb);
   s_h[tid] = 0;
   __syncthreads();
-  const uint32_t used = status->used;
-  const size_t base = size_t(blockIdx.x) * kSortBlock;
+  const size_t base = size_t(lb) * kSortBlock;
 #pragma unroll
   for (int r = 0; r < kSortRounds; ++r) {
     const size_t idx = base + size_t(r) * kSortThreads + tid;
     if (idx < used) atomicAdd(&s_h[(keys[idx] >> shift) & (kSortRadix - 1)], 1u);
   }
   __syncthreads();
-  hist[size_t(tid) * nblk_cap + blockIdx.x] = s_h[tid];
+  hist[size_t(tid) * nblk_cap + lb] = s_h[tid];
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_sort_scan(uint32_t* __restrict__ hist,
@@ -156,8 +161,11 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
   __shared__ uint32_t s_wave[kSortThreads / kWave];
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
   const uint32_t used = status->used;
-  const size_t base = size_t(blockIdx.x) * kSortBlock;
-  if (base >= used) return;  // whole block is past the end (uniform)
+  const uint32_t nb = (used + kSortBlock - 1) / kSortBlock;
+  if (blockIdx.x >= nb) return;  // whole block is past the end (uniform)
+  // the same logical block as in k_sort_hist
+  const uint32_t lb = xcd_block(blockIdx.x, nb);
+  const size_t base = size_t(lb) * kSortBlock;
   // exclusive scan of the digit totals gives each digit's global start
   {
     const uint32_t v = dtot[tid];
@@ -166,7 +174,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
     __syncthreads();
     uint32_t before = 0;
     for (int w = 0; w < wid; ++w) before += s_wave[w];
-    s_base[tid] = before + incl - v + hist[size_t(tid) * nblk_cap + blockIdx.x];
+    s_base[tid] = before + incl - v + hist[size_t(tid) * nblk_cap + lb];
 #pragma unroll
     for (int w = 0; w < kSortThreads / kWave; ++w) s_cnt[w][tid] = 0;
   }
@@ -383,71 +391,6 @@ __global__ __launch_bounds__(256) void k_chunk_emit(const uint32_t* __restrict__
     const uint32_t at = ci < c.nf ? foff + ci : poff;
     desc[at] = make_uint4(uint32_t(t) | (ci == 0 ? kFirstChunk : 0u), beg, end, slot);
   }
-}
-
-// ---------------------------------------------------------------- K5b records
-// Copies every sphere record and payload row into sorted pair order, so the
-// raster kernels read their lists contiguously (coalesced, one dependent load
-// less). The fourth word of the copy holds the pair's emission position
-// sfirst[sphere] + (its tile's row-major index in the sphere's tile
-// rectangle): unique per pair, ordered like the sphere index across spheres
-// (so it serves as the K-nearest tie-break), and the slot of the pair's
-// gradient sums in the backward.
-__global__ __launch_bounds__(256) void k_gather_records(
-    const uint32_t* __restrict__ skeys, const uint32_t* __restrict__ svals,
-    const Status* __restrict__ status, SceneTable tab, int depth_bits,
-    const uint32_t* __restrict__ sfirst, const float4* __restrict__ rec,
-    const float* __restrict__ payload, int C, int vec, float4* __restrict__ srec,
-    float* __restrict__ spay) {
-  // one thread per 16-byte unit: four record units, then the payload row in
-  // float4 units (vec: C % 4 == 0 and a 16-byte aligned payload) or floats
-  const uint32_t pu = vec ? uint32_t(C) / 4u : uint32_t(C);
-  const uint32_t units = 4u + pu;
-  const unsigned long long total = (unsigned long long)status->used * units;
-  for (unsigned long long t = (unsigned long long)blockIdx.x * 256 + threadIdx.x; t < total;
-       t += (unsigned long long)gridDim.x * 256) {
-    const uint32_t j = uint32_t(t / units), u = uint32_t(t % units);
-    const uint32_t id = svals[j];
-    if (u < 4u) {
-      float4 v = rec[4 * size_t(id) + u];
-      if (u == 3u) {
-        // the pair's tile within the sphere's tile rectangle (from the pixel
-        // rectangle: first pixel in record word 0.w, last in word 3.z)
-        const uint32_t tile = skeys[j] >> depth_bits;
-        const int b = find_scene(tab.tile_start, tab.B, tile);
-        const int tiles_x = tab.scenes[b].cam.tiles_x;
-        const int lt = int(tile - tab.scenes[b].tile_off);
-        const int tx = lt % tiles_x, ty = lt / tiles_x;
-        const uint32_t p0 = __float_as_uint(rec[4 * size_t(id)].w), p1 = __float_as_uint(v.z);
-        const int tx0 = int(p0 & 0xffffu) / kTileW, ty0 = int(p0 >> 16) / kTileH;
-        const int tw = int(p1 & 0xffffu) / kTileW - tx0 + 1;
-        v.w = __uint_as_float(sfirst[id] + uint32_t((ty - ty0) * tw + (tx - tx0)));
-      }
-      srec[4 * size_t(j) + u] = v;
-    } else if (vec) {
-      const uint32_t q = u - 4u;
-      const float4 v = reinterpret_cast<const float4*>(payload + size_t(id) * size_t(C))[q];
-      reinterpret_cast<float4*>(spay + size_t(j) * size_t(C))[q] = v;
-    } else {
-      const uint32_t c = u - 4u;
-      const float v = payload[size_t(id) * size_t(C) + c];
-      spay[size_t(j) * size_t(C) + c] = v;
-    }
-  }
-}
-
-void launch_gather_records(const Plan& q, const float* payload, char* ws, hipStream_t stream) {
-  const uint32_t* svals = ws_ptr<uint32_t>(ws, sorted_in_a(q) ? q.off_valsA : q.off_valsB);
-  const int vec = (q.C & 3) == 0 && (reinterpret_cast<uintptr_t>(payload) & 15u) == 0u;
-  const long long units = 4 + (vec ? q.C / 4 : q.C);
-  long long blocks = (q.cap * units + 255) / 256;
-  if (blocks > 16384) blocks = 16384;
-  const uint32_t* skeys = ws_ptr<uint32_t>(ws, sorted_in_a(q) ? q.off_keysA : q.off_keysB);
-  hipLaunchKernelGGL(k_gather_records, dim3(unsigned(blocks)), dim3(256), 0, stream, skeys, svals,
-                     ws_ptr<Status>(ws, q.off_status), scene_table(q, ws), q.depth_bits,
-                     ws_ptr<uint32_t>(ws, q.off_sfirst), ws_ptr<float4>(ws, q.off_rec), payload,
-                     int(q.C), vec, ws_ptr<float4>(ws, q.off_srec),
-                     ws_ptr<float>(ws, q.off_spay));
 }
 
 void launch_binning(const Plan& q, char* ws, hipStream_t stream) {

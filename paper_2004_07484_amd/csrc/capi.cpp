@@ -209,8 +209,6 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   q.off_bgsum = take(size_t(q.nbgblk) * size_t(C) * 4);
   q.off_pstate = take(size_t(q.pcap) * kWave * size_t(q.pstride) * 4);
   q.off_thr = take(size_t(q.npix) * 8);
-  q.off_srec = take(size_t(cap) * 64);
-  q.off_spay = take(size_t(cap) * size_t(C) * 4);
   q.off_mlist = take(size_t(q.T) * 4);
   // the backward kernel instance keeps cm >= C channels, a power of two up to
   // 32; wider payloads keep only dL/dc, dL/dR | dL/do in the record

@@ -21,6 +21,18 @@ __device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_lo
 __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Workgroups are dispatched to the chip's 8 XCDs (each with its own L2) in
+// round-robin order. xcd_block maps dispatched block b of nb active blocks to
+// a logical block such that each XCD gets one contiguous run of logical
+// blocks: neighbouring logical blocks, which share cache lines of their
+// inputs and outputs, then meet in the same L2. A bijection on [0, nb).
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
+  const uint32_t x = b % kXcds, s = b / kXcds;
+  const uint32_t q = nb / kXcds, r = nb % kXcds;
+  return x * q + (x < r ? x : r) + s;
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

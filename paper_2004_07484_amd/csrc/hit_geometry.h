@@ -87,9 +87,12 @@ struct Hit {
   float dx, dy, cr;  // D and the cross term (pixel units), for the gradient direction
 };
 
-// Exact test. Returns true on a hit (q < R and t <= zfar) and fills h.
-// Deterministic: every kernel gets bitwise the same result for the same
-// (pixel, sphere), which the K-th-nearest threshold relies on.
+// Exact test. Returns true on a hit (q < R and t <= zfar) and fills h (h is
+// meaningless on a miss). Deterministic: every kernel gets bitwise the same
+// result for the same (pixel, sphere), which the K-th-nearest threshold
+// relies on. Written predicated: the FP32 path runs on every lane and only
+// the rare rim candidates branch into FP64, so a caller's loop has no
+// divergent join around it.
 __device__ __forceinline__ bool exact_hit(const PixelRay& ray, const SphereRec& s, float zfar,
                                           Hit& h) {
 #pragma clang fp contract(off)
@@ -97,15 +100,12 @@ __device__ __forceinline__ bool exact_hit(const PixelRay& ray, const SphereRec& 
   const float dy32 = float(ray.py - s.y0) - s.yh;
   const float cr32 = s.axh * dy32 - s.ayh * dx32;
   const float r2c = s.kh * (dx32 * dx32 + dy32 * dy32 + cr32 * cr32) * ray.inv_v2;
-  if (!(r2c < kRejectR2)) return false;
-  float e, ratio;
-  if (r2c < kFastR2) {
-    e = 1.f - r2c;
-    ratio = fast_sqrt(r2c);
-    h.dx = dx32;
-    h.dy = dy32;
-    h.cr = cr32;
-  } else {
+  bool ok = r2c < kRejectR2;
+  float e = 1.f - r2c, ratio = fast_sqrt(r2c);
+  h.dx = dx32;
+  h.dy = dy32;
+  h.cr = cr32;
+  if (ok && !(r2c < kFastR2)) {
     const double X = double(s.xh) + double(s.xl);
     const double Y = double(s.yh) + double(s.yl);
     const double dx = double(ray.px - s.x0) - X;
@@ -115,7 +115,7 @@ __device__ __forceinline__ bool exact_hit(const PixelRay& ray, const SphereRec& 
     const double cr = ax * dy - ay * dx;
     const double S = dx * dx + dy * dy + cr * cr;
     const double r2 = (double(s.kh) + double(s.kl)) * S * ray.inv_v2_d;
-    if (!(r2 < 1.0)) return false;
+    ok = r2 < 1.0;
     e = float(1.0 - r2);
     ratio = fast_sqrt(float(r2));
     h.dx = float(dx);
@@ -124,13 +124,12 @@ __device__ __forceinline__ bool exact_hit(const PixelRay& ray, const SphereRec& 
   }
   const float sq = fast_sqrt(e);
   const float t = s.cz * (ray.ux * s.axh + ray.uy * s.ayh + ray.uz) - s.R * sq;
-  if (!(t <= zfar)) return false;
   h.e = e;
   h.sq = sq;
   h.ratio = ratio;
   h.delta = e * fast_rcp(1.f + ratio);
   h.t = t;
-  return true;
+  return ok && (t <= zfar);
 }
 
 // The same ray as make_ray, from per-tile LDS copies of its fields.
@@ -177,6 +176,21 @@ __device__ __forceinline__ TileScene tile_scene(const SceneTable& tab, uint32_t 
   ts.tx0 = (lt % tiles_x) * kTileW;
   ts.ty0 = (lt / tiles_x) * kTileH;
   return ts;
+}
+
+// Emission position of the pair (sphere, tile (tx, ty)), tile coordinates
+// inside the sphere's scene: the sphere's first pair (its projection block's
+// offset boff plus the in-block prefix in record word 3.w) plus the row-major
+// index of the tile in the sphere's tile rectangle (derived from the pixel
+// rectangle in words 0.w and 3.z). Unique per pair and ordered like the
+// sphere index across spheres, so it serves as the K-nearest tie-break; it is
+// also the pair's gradient slot. Integer arithmetic, identical everywhere.
+__device__ __forceinline__ uint32_t pair_position(const float4& r0, const float4& r3,
+                                                  uint32_t boff, int tx, int ty) {
+  const uint32_t p0 = __float_as_uint(r0.w), p1 = __float_as_uint(r3.z);
+  const int tx0 = int(p0 & 0xffffu) / kTileW, ty0 = int(p0 >> 16) / kTileH;
+  const int tw = int(p1 & 0xffffu) / kTileW - tx0 + 1;
+  return boff + __float_as_uint(r3.w) + uint32_t((ty - ty0) * tw + (tx - tx0));
 }
 
 // A sphere record is four float4 (see k_project for the layout).

@@ -12,8 +12,10 @@
 //           kappa = (c_z pitch / R)^2 (high FP32 parts)
 //     [1]   (c_x / c_z, c_y / c_z, c_z, R) (ratios as high parts)
 //     [2]   low parts of X_c - x0, Y_c - y0, kappa, c_x / c_z
-//     [3]   (low part of c_y / c_z, opacity, x1 | y1 << 16, tile count): x1,
-//           y1 is the last pixel of its rectangle
+//     [3]   (low part of c_y / c_z, opacity, x1 | y1 << 16, first): x1, y1 is
+//           the last pixel of its rectangle; first is the sum of the tile
+//           counts of the spheres before it in its projection block, so its
+//           first tile pair sits at (block offset + first) in emission order
 // and the per-block sum of counts for the tile-pair scan. High + low FP32
 // parts carry the FP64 values to about 48 bits for the exact hit test.
 #include <cstring>
@@ -102,6 +104,7 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
     }
   }
   uint32_t count = 0;
+  float4 r0, r1, r2, r3;
   if (i < n) {
     int b = 0;
     if (inline_scenes) {
@@ -168,13 +171,11 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
         const float Xh = float(X), Yh = float(Y), kh = float(kap), axh = float(ax),
                     ayh = float(ay);
         const uint32_t packed = uint32_t(j0) | (uint32_t(i0) << 16);
-        float4* r4 = rec + 4 * size_t(i);
-        r4[0] = make_float4(Xh, Yh, kh, __uint_as_float(packed));
-        r4[1] = make_float4(axh, ayh, float(cz), float(R));
-        r4[2] = make_float4(float(X - Xh), float(Y - Yh), float(kap - kh), float(ax - axh));
+        r0 = make_float4(Xh, Yh, kh, __uint_as_float(packed));
+        r1 = make_float4(axh, ayh, float(cz), float(R));
+        r2 = make_float4(float(X - Xh), float(Y - Yh), float(kap - kh), float(ax - axh));
         const uint32_t packed_end = uint32_t(j1) | (uint32_t(i1) << 16);
-        r4[3] = make_float4(float(ay - ayh), o, __uint_as_float(packed_end),
-                            __uint_as_float(count));
+        r3 = make_float4(float(ay - ayh), o, __uint_as_float(packed_end), 0.f);
         // floor quantisation of (tmin - znear) / span, minus one step of margin,
         // so the decoded value never exceeds any float32 hit distance
         const double span = double(cam.zfar) - double(cam.znear);
@@ -186,17 +187,29 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
     }
     counts[i] = count;
   }
-  // per-block sum of tile counts
+  // exclusive prefix of tile counts inside the block, and the block sum
   __shared__ unsigned long long s_sum[kProjectBlock / kWave];
-  const unsigned long long w = wave_sum_u64(count);
-  if ((threadIdx.x & (kWave - 1)) == 0) s_sum[threadIdx.x / kWave] = w;
+  const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+  const unsigned long long incl = wave_incl_scan_u64(count, lane);
+  if (lane == kWave - 1) s_sum[wid] = incl;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long t = 0;
+  unsigned long long before = 0, total = 0;
 #pragma unroll
-    for (int k = 0; k < kProjectBlock / kWave; ++k) t += s_sum[k];
-    partials[blockIdx.x] = t;
+  for (int k = 0; k < kProjectBlock / kWave; ++k) {
+    if (k < wid) before += s_sum[k];
+    total += s_sum[k];
   }
+  if (count != 0) {
+    // a prefix beyond 32 bits only belongs to pairs past any capacity
+    const unsigned long long first = before + incl - count;
+    r3.w = __uint_as_float(first < 0xffffffffull ? uint32_t(first) : 0xffffffffu);
+    float4* r4 = rec + 4 * size_t(i);
+    r4[0] = r0;
+    r4[1] = r1;
+    r4[2] = r2;
+    r4[3] = r3;
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = total;
 }
 
 // Uploads the scene table (unless the projection carries it) and projects.

@@ -99,7 +99,6 @@ struct Plan {
   // K-th nearest hit (t, sphere id); background-gradient block sums
   size_t off_tinfo, off_desc, off_cpart, off_pstate, off_thr, off_bgsum;
   // sphere records and payload rows copied into sorted pair order
-  size_t off_srec, off_spay;
   size_t off_mlist;  // tiles with several work items, for the merge kernel
   size_t off_scenes, off_starts;  // scene table and its start arrays
   // backward: one sum slot per (tile, sphere) pair at its emission position,

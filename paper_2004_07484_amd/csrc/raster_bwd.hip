@@ -29,8 +29,9 @@ struct BwdKernelArgs {
   SceneTable tab;
   Status* status;
   const uint4* desc;
-  const float4* srec;   // sphere records in sorted pair order (pair position in .w)
-  const float* spay;    // payload rows in sorted pair order
+  const float4* rec;                // sphere records, 4 float4 per sphere
+  const float* payload;             // the caller's payload rows [n, C]
+  const unsigned long long* boff;   // first pair of each projection block
   const float* image;
   const float* aux;
   const float* grad_image;
@@ -93,8 +94,14 @@ __device__ __forceinline__ HitGrad hit_grad(const PixelRay& ray, const SphereRec
 // inside the pixel loop and no barrier inside the record loop. CM >= C.
 constexpr int kBwdWaves = 4;
 
+// Up to 8 channels the item kernel is held to 96 VGPRs, so 5 blocks of 4
+// waves fit a CU instead of 4 (a few values spill, reloaded once per item or
+// record, never per pixel); wider instances keep the compiler's budget.
+constexpr int bwd_waves_per_simd(int CM) { return CM <= 8 ? 5 : 1; }
+
 template <int CM>
-__global__ __launch_bounds__(kWave * kBwdWaves) void k_bwd_items(BwdKernelArgs A) {
+__global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_bwd_items(
+    BwdKernelArgs A) {
   __shared__ TileRays s_ray;
   __shared__ float s_G[CM][kWave];
   __shared__ float s_L2[kWave], s_GF[kWave], s_tk[kWave];
@@ -111,22 +118,27 @@ __global__ __launch_bounds__(kWave * kBwdWaves) void k_bwd_items(BwdKernelArgs A
     const CamDev cam = sc.cam;
     const BlendConst bc = sc.bc;
     // the thread's first record and payload row are requested before the
-    // staging below, so the two global round trips overlap
+    // staging below, so the global round trips overlap; a sorted pair names
+    // its sphere, whose record and payload row are read in place
     uint32_t j = beg + uint32_t(tid);
     float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra, rc = ra, rd = ra;
+    uint32_t bo = 0;
     float f[CM];
 #pragma unroll
     for (int c = 0; c < CM; ++c) f[c] = 0.f;
     auto load_record = [&](uint32_t jj) {
-      const float4* rp = A.srec + 4 * size_t(jj);
+      const uint32_t sph = A.svals[jj];
+      const float4* rp = A.rec + 4 * size_t(sph);
       ra = rp[0];
       rb = rp[1];
       rc = rp[2];
       rd = rp[3];
-      const float* fp = A.spay + size_t(jj) * size_t(C);
+      bo = uint32_t(A.boff[sph / kProjectBlock]);
+      const float* fp = A.payload + size_t(sph) * size_t(C);
 #pragma unroll
       for (int c = 0; c < CM; ++c) f[c] = c < C ? fp[c] : 0.f;
     };
+    const int ttx = ts.tx0 / kTileW, tty = ts.ty0 / kTileH;  // the tile, in tile units
     if (j < end) load_record(j);
     __syncthreads();  // the previous item's readers are done with the LDS
     if (tid < kWave) {
@@ -153,7 +165,7 @@ __global__ __launch_bounds__(kWave * kBwdWaves) void k_bwd_items(BwdKernelArgs A
     for (; j < end; j += kWave * kBwdWaves) {
       if (j != beg + uint32_t(tid)) load_record(j);
       const SphereRec s = unpack_rec(ra, rb, rc, rd);
-      const uint32_t id = __float_as_uint(rd.w);  // pair position (tie-break and slot)
+      const uint32_t id = pair_position(ra, rd, bo, ttx, tty);  // tie-break and slot
       const uint32_t p1 = __float_as_uint(rd.z);
       const int xa = max(s.x0, ts.tx0), xb = min(int(p1 & 0xffffu), ts.tx0 + kTileW - 1);
       const int ya = max(s.y0, ts.ty0), yb = min(int(p1 >> 16), ts.ty0 + kTileH - 1);
@@ -241,13 +253,15 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A) {
     for (uint32_t b0 = beg; b0 < end; b0 += kWave) {
       const uint32_t j = b0 + uint32_t(lane);
       if (j >= end) continue;
-      const float4* rp = A.srec + 4 * size_t(j);
-      const float4 d = rp[3];
-      const SphereRec s = unpack_rec(rp[0], rp[1], rp[2], d);
-      const uint32_t slot = __float_as_uint(d.w);  // pair position (tie-break and slot)
-      const uint32_t id = A.svals[j];              // sphere index
+      const uint32_t id = A.svals[j];  // sphere index
+      const float4* rp = A.rec + 4 * size_t(id);
+      const float4 a = rp[0], d = rp[3];
+      const SphereRec s = unpack_rec(a, rp[1], rp[2], d);
+      // pair position (tie-break and slot)
+      const uint32_t slot =
+          pair_position(a, d, uint32_t(A.boff[id / kProjectBlock]), tx0 / kTileW, ty0 / kTileH);
       const uint32_t p1 = __float_as_uint(d.z);
-      const float* fk = A.spay + size_t(j) * size_t(C);
+      const float* fk = A.payload + size_t(id) * size_t(C);
       float gcx = 0.f, gcy = 0.f, gcz = 0.f, gR = 0.f, go = 0.f;
       const int xa = max(s.x0, tx0), xb = min(int(p1 & 0xffffu), tx0 + kTileW - 1);
       const int ya = max(s.y0, ty0), yb = min(int(p1 >> 16), ty0 + kTileH - 1);
@@ -616,8 +630,9 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
   A.tab = tab;
   A.status = ws_ptr<Status>(ws, q.off_status);
   A.desc = ws_ptr<uint4>(ws, q.off_desc);
-  A.srec = ws_ptr<float4>(ws, q.off_srec);
-  A.spay = ws_ptr<float>(ws, q.off_spay);
+  A.rec = ws_ptr<float4>(ws, q.off_rec);
+  A.payload = a.payload;
+  A.boff = ws_ptr<unsigned long long>(ws, q.off_partials);
   A.image = a.image;
   A.aux = a.aux;
   A.grad_image = a.grad_image;

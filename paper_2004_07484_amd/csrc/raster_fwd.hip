@@ -3,8 +3,8 @@
 // Work item = a chunk of at most `chunk` depth-sorted records of one non-empty
 // 8x8 tile (long tile lists are split, so no wave walks thousands of spheres
 // alone); a persistent grid of one-wave blocks takes work items round-robin,
-// full chunks first. Records and payloads were copied into sorted pair order
-// after the sort, so a batch is one contiguous read. Per batch of 64 records:
+// full chunks first. A batch of 64 sorted pairs names its spheres; their
+// records and payload rows are read in place. Per batch of 64 records:
 //   A. sphere-parallel: the (record, pixel of its rectangle inside the tile)
 //      pairs are flattened over the lanes by a prefix sum over rectangle
 //      sizes; each pair runs the cheap FP32 test and a candidate sets bit l
@@ -38,9 +38,11 @@ constexpr uint64_t kKeyNone = ~uint64_t(0);  // empty slot (no hit)
 // K-list in the last K of KM slots, ascending; the leading KM - K slots hold
 // key 0 and never move, so the K-th nearest is always slot KM - 1. Insertion
 // compares the new key with every slot at once and shifts the larger ones up.
+// The test is wave-uniform: lanes whose key does not enter their list run the
+// network as a no-op (every comparison is false).
 template <int KM>
 __device__ __forceinline__ void klist_insert(uint64_t (&kk)[KM], uint64_t key) {
-  if (!(key < kk[KM - 1])) return;
+  if (__ballot(key < kk[KM - 1]) == 0ull) return;
   bool lt[KM];
 #pragma unroll
   for (int i = 0; i < KM; ++i) lt[i] = key < kk[i];
@@ -61,8 +63,10 @@ struct FwdKernelArgs {
   const uint4* desc;
   const uint4* tinfo;
   const uint32_t* mlist;
-  const float4* srec;   // sphere records in sorted pair order, 4 float4 each
-  const float* spay;    // payload rows in sorted pair order
+  const uint32_t* svals;            // sphere index of every sorted pair
+  const float4* rec;                 // sphere records, 4 float4 per sphere
+  const float* payload;              // the caller's payload rows [n, C]
+  const unsigned long long* boff;    // first pair of each projection block
   const float* bg;      // [B, C]
   float* image;
   float* aux;
@@ -147,8 +151,13 @@ __global__ __launch_bounds__(256) void k_fwd_background(FwdKernelArgs A) {
   if (tile < A.T && A.tinfo[tile].y == 0u) fill_background_tile(A, tile, threadIdx.x % kWave);
 }
 
+// Up to 8 channels and an 8-entry K-list the work-item kernel fits 128 VGPRs
+// (4 waves per SIMD, a few registers spilled outside the hit loop); wider
+// instances keep the compiler's own register budget.
+constexpr int fwd_waves_per_simd(int CM, int KM) { return (CM <= 8 && KM <= 8) ? 4 : 1; }
+
 template <int CM, int KM>
-__global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A) {
+__global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM)) void k_fwd_chunks(FwdKernelArgs A) {
   // the batch's records and payloads, padded rows so that lanes reading
   // different records mostly hit different banks
   constexpr int CQ = (CM + 3) / 4;
@@ -157,8 +166,12 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A) {
   __shared__ uint32_t s_id[kWave];
   __shared__ unsigned long long s_mask[kWave];
   __shared__ float s_iv2[kWave];
-  __shared__ uint32_t s_off[kWave], s_box[kWave];
+  __shared__ uint2 s_ob[kWave];  // per record: first flattened pair, rectangle
+  // bit p % 64 of word p / 64 is set when a record's first pair is p (a
+  // batch has at most 64 records of at most 64 pixels, so 64 words suffice)
+  __shared__ unsigned long long s_start[kWave];
   const int lane = threadIdx.x;
+  s_start[lane] = 0ull;
   const uint32_t nchunks = A.status->nchunks;
   for (uint32_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
     const uint4 dsc = A.desc[chunk];
@@ -183,18 +196,22 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A) {
     uint64_t kk[KM];
     klist_init(kk, A.K);
 
+    const int ttx = tx0 / kTileW, tty = ty0 / kTileH;  // the tile, in tile units
     for (uint32_t b0 = beg; b0 < end; b0 += kWave) {
       const uint32_t j = b0 + uint32_t(lane);
       const bool valid = j < end;
       float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a, d = a;
-      uint32_t id = 0;
+      uint32_t id = 0, sph = 0;
       if (valid) {
-        const float4* rp = A.srec + 4 * size_t(j);
+        // the sorted pair names its sphere; the record is read in place
+        sph = A.svals[j];
+        const float4* rp = A.rec + 4 * size_t(sph);
         a = rp[0];
         b = rp[1];
         c = rp[2];
         d = rp[3];
-        id = __float_as_uint(d.w);  // pair position: orders spheres like their index
+        // pair position: orders spheres like their index
+        id = pair_position(a, d, uint32_t(A.boff[sph / kProjectBlock]), ttx, tty);
       }
       // the sphere's rectangle inside this tile, in tile coordinates; the
       // (sphere, pixel) pairs are flattened over the wave by a prefix sum
@@ -209,15 +226,16 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A) {
       const uint32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
       const uint32_t magic = (65536u + w - 1u) / w;  // i / w = (i * magic) >> 16 for i < 64
       __syncthreads();  // previous batch done with s_rec / s_pay / s_mask
-      s_off[lane] = incl - n;
-      s_box[lane] = uint32_t(xa) | (uint32_t(ya) << 3) | (w << 6) | (magic << 10);
+      s_ob[lane] = make_uint2(incl - n,
+                              uint32_t(xa) | (uint32_t(ya) << 3) | (w << 6) | (magic << 10));
+      if (n != 0u) atomicOr(&s_start[(incl - n) >> 6], 1ull << ((incl - n) & 63u));
       s_mask[lane] = 0ull;
       s_id[lane] = id;
       s_rec[lane][0] = a;
       s_rec[lane][1] = b;
       s_rec[lane][2] = c;
       s_rec[lane][3] = d;
-      const float* fp = A.spay + size_t(valid ? j : 0u) * size_t(A.C) + A.c0;
+      const float* fp = A.payload + size_t(sph) * size_t(A.C) + A.c0;
 #pragma unroll
       for (int q = 0; q < CQ; ++q) {
         float v[4];
@@ -229,21 +247,19 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A) {
         s_pay[lane][q] = make_float4(v[0], v[1], v[2], v[3]);
       }
       __syncthreads();
-      // A. every (record, pixel of its rectangle) pair, 64 at a time
+      // A. every (record, pixel of its rectangle) pair, 64 at a time. Valid
+      // records own at least one pair each, so the owner of a pair is the
+      // number of records starting at or before it, minus one: a popcount of
+      // the start bits, with no search.
+      uint32_t before = 0;  // records starting in earlier blocks of 64 pairs
       for (uint32_t pb = 0; pb < total; pb += kWave) {
+        const unsigned long long starts = s_start[pb >> 6];
+        const int r = int(before + uint32_t(__popcll(starts & ((2ull << lane) - 1ull)))) - 1;
+        before += uint32_t(__popcll(starts));
         const uint32_t pair = pb + uint32_t(lane);
         if (pair >= total) continue;
-        int lo = 0, hi = kWave - 1;  // owner: the last record whose first pair is <= pair
-#pragma unroll
-        for (int step = 0; step < 6; ++step) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (s_off[mid] <= pair)
-            lo = mid;
-          else
-            hi = mid - 1;
-        }
-        const int r = lo;
-        const uint32_t i = pair - s_off[r], box = s_box[r];
+        const uint2 ob = s_ob[r];
+        const uint32_t i = pair - ob.x, box = ob.y;
         const uint32_t bw = (box >> 6) & 15u, yy = (i * (box >> 10)) >> 16;
         const int x = int(box & 7u) + int(i - yy * bw), y = int((box >> 3) & 7u) + int(yy);
         const int pl = y * kTileW + x;
@@ -255,37 +271,49 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A) {
         const float r2 = ra.z * (dx * dx + dy * dy + cr * cr) * s_iv2[pl];
         if (r2 < kRejectR2) atomicOr(&s_mask[pl], 1ull << r);
       }
+      s_start[lane] = 0ull;  // for the next batch (this wave's reads above are issued first)
       __syncthreads();
-      // B. pixel p over its candidates, near to far
+      // B. pixel p over its candidates, in list order. Every lane runs the
+      // same body each round (a lane out of candidates, or missing, changes
+      // nothing), so the loop has no divergent join to copy its state at;
+      // the rare rescale and K-list insertions branch wave-uniformly.
       unsigned long long hits = s_mask[lane];
-      while (__ballot(hits != 0ull) != 0ull) {
-        if (hits != 0ull) {
-          const int k = __builtin_ctzll(hits);
-          hits &= hits - 1ull;
-          const SphereRec s = unpack_rec(s_rec[k][0], s_rec[k][1], s_rec[k][2], s_rec[k][3]);
-          Hit h;
-          if (exact_hit(ray, s, bc.zfar, h)) {
-            const float s2 = s.o * (bc.zfar - h.t) * bc.kz;
-            if (s2 > m2) {
-              const float sc = fast_exp2(m2 - s2);
-              D *= sc;
+      // rounds = the most candidates any lane has (a wave-uniform trip count)
+      uint32_t rounds = uint32_t(__popcll(hits));
 #pragma unroll
-              for (int ch = 0; ch < CM; ++ch) N[ch] *= sc;
-              m2 = s2;
-            }
-            const float wgt = s.o * h.delta * fast_exp2(s2 - m2);
-            D += wgt;
+      for (int off = 32; off > 0; off >>= 1) rounds = max(rounds, uint32_t(__shfl_xor(int(rounds), off, 64)));
+      rounds = __builtin_amdgcn_readfirstlane(rounds);
+      for (uint32_t round = 0; round < rounds; ++round) {
+        const bool act = hits != 0ull;
+        const int k = act ? __builtin_ctzll(hits) : 0;
+        hits &= hits - 1ull;
+        const SphereRec s = unpack_rec(s_rec[k][0], s_rec[k][1], s_rec[k][2], s_rec[k][3]);
+        Hit h;
+        const bool hit = exact_hit(ray, s, bc.zfar, h) && act;
+        const float s2 = s.o * (bc.zfar - h.t) * bc.kz;
+        const bool grow = hit && s2 > m2;
+        if (__ballot(grow) != 0ull) {
+          const float sc = grow ? fast_exp2(m2 - s2) : 1.f;
+          D *= sc;
 #pragma unroll
-            for (int q = 0; q < CQ; ++q) {
-              const float4 f = s_pay[k][q];
-              const float fv[4] = {f.x, f.y, f.z, f.w};
-#pragma unroll
-              for (int u = 0; u < 4; ++u)
-                if (4 * q + u < CM) N[4 * q + u] += wgt * fv[u];
-            }
-            if (A.track) klist_insert(kk, hit_key(h.t, s_id[k]));
-          }
+          for (int ch = 0; ch < CM; ++ch) N[ch] *= sc;
+          m2 = grow ? s2 : m2;
         }
+        const float wgt = hit ? s.o * h.delta * fast_exp2(s2 - m2) : 0.f;
+        D += wgt;
+        float fv[4 * CQ];
+#pragma unroll
+        for (int q = 0; q < CQ; ++q) {
+          const float4 f = s_pay[k][q];
+          fv[4 * q + 0] = f.x;
+          fv[4 * q + 1] = f.y;
+          fv[4 * q + 2] = f.z;
+          fv[4 * q + 3] = f.w;
+        }
+        // a miss adds nothing, even against a non-finite payload
+#pragma unroll
+        for (int c = 0; c < CM; ++c) N[c] = hit ? fmaf(wgt, fv[c], N[c]) : N[c];
+        if (A.track) klist_insert(kk, hit ? hit_key(h.t, s_id[k]) : kKeyNone);
       }
     }
 
@@ -331,6 +359,7 @@ __global__ __launch_bounds__(kWave) void k_fwd_chunks(FwdKernelArgs A) {
 // fixed, so the result is deterministic. A persistent grid walks the list of
 // such tiles.
 constexpr int kMergeWaves = 4;
+constexpr long long kMergeGrid = 2048;
 
 template <int CM, int KM>
 __global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(FwdKernelArgs A) {
@@ -413,7 +442,6 @@ __global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(FwdKernelArgs
 void launch_project(const Plan& q, const std::vector<SceneDev>& sc, const FwdArgs& a, char* ws,
                     hipStream_t stream);
 void launch_binning(const Plan& q, char* ws, hipStream_t stream);
-void launch_gather_records(const Plan& q, const float* payload, char* ws, hipStream_t stream);
 
 template <int CM, int KM>
 static void launch_raster_fwd_cm(const Plan& q, const FwdKernelArgs& A, hipStream_t stream) {
@@ -424,7 +452,10 @@ static void launch_raster_fwd_cm(const Plan& q, const FwdKernelArgs& A, hipStrea
     hipLaunchKernelGGL(k_fwd_background, dim3(unsigned((q.T + 3) / 4)), dim3(256), 0, stream, A);
   stage_end(PULSAR_STAGE_RASTER_FWD, stream);
   stage_begin(PULSAR_STAGE_MERGE, stream);
-  const long long mg = q.T < q.raster_grid ? q.T : q.raster_grid;
+  // merge tiles are a minority of the tiles; a grid of at most kMergeGrid
+  // blocks walks them without paying the dispatch of idle blocks
+  long long mg = q.T < q.raster_grid ? q.T : q.raster_grid;
+  if (mg > kMergeGrid) mg = kMergeGrid;
   hipLaunchKernelGGL((k_fwd_merge<CM, KM>), dim3(unsigned(mg)), dim3(kWave * kMergeWaves), 0,
                      stream, A);
   stage_end(PULSAR_STAGE_MERGE, stream);
@@ -453,7 +484,6 @@ hipError_t launch_forward(const Plan& q, const std::vector<SceneDev>& scenes, co
   stage_end(PULSAR_STAGE_PROJECT, stream);
   stage_begin(PULSAR_STAGE_BINNING, stream);
   launch_binning(q, ws, stream);
-  if (q.n > 0) launch_gather_records(q, a.payload, ws, stream);
   stage_end(PULSAR_STAGE_BINNING, stream);
   FwdKernelArgs A;
   A.tab = scene_table(q, ws);
@@ -461,8 +491,10 @@ hipError_t launch_forward(const Plan& q, const std::vector<SceneDev>& scenes, co
   A.desc = ws_ptr<uint4>(ws, q.off_desc);
   A.tinfo = ws_ptr<uint4>(ws, q.off_tinfo);
   A.mlist = ws_ptr<uint32_t>(ws, q.off_mlist);
-  A.srec = ws_ptr<float4>(ws, q.off_srec);
-  A.spay = ws_ptr<float>(ws, q.off_spay);
+  A.svals = ws_ptr<uint32_t>(ws, sorted_in_a(q) ? q.off_valsA : q.off_valsB);
+  A.rec = ws_ptr<float4>(ws, q.off_rec);
+  A.payload = a.payload;
+  A.boff = ws_ptr<unsigned long long>(ws, q.off_partials);
   A.bg = a.bg;
   A.image = a.image;
   A.aux = a.aux;
