@@ -27,6 +27,10 @@ __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcp
 // blocks: neighbouring logical blocks, which share cache lines of their
 // inputs and outputs, then meet in the same L2. A bijection on [0, nb).
 constexpr uint32_t kXcds = 8;
+
+// s_waitcnt operand (gfx9 encoding) that waits for every outstanding vector
+// memory operation, global-to-LDS loads included, and nothing else.
+constexpr int kWaitVmem0 = 0x0F70;
 __device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t nb) {
   const uint32_t x = b % kXcds, s = b / kXcds;
   const uint32_t q = nb / kXcds, r = nb % kXcds;

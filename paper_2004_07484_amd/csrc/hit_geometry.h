@@ -168,6 +168,21 @@ struct TileScene {
   int tx0, ty0;
 };
 
+// The same from the scene arrays passed as restrict kernel parameters: the
+// compiler then knows no store of the kernel can change them and reads them
+// through the scalar cache, off the vector memory queue.
+__device__ __forceinline__ TileScene tile_scene(const SceneDev* __restrict__ scenes,
+                                                const uint32_t* __restrict__ tile_start, int B,
+                                                uint32_t tile) {
+  TileScene ts;
+  ts.b = find_scene(tile_start, B, tile);
+  const int lt = int(tile - scenes[ts.b].tile_off);
+  const int tiles_x = scenes[ts.b].cam.tiles_x;
+  ts.tx0 = (lt % tiles_x) * kTileW;
+  ts.ty0 = (lt / tiles_x) * kTileH;
+  return ts;
+}
+
 __device__ __forceinline__ TileScene tile_scene(const SceneTable& tab, uint32_t tile) {
   TileScene ts;
   ts.b = find_scene(tab.tile_start, tab.B, tile);

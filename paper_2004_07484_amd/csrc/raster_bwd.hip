@@ -101,7 +101,8 @@ constexpr int bwd_waves_per_simd(int CM) { return CM <= 8 ? 5 : 1; }
 
 template <int CM>
 __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_bwd_items(
-    BwdKernelArgs A) {
+    BwdKernelArgs A, const SceneDev* __restrict__ scenes, const uint32_t* __restrict__ tile_start,
+    const uint4* __restrict__ desc) {
   __shared__ TileRays s_ray;
   __shared__ float s_G[CM][kWave];
   __shared__ float s_L2[kWave], s_GF[kWave], s_tk[kWave];
@@ -110,11 +111,11 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
   const int C = A.C;
   const uint32_t nchunks = A.status->nchunks;
   for (uint32_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
-    const uint4 dsc = A.desc[chunk];
+    const uint4 dsc = desc[chunk];
     const uint32_t tile = dsc.x & ~kFirstChunk;
     const uint32_t beg = dsc.y, end = dsc.z;
-    const TileScene ts = tile_scene(A.tab, tile);
-    const SceneDev& sc = A.tab.scenes[ts.b];
+    const TileScene ts = tile_scene(scenes, tile_start, A.tab.B, tile);
+    const SceneDev& sc = scenes[ts.b];
     const CamDev cam = sc.cam;
     const BlendConst bc = sc.bc;
     // the thread's first record and payload row are requested before the
@@ -135,29 +136,41 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
       rd = rp[3];
       bo = uint32_t(A.boff[sph / kProjectBlock]);
       const float* fp = A.payload + size_t(sph) * size_t(C);
+      // unconditional loads (clamped to the row), so they issue together
 #pragma unroll
-      for (int c = 0; c < CM; ++c) f[c] = c < C ? fp[c] : 0.f;
+      for (int c = 0; c < CM; ++c) f[c] = fp[min(c, C - 1)];
+#pragma unroll
+      for (int c = 0; c < CM; ++c) f[c] = c < C ? f[c] : 0.f;
     };
     const int ttx = ts.tx0 / kTileW, tty = ts.ty0 / kTileH;  // the tile, in tile units
     if (j < end) load_record(j);
     __syncthreads();  // the previous item's readers are done with the LDS
     if (tid < kWave) {
+      // every load unconditional (pixels outside the image read one inside
+      // it and are masked; channels are clamped), so they issue together
       const int px = ts.tx0 + (tid % kTileW), py = ts.ty0 + (tid / kTileW);
       const bool inside = px < cam.W && py < cam.H;
-      const size_t p =
-          inside ? size_t(sc.pix_off) + size_t(py) * size_t(cam.W) + size_t(px) : 0;
+      const size_t p = size_t(sc.pix_off) + (inside ? size_t(py) * size_t(cam.W) + size_t(px)
+                                                    : size_t(ts.ty0) * size_t(cam.W) +
+                                                          size_t(ts.tx0));
+      const float aux = A.aux[p];
+      const float2 th = A.thr[p];
+      float gi[CM], fi[CM];
+#pragma unroll
+      for (int c = 0; c < CM; ++c) {
+        gi[c] = A.grad_image[p * size_t(C) + size_t(min(c, C - 1))];
+        fi[c] = A.image[p * size_t(C) + size_t(min(c, C - 1))];
+      }
       store_ray(s_ray, tid, make_ray(cam, px, py));
-      s_L2[tid] = inside ? A.aux[p] * 1.4426950408889634f : 0.f;
-      const float2 th = inside ? A.thr[p] : make_float2(-INFINITY, 0.f);
-      s_tk[tid] = th.x;
-      s_ik[tid] = __float_as_uint(th.y);
+      s_L2[tid] = inside ? aux * 1.4426950408889634f : 0.f;
+      s_tk[tid] = inside ? th.x : -INFINITY;
+      s_ik[tid] = inside ? __float_as_uint(th.y) : 0u;
       float gf = 0.f;
 #pragma unroll
       for (int c = 0; c < CM; ++c) {
-        const float g = (inside && c < C) ? A.grad_image[p * size_t(C) + c] : 0.f;
-        const float f = (inside && c < C) ? A.image[p * size_t(C) + c] : 0.f;
+        const float g = (inside && c < C) ? gi[c] : 0.f;
         s_G[c][tid] = g;
-        gf += g * f;
+        gf += g * ((inside && c < C) ? fi[c] : 0.f);
       }
       s_GF[tid] = gf;
     }
@@ -223,7 +236,10 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
 
 // Channels beyond the register budget: same walk, the pixel terms read from
 // global memory and payload gradients go out per hit.
-__global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A) {
+__global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A,
+                                                           const SceneDev* __restrict__ scenes,
+                                                           const uint32_t* __restrict__ tile_start,
+                                                           const uint4* __restrict__ desc) {
   __shared__ TileRays s_ray;
   __shared__ float s_L2[kWave], s_tk[kWave];
   __shared__ uint32_t s_ik[kWave];
@@ -231,11 +247,11 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A) {
   const int C = A.C;
   const uint32_t nchunks = A.status->nchunks;
   for (uint32_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
-    const uint4 dsc = A.desc[chunk];
+    const uint4 dsc = desc[chunk];
     const uint32_t tile = dsc.x & ~kFirstChunk;
     const uint32_t beg = dsc.y, end = dsc.z;
-    const TileScene ts = tile_scene(A.tab, tile);
-    const SceneDev& sc = A.tab.scenes[ts.b];
+    const TileScene ts = tile_scene(scenes, tile_start, A.tab.B, tile);
+    const SceneDev& sc = scenes[ts.b];
     const CamDev cam = sc.cam;
     const BlendConst bc = sc.bc;
     const int tx0 = ts.tx0, ty0 = ts.ty0;
@@ -659,20 +675,26 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
   stage_begin(PULSAR_STAGE_RASTER_BWD, stream);
   const dim3 ig{unsigned(q.raster_grid), 1u, 1u}, it{unsigned(kWave * kBwdWaves), 1u, 1u};
   if (a.C <= 1)
-    hipLaunchKernelGGL(k_bwd_items<1>, ig, it, 0, stream, A);
+    hipLaunchKernelGGL(k_bwd_items<1>, ig, it, 0, stream, A, A.tab.scenes, A.tab.tile_start,
+                       A.desc);
   else if (a.C <= 2)
-    hipLaunchKernelGGL(k_bwd_items<2>, ig, it, 0, stream, A);
+    hipLaunchKernelGGL(k_bwd_items<2>, ig, it, 0, stream, A, A.tab.scenes, A.tab.tile_start,
+                       A.desc);
   else if (a.C <= 4)
-    hipLaunchKernelGGL(k_bwd_items<4>, ig, it, 0, stream, A);
+    hipLaunchKernelGGL(k_bwd_items<4>, ig, it, 0, stream, A, A.tab.scenes, A.tab.tile_start,
+                       A.desc);
   else if (a.C <= 8)
-    hipLaunchKernelGGL(k_bwd_items<8>, ig, it, 0, stream, A);
+    hipLaunchKernelGGL(k_bwd_items<8>, ig, it, 0, stream, A, A.tab.scenes, A.tab.tile_start,
+                       A.desc);
   else if (a.C <= 16)
-    hipLaunchKernelGGL(k_bwd_items<16>, ig, it, 0, stream, A);
+    hipLaunchKernelGGL(k_bwd_items<16>, ig, it, 0, stream, A, A.tab.scenes, A.tab.tile_start,
+                       A.desc);
   else if (!wide)
-    hipLaunchKernelGGL(k_bwd_items<32>, ig, it, 0, stream, A);
+    hipLaunchKernelGGL(k_bwd_items<32>, ig, it, 0, stream, A, A.tab.scenes, A.tab.tile_start,
+                       A.desc);
   else
     hipLaunchKernelGGL(k_bwd_chunks_wide, dim3(unsigned(q.raster_grid)), dim3(kWave), 0, stream,
-                       A);
+                       A, A.tab.scenes, A.tab.tile_start, A.desc);
   stage_end(PULSAR_STAGE_RASTER_BWD, stream);
   stage_begin(PULSAR_STAGE_FINALIZE, stream);
   if (a.grad_bg && wide) {

@@ -157,12 +157,15 @@ __global__ __launch_bounds__(256) void k_fwd_background(FwdKernelArgs A) {
 constexpr int fwd_waves_per_simd(int CM, int KM) { return (CM <= 8 && KM <= 8) ? 4 : 1; }
 
 template <int CM, int KM>
-__global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM)) void k_fwd_chunks(FwdKernelArgs A) {
-  // the batch's records and payloads, padded rows so that lanes reading
-  // different records mostly hit different banks
-  constexpr int CQ = (CM + 3) / 4;
-  __shared__ float4 s_rec[kWave][5];
-  __shared__ float4 s_pay[kWave][CQ + 1];
+__global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM)) void k_fwd_chunks(
+    FwdKernelArgs A, const SceneDev* __restrict__ scenes, const uint32_t* __restrict__ tile_start,
+    const uint4* __restrict__ desc) {
+  // the batch's records (part-major: s_rec[q][r] is float4 q of record r)
+  // and payloads (channel-major: s_pay[c][r]); both are filled by
+  // global-to-LDS loads, one instruction per record part or channel with
+  // lane r fetching record r, so no registers hold them on the way
+  __shared__ float4 s_rec[4][kWave];
+  __shared__ float s_pay[CM][kWave];
   __shared__ uint32_t s_id[kWave];
   __shared__ unsigned long long s_mask[kWave];
   __shared__ float s_iv2[kWave];
@@ -172,14 +175,18 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM)) void k_fwd_chunk
   __shared__ unsigned long long s_start[kWave];
   const int lane = threadIdx.x;
   s_start[lane] = 0ull;
+  // channels past this pass's width are never loaded: keep them zero
+#pragma unroll
+  for (int c = 0; c < CM; ++c)
+    if (c >= A.cn) s_pay[c][lane] = 0.f;
   const uint32_t nchunks = A.status->nchunks;
   for (uint32_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
-    const uint4 dsc = A.desc[chunk];
+    const uint4 dsc = desc[chunk];
     const uint32_t tile = dsc.x & ~kFirstChunk;
     const bool first = (dsc.x & kFirstChunk) != 0u;
     const uint32_t beg = dsc.y, end = dsc.z, slot = dsc.w;
-    const TileScene ts = tile_scene(A.tab, tile);
-    const SceneDev& sc = A.tab.scenes[ts.b];
+    const TileScene ts = tile_scene(scenes, tile_start, A.tab.B, tile);
+    const SceneDev& sc = scenes[ts.b];
     const CamDev cam = sc.cam;
     const BlendConst bc = sc.bc;
     const int tx0 = ts.tx0, ty0 = ts.ty0;
@@ -197,22 +204,30 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM)) void k_fwd_chunk
     klist_init(kk, A.K);
 
     const int ttx = tx0 / kTileW, tty = ty0 / kTileH;  // the tile, in tile units
+    // the sorted pairs name their spheres, whose records and payload rows are
+    // read in place; lanes past the end repeat the last pair, so every load
+    // is unconditional. The next batch's sphere indices are requested with
+    // this batch's records, so a batch costs one round trip after the first.
+    uint32_t sph_next = A.svals[min(beg + uint32_t(lane), end - 1u)];
     for (uint32_t b0 = beg; b0 < end; b0 += kWave) {
       const uint32_t j = b0 + uint32_t(lane);
       const bool valid = j < end;
-      float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, c = a, d = a;
-      uint32_t id = 0, sph = 0;
-      if (valid) {
-        // the sorted pair names its sphere; the record is read in place
-        sph = A.svals[j];
-        const float4* rp = A.rec + 4 * size_t(sph);
-        a = rp[0];
-        b = rp[1];
-        c = rp[2];
-        d = rp[3];
-        // pair position: orders spheres like their index
-        id = pair_position(a, d, uint32_t(A.boff[sph / kProjectBlock]), ttx, tty);
-      }
+      const uint32_t sph = sph_next;
+      if (b0 + kWave < end) sph_next = A.svals[min(j + uint32_t(kWave), end - 1u)];
+      __syncthreads();  // previous batch done with s_rec / s_pay / s_mask
+      const float4* rp = A.rec + 4 * size_t(sph);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) __builtin_amdgcn_global_load_lds(rp + q, &s_rec[q][0], 16, 0, 0);
+      const float* fp = A.payload + size_t(sph) * size_t(A.C) + A.c0;
+#pragma unroll
+      for (int c = 0; c < CM; ++c)
+        if (c < A.cn) __builtin_amdgcn_global_load_lds(fp + c, &s_pay[c][0], 4, 0, 0);
+      const uint32_t bo = uint32_t(A.boff[sph / kProjectBlock]);
+      __builtin_amdgcn_s_waitcnt(kWaitVmem0);
+      __syncthreads();
+      const float4 a = s_rec[0][lane], d = s_rec[3][lane];
+      // pair position: orders spheres like their index
+      const uint32_t id = valid ? pair_position(a, d, bo, ttx, tty) : 0u;
       // the sphere's rectangle inside this tile, in tile coordinates; the
       // (sphere, pixel) pairs are flattened over the wave by a prefix sum
       const uint32_t p0 = __float_as_uint(a.w), p1 = __float_as_uint(d.z);
@@ -225,27 +240,11 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM)) void k_fwd_chunk
       const uint32_t incl = wave_incl_scan_u32(n, lane);
       const uint32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
       const uint32_t magic = (65536u + w - 1u) / w;  // i / w = (i * magic) >> 16 for i < 64
-      __syncthreads();  // previous batch done with s_rec / s_pay / s_mask
       s_ob[lane] = make_uint2(incl - n,
                               uint32_t(xa) | (uint32_t(ya) << 3) | (w << 6) | (magic << 10));
       if (n != 0u) atomicOr(&s_start[(incl - n) >> 6], 1ull << ((incl - n) & 63u));
       s_mask[lane] = 0ull;
       s_id[lane] = id;
-      s_rec[lane][0] = a;
-      s_rec[lane][1] = b;
-      s_rec[lane][2] = c;
-      s_rec[lane][3] = d;
-      const float* fp = A.payload + size_t(sph) * size_t(A.C) + A.c0;
-#pragma unroll
-      for (int q = 0; q < CQ; ++q) {
-        float v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const int ch = 4 * q + u;
-          v[u] = (valid && ch < A.cn) ? fp[ch] : 0.f;
-        }
-        s_pay[lane][q] = make_float4(v[0], v[1], v[2], v[3]);
-      }
       __syncthreads();
       // A. every (record, pixel of its rectangle) pair, 64 at a time. Valid
       // records own at least one pair each, so the owner of a pair is the
@@ -263,7 +262,7 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM)) void k_fwd_chunk
         const uint32_t bw = (box >> 6) & 15u, yy = (i * (box >> 10)) >> 16;
         const int x = int(box & 7u) + int(i - yy * bw), y = int((box >> 3) & 7u) + int(yy);
         const int pl = y * kTileW + x;
-        const float4 ra = s_rec[r][0], rb = s_rec[r][1];
+        const float4 ra = s_rec[0][r], rb = s_rec[1][r];
         const uint32_t pk = __float_as_uint(ra.w);
         const float dx = float(tx0 + x - int(pk & 0xffffu)) - ra.x;
         const float dy = float(ty0 + y - int(pk >> 16)) - ra.y;
@@ -287,7 +286,7 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM)) void k_fwd_chunk
         const bool act = hits != 0ull;
         const int k = act ? __builtin_ctzll(hits) : 0;
         hits &= hits - 1ull;
-        const SphereRec s = unpack_rec(s_rec[k][0], s_rec[k][1], s_rec[k][2], s_rec[k][3]);
+        const SphereRec s = unpack_rec(s_rec[0][k], s_rec[1][k], s_rec[2][k], s_rec[3][k]);
         Hit h;
         const bool hit = exact_hit(ray, s, bc.zfar, h) && act;
         const float s2 = s.o * (bc.zfar - h.t) * bc.kz;
@@ -301,15 +300,9 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM)) void k_fwd_chunk
         }
         const float wgt = hit ? s.o * h.delta * fast_exp2(s2 - m2) : 0.f;
         D += wgt;
-        float fv[4 * CQ];
+        float fv[CM];
 #pragma unroll
-        for (int q = 0; q < CQ; ++q) {
-          const float4 f = s_pay[k][q];
-          fv[4 * q + 0] = f.x;
-          fv[4 * q + 1] = f.y;
-          fv[4 * q + 2] = f.z;
-          fv[4 * q + 3] = f.w;
-        }
+        for (int c = 0; c < CM; ++c) fv[c] = s_pay[c][k];
         // a miss adds nothing, even against a non-finite payload
 #pragma unroll
         for (int c = 0; c < CM; ++c) N[c] = hit ? fmaf(wgt, fv[c], N[c]) : N[c];
@@ -362,14 +355,16 @@ constexpr int kMergeWaves = 4;
 constexpr long long kMergeGrid = 2048;
 
 template <int CM, int KM>
-__global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(FwdKernelArgs A) {
+__global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(
+    FwdKernelArgs A, const SceneDev* __restrict__ scenes, const uint32_t* __restrict__ tile_start,
+    const uint4* __restrict__ tinfo) {
   constexpr int NF = 2 + CM + 2 * KM;  // m, D, numerator[CM], K-list t[KM], id[KM]
   __shared__ float s_state[kMergeWaves - 1][NF][kWave];
   const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
   const uint32_t nmerge = A.status->nmerge;
   for (uint32_t mi = blockIdx.x; mi < nmerge; mi += gridDim.x) {
     const int tile = int(A.mlist[mi]);
-    const uint4 ti = A.tinfo[tile];
+    const uint4 ti = tinfo[tile];
     if ((long long)ti.x + ti.y > A.pcap) continue;  // capacity exceeded (reported)
     float m2 = -INFINITY, D = 0.f, N[CM];
     uint64_t kk[KM];
@@ -431,8 +426,8 @@ __global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(FwdKernelArgs
         for (int f = 0; f < NF; ++f) st[f] = s_state[w][f][lane];
         fold(st);
       }
-      const TileScene ts = tile_scene(A.tab, uint32_t(tile));
-      const SceneDev& sc = A.tab.scenes[ts.b];
+      const TileScene ts = tile_scene(scenes, tile_start, A.tab.B, uint32_t(tile));
+      const SceneDev& sc = scenes[ts.b];
       write_pixel(A, sc.cam, sc.pix_off, ts.tx0 + lane % kTileW, ts.ty0 + lane / kTileW, m2, D,
                   N, kk);
     }
@@ -447,7 +442,7 @@ template <int CM, int KM>
 static void launch_raster_fwd_cm(const Plan& q, const FwdKernelArgs& A, hipStream_t stream) {
   stage_begin(PULSAR_STAGE_RASTER_FWD, stream);
   hipLaunchKernelGGL((k_fwd_chunks<CM, KM>), dim3(unsigned(q.raster_grid)), dim3(kWave), 0,
-                     stream, A);
+                     stream, A, A.tab.scenes, A.tab.tile_start, A.desc);
   if (!A.fill_in_tail)
     hipLaunchKernelGGL(k_fwd_background, dim3(unsigned((q.T + 3) / 4)), dim3(256), 0, stream, A);
   stage_end(PULSAR_STAGE_RASTER_FWD, stream);
@@ -457,7 +452,7 @@ static void launch_raster_fwd_cm(const Plan& q, const FwdKernelArgs& A, hipStrea
   long long mg = q.T < q.raster_grid ? q.T : q.raster_grid;
   if (mg > kMergeGrid) mg = kMergeGrid;
   hipLaunchKernelGGL((k_fwd_merge<CM, KM>), dim3(unsigned(mg)), dim3(kWave * kMergeWaves), 0,
-                     stream, A);
+                     stream, A, A.tab.scenes, A.tab.tile_start, A.tinfo);
   stage_end(PULSAR_STAGE_MERGE, stream);
 }
 
