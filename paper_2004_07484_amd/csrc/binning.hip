@@ -1,5 +1,6 @@
-// Tile binning: K2 scan of per-sphere tile counts, K3 emission of
-// (tile, depth) keys, K4 LSD radix sort, K5 per-tile ranges.
+// Tile binning: K3 emission of (tile, depth) keys (each block first sums the
+// projection's per-block tile counts before it), K4 LSD radix sort, K5
+// per-tile ranges and the work-item plan.
 //
 // The paper sorts all spheres by their earliest possible hit depth and then
 // filters them per image region (App. B, Step 0 and Step 1). Here the same
@@ -11,68 +12,48 @@
 
 namespace pulsar {
 
-// ---------------------------------------------------------------- K2 scan
-// Single block: exclusive scan of the per-block sums in place; writes the
-// total pair count and the capacity status. Thread t owns a run of
-// consecutive entries, loaded together, so one pass over the block suffices
-// for up to kScanThreads * kScanRun entries (more take further passes).
-constexpr int kScanRun = 8;
-__global__ __launch_bounds__(kScanThreads) void k_scan_partials(
-    unsigned long long* __restrict__ partials, int nblk, long long cap,
-    Status* __restrict__ status) {
-  __shared__ unsigned long long s_wave[kScanThreads / kWave];
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-  unsigned long long carry = 0;
-  for (int base = 0; base < nblk; base += kScanThreads * kScanRun) {
-    const int i0 = base + tid * kScanRun;
-    unsigned long long v[kScanRun];
-    unsigned long long run = 0;
-#pragma unroll
-    for (int k = 0; k < kScanRun; ++k) {
-      v[k] = i0 + k < nblk ? partials[i0 + k] : 0ull;
-      run += v[k];
-    }
-    const unsigned long long incl = wave_incl_scan_u64(run, lane);
-    if (lane == kWave - 1) s_wave[wid] = incl;
-    __syncthreads();
-    unsigned long long before = 0, total = 0;
-    for (int w = 0; w < kScanThreads / kWave; ++w) {
-      const unsigned long long x = s_wave[w];
-      if (w < wid) before += x;
-      total += x;
-    }
-    unsigned long long at = carry + before + incl - run;
-#pragma unroll
-    for (int k = 0; k < kScanRun; ++k) {
-      if (i0 + k < nblk) partials[i0 + k] = at;
-      at += v[k];
-    }
-    carry += total;
-    __syncthreads();
-  }
-  if (tid == 0) {
-    status->pairs = carry;
-    status->used = uint32_t(carry < (unsigned long long)cap ? carry : (unsigned long long)cap);
-    status->code = carry > (unsigned long long)cap ? uint32_t(-PULSAR_ERR_CAPACITY) : 0u;
-  }
-}
-
 // ---------------------------------------------------------------- K3 emit
 // Block b re-scans the tile counts of its spheres and writes one
-// (key, sphere id) pair per touched tile, dropping pairs beyond capacity.
+// (key, sphere id) pair per touched tile, dropping pairs beyond capacity. It
+// also records its first emission position (boff, read by the raster
+// kernels to place pairs), and the last block writes the pair total and the
+// capacity status.
 __global__ __launch_bounds__(kProjectBlock) void k_emit(
     int n, const uint32_t* __restrict__ counts, const ushort4* __restrict__ trect,
     const uint32_t* __restrict__ qdepth, const unsigned long long* __restrict__ partials,
+    unsigned long long* __restrict__ boff, Status* __restrict__ status,
     SceneTable tab, int depth_bits, long long cap, uint32_t* __restrict__ keys,
     uint32_t* __restrict__ vals, uint32_t* __restrict__ sfirst) {
-  __shared__ unsigned long long s_wave[kProjectBlock / kWave];
+  __shared__ unsigned long long s_wave[kProjectBlock / kWave], s_pre[kProjectBlock / kWave];
   const int i = blockIdx.x * kProjectBlock + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
   const uint32_t c = i < n ? counts[i] : 0u;
+  // this block's first emission position: the sum of the projection block
+  // sums before it (a few KB, read from cache by every block, so no
+  // separate scan launch is needed)
+  unsigned long long pre = 0;
+  for (int k = threadIdx.x; k < int(blockIdx.x); k += kProjectBlock) pre += partials[k];
+  pre = wave_sum_u64(pre);
   const unsigned long long incl = wave_incl_scan_u64(c, lane);
   if (lane == kWave - 1) s_wave[wid] = incl;
+  if (lane == 0) s_pre[wid] = pre;
   __syncthreads();
-  unsigned long long before = partials[blockIdx.x];
+  unsigned long long before = 0, btot = 0;
+#pragma unroll
+  for (int w = 0; w < kProjectBlock / kWave; ++w) {
+    before += s_pre[w];
+    btot += s_wave[w];
+  }
+  if (threadIdx.x == 0) {
+    boff[blockIdx.x] = before;
+    if (blockIdx.x == gridDim.x - 1) {
+      // the last block knows the total number of pairs
+      const unsigned long long total = before + btot;
+      status->pairs = total;
+      status->used = uint32_t(total < (unsigned long long)cap ? total : (unsigned long long)cap);
+      status->code = total > (unsigned long long)cap ? uint32_t(-PULSAR_ERR_CAPACITY) : 0u;
+    }
+  }
   for (int w = 0; w < wid; ++w) before += s_wave[w];
   if (c == 0) return;
   unsigned long long at = before + incl - c;
@@ -402,14 +383,13 @@ void launch_binning(const Plan& q, char* ws, hipStream_t stream) {
   uint32_t* vB = ws_ptr<uint32_t>(ws, q.off_valsB);
   uint32_t* hist = ws_ptr<uint32_t>(ws, q.off_hist);
   uint32_t* dtot = ws_ptr<uint32_t>(ws, q.off_dtot);
-  hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(kScanThreads), 0, stream, partials,
-                     q.nblk_proj, (long long)q.cap, status);
-  if (q.n > 0)
-    hipLaunchKernelGGL(k_emit, dim3(q.nblk_proj), dim3(kProjectBlock), 0, stream, int(q.n),
-                       ws_ptr<uint32_t>(ws, q.off_counts), ws_ptr<ushort4>(ws, q.off_trect),
-                       ws_ptr<uint32_t>(ws, q.off_qdepth), partials, scene_table(q, ws),
-                       q.depth_bits, (long long)q.cap, kA, vA,
-                       ws_ptr<uint32_t>(ws, q.off_sfirst));
+  // with no spheres one block still runs, to write the (empty) status
+  hipLaunchKernelGGL(k_emit, dim3(q.nblk_proj > 0 ? unsigned(q.nblk_proj) : 1u),
+                     dim3(kProjectBlock), 0, stream, int(q.n), ws_ptr<uint32_t>(ws, q.off_counts),
+                     ws_ptr<ushort4>(ws, q.off_trect), ws_ptr<uint32_t>(ws, q.off_qdepth),
+                     partials, ws_ptr<unsigned long long>(ws, q.off_boff), status,
+                     scene_table(q, ws), q.depth_bits, (long long)q.cap, kA, vA,
+                     ws_ptr<uint32_t>(ws, q.off_sfirst));
   for (int p = 0; p < q.passes; ++p) {
     const int shift = 8 * p;
     const uint32_t* kin = (p % 2 == 0) ? kA : kB;

@@ -188,6 +188,7 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   q.off_qdepth = take(nn * 4);
   q.off_rec = take(nn * 64);
   q.off_partials = take(size_t(q.nblk_proj + 1) * 8);
+  q.off_boff = take(size_t(q.nblk_proj + 1) * 8);
   q.off_keysA = take(size_t(cap) * 4);
   q.off_valsA = take(size_t(cap) * 4);
   q.off_keysB = take(size_t(cap) * 4);
@@ -236,6 +237,10 @@ CamDev make_cam(const pulsar_camera_t* c) {
   d.sh = float(double(c->sensor_width) * double(c->height) / double(c->width));
   d.tiles_x = (c->width + kTileW - 1) / kTileW;
   d.tiles_y = (c->height + kTileH - 1) / kTileH;
+  d.dpitch = double(c->sensor_width) / double(c->width);
+  d.dinv_pitch = double(c->width) / double(c->sensor_width);
+  d.dsh = double(c->sensor_width) * double(c->height) / double(c->width);
+  d.dhalf_sh = 0.5 * double(c->sensor_width) * double(c->height) / double(c->width);
   return d;
 }
 

@@ -52,9 +52,9 @@ __device__ __forceinline__ PixelRay make_ray(const CamDev& cam, int px, int py) 
   r.ux = r.xs * inv_len;
   r.uy = r.ys * inv_len;
   r.uz = cam.f * inv_len;
-  const double pitch = double(cam.s) / double(cam.W);
+  const double pitch = cam.dpitch;
   const double xs = (double(px) + 0.5) * pitch - 0.5 * double(cam.s);
-  const double ys = (double(py) + 0.5) * pitch - 0.5 * double(cam.s) * double(cam.H) / double(cam.W);
+  const double ys = (double(py) + 0.5) * pitch - cam.dhalf_sh;
   r.inv_v2_d = 1.0 / (xs * xs + ys * ys + double(cam.f) * double(cam.f));
   return r;
 }

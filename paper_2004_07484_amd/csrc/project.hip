@@ -126,9 +126,9 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
     const double cz = double(cam.R[6]) * px + double(cam.R[7]) * py + double(cam.R[8]) * pz +
                       double(cam.t[2]);
     const double f = cam.f;
-    const double pitch = double(cam.s) / double(cam.W);
-    const double inv_pitch = double(cam.W) / double(cam.s);
-    const double sh = double(cam.s) * double(cam.H) / double(cam.W);
+    const double pitch = cam.dpitch;
+    const double inv_pitch = cam.dinv_pitch;
+    const double sh = cam.dsh;
     double R = r;
     if (min_radius_px > 0.f) {
       const double rmin = double(min_radius_px) * pitch * cz / f;

@@ -16,7 +16,6 @@ constexpr int kTileW = 8;
 constexpr int kTileH = 8;
 constexpr int kWave = 64;
 constexpr int kProjectBlock = 256;           // spheres per projection block
-constexpr int kScanThreads = 1024;           // single-block scan of block sums
 constexpr int kSortThreads = 256;
 constexpr int kSortRounds = 4;
 constexpr int kSortBlock = kSortThreads * kSortRounds;  // keys per sort block
@@ -51,6 +50,12 @@ struct CamDev {
   float pitch;  // s / W
   float sh;     // sensor height s H / W
   int W, H, tiles_x, tiles_y;
+  // FP64 camera constants, computed once on the host with the same
+  // expressions the kernels would evaluate (so the results are identical)
+  double dpitch;      // s / W
+  double dinv_pitch;  // W / s
+  double dsh;         // s H / W
+  double dhalf_sh;    // 0.5 s H / W
 };
 
 // Blend constants of Eq. 1 in base-2 exponent units.
@@ -91,7 +96,7 @@ struct Plan {
   int B, chunk, raster_grid;
   int tile_bits, depth_bits, passes, nblk_proj, nblk_sort;
   size_t off_status, off_counts, off_trect, off_qdepth, off_rec;
-  size_t off_partials, off_keysA, off_valsA, off_keysB, off_valsB, off_hist, off_dtot;
+  size_t off_partials, off_boff, off_keysA, off_valsA, off_keysB, off_valsB, off_hist, off_dtot;
   size_t off_ranges;
   // raster work items: per tile uint4 (first partial-state slot, chunks, 0, 0);
   // the work list uint4 (tile | kFirstChunk, begin, end, slot or kNoSlot);

@@ -648,7 +648,7 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
   A.desc = ws_ptr<uint4>(ws, q.off_desc);
   A.rec = ws_ptr<float4>(ws, q.off_rec);
   A.payload = a.payload;
-  A.boff = ws_ptr<unsigned long long>(ws, q.off_partials);
+  A.boff = ws_ptr<unsigned long long>(ws, q.off_boff);
   A.image = a.image;
   A.aux = a.aux;
   A.grad_image = a.grad_image;

@@ -489,7 +489,7 @@ hipError_t launch_forward(const Plan& q, const std::vector<SceneDev>& scenes, co
   A.svals = ws_ptr<uint32_t>(ws, sorted_in_a(q) ? q.off_valsA : q.off_valsB);
   A.rec = ws_ptr<float4>(ws, q.off_rec);
   A.payload = a.payload;
-  A.boff = ws_ptr<unsigned long long>(ws, q.off_partials);
+  A.boff = ws_ptr<unsigned long long>(ws, q.off_boff);
   A.bg = a.bg;
   A.image = a.image;
   A.aux = a.aux;
