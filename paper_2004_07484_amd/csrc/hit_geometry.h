@@ -132,6 +132,16 @@ __device__ __forceinline__ bool exact_hit(const PixelRay& ray, const SphereRec& 
   return ok && (t <= zfar);
 }
 
+// A lower bound on the distance t of any front hit of the sphere: every ray
+// meets the sphere no closer than its nearest point, |c| - R (for a ray at
+// distance q from the centre, t = sqrt(|c|^2 - q^2) - sqrt(R^2 - q^2) grows
+// with q). Lowered by 1e-4 |c|, far beyond the FP32 rounding of both this
+// bound and exact_hit's t, so it never exceeds a computed t.
+__device__ __forceinline__ float front_bound(const SphereRec& s) {
+  const float cn = s.cz * fast_sqrt(s.axh * s.axh + s.ayh * s.ayh + 1.f);
+  return (cn - s.R) - 1e-4f * cn;
+}
+
 // The same ray as make_ray, from per-tile LDS copies of its fields.
 struct TileRays {
   float xs[kWave], ys[kWave], ux[kWave], uy[kWave], uz[kWave], iv2[kWave];

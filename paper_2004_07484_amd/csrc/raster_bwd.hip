@@ -187,13 +187,16 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
       for (int c = 0; c < CM; ++c) gf[c] = 0.f;
       float gcx = 0.f, gcy = 0.f, gcz = 0.f, gR = 0.f, go = 0.f;
       uint32_t nh = 0;
+      const float tlo = front_bound(s);
       for (int py = ya; py <= yb; ++py) {
         for (int px = xa; px <= xb; ++px) {
           const int pl = (py - ts.ty0) * kTileW + (px - ts.tx0);
+          const float tk = s_tk[pl];
+          // behind the pixel's K-th nearest hit: no gradient, no test needed
+          if (tlo > tk) continue;
           const PixelRay ray = load_ray(s_ray, pl, px, py);
           Hit h;
           if (!exact_hit(ray, s, bc.zfar, h)) continue;
-          const float tk = s_tk[pl];
           const uint32_t ik = s_ik[pl];
           if (!(id == ik || h.t < tk || (h.t == tk && id < ik))) continue;
           float hs = -s_GF[pl];  // G . (f_k - F)
@@ -281,13 +284,15 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A,
       float gcx = 0.f, gcy = 0.f, gcz = 0.f, gR = 0.f, go = 0.f;
       const int xa = max(s.x0, tx0), xb = min(int(p1 & 0xffffu), tx0 + kTileW - 1);
       const int ya = max(s.y0, ty0), yb = min(int(p1 >> 16), ty0 + kTileH - 1);
+      const float tlo = front_bound(s);
       for (int iy = ya; iy <= yb; ++iy) {
         for (int ix = xa; ix <= xb; ++ix) {
           const int pl = (iy - ty0) * kTileW + (ix - tx0);
+          const float tk = s_tk[pl];
+          if (tlo > tk) continue;  // behind the K-th nearest hit
           const PixelRay ray = load_ray(s_ray, pl, ix, iy);
           Hit h;
           if (!exact_hit(ray, s, bc.zfar, h)) continue;
-          const float tk = s_tk[pl];
           const uint32_t ik = s_ik[pl];
           if (!(slot == ik || h.t < tk || (h.t == tk && slot < ik))) continue;
           const size_t pp = size_t(sc.pix_off) + size_t(iy) * size_t(cam.W) + size_t(ix);
