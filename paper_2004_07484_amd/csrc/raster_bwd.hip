@@ -678,7 +678,10 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
                        int(q.n), counts, a.C, a.grad_payload);
   stage_end(PULSAR_STAGE_ZERO, stream);
   stage_begin(PULSAR_STAGE_RASTER_BWD, stream);
-  const dim3 ig{unsigned(q.raster_grid), 1u, 1u}, it{unsigned(kWave * kBwdWaves), 1u, 1u};
+  // as many waves as the forward's grid of one-wave blocks: blocks past the
+  // work items would only be dispatched after them to find nothing to do
+  const long long bg = q.raster_grid / kBwdWaves > 0 ? q.raster_grid / kBwdWaves : 1;
+  const dim3 ig{unsigned(bg), 1u, 1u}, it{unsigned(kWave * kBwdWaves), 1u, 1u};
   if (a.C <= 1)
     hipLaunchKernelGGL(k_bwd_items<1>, ig, it, 0, stream, A, A.tab.scenes, A.tab.tile_start,
                        A.desc);
