@@ -51,6 +51,29 @@ __device__ __forceinline__ void klist_insert(uint64_t (&kk)[KM], uint64_t key) {
   kk[0] = lt[0] ? key : kk[0];
 }
 
+// kk := the KM smallest keys of kk and b, ascending (both ascending): the
+// elementwise minimum of kk and reversed b is a bitonic sequence holding
+// exactly those keys, which a bitonic half-cleaner network then sorts.
+// Keys are unique apart from kKeyNone, so the result equals inserting every
+// key of b one by one.
+template <int KM>
+__device__ __forceinline__ void klist_merge(uint64_t (&kk)[KM], const uint64_t (&b)[KM]) {
+#pragma unroll
+  for (int i = 0; i < KM; ++i) kk[i] = kk[i] < b[KM - 1 - i] ? kk[i] : b[KM - 1 - i];
+#pragma unroll
+  for (int d = KM / 2; d > 0; d /= 2) {
+#pragma unroll
+    for (int i = 0; i < KM; ++i) {
+      if ((i & d) == 0) {
+        const uint64_t lo = kk[i] < kk[i + d] ? kk[i] : kk[i + d];
+        const uint64_t hi = kk[i] < kk[i + d] ? kk[i + d] : kk[i];
+        kk[i] = lo;
+        kk[i + d] = hi;
+      }
+    }
+  }
+}
+
 template <int KM>
 __device__ __forceinline__ void klist_init(uint64_t (&kk)[KM], int K) {
 #pragma unroll
@@ -357,13 +380,13 @@ constexpr long long kMergeGrid = 2048;
 template <int CM, int KM>
 __global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(
     FwdKernelArgs A, const SceneDev* __restrict__ scenes, const uint32_t* __restrict__ tile_start,
-    const uint4* __restrict__ tinfo) {
+    const uint4* __restrict__ tinfo, const uint32_t* __restrict__ mlist) {
   constexpr int NF = 2 + CM + 2 * KM;  // m, D, numerator[CM], K-list t[KM], id[KM]
   __shared__ float s_state[kMergeWaves - 1][NF][kWave];
   const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
   const uint32_t nmerge = A.status->nmerge;
   for (uint32_t mi = blockIdx.x; mi < nmerge; mi += gridDim.x) {
-    const int tile = int(A.mlist[mi]);
+    const int tile = int(mlist[mi]);
     const uint4 ti = tinfo[tile];
     if ((long long)ti.x + ti.y > A.pcap) continue;  // capacity exceeded (reported)
     float m2 = -INFINITY, D = 0.f, N[CM];
@@ -390,12 +413,15 @@ __global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(
         m2 = mm;
       }
       if (A.track) {
+        uint64_t other[KM];
 #pragma unroll
         for (int i = 0; i < KM; ++i) {
           const uint64_t key = (uint64_t(__float_as_uint(st[2 + CM + i])) << 32) |
                                uint64_t(__float_as_uint(st[2 + CM + KM + i]));
-          if (key != 0u && key != kKeyNone) klist_insert(kk, key);
+          // the other list's fixed leading zeros must not enter this one
+          other[i] = key == 0u ? kKeyNone : key;
         }
+        klist_merge(kk, other);
       }
     };
     uint32_t ci = uint32_t(wv);
@@ -452,7 +478,7 @@ static void launch_raster_fwd_cm(const Plan& q, const FwdKernelArgs& A, hipStrea
   long long mg = q.T < q.raster_grid ? q.T : q.raster_grid;
   if (mg > kMergeGrid) mg = kMergeGrid;
   hipLaunchKernelGGL((k_fwd_merge<CM, KM>), dim3(unsigned(mg)), dim3(kWave * kMergeWaves), 0,
-                     stream, A, A.tab.scenes, A.tab.tile_start, A.tinfo);
+                     stream, A, A.tab.scenes, A.tab.tile_start, A.tinfo, A.mlist);
   stage_end(PULSAR_STAGE_MERGE, stream);
 }
 
