@@ -32,7 +32,18 @@ __global__ __launch_bounds__(kProjectBlock) void k_emit(
   // sums before it (a few KB, read from cache by every block, so no
   // separate scan launch is needed)
   unsigned long long pre = 0;
-  for (int k = threadIdx.x; k < int(blockIdx.x); k += kProjectBlock) pre += partials[k];
+  {
+    // eight independent loads in flight per round
+    int k = threadIdx.x;
+    for (; k + 7 * kProjectBlock < int(blockIdx.x); k += 8 * kProjectBlock) {
+      unsigned long long v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = partials[k + u * kProjectBlock];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) pre += v[u];
+    }
+    for (; k < int(blockIdx.x); k += kProjectBlock) pre += partials[k];
+  }
   pre = wave_sum_u64(pre);
   const unsigned long long incl = wave_incl_scan_u64(c, lane);
   if (lane == kWave - 1) s_wave[wid] = incl;
@@ -61,7 +72,7 @@ __global__ __launch_bounds__(kProjectBlock) void k_emit(
   // in row-major order over its tile rectangle
   sfirst[i] = uint32_t(at < (unsigned long long)cap ? at : (unsigned long long)cap);
   const ushort4 tr = trect[i];
-  const uint32_t q = qdepth[i];
+  const uint32_t q = depth_bits > 0 ? qdepth[i] : 0u;  // no depth in the key: not read
   // tiles are numbered scene by scene, row-major inside each scene
   const SceneDev& sc = tab.scenes[find_scene(tab.sph_start, tab.B, uint32_t(i))];
   const uint32_t tiles_x = uint32_t(sc.cam.tiles_x), tile0 = sc.tile_off;

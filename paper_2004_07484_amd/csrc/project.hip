@@ -176,13 +176,15 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
         r2 = make_float4(float(X - Xh), float(Y - Yh), float(kap - kh), float(ax - axh));
         const uint32_t packed_end = uint32_t(j1) | (uint32_t(i1) << 16);
         r3 = make_float4(float(ay - ayh), o, __uint_as_float(packed_end), 0.f);
-        // floor quantisation of (tmin - znear) / span, minus one step of margin,
-        // so the decoded value never exceeds any float32 hit distance
-        const double span = double(cam.zfar) - double(cam.znear);
-        const double levels = double(1u << depth_bits);
-        double qd = floor((tmin - double(cam.znear)) / span * levels) - 1.0;
-        qd = fmin(fmax(qd, 0.0), levels - 1.0);
-        qdepth[i] = uint32_t(qd);
+        if (depth_bits > 0) {
+          // floor quantisation of (tmin - znear) / span, minus one step of margin,
+          // so the decoded value never exceeds any float32 hit distance
+          const double span = double(cam.zfar) - double(cam.znear);
+          const double levels = double(1u << depth_bits);
+          double qd = floor((tmin - double(cam.znear)) / span * levels) - 1.0;
+          qd = fmin(fmax(qd, 0.0), levels - 1.0);
+          qdepth[i] = uint32_t(qd);
+        }
       }
     }
     counts[i] = count;

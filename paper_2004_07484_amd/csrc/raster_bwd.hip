@@ -385,7 +385,10 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
   const int i0 = blockIdx.x * kFinThreads;
   const int nloc = min(kFinThreads, n - i0);
   const int i = i0 + t;
+  // the tile count and the first slot are requested together (a sphere
+  // without tiles has no first slot; the value read is then unused)
   const uint32_t count = t < nloc ? counts[i] : 0u;
+  const uint32_t base = t < nloc ? sfirst[i] : 0u;
   s_cnt[t] = count;
   float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
   float go = 0.f;
@@ -393,7 +396,6 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
 #pragma unroll
   for (int c = 0; c < CS; ++c) gf[c] = 0.f;
   if (count != 0u) {
-    const uint32_t base = sfirst[i];
     // after a capacity overflow (outputs invalid) the slots may be missing
     if (size_t(base) + count <= size_t(status->used)) {
       for (uint32_t k = 0; k < count; ++k) {
