@@ -94,6 +94,28 @@ def test_small_scene_variants(case):
         assert fwd["nhits"].max() > wl.params.K  # the truncation is exercised
 
 
+def test_near_plane_deep_stack():
+    """Large spheres whose nearest points sit just beyond the near plane,
+    stacked deep with a small K: the backward skips a sphere at pixels whose
+    K-th nearest hit lies before the sphere's nearest point (|c| - R, lowered
+    by a margin), and that skip must never drop a gradient, also where |c| - R
+    is small against |c|."""
+    rng = np.random.default_rng(77)
+    n, C = 40, 3
+    r = rng.uniform(0.15, 0.5, n)
+    z = 1.0 + r + rng.uniform(1e-4, 0.3, n)  # nearest point just past znear = 1
+    x = rng.uniform(-0.4, 0.4, n)
+    y = rng.uniform(-0.3, 0.3, n)
+    f32 = lambda a: np.ascontiguousarray(np.asarray(a, np.float64).astype(np.float32))
+    sc = sg.Scene(pos=f32(np.stack([x, y, z], 1)), radius=f32(r),
+                  opacity=f32(rng.uniform(0.3, 1.0, n)), payload=f32(rng.standard_normal((n, C))),
+                  bg=f32(rng.uniform(-0.5, 0.5, C)))
+    wl = sg.Workload("near_stack", sc, sg.identity_camera(48, 40, focal=1.0),
+                     sg.Params(gamma=0.3, eps=1e-5, K=3), 77)
+    fwd, _ = _parity(wl, what="near-plane deep stack")
+    assert fwd["nhits"].max() > 3 * wl.params.K  # deep pixels: most hits lie behind the K-th
+
+
 def test_many_tiles_per_sphere():
     """Spheres covering dozens of tiles, deep pixels, several sort blocks."""
     wl = sg.tiny_scene(55, n=300, C=4, W=160, H=120, r_lo=0.05, r_hi=0.4)
