@@ -70,6 +70,26 @@ typedef struct pulsar_camera {
   int32_t height;      /* H in [1, 65535] */
 } pulsar_camera_t;
 
+/* Flags of pulsar_params_t.flags.
+ *
+ * PULSAR_NO_BWD_AUX: the forward keeps no backward state. It still writes the
+ *   image and, when aux is not NULL, the log-normaliser, but skips tracking
+ *   each pixel's K nearest hits (App. B keeps backward information optional).
+ *   A pulsar_bwd on that workspace must then set PULSAR_REBIN; without it
+ *   pulsar_bwd returns PULSAR_ERR_INVALID_ARGUMENT for this flag.
+ * PULSAR_REBIN: pulsar_bwd rebuilds what it needs from the scene itself
+ *   (projection, tile lists and each pixel's K-th nearest hit: App. B, Steps
+ *   0-2 without the blend's image output) instead of reading the state a
+ *   pulsar_fwd left in the workspace. Any workspace of the right size works,
+ *   and other calls may use it between the forward and the backward. image and
+ *   aux must still be the forward's outputs for the same inputs. The
+ *   gradients are bitwise those of a pulsar_bwd right after pulsar_fwd. In
+ *   pulsar_fwd the flag has no effect.
+ * Storing per-pixel hit lists instead of recomputing them (App. B stores the
+ * nearest hits per pixel) is not built: its bit is reserved. */
+#define PULSAR_NO_BWD_AUX 0x1u
+#define PULSAR_REBIN 0x2u
+
 /* Render parameters (host struct). */
 typedef struct pulsar_params {
   float gamma;          /* blending softness of Eq. 1, in [1e-5, 1] (Sec. 3.2) */
@@ -78,7 +98,8 @@ typedef struct pulsar_params {
                            pixels wide in radius: R = max(r, min_radius_px * pitch * c_z / f)
                            (App. B, Step 0). 0 = off. */
   int32_t K;            /* nearest hits per pixel that receive gradients, 1..32 */
-  uint32_t flags;       /* reserved, must be 0 */
+  uint32_t flags;       /* OR of PULSAR_NO_BWD_AUX and PULSAR_REBIN; any other
+                           bit is reserved (PULSAR_ERR_UNSUPPORTED) */
   int32_t max_pairs;    /* capacity of (screen tile, sphere) pairs; 0 = default
                            (2 n + number of tiles + 65536) */
   int32_t depth_bits;   /* bits of quantised depth in the sort key (tile lists
@@ -111,7 +132,8 @@ size_t pulsar_workspace_size(int32_t n, int32_t width, int32_t height, int32_t C
  *   image [H,W,C]  (out)       F, channels last
  *   aux [H,W]      (out)       per-pixel L = log of the Eq. 1 denominator,
  *                              needed by pulsar_bwd; may be NULL if no backward
- *                              pass follows
+ *                              pass follows (then no backward state is kept,
+ *                              as with PULSAR_NO_BWD_AUX)
  *   ws, ws_bytes               caller-owned device workspace; after the call it
  *                              holds the sorted tile lists that pulsar_bwd reuses
  * n = 0 is valid and renders the background. Outputs must not alias inputs. */
@@ -128,8 +150,11 @@ int pulsar_fwd(const float* pos, const float* radius, const float* opacity,
  * required gradients are computed); grad_opacity must be NULL when opacity is.
  * Scene, camera, params, image and aux must be exactly those of the preceding
  * pulsar_fwd on the same workspace, with no other call on that workspace in
- * between. The per-pixel hits are recomputed from the workspace's sorted tile
- * lists; nothing per pixel beyond image and aux is stored. */
+ * between, unless params.flags has PULSAR_REBIN (then only image and aux must
+ * come from a forward of the same inputs). The per-pixel hits are recomputed
+ * from the sorted tile lists; nothing per pixel beyond image and aux is
+ * stored. PULSAR_NO_BWD_AUX without PULSAR_REBIN, or aux NULL, is
+ * PULSAR_ERR_INVALID_ARGUMENT. */
 int pulsar_bwd(const float* pos, const float* radius, const float* opacity,
                const float* payload, int32_t n, int32_t C, const float* background,
                const pulsar_camera_t* cam, const pulsar_params_t* params, const float* image,

@@ -28,6 +28,8 @@ EXPORTED = ("pulsar_workspace_size", "pulsar_fwd", "pulsar_bwd", "pulsar_batch_w
             "pulsar_timing_read", "pulsar_stage_name", "pulsar_version")
 
 PULSAR_NUM_STAGES = 7
+PULSAR_NO_BWD_AUX = 0x1   # forward keeps no backward state
+PULSAR_REBIN = 0x2        # backward rebuilds its tile lists and thresholds
 PULSAR_MAX_SCENES = 4096
 
 
@@ -134,10 +136,10 @@ def make_camera(R, t, focal, sensor_width, znear, zfar, width, height) -> pulsar
 
 
 def make_params(gamma=0.1, eps=1e-5, min_radius_px=0.0, K=8, max_pairs=0,
-                depth_bits=0, chunk=0, raster_blocks=0) -> pulsar_params_t:
+                depth_bits=0, chunk=0, raster_blocks=0, flags=0) -> pulsar_params_t:
     p = pulsar_params_t()
     p.gamma, p.eps, p.min_radius_px = float(gamma), float(eps), float(min_radius_px)
-    p.K, p.flags, p.max_pairs, p.depth_bits, p.reserved = int(K), 0, int(max_pairs), \
+    p.K, p.flags, p.max_pairs, p.depth_bits, p.reserved = int(K), int(flags), int(max_pairs), \
         int(depth_bits), 0
     p.chunk, p.raster_blocks = int(chunk), int(raster_blocks)
     return p

@@ -61,7 +61,8 @@ int check_params(const pulsar_params_t* p) {
     return PULSAR_ERR_INVALID_ARGUMENT;
   if (p->raster_blocks != 0 && (p->raster_blocks < 256 || p->raster_blocks > 65536))
     return PULSAR_ERR_INVALID_ARGUMENT;
-  if (p->flags != 0u || p->reserved != 0) return PULSAR_ERR_UNSUPPORTED;
+  if ((p->flags & ~(PULSAR_NO_BWD_AUX | PULSAR_REBIN)) != 0u || p->reserved != 0)
+    return PULSAR_ERR_UNSUPPORTED;
   return PULSAR_OK;
 }
 
@@ -312,6 +313,7 @@ int pulsar_fwd_batched(const pulsar_scene_t* scenes, int32_t B, const float* pos
   a.image = image;
   a.aux = aux;
   a.min_radius_px = params->min_radius_px;
+  a.track = aux != nullptr && (params->flags & PULSAR_NO_BWD_AUX) == 0u;
   hipError_t e = launch_forward(q, sc, a, static_cast<char*>(ws),
                                 static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail_hip(e);
@@ -335,7 +337,28 @@ int pulsar_bwd_batched(const pulsar_scene_t* scenes, int32_t B, const float* pos
   if (q.n > 0 && (!pos || !radius || !payload)) return PULSAR_ERR_INVALID_ARGUMENT;
   if (!background || !image || !aux || !grad_image || !ws) return PULSAR_ERR_INVALID_ARGUMENT;
   if (grad_opacity && !opacity) return PULSAR_ERR_INVALID_ARGUMENT;
+  const bool rebin = (params->flags & PULSAR_REBIN) != 0u;
+  // without the forward's thresholds in the workspace only a rebin can help
+  if (!rebin && (params->flags & PULSAR_NO_BWD_AUX) != 0u) return PULSAR_ERR_INVALID_ARGUMENT;
   if (ws_bytes < q.total) return PULSAR_ERR_WORKSPACE;
+  if (rebin) {
+    FwdArgs f;
+    f.pos = pos;
+    f.radius = radius;
+    f.opacity = opacity;
+    f.payload = payload;
+    f.bg = background;
+    f.n = int(q.n);
+    f.C = C;
+    f.K = params->K;
+    f.image = nullptr;
+    f.aux = nullptr;
+    f.min_radius_px = params->min_radius_px;
+    f.track = true;
+    hipError_t e = launch_rebin(q, sc, f, static_cast<char*>(ws),
+                                static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return fail_hip(e);
+  }
   BwdArgs a;
   a.pos = pos;
   a.radius = radius;

@@ -136,6 +136,7 @@ struct FwdArgs {
   float* image;
   float* aux;
   float min_radius_px;
+  bool track;  // keep each pixel's K nearest hits for a following backward
 };
 
 struct BwdArgs {
@@ -162,6 +163,11 @@ struct BwdArgs {
 hipError_t launch_forward(const Plan& plan, const std::vector<SceneDev>& scenes,
                           const FwdArgs& a, char* ws, hipStream_t stream);
 hipError_t launch_backward(const Plan& plan, const BwdArgs& a, char* ws, hipStream_t stream);
+// The forward's backward state without its image: projection, binning and a
+// raster pass that only keeps each pixel's K nearest hits (image and aux of
+// `a` are not written and may be NULL).
+hipError_t launch_rebin(const Plan& plan, const std::vector<SceneDev>& scenes, const FwdArgs& a,
+                        char* ws, hipStream_t stream);
 
 // Stage timing hooks (no-ops unless pulsar_timing_enable(1) was called).
 void stage_begin(int stage, hipStream_t stream);

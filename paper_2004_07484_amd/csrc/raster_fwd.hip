@@ -97,7 +97,7 @@ struct FwdKernelArgs {
   float* pstate;
   long long pcap;
   int C, c0, cn, K, pstride, kfield;  // kfield: first K-list field of a partial state
-  int track;                          // keep K-lists (first channel pass with aux)
+  int track;                          // keep K-lists (first channel pass, backward state on)
   int vec4;                           // one channel pass, C % 4 == 0, 16-byte aligned image
   uint32_t T;                         // tiles of all scenes
   int fill_in_tail;                   // empty tiles filled by the work-item kernel
@@ -469,7 +469,7 @@ static void launch_raster_fwd_cm(const Plan& q, const FwdKernelArgs& A, hipStrea
   stage_begin(PULSAR_STAGE_RASTER_FWD, stream);
   hipLaunchKernelGGL((k_fwd_chunks<CM, KM>), dim3(unsigned(q.raster_grid)), dim3(kWave), 0,
                      stream, A, A.tab.scenes, A.tab.tile_start, A.desc);
-  if (!A.fill_in_tail)
+  if (!A.fill_in_tail && A.image)
     hipLaunchKernelGGL(k_fwd_background, dim3(unsigned((q.T + 3) / 4)), dim3(256), 0, stream, A);
   stage_end(PULSAR_STAGE_RASTER_FWD, stream);
   stage_begin(PULSAR_STAGE_MERGE, stream);
@@ -498,14 +498,8 @@ static void dispatch_cm(const Plan& q, const FwdKernelArgs& A, hipStream_t strea
     launch_raster_fwd_cm<32, KM>(q, A, stream);
 }
 
-hipError_t launch_forward(const Plan& q, const std::vector<SceneDev>& scenes, const FwdArgs& a,
-                          char* ws, hipStream_t stream) {
-  stage_begin(PULSAR_STAGE_PROJECT, stream);
-  launch_project(q, scenes, a, ws, stream);
-  stage_end(PULSAR_STAGE_PROJECT, stream);
-  stage_begin(PULSAR_STAGE_BINNING, stream);
-  launch_binning(q, ws, stream);
-  stage_end(PULSAR_STAGE_BINNING, stream);
+static FwdKernelArgs raster_args(const Plan& q, const std::vector<SceneDev>& scenes,
+                                 const FwdArgs& a, char* ws) {
   FwdKernelArgs A;
   A.tab = scene_table(q, ws);
   A.status = ws_ptr<Status>(ws, q.off_status);
@@ -531,23 +525,64 @@ hipError_t launch_forward(const Plan& q, const std::vector<SceneDev>& scenes, co
   // a few tiles per block fill well in the tail of the work-item kernel; many
   // more (large batches) get a launch of their own with one wave per tile
   A.fill_in_tail = q.T <= 4LL * q.raster_grid ? 1 : 0;
+  A.c0 = 0;
+  A.cn = 0;
+  A.track = 0;
+  A.vec4 = 0;
+  return A;
+}
+
+static void dispatch_klist(const Plan& q, const FwdKernelArgs& A, hipStream_t stream) {
+  if (q.klist_slots <= 4)
+    dispatch_cm<4>(q, A, stream);
+  else if (q.klist_slots <= 8)
+    dispatch_cm<8>(q, A, stream);
+  else if (q.klist_slots <= 16)
+    dispatch_cm<16>(q, A, stream);
+  else
+    dispatch_cm<32>(q, A, stream);
+}
+
+static void launch_tile_lists(const Plan& q, const std::vector<SceneDev>& scenes,
+                              const FwdArgs& a, char* ws, hipStream_t stream) {
+  stage_begin(PULSAR_STAGE_PROJECT, stream);
+  launch_project(q, scenes, a, ws, stream);
+  stage_end(PULSAR_STAGE_PROJECT, stream);
+  stage_begin(PULSAR_STAGE_BINNING, stream);
+  launch_binning(q, ws, stream);
+  stage_end(PULSAR_STAGE_BINNING, stream);
+}
+
+hipError_t launch_forward(const Plan& q, const std::vector<SceneDev>& scenes, const FwdArgs& a,
+                          char* ws, hipStream_t stream) {
+  launch_tile_lists(q, scenes, a, ws, stream);
+  FwdKernelArgs A = raster_args(q, scenes, a, ws);
   for (int c0 = 0; c0 < a.C; c0 += kFwdChannels) {
     A.c0 = c0;
     A.cn = a.C - c0 < kFwdChannels ? a.C - c0 : kFwdChannels;
-    A.track = (c0 == 0 && a.aux != nullptr) ? 1 : 0;
+    A.track = (c0 == 0 && a.track) ? 1 : 0;
     A.vec4 = (a.C <= kFwdChannels && (a.C & 3) == 0 &&
               (reinterpret_cast<uintptr_t>(a.image) & 15u) == 0u)
                  ? 1
                  : 0;
-    if (q.klist_slots <= 4)
-      dispatch_cm<4>(q, A, stream);
-    else if (q.klist_slots <= 8)
-      dispatch_cm<8>(q, A, stream);
-    else if (q.klist_slots <= 16)
-      dispatch_cm<16>(q, A, stream);
-    else
-      dispatch_cm<32>(q, A, stream);
+    dispatch_klist(q, A, stream);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_rebin(const Plan& q, const std::vector<SceneDev>& scenes, const FwdArgs& a,
+                        char* ws, hipStream_t stream) {
+  launch_tile_lists(q, scenes, a, ws, stream);
+  // one pass with no channel: the blend's weights and the K-lists are
+  // computed as in the forward (the same summation order, so the same
+  // thresholds), but no payload is read and neither image, log-normaliser
+  // nor empty tiles are written
+  FwdKernelArgs A = raster_args(q, scenes, a, ws);
+  A.image = nullptr;
+  A.aux = nullptr;
+  A.fill_in_tail = 0;
+  A.track = 1;
+  dispatch_klist(q, A, stream);
   return hipGetLastError();
 }
 

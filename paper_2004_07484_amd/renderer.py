@@ -63,7 +63,7 @@ def _forward_into(pos, radius, opacity, payload, bg, cam, params, check: bool):
             return image, aux, ws, params
         grown = _capi.make_params(params.gamma, params.eps, params.min_radius_px, params.K,
                                   int(min(2**31 - 1, pairs * 5 // 4 + 1024)), params.depth_bits,
-                                  params.chunk, params.raster_blocks)
+                                  params.chunk, params.raster_blocks, params.flags)
         if grown.max_pairs <= params.max_pairs:
             raise _capi.PulsarError(code, "pulsar_fwd")
         params = grown
@@ -244,6 +244,10 @@ class Renderer(torch.nn.Module):
             params = self._tuned(params, pos.detach().contiguous(), radius.detach().contiguous(),
                                  None if opacity is None else opacity.detach().contiguous(),
                                  payload.detach().contiguous(), bg.detach().contiguous(), cs)
+        if not (torch.is_grad_enabled() and any(
+                t is not None and t.requires_grad for t in (pos, radius, opacity, payload, bg))):
+            # no backward can follow: skip keeping its per-pixel state
+            params.flags |= _capi.PULSAR_NO_BWD_AUX
         image, aux = PulsarFunction.apply(pos, radius, opacity, payload, bg, cs, params,
                                           self.check_capacity)
         return (image, aux) if return_aux else image

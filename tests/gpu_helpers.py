@@ -24,17 +24,24 @@ def to_dev(a):
 
 
 def gpu_render(scene, cam, params, G=None, max_pairs=0, depth_bits=0, need=None,
-               stream=None, chunk=0, raster_blocks=0):
-    """Forward (and backward when G is given) on cuda:0; numpy results."""
+               stream=None, chunk=0, raster_blocks=0, fwd_flags=0, bwd_flags=0,
+               workspace=None, bwd_workspace=None):
+    """Forward (and backward when G is given) on cuda:0; numpy results.
+    workspace: a device byte tensor to use instead of a new one. bwd_workspace,
+    when given, is called with the forward's workspace and returns the one the
+    backward runs on."""
     import torch
     cs = cam_struct(cam)
     ps = _capi.make_params(params.gamma, params.eps, params.min_radius_px, params.K,
-                           max_pairs, depth_bits, chunk, raster_blocks)
+                           max_pairs, depth_bits, chunk, raster_blocks, fwd_flags)
+    pb = _capi.make_params(params.gamma, params.eps, params.min_radius_px, params.K,
+                           max_pairs, depth_bits, chunk, raster_blocks, bwd_flags)
     n, C = scene.payload.shape
     pos, rad, opa = to_dev(scene.pos), to_dev(scene.radius), to_dev(scene.opacity)
     pay, bg = to_dev(scene.payload), to_dev(scene.bg)
-    ws = torch.empty(_capi.pulsar_workspace_size(n, cam.width, cam.height, C, ps),
-                     dtype=torch.uint8, device="cuda:0")
+    ws = workspace if workspace is not None else torch.empty(
+        _capi.pulsar_workspace_size(n, cam.width, cam.height, C, ps), dtype=torch.uint8,
+        device="cuda:0")
     image = torch.empty((cam.height, cam.width, C), device="cuda:0")
     aux = torch.empty((cam.height, cam.width), device="cuda:0")
     _capi.pulsar_fwd(pos, rad, opa, pay, bg, cs, ps, image, aux, ws, stream)
@@ -49,8 +56,9 @@ def gpu_render(scene, cam, params, G=None, max_pairs=0, depth_bits=0, need=None,
         gp, gr = buf("pos", (n, 3)), buf("radius", (n,))
         go = buf("opacity", (n,)) if opa is not None else None
         gf, gb = buf("payload", (n, C)), buf("bg", (C,))
-        _capi.pulsar_bwd(pos, rad, opa, pay, bg, cs, ps, image, aux, to_dev(G), gp, gr, go, gf,
-                         gb, ws, stream)
+        wsb = ws if bwd_workspace is None else bwd_workspace(ws)
+        _capi.pulsar_bwd(pos, rad, opa, pay, bg, cs, pb, image, aux, to_dev(G), gp, gr, go, gf,
+                         gb, wsb, stream)
         torch.cuda.synchronize()
         for key, t in [("grad_pos", gp), ("grad_radius", gr), ("grad_opacity", go),
                        ("grad_payload", gf), ("grad_bg", gb)]:

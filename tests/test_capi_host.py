@@ -113,9 +113,20 @@ def test_bad_params_are_rejected(par_kw, code):
 
 
 def test_reserved_flags_are_unsupported():
-    p = _capi.make_params()
-    p.flags = 1
-    assert _call_fwd(_cam(), p) == _capi.PULSAR_ERR_UNSUPPORTED
+    for bit in [0x4, 0x8, 0x80000000]:
+        p = _capi.make_params(flags=bit | _capi.PULSAR_REBIN)
+        assert _call_fwd(_cam(), p) == _capi.PULSAR_ERR_UNSUPPORTED
+
+
+def test_known_flags_pass_validation():
+    # validation accepts them and stops at the next check, the workspace size
+    for flags in [_capi.PULSAR_NO_BWD_AUX, _capi.PULSAR_REBIN,
+                  _capi.PULSAR_NO_BWD_AUX | _capi.PULSAR_REBIN]:
+        p = _capi.make_params(flags=flags)
+        assert _call_fwd(_cam(), p, ws_bytes=1024) == _capi.PULSAR_ERR_WORKSPACE
+        # flags change no workspace size
+        assert _capi.pulsar_workspace_size(10, 64, 64, 3, p) == \
+            _capi.pulsar_workspace_size(10, 64, 64, 3, _capi.make_params())
 
 
 def test_missing_pointers_and_small_workspace():
@@ -143,6 +154,16 @@ def test_backward_argument_checks():
     small = list(args)
     small[18] = 1024
     assert lib.pulsar_bwd(*small) == _capi.PULSAR_ERR_WORKSPACE
+    # a forward without backward state leaves nothing to reuse: only a rebin
+    # may follow it
+    no_state = _capi.make_params(flags=_capi.PULSAR_NO_BWD_AUX)
+    args_ns = list(args)
+    args_ns[8] = ctypes.byref(no_state)
+    assert lib.pulsar_bwd(*args_ns) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    rebin = _capi.make_params(flags=_capi.PULSAR_NO_BWD_AUX | _capi.PULSAR_REBIN)
+    args_rb = list(small)
+    args_rb[8] = ctypes.byref(rebin)
+    assert lib.pulsar_bwd(*args_rb) == _capi.PULSAR_ERR_WORKSPACE
 
 
 def test_launch_without_device_reports_hip_error():

@@ -205,6 +205,37 @@ def test_backward_is_bitwise_reproducible():
         assert np.array_equal(a[key], b[key], equal_nan=False), key
 
 
+@pytest.mark.parametrize("make", [sg.config1, sg.config2])
+def test_rebin_backward_on_another_workspace(make):
+    """A forward with PULSAR_NO_BWD_AUX writes the same image and
+    log-normaliser as one that keeps its backward state; a backward with
+    PULSAR_REBIN on another workspace, whose bytes an unrelated render left
+    behind, gives bitwise the gradients of the backward that reuses the
+    forward's workspace."""
+    import torch
+    wl = make()
+    cam = wl.camera
+    _say(f"[rebin] {wl.name}")
+    G = sg.upstream_grad(wl.seed + 77, cam.height, cam.width, wl.scene.C)
+    a = gpu_render(wl.scene, cam, wl.params, G)
+    # fewer spheres, same image and parameters: fits the same workspace size
+    other = sg.box_scene(np.random.default_rng(99), wl.scene.n // 2, wl.scene.C, 0.002, 0.03)
+
+    def dirty(ws):
+        fresh = torch.full_like(ws, 0xA5)
+        # an unrelated scene's forward and backward on the new workspace
+        r = gpu_render(other, cam, wl.params, np.ones((cam.height, cam.width, wl.scene.C),
+                                                      np.float32), workspace=fresh)
+        assert r["status"] == _capi.PULSAR_OK
+        return fresh
+
+    b = gpu_render(wl.scene, cam, wl.params, G, fwd_flags=_capi.PULSAR_NO_BWD_AUX,
+                   bwd_flags=_capi.PULSAR_NO_BWD_AUX | _capi.PULSAR_REBIN, bwd_workspace=dirty)
+    assert a["status"] == _capi.PULSAR_OK and b["status"] == _capi.PULSAR_OK
+    for key in ["F", "L", "grad_pos", "grad_radius", "grad_opacity", "grad_payload", "grad_bg"]:
+        assert np.array_equal(a[key], b[key]), key
+
+
 def test_capacity_overflow_is_reported_then_recovers():
     wl = sg.config1()
     small = gpu_render(wl.scene, wl.camera, wl.params, max_pairs=100)
