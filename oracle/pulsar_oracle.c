@@ -293,13 +293,24 @@ int oracle_forward(int n, int C, const double* pos, const double* radius, const 
  * radius, opacity and features of each sphere in a pixel's K-list, then chained
  * to world position (dLoss/dp = R^T dLoss/dc) and radius. Outputs are overwritten.
  * grad_opacity may be NULL (no opacity input).
+ *
+ * Camera gradients (Sec. 3.1: the render map is differentiable in the camera
+ * too), written when grad_cam is not NULL, as 14 values: dLoss/dR (row-major
+ * 3x3, R taken as a free matrix), dLoss/dt, dLoss/df, dLoss/ds. R and t act
+ * only through c = R p + t, so they collect dLoss/dc of every sphere. f and s
+ * act through every pixel ray u (its direction (x_s, y_s, f), with x_s, y_s
+ * proportional to s) and through the minimum-size radius rho c_z / f with
+ * rho proportional to s. grad_cam_abs (may be NULL) receives, per value, the
+ * sum of the absolute values of the terms added into it, a scale for
+ * comparing sums that cancel.
  */
 int oracle_backward(int n, int C, const double* pos, const double* radius, const double* opacity,
                     const double* payload, const double* bg, const double* cam16, int W, int H,
                     double gamma, double eps, double min_radius_px, int K, int n_rows,
                     const int* rows, const double* G, const double* F, const double* L,
                     const int* klist_id, double* grad_pos, double* grad_radius,
-                    double* grad_opacity, double* grad_payload, double* grad_bg) {
+                    double* grad_opacity, double* grad_payload, double* grad_bg,
+                    double* grad_cam, double* grad_cam_abs) {
   (void)bg;
   if (n < 0 || C < 1 || W < 1 || H < 1 || K < 1 || !(gamma > 0.0)) return ORACLE_BAD_ARG;
   camera_t cam;
@@ -313,6 +324,7 @@ int oracle_backward(int n, int C, const double* pos, const double* radius, const
   if (grad_opacity) memset(grad_opacity, 0, sizeof(double) * (size_t)n);
   memset(grad_payload, 0, sizeof(double) * (size_t)n * C);
   memset(grad_bg, 0, sizeof(double) * (size_t)C);
+  double gcam[14] = {0}, gabs[14] = {0};
   int nr = rows ? n_rows : H;
   const double span = cam.zfar - cam.znear;
   for (int ri = 0; ri < nr; ++ri) {
@@ -326,6 +338,21 @@ int oracle_backward(int n, int C, const double* pos, const double* radius, const
       for (int c = 0; c < C; ++c) grad_bg[c] += wbg * Gp[c];
       double u[3];
       pixel_ray(&cam, i, j, u);
+      /* the ray's unnormalised direction v = (x_s, y_s, f) and its
+         derivatives: dv/df = e_z, dv/ds = (x_s / s, y_s / s, 0); then
+         du/dx = (dv/dx - u (u . dv/dx)) / |v| */
+      double xs = (j + 0.5) * cam.pitch - 0.5 * cam.s;
+      double ys = (i + 0.5) * cam.pitch - 0.5 * cam.sh;
+      double vlen = sqrt(xs * xs + ys * ys + cam.f * cam.f);
+      double du_df[3], du_ds[3];
+      {
+        double dvs[3] = {xs / cam.s, ys / cam.s, 0.0};
+        double uf = u[2], us = u[0] * dvs[0] + u[1] * dvs[1];
+        for (int a = 0; a < 3; ++a) {
+          du_df[a] = ((a == 2 ? 1.0 : 0.0) - u[a] * uf) / vlen;
+          du_ds[a] = (dvs[a] - u[a] * us) / vlen;
+        }
+      }
       for (int r = 0; r < K; ++r) {
         int k = klist_id[p * K + r];
         if (k < 0) break;
@@ -351,6 +378,20 @@ int oracle_backward(int n, int C, const double* pos, const double* radius, const
           gc[3 * (size_t)k + a] += g_t * dt_dc + g_delta * ddelta_dc;
         }
         gR[k] += g_t * (-Rk / root) + g_delta * (q / (Rk * Rk));
+        if (grad_cam) {
+          /* with c fixed: b = u . c, q^2 = |c|^2 - b^2, so db/du = c,
+             dt/du = c - (b / root) c, d delta/du = (b / (q R)) c */
+          double sdu = g_t * (1.0 - b / root) + (q > 0.0 ? g_delta * b / (q * Rk) : 0.0);
+          double cf = 0.0, cs = 0.0;
+          for (int a = 0; a < 3; ++a) {
+            cf += sc[k].c[a] * du_df[a];
+            cs += sc[k].c[a] * du_ds[a];
+          }
+          gcam[12] += sdu * cf;
+          gabs[12] += fabs(sdu * cf);
+          gcam[13] += sdu * cs;
+          gabs[13] += fabs(sdu * cs);
+        }
       }
     }
   }
@@ -360,14 +401,30 @@ int oracle_backward(int n, int C, const double* pos, const double* radius, const
       /* R = rho c_z / f depends on the depth, not on r */
       g[2] += gR[k] * min_radius_px * cam.pitch / cam.f;
       grad_radius[k] = 0.0;
+      /* and on the camera: rho = min_radius_px s / W, so dR/df = -R/f, dR/ds = R/s */
+      gcam[12] += gR[k] * (-sc[k].R / cam.f);
+      gabs[12] += fabs(gR[k] * sc[k].R / cam.f);
+      gcam[13] += gR[k] * (sc[k].R / cam.s);
+      gabs[13] += fabs(gR[k] * sc[k].R / cam.s);
     } else {
       grad_radius[k] = gR[k];
+    }
+    /* c = R p + t: dLoss/dR_ab = dLoss/dc_a p_b, dLoss/dt = dLoss/dc */
+    for (int a = 0; a < 3; ++a) {
+      for (int b2 = 0; b2 < 3; ++b2) {
+        gcam[3 * a + b2] += g[a] * pos[3 * (size_t)k + b2];
+        gabs[3 * a + b2] += fabs(g[a] * pos[3 * (size_t)k + b2]);
+      }
+      gcam[9 + a] += g[a];
+      gabs[9 + a] += fabs(g[a]);
     }
     /* c = R p + t  =>  dLoss/dp = R^T dLoss/dc */
     for (int a = 0; a < 3; ++a)
       grad_pos[3 * (size_t)k + a] =
           cam.R[0 * 3 + a] * g[0] + cam.R[1 * 3 + a] * g[1] + cam.R[2 * 3 + a] * g[2];
   }
+  if (grad_cam) memcpy(grad_cam, gcam, sizeof(gcam));
+  if (grad_cam_abs) memcpy(grad_cam_abs, gabs, sizeof(gabs));
   free(sc);
   free(gc);
   free(gR);

@@ -43,7 +43,7 @@ def _load():
         lib.oracle_backward.argtypes = [
             ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int,
             ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
-            ctypes.c_int, _ip, _dp, _dp, _dp, _ip, _dp, _dp, _dp, _dp, _dp]
+            ctypes.c_int, _ip, _dp, _dp, _dp, _ip, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
         lib.oracle_pixel_hits.restype = ctypes.c_int
         lib.oracle_pixel_hits.argtypes = [
             ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
@@ -108,7 +108,9 @@ def forward(scene, cam, params, rows: Optional[Sequence[int]] = None,
 
 
 def backward(scene, cam, params, G, fwd: dict, rows: Optional[Sequence[int]] = None) -> dict:
-    """Gradients of sum(G * F) for the scene parameters and the background."""
+    """Gradients of sum(G * F) for the scene parameters, the background and
+    the camera: grad_camera = [dR (3x3 row-major), dt (3), df, ds], with
+    grad_camera_abs the sum of |term| behind each value."""
     lib = _load()
     pos, rad = _d(scene.pos), _d(scene.radius)
     opa = None if scene.opacity is None else _d(scene.opacity)
@@ -123,6 +125,8 @@ def backward(scene, cam, params, G, fwd: dict, rows: Optional[Sequence[int]] = N
     go = np.zeros(n) if opa is not None else None
     gf = np.zeros((n, C))
     gb = np.zeros(C)
+    gcam = np.zeros(14)
+    gabs = np.zeros(14)
     F = _d(np.nan_to_num(fwd["F"]))
     L = _d(np.nan_to_num(fwd["L"]))
     kid = np.ascontiguousarray(fwd["klist_id"].astype(np.int32))
@@ -130,10 +134,12 @@ def backward(scene, cam, params, G, fwd: dict, rows: Optional[Sequence[int]] = N
                              _ptr(camera_vector(cam)), W, H, float(params.gamma),
                              float(params.eps), float(params.min_radius_px), K, nr,
                              _ptr(r, _ip), _ptr(G), _ptr(F), _ptr(L), _ptr(kid, _ip),
-                             _ptr(gp), _ptr(gr), _ptr(go), _ptr(gf), _ptr(gb))
+                             _ptr(gp), _ptr(gr), _ptr(go), _ptr(gf), _ptr(gb), _ptr(gcam),
+                             _ptr(gabs))
     if rc != 0:
         raise ValueError(f"oracle_backward failed with code {rc}")
-    return dict(grad_pos=gp, grad_radius=gr, grad_opacity=go, grad_payload=gf, grad_bg=gb)
+    return dict(grad_pos=gp, grad_radius=gr, grad_opacity=go, grad_payload=gf, grad_bg=gb,
+                grad_camera=gcam, grad_camera_abs=gabs)
 
 
 def pixel_hits(scene, cam, params, i: int, j: int) -> dict:

@@ -66,3 +66,34 @@ def fd_grads(scene, cam, params, G, rel_h=1e-6, rows=None, which=None):
             g[idx] = (loss(sp, cam, params, G, rows) - loss(sm, cam, params, G, rows)) / (2 * h)
         out[gname] = g
     return out
+
+
+def fd_camera_grads(scene, cam, params, G, rel_h=1e-6, rows=None) -> np.ndarray:
+    """Central finite differences of sum(G * F) for the 14 camera values
+    [R (3x3 row-major, perturbed entry by entry as a free matrix), t, focal,
+    sensor_width]."""
+    out = np.zeros(14)
+    for k in range(14):
+        cp, cm = copy.deepcopy(cam), copy.deepcopy(cam)
+        if k < 9:
+            x = float(np.asarray(cam.R, np.float64).reshape(9)[k])
+        elif k < 12:
+            x = float(np.asarray(cam.t, np.float64)[k - 9])
+        else:
+            x = float(cam.focal if k == 12 else cam.sensor_width)
+        h = rel_h * max(1.0, abs(x))
+        for c, v in ((cp, x + h), (cm, x - h)):
+            if k < 9:
+                R = np.array(c.R, np.float64).reshape(9)
+                R[k] = v
+                c.R = R.reshape(3, 3)
+            elif k < 12:
+                t = np.array(c.t, np.float64)
+                t[k - 9] = v
+                c.t = t
+            elif k == 12:
+                c.focal = v
+            else:
+                c.sensor_width = v
+        out[k] = (loss(scene, cp, params, G, rows) - loss(scene, cm, params, G, rows)) / (2 * h)
+    return out

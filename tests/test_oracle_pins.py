@@ -16,7 +16,8 @@ import pytest
 
 from oracle import reference as ref
 from paper_2004_07484_amd import scenegen as sg
-from tests.oracle_helpers import as_f64, fd_grads, pixel_direction, random_rotation
+from tests.oracle_helpers import as_f64, fd_camera_grads, fd_grads, pixel_direction, \
+    random_rotation
 
 
 def _rotated_world(wl, rng):
@@ -307,6 +308,53 @@ def test_minimum_size_gradients_match_finite_differences():
     assert np.all(an["grad_radius"][clamped] == 0)
     fd = fd_grads(sc, wl.camera, params, G)
     _assert_grads_close(an, fd, rtol=2e-6)
+
+
+@pytest.mark.parametrize("seed,rotate,min_radius_px", [(1, False, 0.0), (2, True, 0.0),
+                                                       (12, True, 2.5)])
+def test_camera_gradients_match_finite_differences(seed, rotate, min_radius_px):
+    """dLoss/d(R, t, f, s) against FP64 central differences of the forward
+    with the camera perturbed (R entry by entry as a free matrix). The third
+    case has clamped minimum-size spheres, whose radius follows f and s."""
+    if min_radius_px > 0:
+        wl = sg.tiny_scene(seed, n=4, C=2, W=24, H=24, r_lo=0.02, r_hi=0.06)
+        params = sg.Params(gamma=0.5, eps=1e-5, min_radius_px=min_radius_px, K=8)
+    else:
+        wl = sg.tiny_scene(seed, n=5, C=2)
+        params = wl.params
+    if rotate:
+        sc, cam = _rotated_world(wl, np.random.default_rng(seed))
+    else:
+        sc, cam = as_f64(wl.scene), wl.camera
+    G = sg.upstream_grad(200 + seed, cam.height, cam.width, 2).astype(np.float64)
+    fwd = ref.forward(sc, cam, params)
+    assert fwd["nhits"].max() <= params.K and fwd["nhits"].sum() > 10
+    an = ref.backward(sc, cam, params, G, fwd)["grad_camera"]
+    fd = fd_camera_grads(sc, cam, params, G)
+    scale = np.abs(fd).max()
+    assert np.all(np.abs(an - fd) <= 2e-6 * np.maximum(np.abs(fd), 1e-4 * scale)), \
+        (an.tolist(), fd.tolist())
+    # the focal length and the sensor width act only through their ratio
+    # (rays and the minimum-size radius): f df + s ds = 0
+    assert abs(cam.focal * an[12] + cam.sensor_width * an[13]) <= 1e-9 * (
+        abs(cam.focal * an[12]) + 1e-300)
+
+
+def test_camera_pose_gradient_is_the_rotated_position_sum():
+    """Moving the camera by dt moves every centre by dt in camera space, the
+    same as moving every sphere by R^T dt: dLoss/dt = R sum_i dLoss/dp_i, and
+    likewise dLoss/dR = sum_i (R dLoss/dp_i) p_i^T."""
+    wl = sg.tiny_scene(4, n=6, C=2)
+    sc, cam = _rotated_world(wl, np.random.default_rng(4))
+    params = wl.params
+    G = sg.upstream_grad(44, cam.height, cam.width, 2).astype(np.float64)
+    g = ref.backward(sc, cam, params, G, ref.forward(sc, cam, params))
+    R = np.asarray(cam.R, np.float64)
+    gc = g["grad_pos"] @ R.T  # rows R dLoss/dp_i
+    np.testing.assert_allclose(g["grad_camera"][9:12], gc.sum(0), rtol=1e-9,
+                               atol=1e-12 * np.abs(gc).sum())
+    np.testing.assert_allclose(g["grad_camera"][:9].reshape(3, 3), gc.T @ sc.pos, rtol=1e-9,
+                               atol=1e-12 * np.abs(gc).sum())
 
 
 def test_truncated_gradient_is_masked_derivative():
