@@ -162,6 +162,27 @@ int pulsar_bwd(const float* pos, const float* radius, const float* opacity,
                float* grad_opacity, float* grad_payload, float* grad_background, void* ws,
                size_t ws_bytes, void* stream);
 
+/* pulsar_bwd plus the camera gradients (Sec. 3.1: the render map is
+ * differentiable in the camera as well as in the scene), for
+ * grad_camera [14] (out, not NULL): dLoss/dR as a row-major 3x3 (R taken as a
+ * free matrix: the caller chains through its own rotation parameters),
+ * dLoss/dt [3], dLoss/dfocal and dLoss/dsensor_width. Every other argument,
+ * state requirement and error is that of pulsar_bwd; NULL grad_camera is
+ * PULSAR_ERR_INVALID_ARGUMENT.
+ * The camera acts through the camera-space centres c = R p + t of every
+ * sphere and, via the ratio focal / sensor_width, through every pixel ray and
+ * the minimum-size radius (App. B, Step 0), so focal dL/dfocal + sensor_width
+ * dL/dsensor_width = 0. Like the scene gradients these are the derivatives
+ * of the truncated backward: a pixel passes gradients to its K nearest hits
+ * only. Sums are taken in FP64 over per-sphere FP32 terms, in a fixed order. */
+int pulsar_bwd_camera(const float* pos, const float* radius, const float* opacity,
+                      const float* payload, int32_t n, int32_t C, const float* background,
+                      const pulsar_camera_t* cam, const pulsar_params_t* params,
+                      const float* image, const float* aux, const float* grad_image,
+                      float* grad_pos, float* grad_radius, float* grad_opacity,
+                      float* grad_payload, float* grad_background, float* grad_camera, void* ws,
+                      size_t ws_bytes, void* stream);
+
 /* ---- Batched rendering: several independent scenes in one call.
  *
  * Each scene is the problem of Sec. 3.1-3.2 on its own: a sphere set, a
@@ -215,6 +236,16 @@ int pulsar_bwd_batched(const pulsar_scene_t* scenes, int32_t B, const float* pos
                        float* grad_payload, float* grad_background, void* ws,
                        size_t ws_bytes, void* stream);
 
+/* pulsar_bwd_batched plus the camera gradients of every scene, grad_camera
+ * [B,14] (out, not NULL), row b laid out as in pulsar_bwd_camera. */
+int pulsar_bwd_camera_batched(const pulsar_scene_t* scenes, int32_t B, const float* pos,
+                              const float* radius, const float* opacity, const float* payload,
+                              int32_t C, const float* background, const pulsar_params_t* params,
+                              const float* image, const float* aux, const float* grad_image,
+                              float* grad_pos, float* grad_radius, float* grad_opacity,
+                              float* grad_payload, float* grad_background, float* grad_camera,
+                              void* ws, size_t ws_bytes, void* stream);
+
 /* Synchronises `stream` and reports the status the device wrote into the
  * workspace during the last pulsar_fwd: PULSAR_OK or PULSAR_ERR_CAPACITY.
  * If pairs is not NULL it receives the number of (tile, sphere) pairs that
@@ -246,7 +277,7 @@ int pulsar_timing_enable(int on);
 int pulsar_timing_read(double* total_ms, int64_t* counts);
 const char* pulsar_stage_name(int stage);
 
-/* ABI version of this header, currently 2. */
+/* ABI version of this header, currently 3. */
 int pulsar_version(void);
 
 #ifdef __cplusplus

@@ -23,7 +23,8 @@ PULSAR_ERR_HIP = -4
 PULSAR_ERR_CAPACITY = -5
 
 EXPORTED = ("pulsar_workspace_size", "pulsar_fwd", "pulsar_bwd", "pulsar_batch_workspace_size",
-            "pulsar_fwd_batched", "pulsar_bwd_batched", "pulsar_query_status",
+            "pulsar_fwd_batched", "pulsar_bwd_batched", "pulsar_bwd_camera",
+            "pulsar_bwd_camera_batched", "pulsar_query_status",
             "pulsar_status_string", "pulsar_last_hip_error", "pulsar_timing_enable",
             "pulsar_timing_read", "pulsar_stage_name", "pulsar_version")
 
@@ -101,6 +102,17 @@ def load():
                                        _vp, _vp, ctypes.c_int32, _vp,
                                        ctypes.POINTER(pulsar_params_t), _vp, _vp, _vp, _vp, _vp,
                                        _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    lib.pulsar_bwd_camera.restype = ctypes.c_int
+    lib.pulsar_bwd_camera.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp,
+                                      ctypes.POINTER(pulsar_camera_t),
+                                      ctypes.POINTER(pulsar_params_t), _vp, _vp, _vp, _vp, _vp,
+                                      _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    lib.pulsar_bwd_camera_batched.restype = ctypes.c_int
+    lib.pulsar_bwd_camera_batched.argtypes = [ctypes.POINTER(pulsar_scene_t), ctypes.c_int32,
+                                              _vp, _vp, _vp, _vp, ctypes.c_int32, _vp,
+                                              ctypes.POINTER(pulsar_params_t), _vp, _vp, _vp,
+                                              _vp, _vp, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
+                                              _vp]
     lib.pulsar_query_status.restype = ctypes.c_int
     lib.pulsar_query_status.argtypes = [_vp, ctypes.c_size_t, _vp,
                                         ctypes.POINTER(ctypes.c_int64)]
@@ -251,6 +263,29 @@ def pulsar_bwd(pos, radius, opacity, payload, background, cam: pulsar_camera_t,
         raise PulsarError(rc, "pulsar_bwd")
 
 
+def pulsar_bwd_camera(pos, radius, opacity, payload, background, cam: pulsar_camera_t,
+                      params: pulsar_params_t, image, aux, grad_image, grad_pos, grad_radius,
+                      grad_opacity, grad_payload, grad_background, grad_camera, ws,
+                      stream=None) -> None:
+    """pulsar_bwd plus grad_camera [14]: dR (3x3 row-major), dt, dfocal, dsensor_width."""
+    n, C = int(payload.shape[0]), int(payload.shape[1])
+    H, W = int(cam.height), int(cam.width)
+    rc = load().pulsar_bwd_camera(
+        _ptr(pos, "pos", n > 0, (n, 3)), _ptr(radius, "radius", n > 0, (n,)),
+        _ptr(opacity, "opacity", False, (n,)), _ptr(payload, "payload", n > 0, (n, C)), n, C,
+        _ptr(background, "background", True, (C,)), ctypes.byref(cam), ctypes.byref(params),
+        _ptr(image, "image", True, (H, W, C)), _ptr(aux, "aux", True, (H, W)),
+        _ptr(grad_image, "grad_image", True, (H, W, C)),
+        _ptr(grad_pos, "grad_pos", False, (n, 3)), _ptr(grad_radius, "grad_radius", False, (n,)),
+        _ptr(grad_opacity, "grad_opacity", False, (n,)),
+        _ptr(grad_payload, "grad_payload", False, (n, C)),
+        _ptr(grad_background, "grad_background", False, (C,)),
+        _ptr(grad_camera, "grad_camera", True, (14,)),
+        _ws_ptr(ws), int(ws.numel()), _stream(stream))
+    if rc != PULSAR_OK:
+        raise PulsarError(rc, "pulsar_bwd_camera")
+
+
 def pulsar_batch_workspace_size(scenes, C: int, params: pulsar_params_t) -> int:
     return int(load().pulsar_batch_workspace_size(scenes, len(scenes), int(C),
                                                   ctypes.byref(params)))
@@ -291,6 +326,29 @@ def pulsar_bwd_batched(scenes, pos, radius, opacity, payload, background,
         _ws_ptr(ws), int(ws.numel()), _stream(stream))
     if rc != PULSAR_OK:
         raise PulsarError(rc, "pulsar_bwd_batched")
+
+
+def pulsar_bwd_camera_batched(scenes, pos, radius, opacity, payload, background,
+                              params: pulsar_params_t, image, aux, grad_image, grad_pos,
+                              grad_radius, grad_opacity, grad_payload, grad_background,
+                              grad_camera, ws, stream=None) -> None:
+    B = len(scenes)
+    N, P = batch_sizes(scenes)
+    C = int(payload.shape[1])
+    rc = load().pulsar_bwd_camera_batched(
+        scenes, B, _ptr(pos, "pos", N > 0, (N, 3)), _ptr(radius, "radius", N > 0, (N,)),
+        _ptr(opacity, "opacity", False, (N,)), _ptr(payload, "payload", N > 0, (N, C)), C,
+        _ptr(background, "background", True, (B, C)), ctypes.byref(params),
+        _ptr(image, "image", True, (P, C)), _ptr(aux, "aux", True, (P,)),
+        _ptr(grad_image, "grad_image", True, (P, C)),
+        _ptr(grad_pos, "grad_pos", False, (N, 3)), _ptr(grad_radius, "grad_radius", False, (N,)),
+        _ptr(grad_opacity, "grad_opacity", False, (N,)),
+        _ptr(grad_payload, "grad_payload", False, (N, C)),
+        _ptr(grad_background, "grad_background", False, (B, C)),
+        _ptr(grad_camera, "grad_camera", True, (B, 14)),
+        _ws_ptr(ws), int(ws.numel()), _stream(stream))
+    if rc != PULSAR_OK:
+        raise PulsarError(rc, "pulsar_bwd_camera_batched")
 
 
 def pulsar_query_status(ws, stream=None) -> Tuple[int, int]:

@@ -219,6 +219,9 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   q.bwd_ps4 = C <= kBwdChannels ? 1 + (bcm + 4) / 4 : 2;
   q.off_pslot = take(size_t(cap) * size_t(q.bwd_ps4) * 16);
   q.off_sfirst = take(nn * 4);
+  q.ncampart = int64_t(q.B) + n / kCamSpan + 1;
+  q.off_camg = take(nn * 16);
+  q.off_campart = take(size_t(q.ncampart) * 16 * 8);
   q.total = o;
   *out = q;
   return PULSAR_OK;
@@ -320,13 +323,13 @@ int pulsar_fwd_batched(const pulsar_scene_t* scenes, int32_t B, const float* pos
   return PULSAR_OK;
 }
 
-int pulsar_bwd_batched(const pulsar_scene_t* scenes, int32_t B, const float* pos,
-                       const float* radius, const float* opacity, const float* payload,
-                       int32_t C, const float* background, const pulsar_params_t* params,
-                       const float* image, const float* aux, const float* grad_image,
-                       float* grad_pos, float* grad_radius, float* grad_opacity,
-                       float* grad_payload, float* grad_background, void* ws,
-                       size_t ws_bytes, void* stream) {
+static int bwd_impl(const pulsar_scene_t* scenes, int32_t B, const float* pos,
+                    const float* radius, const float* opacity, const float* payload, int32_t C,
+                    const float* background, const pulsar_params_t* params, const float* image,
+                    const float* aux, const float* grad_image, float* grad_pos,
+                    float* grad_radius, float* grad_opacity, float* grad_payload,
+                    float* grad_background, float* grad_camera, void* ws, size_t ws_bytes,
+                    void* stream) {
   std::vector<SceneDev> sc;
   int rc = make_scenes(scenes, B, params, &sc);
   if (rc != PULSAR_OK) return rc;
@@ -375,11 +378,37 @@ int pulsar_bwd_batched(const pulsar_scene_t* scenes, int32_t B, const float* pos
   a.grad_opacity = grad_opacity;
   a.grad_payload = grad_payload;
   a.grad_bg = grad_background;
+  a.grad_cam = grad_camera;
   a.min_radius_px = params->min_radius_px;
   a.eps2 = sc[0].bc.eps2;
   hipError_t e = launch_backward(q, a, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail_hip(e);
   return PULSAR_OK;
+}
+
+int pulsar_bwd_batched(const pulsar_scene_t* scenes, int32_t B, const float* pos,
+                       const float* radius, const float* opacity, const float* payload,
+                       int32_t C, const float* background, const pulsar_params_t* params,
+                       const float* image, const float* aux, const float* grad_image,
+                       float* grad_pos, float* grad_radius, float* grad_opacity,
+                       float* grad_payload, float* grad_background, void* ws,
+                       size_t ws_bytes, void* stream) {
+  return bwd_impl(scenes, B, pos, radius, opacity, payload, C, background, params, image, aux,
+                  grad_image, grad_pos, grad_radius, grad_opacity, grad_payload, grad_background,
+                  nullptr, ws, ws_bytes, stream);
+}
+
+int pulsar_bwd_camera_batched(const pulsar_scene_t* scenes, int32_t B, const float* pos,
+                              const float* radius, const float* opacity, const float* payload,
+                              int32_t C, const float* background, const pulsar_params_t* params,
+                              const float* image, const float* aux, const float* grad_image,
+                              float* grad_pos, float* grad_radius, float* grad_opacity,
+                              float* grad_payload, float* grad_background, float* grad_camera,
+                              void* ws, size_t ws_bytes, void* stream) {
+  if (!grad_camera) return PULSAR_ERR_INVALID_ARGUMENT;
+  return bwd_impl(scenes, B, pos, radius, opacity, payload, C, background, params, image, aux,
+                  grad_image, grad_pos, grad_radius, grad_opacity, grad_payload, grad_background,
+                  grad_camera, ws, ws_bytes, stream);
 }
 
 static pulsar_scene_t single_scene(const pulsar_camera_t* cam, int32_t n) {
@@ -411,6 +440,21 @@ int pulsar_bwd(const float* pos, const float* radius, const float* opacity,
   return pulsar_bwd_batched(&sc, 1, pos, radius, opacity, payload, C, background, params,
                             image, aux, grad_image, grad_pos, grad_radius, grad_opacity,
                             grad_payload, grad_background, ws, ws_bytes, stream);
+}
+
+int pulsar_bwd_camera(const float* pos, const float* radius, const float* opacity,
+                      const float* payload, int32_t n, int32_t C, const float* background,
+                      const pulsar_camera_t* cam, const pulsar_params_t* params,
+                      const float* image, const float* aux, const float* grad_image,
+                      float* grad_pos, float* grad_radius, float* grad_opacity,
+                      float* grad_payload, float* grad_background, float* grad_camera, void* ws,
+                      size_t ws_bytes, void* stream) {
+  if (!cam) return PULSAR_ERR_INVALID_ARGUMENT;
+  const pulsar_scene_t sc = single_scene(cam, n);
+  return pulsar_bwd_camera_batched(&sc, 1, pos, radius, opacity, payload, C, background, params,
+                                   image, aux, grad_image, grad_pos, grad_radius, grad_opacity,
+                                   grad_payload, grad_background, grad_camera, ws, ws_bytes,
+                                   stream);
 }
 
 int pulsar_query_status(const void* ws, size_t ws_bytes, void* stream, int64_t* pairs) {
@@ -475,6 +519,6 @@ const char* pulsar_stage_name(int stage) {
   return (stage >= 0 && stage < PULSAR_NUM_STAGES) ? names[stage] : "unknown";
 }
 
-int pulsar_version(void) { return 2; }
+int pulsar_version(void) { return 3; }
 
 }  // extern "C"

@@ -27,6 +27,7 @@ constexpr int kChunkDefault = 128;           // sphere records per raster work i
 constexpr int kRasterGridDefault = 4096;     // persistent raster grid (one wave per block)
 constexpr int kUploadScenes = 12;            // scene descriptors per upload launch
 constexpr int kBgBlockPixels = 1024;         // pixels per background-gradient block
+constexpr int kCamSpan = 4096;               // spheres per camera-gradient partial sum
 constexpr uint32_t kFirstChunk = 0x80000000u;  // work item flag: first chunk of its tile
 constexpr uint32_t kNoSlot = 0xffffffffu;      // work item writes final pixels, no partial state
 
@@ -103,13 +104,17 @@ struct Plan {
   // block sums of the chunk scan; the partial blend states; the per-pixel
   // K-th nearest hit (t, sphere id); background-gradient block sums
   size_t off_tinfo, off_desc, off_cpart, off_pstate, off_thr, off_bgsum;
-  // sphere records and payload rows copied into sorted pair order
   size_t off_mlist;  // tiles with several work items, for the merge kernel
   size_t off_scenes, off_starts;  // scene table and its start arrays
   // backward: one sum slot per (tile, sphere) pair at its emission position,
-  // bwd_ps4 float4 each (dL/dc, dL/dR | dL/df[cm] | dL/do, padding), and each
-  // sphere's first emission position
+  // bwd_ps4 float4 each (dL/dc, dL/dR | dL/df[cm] | dL/do, dL/d(f/s),
+  // padding), and each sphere's first emission position
   size_t off_pslot, off_sfirst;
+  // camera gradients: per sphere float4 (dL/dc, dL/d(f/s)); per-scene runs of
+  // partial sums, 16 doubles each (scene b's run starts at b + first sphere /
+  // kCamSpan)
+  size_t off_camg, off_campart;
+  int64_t ncampart;
   int bwd_ps4;
   int64_t max_chunks, pcap;
   int nblk_tiles, fwd_cm, klist_slots, pstride;
@@ -153,6 +158,7 @@ struct BwdArgs {
   float* grad_opacity;
   float* grad_payload;
   float* grad_bg;
+  float* grad_cam;  // [B, 14]: dL/dR (3x3), dL/dt, dL/df, dL/ds per scene, or null
   float min_radius_px;
   float eps2;  // eps / gamma * log2(e), the background exponent (camera independent)
 };

@@ -41,7 +41,7 @@ struct BwdKernelArgs {
   const uint32_t* svals;  // sphere index of every sorted pair
   float* grad_payload;  // caller's output, added per hit by the wide path only
   int C;
-  int need_geo, need_op, need_pay;
+  int need_geo, need_op, need_pay, need_cam;
   float* bgsum;       // background-gradient block sums, or null
   uint32_t nbgblk;
   float eps2;
@@ -57,6 +57,7 @@ __device__ void bg_partial_block(const SceneTable& tab, const float* __restrict_
 // nearest: derivatives of Eq. 1 through t (depth), 1 - q/R (distance), o and f.
 struct HitGrad {
   float gcx, gcy, gcz, gR, go, w;
+  float gt, coef;  // dL/dt and the coefficient of (c - (u.c) u) / R in dL/dc
 };
 
 __device__ __forceinline__ HitGrad hit_grad(const PixelRay& ray, const SphereRec& s,
@@ -82,7 +83,25 @@ __device__ __forceinline__ HitGrad hit_grad(const PixelRay& ray, const SphereRec
   g.gcy = gt * ray.uy + coef * dny;
   g.gcz = gt * ray.uz + coef * dnz;
   g.gR = -gt * isq + gd * h.ratio * fast_rcp(s.R);
+  g.gt = gt;
+  g.coef = coef;
   return g;
+}
+
+// The same hit's derivative with respect to kappa = f / s, the only way the
+// focal length and the sensor width enter a ray: u is the unit vector along
+// (x_s, y_s, f) = s (a, b, kappa). With c fixed, t and 1 - q/R depend on u
+// through b = u.c and q^2 = |c|^2 - b^2, which gives dL/du = (dL/dt - b
+// coef / R) c, and c . du/dkappa = s (c_z - u_z b) / |v| = s c_z pitch
+// (x_s D_x + y_s D_y) / |v|^3 (D in pixels: x_s - f c_x / c_z = pitch D_x),
+// which stays accurate where c_z - u_z b cancels.
+__device__ __forceinline__ float hit_grad_kappa(const PixelRay& ray, const SphereRec& s,
+                                                const Hit& h, const CamDev& cam,
+                                                const HitGrad& g) {
+  const float b = h.t + s.R * h.sq;  // u . c
+  const float du = g.gt - b * g.coef * fast_rcp(s.R);
+  const float proj = (ray.xs * h.dx + ray.ys * h.dy) * (cam.pitch * cam.s);
+  return du * s.cz * proj * ray.inv_v2 * fast_sqrt(ray.inv_v2);
 }
 
 // K7 by work item: a block of kBwdWaves waves takes one work item (a chunk of
@@ -99,7 +118,7 @@ constexpr int kBwdWaves = 4;
 // record, never per pixel); wider instances keep the compiler's budget.
 constexpr int bwd_waves_per_simd(int CM) { return CM <= 8 ? 5 : 1; }
 
-template <int CM>
+template <int CM, bool CAM>
 __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_bwd_items(
     BwdKernelArgs A, const SceneDev* __restrict__ scenes, const uint32_t* __restrict__ tile_start,
     const uint4* __restrict__ desc) {
@@ -185,7 +204,7 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
       float gf[CM];
 #pragma unroll
       for (int c = 0; c < CM; ++c) gf[c] = 0.f;
-      float gcx = 0.f, gcy = 0.f, gcz = 0.f, gR = 0.f, go = 0.f;
+      float gcx = 0.f, gcy = 0.f, gcz = 0.f, gR = 0.f, go = 0.f, gk = 0.f;
       uint32_t nh = 0;
       const float tlo = front_bound(s);
       for (int py = ya; py <= yb; ++py) {
@@ -208,6 +227,7 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
           gcz += g.gcz;
           gR += g.gR;
           go += g.go;
+          if (CAM) gk += hit_grad_kappa(ray, s, h, cam, g);
 #pragma unroll
           for (int c = 0; c < CM; ++c) gf[c] += g.w * s_G[c][pl];
           ++nh;
@@ -215,7 +235,8 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
       }
       // the pair's sums go whole into its slot
       float4* sr = A.pslot + size_t(id) * size_t(A.ps4);
-      constexpr int NT = (CM + 4) / 4;  // float4 holding dL/df[CM], then dL/do
+      // float4 holding dL/df[CM], then dL/do and dL/d(f/s)
+      constexpr int NT = (CM + 4) / 4;
       sr[0] = make_float4(gcx, gcy, gcz, gR);
 #pragma unroll
       for (int q = 0; q < NT; ++q) {
@@ -223,7 +244,7 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int k = 4 * q + u;
-          v[u] = k < CM ? gf[k < CM ? k : 0] : (k == CM ? go : 0.f);
+          v[u] = k < CM ? gf[k < CM ? k : 0] : (k == CM ? go : (k == CM + 1 ? gk : 0.f));
         }
         sr[1 + q] = make_float4(v[0], v[1], v[2], v[3]);
       }
@@ -281,7 +302,7 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A,
           pair_position(a, d, uint32_t(A.boff[id / kProjectBlock]), tx0 / kTileW, ty0 / kTileH);
       const uint32_t p1 = __float_as_uint(d.z);
       const float* fk = A.payload + size_t(id) * size_t(C);
-      float gcx = 0.f, gcy = 0.f, gcz = 0.f, gR = 0.f, go = 0.f;
+      float gcx = 0.f, gcy = 0.f, gcz = 0.f, gR = 0.f, go = 0.f, gk = 0.f;
       const int xa = max(s.x0, tx0), xb = min(int(p1 & 0xffffu), tx0 + kTileW - 1);
       const int ya = max(s.y0, ty0), yb = min(int(p1 >> 16), ty0 + kTileH - 1);
       const float tlo = front_bound(s);
@@ -321,13 +342,19 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A,
           gcy += gt * ray.uy + coef * dny;
           gcz += gt * ray.uz + coef * dnz;
           gR += -gt / h.sq + gd * h.ratio / s.R;
+          if (A.need_cam) {
+            HitGrad g;
+            g.gt = gt;
+            g.coef = coef;
+            gk += hit_grad_kappa(ray, s, h, cam, g);
+          }
         }
       }
       // dL/dc, dL/dR, dL/do whole into the pair's slot (the payload terms
       // went out per hit)
       float4* sr = A.pslot + size_t(slot) * size_t(A.ps4);
       sr[0] = make_float4(gcx, gcy, gcz, gR);
-      sr[1] = make_float4(go, 0.f, 0.f, 0.f);
+      sr[1] = make_float4(go, gk, 0.f, 0.f);
     }
   }
 }
@@ -359,7 +386,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
     const float4* __restrict__ pslot, int ps4, float* __restrict__ grad_pos,
     float* __restrict__ grad_radius, float* __restrict__ grad_opacity,
     float* __restrict__ grad_payload, uint32_t nfin, const float* __restrict__ bgsum,
-    float* __restrict__ grad_bg) {
+    float* __restrict__ grad_bg, float4* __restrict__ camg) {
   constexpr int CS = CM > 0 ? CM : 1;
   __shared__ uint32_t s_cnt[kFinThreads];
   __shared__ float s_gp[3 * kFinThreads];
@@ -391,7 +418,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
   const uint32_t base = t < nloc ? sfirst[i] : 0u;
   s_cnt[t] = count;
   float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
-  float go = 0.f;
+  float go = 0.f, gk = 0.f;
   float gf[CS];
 #pragma unroll
   for (int c = 0; c < CS; ++c) gf[c] = 0.f;
@@ -418,17 +445,21 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
                 gf[kk < CS ? kk : 0] += vv[u];
               else if (kk == CM)
                 go += vv[u];
+              else if (kk == CM + 1)
+                gk += vv[u];
             }
           }
         } else {
-          go += sr[1].x;
+          const float4 v = sr[1];
+          go += v.x;
+          gk += v.y;
         }
       }
     }
   }
   if (t < nloc) {
     if (grad_opacity) grad_opacity[i] = go;
-    if (grad_pos || grad_radius) {
+    if (grad_pos || grad_radius || camg) {
       float gx = g.x, gy = g.y, gz = g.z, gR = g.w;
       bool clamped = false;
       const CamDev cam = tab.scenes[find_scene(tab.sph_start, tab.B, uint32_t(i))].cam;
@@ -439,8 +470,14 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
         const double pitch = double(cam.s) / double(cam.W);
         const double k = double(min_radius_px) * pitch / double(cam.f);
         clamped = k * cz > double(radius[i]);
-        if (clamped) gz += float(double(gR) * k);  // R = k c_z depends on depth only
+        if (clamped) {
+          gz += float(double(gR) * k);  // R = k c_z depends on depth only
+          // and on the camera through k = min_radius_px / (W kappa):
+          // dR/dkappa = -R / kappa
+          gk -= float(double(gR) * k * cz * double(cam.s) / double(cam.f));
+        }
       }
+      if (camg) camg[i] = make_float4(gx, gy, gz, gk);
       if (grad_radius) grad_radius[i] = clamped ? 0.f : gR;
       // c = R p + t  =>  dL/dp = R^T dL/dc
       s_gp[3 * t + 0] = cam.R[0] * gx + cam.R[3] * gy + cam.R[6] * gz;
@@ -636,6 +673,16 @@ __global__ __launch_bounds__(kBgThreads) void k_bg_partial_wide(SceneTable tab,
 }
 
 template <int CM>
+static void launch_items(const BwdKernelArgs& A, dim3 grid, dim3 block, hipStream_t stream) {
+  if (A.need_cam)
+    hipLaunchKernelGGL((k_bwd_items<CM, true>), grid, block, 0, stream, A, A.tab.scenes,
+                       A.tab.tile_start, A.desc);
+  else
+    hipLaunchKernelGGL((k_bwd_items<CM, false>), grid, block, 0, stream, A, A.tab.scenes,
+                       A.tab.tile_start, A.desc);
+}
+
+template <int CM>
 static void launch_finalize(const Plan& q, const BwdArgs& a, char* ws, hipStream_t stream,
                             uint32_t nfin, uint32_t nred) {
   hipLaunchKernelGGL((k_finalize<CM>), dim3(nfin + nred), dim3(kFinThreads), 0, stream, int(q.n),
@@ -643,7 +690,92 @@ static void launch_finalize(const Plan& q, const BwdArgs& a, char* ws, hipStream
                      ws_ptr<Status>(ws, q.off_status), a.pos, a.radius, scene_table(q, ws),
                      a.min_radius_px, a.C, ws_ptr<float4>(ws, q.off_pslot), q.bwd_ps4, a.grad_pos,
                      a.grad_radius, a.grad_opacity, a.grad_payload, nfin,
-                     ws_ptr<float>(ws, q.off_bgsum), a.grad_bg);
+                     ws_ptr<float>(ws, q.off_bgsum), a.grad_bg,
+                     a.grad_cam ? ws_ptr<float4>(ws, q.off_camg) : nullptr);
+}
+
+// Camera gradients: dL/dR = sum_i dL/dc_i p_i^T, dL/dt = sum_i dL/dc_i and
+// dL/dkappa = sum_i dL/dkappa_i over each scene's spheres (c = R p + t),
+// in FP64 and in a fixed order. K9a: block g adds kCamSpan spheres of one
+// scene (scene b owns blocks b + sph_off_b / kCamSpan onwards, as many as
+// its spheres need; blocks in the gaps do nothing). K9b: one block per scene
+// adds its block sums in order and maps dL/dkappa to the focal length and
+// the sensor width (kappa = f / s).
+constexpr int kCamThreads = 256;
+constexpr int kCamVals = 13;  // R (9), t (3), kappa
+
+__device__ __forceinline__ uint32_t cam_first_block(const SceneDev& sc, int b) {
+  return uint32_t(b) + sc.sph_off / uint32_t(kCamSpan);
+}
+
+__global__ __launch_bounds__(kCamThreads) void k_cam_partial(const SceneDev* __restrict__ scenes,
+                                                             int B, const float4* __restrict__ camg,
+                                                             const float* __restrict__ pos,
+                                                             double* __restrict__ part) {
+  __shared__ double s_acc[kCamVals][kCamThreads];
+  const uint32_t g = blockIdx.x;
+  int lo = 0, hi = B - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cam_first_block(scenes[mid], mid) <= g)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const SceneDev& sc = scenes[lo];
+  const uint32_t local = g - cam_first_block(sc, lo);
+  const uint32_t nblk = (sc.n + uint32_t(kCamSpan) - 1u) / uint32_t(kCamSpan);
+  if (local >= nblk) return;  // the whole block: no barrier is reached
+  const uint32_t i0 = sc.sph_off + local * uint32_t(kCamSpan);
+  const uint32_t i1 = min(i0 + uint32_t(kCamSpan), sc.sph_off + sc.n);
+  double acc[kCamVals];
+#pragma unroll
+  for (int k = 0; k < kCamVals; ++k) acc[k] = 0.0;
+  for (uint32_t i = i0 + threadIdx.x; i < i1; i += kCamThreads) {
+    const float4 gc = camg[i];
+    const double c[3] = {gc.x, gc.y, gc.z};
+    const double p[3] = {pos[3 * size_t(i)], pos[3 * size_t(i) + 1], pos[3 * size_t(i) + 2]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+      for (int b = 0; b < 3; ++b) acc[3 * a + b] += c[a] * p[b];
+      acc[9 + a] += c[a];
+    }
+    acc[12] += double(gc.w);
+  }
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < kCamVals; ++k) s_acc[k][t] = acc[k];
+  __syncthreads();
+  for (int w = kCamThreads / 2; w > 0; w >>= 1) {
+    if (t < w)
+#pragma unroll
+      for (int k = 0; k < kCamVals; ++k) s_acc[k][t] += s_acc[k][t + w];
+    __syncthreads();
+  }
+  if (t < kCamVals) part[size_t(g) * 16 + size_t(t)] = s_acc[t][0];
+}
+
+__global__ __launch_bounds__(kWave) void k_cam_final(const SceneDev* __restrict__ scenes,
+                                                     const double* __restrict__ part,
+                                                     float* __restrict__ grad_cam) {
+  __shared__ double s_v[kCamVals];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const SceneDev& sc = scenes[b];
+  const uint32_t first = cam_first_block(sc, b);
+  const uint32_t nblk = (sc.n + uint32_t(kCamSpan) - 1u) / uint32_t(kCamSpan);
+  if (t < kCamVals) {
+    double v = 0.0;
+    for (uint32_t j = 0; j < nblk; ++j) v += part[size_t(first + j) * 16 + size_t(t)];
+    s_v[t] = v;
+  }
+  __syncthreads();
+  if (t < 14) {
+    const double f = sc.cam.f, s = sc.cam.s, gk = s_v[12];
+    // kappa = f / s: dL/df = dL/dkappa / s, dL/ds = -dL/dkappa f / s^2
+    const double v = t < 12 ? s_v[t] : (t == 12 ? gk / s : -gk * f / (s * s));
+    grad_cam[size_t(b) * 14 + size_t(t)] = float(v);
+  }
 }
 
 hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_t stream) {
@@ -665,7 +797,8 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
   A.svals = ws_ptr<uint32_t>(ws, sorted_in_a(q) ? q.off_valsA : q.off_valsB);
   A.grad_payload = a.grad_payload;
   A.C = a.C;
-  A.need_geo = (a.grad_pos || a.grad_radius) ? 1 : 0;
+  A.need_geo = (a.grad_pos || a.grad_radius || a.grad_cam) ? 1 : 0;
+  A.need_cam = a.grad_cam ? 1 : 0;
   A.need_op = a.grad_opacity ? 1 : 0;
   A.need_pay = a.grad_payload ? 1 : 0;
   // the narrow raster kernel also computes the background block sums
@@ -685,23 +818,17 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
   const long long bg = q.raster_grid / kBwdWaves > 0 ? q.raster_grid / kBwdWaves : 1;
   const dim3 ig{unsigned(bg), 1u, 1u}, it{unsigned(kWave * kBwdWaves), 1u, 1u};
   if (a.C <= 1)
-    hipLaunchKernelGGL(k_bwd_items<1>, ig, it, 0, stream, A, A.tab.scenes, A.tab.tile_start,
-                       A.desc);
+    launch_items<1>(A, ig, it, stream);
   else if (a.C <= 2)
-    hipLaunchKernelGGL(k_bwd_items<2>, ig, it, 0, stream, A, A.tab.scenes, A.tab.tile_start,
-                       A.desc);
+    launch_items<2>(A, ig, it, stream);
   else if (a.C <= 4)
-    hipLaunchKernelGGL(k_bwd_items<4>, ig, it, 0, stream, A, A.tab.scenes, A.tab.tile_start,
-                       A.desc);
+    launch_items<4>(A, ig, it, stream);
   else if (a.C <= 8)
-    hipLaunchKernelGGL(k_bwd_items<8>, ig, it, 0, stream, A, A.tab.scenes, A.tab.tile_start,
-                       A.desc);
+    launch_items<8>(A, ig, it, stream);
   else if (a.C <= 16)
-    hipLaunchKernelGGL(k_bwd_items<16>, ig, it, 0, stream, A, A.tab.scenes, A.tab.tile_start,
-                       A.desc);
+    launch_items<16>(A, ig, it, stream);
   else if (!wide)
-    hipLaunchKernelGGL(k_bwd_items<32>, ig, it, 0, stream, A, A.tab.scenes, A.tab.tile_start,
-                       A.desc);
+    launch_items<32>(A, ig, it, stream);
   else
     hipLaunchKernelGGL(k_bwd_chunks_wide, dim3(unsigned(q.raster_grid)), dim3(kWave), 0, stream,
                        A, A.tab.scenes, A.tab.tile_start, A.desc);
@@ -732,6 +859,13 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
       launch_finalize<32>(q, a, ws, stream, nfin, nred);
     else
       launch_finalize<0>(q, a, ws, stream, nfin, nred);
+  }
+  if (a.grad_cam) {
+    hipLaunchKernelGGL(k_cam_partial, dim3(unsigned(q.ncampart)), dim3(kCamThreads), 0, stream,
+                       tab.scenes, q.B, ws_ptr<float4>(ws, q.off_camg), a.pos,
+                       ws_ptr<double>(ws, q.off_campart));
+    hipLaunchKernelGGL(k_cam_final, dim3(unsigned(q.B)), dim3(kWave), 0, stream, tab.scenes,
+                       ws_ptr<double>(ws, q.off_campart), a.grad_cam);
   }
   stage_end(PULSAR_STAGE_FINALIZE, stream);
   return hipGetLastError();

@@ -74,6 +74,21 @@ __device__ __forceinline__ void klist_merge(uint64_t (&kk)[KM], const uint64_t (
   }
 }
 
+// A K-list of K < KM keys starts with KM - K fixed zeros (below every key).
+// For merging, another list's zeros must leave: its keys move to the front
+// and kKeyNone fills the end, which keeps it ascending. z = KM - K is the
+// same for every lane, so the shifts by its bits branch uniformly.
+template <int KM>
+__device__ __forceinline__ void klist_drop_zeros(uint64_t (&b)[KM], int z) {
+#pragma unroll
+  for (int sh = 1; sh < KM; sh <<= 1) {
+    if (z & sh) {
+#pragma unroll
+      for (int i = 0; i < KM; ++i) b[i] = i + sh < KM ? b[i + sh < KM ? i + sh : 0] : kKeyNone;
+    }
+  }
+}
+
 template <int KM>
 __device__ __forceinline__ void klist_init(uint64_t (&kk)[KM], int K) {
 #pragma unroll
@@ -415,12 +430,11 @@ __global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(
       if (A.track) {
         uint64_t other[KM];
 #pragma unroll
-        for (int i = 0; i < KM; ++i) {
-          const uint64_t key = (uint64_t(__float_as_uint(st[2 + CM + i])) << 32) |
-                               uint64_t(__float_as_uint(st[2 + CM + KM + i]));
-          // the other list's fixed leading zeros must not enter this one
-          other[i] = key == 0u ? kKeyNone : key;
-        }
+        for (int i = 0; i < KM; ++i)
+          other[i] = (uint64_t(__float_as_uint(st[2 + CM + i])) << 32) |
+                     uint64_t(__float_as_uint(st[2 + CM + KM + i]));
+        // the other list's fixed leading zeros must not enter this one
+        klist_drop_zeros(other, KM - A.K);
         klist_merge(kk, other);
       }
     };

@@ -28,6 +28,27 @@ def axis_angle_to_matrix(r) -> list:
             kz * kx * v - ky * s, kz * ky * v + kx * s, c + kz * kz * v]
 
 
+def axis_angle_to_matrix_torch(r: torch.Tensor) -> torch.Tensor:
+    """Rodrigues' formula as differentiable torch operations: [3] -> [3, 3]
+    (R = I + sin(th) K + (1 - cos(th)) K^2, K the cross-product matrix of the
+    unit axis; first order at th = 0 so the derivative there is exact)."""
+    r = r.reshape(3)
+    th2 = (r * r).sum()
+    zero = torch.zeros((), dtype=r.dtype, device=r.device)
+
+    def skew(k):
+        return torch.stack([torch.stack([zero, -k[2], k[1]]),
+                            torch.stack([k[2], zero, -k[0]]),
+                            torch.stack([-k[1], k[0], zero])])
+
+    eye = torch.eye(3, dtype=r.dtype, device=r.device)
+    if float(th2) < 1e-20:
+        return eye + skew(r)
+    th = torch.sqrt(th2)
+    K = skew(r / th)
+    return eye + torch.sin(th) * K + (1.0 - torch.cos(th)) * (K @ K)
+
+
 def camera_struct(cam, width: int, height: int, znear: float, zfar: float):
     """Accepts a pulsar_camera_t, an object with R, t, focal, sensor_width
     (znear/zfar/width/height optional), or the 8-vector [t (3), axis-angle (3),
@@ -73,13 +94,19 @@ class PulsarFunction(torch.autograd.Function):
     """F = R(S, camera) with the hand-written backward of libpulsar.so."""
 
     @staticmethod
-    def forward(ctx, pos, radius, opacity, payload, bg, cam, params, check=True):
+    def forward(ctx, pos, radius, opacity, payload, bg, cam, params, check=True, cam_R=None,
+                cam_t=None, cam_f=None, cam_s=None):
+        """cam is the pulsar_camera_t the kernels use; cam_R [3,3], cam_t [3],
+        cam_f, cam_s, when given, are tensors holding the same values, and
+        receive dLoss/dR (R as a free matrix), dLoss/dt, dLoss/dfocal and
+        dLoss/dsensor_width."""
         pos, radius, payload, bg = (t.contiguous() for t in (pos, radius, payload, bg))
         opacity = opacity.contiguous() if opacity is not None else None
         image, aux, ws, params = _forward_into(pos, radius, opacity, payload, bg, cam, params,
                                                check)
         ctx.save_for_backward(pos, radius, opacity, payload, bg, image, aux, ws)
         ctx.cam, ctx.params = cam, params
+        ctx.cam_shapes = [None if x is None else x.shape for x in (cam_R, cam_t, cam_f, cam_s)]
         ctx.mark_non_differentiable(aux)
         return image, aux
 
@@ -98,9 +125,20 @@ class PulsarFunction(torch.autograd.Function):
         gf, gb = out(need[3], (n, C)), out(need[4], (C,))
         if grad_image is None:
             grad_image = torch.zeros_like(image)
-        _capi.pulsar_bwd(pos, radius, opacity, payload, bg, ctx.cam, ctx.params, image, aux,
-                         grad_image.contiguous(), gp, gr, go, gf, gb, ws)
-        return gp, gr, go, gf, gb, None, None, None
+        cam_grads = [None] * 4
+        if any(need[8:12]):
+            gcam = torch.empty(14, device=payload.device, dtype=torch.float32)
+            _capi.pulsar_bwd_camera(pos, radius, opacity, payload, bg, ctx.cam, ctx.params,
+                                    image, aux, grad_image.contiguous(), gp, gr, go, gf, gb,
+                                    gcam, ws)
+            parts = (gcam[0:9], gcam[9:12], gcam[12], gcam[13])
+            for k in range(4):
+                if need[8 + k]:
+                    cam_grads[k] = parts[k].reshape(ctx.cam_shapes[k])
+        else:
+            _capi.pulsar_bwd(pos, radius, opacity, payload, bg, ctx.cam, ctx.params, image, aux,
+                             grad_image.contiguous(), gp, gr, go, gf, gb, ws)
+        return (gp, gr, go, gf, gb, None, None, None, *cam_grads)
 
 
 class PulsarBatchFunction(torch.autograd.Function):
@@ -238,16 +276,31 @@ class Renderer(torch.nn.Module):
         C = payload.shape[1]
         if bg is None:
             bg = torch.zeros(C, device=payload.device, dtype=torch.float32)
-        cs = camera_struct(cam, self.width, self.height, min_depth, max_depth)
+        cam_tensors = (None, None, None, None)
+        if torch.is_tensor(cam) and cam.requires_grad and torch.is_grad_enabled():
+            # the 8-vector [t, axis-angle, focal, sensor_width] as differentiable
+            # parts; the kernels get the same values
+            v = cam.reshape(-1)
+            if v.numel() != 8:
+                raise ValueError("camera vector must be [t(3), axis-angle(3), focal, "
+                                 "sensor_width]")
+            cam_tensors = (axis_angle_to_matrix_torch(v[3:6]), v[0:3], v[6], v[7])
+            Rv = cam_tensors[0].detach().cpu().reshape(9).tolist()
+            hv = v.detach().cpu().tolist()
+            cs = _capi.make_camera(Rv, hv[0:3], hv[6], hv[7], min_depth, max_depth, self.width,
+                                   self.height)
+        else:
+            cs = camera_struct(cam, self.width, self.height, min_depth, max_depth)
         params = _capi.make_params(gamma, eps, min_radius_px, self.K, self.max_pairs)
         if self.autotune:
             params = self._tuned(params, pos.detach().contiguous(), radius.detach().contiguous(),
                                  None if opacity is None else opacity.detach().contiguous(),
                                  payload.detach().contiguous(), bg.detach().contiguous(), cs)
         if not (torch.is_grad_enabled() and any(
-                t is not None and t.requires_grad for t in (pos, radius, opacity, payload, bg))):
+                t is not None and t.requires_grad
+                for t in (pos, radius, opacity, payload, bg) + cam_tensors)):
             # no backward can follow: skip keeping its per-pixel state
             params.flags |= _capi.PULSAR_NO_BWD_AUX
         image, aux = PulsarFunction.apply(pos, radius, opacity, payload, bg, cs, params,
-                                          self.check_capacity)
+                                          self.check_capacity, *cam_tensors)
         return (image, aux) if return_aux else image

@@ -25,7 +25,7 @@ def to_dev(a):
 
 def gpu_render(scene, cam, params, G=None, max_pairs=0, depth_bits=0, need=None,
                stream=None, chunk=0, raster_blocks=0, fwd_flags=0, bwd_flags=0,
-               workspace=None, bwd_workspace=None):
+               workspace=None, bwd_workspace=None, camera_grad=False):
     """Forward (and backward when G is given) on cuda:0; numpy results.
     workspace: a device byte tensor to use instead of a new one. bwd_workspace,
     when given, is called with the forward's workspace and returns the one the
@@ -57,8 +57,15 @@ def gpu_render(scene, cam, params, G=None, max_pairs=0, depth_bits=0, need=None,
         go = buf("opacity", (n,)) if opa is not None else None
         gf, gb = buf("payload", (n, C)), buf("bg", (C,))
         wsb = ws if bwd_workspace is None else bwd_workspace(ws)
-        _capi.pulsar_bwd(pos, rad, opa, pay, bg, cs, pb, image, aux, to_dev(G), gp, gr, go, gf,
-                         gb, wsb, stream)
+        if camera_grad:
+            gcam = torch.full((14,), float("nan"), device="cuda:0")
+            _capi.pulsar_bwd_camera(pos, rad, opa, pay, bg, cs, pb, image, aux, to_dev(G), gp, gr,
+                                    go, gf, gb, gcam, wsb, stream)
+            torch.cuda.synchronize()
+            out["grad_camera"] = gcam.cpu().numpy()
+        else:
+            _capi.pulsar_bwd(pos, rad, opa, pay, bg, cs, pb, image, aux, to_dev(G), gp, gr, go,
+                             gf, gb, wsb, stream)
         torch.cuda.synchronize()
         for key, t in [("grad_pos", gp), ("grad_radius", gr), ("grad_opacity", go),
                        ("grad_payload", gf), ("grad_bg", gb)]:
@@ -155,3 +162,14 @@ def gpu_render_batch(workloads, params, Gs=None, depth_bits=0, chunk=0, raster_b
             o.update(grad_pos=gp[n0:n0 + n], grad_radius=gr[n0:n0 + n],
                      grad_opacity=go[n0:n0 + n], grad_payload=gf[n0:n0 + n], grad_bg=gb[b])
     return outs
+
+
+def assert_camera_close(got, ref, ref_abs, what, rel=GRAD_REL):
+    """Camera gradients are sums over every hit of terms of both signs: the
+    scale of each value is the larger of |ref| and 1e-2 of the sum of the
+    absolute values of its terms."""
+    got = np.asarray(got, np.float64)
+    scale = np.maximum(np.abs(ref), FLOOR * np.asarray(ref_abs, np.float64))
+    err = np.abs(got - ref) / np.maximum(scale, 1e-300)
+    assert np.all(err <= rel), f"{what}: worst {err.max():.3g} at {int(err.argmax())}: " \
+        f"got {got.tolist()} ref {np.asarray(ref).tolist()}"

@@ -43,7 +43,7 @@ def test_header_declarations_are_exported():
 
 def test_version_and_status_strings():
     _lib()
-    assert _capi.pulsar_version() == 2
+    assert _capi.pulsar_version() == 3
     for code in [0, -1, -2, -3, -4, -5, -99]:
         assert len(_capi.pulsar_status_string(code)) > 5
     assert "capacity" in _capi.pulsar_status_string(_capi.PULSAR_ERR_CAPACITY)
@@ -160,6 +160,13 @@ def test_backward_argument_checks():
     args_ns = list(args)
     args_ns[8] = ctypes.byref(no_state)
     assert lib.pulsar_bwd(*args_ns) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    # the camera variant needs its output and otherwise checks like pulsar_bwd
+    cam_args = args[:17] + [None] + args[17:]
+    assert lib.pulsar_bwd_camera(*cam_args) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    cam_small = small[:17] + [FAKE] + small[17:]
+    assert lib.pulsar_bwd_camera(*cam_small) == _capi.PULSAR_ERR_WORKSPACE
+    cam_bad_aux = bad_aux[:17] + [FAKE] + bad_aux[17:]
+    assert lib.pulsar_bwd_camera(*cam_bad_aux) == _capi.PULSAR_ERR_INVALID_ARGUMENT
     rebin = _capi.make_params(flags=_capi.PULSAR_NO_BWD_AUX | _capi.PULSAR_REBIN)
     args_rb = list(small)
     args_rb[8] = ctypes.byref(rebin)

@@ -94,6 +94,28 @@ def test_small_scene_variants(case):
         assert fwd["nhits"].max() > wl.params.K  # the truncation is exercised
 
 
+@pytest.mark.parametrize("K", [3, 5, 8, 13])
+def test_dense_tiles_with_short_klists(K):
+    """Tiles split into several work items whose K-lists are merged, with K
+    below the register list size (fixed leading entries) and at it: the
+    merged K-th nearest hit must be that of one pass over the whole list."""
+    wl = sg.config1()
+    sc = wl.scene
+    sc.radius = (sc.radius * 8.0).astype(np.float32)
+    par = sg.Params(gamma=0.1, eps=1e-5, K=K)
+    cam = wl.camera
+    _say(f"[parity] dense tiles K={K} chunk=64")
+    fwd = ref.forward(sc, cam, par)
+    assert fwd["nhits"].max() > 64  # several work items per tile
+    G = sg.upstream_grad(300 + K, cam.height, cam.width, sc.C)
+    Gm = masked_G(G, None, fwd["ambiguous"])
+    out = gpu_render(sc, cam, par, Gm, chunk=64)
+    assert out["status"] == _capi.PULSAR_OK
+    assert_close(out["F"], fwd["F"], IMAGE_REL, "dense image")
+    g = ref.backward(sc, cam, par, Gm, fwd)
+    compare_grads(out, g, f"dense K={K}")
+
+
 def test_near_plane_deep_stack():
     """Large spheres whose nearest points sit just beyond the near plane,
     stacked deep with a small K: the backward skips a sphere at pixels whose
