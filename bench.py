@@ -254,6 +254,8 @@ def main() -> int:
     ap.add_argument("--no-graph", action="store_true", help="time eager launches only")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-vs-looped measurement of 32 uneven scenes")
+    ap.add_argument("--no-camera", action="store_true",
+                    help="skip timing the backward that also returns camera gradients")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the default launch knobs instead of autotuning them first")
     ap.add_argument("--knobs", default="", metavar="K=V,...",
@@ -448,6 +450,29 @@ def main() -> int:
                for k, v in per_stage_bytes.items()}
     io_frac = (fwd_b + bwd_b) / (step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
 
+    # the backward with camera gradients, timed on its own after the step
+    # above (same forward state; its extra kernels are the two camera sums)
+    camera = None
+    if not args.no_camera:
+        gcam = torch.empty(14, device=dev)
+        _capi.pulsar_fwd(pos, rad, opa, pay, bg, cs, ps, image, aux, ws, stream)
+        for _ in range(args.warmup):
+            _capi.pulsar_bwd_camera(pos, rad, opa, pay, bg, cs, ps, image, aux, G, gp, gr, go, gf,
+                                    gb, gcam, ws, stream)
+        cev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        for e0, e1 in cev:
+            e0.record(stream)
+            _capi.pulsar_bwd_camera(pos, rad, opa, pay, bg, cs, ps, image, aux, G, gp, gr, go, gf,
+                                    gb, gcam, ws, stream)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        cam_ms = float(np.median([a.elapsed_time(b) for a, b in cev]))
+        assert bool(torch.isfinite(gcam).all())
+        camera = {"bwd_with_camera_ms": round(cam_ms, 4), "bwd_ms": round(bwd_ms, 4),
+                  "extra_ms": round(cam_ms - bwd_ms, 4)}
+        log(f"[bench] backward with camera gradients: {cam_ms:.3f} ms (without: {bwd_ms:.3f})")
+
     batch = None
     if not args.no_batch:
         batch = bench_batch(args, dev)
@@ -486,6 +511,7 @@ def main() -> int:
         "roofline": roofline,
         "kernels": kernels,
         "tuned_knobs": None if tune_info is None else tune_info["knobs"],
+        "camera_gradients": camera,
         "batched": batch,
         "cpu_baseline": cpu,
         "paper_context": "RTX 2080, 1M spheres at 1000^2: fwd 19 ms, bwd 4.7 ms (CUDA only)",
