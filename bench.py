@@ -450,28 +450,38 @@ def main() -> int:
                for k, v in per_stage_bytes.items()}
     io_frac = (fwd_b + bwd_b) / (step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
 
-    # the backward with camera gradients, timed on its own after the step
-    # above (same forward state; its extra kernels are the two camera sums)
+    # the backward with camera gradients against the plain one, each timed
+    # after a forward of its own, like the step above
     camera = None
     if not args.no_camera:
         gcam = torch.empty(14, device=dev)
-        _capi.pulsar_fwd(pos, rad, opa, pay, bg, cs, ps, image, aux, ws, stream)
-        for _ in range(args.warmup):
+
+        def bwd_plain():
+            _capi.pulsar_bwd(pos, rad, opa, pay, bg, cs, ps, image, aux, G, gp, gr, go, gf, gb,
+                             ws, stream)
+
+        def bwd_cam():
             _capi.pulsar_bwd_camera(pos, rad, opa, pay, bg, cs, ps, image, aux, G, gp, gr, go, gf,
                                     gb, gcam, ws, stream)
-        cev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.steps)]
-        for e0, e1 in cev:
-            e0.record(stream)
-            _capi.pulsar_bwd_camera(pos, rad, opa, pay, bg, cs, ps, image, aux, G, gp, gr, go, gf,
-                                    gb, gcam, ws, stream)
-            e1.record(stream)
-        torch.cuda.synchronize()
-        cam_ms = float(np.median([a.elapsed_time(b) for a, b in cev]))
+
+        cms = {}
+        for name, fn in (("plain", bwd_plain), ("camera", bwd_cam)):
+            cev = []
+            for k in range(args.warmup + args.steps):
+                _capi.pulsar_fwd(pos, rad, opa, pay, bg, cs, ps, image, aux, ws, stream)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                fn()
+                e1.record(stream)
+                if k >= args.warmup:
+                    cev.append((e0, e1))
+            torch.cuda.synchronize()
+            cms[name] = float(np.median([a.elapsed_time(b) for a, b in cev]))
         assert bool(torch.isfinite(gcam).all())
-        camera = {"bwd_with_camera_ms": round(cam_ms, 4), "bwd_ms": round(bwd_ms, 4),
-                  "extra_ms": round(cam_ms - bwd_ms, 4)}
-        log(f"[bench] backward with camera gradients: {cam_ms:.3f} ms (without: {bwd_ms:.3f})")
+        camera = {"bwd_with_camera_ms": round(cms["camera"], 4), "bwd_ms": round(cms["plain"], 4),
+                  "extra_ms": round(cms["camera"] - cms["plain"], 4)}
+        log(f"[bench] backward with camera gradients: {cms['camera']:.3f} ms (without: "
+            f"{cms['plain']:.3f})")
 
     batch = None
     if not args.no_batch:

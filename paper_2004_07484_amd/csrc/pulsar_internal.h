@@ -27,7 +27,7 @@ constexpr int kChunkDefault = 128;           // sphere records per raster work i
 constexpr int kRasterGridDefault = 4096;     // persistent raster grid (one wave per block)
 constexpr int kUploadScenes = 12;            // scene descriptors per upload launch
 constexpr int kBgBlockPixels = 1024;         // pixels per background-gradient block
-constexpr int kCamSpan = 4096;               // spheres per camera-gradient partial sum
+constexpr int kCamSpan = 1024;               // spheres per camera-gradient partial sum
 constexpr uint32_t kFirstChunk = 0x80000000u;  // work item flag: first chunk of its tile
 constexpr uint32_t kNoSlot = 0xffffffffu;      // work item writes final pixels, no partial state
 

@@ -113,10 +113,11 @@ __device__ __forceinline__ float hit_grad_kappa(const PixelRay& ray, const Spher
 // inside the pixel loop and no barrier inside the record loop. CM >= C.
 constexpr int kBwdWaves = 4;
 
-// Up to 8 channels the item kernel is held to 96 VGPRs, so 5 blocks of 4
-// waves fit a CU instead of 4 (a few values spill, reloaded once per item or
-// record, never per pixel); wider instances keep the compiler's budget.
-constexpr int bwd_waves_per_simd(int CM) { return CM <= 8 ? 5 : 1; }
+// Up to 8 channels the item kernel is held to 128 VGPRs (4 blocks of 4 waves
+// per CU) and then spills nothing; held to 96 (5 blocks) it spilled inside
+// the record loop and measured 3 us slower. Wider instances keep the
+// compiler's budget.
+constexpr int bwd_waves_per_simd(int CM) { return CM <= 8 ? 4 : 1; }
 
 template <int CM, bool CAM>
 __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_bwd_items(
@@ -699,8 +700,8 @@ static void launch_finalize(const Plan& q, const BwdArgs& a, char* ws, hipStream
 // in FP64 and in a fixed order. K9a: block g adds kCamSpan spheres of one
 // scene (scene b owns blocks b + sph_off_b / kCamSpan onwards, as many as
 // its spheres need; blocks in the gaps do nothing). K9b: one block per scene
-// adds its block sums in order and maps dL/dkappa to the focal length and
-// the sensor width (kappa = f / s).
+// adds its block sums (strided over threads, then a fixed tree) and maps
+// dL/dkappa to the focal length and the sensor width (kappa = f / s).
 constexpr int kCamThreads = 256;
 constexpr int kCamVals = 13;  // R (9), t (3), kappa
 
@@ -756,24 +757,36 @@ __global__ __launch_bounds__(kCamThreads) void k_cam_partial(const SceneDev* __r
   if (t < kCamVals) part[size_t(g) * 16 + size_t(t)] = s_acc[t][0];
 }
 
-__global__ __launch_bounds__(kWave) void k_cam_final(const SceneDev* __restrict__ scenes,
-                                                     const double* __restrict__ part,
-                                                     float* __restrict__ grad_cam) {
-  __shared__ double s_v[kCamVals];
+__global__ __launch_bounds__(kCamThreads) void k_cam_final(const SceneDev* __restrict__ scenes,
+                                                          const double* __restrict__ part,
+                                                          float* __restrict__ grad_cam) {
+  __shared__ double s_acc[kCamVals][kCamThreads];
   const int b = blockIdx.x, t = threadIdx.x;
   const SceneDev& sc = scenes[b];
   const uint32_t first = cam_first_block(sc, b);
   const uint32_t nblk = (sc.n + uint32_t(kCamSpan) - 1u) / uint32_t(kCamSpan);
-  if (t < kCamVals) {
-    double v = 0.0;
-    for (uint32_t j = 0; j < nblk; ++j) v += part[size_t(first + j) * 16 + size_t(t)];
-    s_v[t] = v;
+  // thread t adds block sums t, t + kCamThreads, ...; then a fixed tree
+  double acc[kCamVals];
+#pragma unroll
+  for (int k = 0; k < kCamVals; ++k) acc[k] = 0.0;
+  for (uint32_t j = uint32_t(t); j < nblk; j += kCamThreads) {
+    const double* pj = part + size_t(first + j) * 16;
+#pragma unroll
+    for (int k = 0; k < kCamVals; ++k) acc[k] += pj[k];
   }
+#pragma unroll
+  for (int k = 0; k < kCamVals; ++k) s_acc[k][t] = acc[k];
   __syncthreads();
+  for (int w = kCamThreads / 2; w > 0; w >>= 1) {
+    if (t < w)
+#pragma unroll
+      for (int k = 0; k < kCamVals; ++k) s_acc[k][t] += s_acc[k][t + w];
+    __syncthreads();
+  }
   if (t < 14) {
-    const double f = sc.cam.f, s = sc.cam.s, gk = s_v[12];
+    const double f = sc.cam.f, s = sc.cam.s, gk = s_acc[12][0];
     // kappa = f / s: dL/df = dL/dkappa / s, dL/ds = -dL/dkappa f / s^2
-    const double v = t < 12 ? s_v[t] : (t == 12 ? gk / s : -gk * f / (s * s));
+    const double v = t < 12 ? s_acc[t][0] : (t == 12 ? gk / s : -gk * f / (s * s));
     grad_cam[size_t(b) * 14 + size_t(t)] = float(v);
   }
 }
@@ -864,7 +877,7 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
     hipLaunchKernelGGL(k_cam_partial, dim3(unsigned(q.ncampart)), dim3(kCamThreads), 0, stream,
                        tab.scenes, q.B, ws_ptr<float4>(ws, q.off_camg), a.pos,
                        ws_ptr<double>(ws, q.off_campart));
-    hipLaunchKernelGGL(k_cam_final, dim3(unsigned(q.B)), dim3(kWave), 0, stream, tab.scenes,
+    hipLaunchKernelGGL(k_cam_final, dim3(unsigned(q.B)), dim3(kCamThreads), 0, stream, tab.scenes,
                        ws_ptr<double>(ws, q.off_campart), a.grad_cam);
   }
   stage_end(PULSAR_STAGE_FINALIZE, stream);
