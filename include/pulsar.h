@@ -85,10 +85,18 @@ typedef struct pulsar_camera {
  *   aux must still be the forward's outputs for the same inputs. The
  *   gradients are bitwise those of a pulsar_bwd right after pulsar_fwd. In
  *   pulsar_fwd the flag has no effect.
+ * PULSAR_GRAD_PAPER_NORM: the paper's gradients for optimisation instead of
+ *   exact derivatives (pulsar_bwd only; C <= 32, else PULSAR_ERR_UNSUPPORTED):
+ *   every gradient of a sphere (position, radius, opacity, payload) is divided
+ *   by the number of pixels it received gradients from (App. B), and spheres
+ *   whose projected radius R f / (c_z pitch) is at most 3 pixels get no
+ *   position or radius gradient (Sec. 3.2, Sec. 7 limitation 1). Camera and
+ *   background gradients stay exact.
  * Storing per-pixel hit lists instead of recomputing them (App. B stores the
  * nearest hits per pixel) is not built: its bit is reserved. */
 #define PULSAR_NO_BWD_AUX 0x1u
 #define PULSAR_REBIN 0x2u
+#define PULSAR_GRAD_PAPER_NORM 0x4u
 
 /* Render parameters (host struct). */
 typedef struct pulsar_params {
@@ -98,8 +106,9 @@ typedef struct pulsar_params {
                            pixels wide in radius: R = max(r, min_radius_px * pitch * c_z / f)
                            (App. B, Step 0). 0 = off. */
   int32_t K;            /* nearest hits per pixel that receive gradients, 1..32 */
-  uint32_t flags;       /* OR of PULSAR_NO_BWD_AUX and PULSAR_REBIN; any other
-                           bit is reserved (PULSAR_ERR_UNSUPPORTED) */
+  uint32_t flags;       /* OR of PULSAR_NO_BWD_AUX, PULSAR_REBIN and
+                           PULSAR_GRAD_PAPER_NORM; any other bit is reserved
+                           (PULSAR_ERR_UNSUPPORTED) */
   int32_t max_pairs;    /* capacity of (screen tile, sphere) pairs; 0 = default
                            (2 n + number of tiles + 65536) */
   int32_t depth_bits;   /* bits of quantised depth in the sort key (tile lists

@@ -142,6 +142,45 @@ def backward(scene, cam, params, G, fwd: dict, rows: Optional[Sequence[int]] = N
                 grad_camera=gcam, grad_camera_abs=gabs)
 
 
+def paper_normalised(scene, cam, params, fwd: dict, grads: dict,
+                     rows: Optional[Sequence[int]] = None) -> dict:
+    """The paper's gradients for optimisation, from the exact ones: every
+    gradient of sphere k (position, radius, opacity, payload) divided by the
+    number of pixels whose K nearest hits include k (App. B, normalisation),
+    and no position or radius gradient for a sphere whose projected radius
+    R f / (c_z pitch) is at most 3 pixels (Sec. 3.2; Sec. 7, limitation 1),
+    R the effective radius (App. B, Step 0). Camera and background gradients
+    are returned unchanged. Counts run over the evaluated rows."""
+    K = int(params.K)
+    kid = np.asarray(fwd["klist_id"])
+    H = kid.shape[0]
+    sel = range(H) if rows is None else rows
+    n = int(np.asarray(scene.pos).shape[0])
+    count = np.zeros(n)
+    for i in sel:
+        ids = kid[i].reshape(-1, K)
+        ids = ids[ids >= 0]
+        np.add.at(count, ids, 1.0)
+    pos = np.asarray(scene.pos, np.float64)
+    R = np.asarray(cam.R, np.float64).reshape(3, 3)
+    cz = pos @ R[2] + float(np.asarray(cam.t, np.float64)[2])
+    pitch = float(cam.sensor_width) / float(cam.width)
+    r = np.asarray(scene.radius, np.float64)
+    reff = np.maximum(r, float(params.min_radius_px) * pitch * cz / float(cam.focal)) \
+        if params.min_radius_px > 0 else r
+    gated = ~(reff * float(cam.focal) / (cz * pitch) > 3.0)
+    scale = np.where(count > 0, 1.0 / np.maximum(count, 1.0), 1.0)
+    out = dict(grads)
+    out["grad_pos"] = grads["grad_pos"] * (scale * ~gated)[:, None]
+    out["grad_radius"] = grads["grad_radius"] * scale * ~gated
+    if grads.get("grad_opacity") is not None:
+        out["grad_opacity"] = grads["grad_opacity"] * scale
+    out["grad_payload"] = grads["grad_payload"] * scale[:, None]
+    out["pixel_count"] = count
+    out["projected_radius_px"] = reff * float(cam.focal) / (cz * pitch)
+    return out
+
+
 def pixel_hits(scene, cam, params, i: int, j: int) -> dict:
     """Per-sphere ray test of pixel (i, j): hit, t, q, b, camera-space centre, radius, ray."""
     lib = _load()

@@ -61,7 +61,8 @@ int check_params(const pulsar_params_t* p) {
     return PULSAR_ERR_INVALID_ARGUMENT;
   if (p->raster_blocks != 0 && (p->raster_blocks < 256 || p->raster_blocks > 65536))
     return PULSAR_ERR_INVALID_ARGUMENT;
-  if ((p->flags & ~(PULSAR_NO_BWD_AUX | PULSAR_REBIN)) != 0u || p->reserved != 0)
+  if ((p->flags & ~(PULSAR_NO_BWD_AUX | PULSAR_REBIN | PULSAR_GRAD_PAPER_NORM)) != 0u ||
+      p->reserved != 0)
     return PULSAR_ERR_UNSUPPORTED;
   return PULSAR_OK;
 }
@@ -216,7 +217,7 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   // 32; wider payloads keep only dL/dc, dL/dR | dL/do in the record
   int bcm = 1;
   while (bcm < C && bcm < kBwdChannels) bcm *= 2;
-  q.bwd_ps4 = C <= kBwdChannels ? 1 + (bcm + 4) / 4 : 2;
+  q.bwd_ps4 = C <= kBwdChannels ? 1 + (bcm + 6) / 4 : 2;
   q.off_pslot = take(size_t(cap) * size_t(q.bwd_ps4) * 16);
   q.off_sfirst = take(nn * 4);
   q.ncampart = int64_t(q.B) + n / kCamSpan + 1;
@@ -341,6 +342,9 @@ static int bwd_impl(const pulsar_scene_t* scenes, int32_t B, const float* pos,
   if (!background || !image || !aux || !grad_image || !ws) return PULSAR_ERR_INVALID_ARGUMENT;
   if (grad_opacity && !opacity) return PULSAR_ERR_INVALID_ARGUMENT;
   const bool rebin = (params->flags & PULSAR_REBIN) != 0u;
+  const bool paper_norm = (params->flags & PULSAR_GRAD_PAPER_NORM) != 0u;
+  // the wide backward adds payload gradients in place, per hit
+  if (paper_norm && C > kBwdChannels) return PULSAR_ERR_UNSUPPORTED;
   // without the forward's thresholds in the workspace only a rebin can help
   if (!rebin && (params->flags & PULSAR_NO_BWD_AUX) != 0u) return PULSAR_ERR_INVALID_ARGUMENT;
   if (ws_bytes < q.total) return PULSAR_ERR_WORKSPACE;
@@ -379,6 +383,7 @@ static int bwd_impl(const pulsar_scene_t* scenes, int32_t B, const float* pos,
   a.grad_payload = grad_payload;
   a.grad_bg = grad_background;
   a.grad_cam = grad_camera;
+  a.paper_norm = paper_norm;
   a.min_radius_px = params->min_radius_px;
   a.eps2 = sc[0].bc.eps2;
   hipError_t e = launch_backward(q, a, static_cast<char*>(ws), static_cast<hipStream_t>(stream));

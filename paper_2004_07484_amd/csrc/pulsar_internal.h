@@ -107,8 +107,8 @@ struct Plan {
   size_t off_mlist;  // tiles with several work items, for the merge kernel
   size_t off_scenes, off_starts;  // scene table and its start arrays
   // backward: one sum slot per (tile, sphere) pair at its emission position,
-  // bwd_ps4 float4 each (dL/dc, dL/dR | dL/df[cm] | dL/do, dL/d(f/s),
-  // padding), and each sphere's first emission position
+  // bwd_ps4 float4 each (dL/dc, dL/dR | dL/df[cm] | dL/do, dL/d(f/s), pixel
+  // count, padding), and each sphere's first emission position
   size_t off_pslot, off_sfirst;
   // camera gradients: per sphere float4 (dL/dc, dL/d(f/s)); per-scene runs of
   // partial sums, 16 doubles each (scene b's run starts at b + first sphere /
@@ -159,6 +159,7 @@ struct BwdArgs {
   float* grad_payload;
   float* grad_bg;
   float* grad_cam;  // [B, 14]: dL/dR (3x3), dL/dt, dL/df, dL/ds per scene, or null
+  bool paper_norm;  // per-pixel averaging and the 3-pixel position gate
   float min_radius_px;
   float eps2;  // eps / gamma * log2(e), the background exponent (camera independent)
 };

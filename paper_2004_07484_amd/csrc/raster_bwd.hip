@@ -236,8 +236,8 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
       }
       // the pair's sums go whole into its slot
       float4* sr = A.pslot + size_t(id) * size_t(A.ps4);
-      // float4 holding dL/df[CM], then dL/do and dL/d(f/s)
-      constexpr int NT = (CM + 4) / 4;
+      // float4 holding dL/df[CM], then dL/do, dL/d(f/s) and the pixel count
+      constexpr int NT = (CM + 6) / 4;
       sr[0] = make_float4(gcx, gcy, gcz, gR);
 #pragma unroll
       for (int q = 0; q < NT; ++q) {
@@ -245,11 +245,11 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int k = 4 * q + u;
-          v[u] = k < CM ? gf[k < CM ? k : 0] : (k == CM ? go : (k == CM + 1 ? gk : 0.f));
+          v[u] = k < CM ? gf[k < CM ? k : 0]
+                        : (k == CM ? go : (k == CM + 1 ? gk : (k == CM + 2 ? float(nh) : 0.f)));
         }
         sr[1 + q] = make_float4(v[0], v[1], v[2], v[3]);
       }
-      (void)nh;
     }
   }
   // then the background-gradient block sums on the same grid (their reads
@@ -387,7 +387,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
     const float4* __restrict__ pslot, int ps4, float* __restrict__ grad_pos,
     float* __restrict__ grad_radius, float* __restrict__ grad_opacity,
     float* __restrict__ grad_payload, uint32_t nfin, const float* __restrict__ bgsum,
-    float* __restrict__ grad_bg, float4* __restrict__ camg) {
+    float* __restrict__ grad_bg, float4* __restrict__ camg, int paper_norm) {
   constexpr int CS = CM > 0 ? CM : 1;
   __shared__ uint32_t s_cnt[kFinThreads];
   __shared__ float s_gp[3 * kFinThreads];
@@ -419,7 +419,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
   const uint32_t base = t < nloc ? sfirst[i] : 0u;
   s_cnt[t] = count;
   float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
-  float go = 0.f, gk = 0.f;
+  float go = 0.f, gk = 0.f, npx = 0.f;
   float gf[CS];
 #pragma unroll
   for (int c = 0; c < CS; ++c) gf[c] = 0.f;
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
         g.z += a.z;
         g.w += a.w;
         if (CM > 0) {
-          constexpr int NT = (CM + 4) / 4;
+          constexpr int NT = (CM + 6) / 4;
 #pragma unroll
           for (int q = 0; q < NT; ++q) {
             const float4 v = sr[1 + q];
@@ -448,6 +448,8 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
                 go += vv[u];
               else if (kk == CM + 1)
                 gk += vv[u];
+              else if (kk == CM + 2)
+                npx += vv[u];
             }
           }
         } else {
@@ -458,37 +460,45 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
       }
     }
   }
+  // the paper's optimisation-friendly variant (App. B normalisation, Sec. 7
+  // limitation 1): every gradient of a sphere divided by the number of
+  // pixels it received gradients from; position and radius gradients only
+  // for spheres wider than 3 pixels in radius (R f / (c_z pitch))
+  const float scale = (paper_norm && npx > 0.f) ? 1.f / npx : 1.f;
   if (t < nloc) {
-    if (grad_opacity) grad_opacity[i] = go;
+    if (grad_opacity) grad_opacity[i] = go * scale;
     if (grad_pos || grad_radius || camg) {
       float gx = g.x, gy = g.y, gz = g.z, gR = g.w;
-      bool clamped = false;
+      bool clamped = false, gated = false;
       const CamDev cam = tab.scenes[find_scene(tab.sph_start, tab.B, uint32_t(i))].cam;
-      if (count != 0u && min_radius_px > 0.f) {
+      if (count != 0u && (min_radius_px > 0.f || paper_norm)) {
         const float px = pos[3 * i + 0], py = pos[3 * i + 1], pz = pos[3 * i + 2];
         const double cz = double(cam.R[6]) * px + double(cam.R[7]) * py +
                           double(cam.R[8]) * pz + double(cam.t[2]);
         const double pitch = double(cam.s) / double(cam.W);
         const double k = double(min_radius_px) * pitch / double(cam.f);
-        clamped = k * cz > double(radius[i]);
+        clamped = min_radius_px > 0.f && k * cz > double(radius[i]);
         if (clamped) {
           gz += float(double(gR) * k);  // R = k c_z depends on depth only
           // and on the camera through k = min_radius_px / (W kappa):
           // dR/dkappa = -R / kappa
           gk -= float(double(gR) * k * cz * double(cam.s) / double(cam.f));
         }
+        const double reff = clamped ? k * cz : double(radius[i]);
+        gated = paper_norm && !(reff * double(cam.f) / (cz * pitch) > 3.0);
       }
       if (camg) camg[i] = make_float4(gx, gy, gz, gk);
-      if (grad_radius) grad_radius[i] = clamped ? 0.f : gR;
+      if (grad_radius) grad_radius[i] = (clamped || gated) ? 0.f : gR * scale;
       // c = R p + t  =>  dL/dp = R^T dL/dc
-      s_gp[3 * t + 0] = cam.R[0] * gx + cam.R[3] * gy + cam.R[6] * gz;
-      s_gp[3 * t + 1] = cam.R[1] * gx + cam.R[4] * gy + cam.R[7] * gz;
-      s_gp[3 * t + 2] = cam.R[2] * gx + cam.R[5] * gy + cam.R[8] * gz;
+      const float ps = gated ? 0.f : scale;
+      s_gp[3 * t + 0] = (cam.R[0] * gx + cam.R[3] * gy + cam.R[6] * gz) * ps;
+      s_gp[3 * t + 1] = (cam.R[1] * gx + cam.R[4] * gy + cam.R[7] * gz) * ps;
+      s_gp[3 * t + 2] = (cam.R[2] * gx + cam.R[5] * gy + cam.R[8] * gz) * ps;
     }
   }
   if (CM > 0) {
 #pragma unroll
-    for (int c = 0; c < CS; ++c) s_pay[t * CS + c] = gf[c];
+    for (int c = 0; c < CS; ++c) s_pay[t * CS + c] = gf[c] * scale;
   }
   __syncthreads();
   if (grad_pos) {
@@ -692,7 +702,7 @@ static void launch_finalize(const Plan& q, const BwdArgs& a, char* ws, hipStream
                      a.min_radius_px, a.C, ws_ptr<float4>(ws, q.off_pslot), q.bwd_ps4, a.grad_pos,
                      a.grad_radius, a.grad_opacity, a.grad_payload, nfin,
                      ws_ptr<float>(ws, q.off_bgsum), a.grad_bg,
-                     a.grad_cam ? ws_ptr<float4>(ws, q.off_camg) : nullptr);
+                     a.grad_cam ? ws_ptr<float4>(ws, q.off_camg) : nullptr, a.paper_norm ? 1 : 0);
 }
 
 // Camera gradients: dL/dR = sum_i dL/dc_i p_i^T, dL/dt = sum_i dL/dc_i and

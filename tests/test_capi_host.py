@@ -113,15 +113,15 @@ def test_bad_params_are_rejected(par_kw, code):
 
 
 def test_reserved_flags_are_unsupported():
-    for bit in [0x4, 0x8, 0x80000000]:
+    for bit in [0x8, 0x10, 0x80000000]:
         p = _capi.make_params(flags=bit | _capi.PULSAR_REBIN)
         assert _call_fwd(_cam(), p) == _capi.PULSAR_ERR_UNSUPPORTED
 
 
 def test_known_flags_pass_validation():
     # validation accepts them and stops at the next check, the workspace size
-    for flags in [_capi.PULSAR_NO_BWD_AUX, _capi.PULSAR_REBIN,
-                  _capi.PULSAR_NO_BWD_AUX | _capi.PULSAR_REBIN]:
+    for flags in [_capi.PULSAR_NO_BWD_AUX, _capi.PULSAR_REBIN, _capi.PULSAR_GRAD_PAPER_NORM,
+                  _capi.PULSAR_NO_BWD_AUX | _capi.PULSAR_REBIN | _capi.PULSAR_GRAD_PAPER_NORM]:
         p = _capi.make_params(flags=flags)
         assert _call_fwd(_cam(), p, ws_bytes=1024) == _capi.PULSAR_ERR_WORKSPACE
         # flags change no workspace size
@@ -167,6 +167,12 @@ def test_backward_argument_checks():
     assert lib.pulsar_bwd_camera(*cam_small) == _capi.PULSAR_ERR_WORKSPACE
     cam_bad_aux = bad_aux[:17] + [FAKE] + bad_aux[17:]
     assert lib.pulsar_bwd_camera(*cam_bad_aux) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    # the paper's normalisation needs the register backward (C <= 32)
+    norm = _capi.make_params(flags=_capi.PULSAR_GRAD_PAPER_NORM)
+    args_wide = list(args)
+    args_wide[5] = 40
+    args_wide[8] = ctypes.byref(norm)
+    assert lib.pulsar_bwd(*args_wide) == _capi.PULSAR_ERR_UNSUPPORTED
     rebin = _capi.make_params(flags=_capi.PULSAR_NO_BWD_AUX | _capi.PULSAR_REBIN)
     args_rb = list(small)
     args_rb[8] = ctypes.byref(rebin)

@@ -282,3 +282,50 @@ def test_only_requested_gradients_are_written():
     assert part["grad_pos"] is None and part["grad_radius"] is None
     assert_close(part["grad_payload"], full["grad_payload"], 1e-5, "payload")
     assert_close(part["grad_bg"], full["grad_bg"], 1e-5, "bg")
+
+
+@pytest.mark.parametrize("case", ["plain", "rotated", "min_radius", "dense_K3"])
+def test_paper_normalised_gradients(case):
+    """PULSAR_GRAD_PAPER_NORM: gradients averaged over each sphere's pixel
+    count and the 3-pixel position gate, against the oracle's definition.
+    Full frames without rounding-sensitive pixels, so the counts are exact."""
+    wl = sg.config1()
+    sc, cam, par = wl.scene, wl.camera, wl.params
+    # radii x4: some spheres wider than 3 pixels, no rounding-sensitive pixel
+    sc.radius = (sc.radius * 4.0).astype(np.float32)
+    if case == "rotated":
+        rng = np.random.default_rng(8)
+        q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+        q = q * np.sign(np.diag(r))
+        if np.linalg.det(q) < 0:
+            q[:, 0] = -q[:, 0]
+        tq = rng.uniform(-1, 1, 3)
+        sc.pos = ((sc.pos.astype(np.float64) - tq) @ q).astype(np.float32)
+        cam.R, cam.t = q.astype(np.float32), tq.astype(np.float32)
+    if case == "min_radius":
+        par = sg.Params(gamma=0.1, eps=1e-5, min_radius_px=0.7071, K=5)
+    if case == "dense_K3":
+        sc.radius = (sc.radius * 1.25).astype(np.float32)
+        par = sg.Params(gamma=0.1, eps=1e-5, K=3)
+    _say(f"[parity] paper-normalised gradients, {case}")
+    fwd = ref.forward(sc, cam, par)
+    assert not fwd["ambiguous"].any()
+    G = sg.upstream_grad(700, cam.height, cam.width, sc.C)
+    g = ref.paper_normalised(sc, cam, par, fwd, ref.backward(sc, cam, par, G, fwd))
+    pr = g["projected_radius_px"]
+    assert (pr <= 3.0).any() and (pr > 3.0).any()
+    assert np.all(np.abs(pr - 3.0) > 1e-4)  # gate decisions are not rounding-sensitive
+    out = gpu_render(sc, cam, par, G, bwd_flags=_capi.PULSAR_GRAD_PAPER_NORM)
+    assert out["status"] == _capi.PULSAR_OK
+    compare_grads(out, g, f"paper-normalised {case}")
+
+
+def test_paper_normalisation_rejects_wide_payloads():
+    import torch
+    wl = sg.tiny_scene(3, n=4, C=40)
+    sc, cam, par = wl.scene, wl.camera, wl.params
+    with pytest.raises(_capi.PulsarError) as e:
+        gpu_render(sc, cam, par, np.ones((cam.height, cam.width, 40), np.float32),
+                   bwd_flags=_capi.PULSAR_GRAD_PAPER_NORM)
+    assert e.value.code == _capi.PULSAR_ERR_UNSUPPORTED
+    torch.cuda.synchronize()

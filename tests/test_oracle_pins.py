@@ -357,6 +357,43 @@ def test_camera_pose_gradient_is_the_rotated_position_sum():
                                atol=1e-12 * np.abs(gc).sum())
 
 
+def test_paper_normalisation_counts_and_gate():
+    """The optimisation variant of the gradients: the pixel count of every
+    sphere equals a brute-force count from per-pixel ray tests (its rank in
+    (t, index) order below K), small spheres lose exactly their position and
+    radius gradients, and the rest is the exact gradient over the count."""
+    wl = sg.tiny_scene(21, n=8, C=2, W=32, H=32, r_lo=0.05, r_hi=0.5)
+    sc, cam = as_f64(wl.scene), wl.camera
+    params = sg.Params(gamma=0.3, eps=1e-5, K=3)
+    fwd = ref.forward(sc, cam, params)
+    G = sg.upstream_grad(55, 32, 32, 2).astype(np.float64)
+    exact = ref.backward(sc, cam, params, G, fwd)
+    pn = ref.paper_normalised(sc, cam, params, fwd, exact)
+    n = sc.pos.shape[0]
+    brute = np.zeros(n)
+    for i in range(32):
+        for j in range(32):
+            h = ref.pixel_hits(sc, cam, params, i, j)
+            ks = sorted(np.nonzero(h["hit"])[0], key=lambda k: (h["t"][k], k))[:params.K]
+            brute[ks] += 1
+    np.testing.assert_array_equal(pn["pixel_count"], brute)
+    # projected radius against the pinhole intrinsics: f in pixels times R / c_z
+    fpx = cam.focal * cam.width / cam.sensor_width
+    np.testing.assert_allclose(pn["projected_radius_px"], fpx * sc.radius / sc.pos[:, 2],
+                               rtol=1e-12)
+    small = pn["projected_radius_px"] <= 3.0
+    assert small.any() and (~small).any() and (brute > 1).any()
+    seen = brute > 0
+    for key in ["grad_opacity", "grad_payload"]:
+        want = exact[key][seen] / (brute[seen][:, None] if exact[key].ndim == 2 else brute[seen])
+        np.testing.assert_allclose(pn[key][seen], want, rtol=1e-12)
+    assert np.all(pn["grad_pos"][small] == 0) and np.all(pn["grad_radius"][small] == 0)
+    big = seen & ~small
+    np.testing.assert_allclose(pn["grad_pos"][big], exact["grad_pos"][big] / brute[big][:, None],
+                               rtol=1e-12)
+    np.testing.assert_array_equal(pn["grad_bg"], exact["grad_bg"])
+
+
 def test_truncated_gradient_is_masked_derivative():
     """With K below the hit count, sphere j's gradient is the derivative of
     sum over pixels where j is among the K nearest of G * F (App. B, Step 2):
