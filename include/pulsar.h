@@ -86,7 +86,7 @@ typedef struct pulsar_camera {
  *   gradients are bitwise those of a pulsar_bwd right after pulsar_fwd. In
  *   pulsar_fwd the flag has no effect.
  * PULSAR_GRAD_PAPER_NORM: the paper's gradients for optimisation instead of
- *   exact derivatives (pulsar_bwd only; C <= 32, else PULSAR_ERR_UNSUPPORTED):
+ *   exact derivatives (pulsar_bwd only):
  *   every gradient of a sphere (position, radius, opacity, payload) is divided
  *   by the number of pixels it received gradients from (App. B), and spheres
  *   whose projected radius R f / (c_z pitch) is at most 3 pixels get no

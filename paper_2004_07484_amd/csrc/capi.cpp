@@ -343,8 +343,6 @@ static int bwd_impl(const pulsar_scene_t* scenes, int32_t B, const float* pos,
   if (grad_opacity && !opacity) return PULSAR_ERR_INVALID_ARGUMENT;
   const bool rebin = (params->flags & PULSAR_REBIN) != 0u;
   const bool paper_norm = (params->flags & PULSAR_GRAD_PAPER_NORM) != 0u;
-  // the wide backward adds payload gradients in place, per hit
-  if (paper_norm && C > kBwdChannels) return PULSAR_ERR_UNSUPPORTED;
   // without the forward's thresholds in the workspace only a rebin can help
   if (!rebin && (params->flags & PULSAR_NO_BWD_AUX) != 0u) return PULSAR_ERR_INVALID_ARGUMENT;
   if (ws_bytes < q.total) return PULSAR_ERR_WORKSPACE;

@@ -303,7 +303,7 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A,
           pair_position(a, d, uint32_t(A.boff[id / kProjectBlock]), tx0 / kTileW, ty0 / kTileH);
       const uint32_t p1 = __float_as_uint(d.z);
       const float* fk = A.payload + size_t(id) * size_t(C);
-      float gcx = 0.f, gcy = 0.f, gcz = 0.f, gR = 0.f, go = 0.f, gk = 0.f;
+      float gcx = 0.f, gcy = 0.f, gcz = 0.f, gR = 0.f, go = 0.f, gk = 0.f, npx = 0.f;
       const int xa = max(s.x0, tx0), xb = min(int(p1 & 0xffffu), tx0 + kTileW - 1);
       const int ya = max(s.y0, ty0), yb = min(int(p1 >> 16), ty0 + kTileH - 1);
       const float tlo = front_bound(s);
@@ -349,13 +349,14 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A,
             g.coef = coef;
             gk += hit_grad_kappa(ray, s, h, cam, g);
           }
+          npx += 1.f;
         }
       }
-      // dL/dc, dL/dR, dL/do whole into the pair's slot (the payload terms
-      // went out per hit)
+      // dL/dc, dL/dR, dL/do, dL/d(f/s) and the pixel count whole into the
+      // pair's slot (the payload terms went out per hit)
       float4* sr = A.pslot + size_t(slot) * size_t(A.ps4);
       sr[0] = make_float4(gcx, gcy, gcz, gR);
-      sr[1] = make_float4(go, gk, 0.f, 0.f);
+      sr[1] = make_float4(go, gk, npx, 0.f);
     }
   }
 }
@@ -456,6 +457,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
           const float4 v = sr[1];
           go += v.x;
           gk += v.y;
+          npx += v.z;
         }
       }
     }
@@ -524,6 +526,9 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
   } else if (t < nloc && count == 0u) {
     // the wide path added into the caller's rows; spheres without a tile get zeros
     for (int c = 0; c < C; ++c) grad_payload[size_t(i) * size_t(C) + c] = 0.f;
+  } else if (t < nloc && scale != 1.f) {
+    // ... and its per-hit sums take the pixel-count average here
+    for (int c = 0; c < C; ++c) grad_payload[size_t(i) * size_t(C) + c] *= scale;
   }
 }
 

@@ -167,12 +167,6 @@ def test_backward_argument_checks():
     assert lib.pulsar_bwd_camera(*cam_small) == _capi.PULSAR_ERR_WORKSPACE
     cam_bad_aux = bad_aux[:17] + [FAKE] + bad_aux[17:]
     assert lib.pulsar_bwd_camera(*cam_bad_aux) == _capi.PULSAR_ERR_INVALID_ARGUMENT
-    # the paper's normalisation needs the register backward (C <= 32)
-    norm = _capi.make_params(flags=_capi.PULSAR_GRAD_PAPER_NORM)
-    args_wide = list(args)
-    args_wide[5] = 40
-    args_wide[8] = ctypes.byref(norm)
-    assert lib.pulsar_bwd(*args_wide) == _capi.PULSAR_ERR_UNSUPPORTED
     rebin = _capi.make_params(flags=_capi.PULSAR_NO_BWD_AUX | _capi.PULSAR_REBIN)
     args_rb = list(small)
     args_rb[8] = ctypes.byref(rebin)

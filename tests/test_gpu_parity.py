@@ -320,12 +320,20 @@ def test_paper_normalised_gradients(case):
     compare_grads(out, g, f"paper-normalised {case}")
 
 
-def test_paper_normalisation_rejects_wide_payloads():
-    import torch
-    wl = sg.tiny_scene(3, n=4, C=40)
-    sc, cam, par = wl.scene, wl.camera, wl.params
-    with pytest.raises(_capi.PulsarError) as e:
-        gpu_render(sc, cam, par, np.ones((cam.height, cam.width, 40), np.float32),
-                   bwd_flags=_capi.PULSAR_GRAD_PAPER_NORM)
-    assert e.value.code == _capi.PULSAR_ERR_UNSUPPORTED
-    torch.cuda.synchronize()
+def test_paper_normalisation_wide_payload():
+    """C > 32 takes the wide backward, whose payload gradients are added per
+    hit and averaged afterwards."""
+    rng = np.random.default_rng(23)
+    sc = sg.box_scene(rng, 120, 40, 0.15, 0.7)
+    cam = sg.identity_camera(40, 40)
+    par = sg.Params(gamma=0.1, eps=1e-5, K=4)
+    _say("[parity] paper-normalised gradients, C=40")
+    fwd = ref.forward(sc, cam, par)
+    assert not fwd["ambiguous"].any()
+    G = sg.upstream_grad(701, cam.height, cam.width, sc.C)
+    g = ref.paper_normalised(sc, cam, par, fwd, ref.backward(sc, cam, par, G, fwd))
+    pr = g["projected_radius_px"]
+    assert (pr <= 3.0).any() and (pr > 3.0).any() and np.all(np.abs(pr - 3.0) > 1e-4)
+    out = gpu_render(sc, cam, par, G, bwd_flags=_capi.PULSAR_GRAD_PAPER_NORM)
+    assert out["status"] == _capi.PULSAR_OK
+    compare_grads(out, g, "paper-normalised C=40")
