@@ -98,6 +98,12 @@ typedef struct pulsar_camera {
 #define PULSAR_REBIN 0x2u
 #define PULSAR_GRAD_PAPER_NORM 0x4u
 
+/* min_radius_px preset for the paper's rule that every sphere is drawn at
+ * least one pixel large, so none falls between the pixel rays (App. B,
+ * Step 0): a projected disk of radius sqrt(2)/2 pixel contains a pixel
+ * centre wherever it lies. */
+#define PULSAR_MIN_RADIUS_PX_PAPER 0.70710678f
+
 /* Render parameters (host struct). */
 typedef struct pulsar_params {
   float gamma;          /* blending softness of Eq. 1, in [1e-5, 1] (Sec. 3.2) */

@@ -222,8 +222,11 @@ class Renderer(torch.nn.Module):
     """Lst. 1 style renderer: Renderer(width, height, max_num_spheres)(pos, payload, radius, cam).
 
     The camera is an 8-vector [t, axis-angle, focal, sensor_width] or an
-    object with R, t, focal and sensor_width. ``max_depth`` is the far clip
+    object with R, t, focal and sensor_width; an 8-vector tensor that
+    requires grad receives dLoss/dcamera. ``max_depth`` is the far clip
     zfar and ``min_depth`` the near clip znear of the depth mapping.
+    ``min_radius_px=_capi.PULSAR_MIN_RADIUS_PX_PAPER`` draws every sphere at
+    least one pixel large, as the paper does.
     """
 
     def __init__(self, width: int, height: int, max_num_spheres: int, n_channels: int = 3,

@@ -394,6 +394,30 @@ def test_paper_normalisation_counts_and_gate():
     np.testing.assert_array_equal(pn["grad_bg"], exact["grad_bg"])
 
 
+def test_paper_minimum_size_reaches_a_pixel_centre():
+    """With min_radius_px = sqrt(2)/2 (the one-pixel rule of App. B, Step 0)
+    every sphere far too small to be seen is still hit by at least one pixel
+    ray: brute force over every pixel of a 24 x 24 image."""
+    from paper_2004_07484_amd import _capi
+    rng = np.random.default_rng(77)
+    n = 40
+    cam = sg.identity_camera(24, 24, focal=1.5)
+    z = rng.uniform(2.0, 8.0, n)
+    half = 0.5 * cam.sensor_width / cam.focal * 0.95  # inside the field of view
+    sc = types.SimpleNamespace(
+        pos=np.stack([rng.uniform(-half, half, n) * z, rng.uniform(-half, half, n) * z, z], 1),
+        radius=np.full(n, 1e-5), opacity=None, payload=np.ones((n, 1)), bg=np.zeros(1))
+    hit_any = np.zeros(n, bool)
+    missed = np.zeros(n, bool)
+    for mr, out in [(_capi.PULSAR_MIN_RADIUS_PX_PAPER, hit_any), (0.3, missed)]:
+        params = sg.Params(gamma=0.5, eps=1e-5, min_radius_px=mr, K=4)
+        for i in range(24):
+            for j in range(24):
+                out |= ref.pixel_hits(sc, cam, params, i, j)["hit"]
+    assert hit_any.all()
+    assert not missed.all()  # a smaller minimum loses some spheres between rays
+
+
 def test_truncated_gradient_is_masked_derivative():
     """With K below the hit count, sphere j's gradient is the derivative of
     sum over pixels where j is among the K nearest of G * F (App. B, Step 2):
