@@ -181,7 +181,7 @@ int oracle_forward(int n, int C, const double* pos, const double* radius, const 
                    double gamma, double eps, double min_radius_px, int K, double amb_rel,
                    int n_rows, const int* rows, double* F, double* L, int* nhits,
                    double* klist_t, int* klist_id, double* t_next, uint8_t* ambiguous,
-                   int n_threads) {
+                   int n_threads, int blend_topk) {
   if (n < 0 || C < 1 || W < 1 || H < 1 || K < 1 || !(gamma > 0.0)) return ORACLE_BAD_ARG;
   if (n > 0 && (!pos || !radius || !payload)) return ORACLE_BAD_ARG;
   if (opacity)
@@ -224,7 +224,21 @@ int oracle_forward(int n, int C, const double* pos, const double* radius, const 
           if (s > m) m = s;
         }
       }
-      /* near misses go after the hits; the blend below reads only hits[0 .. nh) */
+      /* the top-K variant blends only the K nearest hits, in (t, index)
+         order, with the shift m taken over those */
+      int nb = nh;
+      if (blend_topk && nh > K) {
+        qsort(hits, (size_t)nh, sizeof(hit_key_t), cmp_hit);
+        nb = K;
+        m = eps / gamma;
+        for (int h = 0; h < nb; ++h) {
+          int k = hits[h].k;
+          double o = opacity ? opacity[k] : 1.0;
+          double s = o * ((cam.zfar - hits[h].t) / (cam.zfar - cam.znear)) / gamma;
+          if (s > m) m = s;
+        }
+      }
+      /* near misses go after the hits; the blend below reads only hits[0 .. nb) */
       int nall = nh;
       for (int k = 0; k < n; ++k) {
         double t;
@@ -240,7 +254,7 @@ int oracle_forward(int n, int C, const double* pos, const double* radius, const 
       double wbg = exp(eps / gamma - m);
       double D = wbg;
       for (int c = 0; c < C; ++c) acc[c] = wbg * bg[c];
-      for (int h = 0; h < nh; ++h) {
+      for (int h = 0; h < nb; ++h) {
         int k = hits[h].k;
         double t = 0.0, q = 0.0, b = 0.0, d[3];
         ray_sphere(&cam, u, &sc[k], &t, &q, &b, d);

@@ -418,6 +418,50 @@ def test_paper_minimum_size_reaches_a_pixel_centre():
     assert not missed.all()  # a smaller minimum loses some spheres between rays
 
 
+def test_topk_blend_against_brute_force_and_derivative():
+    """The top-K blend: (a) with K above every pixel's hit count it is the
+    full blend; (b) per pixel it equals Eq. 1 written out over the K nearest
+    hits of a brute-force ray test; (c) the backward, given its F and L, is
+    its exact derivative (central differences; the scene has no pixel whose
+    K nearest change under the step)."""
+    wl = sg.tiny_scene(31, n=10, C=2, W=20, H=20, r_lo=0.3, r_hi=0.6)
+    sc, cam = as_f64(wl.scene), wl.camera
+    full = ref.forward(sc, cam, sg.Params(gamma=0.3, eps=1e-5, K=8))
+    top8 = ref.forward(sc, cam, sg.Params(gamma=0.3, eps=1e-5, K=8), blend_topk=True)
+    assert full["nhits"].max() <= 8
+    np.testing.assert_array_equal(top8["F"], full["F"])
+    params = sg.Params(gamma=0.3, eps=1e-5, K=2)
+    top = ref.forward(sc, cam, params, blend_topk=True)
+    assert top["nhits"].max() > 2
+    for i in range(0, 20, 3):
+        for j in range(0, 20, 3):
+            h = ref.pixel_hits(sc, cam, params, i, j)
+            ks = sorted(np.nonzero(h["hit"])[0], key=lambda k: (h["t"][k], k))[:params.K]
+            z = (cam.zfar - h["t"][ks]) / (cam.zfar - cam.znear)
+            o = sc.opacity[ks]
+            w = o * (1.0 - h["q"][ks] / h["reff"][ks]) * np.exp(o * z / params.gamma)
+            wb = np.exp(params.eps / params.gamma)
+            F = (w @ sc.payload[ks] + wb * sc.bg) / (w.sum() + wb)
+            np.testing.assert_allclose(top["F"][i, j], F, rtol=1e-12, atol=1e-14)
+    G = sg.upstream_grad(66, 20, 20, 2).astype(np.float64)
+    an = ref.backward(sc, cam, params, G, top)
+    def loss_topk(s):
+        return float(np.sum(G * ref.forward(s, cam, params, blend_topk=True)["F"]))
+    for field, gname in [("pos", "grad_pos"), ("radius", "grad_radius"),
+                         ("opacity", "grad_opacity"), ("payload", "grad_payload")]:
+        base = getattr(sc, field)
+        fd = np.zeros_like(base)
+        for idx in np.ndindex(base.shape):
+            x = base[idx]
+            hstep = 1e-6 * max(1.0, abs(x))
+            sp, sm = copy.deepcopy(sc), copy.deepcopy(sc)
+            getattr(sp, field)[idx] = x + hstep
+            getattr(sm, field)[idx] = x - hstep
+            fd[idx] = (loss_topk(sp) - loss_topk(sm)) / (2 * hstep)
+        scale = np.abs(fd).max()
+        np.testing.assert_allclose(an[gname], fd, rtol=2e-6, atol=1e-5 * scale)
+
+
 def test_truncated_gradient_is_masked_derivative():
     """With K below the hit count, sphere j's gradient is the derivative of
     sum over pixels where j is among the K nearest of G * F (App. B, Step 2):
