@@ -92,11 +92,18 @@ typedef struct pulsar_camera {
  *   whose projected radius R f / (c_z pitch) is at most 3 pixels get no
  *   position or radius gradient (Sec. 3.2, Sec. 7 limitation 1). Camera and
  *   background gradients stay exact.
+ * PULSAR_BLEND_TOPK: the other reading of K (Sec. 3.2, App. B Step 2): only
+ *   each pixel's K nearest hits in (t, index) order enter Eq. 1, in the image
+ *   and in the log-normaliser. The forward then makes one more raster pass
+ *   (the K-th nearest hit of every pixel, before blending). pulsar_bwd needs
+ *   no flag for it: given that image and aux, its gradients are the exact
+ *   derivatives of the top-K blend (away from changes of the K nearest).
  * Storing per-pixel hit lists instead of recomputing them (App. B stores the
  * nearest hits per pixel) is not built: its bit is reserved. */
 #define PULSAR_NO_BWD_AUX 0x1u
 #define PULSAR_REBIN 0x2u
 #define PULSAR_GRAD_PAPER_NORM 0x4u
+#define PULSAR_BLEND_TOPK 0x8u
 
 /* min_radius_px preset for the paper's rule that every sphere is drawn at
  * least one pixel large, so none falls between the pixel rays (App. B,
@@ -112,9 +119,9 @@ typedef struct pulsar_params {
                            pixels wide in radius: R = max(r, min_radius_px * pitch * c_z / f)
                            (App. B, Step 0). 0 = off. */
   int32_t K;            /* nearest hits per pixel that receive gradients, 1..32 */
-  uint32_t flags;       /* OR of PULSAR_NO_BWD_AUX, PULSAR_REBIN and
-                           PULSAR_GRAD_PAPER_NORM; any other bit is reserved
-                           (PULSAR_ERR_UNSUPPORTED) */
+  uint32_t flags;       /* OR of PULSAR_NO_BWD_AUX, PULSAR_REBIN,
+                           PULSAR_GRAD_PAPER_NORM and PULSAR_BLEND_TOPK; any
+                           other bit is reserved (PULSAR_ERR_UNSUPPORTED) */
   int32_t max_pairs;    /* capacity of (screen tile, sphere) pairs; 0 = default
                            (2 n + number of tiles + 65536) */
   int32_t depth_bits;   /* bits of quantised depth in the sort key (tile lists

@@ -61,7 +61,8 @@ int check_params(const pulsar_params_t* p) {
     return PULSAR_ERR_INVALID_ARGUMENT;
   if (p->raster_blocks != 0 && (p->raster_blocks < 256 || p->raster_blocks > 65536))
     return PULSAR_ERR_INVALID_ARGUMENT;
-  if ((p->flags & ~(PULSAR_NO_BWD_AUX | PULSAR_REBIN | PULSAR_GRAD_PAPER_NORM)) != 0u ||
+  if ((p->flags & ~(PULSAR_NO_BWD_AUX | PULSAR_REBIN | PULSAR_GRAD_PAPER_NORM |
+                    PULSAR_BLEND_TOPK)) != 0u ||
       p->reserved != 0)
     return PULSAR_ERR_UNSUPPORTED;
   return PULSAR_OK;
@@ -318,6 +319,7 @@ int pulsar_fwd_batched(const pulsar_scene_t* scenes, int32_t B, const float* pos
   a.aux = aux;
   a.min_radius_px = params->min_radius_px;
   a.track = aux != nullptr && (params->flags & PULSAR_NO_BWD_AUX) == 0u;
+  a.topk = (params->flags & PULSAR_BLEND_TOPK) != 0u;
   hipError_t e = launch_forward(q, sc, a, static_cast<char*>(ws),
                                 static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail_hip(e);
@@ -360,6 +362,7 @@ static int bwd_impl(const pulsar_scene_t* scenes, int32_t B, const float* pos,
     f.aux = nullptr;
     f.min_radius_px = params->min_radius_px;
     f.track = true;
+    f.topk = false;
     hipError_t e = launch_rebin(q, sc, f, static_cast<char*>(ws),
                                 static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail_hip(e);

@@ -142,6 +142,7 @@ struct FwdArgs {
   float* aux;
   float min_radius_px;
   bool track;  // keep each pixel's K nearest hits for a following backward
+  bool topk;   // blend only each pixel's K nearest hits
 };
 
 struct BwdArgs {

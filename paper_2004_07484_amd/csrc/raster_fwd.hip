@@ -113,6 +113,7 @@ struct FwdKernelArgs {
   long long pcap;
   int C, c0, cn, K, pstride, kfield;  // kfield: first K-list field of a partial state
   int track;                          // keep K-lists (first channel pass, backward state on)
+  int topk;                           // blend only hits up to thr (the K nearest)
   int vec4;                           // one channel pass, C % 4 == 0, 16-byte aligned image
   uint32_t T;                         // tiles of all scenes
   int fill_in_tail;                   // empty tiles filled by the work-item kernel
@@ -230,6 +231,15 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM)) void k_fwd_chunk
     const int tx0 = ts.tx0, ty0 = ts.ty0;
     const float* bg = A.bg + size_t(ts.b) * size_t(A.C);
     const PixelRay ray = make_ray(cam, tx0 + (lane % kTileW), ty0 + (lane / kTileW));
+    // top-K blend: only hits up to the pixel's K-th nearest (t, id) count
+    float tk = INFINITY;
+    uint32_t ik = 0xffffffffu;
+    if (A.topk && ray.px < cam.W && ray.py < cam.H) {
+      const float2 th = A.thr[size_t(sc.pix_off) + size_t(ray.py) * size_t(cam.W) +
+                              size_t(ray.px)];
+      tk = th.x;
+      ik = __float_as_uint(th.y);
+    }
     __syncthreads();  // the previous chunk's LDS reads are done
     s_iv2[lane] = ray.inv_v2;
     // the background enters only through the tile's first chunk
@@ -326,7 +336,8 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM)) void k_fwd_chunk
         hits &= hits - 1ull;
         const SphereRec s = unpack_rec(s_rec[0][k], s_rec[1][k], s_rec[2][k], s_rec[3][k]);
         Hit h;
-        const bool hit = exact_hit(ray, s, bc.zfar, h) && act;
+        const bool hit = exact_hit(ray, s, bc.zfar, h) && act &&
+                         (h.t < tk || (h.t == tk && s_id[k] <= ik));
         const float s2 = s.o * (bc.zfar - h.t) * bc.kz;
         const bool grow = hit && s2 > m2;
         if (__ballot(grow) != 0ull) {
@@ -542,9 +553,11 @@ static FwdKernelArgs raster_args(const Plan& q, const std::vector<SceneDev>& sce
   A.c0 = 0;
   A.cn = 0;
   A.track = 0;
+  A.topk = 0;
   A.vec4 = 0;
   return A;
 }
+
 
 static void dispatch_klist(const Plan& q, const FwdKernelArgs& A, hipStream_t stream) {
   if (q.klist_slots <= 4)
@@ -555,6 +568,20 @@ static void dispatch_klist(const Plan& q, const FwdKernelArgs& A, hipStream_t st
     dispatch_cm<16>(q, A, stream);
   else
     dispatch_cm<32>(q, A, stream);
+}
+
+// Each pixel's K-th nearest hit into thr: one pass with no channel. The
+// weights and K-lists are those of the blending pass (the same summation
+// order, so the same thresholds), but no payload is read and neither image,
+// log-normaliser nor empty tiles are written.
+static void launch_thresholds(const Plan& q, const std::vector<SceneDev>& scenes,
+                              const FwdArgs& a, char* ws, hipStream_t stream) {
+  FwdKernelArgs A = raster_args(q, scenes, a, ws);
+  A.image = nullptr;
+  A.aux = nullptr;
+  A.fill_in_tail = 0;
+  A.track = 1;
+  dispatch_klist(q, A, stream);
 }
 
 static void launch_tile_lists(const Plan& q, const std::vector<SceneDev>& scenes,
@@ -570,11 +597,14 @@ static void launch_tile_lists(const Plan& q, const std::vector<SceneDev>& scenes
 hipError_t launch_forward(const Plan& q, const std::vector<SceneDev>& scenes, const FwdArgs& a,
                           char* ws, hipStream_t stream) {
   launch_tile_lists(q, scenes, a, ws, stream);
+  // the top-K blend needs every pixel's K-th nearest hit before blending
+  if (a.topk) launch_thresholds(q, scenes, a, ws, stream);
   FwdKernelArgs A = raster_args(q, scenes, a, ws);
+  A.topk = a.topk ? 1 : 0;
   for (int c0 = 0; c0 < a.C; c0 += kFwdChannels) {
     A.c0 = c0;
     A.cn = a.C - c0 < kFwdChannels ? a.C - c0 : kFwdChannels;
-    A.track = (c0 == 0 && a.track) ? 1 : 0;
+    A.track = (c0 == 0 && a.track && !a.topk) ? 1 : 0;
     A.vec4 = (a.C <= kFwdChannels && (a.C & 3) == 0 &&
               (reinterpret_cast<uintptr_t>(a.image) & 15u) == 0u)
                  ? 1
@@ -587,16 +617,7 @@ hipError_t launch_forward(const Plan& q, const std::vector<SceneDev>& scenes, co
 hipError_t launch_rebin(const Plan& q, const std::vector<SceneDev>& scenes, const FwdArgs& a,
                         char* ws, hipStream_t stream) {
   launch_tile_lists(q, scenes, a, ws, stream);
-  // one pass with no channel: the blend's weights and the K-lists are
-  // computed as in the forward (the same summation order, so the same
-  // thresholds), but no payload is read and neither image, log-normaliser
-  // nor empty tiles are written
-  FwdKernelArgs A = raster_args(q, scenes, a, ws);
-  A.image = nullptr;
-  A.aux = nullptr;
-  A.fill_in_tail = 0;
-  A.track = 1;
-  dispatch_klist(q, A, stream);
+  launch_thresholds(q, scenes, a, ws, stream);
   return hipGetLastError();
 }
 

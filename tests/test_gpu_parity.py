@@ -337,3 +337,44 @@ def test_paper_normalisation_wide_payload():
     out = gpu_render(sc, cam, par, G, bwd_flags=_capi.PULSAR_GRAD_PAPER_NORM)
     assert out["status"] == _capi.PULSAR_OK
     compare_grads(out, g, "paper-normalised C=40")
+
+
+@pytest.mark.parametrize("case", ["spheres1k", "dense_split_tiles", "rotated_rebin"])
+def test_topk_blend(case):
+    """PULSAR_BLEND_TOPK: only each pixel's K nearest hits enter Eq. 1 (image
+    and log-normaliser), and the unchanged backward is its derivative;
+    against the oracle's top-K forward. Pixels whose K nearest the oracle
+    flags as rounding-sensitive are left out of the image comparison and get
+    no upstream gradient."""
+    wl = sg.config1()
+    sc, cam, par = wl.scene, wl.camera, wl.params
+    chunk, bwd_flags = 0, 0
+    if case == "dense_split_tiles":
+        sc.radius = (sc.radius * 8.0).astype(np.float32)
+        chunk = 64
+    if case == "rotated_rebin":
+        rng = np.random.default_rng(9)
+        q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+        q = q * np.sign(np.diag(r))
+        if np.linalg.det(q) < 0:
+            q[:, 0] = -q[:, 0]
+        tq = rng.uniform(-1, 1, 3)
+        sc.pos = ((sc.pos.astype(np.float64) - tq) @ q).astype(np.float32)
+        cam.R, cam.t = q.astype(np.float32), tq.astype(np.float32)
+        bwd_flags = _capi.PULSAR_REBIN
+    _say(f"[parity] top-K blend, {case}")
+    fwd = ref.forward(sc, cam, par, blend_topk=True)
+    assert fwd["nhits"].max() > par.K
+    G = sg.upstream_grad(800, cam.height, cam.width, sc.C)
+    Gm = masked_G(G, None, fwd["ambiguous"])
+    out = gpu_render(sc, cam, par, Gm, chunk=chunk, fwd_flags=_capi.PULSAR_BLEND_TOPK,
+                     bwd_flags=bwd_flags)
+    assert out["status"] == _capi.PULSAR_OK
+    ok = ~fwd["ambiguous"]
+    assert_close(out["F"][ok], fwd["F"][ok], IMAGE_REL, f"top-K image {case}")
+    assert_close(out["L"][ok], fwd["L"][ok], IMAGE_REL, f"top-K log-normaliser {case}")
+    full = ref.forward(sc, cam, par)
+    deep = (fwd["nhits"] > par.K) & ok
+    assert np.abs(full["F"][deep] - fwd["F"][deep]).max() > 1e-5  # the variant matters
+    g = ref.backward(sc, cam, par, Gm, fwd)
+    compare_grads(out, g, f"top-K {case}")
