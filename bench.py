@@ -482,6 +482,42 @@ def main() -> int:
                   "extra_ms": round(cms["camera"] - cms["plain"], 4)}
         log(f"[bench] backward with camera gradients: {cms['camera']:.3f} ms (without: "
             f"{cms['plain']:.3f})")
+        # the flag variants on the same workload: top-K-only blend (forward)
+        # and the paper's gradient normalisation (backward)
+        p_topk = _capi.make_params(par.gamma, par.eps, par.min_radius_px, par.K, ps.max_pairs,
+                                   ps.depth_bits, ps.chunk, ps.raster_blocks,
+                                   _capi.PULSAR_BLEND_TOPK)
+        p_norm = _capi.make_params(par.gamma, par.eps, par.min_radius_px, par.K, ps.max_pairs,
+                                   ps.depth_bits, ps.chunk, ps.raster_blocks,
+                                   _capi.PULSAR_GRAD_PAPER_NORM)
+
+        def timed(fn, before=None):
+            evs = []
+            for k in range(args.warmup + args.steps):
+                if before is not None:
+                    before()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                fn()
+                e1.record(stream)
+                if k >= args.warmup:
+                    evs.append((e0, e1))
+            torch.cuda.synchronize()
+            return float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+        fwd_plain = timed(lambda: _capi.pulsar_fwd(pos, rad, opa, pay, bg, cs, ps, image, aux,
+                                                   ws, stream))
+        fwd_topk = timed(lambda: _capi.pulsar_fwd(pos, rad, opa, pay, bg, cs, p_topk, image, aux,
+                                                  ws, stream))
+        fwd_again = lambda: _capi.pulsar_fwd(pos, rad, opa, pay, bg, cs, ps, image, aux, ws,
+                                             stream)
+        bwd_norm = timed(lambda: _capi.pulsar_bwd(pos, rad, opa, pay, bg, cs, p_norm, image, aux,
+                                                  G, gp, gr, go, gf, gb, ws, stream), fwd_again)
+        camera["variants_ms"] = {"fwd": round(fwd_plain, 4), "fwd_topk_blend": round(fwd_topk, 4),
+                                 "bwd": round(cms["plain"], 4),
+                                 "bwd_paper_norm": round(bwd_norm, 4)}
+        log(f"[bench] forward {fwd_plain:.3f} ms, top-K blend {fwd_topk:.3f} ms; backward with "
+            f"the paper's normalisation {bwd_norm:.3f} ms")
 
     batch = None
     if not args.no_batch:
@@ -521,7 +557,7 @@ def main() -> int:
         "roofline": roofline,
         "kernels": kernels,
         "tuned_knobs": None if tune_info is None else tune_info["knobs"],
-        "camera_gradients": camera,
+        "camera_gradients_and_variants": camera,
         "batched": batch,
         "cpu_baseline": cpu,
         "paper_context": "RTX 2080, 1M spheres at 1000^2: fwd 19 ms, bwd 4.7 ms (CUDA only)",
