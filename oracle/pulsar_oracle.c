@@ -50,12 +50,13 @@
 #define ORACLE_BAD_ARG -1
 #define ORACLE_NEG_OPACITY -2
 
-/* cam[16] = R (row-major 9), t (3), f, s, near, far */
+/* cam[17] = R (row-major 9), t (3), f, s, near, far, projection (0 pinhole, 1 orthographic) */
 typedef struct {
   double R[9], t[3];
   double f, s, znear, zfar;
   int W, H;
   double pitch, sh;
+  int ortho; /* orthographic projection: parallel rays along +z from the sensor plane */
 } camera_t;
 
 typedef struct {
@@ -83,13 +84,27 @@ static void make_camera(camera_t* cam, const double* c16, int W, int H) {
   cam->H = H;
   cam->pitch = cam->s / (double)W;
   cam->sh = cam->s * (double)H / (double)W;
+  cam->ortho = c16[16] != 0.0;
 }
 
-/* unit ray through the centre of pixel (i, j) */
-static void pixel_ray(const camera_t* cam, int i, int j, double u[3]) {
+/* ray through the centre of pixel (i, j): origin o, unit direction u. The
+ * pinhole ray starts at the camera centre; the orthographic one starts at the
+ * pixel centre on the sensor plane z = 0 and runs along +z (Sec. 3.1 names
+ * both projection models). */
+static void pixel_ray(const camera_t* cam, int i, int j, double u[3], double o[3]) {
   double xs = (j + 0.5) * cam->pitch - 0.5 * cam->s;
   double ys = (i + 0.5) * cam->pitch - 0.5 * cam->sh;
+  if (cam->ortho) {
+    o[0] = xs;
+    o[1] = ys;
+    o[2] = 0.0;
+    u[0] = 0.0;
+    u[1] = 0.0;
+    u[2] = 1.0;
+    return;
+  }
   double len = sqrt(xs * xs + ys * ys + cam->f * cam->f);
+  o[0] = o[1] = o[2] = 0.0;
   u[0] = xs / len;
   u[1] = ys / len;
   u[2] = cam->f / len;
@@ -100,7 +115,10 @@ static void sphere_to_camera(const camera_t* cam, const double* pos, double r, d
   for (int a = 0; a < 3; ++a)
     sc->c[a] = cam->R[3 * a + 0] * pos[0] + cam->R[3 * a + 1] * pos[1] +
                cam->R[3 * a + 2] * pos[2] + cam->t[a];
-  double rmin = min_radius_px * cam->pitch * sc->c[2] / cam->f;
+  /* the minimum size in pixels: at depth c_z for the pinhole, at any depth
+     for the orthographic projection */
+  double rmin = cam->ortho ? min_radius_px * cam->pitch
+                           : min_radius_px * cam->pitch * sc->c[2] / cam->f;
   sc->clamped = (min_radius_px > 0.0) && (rmin > r);
   sc->R = sc->clamped ? rmin : r;
   int finite = isfinite(pos[0]) && isfinite(pos[1]) && isfinite(pos[2]) && isfinite(r) &&
@@ -111,11 +129,12 @@ static void sphere_to_camera(const camera_t* cam, const double* pos, double r, d
 /* Ray-sphere test along unit direction u. Returns 1 on a hit and fills
  * t (front intersection distance), q (distance of the centre from the ray),
  * b (projection of the centre on the ray) and d (vector from the ray to the centre). */
-static int ray_sphere(const camera_t* cam, const double u[3], const sphere_cam_t* sc,
-                      double* t, double* q, double* b, double d[3]) {
+static int ray_sphere(const camera_t* cam, const double u[3], const double o[3],
+                      const sphere_cam_t* sc, double* t, double* q, double* b, double d[3]) {
   if (!sc->take_part) return 0;
-  double bb = u[0] * sc->c[0] + u[1] * sc->c[1] + u[2] * sc->c[2];
-  double dd[3] = {sc->c[0] - bb * u[0], sc->c[1] - bb * u[1], sc->c[2] - bb * u[2]};
+  double c[3] = {sc->c[0] - o[0], sc->c[1] - o[1], sc->c[2] - o[2]};
+  double bb = u[0] * c[0] + u[1] * c[1] + u[2] * c[2];
+  double dd[3] = {c[0] - bb * u[0], c[1] - bb * u[1], c[2] - bb * u[2]};
   double qq = sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
   if (!(qq < sc->R)) return 0;
   double tt = bb - sqrt(sc->R * sc->R - qq * qq);
@@ -132,11 +151,12 @@ static int ray_sphere(const camera_t* cam, const double u[3], const sphere_cam_t
 /* Distance along u to the point of closest approach when the ray misses the
  * sphere by less than rel * R (q in [R, R (1 + rel))); used only to flag
  * pixels whose K nearest hits could change under float32 rounding. */
-static int near_miss(const camera_t* cam, const double u[3], const sphere_cam_t* sc, double rel,
-                     double* t) {
+static int near_miss(const camera_t* cam, const double u[3], const double o[3],
+                     const sphere_cam_t* sc, double rel, double* t) {
   if (!sc->take_part) return 0;
-  double bb = u[0] * sc->c[0] + u[1] * sc->c[1] + u[2] * sc->c[2];
-  double dd[3] = {sc->c[0] - bb * u[0], sc->c[1] - bb * u[1], sc->c[2] - bb * u[2]};
+  double c[3] = {sc->c[0] - o[0], sc->c[1] - o[1], sc->c[2] - o[2]};
+  double bb = u[0] * c[0] + u[1] * c[1] + u[2] * c[2];
+  double dd[3] = {c[0] - bb * u[0], c[1] - bb * u[1], c[2] - bb * u[2]};
   double qq = sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
   if (!(qq >= sc->R && qq < sc->R * (1.0 + rel))) return 0;
   if (!(bb <= cam->zfar * (1.0 + rel))) return 0;
@@ -205,14 +225,14 @@ int oracle_forward(int n, int C, const double* pos, const double* radius, const 
       int i = rows ? rows[pix / W] : (int)(pix / W);
       int j = (int)(pix % W);
       size_t p = (size_t)i * W + j;
-      double u[3];
-      pixel_ray(&cam, i, j, u);
+      double u[3], ro[3];
+      pixel_ray(&cam, i, j, u, ro);
       /* collect every intersected sphere */
       int nh = 0;
       double m = eps / gamma;
       for (int k = 0; k < n; ++k) {
         double t, q, b, d[3];
-        if (ray_sphere(&cam, u, &sc[k], &t, &q, &b, d)) {
+        if (ray_sphere(&cam, u, ro, &sc[k], &t, &q, &b, d)) {
           hits[nh].t = t;
           hits[nh].k = k;
           hits[nh].is_hit = 1;
@@ -242,7 +262,7 @@ int oracle_forward(int n, int C, const double* pos, const double* radius, const 
       int nall = nh;
       for (int k = 0; k < n; ++k) {
         double t;
-        if (near_miss(&cam, u, &sc[k], amb_rel, &t)) {
+        if (near_miss(&cam, u, ro, &sc[k], amb_rel, &t)) {
           hits[nall].t = t;
           hits[nall].k = k;
           hits[nall].is_hit = 0;
@@ -257,7 +277,7 @@ int oracle_forward(int n, int C, const double* pos, const double* radius, const 
       for (int h = 0; h < nb; ++h) {
         int k = hits[h].k;
         double t = 0.0, q = 0.0, b = 0.0, d[3];
-        ray_sphere(&cam, u, &sc[k], &t, &q, &b, d);
+        ray_sphere(&cam, u, ro, &sc[k], &t, &q, &b, d);
         double o = opacity ? opacity[k] : 1.0;
         double z = (cam.zfar - t) / (cam.zfar - cam.znear);
         double delta = 1.0 - q / sc[k].R;
@@ -350,8 +370,8 @@ int oracle_backward(int n, int C, const double* pos, const double* radius, const
       /* background weight exp(eps/gamma) / denominator */
       double wbg = exp(eps / gamma - L[p]);
       for (int c = 0; c < C; ++c) grad_bg[c] += wbg * Gp[c];
-      double u[3];
-      pixel_ray(&cam, i, j, u);
+      double u[3], ro[3];
+      pixel_ray(&cam, i, j, u, ro);
       /* the ray's unnormalised direction v = (x_s, y_s, f) and its
          derivatives: dv/df = e_z, dv/ds = (x_s / s, y_s / s, 0); then
          du/dx = (dv/dx - u (u . dv/dx)) / |v| */
@@ -371,7 +391,7 @@ int oracle_backward(int n, int C, const double* pos, const double* radius, const
         int k = klist_id[p * K + r];
         if (k < 0) break;
         double t = 0.0, q = 0.0, b = 0.0, d[3];
-        if (!ray_sphere(&cam, u, &sc[k], &t, &q, &b, d)) continue; /* cannot happen */
+        if (!ray_sphere(&cam, u, ro, &sc[k], &t, &q, &b, d)) continue; /* cannot happen */
         double o = opacity ? opacity[k] : 1.0;
         double Rk = sc[k].R;
         double z = (cam.zfar - t) / span;
@@ -392,7 +412,7 @@ int oracle_backward(int n, int C, const double* pos, const double* radius, const
           gc[3 * (size_t)k + a] += g_t * dt_dc + g_delta * ddelta_dc;
         }
         gR[k] += g_t * (-Rk / root) + g_delta * (q / (Rk * Rk));
-        if (grad_cam) {
+        if (grad_cam && !cam.ortho) {
           /* with c fixed: b = u . c, q^2 = |c|^2 - b^2, so db/du = c,
              dt/du = c - (b / root) c, d delta/du = (b / (q R)) c */
           double sdu = g_t * (1.0 - b / root) + (q > 0.0 ? g_delta * b / (q * Rk) : 0.0);
@@ -411,7 +431,10 @@ int oracle_backward(int n, int C, const double* pos, const double* radius, const
   }
   for (int k = 0; k < n; ++k) {
     double g[3] = {gc[3 * (size_t)k], gc[3 * (size_t)k + 1], gc[3 * (size_t)k + 2]};
-    if (sc[k].clamped) {
+    if (sc[k].clamped && cam.ortho) {
+      /* R = min_radius_px pitch depends on neither the sphere nor its depth */
+      grad_radius[k] = 0.0;
+    } else if (sc[k].clamped) {
       /* R = rho c_z / f depends on the depth, not on r */
       g[2] += gR[k] * min_radius_px * cam.pitch / cam.f;
       grad_radius[k] = 0.0;
@@ -457,15 +480,15 @@ int oracle_pixel_hits(int n, const double* pos, const double* radius, const doub
   if (n < 0 || W < 1 || H < 1 || i < 0 || i >= H || j < 0 || j >= W) return ORACLE_BAD_ARG;
   camera_t cam;
   make_camera(&cam, cam16, W, H);
-  double u[3];
-  pixel_ray(&cam, i, j, u);
+  double u[3], ro[3];
+  pixel_ray(&cam, i, j, u, ro);
   for (int a = 0; a < 3; ++a) u_out[a] = u[a];
   for (int k = 0; k < n; ++k) {
     sphere_cam_t sc;
     sphere_to_camera(&cam, pos + 3 * (size_t)k, radius[k], opacity ? opacity[k] : 1.0,
                      min_radius_px, &sc);
     double t = NAN, q = NAN, b = NAN, d[3];
-    hit[k] = (uint8_t)ray_sphere(&cam, u, &sc, &t, &q, &b, d);
+    hit[k] = (uint8_t)ray_sphere(&cam, u, ro, &sc, &t, &q, &b, d);
     t_out[k] = t;
     q_out[k] = q;
     b_out[k] = b;

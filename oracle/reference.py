@@ -63,7 +63,8 @@ def _ptr(a, typ=_dp):
 def camera_vector(cam) -> np.ndarray:
     return _d(np.concatenate([np.asarray(cam.R, np.float64).reshape(9),
                               np.asarray(cam.t, np.float64).reshape(3),
-                              [cam.focal, cam.sensor_width, cam.znear, cam.zfar]]))
+                              [cam.focal, cam.sensor_width, cam.znear, cam.zfar,
+                               1.0 if getattr(cam, "orthographic", False) else 0.0]]))
 
 
 def _rows(rows: Optional[Sequence[int]], H: int):

@@ -28,6 +28,8 @@ class Camera:
     ``focal`` and ``sensor_width`` share one unit (Lst. 1 passes them as
     f and s). Pixels are square: pitch = sensor_width / width. ``znear`` and
     ``zfar`` bound the hit distance that maps to the depth z in [0, 1].
+    ``orthographic``: parallel rays along +z from the pixel centres on the
+    sensor plane z = 0 instead (``focal`` then plays no part).
     """
 
     R: np.ndarray  # [3, 3] float32, world -> camera
@@ -38,6 +40,7 @@ class Camera:
     zfar: float
     width: int
     height: int
+    orthographic: bool = False
 
 
 @dataclasses.dataclass

@@ -462,6 +462,53 @@ def test_topk_blend_against_brute_force_and_derivative():
         np.testing.assert_allclose(an[gname], fd, rtol=2e-6, atol=1e-5 * scale)
 
 
+def _ortho(wl):
+    cam = copy.deepcopy(wl.camera)
+    cam.orthographic = True
+    return cam
+
+
+def test_orthographic_rays_closed_form_and_shift():
+    """Orthographic projection (Sec. 3.1): the ray of pixel (i, j) starts at
+    its centre on the sensor plane and runs along +z, so a sphere's hit is
+    t = c_z - sqrt(R^2 - q^2) with q its distance in x, y from the pixel
+    centre, the covered pixels do not depend on depth, and moving every
+    sphere by a whole number of pixels in x shifts the image by as many."""
+    wl = sg.tiny_scene(41, n=6, C=2, W=32, H=32, r_lo=0.1, r_hi=0.3)
+    sc, cam = as_f64(wl.scene), _ortho(wl)
+    params = sg.Params(gamma=0.4, eps=1e-5, K=8)
+    pitch = cam.sensor_width / cam.width
+    for (i, j) in [(5, 7), (16, 16), (20, 11)]:
+        h = ref.pixel_hits(sc, cam, params, i, j)
+        xs = (j + 0.5) * pitch - cam.sensor_width / 2
+        ys = (i + 0.5) * pitch - cam.sensor_width * cam.height / cam.width / 2
+        q = np.hypot(sc.pos[:, 0] - xs, sc.pos[:, 1] - ys)
+        want = q < sc.radius
+        np.testing.assert_array_equal(h["hit"], want)
+        np.testing.assert_allclose(h["t"][want], sc.pos[want, 2] -
+                                   np.sqrt(sc.radius[want] ** 2 - q[want] ** 2), rtol=1e-13)
+    base = ref.forward(sc, cam, params)
+    assert base["nhits"].max() >= 2
+    deeper = copy.deepcopy(sc)
+    deeper.pos[:, 2] += 1.5
+    np.testing.assert_array_equal(ref.forward(deeper, cam, params)["nhits"], base["nhits"])
+    moved = copy.deepcopy(sc)
+    moved.pos[:, 0] += 3 * pitch
+    F = ref.forward(moved, cam, params)["F"]
+    np.testing.assert_allclose(F[:, 3:], base["F"][:, :-3], rtol=1e-9, atol=1e-12)
+
+
+def test_orthographic_gradients_match_finite_differences():
+    wl = sg.tiny_scene(42, n=5, C=2, W=24, H=24, r_lo=0.15, r_hi=0.4)
+    sc, cam = as_f64(wl.scene), _ortho(wl)
+    for params in [wl.params, sg.Params(gamma=0.5, eps=1e-5, min_radius_px=2.5, K=8)]:
+        G = sg.upstream_grad(43, cam.height, cam.width, 2).astype(np.float64)
+        fwd = ref.forward(sc, cam, params)
+        assert fwd["nhits"].max() <= params.K and fwd["nhits"].sum() > 10
+        an = ref.backward(sc, cam, params, G, fwd)
+        _assert_grads_close(an, fd_grads(sc, cam, params, G), rtol=2e-6)
+
+
 def test_truncated_gradient_is_masked_derivative():
     """With K below the hit count, sphere j's gradient is the derivative of
     sum over pixels where j is among the K nearest of G * F (App. B, Step 2):
