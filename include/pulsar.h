@@ -98,12 +98,19 @@ typedef struct pulsar_camera {
  *   (the K-th nearest hit of every pixel, before blending). pulsar_bwd needs
  *   no flag for it: given that image and aux, its gradients are the exact
  *   derivatives of the top-K blend (away from changes of the K nearest).
+ * PULSAR_ORTHO: orthographic instead of pinhole projection (Sec. 3.1 names
+ *   both): the ray of pixel (i, j) starts at its centre on the sensor plane
+ *   z = 0 of camera space and runs along +z, so t is the distance from that
+ *   plane and focal plays no part (it must still be valid). The minimum size
+ *   becomes the constant radius min_radius_px * pitch. pulsar_bwd_camera
+ *   returns PULSAR_ERR_UNSUPPORTED for it.
  * Storing per-pixel hit lists instead of recomputing them (App. B stores the
  * nearest hits per pixel) is not built: its bit is reserved. */
 #define PULSAR_NO_BWD_AUX 0x1u
 #define PULSAR_REBIN 0x2u
 #define PULSAR_GRAD_PAPER_NORM 0x4u
 #define PULSAR_BLEND_TOPK 0x8u
+#define PULSAR_ORTHO 0x10u
 
 /* min_radius_px preset for the paper's rule that every sphere is drawn at
  * least one pixel large, so none falls between the pixel rays (App. B,
@@ -120,8 +127,9 @@ typedef struct pulsar_params {
                            (App. B, Step 0). 0 = off. */
   int32_t K;            /* nearest hits per pixel that receive gradients, 1..32 */
   uint32_t flags;       /* OR of PULSAR_NO_BWD_AUX, PULSAR_REBIN,
-                           PULSAR_GRAD_PAPER_NORM and PULSAR_BLEND_TOPK; any
-                           other bit is reserved (PULSAR_ERR_UNSUPPORTED) */
+                           PULSAR_GRAD_PAPER_NORM, PULSAR_BLEND_TOPK and
+                           PULSAR_ORTHO; any other bit is reserved
+                           (PULSAR_ERR_UNSUPPORTED) */
   int32_t max_pairs;    /* capacity of (screen tile, sphere) pairs; 0 = default
                            (2 n + number of tiles + 65536) */
   int32_t depth_bits;   /* bits of quantised depth in the sort key (tile lists

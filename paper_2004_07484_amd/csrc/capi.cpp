@@ -62,7 +62,7 @@ int check_params(const pulsar_params_t* p) {
   if (p->raster_blocks != 0 && (p->raster_blocks < 256 || p->raster_blocks > 65536))
     return PULSAR_ERR_INVALID_ARGUMENT;
   if ((p->flags & ~(PULSAR_NO_BWD_AUX | PULSAR_REBIN | PULSAR_GRAD_PAPER_NORM |
-                    PULSAR_BLEND_TOPK)) != 0u ||
+                    PULSAR_BLEND_TOPK | PULSAR_ORTHO)) != 0u ||
       p->reserved != 0)
     return PULSAR_ERR_UNSUPPORTED;
   return PULSAR_OK;
@@ -124,6 +124,10 @@ int make_scenes(const pulsar_scene_t* scenes, int B, const pulsar_params_t* p,
     SceneDev d;
     std::memset(&d, 0, sizeof(d));
     d.cam = make_cam(&sc.camera);
+    if ((p->flags & PULSAR_ORTHO) != 0u) {
+      d.cam.ortho = 1;
+      d.cam.f = 1.f;  // the kernels' ray direction (0, 0, f) is then the unit +z
+    }
     d.bc = make_blend(&sc.camera, p);
     d.sph_off = uint32_t(sph);
     d.n = uint32_t(sc.n);
@@ -247,6 +251,7 @@ CamDev make_cam(const pulsar_camera_t* c) {
   d.dinv_pitch = double(c->width) / double(c->sensor_width);
   d.dsh = double(c->sensor_width) * double(c->height) / double(c->width);
   d.dhalf_sh = 0.5 * double(c->sensor_width) * double(c->height) / double(c->width);
+  d.ortho = 0;
   return d;
 }
 
@@ -412,6 +417,8 @@ int pulsar_bwd_camera_batched(const pulsar_scene_t* scenes, int32_t B, const flo
                               float* grad_payload, float* grad_background, float* grad_camera,
                               void* ws, size_t ws_bytes, void* stream) {
   if (!grad_camera) return PULSAR_ERR_INVALID_ARGUMENT;
+  // the focal and sensor-width terms follow the pinhole rays
+  if (params && (params->flags & PULSAR_ORTHO) != 0u) return PULSAR_ERR_UNSUPPORTED;
   return bwd_impl(scenes, B, pos, radius, opacity, payload, C, background, params, image, aux,
                   grad_image, grad_pos, grad_radius, grad_opacity, grad_payload, grad_background,
                   grad_camera, ws, ws_bytes, stream);

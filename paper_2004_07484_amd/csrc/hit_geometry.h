@@ -44,8 +44,10 @@ __device__ __forceinline__ PixelRay make_ray(const CamDev& cam, int px, int py) 
   PixelRay r;
   r.px = px;
   r.py = py;
-  r.xs = (float(px) + 0.5f) * cam.pitch - 0.5f * cam.s;
-  r.ys = (float(py) + 0.5f) * cam.pitch - 0.5f * cam.sh;
+  // the orthographic ray leaves its pixel centre along +z: in the
+  // sphere's pixel-space record the offset is already taken into account
+  r.xs = cam.ortho ? 0.f : (float(px) + 0.5f) * cam.pitch - 0.5f * cam.s;
+  r.ys = cam.ortho ? 0.f : (float(py) + 0.5f) * cam.pitch - 0.5f * cam.sh;
   const float v2 = r.xs * r.xs + r.ys * r.ys + cam.f * cam.f;
   r.inv_v2 = 1.f / v2;
   const float inv_len = 1.f / sqrtf(v2);
@@ -53,8 +55,8 @@ __device__ __forceinline__ PixelRay make_ray(const CamDev& cam, int px, int py) 
   r.uy = r.ys * inv_len;
   r.uz = cam.f * inv_len;
   const double pitch = cam.dpitch;
-  const double xs = (double(px) + 0.5) * pitch - 0.5 * double(cam.s);
-  const double ys = (double(py) + 0.5) * pitch - cam.dhalf_sh;
+  const double xs = cam.ortho ? 0.0 : (double(px) + 0.5) * pitch - 0.5 * double(cam.s);
+  const double ys = cam.ortho ? 0.0 : (double(py) + 0.5) * pitch - cam.dhalf_sh;
   r.inv_v2_d = 1.0 / (xs * xs + ys * ys + double(cam.f) * double(cam.f));
   return r;
 }

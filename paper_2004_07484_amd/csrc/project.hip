@@ -129,23 +129,31 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
     const double pitch = cam.dpitch;
     const double inv_pitch = cam.dinv_pitch;
     const double sh = cam.dsh;
+    const bool ortho = cam.ortho != 0;
     double R = r;
     if (min_radius_px > 0.f) {
-      const double rmin = double(min_radius_px) * pitch * cz / f;
+      // the minimum size in pixels: at depth c_z (pinhole) or at any depth
+      const double rmin = ortho ? double(min_radius_px) * pitch
+                                : double(min_radius_px) * pitch * cz / f;
       if (rmin > R) R = rmin;
     }
     ok = ok && (cz - R >= double(cam.znear));
-    const double tmin = sqrt(cx * cx + cy * cy + cz * cz) - R;
+    // the nearest point any ray can reach
+    const double tmin = ortho ? cz - R : sqrt(cx * cx + cy * cy + cz * cz) - R;
     ok = ok && (tmin <= double(cam.zfar));
     if (ok) {
       // The cone of rays through the sphere lies between the two planes through
       // the camera centre tangent to it; on the plane z = f they bound
       // x in f (c_x c_z -+ R sqrt(c_x^2 + c_z^2 - R^2)) / (c_z^2 - R^2), same for y.
+      // (orthographic: the sphere's shadow on the sensor is the disk of
+      // radius R around (c_x, c_y))
       const double fden = f / (cz * cz - R * R);
       const double sx = R * sqrt(cx * cx + cz * cz - R * R);
       const double sy = R * sqrt(cy * cy + cz * cz - R * R);
-      const double xlo = (cx * cz - sx) * fden, xhi = (cx * cz + sx) * fden;
-      const double ylo = (cy * cz - sy) * fden, yhi = (cy * cz + sy) * fden;
+      const double xlo = ortho ? cx - R : (cx * cz - sx) * fden;
+      const double xhi = ortho ? cx + R : (cx * cz + sx) * fden;
+      const double ylo = ortho ? cy - R : (cy * cz - sy) * fden;
+      const double yhi = ortho ? cy + R : (cy * cz + sy) * fden;
       // pixel j has its centre at sensor x (j + 1/2) pitch - s/2; widen by a
       // small margin so rounding never drops a pixel the exact cone covers
       const double margin = 1e-3;
@@ -162,11 +170,15 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
         const int tx0 = j0 / kTileW, tx1 = j1 / kTileW, ty0 = i0 / kTileH, ty1 = i1 / kTileH;
         count = uint32_t(tx1 - tx0 + 1) * uint32_t(ty1 - ty0 + 1);
         trect[i] = make_ushort4(uint16_t(tx0), uint16_t(ty0), uint16_t(tx1), uint16_t(ty1));
+        // the centre's pixel position and the pixel-space scale of the hit
+        // test: q^2 / R^2 = kap (D_x^2 + D_y^2 + cross^2) / |v|^2 with the
+        // pinhole ray direction v; orthographic rays have v = e_z and no
+        // cross term, so q^2 / R^2 = (pitch / R)^2 (D_x^2 + D_y^2)
         const double inv_cz = 1.0 / cz;
-        const double ax = cx * inv_cz, ay = cy * inv_cz;
-        const double Xc = (f * ax + 0.5 * double(cam.s)) * inv_pitch - 0.5;
-        const double Yc = (f * ay + 0.5 * sh) * inv_pitch - 0.5;
-        const double kr = cz * pitch / R;
+        const double ax = ortho ? 0.0 : cx * inv_cz, ay = ortho ? 0.0 : cy * inv_cz;
+        const double Xc = ((ortho ? cx : f * ax) + 0.5 * double(cam.s)) * inv_pitch - 0.5;
+        const double Yc = ((ortho ? cy : f * ay) + 0.5 * sh) * inv_pitch - 0.5;
+        const double kr = (ortho ? 1.0 : cz) * pitch / R;
         const double X = Xc - j0, Y = Yc - i0, kap = kr * kr;
         const float Xh = float(X), Yh = float(Y), kh = float(kap), axh = float(ax),
                     ayh = float(ay);

@@ -57,6 +57,10 @@ struct CamDev {
   double dinv_pitch;  // W / s
   double dsh;         // s H / W
   double dhalf_sh;    // 0.5 s H / W
+  // orthographic projection: rays along +z from the pixel centres on the
+  // sensor plane; f is then 1, so the pinhole expressions of the kernels
+  // (ray direction (x_s, y_s, f) with x_s = y_s = 0) give those rays
+  int ortho;
 };
 
 // Blend constants of Eq. 1 in base-2 exponent units.

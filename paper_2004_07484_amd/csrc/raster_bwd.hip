@@ -478,16 +478,19 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
         const double cz = double(cam.R[6]) * px + double(cam.R[7]) * py +
                           double(cam.R[8]) * pz + double(cam.t[2]);
         const double pitch = double(cam.s) / double(cam.W);
-        const double k = double(min_radius_px) * pitch / double(cam.f);
-        clamped = min_radius_px > 0.f && k * cz > double(radius[i]);
-        if (clamped) {
+        // orthographic: the minimum radius min_radius_px pitch is constant
+        const double k = cam.ortho ? 0.0 : double(min_radius_px) * pitch / double(cam.f);
+        const double rmin = cam.ortho ? double(min_radius_px) * pitch : k * cz;
+        clamped = min_radius_px > 0.f && rmin > double(radius[i]);
+        if (clamped && !cam.ortho) {
           gz += float(double(gR) * k);  // R = k c_z depends on depth only
           // and on the camera through k = min_radius_px / (W kappa):
           // dR/dkappa = -R / kappa
           gk -= float(double(gR) * k * cz * double(cam.s) / double(cam.f));
         }
-        const double reff = clamped ? k * cz : double(radius[i]);
-        gated = paper_norm && !(reff * double(cam.f) / (cz * pitch) > 3.0);
+        const double reff = clamped ? rmin : double(radius[i]);
+        const double rpx = cam.ortho ? reff / pitch : reff * double(cam.f) / (cz * pitch);
+        gated = paper_norm && !(rpx > 3.0);
       }
       if (camg) camg[i] = make_float4(gx, gy, gz, gk);
       if (grad_radius) grad_radius[i] = (clamped || gated) ? 0.f : gR * scale;

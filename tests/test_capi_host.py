@@ -113,7 +113,7 @@ def test_bad_params_are_rejected(par_kw, code):
 
 
 def test_reserved_flags_are_unsupported():
-    for bit in [0x10, 0x20, 0x80000000]:
+    for bit in [0x20, 0x40, 0x80000000]:
         p = _capi.make_params(flags=bit | _capi.PULSAR_REBIN)
         assert _call_fwd(_cam(), p) == _capi.PULSAR_ERR_UNSUPPORTED
 
@@ -121,7 +121,7 @@ def test_reserved_flags_are_unsupported():
 def test_known_flags_pass_validation():
     # validation accepts them and stops at the next check, the workspace size
     for flags in [_capi.PULSAR_NO_BWD_AUX, _capi.PULSAR_REBIN, _capi.PULSAR_GRAD_PAPER_NORM,
-                  _capi.PULSAR_BLEND_TOPK,
+                  _capi.PULSAR_BLEND_TOPK, _capi.PULSAR_ORTHO,
                   _capi.PULSAR_NO_BWD_AUX | _capi.PULSAR_REBIN | _capi.PULSAR_GRAD_PAPER_NORM]:
         p = _capi.make_params(flags=flags)
         assert _call_fwd(_cam(), p, ws_bytes=1024) == _capi.PULSAR_ERR_WORKSPACE

@@ -378,3 +378,41 @@ def test_topk_blend(case):
     assert np.abs(full["F"][deep] - fwd["F"][deep]).max() > 1e-5  # the variant matters
     g = ref.backward(sc, cam, par, Gm, fwd)
     compare_grads(out, g, f"top-K {case}")
+
+
+@pytest.mark.parametrize("case", ["spheres1k", "rotated", "min_radius", "dense_split_tiles"])
+def test_orthographic_projection(case):
+    """PULSAR_ORTHO against the oracle's orthographic rays: image,
+    log-normaliser and every scene gradient."""
+    import copy as _copy
+    wl = sg.config1()
+    sc, par = wl.scene, wl.params
+    cam = _copy.deepcopy(wl.camera)
+    cam.orthographic = True
+    chunk = 0
+    if case == "rotated":
+        rng = np.random.default_rng(12)
+        q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+        q = q * np.sign(np.diag(r))
+        if np.linalg.det(q) < 0:
+            q[:, 0] = -q[:, 0]
+        tq = rng.uniform(-1, 1, 3)
+        sc.pos = ((sc.pos.astype(np.float64) - tq) @ q).astype(np.float32)
+        cam.R, cam.t = q.astype(np.float32), tq.astype(np.float32)
+    if case == "min_radius":
+        par = sg.Params(gamma=0.1, eps=1e-5, min_radius_px=1.5, K=5)
+    if case == "dense_split_tiles":
+        sc.radius = (sc.radius * 6.0).astype(np.float32)
+        chunk = 64
+    _say(f"[parity] orthographic, {case}")
+    fwd = ref.forward(sc, cam, par)
+    assert fwd["nhits"].max() > 1
+    G = sg.upstream_grad(900, cam.height, cam.width, sc.C)
+    Gm = masked_G(G, None, fwd["ambiguous"])
+    flags = _capi.PULSAR_ORTHO
+    out = gpu_render(sc, cam, par, Gm, chunk=chunk, fwd_flags=flags, bwd_flags=flags)
+    assert out["status"] == _capi.PULSAR_OK
+    assert_close(out["F"], fwd["F"], IMAGE_REL, f"orthographic image {case}")
+    assert_close(out["L"], fwd["L"], IMAGE_REL, f"orthographic log-normaliser {case}")
+    g = ref.backward(sc, cam, par, Gm, fwd)
+    compare_grads(out, g, f"orthographic {case}")
