@@ -273,7 +273,14 @@ class Renderer(torch.nn.Module):
     def forward(self, pos, payload, radius, cam, opacity: Optional[torch.Tensor] = None,
                 gamma: float = 0.1, max_depth: float = 10.0, min_depth: float = 1.0,
                 bg: Optional[torch.Tensor] = None, eps: float = 1e-5,
-                min_radius_px: float = 0.0, return_aux: bool = False):
+                min_radius_px: float = 0.0, return_aux: bool = False,
+                orthographic: bool = False, blend_topk: bool = False,
+                paper_gradients: bool = False):
+        """orthographic: parallel rays along +z (PULSAR_ORTHO; no camera
+        gradient). blend_topk: only each pixel's K nearest hits blend
+        (PULSAR_BLEND_TOPK). paper_gradients: the paper's gradients for
+        optimisation, averaged over each sphere's pixels with the 3-pixel
+        position gate (PULSAR_GRAD_PAPER_NORM)."""
         if pos.shape[0] > self.max_num_spheres:
             raise ValueError("more spheres than the renderer was built for")
         C = payload.shape[1]
@@ -294,7 +301,12 @@ class Renderer(torch.nn.Module):
                                    self.height)
         else:
             cs = camera_struct(cam, self.width, self.height, min_depth, max_depth)
-        params = _capi.make_params(gamma, eps, min_radius_px, self.K, self.max_pairs)
+        flags = ((_capi.PULSAR_ORTHO if orthographic else 0) |
+                 (_capi.PULSAR_BLEND_TOPK if blend_topk else 0) |
+                 (_capi.PULSAR_GRAD_PAPER_NORM if paper_gradients else 0))
+        if orthographic and torch.is_tensor(cam) and cam.requires_grad:
+            raise ValueError("camera gradients are not available for the orthographic projection")
+        params = _capi.make_params(gamma, eps, min_radius_px, self.K, self.max_pairs, flags=flags)
         if self.autotune:
             params = self._tuned(params, pos.detach().contiguous(), radius.detach().contiguous(),
                                  None if opacity is None else opacity.detach().contiguous(),

@@ -122,3 +122,34 @@ def test_listing1_example_renders_like_the_oracle():
     got = img.detach().cpu().numpy()
     assert_close(got[rows], fwd["F"][rows], IMAGE_REL, "Lst. 1 image")
     assert (fwd["nhits"][rows] > 0).sum() > 100
+
+
+@pytest.mark.parametrize("opts", [dict(orthographic=True), dict(blend_topk=True),
+                                  dict(paper_gradients=True),
+                                  dict(orthographic=True, blend_topk=True,
+                                       paper_gradients=True)])
+def test_renderer_options_match_c_abi(opts):
+    """Renderer(orthographic=, blend_topk=, paper_gradients=) gives bitwise
+    the image and gradients of the C ABI called with the matching flags."""
+    import torch
+    from paper_2004_07484_amd import _capi
+    from paper_2004_07484_amd.renderer import Renderer
+    from tests.gpu_helpers import to_dev
+    wl = sg.config1()
+    sc, cam, par = wl.scene, wl.camera, wl.params
+    sc.radius = (sc.radius * 3.0).astype(np.float32)
+    flags = ((_capi.PULSAR_ORTHO if opts.get("orthographic") else 0) |
+             (_capi.PULSAR_BLEND_TOPK if opts.get("blend_topk") else 0))
+    bflags = flags | (_capi.PULSAR_GRAD_PAPER_NORM if opts.get("paper_gradients") else 0)
+    G = sg.upstream_grad(2100, cam.height, cam.width, sc.C)
+    direct = gpu_render(sc, cam, par, G, fwd_flags=flags, bwd_flags=bflags)
+    r = Renderer(cam.width, cam.height, sc.n, n_channels=sc.C, K=par.K)
+    leaves = [to_dev(a).requires_grad_(True) for a in (sc.pos, sc.payload, sc.radius,
+                                                        sc.opacity, sc.bg)]
+    img = r(leaves[0], leaves[1], leaves[2], cam, opacity=leaves[3], gamma=par.gamma,
+            max_depth=cam.zfar, min_depth=cam.znear, bg=leaves[4], eps=par.eps, **opts)
+    img.backward(to_dev(G))
+    assert np.array_equal(img.detach().cpu().numpy(), direct["F"])
+    for leaf, key in zip(leaves, ["grad_pos", "grad_payload", "grad_radius", "grad_opacity",
+                                  "grad_bg"]):
+        assert np.array_equal(leaf.grad.cpu().numpy(), direct[key]), key
