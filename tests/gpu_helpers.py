@@ -114,14 +114,14 @@ def compare_grads(gpu, ref, what=""):
 
 
 def gpu_render_batch(workloads, params, Gs=None, depth_bits=0, chunk=0, raster_blocks=0,
-                     bgs=None, stream=None):
+                     bgs=None, stream=None, flags=0):
     """One batched forward (and backward when Gs is given) over several
     workloads sharing C and params; returns one result dict per scene."""
     import torch
     B = len(workloads)
     C = workloads[0].scene.payload.shape[1]
     ps = _capi.make_params(params.gamma, params.eps, params.min_radius_px, params.K, 0,
-                           depth_bits, chunk, raster_blocks)
+                           depth_bits, chunk, raster_blocks, flags)
     scenes = _capi.make_scenes([cam_struct(w.camera) for w in workloads],
                                [w.scene.n for w in workloads])
     cat = lambda xs, shape: np.concatenate([np.asarray(x, np.float32).reshape(shape) for x in xs])

@@ -217,3 +217,30 @@ def test_tuning_knobs_keep_results(knob):
     rel = 1e-4 if "raster_blocks" in knob else GRAD_REL
     for key in ["grad_pos", "grad_radius", "grad_opacity", "grad_payload", "grad_bg"]:
         assert_close(got[key], base[key], rel, key, floor=1e-2)
+
+
+@pytest.mark.parametrize("flags", [_capi.PULSAR_ORTHO, _capi.PULSAR_BLEND_TOPK,
+                                   _capi.PULSAR_ORTHO | _capi.PULSAR_BLEND_TOPK])
+def test_batched_variants_match_oracle(flags):
+    """The orthographic projection and the top-K blend in a batched call of
+    small scenes, against the oracle per scene."""
+    import copy
+    ortho = bool(flags & _capi.PULSAR_ORTHO)
+    topk = bool(flags & _capi.PULSAR_BLEND_TOPK)
+    wls = [copy.deepcopy(w) for w in _small_batch()]
+    Gs, fwds = [], []
+    for b, wl in enumerate(wls):
+        wl.camera.orthographic = ortho
+        fwd = ref.forward(wl.scene, wl.camera, PARAMS, blend_topk=topk)
+        G = sg.upstream_grad(950 + b, wl.camera.height, wl.camera.width, 3)
+        Gs.append(masked_G(G, None, fwd["ambiguous"]))
+        fwds.append(fwd)
+    _say(f"[batched] {len(wls)} small scenes, flags {flags}")
+    outs = gpu_render_batch(wls, PARAMS, Gs, flags=flags)
+    for b, (wl, fwd, G, out) in enumerate(zip(wls, fwds, Gs, outs)):
+        assert out["status"] == _capi.PULSAR_OK
+        ok = ~fwd["ambiguous"]
+        assert_close(out["F"][ok], fwd["F"][ok], IMAGE_REL, f"scene {b} image")
+        assert_close(out["L"][ok], fwd["L"][ok], IMAGE_REL, f"scene {b} log-normaliser")
+        g = ref.backward(wl.scene, wl.camera, PARAMS, G, fwd)
+        compare_grads(out, g, f"scene {b}")
