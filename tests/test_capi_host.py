@@ -283,3 +283,19 @@ def test_batched_backward_argument_checks():
     small = list(args)
     small[18] = 4096
     assert lib.pulsar_bwd_batched(*small) == _capi.PULSAR_ERR_WORKSPACE
+
+
+def test_flag_constants_mirror_the_header():
+    """Every PULSAR_* flag and preset the header defines has the same value
+    in the Python binding."""
+    text = open(HEADER).read()
+    defs = dict(re.findall(r"^#define (PULSAR_[A-Z0-9_]+) (0x[0-9a-fA-F]+)u$", text, re.M))
+    assert {"PULSAR_NO_BWD_AUX", "PULSAR_REBIN", "PULSAR_GRAD_PAPER_NORM", "PULSAR_BLEND_TOPK",
+            "PULSAR_ORTHO"} <= set(defs)
+    for name, val in defs.items():
+        assert getattr(_capi, name) == int(val, 16), name
+    vals = [int(v, 16) for v in defs.values()]
+    assert all(v & (v - 1) == 0 for v in vals) and len(set(vals)) == len(vals)  # distinct bits
+    preset = re.search(r"^#define PULSAR_MIN_RADIUS_PX_PAPER ([0-9.]+)f$", text, re.M)
+    assert preset and abs(float(preset.group(1)) - _capi.PULSAR_MIN_RADIUS_PX_PAPER) < 1e-8
+    assert abs(_capi.PULSAR_MIN_RADIUS_PX_PAPER - 0.5 * 2 ** 0.5) < 1e-8
