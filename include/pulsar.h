@@ -181,7 +181,10 @@ int pulsar_fwd(const float* pos, const float* radius, const float* opacity,
  * Scene, camera, params, image and aux must be exactly those of the preceding
  * pulsar_fwd on the same workspace, with no other call on that workspace in
  * between, unless params.flags has PULSAR_REBIN (then only image and aux must
- * come from a forward of the same inputs). The per-pixel hits are recomputed
+ * come from a forward of the same inputs). The flags that act on the
+ * backward alone (PULSAR_REBIN, PULSAR_GRAD_PAPER_NORM) may differ from the
+ * forward's, and PULSAR_NO_BWD_AUX and PULSAR_BLEND_TOPK are ignored here;
+ * PULSAR_ORTHO must match. The per-pixel hits are recomputed
  * from the sorted tile lists; nothing per pixel beyond image and aux is
  * stored. PULSAR_NO_BWD_AUX without PULSAR_REBIN, or aux NULL, is
  * PULSAR_ERR_INVALID_ARGUMENT. */
