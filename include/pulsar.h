@@ -183,8 +183,8 @@ int pulsar_fwd(const float* pos, const float* radius, const float* opacity,
  * between, unless params.flags has PULSAR_REBIN (then only image and aux must
  * come from a forward of the same inputs). The flags that act on the
  * backward alone (PULSAR_REBIN, PULSAR_GRAD_PAPER_NORM) may differ from the
- * forward's, and PULSAR_NO_BWD_AUX and PULSAR_BLEND_TOPK are ignored here;
- * PULSAR_ORTHO must match. The per-pixel hits are recomputed
+ * forward's, PULSAR_BLEND_TOPK is ignored here (image and aux carry it),
+ * PULSAR_NO_BWD_AUX needs PULSAR_REBIN (below) and PULSAR_ORTHO must match. The per-pixel hits are recomputed
  * from the sorted tile lists; nothing per pixel beyond image and aux is
  * stored. PULSAR_NO_BWD_AUX without PULSAR_REBIN, or aux NULL, is
  * PULSAR_ERR_INVALID_ARGUMENT. */
