@@ -169,9 +169,13 @@ def paper_normalised(scene, cam, params, fwd: dict, grads: dict,
     cz = pos @ R[2] + float(np.asarray(cam.t, np.float64)[2])
     pitch = float(cam.sensor_width) / float(cam.width)
     r = np.asarray(scene.radius, np.float64)
-    reff = np.maximum(r, float(params.min_radius_px) * pitch * cz / float(cam.focal)) \
-        if params.min_radius_px > 0 else r
-    gated = ~(reff * float(cam.focal) / (cz * pitch) > 3.0)
+    ortho = bool(getattr(cam, "orthographic", False))
+    # projected radius in pixels: R f / (c_z pitch), or R / pitch for the
+    # orthographic projection (where the minimum size is min_radius_px pixels)
+    rmin = float(params.min_radius_px) * pitch * (1.0 if ortho else cz / float(cam.focal))
+    reff = np.maximum(r, rmin) if params.min_radius_px > 0 else r
+    rpx = reff / pitch if ortho else reff * float(cam.focal) / (cz * pitch)
+    gated = ~(rpx > 3.0)
     scale = np.where(count > 0, 1.0 / np.maximum(count, 1.0), 1.0)
     out = dict(grads)
     out["grad_pos"] = grads["grad_pos"] * (scale * ~gated)[:, None]
@@ -180,7 +184,7 @@ def paper_normalised(scene, cam, params, fwd: dict, grads: dict,
         out["grad_opacity"] = grads["grad_opacity"] * scale
     out["grad_payload"] = grads["grad_payload"] * scale[:, None]
     out["pixel_count"] = count
-    out["projected_radius_px"] = reff * float(cam.focal) / (cz * pitch)
+    out["projected_radius_px"] = rpx
     return out
 
 

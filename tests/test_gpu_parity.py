@@ -284,7 +284,7 @@ def test_only_requested_gradients_are_written():
     assert_close(part["grad_bg"], full["grad_bg"], 1e-5, "bg")
 
 
-@pytest.mark.parametrize("case", ["plain", "rotated", "min_radius", "dense_K3"])
+@pytest.mark.parametrize("case", ["plain", "rotated", "min_radius", "dense_K3", "ortho"])
 def test_paper_normalised_gradients(case):
     """PULSAR_GRAD_PAPER_NORM: gradients averaged over each sphere's pixel
     count and the 3-pixel position gate, against the oracle's definition.
@@ -307,6 +307,13 @@ def test_paper_normalised_gradients(case):
     if case == "dense_K3":
         sc.radius = (sc.radius * 1.25).astype(np.float32)
         par = sg.Params(gamma=0.1, eps=1e-5, K=3)
+    flags = 0
+    if case == "ortho":
+        # orthographic spheres look larger: the unscaled radii (x4 / 4 is exact)
+        sc.radius = (sc.radius / 4.0).astype(np.float32)
+        cam.orthographic = True
+        par = sg.Params(gamma=0.1, eps=1e-5, min_radius_px=0.7071, K=5)
+        flags = _capi.PULSAR_ORTHO
     _say(f"[parity] paper-normalised gradients, {case}")
     fwd = ref.forward(sc, cam, par)
     assert not fwd["ambiguous"].any()
@@ -315,7 +322,8 @@ def test_paper_normalised_gradients(case):
     pr = g["projected_radius_px"]
     assert (pr <= 3.0).any() and (pr > 3.0).any()
     assert np.all(np.abs(pr - 3.0) > 1e-4)  # gate decisions are not rounding-sensitive
-    out = gpu_render(sc, cam, par, G, bwd_flags=_capi.PULSAR_GRAD_PAPER_NORM)
+    out = gpu_render(sc, cam, par, G, fwd_flags=flags,
+                     bwd_flags=flags | _capi.PULSAR_GRAD_PAPER_NORM)
     assert out["status"] == _capi.PULSAR_OK
     compare_grads(out, g, f"paper-normalised {case}")
 
