@@ -113,11 +113,11 @@ __device__ __forceinline__ float hit_grad_kappa(const PixelRay& ray, const Spher
 // inside the pixel loop and no barrier inside the record loop. CM >= C.
 constexpr int kBwdWaves = 4;
 
-// Up to 8 channels the item kernel is held to 128 VGPRs (4 blocks of 4 waves
-// per CU) and then spills nothing; held to 96 (5 blocks) it spilled inside
-// the record loop and measured 3 us slower. Wider instances keep the
-// compiler's budget.
-constexpr int bwd_waves_per_simd(int CM) { return CM <= 8 ? 4 : 1; }
+// Up to 4 channels the item kernel fits 96 VGPRs without spilling, so 5
+// blocks of 4 waves share a CU; with 8 it is held to 128 VGPRs (4 blocks):
+// at 96 it spilled inside the record loop and measured 3 us slower. Wider
+// instances keep the compiler's budget.
+constexpr int bwd_waves_per_simd(int CM) { return CM <= 4 ? 5 : (CM <= 8 ? 4 : 1); }
 
 template <int CM, bool CAM>
 __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_bwd_items(
