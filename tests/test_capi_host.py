@@ -168,6 +168,12 @@ def test_backward_argument_checks():
     assert lib.pulsar_bwd_camera(*cam_small) == _capi.PULSAR_ERR_WORKSPACE
     cam_bad_aux = bad_aux[:17] + [FAKE] + bad_aux[17:]
     assert lib.pulsar_bwd_camera(*cam_bad_aux) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    # no focal / sensor-width terms for parallel rays
+    ortho = _capi.make_params(flags=_capi.PULSAR_ORTHO)
+    cam_ortho = list(cam_args)
+    cam_ortho[8] = ctypes.byref(ortho)
+    cam_ortho[17] = FAKE
+    assert lib.pulsar_bwd_camera(*cam_ortho) == _capi.PULSAR_ERR_UNSUPPORTED
     rebin = _capi.make_params(flags=_capi.PULSAR_NO_BWD_AUX | _capi.PULSAR_REBIN)
     args_rb = list(small)
     args_rb[8] = ctypes.byref(rebin)
