@@ -72,9 +72,12 @@ def measured_traffic(kernel: str, workload: str):
     return int(rec["bytes"]) if sources_hash(kernel) == rec.get("sources_sha256_16") else None
 
 
-def cpu_baseline(wl, G, rows_n: int) -> dict:
+def cpu_baseline(wl, G, rows_n: int):
     """FP64 brute-force oracle on a seeded row subset of the same workload,
-    extrapolated linearly to the full frame."""
+    extrapolated linearly to the full frame. Also returns what the parity
+    check needs: the rows, the oracle's forward and gradients, and the
+    upstream gradient they were taken for (G on those rows, zero elsewhere
+    and on pixels whose K nearest hits are rounding-sensitive)."""
     from oracle import reference as ref
     H = wl.camera.height
     rows = sorted(np.random.default_rng(12345).choice(H, rows_n, replace=False).tolist())
@@ -87,15 +90,79 @@ def cpu_baseline(wl, G, rows_n: int) -> dict:
     t0 = time.perf_counter()
     fwd = ref.forward(wl.scene, wl.camera, wl.params, rows=rows, n_threads=threads)
     t1 = time.perf_counter()
-    ref.backward(wl.scene, wl.camera, wl.params, G, fwd, rows=rows)
+    Gm = np.zeros_like(G)
+    Gm[rows] = G[rows]
+    Gm[fwd["ambiguous"]] = 0.0
+    grads = ref.backward(wl.scene, wl.camera, wl.params, Gm, fwd, rows=rows)
     t2 = time.perf_counter()
     scale = H / rows_n
     total_ms = (t2 - t0) * 1e3 * scale
-    return {"value": round(total_ms, 1), "unit": "ms/frame (extrapolated)", "cores": threads,
+    base = {"value": round(total_ms, 1), "unit": "ms/frame (extrapolated)", "cores": threads,
             "kind": "oracle",
             "sample": f"{rows_n} of {H} seeded rows of the same workload (fwd {t1 - t0:.1f} s, "
                       f"bwd {t2 - t1:.1f} s), scaled by {scale:.0f}",
-            "fwd_ms": round((t1 - t0) * 1e3 * scale, 1), "bwd_ms": round((t2 - t1) * 1e3 * scale, 1)}
+            "fwd_ms": round((t1 - t0) * 1e3 * scale, 1),
+            "bwd_ms": round((t2 - t1) * 1e3 * scale, 1)}
+    return base, dict(rows=rows, fwd=fwd, grads=grads, G=Gm)
+
+
+def max_rel(got, want, floor=1e-2) -> float:
+    """Largest |got - want| / max(|want|, floor max|want|) (the parity scale)."""
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    if want.size == 0:
+        return 0.0
+    scale = np.maximum(np.abs(want), floor * np.abs(want).max())
+    return float((np.abs(got - want) / np.maximum(scale, 1e-300)).max())
+
+
+STAGE_KERNELS = {"project": "k_project", "binning": "binning (several kernels)",
+                 "raster_fwd": "k_fwd_chunks", "merge": "k_fwd_merge",
+                 "raster_bwd": "k_bwd_items", "finalize": "k_finalize"}
+
+
+def stage_bytes(n: int, H: int, W: int, C: int, pairs: int) -> dict:
+    """Algorithmic bytes each stage must move whatever the implementation:
+    the compulsory I/O of the frame that falls to it, and for binning the tile
+    lists it must produce.
+      project     read pos, radius, opacity: n (12 + 4 + 4)
+      binning     write the tile lists: one sphere index per (tile, sphere)
+                  pair (4 B) and the tile ranges (4 B per tile)
+      raster_fwd  read the payload rows, write F and L: n 4C + HW (4C + 4)
+                  (split tiles' pixels are written by the merge, counted here)
+      merge       none beyond the forward's (intermediate partial blends)
+      raster_bwd  read G, F and L and the payload rows: HW (8C + 4) + n 4C
+      finalize    write every sphere gradient: n 4 (C + 5), and the background
+                  gradient 4C"""
+    T = ((W + 7) // 8) * ((H + 7) // 8)
+    return {"project": 20 * n, "binning": 4 * pairs + 4 * (T + 1),
+            "raster_fwd": 4 * C * n + H * W * (4 * C + 4), "merge": 0,
+            "raster_bwd": H * W * (8 * C + 4) + 4 * C * n,
+            "finalize": 4 * (C + 5) * n + 4 * C}
+
+
+def stage_roofline(stage_avg: dict, n, H, W, C, pairs, workload):
+    """roofline object for the stage that takes longest (its algorithmic bytes
+    over its average duration against the HBM peak), and the same figures
+    for every stage."""
+    sb = stage_bytes(n, H, W, C, pairs)
+    kernels = {}
+    for st, nbytes in sb.items():
+        ms = stage_avg.get(st, 0.0)
+        kernels[st] = {"kernel": STAGE_KERNELS[st], "avg_ms": round(ms, 4),
+                       "bytes_per_launch": nbytes,
+                       "achieved_GBs": round(nbytes / (ms * 1e-3) / 1e9, 1) if ms > 0 else None,
+                       "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                       if ms > 0 else None}
+    dom = max(sb, key=lambda k: stage_avg.get(k, 0.0))
+    ms = stage_avg[dom]
+    achieved = sb[dom] / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    kname = STAGE_KERNELS[dom]
+    roofline = {"kernel": kname, "stage": dom, "bound": "hbm", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(kname, workload), "avg_ms": round(ms, 4),
+                "bytes_per_launch": sb[dom]}
+    return roofline, kernels
 
 
 def bench_batch(args, dev) -> dict:
@@ -416,38 +483,7 @@ def main() -> int:
 
     fwd_b, bwd_b = io_bytes(n, H, W, C)
     stage_avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
-    # Algorithmic bytes per launch: each kernel's share of the frame's
-    # compulsory I/O, for the three stages that time a
-    # single kernel:
-    #   raster_bwd (k_bwd_items, with the background-gradient block sums in
-    #     its tail): read G, F and L, read the payload, write dL/df, dL/do and
-    #     the camera-space position/radius sums
-    #   raster_fwd (k_fwd_chunks, with the empty-tile fill in its tail): read
-    #     the payload, write F and L (split tiles' pixels are written by the
-    #     merge, timed as its own stage)
-    #   project (k_project): read pos, radius, opacity
-    # The dominant kernel is the one of these with the longest time.
-    per_stage_bytes = {
-        "raster_bwd": H * W * (8 * C + 4) + n * 4 * C + n * 4 * (C + 5),
-        "raster_fwd": n * 4 * C + H * W * (4 * C + 4),
-        "project": n * 20,
-    }
-    kernel_of = {"raster_bwd": "k_bwd_items", "raster_fwd": "k_fwd_chunks",
-                 "project": "k_project"}
-    dominant = max(per_stage_bytes, key=lambda k: stage_avg.get(k, 0.0))
-    dom_ms = stage_avg[dominant]
-    achieved = per_stage_bytes[dominant] / (dom_ms * 1e-3) / 1e9 if dom_ms > 0 else 0.0
-    kernel_name = kernel_of[dominant]
-    traffic = measured_traffic(kernel_name, wl.name)
-    roofline = {"kernel": kernel_name, "bound": "hbm", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "avg_ms": round(dom_ms, 4),
-                "bytes_per_launch": per_stage_bytes[dominant]}
-    kernels = {kernel_of[k]: {"avg_ms": round(stage_avg.get(k, 0.0), 4),
-                              "bytes_per_launch": v,
-                              "achieved_GBs": round(v / (stage_avg[k] * 1e-3) / 1e9, 1)
-                              if stage_avg.get(k, 0.0) > 0 else None}
-               for k, v in per_stage_bytes.items()}
+    roofline, kernels = stage_roofline(stage_avg, n, H, W, C, int(pairs), wl.name)
     io_frac = (fwd_b + bwd_b) / (step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
 
     # the backward with camera gradients against the plain one, each timed
@@ -524,10 +560,37 @@ def main() -> int:
         batch = bench_batch(args, dev)
 
     cpu = None
+    parity = None
     if not args.no_cpu_baseline:
         log(f"[bench] CPU oracle baseline on {args.cpu_rows} rows")
-        cpu = cpu_baseline(wl, G_np, args.cpu_rows)
+        cpu, orc = cpu_baseline(wl, G_np, args.cpu_rows)
         log(f"[bench] oracle {cpu['value']} ms/frame on {cpu['cores']} threads")
+        # parity of the timed configuration: one more fwd + bwd with the same
+        # launch knobs and workspace, G restricted to the oracle's rows
+        Gd = t(orc["G"].astype(np.float32))
+        step_g = lambda: (
+            _capi.pulsar_fwd(pos, rad, opa, pay, bg, cs, ps, image, aux, ws, stream),
+            _capi.pulsar_bwd(pos, rad, opa, pay, bg, cs, ps, image, aux, Gd, gp, gr, go, gf, gb,
+                             ws, stream))
+        step_g()
+        code, _ = _capi.pulsar_query_status(ws, stream)
+        assert code == _capi.PULSAR_OK
+        rows = orc["rows"]
+        F, L = image.cpu().numpy(), aux.cpu().numpy()
+        rel_img = max(max_rel(F[rows], orc["fwd"]["F"][rows]),
+                      max_rel(L[rows], orc["fwd"]["L"][rows]))
+        got = {"grad_pos": gp, "grad_radius": gr, "grad_opacity": go, "grad_payload": gf,
+               "grad_bg": gb}
+        rel_grad = {k: max_rel(v.cpu().numpy(), orc["grads"][k]) for k, v in got.items()}
+        parity = {"rows": len(rows), "pixels": len(rows) * W,
+                  "masked_pixels": int(orc["fwd"]["ambiguous"][rows].sum()),
+                  "max_rel_image": rel_img, "max_rel_grad": max(rel_grad.values()),
+                  "max_rel_grad_by_tensor": rel_grad, "tolerance": {"image": 1e-4, "grad": 1e-3},
+                  "knobs": {k: int(getattr(ps, k)) for k in ("raster_blocks", "chunk",
+                                                             "depth_bits")}}
+        parity["pass"] = bool(rel_img <= 1e-4 and parity["max_rel_grad"] <= 1e-3)
+        log(f"[bench] parity on {len(rows)} oracle rows: image {rel_img:.2e}, gradients "
+            f"{parity['max_rel_grad']:.2e} ({'pass' if parity['pass'] else 'FAIL'})")
 
     out = {
         "metric": "fwd+bwd ms/frame at 1M spheres 1024^2 FP32; batched vs looped frames/s",
@@ -560,6 +623,7 @@ def main() -> int:
         "camera_gradients_and_variants": camera,
         "batched": batch,
         "cpu_baseline": cpu,
+        "parity": parity,
         "paper_context": "RTX 2080, 1M spheres at 1000^2: fwd 19 ms, bwd 4.7 ms (CUDA only)",
     }
     print(json.dumps(out), flush=True)

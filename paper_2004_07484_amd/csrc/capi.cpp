@@ -204,7 +204,9 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   q.off_dtot = take(size_t(kSortRadix) * 4);
   q.off_ranges = take(size_t(q.T + 1) * 4);
   q.max_chunks = (cap + q.chunk - 1) / q.chunk + q.T;
-  q.pcap = (cap + q.chunk - 1) / q.chunk + 1024;
+  // partial blend states: a tile of L > chunk pairs needs ceil(L / chunk)
+  // < 2 L / chunk of them, so 2 cap / chunk + 1 bounds their sum
+  q.pcap = 2 * ((cap + q.chunk - 1) / q.chunk) + 1;
   q.nblk_tiles = int((q.T + 255) / 256);
   q.fwd_cm = C < kFwdChannels ? C : kFwdChannels;
   int km = 4;  // register K-list slots: a power of two >= K, at least 4

@@ -82,8 +82,10 @@ def _forward_into(pos, radius, opacity, payload, bg, cam, params, check: bool):
         code, pairs = _capi.pulsar_query_status(ws)
         if code == _capi.PULSAR_OK:
             return image, aux, ws, params
+        # never below twice the capacity that overflowed
+        want = max(pairs * 5 // 4 + 1024, 2 * int(params.max_pairs))
         grown = _capi.make_params(params.gamma, params.eps, params.min_radius_px, params.K,
-                                  int(min(2**31 - 1, pairs * 5 // 4 + 1024)), params.depth_bits,
+                                  int(min(2**31 - 1, want)), params.depth_bits,
                                   params.chunk, params.raster_blocks, params.flags)
         if grown.max_pairs <= params.max_pairs:
             raise _capi.PulsarError(code, "pulsar_fwd")

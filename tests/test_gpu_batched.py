@@ -102,31 +102,48 @@ def test_batched_equals_looped_uneven_batch():
             assert_close(out[key], one[key], 1e-4, f"scene {b} {key}", floor=1e-2)
 
 
-def test_batched_default_key_width_and_oracle_rows():
+_CFG4 = {}
+
+
+def _cfg4_oracle_rows():
+    """The 32-scene batch with oracle rows of three scenes (smallest, median,
+    largest): upstream gradients masked to those rows, computed once."""
+    if not _CFG4:
+        wls = _cfg4_batch(extra=False)
+        par = wls[0].params
+        rng = np.random.default_rng(4242)
+        order = np.argsort([w.scene.n for w in wls])
+        check = {int(order[0]): None, int(order[len(order) // 2]): None, int(order[-1]): None}
+        Gs = []
+        for b, w in enumerate(wls):
+            G = sg.upstream_grad(2000 + b, w.camera.height, w.camera.width, 3)
+            if b in check:
+                rows = sorted(rng.choice(w.camera.height, 2, replace=False).tolist())
+                fwd = ref.forward(w.scene, w.camera, par, rows=rows)
+                G = masked_G(G, rows, fwd["ambiguous"])
+                g = ref.backward(w.scene, w.camera, par, G, fwd, rows=rows)
+                check[b] = (rows, fwd, g)
+            Gs.append(G)
+        _CFG4.update(wls=wls, check=check, Gs=Gs)
+    return _CFG4
+
+
+# the default launch and the benchmark's tuned batch configuration
+@pytest.mark.parametrize("knobs", [{}, dict(chunk=512, raster_blocks=16384),
+                                   dict(chunk=64, raster_blocks=4096)])
+def test_batched_default_key_width_and_oracle_rows(knobs):
     """Default depth key width (the batch has other tile numbers, so the key
     layout differs from single calls): images agree to 1e-6, and sampled rows
-    of three scenes match the oracle."""
-    wls = _cfg4_batch(extra=False)
+    of three scenes match the oracle, in each launch configuration."""
+    c = _cfg4_oracle_rows()
+    wls, check, Gs = c["wls"], c["check"], c["Gs"]
     par = wls[0].params
-    rng = np.random.default_rng(4242)
-    order = np.argsort([w.scene.n for w in wls])
-    check = {int(order[0]): None, int(order[len(order) // 2]): None, int(order[-1]): None}
-    Gs = []
-    for b, w in enumerate(wls):
-        G = sg.upstream_grad(2000 + b, w.camera.height, w.camera.width, 3)
-        if b in check:
-            rows = sorted(rng.choice(w.camera.height, 2, replace=False).tolist())
-            fwd = ref.forward(w.scene, w.camera, par, rows=rows)
-            check[b] = (rows, fwd)
-            G = masked_G(G, rows, fwd["ambiguous"])
-        Gs.append(G)
-    _say("[batched] default key width, oracle rows of scenes " + str(sorted(check)))
-    outs = gpu_render_batch(wls, par, Gs)
-    for b, (rows, fwd) in check.items():
-        out, w = outs[b], wls[b]
+    _say(f"[batched] default key width, oracle rows of scenes {sorted(check)}, knobs {knobs}")
+    outs = gpu_render_batch(wls, par, Gs, **knobs)
+    for b, (rows, fwd, g) in check.items():
+        out = outs[b]
         assert out["status"] == _capi.PULSAR_OK
         assert_close(out["F"][rows], fwd["F"][rows], IMAGE_REL, f"scene {b} image")
-        g = ref.backward(w.scene, w.camera, par, Gs[b], fwd, rows=rows)
         compare_grads(out, g, f"scene {b}")
     for b in (0, 7, 31):
         one = gpu_render(wls[b].scene, wls[b].camera, par)

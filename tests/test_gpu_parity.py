@@ -24,20 +24,27 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _parity(wl, rows=None, G_seed=1000, what="", grads=True, max_pairs=0):
+def _parity(wl, rows=None, G_seed=1000, what="", grads=True, max_pairs=0, knobs=None,
+            oracle=None):
+    """GPU (C ABI) against the oracle on wl; `knobs` are launch knobs
+    (chunk, raster_blocks, depth_bits); `oracle` is a cached (fwd, G, grads)."""
     sc, cam, par = wl.scene, wl.camera, wl.params
+    knobs = knobs or {}
     _say(f"[parity] {what} n={sc.n} {cam.width}x{cam.height} C={sc.C} K={par.K} rows="
-         f"{None if rows is None else len(rows)}")
-    fwd = ref.forward(sc, cam, par, rows=rows)
-    G = sg.upstream_grad(wl.seed + G_seed, cam.height, cam.width, sc.C)
-    Gm = masked_G(G, rows, fwd["ambiguous"])
-    out = gpu_render(sc, cam, par, Gm if grads else None, max_pairs=max_pairs)
+         f"{None if rows is None else len(rows)} knobs={knobs}")
+    if oracle is None:
+        fwd = ref.forward(sc, cam, par, rows=rows)
+        G = sg.upstream_grad(wl.seed + G_seed, cam.height, cam.width, sc.C)
+        Gm = masked_G(G, rows, fwd["ambiguous"])
+        g = ref.backward(sc, cam, par, Gm, fwd, rows=rows) if grads else None
+    else:
+        fwd, Gm, g = oracle
+    out = gpu_render(sc, cam, par, Gm if grads else None, max_pairs=max_pairs, **knobs)
     assert out["status"] == _capi.PULSAR_OK
     sel = slice(None) if rows is None else rows
     assert_close(out["F"][sel], fwd["F"][sel], IMAGE_REL, f"{what} image")
     assert_close(out["L"][sel], fwd["L"][sel], IMAGE_REL, f"{what} log-normaliser")
     if grads:
-        g = ref.backward(sc, cam, par, Gm, fwd, rows=rows)
         compare_grads(out, g, what)
     return fwd, out
 
@@ -52,12 +59,36 @@ def test_config2_row_subset():
     _parity(wl, rows=rows, what="100k spheres 512x512")
 
 
-def test_config3_full_size_row_subset():
-    """1M spheres at 1024x1024, C=8, K=8: the benchmark workload and launch
-    configuration, checked on 6 seeded rows (G zero elsewhere)."""
-    wl = sg.config3()
-    rows = sorted(np.random.default_rng(78).choice(1024, 6, replace=False).tolist())
-    fwd, out = _parity(wl, rows=rows, what="1M blobs 1024x1024")
+_CFG3 = {}
+
+
+def _config3_oracle():
+    """1M spheres at 1024x1024 (C=8, K=8) on 6 seeded rows: the oracle's
+    forward and gradients, computed once for every launch configuration."""
+    if not _CFG3:
+        wl = sg.config3()
+        rows = sorted(np.random.default_rng(78).choice(1024, 6, replace=False).tolist())
+        fwd = ref.forward(wl.scene, wl.camera, wl.params, rows=rows)
+        G = sg.upstream_grad(wl.seed + 1000, wl.camera.height, wl.camera.width, wl.scene.C)
+        Gm = masked_G(G, rows, fwd["ambiguous"])
+        g = ref.backward(wl.scene, wl.camera, wl.params, Gm, fwd, rows=rows)
+        _CFG3.update(wl=wl, rows=rows, oracle=(fwd, Gm, g))
+    return _CFG3
+
+
+# the default launch and every configuration the autotuner can pick at this
+# workload, the benchmark's among them (knob ranges of autotune.KNOBS)
+@pytest.mark.parametrize("knobs", [
+    {}, dict(chunk=256, raster_blocks=16384, depth_bits=0),
+    dict(chunk=512, raster_blocks=16384), dict(chunk=64, raster_blocks=1024),
+    dict(chunk=256, raster_blocks=8192, depth_bits=8)])
+def test_config3_full_size_row_subset(knobs):
+    """1M spheres at 1024x1024, C=8, K=8: the benchmark workload, in the
+    default launch configuration and the tuned ones, checked on 6 seeded rows
+    (G zero elsewhere)."""
+    c = _config3_oracle()
+    fwd, out = _parity(c["wl"], rows=c["rows"], what="1M blobs 1024x1024", knobs=knobs,
+                       oracle=c["oracle"])
     assert np.isfinite(out["F"]).all()
 
 

@@ -394,6 +394,85 @@ def test_paper_normalisation_counts_and_gate():
     np.testing.assert_array_equal(pn["grad_bg"], exact["grad_bg"])
 
 
+def _ortho_hits_numpy(sc, cam, reff):
+    """Orthographic ray test written out in numpy, independent of the oracle:
+    the ray of pixel (i, j) leaves (x_s, y_s, 0) along +z; it hits sphere k
+    iff the centre lies less than R_k from the ray and the front intersection
+    c_z - sqrt(R^2 - q^2) is at most zfar (with c_z - R >= znear). Returns
+    hit [H, W, n] and t [H, W, n]."""
+    pitch = cam.sensor_width / cam.width
+    xs = (np.arange(cam.width) + 0.5) * pitch - 0.5 * cam.sensor_width
+    ys = (np.arange(cam.height) + 0.5) * pitch - 0.5 * cam.sensor_width * cam.height / cam.width
+    c = sc.pos @ np.asarray(cam.R, np.float64).reshape(3, 3).T + np.asarray(cam.t, np.float64)
+    q2 = (c[None, None, :, 0] - xs[None, :, None]) ** 2 + \
+        (c[None, None, :, 1] - ys[:, None, None]) ** 2
+    inside = q2 < reff[None, None, :] ** 2
+    t = c[None, None, :, 2] - np.sqrt(np.maximum(reff[None, None, :] ** 2 - q2, 0.0))
+    seen = (c[:, 2] - reff >= cam.znear)[None, None, :]
+    return inside & (t <= cam.zfar) & seen, t
+
+
+@pytest.mark.parametrize("min_radius_px", [0.0, 2.5])
+def test_paper_normalisation_orthographic(min_radius_px):
+    """The optimisation variant under the orthographic projection: pixel
+    counts equal a brute-force count over an independent numpy ray test, the
+    projected radius is R / pitch at any depth (checked against the number of
+    pixel centres a large sphere covers, about pi rpx^2), the minimum size is
+    the constant min_radius_px pixels, and the 3-pixel gate and the averaging
+    follow (Sec. 3.1 orthographic model; App. B normalisation; Sec. 3.2 gate)."""
+    rng = np.random.default_rng(31)
+    n, W, H, C = 9, 40, 36, 2
+    cam = sg.identity_camera(W, H, focal=1.3)
+    cam.orthographic = True
+    pitch = cam.sensor_width / W
+    # depths far apart, so a pinhole radius R f / (c_z pitch) would differ
+    z = rng.uniform(2.0, 9.0, n)
+    r = np.exp(rng.uniform(np.log(0.3 * pitch), np.log(7.0 * pitch), n))
+    r[0] = 8.0 * pitch  # one sphere large enough to count its pixel centres
+    r[1] = 0.2 * pitch  # one well below the minimum size when it is on
+    xy = rng.uniform(-0.6, 0.6, (n, 2))
+    xy[0] = [0.013, -0.021]
+    sc = types.SimpleNamespace(pos=np.column_stack([xy, z]), radius=r,
+                               opacity=rng.uniform(0.3, 1.0, n),
+                               payload=rng.uniform(0, 1, (n, C)), bg=np.zeros(C))
+    params = sg.Params(gamma=0.3, eps=1e-5, K=3, min_radius_px=min_radius_px)
+    fwd = ref.forward(sc, cam, params)
+    G = sg.upstream_grad(56, H, W, C).astype(np.float64)
+    exact = ref.backward(sc, cam, params, G, fwd)
+    pn = ref.paper_normalised(sc, cam, params, fwd, exact)
+    reff = np.maximum(r, min_radius_px * pitch) if min_radius_px > 0 else r
+    hit, t = _ortho_hits_numpy(sc, cam, reff)
+    brute = np.zeros(n)
+    for i in range(H):
+        for j in range(W):
+            ks = sorted(np.nonzero(hit[i, j])[0], key=lambda k: (t[i, j, k], k))[:params.K]
+            brute[ks] += 1
+    np.testing.assert_array_equal(pn["pixel_count"], brute)
+    rpx = pn["projected_radius_px"]
+    # the covered pixel centres of the big sphere: a lattice disk of radius rpx
+    covered = hit[:, :, 0].sum()
+    assert abs(covered - np.pi * rpx[0] ** 2) <= 2.0 * np.pi * rpx[0] + 1.0, (covered, rpx[0])
+    # independent of depth and of the focal length, in pixel units
+    np.testing.assert_allclose(rpx, reff * W / cam.sensor_width, rtol=1e-12)
+    if min_radius_px > 0:
+        assert rpx[1] == pytest.approx(min_radius_px, rel=1e-12)
+    small = rpx <= 3.0
+    assert small.any() and (~small).any()
+    seen = brute > 0
+    assert seen[0] and (brute > 1).any()
+    for key in ["grad_opacity", "grad_payload"]:
+        want = exact[key][seen] / (brute[seen][:, None] if exact[key].ndim == 2 else brute[seen])
+        np.testing.assert_allclose(pn[key][seen], want, rtol=1e-12)
+    assert np.all(pn["grad_pos"][small] == 0) and np.all(pn["grad_radius"][small] == 0)
+    big = seen & ~small
+    assert big.any()
+    np.testing.assert_allclose(pn["grad_pos"][big], exact["grad_pos"][big] / brute[big][:, None],
+                               rtol=1e-12)
+    np.testing.assert_allclose(pn["grad_radius"][big], exact["grad_radius"][big] / brute[big],
+                               rtol=1e-12)
+    np.testing.assert_array_equal(pn["grad_bg"], exact["grad_bg"])
+
+
 def test_paper_minimum_size_reaches_a_pixel_centre():
     """With min_radius_px = sqrt(2)/2 (the one-pixel rule of App. B, Step 0)
     every sphere far too small to be seen is still hit by at least one pixel
