@@ -271,7 +271,7 @@ def bench_batch(args, dev) -> dict:
         wss = {}
 
         def run(p):
-            key = (p.chunk, p.raster_blocks, p.depth_bits)
+            key = (p.chunk, p.raster_blocks)
             if key not in wss:
                 wss[key] = torch.empty(_capi.pulsar_batch_workspace_size(scenes, C, p),
                                        dtype=torch.uint8, device=dev)
@@ -281,9 +281,8 @@ def bench_batch(args, dev) -> dict:
                                      gf, gb, w, stream)
 
         tuned, info = at.tune(run, ps, reps=5, warmup=2)
-        ps.chunk, ps.raster_blocks, ps.depth_bits = tuned.chunk, tuned.raster_blocks, \
-            tuned.depth_bits
-        ws = wss[(ps.chunk, ps.raster_blocks, ps.depth_bits)]
+        ps.chunk, ps.raster_blocks = tuned.chunk, tuned.raster_blocks
+        ws = wss[(ps.chunk, ps.raster_blocks)]
         wss.clear()
         knobs = info["knobs"]
         log(f"[batch] tuned knobs {knobs}")
@@ -327,7 +326,7 @@ def main() -> int:
                     help="use the default launch knobs instead of autotuning them first")
     ap.add_argument("--knobs", default="", metavar="K=V,...",
                     help="fixed launch knobs for the single-scene workload, e.g. "
-                         "raster_blocks=4096,chunk=128,depth_bits=0 (implies no tuning)")
+                         "raster_blocks=4096,chunk=128 (implies no tuning)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times) and exit; "
                          "calibrates the FETCH_SIZE / WRITE_SIZE counters")
@@ -398,21 +397,20 @@ def main() -> int:
     if args.knobs:
         for kv in args.knobs.split(","):
             k, v = kv.split("=")
-            if k not in ("raster_blocks", "chunk", "depth_bits"):
+            if k not in ("raster_blocks", "chunk"):
                 raise SystemExit(f"unknown knob {k}")
             setattr(ps, k, int(v))
         ws = torch.empty(_capi.pulsar_workspace_size(n, W, H, C, ps), dtype=torch.uint8,
                          device=dev)
         step()
-        tune_info = {"knobs": {k: int(getattr(ps, k)) for k in ("raster_blocks", "chunk",
-                                                                 "depth_bits")}}
+        tune_info = {"knobs": {k: int(getattr(ps, k)) for k in ("raster_blocks", "chunk")}}
         log(f"[bench] fixed knobs {tune_info['knobs']}")
     elif not args.no_tune:
         from paper_2004_07484_amd import autotune as at
         wss = {}
 
         def run(p):
-            key = (p.chunk, p.raster_blocks, p.depth_bits)
+            key = (p.chunk, p.raster_blocks)
             if key not in wss:
                 wss[key] = torch.empty(_capi.pulsar_workspace_size(n, W, H, C, p),
                                        dtype=torch.uint8, device=dev)
@@ -422,7 +420,7 @@ def main() -> int:
                              stream)
 
         ps, tune_info = at.tune(run, ps, reps=5, warmup=2)
-        ws = wss[(ps.chunk, ps.raster_blocks, ps.depth_bits)]
+        ws = wss[(ps.chunk, ps.raster_blocks)]
         wss.clear()
         torch.cuda.synchronize()
         log(f"[bench] tuned knobs {tune_info['knobs']} ({tune_info['ms']:.3f} ms eager)")
@@ -586,8 +584,7 @@ def main() -> int:
                   "masked_pixels": int(orc["fwd"]["ambiguous"][rows].sum()),
                   "max_rel_image": rel_img, "max_rel_grad": max(rel_grad.values()),
                   "max_rel_grad_by_tensor": rel_grad, "tolerance": {"image": 1e-4, "grad": 1e-3},
-                  "knobs": {k: int(getattr(ps, k)) for k in ("raster_blocks", "chunk",
-                                                             "depth_bits")}}
+                  "knobs": {k: int(getattr(ps, k)) for k in ("raster_blocks", "chunk")}}
         parity["pass"] = bool(rel_img <= 1e-4 and parity["max_rel_grad"] <= 1e-3)
         log(f"[bench] parity on {len(rows)} oracle rows: image {rel_img:.2e}, gradients "
             f"{parity['max_rel_grad']:.2e} ({'pass' if parity['pass'] else 'FAIL'})")

@@ -90,8 +90,11 @@ typedef struct pulsar_camera {
  *   every gradient of a sphere (position, radius, opacity, payload) is divided
  *   by the number of pixels it received gradients from (App. B), and spheres
  *   whose projected radius R f / (c_z pitch) is at most 3 pixels get no
- *   position or radius gradient (Sec. 3.2, Sec. 7 limitation 1). Camera and
- *   background gradients stay exact.
+ *   position or radius gradient (Sec. 3.2, Sec. 7 limitation 1). The camera
+ *   gradients of pulsar_bwd_camera are normalised by each sphere's image area
+ *   (App. B): the part that comes from a sphere is scaled by
+ *   1e-3 / (pi (R f / (c_z pitch))^2) before the sum over spheres. The
+ *   background gradient stays exact.
  * PULSAR_BLEND_TOPK: the other reading of K (Sec. 3.2, App. B Step 2): only
  *   each pixel's K nearest hits in (t, index) order enter Eq. 1, in the image
  *   and in the log-normaliser. The forward then makes one more raster pass
@@ -132,9 +135,9 @@ typedef struct pulsar_params {
                            (PULSAR_ERR_UNSUPPORTED) */
   int32_t max_pairs;    /* capacity of (screen tile, sphere) pairs; 0 = default
                            (2 n + number of tiles + 65536) */
-  int32_t depth_bits;   /* bits of quantised depth in the sort key (tile lists
-                           near to far); 0 = automatic (fills the last radix
-                           digit). Changes only the summation order. */
+  int32_t depth_bits;   /* reserved, must be 0 (PULSAR_ERR_UNSUPPORTED
+                           otherwise): every tile list holds its spheres in
+                           the order of their index */
   int32_t chunk;        /* sphere records per raster work item: 0 = automatic
                            (128), else a multiple of 64 in [64, 1024]. Long tile
                            lists are split into work items of this size and

@@ -336,7 +336,10 @@ int oracle_forward(int n, int C, const double* pos, const double* radius, const 
  * proportional to s) and through the minimum-size radius rho c_z / f with
  * rho proportional to s. grad_cam_abs (may be NULL) receives, per value, the
  * sum of the absolute values of the terms added into it, a scale for
- * comparing sums that cancel.
+ * comparing sums that cancel. grad_cam_sphere (may be NULL) receives [n, 14]:
+ * row k holds the part of those 14 values that comes from sphere k (its
+ * centre through R and t, its hits through f and s, its minimum-size radius);
+ * the rows add up to grad_cam.
  */
 int oracle_backward(int n, int C, const double* pos, const double* radius, const double* opacity,
                     const double* payload, const double* bg, const double* cam16, int W, int H,
@@ -344,7 +347,7 @@ int oracle_backward(int n, int C, const double* pos, const double* radius, const
                     const int* rows, const double* G, const double* F, const double* L,
                     const int* klist_id, double* grad_pos, double* grad_radius,
                     double* grad_opacity, double* grad_payload, double* grad_bg,
-                    double* grad_cam, double* grad_cam_abs) {
+                    double* grad_cam, double* grad_cam_abs, double* grad_cam_sphere) {
   (void)bg;
   if (n < 0 || C < 1 || W < 1 || H < 1 || K < 1 || !(gamma > 0.0)) return ORACLE_BAD_ARG;
   camera_t cam;
@@ -352,7 +355,9 @@ int oracle_backward(int n, int C, const double* pos, const double* radius, const
   sphere_cam_t* sc = transform_all(&cam, n, pos, radius, opacity, min_radius_px);
   double* gc = (double*)calloc((size_t)(n > 0 ? n : 1) * 3, sizeof(double));
   double* gR = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
-  if (!sc || !gc || !gR) return ORACLE_BAD_ARG;
+  /* per sphere: its f and s terms from the pixel rays */
+  double* gfs = (double*)calloc((size_t)(n > 0 ? n : 1) * 2, sizeof(double));
+  if (!sc || !gc || !gR || !gfs) return ORACLE_BAD_ARG;
   memset(grad_pos, 0, sizeof(double) * 3 * (size_t)n);
   memset(grad_radius, 0, sizeof(double) * (size_t)n);
   if (grad_opacity) memset(grad_opacity, 0, sizeof(double) * (size_t)n);
@@ -425,12 +430,22 @@ int oracle_backward(int n, int C, const double* pos, const double* radius, const
           gabs[12] += fabs(sdu * cf);
           gcam[13] += sdu * cs;
           gabs[13] += fabs(sdu * cs);
+          gfs[2 * (size_t)k] += sdu * cf;
+          gfs[2 * (size_t)k + 1] += sdu * cs;
         }
       }
     }
   }
   for (int k = 0; k < n; ++k) {
     double g[3] = {gc[3 * (size_t)k], gc[3 * (size_t)k + 1], gc[3 * (size_t)k + 2]};
+    double* row = grad_cam_sphere ? grad_cam_sphere + 14 * (size_t)k : NULL;
+    if (row) {
+      memset(row, 0, 14 * sizeof(double));
+      if (!cam.ortho) {
+        row[12] = gfs[2 * (size_t)k];
+        row[13] = gfs[2 * (size_t)k + 1];
+      }
+    }
     if (sc[k].clamped && cam.ortho) {
       /* R = min_radius_px pitch depends on neither the sphere nor its depth */
       grad_radius[k] = 0.0;
@@ -443,6 +458,10 @@ int oracle_backward(int n, int C, const double* pos, const double* radius, const
       gabs[12] += fabs(gR[k] * sc[k].R / cam.f);
       gcam[13] += gR[k] * (sc[k].R / cam.s);
       gabs[13] += fabs(gR[k] * sc[k].R / cam.s);
+      if (row) {
+        row[12] += gR[k] * (-sc[k].R / cam.f);
+        row[13] += gR[k] * (sc[k].R / cam.s);
+      }
     } else {
       grad_radius[k] = gR[k];
     }
@@ -454,6 +473,10 @@ int oracle_backward(int n, int C, const double* pos, const double* radius, const
       }
       gcam[9 + a] += g[a];
       gabs[9 + a] += fabs(g[a]);
+      if (row) {
+        for (int b2 = 0; b2 < 3; ++b2) row[3 * a + b2] = g[a] * pos[3 * (size_t)k + b2];
+        row[9 + a] = g[a];
+      }
     }
     /* c = R p + t  =>  dLoss/dp = R^T dLoss/dc */
     for (int a = 0; a < 3; ++a)
@@ -465,6 +488,7 @@ int oracle_backward(int n, int C, const double* pos, const double* radius, const
   free(sc);
   free(gc);
   free(gR);
+  free(gfs);
   return ORACLE_OK;
 }
 

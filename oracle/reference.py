@@ -43,7 +43,7 @@ def _load():
         lib.oracle_backward.argtypes = [
             ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int,
             ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
-            ctypes.c_int, _ip, _dp, _dp, _dp, _ip, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+            ctypes.c_int, _ip, _dp, _dp, _dp, _ip, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
         lib.oracle_pixel_hits.restype = ctypes.c_int
         lib.oracle_pixel_hits.argtypes = [
             ctypes.c_int, _dp, _dp, _dp, _dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
@@ -113,7 +113,8 @@ def forward(scene, cam, params, rows: Optional[Sequence[int]] = None,
 def backward(scene, cam, params, G, fwd: dict, rows: Optional[Sequence[int]] = None) -> dict:
     """Gradients of sum(G * F) for the scene parameters, the background and
     the camera: grad_camera = [dR (3x3 row-major), dt (3), df, ds], with
-    grad_camera_abs the sum of |term| behind each value."""
+    grad_camera_abs the sum of |term| behind each value and grad_camera_sphere
+    [n, 14] the part of grad_camera that comes from each sphere."""
     lib = _load()
     pos, rad = _d(scene.pos), _d(scene.radius)
     opa = None if scene.opacity is None else _d(scene.opacity)
@@ -130,6 +131,7 @@ def backward(scene, cam, params, G, fwd: dict, rows: Optional[Sequence[int]] = N
     gb = np.zeros(C)
     gcam = np.zeros(14)
     gabs = np.zeros(14)
+    gsph = np.zeros((n, 14))
     F = _d(np.nan_to_num(fwd["F"]))
     L = _d(np.nan_to_num(fwd["L"]))
     kid = np.ascontiguousarray(fwd["klist_id"].astype(np.int32))
@@ -138,11 +140,11 @@ def backward(scene, cam, params, G, fwd: dict, rows: Optional[Sequence[int]] = N
                              float(params.eps), float(params.min_radius_px), K, nr,
                              _ptr(r, _ip), _ptr(G), _ptr(F), _ptr(L), _ptr(kid, _ip),
                              _ptr(gp), _ptr(gr), _ptr(go), _ptr(gf), _ptr(gb), _ptr(gcam),
-                             _ptr(gabs))
+                             _ptr(gabs), _ptr(gsph))
     if rc != 0:
         raise ValueError(f"oracle_backward failed with code {rc}")
     return dict(grad_pos=gp, grad_radius=gr, grad_opacity=go, grad_payload=gf, grad_bg=gb,
-                grad_camera=gcam, grad_camera_abs=gabs)
+                grad_camera=gcam, grad_camera_abs=gabs, grad_camera_sphere=gsph)
 
 
 def paper_normalised(scene, cam, params, fwd: dict, grads: dict,
@@ -152,8 +154,13 @@ def paper_normalised(scene, cam, params, fwd: dict, grads: dict,
     number of pixels whose K nearest hits include k (App. B, normalisation),
     and no position or radius gradient for a sphere whose projected radius
     R f / (c_z pitch) is at most 3 pixels (Sec. 3.2; Sec. 7, limitation 1),
-    R the effective radius (App. B, Step 0). Camera and background gradients
-    are returned unchanged. Counts run over the evaluated rows."""
+    R the effective radius (App. B, Step 0). Camera gradients are normalised
+    by each sphere's image area (App. B, normalisation of the camera
+    gradients; reading: the part of the camera gradient that comes from
+    sphere k, grads["grad_camera_sphere"][k], is scaled by 1e-3 / A_k with A_k
+    = pi (R f / (c_z pitch))^2 its projected disk area in pixels, then the
+    parts are added). The background gradient is returned unchanged. Counts
+    run over the evaluated rows."""
     K = int(params.K)
     kid = np.asarray(fwd["klist_id"])
     H = kid.shape[0]
@@ -183,6 +190,11 @@ def paper_normalised(scene, cam, params, fwd: dict, grads: dict,
     if grads.get("grad_opacity") is not None:
         out["grad_opacity"] = grads["grad_opacity"] * scale
     out["grad_payload"] = grads["grad_payload"] * scale[:, None]
+    if grads.get("grad_camera_sphere") is not None:
+        area = np.pi * rpx * rpx
+        out["grad_camera"] = (grads["grad_camera_sphere"] * (1e-3 / area)[:, None]).sum(0)
+        out["grad_camera_abs"] = np.abs(grads["grad_camera_sphere"] *
+                                        (1e-3 / area)[:, None]).sum(0)
     out["pixel_count"] = count
     out["projected_radius_px"] = rpx
     return out

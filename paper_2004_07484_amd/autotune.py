@@ -7,8 +7,6 @@ computed are measured on the device instead:
   raster_blocks  size of the persistent raster grid (never changes the image)
   chunk          sphere records per raster work item (changes only the
                  summation order of the blend)
-  depth_bits     width of the quantised depth in the sort key (summation order
-                 only; more bits cost radix passes)
 
 The 8x8 tile is not a knob: one wave64 owns one tile, lane = pixel, which the
 kernels rely on for their LDS layouts and ballots.
@@ -34,7 +32,6 @@ from . import _capi
 KNOBS: Tuple[Tuple[str, Tuple[int, ...]], ...] = (
     ("raster_blocks", (1024, 2048, 4096, 8192, 16384)),
     ("chunk", (64, 128, 256, 512)),
-    ("depth_bits", (0, 8)),
 )
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pulsar_amd_autotune.json")

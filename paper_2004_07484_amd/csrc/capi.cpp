@@ -21,12 +21,6 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-int ceil_log2(int64_t v) {
-  int b = 0;
-  while ((int64_t(1) << b) < v) ++b;
-  return b;
-}
-
 bool finite_all(const float* v, int k) {
   for (int i = 0; i < k; ++i)
     if (!std::isfinite(v[i])) return false;
@@ -56,7 +50,8 @@ int check_params(const pulsar_params_t* p) {
     return PULSAR_ERR_INVALID_ARGUMENT;
   if (p->K < 1 || p->K > kMaxK) return PULSAR_ERR_INVALID_ARGUMENT;
   if (p->max_pairs < 0) return PULSAR_ERR_INVALID_ARGUMENT;
-  if (p->depth_bits < 0 || p->depth_bits > 16) return PULSAR_ERR_INVALID_ARGUMENT;
+  // the tile lists are in sphere order; a depth key is no longer offered
+  if (p->depth_bits != 0) return PULSAR_ERR_UNSUPPORTED;
   if (p->chunk != 0 && (p->chunk < 64 || p->chunk > 1024 || p->chunk % 64 != 0))
     return PULSAR_ERR_INVALID_ARGUMENT;
   if (p->raster_blocks != 0 && (p->raster_blocks < 256 || p->raster_blocks > 65536))
@@ -68,13 +63,9 @@ int check_params(const pulsar_params_t* p) {
   return PULSAR_OK;
 }
 
-int fail_hip(hipError_t e) {
-  g_last_hip_error = hipGetErrorString(e);
-  return PULSAR_ERR_HIP;
-}
-
 // ---- stage timing
 std::atomic<int> g_timing{0};
+thread_local int g_timing_off = 0;  // > 0: this thread's calls record no events
 std::mutex g_timing_mu;
 struct Mark {
   int stage;
@@ -85,8 +76,16 @@ hipEvent_t g_open[PULSAR_NUM_STAGES] = {};  // begin events without their end ye
 
 }  // namespace
 
+int fail_hip(hipError_t e) {
+  g_last_hip_error = hipGetErrorString(e);
+  return PULSAR_ERR_HIP;
+}
+
+TimingOff::TimingOff() { ++g_timing_off; }
+TimingOff::~TimingOff() { --g_timing_off; }
+
 void stage_begin(int stage, hipStream_t stream) {
-  if (!g_timing.load(std::memory_order_relaxed)) return;
+  if (g_timing_off > 0 || !g_timing.load(std::memory_order_relaxed)) return;
   std::lock_guard<std::mutex> lk(g_timing_mu);
   hipEvent_t e;
   if (hipEventCreate(&e) != hipSuccess) return;
@@ -96,7 +95,7 @@ void stage_begin(int stage, hipStream_t stream) {
 }
 
 void stage_end(int stage, hipStream_t stream) {
-  if (!g_timing.load(std::memory_order_relaxed)) return;
+  if (g_timing_off > 0 || !g_timing.load(std::memory_order_relaxed)) return;
   std::lock_guard<std::mutex> lk(g_timing_mu);
   if (!g_open[stage]) return;
   hipEvent_t e;
@@ -144,10 +143,34 @@ int make_scenes(const pulsar_scene_t* scenes, int B, const pulsar_params_t* p,
       return PULSAR_ERR_INVALID_ARGUMENT;
     out->push_back(d);
   }
+  // bin blocks: S spheres each, so that the count matrix, sum over scenes of
+  // (bin blocks) x (tiles), stays near kBinCells entries, but at most
+  // kBinMaxG blocks per scene; units and matrix rows scene by scene
+  double work = 0.0;
+  for (const SceneDev& d : *out) work += double(d.n) * double(d.cam.tiles_x) * d.cam.tiles_y;
+  int64_t per = int64_t(std::ceil(work / double(kBinCells) / double(kBinThreads)));
+  if (per < 1) per = 1;
+  int64_t units = 0;
+  unsigned long long rows = 0;
+  for (SceneDev& d : *out) {
+    const int64_t nb = (int64_t(d.n) + kBinThreads - 1) / kBinThreads;  // rounds
+    int64_t pb = per;
+    if ((nb + pb - 1) / pb > kBinMaxG) pb = (nb + kBinMaxG - 1) / kBinMaxG;
+    const int64_t T_b = int64_t(d.cam.tiles_x) * d.cam.tiles_y;
+    d.bin_S = uint32_t(pb * kBinThreads);
+    d.bin_G = uint32_t(nb > 0 ? (nb + pb - 1) / pb : 0);
+    d.slices = uint32_t((T_b + kBinSlice - 1) / kBinSlice);
+    d.unit_off = uint32_t(units);
+    d.row_off = rows;
+    units += int64_t(d.bin_G) * d.slices;
+    rows += (unsigned long long)d.bin_G * (unsigned long long)T_b;
+    if (units > INT32_MAX) return PULSAR_ERR_INVALID_ARGUMENT;
+  }
   return PULSAR_OK;
 }
 
-int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, Plan* out) {
+int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, Plan* out,
+              bool fwd_only) {
   if (sc.empty() || C < 1) return PULSAR_ERR_INVALID_ARGUMENT;
   int rc = check_params(p);
   if (rc != PULSAR_OK) return rc;
@@ -163,23 +186,14 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   q.nbgblk = int64_t(last.bgblk_off) + (lastpix + kBgBlockPixels - 1) / kBgBlockPixels;
   q.chunk = p->chunk > 0 ? p->chunk : kChunkDefault;
   q.raster_grid = p->raster_blocks > 0 ? p->raster_blocks : kRasterGridDefault;
-  q.tile_bits = ceil_log2(q.T);
-  if (q.tile_bits < 1) q.tile_bits = 1;
-  if (p->depth_bits > 0) {
-    q.depth_bits = p->depth_bits;
-  } else {
-    // the exact blend needs no depth order: only fill the last 8-bit digit
-    int total = (q.tile_bits + 7) / 8 * 8;
-    q.depth_bits = total - q.tile_bits;
-  }
-  if (q.tile_bits + q.depth_bits > 32) return PULSAR_ERR_UNSUPPORTED;
-  q.passes = (q.tile_bits + q.depth_bits + 7) / 8;
   const int64_t n = q.n;
   int64_t cap = p->max_pairs > 0 ? int64_t(p->max_pairs) : 2 * n + q.T + 65536;
   if (cap > (int64_t(1) << 31) - 1) cap = (int64_t(1) << 31) - 1;
   q.cap = cap;
   q.nblk_proj = int((n + kProjectBlock - 1) / kProjectBlock);
-  q.nblk_sort = int((cap + kSortBlock - 1) / kSortBlock);
+  q.bin_units = int64_t(last.unit_off) + int64_t(last.bin_G) * last.slices;
+  q.bin_cells = int64_t(last.row_off) +
+                int64_t(last.bin_G) * int64_t(last.cam.tiles_x) * last.cam.tiles_y;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -189,25 +203,21 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   const size_t nn = size_t(n > 0 ? n : 1);
   q.off_status = take(sizeof(Status));
   q.off_scenes = take(size_t(q.B) * sizeof(SceneDev));
-  q.off_starts = take(size_t(3) * size_t(q.B + 1) * 4);
+  q.off_starts = take(size_t(kStartArrays) * size_t(q.B + 1) * 4);
   q.off_counts = take(nn * 4);
   q.off_trect = take(nn * 8);
-  q.off_qdepth = take(nn * 4);
   q.off_rec = take(nn * 64);
   q.off_partials = take(size_t(q.nblk_proj + 1) * 8);
   q.off_boff = take(size_t(q.nblk_proj + 1) * 8);
-  q.off_keysA = take(size_t(cap) * 4);
-  q.off_valsA = take(size_t(cap) * 4);
-  q.off_keysB = take(size_t(cap) * 4);
-  q.off_valsB = take(size_t(cap) * 4);
-  q.off_hist = take(size_t(kSortRadix) * size_t(q.nblk_sort) * 4);
-  q.off_dtot = take(size_t(kSortRadix) * 4);
+  q.off_bmat = take(size_t(q.bin_cells > 0 ? q.bin_cells : 1) * 4);
+  q.off_tcount = take(size_t(q.T) * 4);
+  q.off_gsum = take(size_t((q.T + 63) / 64) * 32);
+  q.off_vals = take(size_t(cap) * 4);
   q.off_ranges = take(size_t(q.T + 1) * 4);
   q.max_chunks = (cap + q.chunk - 1) / q.chunk + q.T;
   // partial blend states: a tile of L > chunk pairs needs ceil(L / chunk)
   // < 2 L / chunk of them, so 2 cap / chunk + 1 bounds their sum
   q.pcap = 2 * ((cap + q.chunk - 1) / q.chunk) + 1;
-  q.nblk_tiles = int((q.T + 255) / 256);
   q.fwd_cm = C < kFwdChannels ? C : kFwdChannels;
   int km = 4;  // register K-list slots: a power of two >= K, at least 4
   while (km < p->K) km *= 2;
@@ -215,21 +225,23 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   q.pstride = 2 + q.fwd_cm + 2 * km;  // m, D, numerator[cm], K-list (t, id)
   q.off_tinfo = take(size_t(q.T) * 16);
   q.off_desc = take(size_t(q.max_chunks) * 16);
-  q.off_cpart = take(size_t(q.nblk_tiles + 1) * 16);
-  q.off_bgsum = take(size_t(q.nbgblk) * size_t(C) * 4);
+  // a forward that keeps no backward state needs none of the backward's
+  // buffers (the top-K blend still needs the per-pixel thresholds)
+  const bool bwd = !fwd_only;
+  const bool thr = bwd || (p->flags & PULSAR_BLEND_TOPK) != 0u;
+  q.off_bgsum = take(bwd ? size_t(q.nbgblk) * size_t(C) * 4 : 0);
   q.off_pstate = take(size_t(q.pcap) * kWave * size_t(q.pstride) * 4);
-  q.off_thr = take(size_t(q.npix) * 8);
+  q.off_thr = take(thr ? size_t(q.npix) * 8 : 0);
   q.off_mlist = take(size_t(q.T) * 4);
   // the backward kernel instance keeps cm >= C channels, a power of two up to
   // 32; wider payloads keep only dL/dc, dL/dR | dL/do in the record
   int bcm = 1;
   while (bcm < C && bcm < kBwdChannels) bcm *= 2;
   q.bwd_ps4 = C <= kBwdChannels ? 1 + (bcm + 6) / 4 : 2;
-  q.off_pslot = take(size_t(cap) * size_t(q.bwd_ps4) * 16);
-  q.off_sfirst = take(nn * 4);
+  q.off_pslot = take(bwd ? size_t(cap) * size_t(q.bwd_ps4) * 16 : 0);
   q.ncampart = int64_t(q.B) + n / kCamSpan + 1;
-  q.off_camg = take(nn * 16);
-  q.off_campart = take(size_t(q.ncampart) * 16 * 8);
+  q.off_camg = take(bwd ? nn * 16 : 0);
+  q.off_campart = take(bwd ? size_t(q.ncampart) * 16 * 8 : 0);
   q.total = o;
   *out = q;
   return PULSAR_OK;

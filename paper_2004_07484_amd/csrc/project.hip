@@ -5,7 +5,6 @@
 // screen-space record exact enough for sub-pixel spheres). Outputs per sphere:
 //   counts  number of 8x8 tiles its pixel rectangle touches (0 = culled)
 //   trect   tile rectangle (tx0, ty0, tx1, ty1)
-//   qdepth  floor-quantised lower bound of its nearest possible hit distance
 //   rec     four float4 per sphere, one 64-byte line:
 //     [0]   (X_c - x0, Y_c - y0, kappa, x0 | y0 << 16): projected centre in
 //           pixel units relative to the first pixel of its rectangle, and
@@ -30,7 +29,7 @@ namespace pulsar {
 // scene also writes the B-th (total) entry of each start array.
 struct SceneUpload {
   int first, count, B;
-  uint32_t total_spheres, total_tiles, total_blocks;
+  uint32_t total_spheres, total_tiles, total_blocks, total_units;
   SceneDev s[kUploadScenes];
 };
 
@@ -44,11 +43,13 @@ __global__ __launch_bounds__(64) void k_upload_scenes(SceneUpload u, SceneDev* _
     starts[b] = u.s[k].sph_off;
     starts[B1 + b] = u.s[k].tile_off;
     starts[2 * B1 + b] = u.s[k].bgblk_off;
+    starts[3 * B1 + b] = u.s[k].unit_off;
   }
   if (k == 0 && u.first + u.count == u.B) {
     starts[u.B] = u.total_spheres;
     starts[B1 + u.B] = u.total_tiles;
     starts[2 * B1 + u.B] = u.total_blocks;
+    starts[3 * B1 + u.B] = u.total_units;
   }
 }
 
@@ -62,6 +63,7 @@ static SceneUpload make_upload(const Plan& q, const std::vector<SceneDev>& sc, i
   u.total_spheres = uint32_t(q.n);
   u.total_tiles = uint32_t(q.T);
   u.total_blocks = uint32_t(q.nbgblk);
+  u.total_units = uint32_t(q.bin_units);
   for (int k = 0; k < u.count; ++k) u.s[k] = sc[size_t(first + k)];
   return u;
 }
@@ -84,9 +86,8 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
     int n, const float* __restrict__ pos, const float* __restrict__ radius,
     const float* __restrict__ opacity, SceneTable tab, SceneUpload u, int inline_scenes,
     SceneDev* __restrict__ tab_out, uint32_t* __restrict__ starts_out, float min_radius_px,
-    int depth_bits,
-    uint32_t* __restrict__ counts, ushort4* __restrict__ trect, uint32_t* __restrict__ qdepth,
-    float4* __restrict__ rec, unsigned long long* __restrict__ partials) {
+    uint32_t* __restrict__ counts, ushort4* __restrict__ trect, float4* __restrict__ rec,
+    unsigned long long* __restrict__ partials) {
   const int i = blockIdx.x * kProjectBlock + threadIdx.x;
   if (inline_scenes && blockIdx.x == 0 && threadIdx.x < kWave) {
     const int k = threadIdx.x;
@@ -96,11 +97,13 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
       starts_out[k] = u.s[k].sph_off;
       starts_out[B1 + k] = u.s[k].tile_off;
       starts_out[2 * B1 + k] = u.s[k].bgblk_off;
+      starts_out[3 * B1 + k] = u.s[k].unit_off;
     }
     if (k == 0) {
       starts_out[u.B] = u.total_spheres;
       starts_out[B1 + u.B] = u.total_tiles;
       starts_out[2 * B1 + u.B] = u.total_blocks;
+      starts_out[3 * B1 + u.B] = u.total_units;
     }
   }
   uint32_t count = 0;
@@ -188,15 +191,6 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
         r2 = make_float4(float(X - Xh), float(Y - Yh), float(kap - kh), float(ax - axh));
         const uint32_t packed_end = uint32_t(j1) | (uint32_t(i1) << 16);
         r3 = make_float4(float(ay - ayh), o, __uint_as_float(packed_end), 0.f);
-        if (depth_bits > 0) {
-          // floor quantisation of (tmin - znear) / span, minus one step of margin,
-          // so the decoded value never exceeds any float32 hit distance
-          const double span = double(cam.zfar) - double(cam.znear);
-          const double levels = double(1u << depth_bits);
-          double qd = floor((tmin - double(cam.znear)) / span * levels) - 1.0;
-          qd = fmin(fmax(qd, 0.0), levels - 1.0);
-          qdepth[i] = uint32_t(qd);
-        }
       }
     }
     counts[i] = count;
@@ -236,9 +230,9 @@ void launch_project(const Plan& q, const std::vector<SceneDev>& sc, const FwdArg
   hipLaunchKernelGGL(k_project, dim3(q.nblk_proj), dim3(kProjectBlock), 0, stream, int(q.n),
                      a.pos, a.radius, a.opacity, scene_table(q, ws), u, inline_scenes ? 1 : 0,
                      ws_ptr<SceneDev>(ws, q.off_scenes), ws_ptr<uint32_t>(ws, q.off_starts),
-                     a.min_radius_px, q.depth_bits,
+                     a.min_radius_px,
                      ws_ptr<uint32_t>(ws, q.off_counts), ws_ptr<ushort4>(ws, q.off_trect),
-                     ws_ptr<uint32_t>(ws, q.off_qdepth), ws_ptr<float4>(ws, q.off_rec),
+                     ws_ptr<float4>(ws, q.off_rec),
                      ws_ptr<unsigned long long>(ws, q.off_partials));
 }
 

@@ -16,10 +16,16 @@ constexpr int kTileW = 8;
 constexpr int kTileH = 8;
 constexpr int kWave = 64;
 constexpr int kProjectBlock = 256;           // spheres per projection block
-constexpr int kSortThreads = 256;
-constexpr int kSortRounds = 4;
-constexpr int kSortBlock = kSortThreads * kSortRounds;  // keys per sort block
-constexpr int kSortRadix = 256;              // 8-bit digits
+// binning: the (bin block, tile) count matrix is built and read in slices of
+// kBinSlice tiles; K3 handles 64 tiles per block of kScanThreads threads, each
+// wave up to kBinRowsPerWave rows of the matrix (so at most kBinMaxG rows)
+constexpr int kBinThreads = 256;
+constexpr int kBinSliceBits = 13;
+constexpr int kBinSlice = 1 << kBinSliceBits;
+constexpr int kScanThreads = 1024;
+constexpr int kBinRowsPerWave = 16;
+constexpr int kBinMaxG = kBinRowsPerWave * (kScanThreads / 64);
+constexpr long long kBinCells = 1LL << 22;  // matrix size the bin-block sizes aim for
 constexpr int kMaxK = 32;
 constexpr int kFwdChannels = 32;             // channels per forward pass (more: several passes)
 constexpr int kBwdChannels = 32;             // channels kept in registers by the backward
@@ -83,15 +89,24 @@ struct SceneDev {
   uint32_t tile_off;   // first tile in the global tile numbering
   uint32_t bgblk_off;  // first background-gradient block
   unsigned long long pix_off;  // first pixel (index into the packed [P] planes)
+  // binning: the scene's spheres in bin_G bin blocks of bin_S (a multiple of
+  // kBinThreads) and its tiles in `slices` slices of kBinSlice; its work
+  // units (bin block, slice) are unit_off .. unit_off + bin_G slices - 1,
+  // bin block g's counts per tile are row row_off + g T_b of the matrix
+  uint32_t bin_S, bin_G, slices, unit_off;
+  unsigned long long row_off;
 };
 
-// Device copy of the scene table plus three ascending start arrays of B + 1
-// entries each (spheres, tiles, background blocks) for scene lookup.
+// Device copy of the scene table plus four ascending start arrays of B + 1
+// entries each (spheres, tiles, background blocks, binning units) for scene
+// lookup.
+constexpr int kStartArrays = 4;
 struct SceneTable {
   const SceneDev* scenes;
   const uint32_t* sph_start;
   const uint32_t* tile_start;
   const uint32_t* blk_start;
+  const uint32_t* unit_start;
   int B;
 };
 
@@ -99,21 +114,28 @@ struct SceneTable {
 struct Plan {
   int64_t n, C, T, npix, cap, nbgblk;
   int B, chunk, raster_grid;
-  int tile_bits, depth_bits, passes, nblk_proj, nblk_sort;
-  size_t off_status, off_counts, off_trect, off_qdepth, off_rec;
-  size_t off_partials, off_boff, off_keysA, off_valsA, off_keysB, off_valsB, off_hist, off_dtot;
-  size_t off_ranges;
+  int nblk_proj;
+  // binning: work units (bin block, tile slice) of all scenes and the size
+  // of the count matrix
+  int64_t bin_units, bin_cells;
+  size_t off_status, off_counts, off_trect, off_rec;
+  size_t off_partials, off_boff;
+  size_t off_bmat;    // [G, T] pairs per (bin block, tile), then their offsets inside the tile
+  size_t off_tcount;  // [T] pairs per tile
+  size_t off_gsum;    // [T / 64] sums over groups of 64 tiles (pairs, work-item counts)
+  size_t off_vals;    // [cap] sphere index of every pair, tile by tile
+  size_t off_ranges;  // [T + 1] first pair of each tile
   // raster work items: per tile uint4 (first partial-state slot, chunks, 0, 0);
   // the work list uint4 (tile | kFirstChunk, begin, end, slot or kNoSlot);
   // block sums of the chunk scan; the partial blend states; the per-pixel
   // K-th nearest hit (t, sphere id); background-gradient block sums
-  size_t off_tinfo, off_desc, off_cpart, off_pstate, off_thr, off_bgsum;
+  size_t off_tinfo, off_desc, off_pstate, off_thr, off_bgsum;
   size_t off_mlist;  // tiles with several work items, for the merge kernel
   size_t off_scenes, off_starts;  // scene table and its start arrays
   // backward: one sum slot per (tile, sphere) pair at its emission position,
   // bwd_ps4 float4 each (dL/dc, dL/dR | dL/df[cm] | dL/do, dL/d(f/s), pixel
-  // count, padding), and each sphere's first emission position
-  size_t off_pslot, off_sfirst;
+  // count, padding)
+  size_t off_pslot;
   // camera gradients: per sphere float4 (dL/dc, dL/d(f/s)); per-scene runs of
   // partial sums, 16 doubles each (scene b's run starts at b + first sphere /
   // kCamSpan)
@@ -121,7 +143,7 @@ struct Plan {
   int64_t ncampart;
   int bwd_ps4;
   int64_t max_chunks, pcap;
-  int nblk_tiles, fwd_cm, klist_slots, pstride;
+  int fwd_cm, klist_slots, pstride;
   size_t total;
 };
 
@@ -131,7 +153,9 @@ int make_scenes(const pulsar_scene_t* scenes, int B, const pulsar_params_t* p,
                 std::vector<SceneDev>* out);
 // Fills `out` from a validated scene table and returns PULSAR_OK, or returns
 // an error code.
-int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, Plan* out);
+// fwd_only: a forward that keeps no backward state (no backward buffers).
+int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, Plan* out,
+              bool fwd_only = false);
 CamDev make_cam(const pulsar_camera_t* c);
 BlendConst make_blend(const pulsar_camera_t* c, const pulsar_params_t* p);
 
@@ -184,15 +208,19 @@ hipError_t launch_rebin(const Plan& plan, const std::vector<SceneDev>& scenes, c
 // Stage timing hooks (no-ops unless pulsar_timing_enable(1) was called).
 void stage_begin(int stage, hipStream_t stream);
 void stage_end(int stage, hipStream_t stream);
+// While one exists, the calling thread's launches record no timing events.
+struct TimingOff {
+  TimingOff();
+  ~TimingOff();
+};
+// Records the HIP error for pulsar_last_hip_error; returns PULSAR_ERR_HIP.
+int fail_hip(hipError_t e);
 
 // Pointers into the workspace.
 template <typename T>
 inline T* ws_ptr(char* ws, size_t off) {
   return reinterpret_cast<T*>(ws + off);
 }
-
-// Result of the LSD sort lands in the A buffers after an even number of passes.
-inline bool sorted_in_a(const Plan& p) { return (p.passes % 2) == 0; }
 
 inline SceneTable scene_table(const Plan& q, char* ws) {
   SceneTable t;
@@ -201,6 +229,7 @@ inline SceneTable scene_table(const Plan& q, char* ws) {
   t.sph_start = st;
   t.tile_start = st + (q.B + 1);
   t.blk_start = st + 2 * (q.B + 1);
+  t.unit_start = st + 3 * (q.B + 1);
   t.B = q.B;
   return t;
 }

@@ -39,6 +39,7 @@ struct BwdKernelArgs {
   float4* pslot;        // per-pair sum slots at emission positions, ps4 float4 each
   int ps4;
   const uint32_t* svals;  // sphere index of every sorted pair
+  uint32_t last_sph;      // n - 1: sorted indices are clamped to it
   float* grad_payload;  // caller's output, added per hit by the wide path only
   int C;
   int need_geo, need_op, need_pay, need_cam;
@@ -148,7 +149,7 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
 #pragma unroll
     for (int c = 0; c < CM; ++c) f[c] = 0.f;
     auto load_record = [&](uint32_t jj) {
-      const uint32_t sph = A.svals[jj];
+      const uint32_t sph = min(A.svals[jj], A.last_sph);
       const float4* rp = A.rec + 4 * size_t(sph);
       ra = rp[0];
       rb = rp[1];
@@ -294,7 +295,7 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A,
     for (uint32_t b0 = beg; b0 < end; b0 += kWave) {
       const uint32_t j = b0 + uint32_t(lane);
       if (j >= end) continue;
-      const uint32_t id = A.svals[j];  // sphere index
+      const uint32_t id = min(A.svals[j], A.last_sph);  // sphere index
       const float4* rp = A.rec + 4 * size_t(id);
       const float4 a = rp[0], d = rp[3];
       const SphereRec s = unpack_rec(a, rp[1], rp[2], d);
@@ -382,8 +383,8 @@ __global__ void k_bwd_prep(int n, const uint32_t* __restrict__ counts, int C,
 constexpr int kFinThreads = 256;
 template <int CM>
 __global__ __launch_bounds__(kFinThreads) void k_finalize(
-    int n, const uint32_t* __restrict__ counts, const uint32_t* __restrict__ sfirst,
-    const Status* __restrict__ status, const float* __restrict__ pos,
+    int n, const uint32_t* __restrict__ counts, const float4* __restrict__ rec,
+    const unsigned long long* __restrict__ boff, const Status* __restrict__ status, const float* __restrict__ pos,
     const float* __restrict__ radius, SceneTable tab, float min_radius_px, int C,
     const float4* __restrict__ pslot, int ps4, float* __restrict__ grad_pos,
     float* __restrict__ grad_radius, float* __restrict__ grad_opacity,
@@ -414,10 +415,12 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
   const int i0 = blockIdx.x * kFinThreads;
   const int nloc = min(kFinThreads, n - i0);
   const int i = i0 + t;
-  // the tile count and the first slot are requested together (a sphere
-  // without tiles has no first slot; the value read is then unused)
+  // the first slot: the projection block's first emission position plus the
+  // in-block prefix in record word 3.w (a sphere without tiles has no record)
   const uint32_t count = t < nloc ? counts[i] : 0u;
-  const uint32_t base = t < nloc ? sfirst[i] : 0u;
+  const uint32_t base =
+      count != 0u ? uint32_t(boff[i / kProjectBlock]) + __float_as_uint(rec[4 * size_t(i) + 3].w)
+                  : 0u;
   s_cnt[t] = count;
   float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
   float go = 0.f, gk = 0.f, npx = 0.f;
@@ -472,6 +475,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
     if (grad_pos || grad_radius || camg) {
       float gx = g.x, gy = g.y, gz = g.z, gR = g.w;
       bool clamped = false, gated = false;
+      float cam_scale = 1.f;  // the paper's camera-gradient normalisation
       const CamDev cam = tab.scenes[find_scene(tab.sph_start, tab.B, uint32_t(i))].cam;
       if (count != 0u && (min_radius_px > 0.f || paper_norm)) {
         const float px = pos[3 * i + 0], py = pos[3 * i + 1], pz = pos[3 * i + 2];
@@ -491,8 +495,12 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
         const double reff = clamped ? rmin : double(radius[i]);
         const double rpx = cam.ortho ? reff / pitch : reff * double(cam.f) / (cz * pitch);
         gated = paper_norm && !(rpx > 3.0);
+        // camera gradients: each sphere's part over its projected disk area
+        // in pixels, times 1e-3 (App. B, normalisation)
+        if (paper_norm) cam_scale = float(1e-3 / (3.141592653589793 * rpx * rpx));
       }
-      if (camg) camg[i] = make_float4(gx, gy, gz, gk);
+      if (camg)
+        camg[i] = make_float4(gx * cam_scale, gy * cam_scale, gz * cam_scale, gk * cam_scale);
       if (grad_radius) grad_radius[i] = (clamped || gated) ? 0.f : gR * scale;
       // c = R p + t  =>  dL/dp = R^T dL/dc
       const float ps = gated ? 0.f : scale;
@@ -705,8 +713,8 @@ template <int CM>
 static void launch_finalize(const Plan& q, const BwdArgs& a, char* ws, hipStream_t stream,
                             uint32_t nfin, uint32_t nred) {
   hipLaunchKernelGGL((k_finalize<CM>), dim3(nfin + nred), dim3(kFinThreads), 0, stream, int(q.n),
-                     ws_ptr<uint32_t>(ws, q.off_counts), ws_ptr<uint32_t>(ws, q.off_sfirst),
-                     ws_ptr<Status>(ws, q.off_status), a.pos, a.radius, scene_table(q, ws),
+                     ws_ptr<uint32_t>(ws, q.off_counts), ws_ptr<float4>(ws, q.off_rec),
+                     ws_ptr<unsigned long long>(ws, q.off_boff), ws_ptr<Status>(ws, q.off_status), a.pos, a.radius, scene_table(q, ws),
                      a.min_radius_px, a.C, ws_ptr<float4>(ws, q.off_pslot), q.bwd_ps4, a.grad_pos,
                      a.grad_radius, a.grad_opacity, a.grad_payload, nfin,
                      ws_ptr<float>(ws, q.off_bgsum), a.grad_bg,
@@ -825,7 +833,8 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
   A.thr = ws_ptr<float2>(ws, q.off_thr);
   A.pslot = ws_ptr<float4>(ws, q.off_pslot);
   A.ps4 = q.bwd_ps4;
-  A.svals = ws_ptr<uint32_t>(ws, sorted_in_a(q) ? q.off_valsA : q.off_valsB);
+  A.svals = ws_ptr<uint32_t>(ws, q.off_vals);
+  A.last_sph = q.n > 0 ? uint32_t(q.n - 1) : 0u;
   A.grad_payload = a.grad_payload;
   A.C = a.C;
   A.need_geo = (a.grad_pos || a.grad_radius || a.grad_cam) ? 1 : 0;

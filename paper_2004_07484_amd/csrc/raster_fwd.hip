@@ -102,6 +102,7 @@ struct FwdKernelArgs {
   const uint4* tinfo;
   const uint32_t* mlist;
   const uint32_t* svals;            // sphere index of every sorted pair
+  uint32_t last_sph;                 // n - 1: sorted indices are clamped to it
   const float4* rec;                 // sphere records, 4 float4 per sphere
   const float* payload;              // the caller's payload rows [n, C]
   const unsigned long long* boff;    // first pair of each projection block
@@ -256,12 +257,13 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM)) void k_fwd_chunk
     // read in place; lanes past the end repeat the last pair, so every load
     // is unconditional. The next batch's sphere indices are requested with
     // this batch's records, so a batch costs one round trip after the first.
-    uint32_t sph_next = A.svals[min(beg + uint32_t(lane), end - 1u)];
+    uint32_t sph_next = min(A.svals[min(beg + uint32_t(lane), end - 1u)], A.last_sph);
     for (uint32_t b0 = beg; b0 < end; b0 += kWave) {
       const uint32_t j = b0 + uint32_t(lane);
       const bool valid = j < end;
       const uint32_t sph = sph_next;
-      if (b0 + kWave < end) sph_next = A.svals[min(j + uint32_t(kWave), end - 1u)];
+      if (b0 + kWave < end)
+        sph_next = min(A.svals[min(j + uint32_t(kWave), end - 1u)], A.last_sph);
       __syncthreads();  // previous batch done with s_rec / s_pay / s_mask
       const float4* rp = A.rec + 4 * size_t(sph);
 #pragma unroll
@@ -531,7 +533,8 @@ static FwdKernelArgs raster_args(const Plan& q, const std::vector<SceneDev>& sce
   A.desc = ws_ptr<uint4>(ws, q.off_desc);
   A.tinfo = ws_ptr<uint4>(ws, q.off_tinfo);
   A.mlist = ws_ptr<uint32_t>(ws, q.off_mlist);
-  A.svals = ws_ptr<uint32_t>(ws, sorted_in_a(q) ? q.off_valsA : q.off_valsB);
+  A.svals = ws_ptr<uint32_t>(ws, q.off_vals);
+  A.last_sph = q.n > 0 ? uint32_t(q.n - 1) : 0u;
   A.rec = ws_ptr<float4>(ws, q.off_rec);
   A.payload = a.payload;
   A.boff = ws_ptr<unsigned long long>(ws, q.off_boff);

@@ -42,17 +42,47 @@ def axis_angle_to_matrix_torch(r: torch.Tensor) -> torch.Tensor:
                             torch.stack([-k[1], k[0], zero])])
 
     eye = torch.eye(3, dtype=r.dtype, device=r.device)
-    if float(th2) < 1e-20:
+    if float(th2.detach()) < 1e-20:
         return eye + skew(r)
     th = torch.sqrt(th2)
     K = skew(r / th)
     return eye + torch.sin(th) * K + (1.0 - torch.cos(th)) * (K @ K)
 
 
+def rotation_6d_to_matrix(r6) -> list:
+    """The continuous 6D rotation parametrisation (Zhou et al., cited in
+    Sec. 4 for the camera vector): two 3-vectors a1, a2 are made orthonormal by
+    Gram-Schmidt, b1 = a1 / |a1|, b2 = (a2 - (b1 . a2) b1) / |.|, b3 = b1 x b2,
+    and R = [b1 b2 b3] by columns. On the host; returns a row-major 3x3 list."""
+    a1 = [float(v) for v in r6[0:3]]
+    a2 = [float(v) for v in r6[3:6]]
+    n1 = math.sqrt(sum(v * v for v in a1))
+    b1 = [v / n1 for v in a1]
+    d = sum(x * y for x, y in zip(b1, a2))
+    u = [y - d * x for x, y in zip(b1, a2)]
+    n2 = math.sqrt(sum(v * v for v in u))
+    b2 = [v / n2 for v in u]
+    b3 = [b1[1] * b2[2] - b1[2] * b2[1], b1[2] * b2[0] - b1[0] * b2[2],
+          b1[0] * b2[1] - b1[1] * b2[0]]
+    return [b1[0], b2[0], b3[0], b1[1], b2[1], b3[1], b1[2], b2[2], b3[2]]
+
+
+def rotation_6d_to_matrix_torch(r6: torch.Tensor) -> torch.Tensor:
+    """rotation_6d_to_matrix as differentiable torch operations: [6] -> [3, 3]."""
+    r6 = r6.reshape(6)
+    a1, a2 = r6[0:3], r6[3:6]
+    b1 = a1 / torch.linalg.vector_norm(a1)
+    u = a2 - (b1 * a2).sum() * b1
+    b2 = u / torch.linalg.vector_norm(u)
+    b3 = torch.linalg.cross(b1, b2)
+    return torch.stack([b1, b2, b3], dim=1)
+
+
 def camera_struct(cam, width: int, height: int, znear: float, zfar: float):
     """Accepts a pulsar_camera_t, an object with R, t, focal, sensor_width
-    (znear/zfar/width/height optional), or the 8-vector [t (3), axis-angle (3),
-    focal, sensor_width] of Lst. 1, read as x_cam = R(axis-angle) x_world + t."""
+    (znear/zfar/width/height optional), the 8-vector [t (3), axis-angle (3),
+    focal, sensor_width] of Lst. 1, read as x_cam = R(axis-angle) x_world + t,
+    or the 11-vector [t (3), 6D rotation (6), focal, sensor_width] (Sec. 4)."""
     if isinstance(cam, _capi.pulsar_camera_t):
         return cam
     if hasattr(cam, "R"):
@@ -60,10 +90,14 @@ def camera_struct(cam, width: int, height: int, znear: float, zfar: float):
                                  getattr(cam, "znear", znear), getattr(cam, "zfar", zfar),
                                  getattr(cam, "width", width), getattr(cam, "height", height))
     v = cam.detach().cpu().reshape(-1).tolist() if hasattr(cam, "detach") else list(cam)
-    if len(v) != 8:
-        raise ValueError("camera vector must be [t(3), axis-angle(3), focal, sensor_width]")
-    return _capi.make_camera(axis_angle_to_matrix(v[3:6]), v[0:3], v[6], v[7], znear, zfar,
-                             width, height)
+    if len(v) == 8:
+        return _capi.make_camera(axis_angle_to_matrix(v[3:6]), v[0:3], v[6], v[7], znear, zfar,
+                                 width, height)
+    if len(v) == 11:
+        return _capi.make_camera(rotation_6d_to_matrix(v[3:9]), v[0:3], v[9], v[10], znear,
+                                 zfar, width, height)
+    raise ValueError("camera vector must be [t(3), axis-angle(3), focal, sensor_width] or "
+                     "[t(3), 6D rotation(6), focal, sensor_width]")
 
 
 def _forward_into(pos, radius, opacity, payload, bg, cam, params, check: bool):
@@ -223,9 +257,10 @@ def render_batch(cams, counts, pos, radius, payload, opacity=None, bg=None, gamm
 class Renderer(torch.nn.Module):
     """Lst. 1 style renderer: Renderer(width, height, max_num_spheres)(pos, payload, radius, cam).
 
-    The camera is an 8-vector [t, axis-angle, focal, sensor_width] or an
-    object with R, t, focal and sensor_width; an 8-vector tensor that
-    requires grad receives dLoss/dcamera. ``max_depth`` is the far clip
+    The camera is an 8-vector [t, axis-angle, focal, sensor_width], an
+    11-vector [t, 6D rotation, focal, sensor_width] or an object with R, t,
+    focal and sensor_width; a vector tensor that requires grad receives
+    dLoss/dcamera. ``max_depth`` is the far clip
     zfar and ``min_depth`` the near clip znear of the depth mapping.
     ``min_radius_px=_capi.PULSAR_MIN_RADIUS_PX_PAPER`` draws every sphere at
     least one pixel large, as the paper does.
@@ -293,13 +328,17 @@ class Renderer(torch.nn.Module):
             # the 8-vector [t, axis-angle, focal, sensor_width] as differentiable
             # parts; the kernels get the same values
             v = cam.reshape(-1)
-            if v.numel() != 8:
+            if v.numel() == 8:
+                cam_tensors = (axis_angle_to_matrix_torch(v[3:6]), v[0:3], v[6], v[7])
+            elif v.numel() == 11:
+                cam_tensors = (rotation_6d_to_matrix_torch(v[3:9]), v[0:3], v[9], v[10])
+            else:
                 raise ValueError("camera vector must be [t(3), axis-angle(3), focal, "
-                                 "sensor_width]")
-            cam_tensors = (axis_angle_to_matrix_torch(v[3:6]), v[0:3], v[6], v[7])
+                                 "sensor_width] or [t(3), 6D rotation(6), focal, sensor_width]")
             Rv = cam_tensors[0].detach().cpu().reshape(9).tolist()
-            hv = v.detach().cpu().tolist()
-            cs = _capi.make_camera(Rv, hv[0:3], hv[6], hv[7], min_depth, max_depth, self.width,
+            hv = [float(cam_tensors[k].detach().cpu().reshape(-1)[j]) for k, j in
+                  ((1, 0), (1, 1), (1, 2), (2, 0), (3, 0))]
+            cs = _capi.make_camera(Rv, hv[0:3], hv[3], hv[4], min_depth, max_depth, self.width,
                                    self.height)
         else:
             cs = camera_struct(cam, self.width, self.height, min_depth, max_depth)

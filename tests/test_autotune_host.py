@@ -20,9 +20,9 @@ def test_cache_round_trip(tmp_path):
     path = str(tmp_path / "sub" / "tune.json")
     c = at.TuneCache(path)
     assert c.get("x") is None
-    c.put("x", {"raster_blocks": 2048, "chunk": 256, "depth_bits": 0}, 0.5)
+    c.put("x", {"raster_blocks": 2048, "chunk": 256}, 0.5)
     again = at.TuneCache(path)
-    assert again.get("x") == {"raster_blocks": 2048, "chunk": 256, "depth_bits": 0}
+    assert again.get("x") == {"raster_blocks": 2048, "chunk": 256}
     data = json.load(open(path))
     assert data["x"]["ms"] == 0.5
     # a corrupt file reads as empty instead of failing
@@ -35,7 +35,7 @@ def test_with_knobs_keeps_other_fields():
     q = at.with_knobs(p, {"chunk": 256, "raster_blocks": 8192})
     assert (q.gamma, q.eps, q.K, q.max_pairs) == (p.gamma, p.eps, p.K, p.max_pairs)
     assert (q.chunk, q.raster_blocks, p.chunk, p.raster_blocks) == (256, 8192, 0, 0)
-    assert at.knobs_of(q) == {"raster_blocks": 8192, "chunk": 256, "depth_bits": 0}
+    assert at.knobs_of(q) == {"raster_blocks": 8192, "chunk": 256}
 
 
 def test_coordinate_search_finds_separable_optimum():
@@ -43,12 +43,13 @@ def test_coordinate_search_finds_separable_optimum():
 
     def cost(k):
         calls.append(dict(k))
-        if k["depth_bits"] == 8:
+        if k["chunk"] == 1024:
             return None  # rejected by the library for this workload
         return abs(k["raster_blocks"] - 8192) / 1000 + abs(k["chunk"] - 256) / 100 + 1.0
 
-    best, ms, trials = at.search(cost, {"raster_blocks": 0, "chunk": 0, "depth_bits": 0})
-    assert best == {"raster_blocks": 8192, "chunk": 256, "depth_bits": 0}
+    knobs = (("raster_blocks", (1024, 4096, 8192)), ("chunk", (64, 256, 1024)))
+    best, ms, trials = at.search(cost, {"raster_blocks": 0, "chunk": 0}, knobs)
+    assert best == {"raster_blocks": 8192, "chunk": 256}
     assert ms == 1.0
     assert len(trials) == len(calls)
     assert any(m is None for _, m in trials)
@@ -57,4 +58,4 @@ def test_coordinate_search_finds_separable_optimum():
 def test_search_rejects_invalid_start():
     import pytest
     with pytest.raises(ValueError):
-        at.search(lambda k: None, {"raster_blocks": 0, "chunk": 0, "depth_bits": 0})
+        at.search(lambda k: None, {"raster_blocks": 0, "chunk": 0})

@@ -101,7 +101,8 @@ def test_bad_camera_is_rejected(cam_kw):
     (dict(K=0), _capi.PULSAR_ERR_INVALID_ARGUMENT),
     (dict(K=33), _capi.PULSAR_ERR_INVALID_ARGUMENT),
     (dict(max_pairs=-5), _capi.PULSAR_ERR_INVALID_ARGUMENT),
-    (dict(depth_bits=17), _capi.PULSAR_ERR_INVALID_ARGUMENT),
+    (dict(depth_bits=17), _capi.PULSAR_ERR_UNSUPPORTED),
+    (dict(depth_bits=8), _capi.PULSAR_ERR_UNSUPPORTED),
     (dict(chunk=32), _capi.PULSAR_ERR_INVALID_ARGUMENT),
     (dict(chunk=100), _capi.PULSAR_ERR_INVALID_ARGUMENT),
     (dict(chunk=2048), _capi.PULSAR_ERR_INVALID_ARGUMENT),
@@ -204,6 +205,7 @@ print("RC", rc, lib.pulsar_last_hip_error().decode())
     if "HAS_GPU" in out.stdout:
         pytest.skip("a GPU is present; this checks the no-device path")
     assert f"RC {_capi.PULSAR_ERR_HIP}" in out.stdout, out.stdout + out.stderr
+
 
 
 # ---------------------------------------------------------------- batched calls

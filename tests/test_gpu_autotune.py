@@ -41,7 +41,7 @@ def test_renderer_autotune_matches_untuned(tmp_path):
     data = json.load(open(path))
     assert len(data) == 1
     entry = next(iter(data.values()))
-    assert set(entry["knobs"]) == {"raster_blocks", "chunk", "depth_bits"}
+    assert set(entry["knobs"]) == {"raster_blocks", "chunk"}
     assert entry["ms"] > 0
     # a second renderer reads the cached choice instead of measuring again
     again = Renderer(cam.width, cam.height, n, n_channels=C, K=par.K, autotune=True,
@@ -56,9 +56,9 @@ def test_batched_autograd_matches_single_scene_autograd():
     from paper_2004_07484_amd.renderer import PulsarFunction, render_batch
     wls = [sg.tiny_scene(600 + b, n=8 + 3 * b, C=3, W=24 + 8 * b, H=20 + 4 * b) for b in range(3)]
     par = sg.Params(gamma=0.3, eps=1e-5, K=4)
-    # a fixed depth key width gives both calls the same tile-list order, so
-    # the images must agree bitwise
-    ps = _capi.make_params(par.gamma, par.eps, 0.0, par.K, depth_bits=8)
+    # both calls list every tile's spheres in index order, so the images must
+    # agree bitwise
+    ps = _capi.make_params(par.gamma, par.eps, 0.0, par.K)
     dev = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda:0")
     cat = lambda f: dev(np.concatenate([f(w) for w in wls]))
     pos = cat(lambda w: w.scene.pos).requires_grad_()

@@ -84,18 +84,18 @@ def _cfg4_batch(extra=True):
 
 def test_batched_equals_looped_uneven_batch():
     """The 32-scene uneven batch (1k-500k spheres, 256^2-1024^2, random
-    cameras) plus a ragged and an empty scene: with a fixed depth key width
-    every tile list has the same order in both calls, so the forward is
-    bitwise equal to per-scene calls; gradients agree to float atomic order."""
+    cameras) plus a ragged and an empty scene: every tile list holds its
+    spheres in index order in both calls, so the forward is bitwise equal to
+    per-scene calls; gradients agree to float summation order."""
     wls = _cfg4_batch()
     par = wls[0].params
     Gs = [sg.upstream_grad(1000 + b, w.camera.height, w.camera.width, 3)
           for b, w in enumerate(wls)]
     _say(f"[batched] uneven batch of {len(wls)} scenes, {sum(w.scene.n for w in wls)} spheres")
-    outs = gpu_render_batch(wls, par, Gs, depth_bits=8)
+    outs = gpu_render_batch(wls, par, Gs)
     for b, (wl, G, out) in enumerate(zip(wls, Gs, outs)):
         assert out["status"] == _capi.PULSAR_OK
-        one = gpu_render(wl.scene, wl.camera, par, G, depth_bits=8)
+        one = gpu_render(wl.scene, wl.camera, par, G)
         assert np.array_equal(out["F"], one["F"]), b
         assert np.array_equal(out["L"], one["L"]), b
         for key in ["grad_pos", "grad_radius", "grad_opacity", "grad_payload", "grad_bg"]:

@@ -171,3 +171,60 @@ def test_renderer_camera_vector_gradient():
     scale = np.concatenate([g["grad_camera_abs"][9:12], np.abs(J).T @ g["grad_camera_abs"][0:9],
                             g["grad_camera_abs"][12:14]])
     assert_camera_close(got, want, scale, "Renderer camera vector")
+
+
+@pytest.mark.parametrize("case", ["rotated", "min_radius"])
+def test_paper_normalised_camera_gradients(case):
+    """PULSAR_GRAD_PAPER_NORM on pulsar_bwd_camera: each sphere's part of the
+    camera gradient scaled by 1e-3 over its projected disk area, beside the
+    averaged and gated scene gradients (oracle paper_normalised)."""
+    wl = sg.config1()
+    par = wl.params
+    if case == "rotated":
+        sc, cam = _rotated(wl, 3)
+    else:
+        sc, cam = wl.scene, wl.camera
+        par = sg.Params(gamma=par.gamma, eps=par.eps, min_radius_px=0.9, K=par.K)
+    _say(f"[camera] paper normalisation, {case}")
+    fwd = ref.forward(sc, cam, par)
+    G = masked_G(sg.upstream_grad(501, cam.height, cam.width, sc.C), None, fwd["ambiguous"])
+    out = gpu_render(sc, cam, par, G, camera_grad=True, bwd_flags=_capi.PULSAR_GRAD_PAPER_NORM)
+    assert out["status"] == _capi.PULSAR_OK
+    pn = ref.paper_normalised(sc, cam, par, fwd, ref.backward(sc, cam, par, G, fwd))
+    compare_grads(out, pn, f"paper norm {case}")
+    assert_camera_close(out["grad_camera"], pn["grad_camera"], pn["grad_camera_abs"],
+                        f"paper norm {case} camera")
+
+
+def test_renderer_6d_camera_vector_gradient():
+    """Renderer with the 11-vector camera [t, 6D rotation, focal,
+    sensor_width] requiring grad: its gradient is the oracle's dLoss/d(R, t,
+    f, s) chained through the 6D parametrisation (Jacobian in FP64 on the
+    CPU)."""
+    import torch
+    from paper_2004_07484_amd.renderer import Renderer, rotation_6d_to_matrix_torch
+    wl = sg.config1()
+    sc, par = wl.scene, wl.params
+    vec = np.array([0.05, -0.1, 0.3, 0.98, 0.1, -0.12, -0.08, 0.97, 0.15, wl.camera.focal,
+                    wl.camera.sensor_width], np.float32)
+    cam_v = torch.tensor(vec, device="cuda:0", requires_grad=True)
+    R32 = rotation_6d_to_matrix_torch(cam_v.detach()[3:9]).cpu().numpy().astype(np.float32)
+    cam = copy.deepcopy(wl.camera)
+    cam.R, cam.t = R32, vec[0:3].copy()
+    fwd = ref.forward(sc, cam, par)
+    Gm = masked_G(sg.upstream_grad(92, cam.height, cam.width, sc.C), None, fwd["ambiguous"])
+    g = ref.backward(sc, cam, par, Gm, fwd)
+    r = Renderer(cam.width, cam.height, sc.n, n_channels=sc.C, K=par.K)
+    img = r(to_dev(sc.pos), to_dev(sc.payload), to_dev(sc.radius), cam_v,
+            opacity=to_dev(sc.opacity), gamma=par.gamma, max_depth=cam.zfar,
+            min_depth=cam.znear, bg=to_dev(sc.bg))
+    img.backward(to_dev(Gm))
+    got = cam_v.grad.cpu().numpy()
+    r6 = torch.tensor(vec[3:9].astype(np.float64))
+    J = torch.autograd.functional.jacobian(lambda a: rotation_6d_to_matrix_torch(a).reshape(9),
+                                           r6).numpy()  # [9, 6]
+    want = np.concatenate([g["grad_camera"][9:12], J.T @ g["grad_camera"][0:9],
+                           g["grad_camera"][12:14]])
+    scale = np.concatenate([g["grad_camera_abs"][9:12], np.abs(J).T @ g["grad_camera_abs"][0:9],
+                            g["grad_camera_abs"][12:14]])
+    assert_camera_close(got, want, scale, "Renderer 6D camera vector")

@@ -340,6 +340,61 @@ def test_camera_gradients_match_finite_differences(seed, rotate, min_radius_px):
         abs(cam.focal * an[12]) + 1e-300)
 
 
+def test_camera_gradient_parts_per_sphere_and_area_normalisation():
+    """Each sphere's part of the camera gradient: with spheres whose images do
+    not overlap, every pixel sees one sphere at most, so the loss is a sum of
+    one term per sphere and sphere k's part equals the FP64 central
+    differences of the camera for a scene holding sphere k alone (the parts
+    also add up to the total). The paper-normalised camera gradient scales
+    each part by 1e-3 over the sphere's projected disk area pi rpx^2 (App. B,
+    normalisation of the camera gradients), rpx = R f / (c_z pitch), which
+    the number of pixel centres the larger sphere covers confirms."""
+    rng = np.random.default_rng(17)
+    cam = sg.identity_camera(40, 36, focal=1.2, sensor_width=2.0)
+    pitch = cam.sensor_width / cam.width
+    # three spheres apart in the image, at different depths, one large
+    pos = np.array([[-0.45, -0.35, 3.2], [0.5, 0.3, 4.5], [0.02, 0.03, 3.8]])
+    radius = np.array([0.12, 0.09, 0.35])
+    C = 2
+    sc = types.SimpleNamespace(pos=pos, radius=radius, opacity=rng.uniform(0.4, 1.0, 3),
+                               payload=rng.uniform(-1, 1, (3, C)), bg=np.array([0.1, -0.2]))
+    params = sg.Params(gamma=0.4, eps=1e-5, K=4)
+    fwd = ref.forward(sc, cam, params)
+    assert fwd["nhits"].max() == 1  # no pixel sees two spheres
+    G = sg.upstream_grad(18, cam.height, cam.width, C).astype(np.float64)
+    g = ref.backward(sc, cam, params, G, fwd)
+    parts = g["grad_camera_sphere"]
+    np.testing.assert_allclose(parts.sum(0), g["grad_camera"], rtol=1e-12,
+                               atol=1e-12 * np.abs(parts).sum())
+    fd_parts = []
+    for k in range(3):
+        one = types.SimpleNamespace(pos=pos[k:k + 1], radius=radius[k:k + 1],
+                                    opacity=sc.opacity[k:k + 1], payload=sc.payload[k:k + 1],
+                                    bg=sc.bg)
+        fd = fd_camera_grads(one, cam, params, G)
+        scale = np.abs(fd).max()
+        assert np.all(np.abs(parts[k] - fd) <= 2e-6 * np.maximum(np.abs(fd), 1e-4 * scale)), \
+            (k, parts[k].tolist(), fd.tolist())
+        fd_parts.append(fd)
+    pn = ref.paper_normalised(sc, cam, params, fwd, g)
+    rpx = pn["projected_radius_px"]
+    np.testing.assert_allclose(rpx, radius * cam.focal / (pos[:, 2] * pitch), rtol=1e-12)
+    covered = int(fwd["nhits"].sum())  # every hit pixel belongs to one sphere
+    big = int(np.argmax(rpx))
+    mask = np.zeros_like(fwd["nhits"], bool)
+    for i in range(cam.height):
+        for j in range(cam.width):
+            mask[i, j] = ref.pixel_hits(sc, cam, params, i, j)["hit"][big]
+    assert covered >= mask.sum() > 0
+    assert abs(mask.sum() - np.pi * rpx[big] ** 2) <= 0.1 * np.pi * rpx[big] ** 2 + \
+        2 * np.pi * rpx[big], (int(mask.sum()), rpx[big])
+    want = sum(1e-3 / (np.pi * rpx[k] ** 2) * fd_parts[k] for k in range(3))
+    scale = np.abs(want).max()
+    assert np.all(np.abs(pn["grad_camera"] - want) <= 2e-6 * np.maximum(np.abs(want),
+                                                                        1e-4 * scale))
+    np.testing.assert_array_equal(pn["grad_bg"], g["grad_bg"])
+
+
 def test_camera_pose_gradient_is_the_rotated_position_sum():
     """Moving the camera by dt moves every centre by dt in camera space, the
     same as moving every sphere by R^T dt: dLoss/dt = R sum_i dLoss/dp_i, and
