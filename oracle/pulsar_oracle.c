@@ -62,6 +62,7 @@ typedef struct {
 typedef struct {
   double c[3];  /* camera-space centre */
   double R;     /* effective radius */
+  float tmin;   /* earliest possible hit distance |c| - R (c_z - R orthographic), in float */
   int take_part;
   int clamped;  /* effective radius comes from the minimum size */
 } sphere_cam_t;
@@ -71,6 +72,7 @@ typedef struct {
   int k;
   int is_hit;     /* 1: a hit; 0: a near miss kept only for the ambiguity flag */
   int uncertain;  /* within rounding distance of the silhouette or the far plane */
+  float tmin;     /* the sphere's earliest possible hit distance (early stop order) */
 } hit_key_t;
 
 static void make_camera(camera_t* cam, const double* c16, int W, int H) {
@@ -121,6 +123,12 @@ static void sphere_to_camera(const camera_t* cam, const double* pos, double r, d
                            : min_radius_px * cam->pitch * sc->c[2] / cam->f;
   sc->clamped = (min_radius_px > 0.0) && (rmin > r);
   sc->R = sc->clamped ? rmin : r;
+  /* no ray meets the sphere before its nearest point: |c| - R from the
+     camera centre, c_z - R from the orthographic sensor plane */
+  sc->tmin = cam->ortho ? (float)(sc->c[2] - sc->R)
+                        : (float)(sqrt(sc->c[0] * sc->c[0] + sc->c[1] * sc->c[1] +
+                                       sc->c[2] * sc->c[2]) -
+                                  sc->R);
   int finite = isfinite(pos[0]) && isfinite(pos[1]) && isfinite(pos[2]) && isfinite(r) &&
                isfinite(o);
   sc->take_part = finite && r > 0.0 && (sc->c[2] - sc->R >= cam->znear);
@@ -164,6 +172,15 @@ static int near_miss(const camera_t* cam, const double u[3], const double o[3],
   return 1;
 }
 
+/* order of the early stop: earliest possible hit distance (in float), then index */
+static int cmp_tmin(const void* pa, const void* pb) {
+  const hit_key_t* a = (const hit_key_t*)pa;
+  const hit_key_t* b = (const hit_key_t*)pb;
+  if (a->tmin < b->tmin) return -1;
+  if (a->tmin > b->tmin) return 1;
+  return (a->k > b->k) - (a->k < b->k);
+}
+
 static int cmp_hit(const void* pa, const void* pb) {
   const hit_key_t* a = (const hit_key_t*)pa;
   const hit_key_t* b = (const hit_key_t*)pb;
@@ -195,13 +212,27 @@ static sphere_cam_t* transform_all(const camera_t* cam, int n, const double* pos
  * amb_rel of the silhouette (1 - q/R < amb_rel or a miss by less than
  * amb_rel R) or of the far plane. It only serves the parity harness.
  * Entries of rows that are not listed are left untouched.
+ *
+ * Early stop (stop_share > 0; Sec. 3.2 and App. B, Step 2): the hits of a
+ * pixel are taken in ascending order of their sphere's earliest possible hit
+ * distance (float32, then index), the order of the paper's device-wide depth
+ * sort. Before a hit is blended, the largest weight any sphere starting at
+ * that depth could have, exp(z(t_min) / gamma) (opacity <= 1 and d <= 1), is
+ * compared with the running denominator D of Eq. 1: if it is below
+ * stop_share / (1 - stop_share) D, no such sphere can reach a share of
+ * stop_share of the pixel, and this hit and every later one are skipped.
+ * Only the blended hits enter F, L, nhits and the K nearest. A pixel whose
+ * decision lies within 1e-3 (natural-log units, relative above 1) of the
+ * threshold is flagged ambiguous.
  */
 int oracle_forward(int n, int C, const double* pos, const double* radius, const double* opacity,
                    const double* payload, const double* bg, const double* cam16, int W, int H,
                    double gamma, double eps, double min_radius_px, int K, double amb_rel,
                    int n_rows, const int* rows, double* F, double* L, int* nhits,
                    double* klist_t, int* klist_id, double* t_next, uint8_t* ambiguous,
-                   int n_threads, int blend_topk) {
+                   int n_threads, int blend_topk, double stop_share) {
+  if (stop_share < 0.0 || stop_share >= 1.0 || (stop_share > 0.0 && blend_topk))
+    return ORACLE_BAD_ARG;
   if (n < 0 || C < 1 || W < 1 || H < 1 || K < 1 || !(gamma > 0.0)) return ORACLE_BAD_ARG;
   if (n > 0 && (!pos || !radius || !payload)) return ORACLE_BAD_ARG;
   if (opacity)
@@ -235,6 +266,7 @@ int oracle_forward(int n, int C, const double* pos, const double* radius, const 
         if (ray_sphere(&cam, u, ro, &sc[k], &t, &q, &b, d)) {
           hits[nh].t = t;
           hits[nh].k = k;
+          hits[nh].tmin = sc[k].tmin;
           hits[nh].is_hit = 1;
           hits[nh].uncertain = (1.0 - q / sc[k].R < amb_rel) || (t > cam.zfar * (1.0 - amb_rel));
           ++nh;
@@ -257,6 +289,34 @@ int oracle_forward(int n, int C, const double* pos, const double* radius, const 
           double s = o * ((cam.zfar - hits[h].t) / (cam.zfar - cam.znear)) / gamma;
           if (s > m) m = s;
         }
+      }
+      /* early stop: walk the hits in the order of the depth sort, keeping the
+         log of the running denominator; drop the stopping hit and the rest */
+      int stop_amb = 0;
+      if (stop_share > 0.0 && nh > 0) {
+        qsort(hits, (size_t)nh, sizeof(hit_key_t), cmp_tmin);
+        const double span = cam.zfar - cam.znear;
+        const double lrho = log(stop_share / (1.0 - stop_share));
+        double Lc = eps / gamma; /* log of the background weight */
+        m = eps / gamma;
+        nb = 0;
+        for (int h = 0; h < nh; ++h) {
+          const int k = hits[h].k;
+          const double bound = (cam.zfar - (double)hits[h].tmin) / span / gamma;
+          const double thr = lrho + Lc;
+          if (fabs(bound - thr) < 1e-3 * fmax(1.0, fabs(thr))) stop_amb = 1;
+          if (bound < thr) break;
+          double t = 0.0, q = 0.0, b = 0.0, d[3];
+          ray_sphere(&cam, u, ro, &sc[k], &t, &q, &b, d);
+          const double o = opacity ? opacity[k] : 1.0;
+          const double lw = log(o * (1.0 - q / sc[k].R)) + o * ((cam.zfar - t) / span) / gamma;
+          /* log(exp(Lc) + exp(lw)) */
+          if (lw > -INFINITY) Lc = lw > Lc ? lw + log1p(exp(Lc - lw)) : Lc + log1p(exp(lw - Lc));
+          const double s = o * ((cam.zfar - t) / span) / gamma;
+          if (s > m) m = s;
+          ++nb;
+        }
+        nh = nb; /* the skipped hits take no part in anything below */
       }
       /* near misses go after the hits; the blend below reads only hits[0 .. nb) */
       int nall = nh;
@@ -308,7 +368,7 @@ int oracle_forward(int n, int C, const double* pos, const double* radius, const 
         klist_id[p * K + r] = -1;
       }
       t_next[p] = tk1;
-      int amb = (nh > K) && (tk1 - tk < amb_rel * tk);
+      int amb = stop_amb || ((nh > K) && (tk1 - tk < amb_rel * tk));
       if (nall > K)
         for (int h = 0; h <= K && h < nall; ++h) amb |= hits[h].uncertain;
       ambiguous[p] = (uint8_t)amb;

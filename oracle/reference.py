@@ -38,7 +38,7 @@ def _load():
             ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int,
             ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
             ctypes.c_double, ctypes.c_int, _ip, _dp, _dp, _ip, _dp, _ip, _dp, _u8p,
-            ctypes.c_int, ctypes.c_int]
+            ctypes.c_int, ctypes.c_int, ctypes.c_double]
         lib.oracle_backward.restype = ctypes.c_int
         lib.oracle_backward.argtypes = [
             ctypes.c_int, ctypes.c_int, _dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_int,
@@ -81,6 +81,9 @@ def forward(scene, cam, params, rows: Optional[Sequence[int]] = None,
     """F [H,W,C], L [H,W], nhits, klist_t/klist_id [H,W,K], t_next, ambiguous.
     blend_topk: blend only each pixel's K nearest hits (the other reading of
     the role of K; the backward formulas are then its exact derivative).
+    params.stop_share (default 0): the early stop of Sec. 3.2 / App. B with
+    that share threshold (the oracle C file states the rule); nhits and the
+    K nearest then count the blended hits only.
 
     Rows that are not listed hold NaN in F and L and -1 in nhits.
     """
@@ -103,7 +106,8 @@ def forward(scene, cam, params, rows: Optional[Sequence[int]] = None,
                             float(params.eps), float(params.min_radius_px), K,
                             AMBIGUITY_REL, nr, _ptr(r, _ip), _ptr(F), _ptr(L), _ptr(nh, _ip),
                             _ptr(kt), _ptr(kid, _ip), _ptr(tn), _ptr(amb, _u8p),
-                            int(n_threads), int(bool(blend_topk)))
+                            int(n_threads), int(bool(blend_topk)),
+                            float(getattr(params, "stop_share", 0.0)))
     if rc != 0:
         raise ValueError(f"oracle_forward failed with code {rc}")
     return dict(F=F, L=L, nhits=nh, klist_t=kt, klist_id=kid, t_next=tn,

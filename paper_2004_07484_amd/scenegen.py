@@ -66,6 +66,7 @@ class Params:
     eps: float = 1e-5
     min_radius_px: float = 0.0
     K: int = 8
+    stop_share: float = 0.0  # early stop threshold (0 = every hit blends)
 
 
 @dataclasses.dataclass

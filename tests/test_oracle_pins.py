@@ -715,3 +715,106 @@ def test_exact_depth_ties_break_by_sphere_index():
                 assert ids.index(0) + 1 == ids.index(3)
                 both += 1
     assert both > 3
+
+
+# ---------------------------------------------------------------- early stop
+
+def _early_stop_brute(sc, cam, gamma, eps, s):
+    """Early stop written out with numpy, independent of the oracle: per
+    pixel the pinhole ray test, the hits ordered by (float32(|c| - R), index),
+    and the walk that stops at the first hit whose largest possible weight
+    exp(z(|c| - R) / gamma) is below s / (1 - s) of the running denominator.
+    Returns F, L, the blended count and, per pixel, the exact weights and
+    shares of the skipped hits."""
+    H, W = cam.height, cam.width
+    C = sc.payload.shape[1]
+    pitch = cam.sensor_width / W
+    c = np.asarray(sc.pos, np.float64)  # identity camera
+    R = np.asarray(sc.radius, np.float64)
+    o = np.asarray(sc.opacity, np.float64)
+    tmin = (np.linalg.norm(c, axis=1) - R).astype(np.float32)
+    span = cam.zfar - cam.znear
+    F = np.zeros((H, W, C))
+    L = np.zeros((H, W))
+    nb = np.zeros((H, W), int)
+    skipped = []
+    for i in range(H):
+        for j in range(W):
+            v = np.array([(j + 0.5) * pitch - cam.sensor_width / 2,
+                          (i + 0.5) * pitch - cam.sensor_width * H / W / 2, cam.focal])
+            u = v / np.linalg.norm(v)
+            b = c @ u
+            q = np.sqrt(np.maximum((c * c).sum(1) - b * b, 0.0))
+            t = b - np.sqrt(np.maximum(R * R - q * q, 0.0))
+            hit = (q < R) & (t <= cam.zfar) & (c[:, 2] - R >= cam.znear)
+            ks = sorted(np.nonzero(hit)[0], key=lambda k: (tmin[k], k))
+            lw = np.log(o * np.maximum(1 - q / R, 1e-300)) + o * (cam.zfar - t) / span / gamma
+            logs = [eps / gamma]
+            used = []
+            for k in ks:
+                bound = (cam.zfar - float(tmin[k])) / span / gamma
+                if bound < np.log(s / (1 - s)) + np.logaddexp.reduce(logs):
+                    break
+                logs.append(lw[k])
+                used.append(k)
+            Lp = np.logaddexp.reduce(logs)
+            w = np.exp(np.array(logs) - Lp)
+            F[i, j] = w[0] * sc.bg + (w[1:, None] * sc.payload[used]).sum(0)
+            L[i, j] = Lp
+            nb[i, j] = len(used)
+            rest = [k for k in ks if k not in used]
+            skipped.append([(np.exp(lw[k]), np.exp(lw[k]) / (np.exp(Lp) + np.exp(lw[k])))
+                            for k in rest])
+    return F, L, nb, skipped
+
+
+def _early_stop_scene():
+    """Spheres stacked in depth over one image region, so near ones dominate
+    and far ones fall below the share."""
+    rng = np.random.default_rng(41)
+    n = 30
+    z = rng.uniform(2.0, 9.0, n)
+    xy = rng.uniform(-0.2, 0.2, (n, 2)) * z[:, None] / 3.0
+    sc = types.SimpleNamespace(pos=np.column_stack([xy, z]),
+                               radius=rng.uniform(0.3, 0.6, n) * z / 3.0,
+                               opacity=rng.uniform(0.5, 1.0, n),
+                               payload=rng.standard_normal((n, 2)), bg=np.array([0.2, -0.3]))
+    cam = sg.identity_camera(20, 18, focal=2.0)
+    return sc, cam
+
+
+def test_early_stop_matches_brute_force_and_bounds_the_skipped_share():
+    """Sec. 3.2 / App. B early stop: the oracle equals an independent brute
+    force (image, log-normaliser, blended counts), and every skipped hit's
+    share of its pixel, w / (D + w) with D the final denominator, is below
+    the threshold: no farther sphere could have reached it."""
+    sc, cam = _early_stop_scene()
+    s = 0.03
+    params = sg.Params(gamma=0.08, eps=1e-5, K=20, stop_share=s)
+    out = ref.forward(sc, cam, params)
+    F, L, nb, skipped = _early_stop_brute(sc, cam, params.gamma, params.eps, s)
+    np.testing.assert_allclose(out["F"], F, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(out["L"], L, rtol=1e-12)
+    np.testing.assert_array_equal(out["nhits"], nb)
+    shares = [sh for px in skipped for _, sh in px]
+    assert len(shares) > 50  # the stop happens, and often
+    assert max(shares) < s
+    exact = ref.forward(sc, cam, sg.Params(gamma=0.08, eps=1e-5, K=20))
+    assert (exact["nhits"] > out["nhits"]).sum() > 20
+    # a share of zero keeps every hit: exactly the plain blend
+    zero = ref.forward(sc, cam, sg.Params(gamma=0.08, eps=1e-5, K=20, stop_share=0.0))
+    assert np.array_equal(zero["F"], exact["F"]) and np.array_equal(zero["L"], exact["L"])
+
+
+def test_early_stop_gradients_match_finite_differences():
+    """With the stop decisions fixed (pixels near a decision carry no
+    upstream gradient), the backward over the blended hits is the derivative
+    of the early-stopped image: FP64 central differences."""
+    sc, cam = _early_stop_scene()
+    params = sg.Params(gamma=0.08, eps=1e-5, K=20, stop_share=0.03)
+    fwd = ref.forward(sc, cam, params)
+    G = sg.upstream_grad(43, cam.height, cam.width, 2).astype(np.float64)
+    G[fwd["ambiguous"]] = 0.0
+    an = ref.backward(sc, cam, params, G, fwd)
+    fd = fd_grads(sc, cam, params, G)
+    _assert_grads_close(an, fd, rtol=1e-5, floor_frac=1e-3)
