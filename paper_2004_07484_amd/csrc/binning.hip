@@ -4,142 +4,402 @@
 //
 // The paper sorts all spheres by earliest possible depth and then filters
 // them per image region. The blend of Eq. 1 is a sum and does not need depth
-// order, so here the pairs are placed by a counting sort on the tile number:
-//   K2 k_bin_count   bin block g (a run of S spheres) counts its pairs per tile
-//                    in LDS and writes row g of the count matrix [G, T]; it
-//                    also writes the first emission position of each of its
-//                    projection blocks (the sphere-major pair numbering)
-//   K3 k_bin_scan    per tile, the exclusive prefix of the counts over g
-//                    (in place); the block that finishes last scans the tile
-//                    totals into tile ranges and emits the work items
-//   K4 k_bin_scatter block g places its pairs: rank inside its (g, tile) cell
-//                    from wave ballots and per-wave counts packed into one
-//                    64-bit LDS word per tile, so the order is deterministic
-// The matrix is sliced by tiles (kBinSlice tiles per block of K2 / K4) so
-// its LDS fits whatever the number of tiles.
+// order, so here the pairs are sorted by tile number only, with a stable LSD
+// radix sort that keeps every tile's spheres in index order:
+//   k_emit          per block of spheres: their pairs in sphere-major order (a
+//                   sphere's first pair sits at the sum of the tile counts of
+//                   the spheres before it), the first digit's counts, and the
+//                   first pair of each projection block
+//   k_sort_hist     the counts of a later digit over blocks of the previous
+//                   pass's output
+//   k_sort_scatter  one stable pass: each block first derives its digits'
+//                   offsets from the digit-major block x digit count matrix
+//                   (a few hundred KB at most, read from L2 by every block,
+//                   which saves a scan launch), then ranks its pairs among
+//                   equal digits with wave ballots and per-wave LDS counts
+//   k_ranges        each tile's [first, end) from the boundaries of the
+//                   sorted keys; it also publishes the pair count and the
+//                   capacity status
+//   k_plan          each tile's work items; the list, the partial-state
+//                   slots and the merge list are allocated per wave with
+//                   atomics, a tile's slots contiguous, so what is computed
+//                   does not depend on the allocation order
 #include "device_common.h"
 #include "pulsar_internal.h"
 
 namespace pulsar {
 
-// The tiles of a sphere's tile rectangle in row-major order have increasing
-// tile numbers, so those inside a slice [t0, t1) form one run of that
-// enumeration, [e0, e0 + nin). The same enumeration index is the pair's
-// place after the sphere's first emission position.
-struct RectRun {
-  uint32_t e0, nin, w;  // first index in the slice, tiles in the slice, rectangle width
+constexpr int kSortThreads = 1024;
+constexpr int kSortWaves = kSortThreads / kWave;
+constexpr int kMaxDigits = 1 << kMaxDigitBits;
+static_assert(kEmitRound / kProjectBlock == kEmitThreads / kWave,
+              "one wave of an emission round covers one projection block");
+static_assert(kEmitThreads == kSortThreads, "the scans below assume one block size");
+static_assert(kMaxSortBlocks <= 4 * kWave, "a wave reads a count-matrix row in one load");
+
+// Rows of the count matrix (one per digit, one entry per block) are padded
+// to a multiple of 4 entries, so a wave reads a row with one 16-byte load per
+// lane.
+__host__ __device__ __forceinline__ uint32_t mat_stride(uint32_t nb) { return (nb + 3u) & ~3u; }
+
+// Exclusive block-wide scan of one value per thread (kSortThreads threads);
+// returns the prefix and leaves the total in *total. Uses s_w[kSortWaves].
+template <typename V>
+__device__ __forceinline__ V block_excl_scan(V v, V* s_w, V* total) {
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
+  V incl = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const V o = __shfl_up(incl, off, kWave);
+    if (lane >= off) incl += o;
+  }
+  __syncthreads();  // earlier users of s_w are done
+  if (lane == kWave - 1) s_w[wid] = incl;
+  __syncthreads();
+  V before = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kSortWaves; ++w) {
+    const V x = s_w[w];
+    if (w < wid) before += x;
+    tot += x;
+  }
+  *total = tot;
+  return before + incl - v;
+}
+
+// ---------------------------------------------------------------- emission
+struct EmitArgs {
+  int n;
+  const uint32_t* counts;
+  const ushort4* trect;
+  const unsigned long long* partials;  // pairs per projection block
+  SceneTable tab;
+  int rounds, nblk, nblk_proj;
+  uint32_t T;
+  long long cap;
+  int digit_bits;  // first digit's width (0: a single tile, nothing to sort)
+  uint32_t* keys;
+  uint32_t* vals;
+  unsigned long long* boff;   // [nblk_proj] first pair of each projection block
+  unsigned long long* ebase;  // [nblk + 1] first pair of each emission block
+  uint32_t* mat;              // [2^digit_bits][nblk] first digit's counts
+  uint2* trange;              // [T] cleared here for k_ranges
 };
 
-__device__ __forceinline__ uint32_t tiles_below(const ushort4& tr, uint32_t tile0,
-                                                uint32_t tiles_x, uint32_t t) {
-  // tiles of the rectangle with number < t
-  const uint32_t w = uint32_t(tr.z) - tr.x + 1u;
-  uint32_t below = 0;
-  for (uint32_t ty = tr.y; ty <= tr.w; ++ty) {
-    const uint32_t first = tile0 + ty * tiles_x + tr.x;
-    if (t <= first) break;  // later rows start even higher
-    below += min(w, t - first);
+// Block b covers spheres b S .. b S + S - 1 (S = rounds kEmitRound) in rounds
+// of kEmitRound; thread k of a round owns 4 consecutive spheres, so wave w
+// covers exactly projection block (first of the round) + w and the
+// projection's in-block prefixes (record word 3.w) are this kernel's wave
+// prefixes. The pairs of a sphere are written in row-major order over its
+// tile rectangle, which is the order pair_position() numbers them in.
+__global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs A) {
+  __shared__ uint32_t s_hist[kMaxDigits];
+  __shared__ unsigned long long s_w64[kSortWaves];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const int b = blockIdx.x;
+  const int ndig = A.digit_bits > 0 ? 1 << A.digit_bits : 0;
+  const uint32_t dmask = uint32_t(ndig) - 1u;
+  for (int d = tid; d < ndig; d += kEmitThreads) s_hist[d] = 0u;
+  // every tile starts with an empty range
+  for (uint32_t t = uint32_t(b) * kEmitThreads + uint32_t(tid); t < A.T;
+       t += uint32_t(A.nblk) * kEmitThreads)
+    A.trange[t] = make_uint2(0u, 0u);
+  // a single scene's tile numbering is the same for every sphere
+  const bool one_scene = A.tab.B == 1;
+  const uint32_t tile0_1 = one_scene ? A.tab.scenes[0].tile_off : 0u;
+  const uint32_t tiles_x_1 = one_scene ? uint32_t(A.tab.scenes[0].cam.tiles_x) : 0u;
+  const int pb_per_round = kEmitRound / kProjectBlock;
+  const int pb0 = b * A.rounds * pb_per_round;
+  const unsigned long long cap = (unsigned long long)A.cap;
+  unsigned long long base = 0;
+  for (int r = 0; r < A.rounds; ++r) {
+    const int i0 = (b * A.rounds + r) * kEmitRound + 4 * tid;
+    // the round's loads go out first: counts and rectangles of this
+    // thread's 4 spheres (counts and trect are 16-byte aligned and padded,
+    // so the vector loads stay inside them)
+    uint32_t c[4] = {0u, 0u, 0u, 0u};
+    uint4 t01 = make_uint4(0u, 0u, 0u, 0u), t23 = t01;
+    if (i0 < A.n) {
+      const uint4 c4 = *reinterpret_cast<const uint4*>(A.counts + i0);
+      const uint4* tp = reinterpret_cast<const uint4*>(A.trect + i0);
+      t01 = tp[0];
+      t23 = tp[1];
+      c[0] = c4.x;
+      c[1] = i0 + 1 < A.n ? c4.y : 0u;
+      c[2] = i0 + 2 < A.n ? c4.z : 0u;
+      c[3] = i0 + 3 < A.n ? c4.w : 0u;
+    }
+    if (r == 0) {
+      // the pairs of every projection block before this emission block
+      unsigned long long pre = 0;
+      for (int k = tid; k < pb0 && k < A.nblk_proj; k += kEmitThreads) pre += A.partials[k];
+      pre = wave_sum_u64(pre);
+      if (lane == 0) s_w64[wv] = pre;
+      __syncthreads();
+#pragma unroll
+      for (int w = 0; w < kSortWaves; ++w) base += s_w64[w];
+      if (tid == 0) A.ebase[b] = base;
+    }
+    const unsigned long long tsum =
+        (unsigned long long)c[0] + c[1] + (unsigned long long)c[2] + c[3];
+    const unsigned long long incl = wave_incl_scan_u64(tsum, lane);
+    __syncthreads();  // earlier readers of s_w64 are done
+    if (lane == kWave - 1) s_w64[wv] = incl;
+    __syncthreads();
+    unsigned long long before = 0, rtot = 0;
+#pragma unroll
+    for (int w = 0; w < kSortWaves; ++w) {
+      const unsigned long long x = s_w64[w];
+      if (w < wv) before += x;
+      rtot += x;
+    }
+    const int pb = pb0 + r * pb_per_round + wv;
+    if (lane == 0 && pb < A.nblk_proj) A.boff[pb] = base + before;
+    unsigned long long pos = base + before + incl - tsum;
+    const uint32_t tw[8] = {t01.x, t01.y, t01.z, t01.w, t23.x, t23.y, t23.z, t23.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (c[k] == 0u) continue;
+      const uint32_t i = uint32_t(i0 + k);
+      // ushort4 (x0, y0, x1, y1) as two words
+      const uint32_t x0 = tw[2 * k] & 0xffffu, y0 = tw[2 * k] >> 16;
+      const uint32_t x1 = tw[2 * k + 1] & 0xffffu, y1 = tw[2 * k + 1] >> 16;
+      uint32_t tile0 = tile0_1, tiles_x = tiles_x_1;
+      if (!one_scene) {
+        const SceneDev& sc = A.tab.scenes[find_scene(A.tab.sph_start, A.tab.B, i)];
+        tile0 = sc.tile_off;
+        tiles_x = uint32_t(sc.cam.tiles_x);
+      }
+      for (uint32_t ty = y0; ty <= y1; ++ty) {
+        for (uint32_t tx = x0; tx <= x1; ++tx) {
+          const uint32_t t = tile0 + ty * tiles_x + tx;
+          if (pos < cap) {
+            A.keys[pos] = t;
+            A.vals[pos] = i;
+          }
+          if (ndig) atomicAdd(&s_hist[t & dmask], 1u);
+          ++pos;
+        }
+      }
+    }
+    base += rtot;
   }
-  return below;
+  if (b == A.nblk - 1 && tid == 0) A.ebase[A.nblk] = base;  // the pair total
+  __syncthreads();
+  for (int d = tid; d < ndig; d += kEmitThreads)
+    A.mat[size_t(d) * mat_stride(uint32_t(A.nblk)) + b] = s_hist[d];
 }
 
-__device__ __forceinline__ RectRun rect_run(const ushort4& tr, uint32_t tile0, uint32_t tiles_x,
-                                            uint32_t t0, uint32_t t1) {
-  RectRun r;
-  r.w = uint32_t(tr.z) - tr.x + 1u;
-  const uint32_t last = tile0 + uint32_t(tr.w) * tiles_x + tr.z;
-  const uint32_t first = tile0 + uint32_t(tr.y) * tiles_x + tr.x;
-  if (last < t0 || first >= t1) {
-    r.e0 = 0;
-    r.nin = 0;
-    return r;
-  }
-  r.e0 = tiles_below(tr, tile0, tiles_x, t0);
-  r.nin = tiles_below(tr, tile0, tiles_x, t1) - r.e0;
-  return r;
-}
-
-__device__ __forceinline__ uint32_t rect_tile(const ushort4& tr, uint32_t tile0, uint32_t tiles_x,
-                                              uint32_t w, uint32_t e) {
-  const uint32_t dy = e / w;
-  return tile0 + (uint32_t(tr.y) + dy) * tiles_x + tr.x + (e - dy * w);
-}
-
-// A work unit of K2 / K4: bin block g of scene b (spheres [i0, i1)) and tile
-// slice h ([t0, t1) in the global tile numbering); its counts live in the
-// matrix row starting at `row` (indexed by the tile's number in the scene).
-struct BinUnit {
-  int b;
-  int i0, i1;
-  uint32_t t0, t1, tile0, tiles_x;
-  size_t row;
+// ---------------------------------------------------------------- radix sort
+struct SortArgs {
+  const uint32_t* keys_in;
+  const uint32_t* vals_in;
+  uint32_t* keys_out;
+  uint32_t* vals_out;
+  uint32_t* mat;
+  const unsigned long long* ebase;  // [nblk_emit + 1] first pair of each emission block
+  int nblk_emit;
+  int first;        // the first pass: its blocks are the emission blocks
+  int shift, bits;  // the digit
+  long long cap;
 };
 
-__device__ __forceinline__ BinUnit bin_unit(const SceneDev* __restrict__ scenes,
-                                            const uint32_t* __restrict__ unit_start, int B,
-                                            uint32_t u) {
-  BinUnit r;
-  r.b = find_scene(unit_start, B, u);
-  const SceneDev& sc = scenes[r.b];
-  const uint32_t local = u - sc.unit_off;
-  const uint32_t g = local / sc.slices, h = local - g * sc.slices;
-  r.i0 = int(sc.sph_off + g * sc.bin_S);
-  r.i1 = int(min(sc.sph_off + sc.n, uint32_t(r.i0) + sc.bin_S));
-  const uint32_t Tb = uint32_t(sc.cam.tiles_x) * uint32_t(sc.cam.tiles_y);
-  r.tile0 = sc.tile_off;
-  r.tiles_x = uint32_t(sc.cam.tiles_x);
-  r.t0 = sc.tile_off + h * uint32_t(kBinSlice);
-  r.t1 = min(sc.tile_off + Tb, r.t0 + uint32_t(kBinSlice));
-  r.row = size_t(sc.row_off) + size_t(g) * Tb;
-  return r;
+// Pairs stored by the emission: all of them, or none past the capacity (the
+// call then reports PULSAR_ERR_CAPACITY and sorts nothing).
+__device__ __forceinline__ uint32_t stored_pairs(const unsigned long long* ebase, int nblk_emit,
+                                                 long long cap) {
+  const unsigned long long total = ebase[nblk_emit];
+  return total > (unsigned long long)cap ? 0u : uint32_t(total);
 }
 
-// K2 block size (no ordering inside it matters), the loads a thread issues at
-// once, and the flat pairs of a K4 round whose owner is mapped in LDS
-constexpr int kCountThreads = 1024;
-constexpr int kBinUnroll = 4;
-constexpr int kFlatMap = 1024;
-static_assert(kBinThreads <= 256, "owners are stored as bytes");
+// Later passes cut the pairs into at most kMaxSortBlocks blocks of a multiple
+// of 1024 pairs, at least kSortMinBlock.
+__device__ __forceinline__ uint32_t sort_block_size(uint32_t used) {
+  const uint32_t per = (used + kMaxSortBlocks - 1u) / kMaxSortBlocks;
+  const uint32_t s = (per + 1023u) & ~1023u;
+  return s > uint32_t(kSortMinBlock) ? s : uint32_t(kSortMinBlock);
+}
 
-// ---------------------------------------------------------------- K2
-__global__ __launch_bounds__(kCountThreads) void k_bin_count(
-    const uint32_t* __restrict__ counts, const ushort4* __restrict__ trect,
-    const SceneDev* __restrict__ scenes, const uint32_t* __restrict__ unit_start, int B,
-    uint32_t* __restrict__ bmat) {
-  __shared__ uint32_t s_cnt[kBinSlice];
+// The pairs [beg, end) of sorting block b; false past the last block.
+__device__ __forceinline__ bool sort_range(const SortArgs& A, uint32_t used, uint32_t* nb,
+                                           uint32_t* beg, uint32_t* end) {
+  const uint32_t b = blockIdx.x;
+  if (A.first) {
+    *nb = uint32_t(A.nblk_emit);
+    if (b >= *nb) return false;
+    *beg = uint32_t(min(A.ebase[b], (unsigned long long)used));
+    *end = uint32_t(min(A.ebase[b + 1], (unsigned long long)used));
+    return true;
+  }
+  const uint32_t S = sort_block_size(used);
+  *nb = (used + S - 1u) / S;
+  if (b >= *nb) return false;
+  *beg = b * S;
+  *end = min(*beg + S, used);
+  return true;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_hist(SortArgs A) {
+  __shared__ uint32_t s_hist[kMaxDigits];
+  const uint32_t used = stored_pairs(A.ebase, A.nblk_emit, A.cap);
+  uint32_t nb, beg, end;
+  if (!sort_range(A, used, &nb, &beg, &end)) return;
   const int tid = threadIdx.x;
-  const BinUnit U = bin_unit(scenes, unit_start, B, blockIdx.x);
-  for (int k = tid; k < kBinSlice; k += kCountThreads) s_cnt[k] = 0u;
+  const uint32_t ndig = 1u << A.bits, dmask = ndig - 1u;
+  for (uint32_t d = tid; d < ndig; d += kSortThreads) s_hist[d] = 0u;
   __syncthreads();
-  // kBinUnroll spheres per thread at a time, every load issued before any is used
-  for (int base = U.i0; base < U.i1; base += kCountThreads * kBinUnroll) {
-    uint32_t c[kBinUnroll];
-    ushort4 tr[kBinUnroll];
+  for (uint32_t j = beg + uint32_t(tid); j < end; j += kSortThreads)
+    atomicAdd(&s_hist[(A.keys_in[j] >> A.shift) & dmask], 1u);
+  __syncthreads();
+  for (uint32_t d = tid; d < ndig; d += kSortThreads)
+    A.mat[size_t(d) * mat_stride(nb) + blockIdx.x] = s_hist[d];
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortArgs A) {
+  __shared__ uint32_t s_off[kMaxDigits];              // next position of each digit
+  __shared__ uint32_t s_below[kMaxDigits];            // the digit's pairs in earlier blocks
+  __shared__ uint32_t s_cnt[kSortWaves][kMaxDigits];  // this round's counts per wave
+  __shared__ uint32_t s_w[kSortWaves];
+  const uint32_t used = stored_pairs(A.ebase, A.nblk_emit, A.cap);
+  uint32_t nb, beg, end;
+  if (!sort_range(A, used, &nb, &beg, &end)) return;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const uint32_t ndig = 1u << A.bits, dmask = ndig - 1u;
+  // the first round's pair is requested before the offsets are worked out;
+  // each round then prefetches the next one's
+  uint32_t key_next = 0u, val_next = 0u;
+  if (beg + uint32_t(tid) < end) {
+    key_next = A.keys_in[beg + uint32_t(tid)];
+    val_next = A.vals_in[beg + uint32_t(tid)];
+  }
+  for (uint32_t d = tid; d < ndig; d += kSortThreads) {
 #pragma unroll
-    for (int k = 0; k < kBinUnroll; ++k) {
-      const int i = min(base + k * kCountThreads + tid, U.i1 - 1);
-      c[k] = counts[i];
-      tr[k] = trect[i];
+    for (int w = 0; w < kSortWaves; ++w) s_cnt[w][d] = 0u;
+  }
+  {
+    // wave w adds rows w, w + 16, ...: each lane one 16-byte piece of the
+    // row, then a wave sum of the digit's total and of its part in blocks
+    // before this one
+    const uint32_t stride = mat_stride(nb);
+    const uint32_t e0 = 4u * uint32_t(lane);
+    constexpr int kRowsPerWave = kMaxDigits / kSortWaves;
+    uint4 v[kRowsPerWave];
+    // every row load is in flight before the first is used
+#pragma unroll
+    for (int k = 0; k < kRowsPerWave; ++k) {
+      const uint32_t d = uint32_t(wv + k * kSortWaves);
+      v[k] = make_uint4(0u, 0u, 0u, 0u);
+      if (d < ndig && e0 < nb)
+        v[k] = *reinterpret_cast<const uint4*>(A.mat + size_t(d) * stride + e0);
     }
 #pragma unroll
-    for (int k = 0; k < kBinUnroll; ++k) {
-      if (base + k * kCountThreads + tid >= U.i1 || c[k] == 0u) continue;
-      const RectRun rr = rect_run(tr[k], U.tile0, U.tiles_x, U.t0, U.t1);
-      for (uint32_t e = rr.e0; e < rr.e0 + rr.nin; ++e)
-        atomicAdd(&s_cnt[rect_tile(tr[k], U.tile0, U.tiles_x, rr.w, e) - U.t0], 1u);
+    for (int k = 0; k < kRowsPerWave; ++k) {
+      const uint32_t d = uint32_t(wv + k * kSortWaves);
+      if (d >= ndig) break;  // wave-uniform
+      const uint32_t x[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
+      uint32_t tot = 0, below = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t bb = e0 + uint32_t(j);
+        const uint32_t xv = bb < nb ? x[j] : 0u;
+        tot += xv;
+        below += bb < blockIdx.x ? xv : 0u;
+      }
+      tot = wave_sum_u32(tot);
+      below = wave_sum_u32(below);
+      if (lane == 0) {
+        s_off[d] = tot;
+        s_below[d] = below;
+      }
     }
   }
   __syncthreads();
-  uint32_t* row = bmat + U.row - U.tile0;
-  for (uint32_t t = U.t0 + uint32_t(tid); t < U.t1; t += kCountThreads) row[t] = s_cnt[t - U.t0];
+  {
+    // digit d starts after all smaller digits and after its pairs in earlier blocks
+    const uint32_t d = uint32_t(tid);
+    const uint32_t v = d < ndig ? s_off[d] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan<uint32_t>(v, s_w, &tot);
+    __syncthreads();
+    if (d < ndig) s_off[d] = ex + s_below[d];
+  }
+  __syncthreads();
+  const uint64_t lt = lanemask_lt(lane);
+  for (uint32_t r0 = beg; r0 < end; r0 += kSortThreads) {
+    const uint32_t j = r0 + uint32_t(tid);
+    const bool valid = j < end;
+    const uint32_t key = key_next, val = val_next;
+    if (j + kSortThreads < end) {
+      key_next = A.keys_in[j + kSortThreads];
+      val_next = A.vals_in[j + kSortThreads];
+    }
+    const uint32_t d = (key >> A.shift) & dmask;
+    // the lanes of this wave with the same digit
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < kMaxDigitBits; ++bit) {
+      if (bit >= A.bits) break;
+      const uint64_t m = __ballot((d >> bit) & 1u);
+      peers &= ((d >> bit) & 1u) ? m : ~m;
+    }
+    const uint32_t below = uint32_t(__popcll(peers & lt));
+    if (valid && below == 0u) s_cnt[wv][d] = uint32_t(__popcll(peers));
+    __syncthreads();
+    if (valid) {
+      uint32_t rank = s_off[d] + below;
+      for (int w = 0; w < wv; ++w) rank += s_cnt[w][d];
+      if (rank < used) {  // always, as the counts and the pairs are the same
+        A.keys_out[rank] = key;
+        A.vals_out[rank] = val;
+      }
+    }
+    __syncthreads();  // every rank of this round is taken
+    for (uint32_t dd = tid; dd < ndig; dd += kSortThreads) {
+      uint32_t add = 0;
+#pragma unroll
+      for (int w = 0; w < kSortWaves; ++w) {
+        add += s_cnt[w][dd];
+        s_cnt[w][dd] = 0u;
+      }
+      s_off[dd] += add;
+    }
+    __syncthreads();
+  }
 }
 
-// ---------------------------------------------------------------- K3
+// ---------------------------------------------------------------- tiles
+// A tile's pairs are the run of its number in the sorted keys: its first pair
+// is where the key changes to it, its end where the key changes from it.
+// Tiles with no pair keep the empty range k_emit wrote. Block 0 also writes
+// the call's pair count and capacity status and clears the work-item
+// counters for k_plan.
+__global__ __launch_bounds__(1024) void k_ranges(uint32_t T, const uint32_t* __restrict__ keys,
+                                                 const unsigned long long* __restrict__ ebase,
+                                                 int nblk_emit, long long cap,
+                                                 Status* __restrict__ status,
+                                                 uint2* __restrict__ trange) {
+  const unsigned long long total = ebase[nblk_emit];
+  const uint32_t used = stored_pairs(ebase, nblk_emit, cap);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    status->pairs = total;
+    status->used = used;
+    status->code = total > (unsigned long long)cap ? uint32_t(-PULSAR_ERR_CAPACITY) : 0u;
+    status->nfull = 0u;
+    status->nshort = 0u;
+    status->npartials = 0u;
+    status->nmerge = 0u;
+  }
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < used; i += gridDim.x * blockDim.x) {
+    const uint32_t k = keys[i];
+    if (k >= T) continue;  // never: keys are tile numbers
+    if (i == 0u || keys[i - 1u] != k) trange[k].x = i;
+    if (i + 1u == used || keys[i + 1u] != k) trange[k].y = i + 1u;
+  }
+}
+
 // Work items: a tile's list of L pairs is cut into L / chunk full chunks and
-// one shorter chunk for the rest. Full chunks of all tiles come first in the
-// work list (the costlier items start first), then the short ones. A tile
-// with several chunks needs one partial blend state per chunk (slots
-// soff .. soff + n - 1), merged afterwards, and is listed for the merge.
+// one shorter chunk for the rest. A tile with several chunks needs one partial
+// blend state per chunk, merged afterwards, and is listed for the merge.
 struct TileChunks {
   uint32_t nf, np, ns, nm;  // full chunks, short chunks (0/1), partial-state slots, merges (0/1)
 };
@@ -154,386 +414,116 @@ __device__ __forceinline__ TileChunks chunks_of(uint32_t L, uint32_t chunk) {
   return c;
 }
 
-// Exclusive block-wide scan of one value per thread (kScanThreads threads);
-// returns the prefix and leaves the total in *total. Uses s_w[kScanWaves].
-template <typename V>
-__device__ __forceinline__ V block_excl_scan(V v, V* s_w, V* total) {
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wid = tid / kWave;
-  V incl = v;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const V o = __shfl_up(incl, off, kWave);
-    if (lane >= off) incl += o;
-  }
-  __syncthreads();  // earlier users of s_w are done
-  if (lane == kWave - 1) s_w[wid] = incl;
-  __syncthreads();
-  V before = 0, tot = 0;
-  for (int w = 0; w < kScanThreads / kWave; ++w) {
-    const V x = s_w[w];
-    if (w < wid) before += x;
-    tot += x;
-  }
-  *total = tot;
-  return before + incl - v;
+// Allocates (a, b) units per lane from the adjacent counters ctr[0], ctr[1]
+// for the whole wave with one 64-bit atomic (neither count reaches 2^32);
+// returns the lane's first unit of each.
+__device__ __forceinline__ uint2 wave_alloc2(uint32_t* ctr, uint32_t a, uint32_t b, int lane) {
+  const uint32_t ia = wave_incl_scan_u32(a, lane), ib = wave_incl_scan_u32(b, lane);
+  const uint32_t ta = __builtin_amdgcn_readlane(ia, kWave - 1);
+  const uint32_t tb = __builtin_amdgcn_readlane(ib, kWave - 1);
+  unsigned long long base = 0;
+  if (lane == 0 && (ta | tb) != 0u)
+    base = atomicAdd(reinterpret_cast<unsigned long long*>(ctr),
+                     (unsigned long long)ta | ((unsigned long long)tb << 32));
+  const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(base), 0);
+  const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(base >> 32), 0);
+  return make_uint2(lo + ia - a, hi + ib - b);
 }
 
-// Sums of one 64-tile group of K3a: pairs, then the work-item counts.
-struct TileGroupSums {
-  unsigned long long pairs;
-  uint32_t nf, np, ns, nm;
-};
+constexpr int kPlanThreads = 256;
 
-// K3a: block k handles tiles 64 k .. 64 k + 63, one per lane. The tile's
-// scene has G_b bin blocks; wave w adds rows w Gq .. w Gq + Gq - 1 of the
-// tile's column (Gq = ceil(G_b / 16) <= kBinRowsPerWave), all loads issued at
-// once, and the per-wave sums give each wave's first offset. Each cell of the
-// column becomes its offset inside the tile (in place; cells with no pair are
-// never read again); the tile's total and the group's sums are written for
-// K3b.
-__global__ __launch_bounds__(kScanThreads) void k_bin_scan(
-    uint32_t T, SceneTable tab, uint32_t chunk, uint32_t* __restrict__ bmat,
-    uint32_t* __restrict__ tcount, TileGroupSums* __restrict__ gsum) {
-  constexpr int NW = kScanThreads / kWave;
-  __shared__ uint32_t s_part[NW][kWave];
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
-  const uint32_t t = blockIdx.x * uint32_t(kWave) + uint32_t(lane);
-  const bool in = t < T;
-  const SceneDev& sc = tab.scenes[find_scene(tab.tile_start, tab.B, in ? t : T - 1u)];
-  const int G = int(sc.bin_G);
-  const uint32_t Tb = uint32_t(sc.cam.tiles_x) * uint32_t(sc.cam.tiles_y);
-  const size_t col = size_t(sc.row_off) + size_t(in ? t - sc.tile_off : 0u);
-  const int Gq = (G + NW - 1) / NW;
-  const int g0 = w * Gq;
-  uint32_t v[kBinRowsPerWave];
-  uint32_t sum = 0;
-#pragma unroll
-  for (int j = 0; j < kBinRowsPerWave; ++j) {
-    const int g = g0 + j;
-    v[j] = (in && j < Gq && g < G) ? bmat[col + size_t(g) * Tb] : 0u;
-    sum += v[j];
-  }
-  s_part[w][lane] = sum;
-  __syncthreads();
-  uint32_t run = 0, tot = 0;
-  for (int k = 0; k < NW; ++k) {
-    const uint32_t x = s_part[k][lane];
-    if (k < w) run += x;
-    tot += x;
-  }
-#pragma unroll
-  for (int j = 0; j < kBinRowsPerWave; ++j) {
-    if (v[j] != 0u) bmat[col + size_t(g0 + j) * Tb] = run;
-    run += v[j];
-  }
-  if (w == 0) {
-    if (in) tcount[t] = tot;
-    const TileChunks c = chunks_of(tot, chunk);
-    const unsigned long long pairs = wave_sum_u64(tot);
-    const uint32_t nf = wave_sum_u32(c.nf), np = wave_sum_u32(c.np), ns = wave_sum_u32(c.ns),
-                   nm = wave_sum_u32(c.nm);
-    if (lane == 0) gsum[blockIdx.x] = TileGroupSums{pairs, nf, np, ns, nm};
-  }
-}
-
-// K3b: block j < ntb plans tiles 1024 j .. 1024 j + 1023, one per thread:
-// the group sums of K3a give the totals (which decide a capacity overflow)
-// and everything before the block; a block scan does the rest. It writes
-// every tile's range in the sorted pair list and its work items; block 0
-// also writes the totals. Blocks ntb .. ntb + nbo - 1 write the first
-// emission position of 1024 projection blocks each (an exclusive scan of
-// their pair counts). Work items of a tile of L pairs: L / chunk full chunks
-// and one shorter chunk for the rest; full chunks of all tiles come first in
-// the work list (the costlier items start first), then the short ones; a
-// tile with several chunks gets one partial blend state per chunk and is
-// listed for the merge. After a capacity overflow (outputs invalid) no work
-// item is written.
-constexpr int kPlanThreads = 1024;
-
-__global__ __launch_bounds__(kPlanThreads) void k_bin_plan(
-    uint32_t T, uint32_t ntb, const uint32_t* __restrict__ tcount,
-    const TileGroupSums* __restrict__ gsum, long long cap, uint32_t chunk, long long pcap,
-    int nblk_proj, const unsigned long long* __restrict__ partials,
-    unsigned long long* __restrict__ boff, Status* __restrict__ status,
-    uint32_t* __restrict__ ranges, uint4* __restrict__ tinfo, uint4* __restrict__ desc,
-    uint32_t* __restrict__ mlist) {
-  constexpr int NW = kPlanThreads / kWave;
-  __shared__ unsigned long long s_w64[NW], s_red64[2][NW];
-  __shared__ uint32_t s_w32[NW], s_red32[8][NW];
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-  if (blockIdx.x >= ntb) {
-    // projection blocks a0 .. a0 + 1023: the sum of all earlier ones, then a scan
-    const int a0 = int(blockIdx.x - ntb) * kPlanThreads;
-    unsigned long long pre = 0;
-    for (int k = tid; k < a0; k += kPlanThreads) pre += partials[k];
-    const int pb = a0 + tid;
-    const unsigned long long v = pb < nblk_proj ? partials[pb] : 0ull;
-    pre = wave_sum_u64(pre);
-    if (lane == 0) s_red64[0][wv] = pre;
-    __syncthreads();
-    unsigned long long before = 0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) before += s_red64[0][w];
-    unsigned long long tot;
-    before += block_excl_scan<unsigned long long>(v, s_w64, &tot);
-    if (pb < nblk_proj) boff[pb] = before;
-    return;
-  }
-  // group sums: all of them (totals) and those before this block (prefix)
-  const uint32_t ng = (T + kWave - 1) / kWave, gfirst = blockIdx.x * uint32_t(NW);
-  const uint32_t t = blockIdx.x * uint32_t(kPlanThreads) + uint32_t(tid);
-  const uint32_t L = t < T ? tcount[t] : 0u;
-  unsigned long long ap = 0, bp = 0;
-  uint32_t a[4] = {0u, 0u, 0u, 0u}, bb[4] = {0u, 0u, 0u, 0u};
-  for (uint32_t k = uint32_t(tid); k < ng; k += kPlanThreads) {
-    const TileGroupSums g = gsum[k];
-    const uint32_t x[4] = {g.nf, g.np, g.ns, g.nm};
-    ap += g.pairs;
-    if (k < gfirst) bp += g.pairs;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      a[q] += x[q];
-      if (k < gfirst) bb[q] += x[q];
-    }
-  }
-  ap = wave_sum_u64(ap);
-  bp = wave_sum_u64(bp);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    a[q] = wave_sum_u32(a[q]);
-    bb[q] = wave_sum_u32(bb[q]);
-  }
-  if (lane == 0) {
-    s_red64[0][wv] = ap;
-    s_red64[1][wv] = bp;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      s_red32[q][wv] = a[q];
-      s_red32[4 + q][wv] = bb[q];
-    }
-  }
-  __syncthreads();
-  unsigned long long total = 0, pbefore = 0;
-  uint32_t tot4[4] = {0u, 0u, 0u, 0u}, pre4[4] = {0u, 0u, 0u, 0u};
-  for (int w = 0; w < NW; ++w) {
-    total += s_red64[0][w];
-    pbefore += s_red64[1][w];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      tot4[q] += s_red32[q][w];
-      pre4[q] += s_red32[4 + q][w];
-    }
-  }
-  const bool over = total > (unsigned long long)cap;
-  const bool ok = !over && (long long)tot4[2] <= pcap;
-  const unsigned long long used = over ? 0ull : total;
-  // this tile's offsets: everything before the block plus the block scan
-  const TileChunks c = chunks_of(L, chunk);
-  unsigned long long xt;
-  uint32_t x32;
-  const unsigned long long p =
-      pbefore + block_excl_scan<unsigned long long>((unsigned long long)L, s_w64, &xt);
-  uint32_t f = pre4[0] + block_excl_scan<uint32_t>(c.nf, s_w32, &x32);
-  uint32_t q = tot4[0] + pre4[1] + block_excl_scan<uint32_t>(c.np, s_w32, &x32);
-  const uint32_t sl = pre4[2] + block_excl_scan<uint32_t>(c.ns, s_w32, &x32);
-  const uint32_t m = pre4[3] + block_excl_scan<uint32_t>(c.nm, s_w32, &x32);
-  if (t < T) {
-    const uint32_t beg = uint32_t(min(p, used));
-    ranges[t] = beg;
-    const uint32_t nch = ok ? c.nf + c.np : 0u;
-    tinfo[t] = make_uint4(sl, nch, 0u, 0u);
-    if (ok && c.nm) mlist[m] = t;
-    for (uint32_t ci = 0; ci < nch; ++ci) {
-      const uint32_t b = beg + ci * chunk;
-      const uint32_t e = min(beg + L, b + chunk);
-      const uint32_t slot = nch >= 2 ? sl + ci : kNoSlot;
-      const uint32_t at = ci < c.nf ? f++ : q++;
-      desc[at] = make_uint4(t | (ci == 0 ? kFirstChunk : 0u), b, e, slot);
-    }
-  }
-  if (blockIdx.x == 0 && tid == 0) {
-    ranges[T] = uint32_t(used);
-    status->pairs = total;
-    status->used = uint32_t(used);
-    status->code = ok ? 0u : uint32_t(-PULSAR_ERR_CAPACITY);
-    status->nfull = ok ? tot4[0] : 0u;
-    status->nchunks = ok ? tot4[0] + tot4[1] : 0u;
-    status->npartials = ok ? tot4[2] : 0u;
-    status->nmerge = ok ? tot4[3] : 0u;
-  }
-}
-
-// ---------------------------------------------------------------- K4
-// Block (g, slice) walks its spheres in rounds of kBinThreads, one sphere per
-// thread. The round's pairs in the slice are numbered in (sphere, tile)
-// order by a block scan of their counts and placed kBinThreads at a time,
-// one per thread (the owner sphere of flat pair p found by binary search).
-// The rank of a pair inside its (g, tile) cell is: the pairs of earlier
-// steps (a running position per tile), those of earlier waves in this step
-// (7-bit per-wave counts packed next to that position in one 64-bit LDS
-// word) and those of earlier lanes in this wave (ballot match on the tile).
-// Every tile's list therefore holds its spheres in the order of the sphere
-// index, whatever the scheduling.
-__global__ __launch_bounds__(kBinThreads) void k_bin_scatter(
-    const uint32_t* __restrict__ counts, const ushort4* __restrict__ trect,
-    const SceneDev* __restrict__ scenes, const uint32_t* __restrict__ unit_start, int B,
-    const uint32_t* __restrict__ bmat, const uint32_t* __restrict__ ranges,
-    const Status* __restrict__ status, long long cap, uint32_t* __restrict__ vals) {
-  constexpr int NW = kBinThreads / kWave;
-  static_assert(NW * 7 <= 32, "per-wave counts must fit the low word");
-  // per tile of the slice: (next position in the sorted list) << 32 | the
-  // per-wave counts of the current step, 7 bits per wave
-  __shared__ unsigned long long s_st[kBinSlice];
-  // the round's spheres: first flat pair, rectangle, first tile in the slice;
-  // the owner of each of the round's first kFlatMap flat pairs
-  __shared__ uint32_t s_start[kBinThreads + 1];
-  __shared__ ushort4 s_tr[kBinThreads];
-  __shared__ uint32_t s_e0[kBinThreads];
-  __shared__ uint32_t s_wsum[NW];
-  __shared__ uint8_t s_owner[kFlatMap];
-  if (status->code != 0u) return;  // capacity exceeded: no work items either
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-  const BinUnit U = bin_unit(scenes, unit_start, B, blockIdx.x);
-  const uint32_t* row = bmat + U.row - U.tile0;
-  // the slice's running positions, every load of a batch issued at once
-  for (uint32_t t0 = U.t0; t0 < U.t1; t0 += kBinThreads * kBinUnroll) {
-    uint32_t rg[kBinUnroll], rw[kBinUnroll];
-#pragma unroll
-    for (int k = 0; k < kBinUnroll; ++k) {
-      const uint32_t t = min(t0 + uint32_t(k * kBinThreads + tid), U.t1 - 1u);
-      rg[k] = ranges[t];
-      rw[k] = row[t];
-    }
-#pragma unroll
-    for (int k = 0; k < kBinUnroll; ++k) {
-      const uint32_t t = t0 + uint32_t(k * kBinThreads + tid);
-      if (t < U.t1) s_st[t - U.t0] = (unsigned long long)(rg[k] + rw[k]) << 32;
-    }
-  }
-  const uint64_t lt = lanemask_lt(lane);
-  // the first round's sphere, then each round requests the next one's
-  int inext = min(U.i0 + tid, U.i1 - 1);
-  uint32_t cnext = counts[inext];
-  ushort4 trnext = trect[inext];
-  for (int r0 = U.i0; r0 < U.i1; r0 += kBinThreads) {
-    const int i = r0 + tid;
-    const uint32_t c = cnext;
-    const ushort4 tr = trnext;
-    if (r0 + kBinThreads < U.i1) {
-      inext = min(i + kBinThreads, U.i1 - 1);
-      cnext = counts[inext];
-      trnext = trect[inext];
-    }
-    RectRun rr;
-    rr.e0 = rr.nin = 0;
-    rr.w = 1;
-    if (i < U.i1 && c != 0u) rr = rect_run(tr, U.tile0, U.tiles_x, U.t0, U.t1);
-    // flat numbering of the round's pairs in the slice
-    const uint32_t incl = wave_incl_scan_u32(rr.nin, lane);
-    __syncthreads();  // the previous round's readers of s_start / s_tr are done
-    if (lane == kWave - 1) s_wsum[wv] = incl;
-    s_tr[tid] = tr;
-    s_e0[tid] = rr.e0;
-    __syncthreads();
-    uint32_t before = 0, total = 0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      before += w < wv ? s_wsum[w] : 0u;
-      total += s_wsum[w];
-    }
-    const uint32_t first = before + incl - rr.nin;
-    s_start[tid] = first;
-    for (uint32_t k = 0; k < rr.nin && first + k < uint32_t(kFlatMap); ++k)
-      s_owner[first + k] = uint8_t(tid);
-    __syncthreads();
-    for (uint32_t p0 = 0; p0 < total; p0 += kBinThreads) {
-      const uint32_t p = p0 + uint32_t(tid);
-      const bool act = p < total;
-      uint32_t key = 0, sph = 0;
-      if (act) {
-        // owner: from the map, or past it the last thread whose first flat
-        // pair is <= p (it has pairs)
-        int lo = 0;
-        if (p < uint32_t(kFlatMap)) {
-          lo = s_owner[p];
-        } else {
-          int hi = kBinThreads - 1;
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_start[mid] <= p)
-              lo = mid;
-            else
-              hi = mid - 1;
-          }
-        }
-        const ushort4 otr = s_tr[lo];
-        const uint32_t w = uint32_t(otr.z) - otr.x + 1u;
-        key = rect_tile(otr, U.tile0, U.tiles_x, w, s_e0[lo] + (p - s_start[lo])) - U.t0;
-        sph = uint32_t(r0 + lo);
-      }
-      uint64_t peers = __ballot(act);
-#pragma unroll
-      for (int b = 0; b < kBinSliceBits; ++b) {
-        const uint64_t m = __ballot((key >> b) & 1u);
-        peers &= ((key >> b) & 1u) ? m : ~m;
-      }
-      const uint32_t rank = uint32_t(__popcll(peers & lt));
-      const bool leader = act && rank == 0u;
-      if (leader)
-        atomicAdd(&s_st[key], (unsigned long long)__popcll(peers) << (7 * wv));
-      __syncthreads();
-      unsigned long long upd = 0ull;
-      if (act) {
-        const unsigned long long st = s_st[key];
-        const uint32_t fields = uint32_t(st);
-        uint32_t below = 0, cnt = 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-          const uint32_t f = (fields >> (7 * w)) & 127u;
-          below += w < wv ? f : 0u;
-          cnt += f;
-        }
-        const unsigned long long dest = (st >> 32) + below + rank;
-        if ((long long)dest < cap) vals[dest] = sph;
-        // the leader of the lowest wave holding this tile moves the step's
-        // count into the running position and clears the per-wave counts
-        if (leader && (fields & ((1u << (7 * wv)) - 1u)) == 0u)
-          upd = ((unsigned long long)cnt << 32) - (unsigned long long)fields;
-      }
-      __syncthreads();  // every read of this step's counts is done
-      if (upd != 0ull) atomicAdd(&s_st[key], upd);
-    }
+// One tile per thread: its work items (full chunks from the front of the
+// list, the short one from the back), its contiguous partial-state slots and
+// its merge entry. The bounds cannot be exceeded when the pairs fit the
+// capacity (at most cap / chunk + T items, 2 cap / chunk + 1 slots, T merge
+// tiles); they are checked anyway, and a violation is reported as a
+// capacity overflow, after which no work item is taken.
+__global__ __launch_bounds__(kPlanThreads) void k_plan(uint32_t T, const uint2* __restrict__ trange,
+                                                        uint32_t chunk, long long pcap,
+                                                        uint32_t max_items, Status* status,
+                                                        uint4* __restrict__ tinfo,
+                                                        uint4* __restrict__ desc,
+                                                        uint32_t* __restrict__ mlist) {
+  const uint32_t t = blockIdx.x * kPlanThreads + threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1);
+  const bool ok = status->code == 0u;
+  const uint2 tr = (t < T && ok) ? trange[t] : make_uint2(0u, 0u);
+  const TileChunks c = chunks_of(tr.y - tr.x, chunk);
+  const uint2 fs = wave_alloc2(&status->nfull, c.nf, c.np, lane);
+  const uint2 pm = wave_alloc2(&status->npartials, c.ns, c.nm, lane);
+  const uint32_t f0 = fs.x, s0 = fs.y, sl = pm.x, m = pm.y;
+  if (t >= T) return;
+  const uint32_t nch = c.nf + c.np;
+  const bool fits = (long long)sl + c.ns <= pcap && f0 + c.nf <= max_items &&
+                    s0 + c.np <= max_items && m + c.nm <= T;
+  if (!fits) atomicMax(&status->code, uint32_t(-PULSAR_ERR_CAPACITY));
+  tinfo[t] = make_uint4(sl, fits ? nch : 0u, 0u, 0u);
+  if (!fits) return;
+  if (c.nm) mlist[m] = t;
+  for (uint32_t ci = 0; ci < nch; ++ci) {
+    const uint32_t b = tr.x + ci * chunk;
+    const uint32_t e = min(tr.y, b + chunk);
+    const uint32_t slot = nch >= 2 ? sl + ci : kNoSlot;
+    const uint32_t at = ci < c.nf ? f0 + ci : max_items - 1u - s0;
+    desc[at] = make_uint4(t | (ci == 0 ? kFirstChunk : 0u), b, e, slot);
   }
 }
 
 void launch_binning(const Plan& q, char* ws, hipStream_t stream) {
   Status* status = ws_ptr<Status>(ws, q.off_status);
-  const SceneTable tab = scene_table(q, ws);
-  uint32_t* bmat = ws_ptr<uint32_t>(ws, q.off_bmat);
-  const uint32_t T = uint32_t(q.T);
-  const uint32_t* counts = ws_ptr<uint32_t>(ws, q.off_counts);
-  const ushort4* trect = ws_ptr<ushort4>(ws, q.off_trect);
-  uint32_t* tcount = ws_ptr<uint32_t>(ws, q.off_tcount);
-  auto* gsum = ws_ptr<TileGroupSums>(ws, q.off_gsum);
-  // with no spheres there are no units; the scans still plan the (empty) tiles
-  if (q.bin_units > 0)
-    hipLaunchKernelGGL(k_bin_count, dim3(unsigned(q.bin_units)), dim3(kCountThreads), 0, stream,
-                       counts, trect, tab.scenes, tab.unit_start, q.B, bmat);
-  hipLaunchKernelGGL(k_bin_scan, dim3(unsigned((q.T + kWave - 1) / kWave)), dim3(kScanThreads),
-                     0, stream, T, tab, uint32_t(q.chunk), bmat, tcount, gsum);
-  const uint32_t ntb = uint32_t((q.T + kPlanThreads - 1) / kPlanThreads);
-  const uint32_t nbo = uint32_t((q.nblk_proj + kPlanThreads - 1) / kPlanThreads);
-  hipLaunchKernelGGL(k_bin_plan, dim3(ntb + nbo), dim3(kPlanThreads), 0, stream, T, ntb, tcount,
-                     gsum, (long long)q.cap, uint32_t(q.chunk), (long long)q.pcap, q.nblk_proj,
-                     ws_ptr<unsigned long long>(ws, q.off_partials),
-                     ws_ptr<unsigned long long>(ws, q.off_boff), status,
-                     ws_ptr<uint32_t>(ws, q.off_ranges), ws_ptr<uint4>(ws, q.off_tinfo),
-                     ws_ptr<uint4>(ws, q.off_desc), ws_ptr<uint32_t>(ws, q.off_mlist));
-  if (q.bin_units > 0)
-    hipLaunchKernelGGL(k_bin_scatter, dim3(unsigned(q.bin_units)), dim3(kBinThreads), 0, stream,
-                       counts, trect, tab.scenes, tab.unit_start, q.B, bmat,
-                       ws_ptr<uint32_t>(ws, q.off_ranges), status, (long long)q.cap,
-                       ws_ptr<uint32_t>(ws, q.off_vals));
+  // pass p reads buffer p % 2 and writes the other; the last pass ends in
+  // off_keys / off_vals, so the pairs are emitted where that parity starts
+  const bool odd = (q.sort_passes & 1) != 0;
+  uint32_t* keys[2] = {ws_ptr<uint32_t>(ws, odd ? q.off_keys2 : q.off_keys),
+                       ws_ptr<uint32_t>(ws, odd ? q.off_keys : q.off_keys2)};
+  uint32_t* vals[2] = {ws_ptr<uint32_t>(ws, odd ? q.off_vals2 : q.off_vals),
+                       ws_ptr<uint32_t>(ws, odd ? q.off_vals : q.off_vals2)};
+  EmitArgs E;
+  E.n = int(q.n);
+  E.counts = ws_ptr<uint32_t>(ws, q.off_counts);
+  E.trect = ws_ptr<ushort4>(ws, q.off_trect);
+  E.partials = ws_ptr<unsigned long long>(ws, q.off_partials);
+  E.tab = scene_table(q, ws);
+  E.rounds = q.emit_rounds;
+  E.nblk = q.nblk_emit;
+  E.nblk_proj = q.nblk_proj;
+  E.T = uint32_t(q.T);
+  E.cap = q.cap;
+  E.digit_bits = q.sort_digit;
+  E.keys = keys[0];
+  E.vals = vals[0];
+  E.boff = ws_ptr<unsigned long long>(ws, q.off_boff);
+  E.ebase = ws_ptr<unsigned long long>(ws, q.off_ebase);
+  E.mat = ws_ptr<uint32_t>(ws, q.off_mat);
+  E.trange = ws_ptr<uint2>(ws, q.off_trange);
+  hipLaunchKernelGGL(k_emit, dim3(unsigned(q.nblk_emit)), dim3(kEmitThreads), 0, stream, E);
+  for (int p = 0; p < q.sort_passes; ++p) {
+    SortArgs S;
+    S.keys_in = keys[p & 1];
+    S.vals_in = vals[p & 1];
+    S.keys_out = keys[(p + 1) & 1];
+    S.vals_out = vals[(p + 1) & 1];
+    S.mat = E.mat;
+    S.ebase = E.ebase;
+    S.nblk_emit = q.nblk_emit;
+    S.first = p == 0 ? 1 : 0;
+    S.shift = p * q.sort_digit;
+    S.bits = q.sort_digit;
+    S.cap = q.cap;
+    const unsigned grid = p == 0 ? unsigned(q.nblk_emit) : unsigned(kMaxSortBlocks);
+    if (p > 0)
+      hipLaunchKernelGGL(k_sort_hist, dim3(grid), dim3(kSortThreads), 0, stream, S);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(grid), dim3(kSortThreads), 0, stream, S);
+  }
+  const long long rg = (q.cap + 4095) / 4096;
+  hipLaunchKernelGGL(k_ranges, dim3(unsigned(rg < 256 ? rg : 256)), dim3(1024), 0, stream,
+                     uint32_t(q.T), ws_ptr<uint32_t>(ws, q.off_keys), E.ebase, q.nblk_emit,
+                     (long long)q.cap, status, E.trange);
+  hipLaunchKernelGGL(k_plan, dim3(unsigned((q.T + kPlanThreads - 1) / kPlanThreads)),
+                     dim3(kPlanThreads), 0, stream, uint32_t(q.T), E.trange, uint32_t(q.chunk),
+                     (long long)q.pcap, uint32_t(q.max_chunks), status,
+                     ws_ptr<uint4>(ws, q.off_tinfo), ws_ptr<uint4>(ws, q.off_desc),
+                     ws_ptr<uint32_t>(ws, q.off_mlist));
 }
 
 }  // namespace pulsar

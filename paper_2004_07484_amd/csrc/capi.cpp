@@ -143,29 +143,6 @@ int make_scenes(const pulsar_scene_t* scenes, int B, const pulsar_params_t* p,
       return PULSAR_ERR_INVALID_ARGUMENT;
     out->push_back(d);
   }
-  // bin blocks: S spheres each, so that the count matrix, sum over scenes of
-  // (bin blocks) x (tiles), stays near kBinCells entries, but at most
-  // kBinMaxG blocks per scene; units and matrix rows scene by scene
-  double work = 0.0;
-  for (const SceneDev& d : *out) work += double(d.n) * double(d.cam.tiles_x) * d.cam.tiles_y;
-  int64_t per = int64_t(std::ceil(work / double(kBinCells) / double(kBinThreads)));
-  if (per < 1) per = 1;
-  int64_t units = 0;
-  unsigned long long rows = 0;
-  for (SceneDev& d : *out) {
-    const int64_t nb = (int64_t(d.n) + kBinThreads - 1) / kBinThreads;  // rounds
-    int64_t pb = per;
-    if ((nb + pb - 1) / pb > kBinMaxG) pb = (nb + kBinMaxG - 1) / kBinMaxG;
-    const int64_t T_b = int64_t(d.cam.tiles_x) * d.cam.tiles_y;
-    d.bin_S = uint32_t(pb * kBinThreads);
-    d.bin_G = uint32_t(nb > 0 ? (nb + pb - 1) / pb : 0);
-    d.slices = uint32_t((T_b + kBinSlice - 1) / kBinSlice);
-    d.unit_off = uint32_t(units);
-    d.row_off = rows;
-    units += int64_t(d.bin_G) * d.slices;
-    rows += (unsigned long long)d.bin_G * (unsigned long long)T_b;
-    if (units > INT32_MAX) return PULSAR_ERR_INVALID_ARGUMENT;
-  }
   return PULSAR_OK;
 }
 
@@ -191,9 +168,19 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   if (cap > (int64_t(1) << 31) - 1) cap = (int64_t(1) << 31) - 1;
   q.cap = cap;
   q.nblk_proj = int((n + kProjectBlock - 1) / kProjectBlock);
-  q.bin_units = int64_t(last.unit_off) + int64_t(last.bin_G) * last.slices;
-  q.bin_cells = int64_t(last.row_off) +
-                int64_t(last.bin_G) * int64_t(last.cam.tiles_x) * last.cam.tiles_y;
+  // LSD passes: enough digits of at most kMaxDigitBits bits for the tile
+  // numbers 0 .. T - 1 (none for a single tile), all of the same width
+  int bits = 0;
+  while ((int64_t(1) << bits) < q.T) ++bits;
+  q.sort_passes = (bits + kMaxDigitBits - 1) / kMaxDigitBits;
+  q.sort_digit = q.sort_passes > 0 ? (bits + q.sort_passes - 1) / q.sort_passes : 0;
+  // emission blocks: at most kMaxSortBlocks of them, whole rounds each
+  const int64_t per_round = int64_t(kMaxSortBlocks) * kEmitRound;
+  q.emit_rounds = int((n + per_round - 1) / per_round);
+  if (q.emit_rounds < 1) q.emit_rounds = 1;
+  const int64_t spb = int64_t(q.emit_rounds) * kEmitRound;
+  q.nblk_emit = int((n + spb - 1) / spb);
+  if (q.nblk_emit < 1) q.nblk_emit = 1;
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t at = o;
@@ -209,11 +196,14 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   q.off_rec = take(nn * 64);
   q.off_partials = take(size_t(q.nblk_proj + 1) * 8);
   q.off_boff = take(size_t(q.nblk_proj + 1) * 8);
-  q.off_bmat = take(size_t(q.bin_cells > 0 ? q.bin_cells : 1) * 4);
-  q.off_tcount = take(size_t(q.T) * 4);
-  q.off_gsum = take(size_t((q.T + 63) / 64) * 32);
+  q.off_ebase = take(size_t(q.nblk_emit + 1) * 8);
+  // block x digit counts, with room for the last block's vector reads past the end
+  q.off_mat = take((size_t(kMaxSortBlocks) << kMaxDigitBits) * 4 + 4096 * 4);
+  q.off_keys = take(size_t(cap) * 4);
   q.off_vals = take(size_t(cap) * 4);
-  q.off_ranges = take(size_t(q.T + 1) * 4);
+  q.off_keys2 = take(size_t(q.sort_passes > 0 ? cap : 1) * 4);
+  q.off_vals2 = take(size_t(q.sort_passes > 0 ? cap : 1) * 4);
+  q.off_trange = take(size_t(q.T) * 8);
   q.max_chunks = (cap + q.chunk - 1) / q.chunk + q.T;
   // partial blend states: a tile of L > chunk pairs needs ceil(L / chunk)
   // < 2 L / chunk of them, so 2 cap / chunk + 1 bounds their sum

@@ -29,7 +29,7 @@ namespace pulsar {
 // scene also writes the B-th (total) entry of each start array.
 struct SceneUpload {
   int first, count, B;
-  uint32_t total_spheres, total_tiles, total_blocks, total_units;
+  uint32_t total_spheres, total_tiles, total_blocks;
   SceneDev s[kUploadScenes];
 };
 
@@ -43,13 +43,11 @@ __global__ __launch_bounds__(64) void k_upload_scenes(SceneUpload u, SceneDev* _
     starts[b] = u.s[k].sph_off;
     starts[B1 + b] = u.s[k].tile_off;
     starts[2 * B1 + b] = u.s[k].bgblk_off;
-    starts[3 * B1 + b] = u.s[k].unit_off;
   }
   if (k == 0 && u.first + u.count == u.B) {
     starts[u.B] = u.total_spheres;
     starts[B1 + u.B] = u.total_tiles;
     starts[2 * B1 + u.B] = u.total_blocks;
-    starts[3 * B1 + u.B] = u.total_units;
   }
 }
 
@@ -63,7 +61,6 @@ static SceneUpload make_upload(const Plan& q, const std::vector<SceneDev>& sc, i
   u.total_spheres = uint32_t(q.n);
   u.total_tiles = uint32_t(q.T);
   u.total_blocks = uint32_t(q.nbgblk);
-  u.total_units = uint32_t(q.bin_units);
   for (int k = 0; k < u.count; ++k) u.s[k] = sc[size_t(first + k)];
   return u;
 }
@@ -97,13 +94,11 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
       starts_out[k] = u.s[k].sph_off;
       starts_out[B1 + k] = u.s[k].tile_off;
       starts_out[2 * B1 + k] = u.s[k].bgblk_off;
-      starts_out[3 * B1 + k] = u.s[k].unit_off;
     }
     if (k == 0) {
       starts_out[u.B] = u.total_spheres;
       starts_out[B1 + u.B] = u.total_tiles;
       starts_out[2 * B1 + u.B] = u.total_blocks;
-      starts_out[3 * B1 + u.B] = u.total_units;
     }
   }
   uint32_t count = 0;
@@ -221,16 +216,16 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
 }
 
 // Uploads the scene table (unless the projection carries it) and projects.
+// The projection runs even with no sphere (it then only writes the scene table).
 void launch_project(const Plan& q, const std::vector<SceneDev>& sc, const FwdArgs& a, char* ws,
                     hipStream_t stream) {
-  const bool inline_scenes = q.B <= kUploadScenes && q.n > 0;
+  const bool inline_scenes = q.B <= kUploadScenes;
   if (!inline_scenes) launch_upload_scenes(q, sc, ws, stream);
-  if (q.n == 0) return;
   const SceneUpload u = make_upload(q, sc, 0);
-  hipLaunchKernelGGL(k_project, dim3(q.nblk_proj), dim3(kProjectBlock), 0, stream, int(q.n),
-                     a.pos, a.radius, a.opacity, scene_table(q, ws), u, inline_scenes ? 1 : 0,
-                     ws_ptr<SceneDev>(ws, q.off_scenes), ws_ptr<uint32_t>(ws, q.off_starts),
-                     a.min_radius_px,
+  hipLaunchKernelGGL(k_project, dim3(q.nblk_proj > 0 ? q.nblk_proj : 1), dim3(kProjectBlock), 0,
+                     stream, int(q.n), a.pos, a.radius, a.opacity, scene_table(q, ws), u,
+                     inline_scenes ? 1 : 0, ws_ptr<SceneDev>(ws, q.off_scenes),
+                     ws_ptr<uint32_t>(ws, q.off_starts), a.min_radius_px,
                      ws_ptr<uint32_t>(ws, q.off_counts), ws_ptr<ushort4>(ws, q.off_trect),
                      ws_ptr<float4>(ws, q.off_rec),
                      ws_ptr<unsigned long long>(ws, q.off_partials));

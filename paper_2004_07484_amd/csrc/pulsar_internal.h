@@ -16,16 +16,14 @@ constexpr int kTileW = 8;
 constexpr int kTileH = 8;
 constexpr int kWave = 64;
 constexpr int kProjectBlock = 256;           // spheres per projection block
-// binning: the (bin block, tile) count matrix is built and read in slices of
-// kBinSlice tiles; K3 handles 64 tiles per block of kScanThreads threads, each
-// wave up to kBinRowsPerWave rows of the matrix (so at most kBinMaxG rows)
-constexpr int kBinThreads = 256;
-constexpr int kBinSliceBits = 13;
-constexpr int kBinSlice = 1 << kBinSliceBits;
-constexpr int kScanThreads = 1024;
-constexpr int kBinRowsPerWave = 16;
-constexpr int kBinMaxG = kBinRowsPerWave * (kScanThreads / 64);
-constexpr long long kBinCells = 1LL << 22;  // matrix size the bin-block sizes aim for
+// binning: a stable LSD radix sort of the pairs by tile number, digits of
+// at most kMaxDigitBits bits; every counting kernel has at most
+// kMaxSortBlocks blocks, so the block x digit count matrices stay small
+constexpr int kMaxDigitBits = 8;
+constexpr int kMaxSortBlocks = 256;
+constexpr int kSortMinBlock = 2048;          // pairs per sorting block, at least
+constexpr int kEmitThreads = 1024;
+constexpr int kEmitRound = 4 * kEmitThreads;  // spheres per emission round, 4 per thread
 constexpr int kMaxK = 32;
 constexpr int kFwdChannels = 32;             // channels per forward pass (more: several passes)
 constexpr int kBwdChannels = 32;             // channels kept in registers by the backward
@@ -40,14 +38,25 @@ constexpr uint32_t kNoSlot = 0xffffffffu;      // work item writes final pixels,
 // Device status block at the start of the workspace.
 struct Status {
   uint32_t code;                // PULSAR_OK or PULSAR_ERR_CAPACITY
-  uint32_t used;                // pairs actually stored: min(pairs, capacity)
+  uint32_t used;                // pairs stored and sorted: the pair count, or 0 past capacity
   unsigned long long pairs;     // pairs the scene produced
-  uint32_t nchunks;             // raster work items (chunks of <= chunk records of one tile)
-  uint32_t npartials;           // partial blend states needed by tiles with several chunks
-  uint32_t nfull;               // work items with exactly chunk records (listed first)
+  uint32_t nfull;               // work items with exactly chunk records (front of the list)
+  uint32_t nshort;              // shorter work items (back of the list)
+  uint32_t npartials;           // partial blend states needed by tiles with several work items
   uint32_t nmerge;              // tiles with several work items
   uint32_t pad[56];
 };
+static_assert(sizeof(Status) == 256, "status block");
+
+// Raster work items: full chunks fill the list from the front, shorter ones
+// from the back (full chunks, the costlier items, are taken first).
+__host__ __device__ inline uint32_t item_slot(uint32_t i, uint32_t nfull, uint32_t max_items) {
+  return i < nfull ? i : max_items - 1u - (i - nfull);
+}
+// Work items of the call (none after a capacity overflow).
+__device__ inline uint32_t item_count(const Status* st) {
+  return st->code == 0u ? st->nfull + st->nshort : 0u;
+}
 
 // Camera constants in the form the kernels use.
 struct CamDev {
@@ -89,24 +98,16 @@ struct SceneDev {
   uint32_t tile_off;   // first tile in the global tile numbering
   uint32_t bgblk_off;  // first background-gradient block
   unsigned long long pix_off;  // first pixel (index into the packed [P] planes)
-  // binning: the scene's spheres in bin_G bin blocks of bin_S (a multiple of
-  // kBinThreads) and its tiles in `slices` slices of kBinSlice; its work
-  // units (bin block, slice) are unit_off .. unit_off + bin_G slices - 1,
-  // bin block g's counts per tile are row row_off + g T_b of the matrix
-  uint32_t bin_S, bin_G, slices, unit_off;
-  unsigned long long row_off;
 };
 
-// Device copy of the scene table plus four ascending start arrays of B + 1
-// entries each (spheres, tiles, background blocks, binning units) for scene
-// lookup.
-constexpr int kStartArrays = 4;
+// Device copy of the scene table plus three ascending start arrays of B + 1
+// entries each (spheres, tiles, background blocks) for scene lookup.
+constexpr int kStartArrays = 3;
 struct SceneTable {
   const SceneDev* scenes;
   const uint32_t* sph_start;
   const uint32_t* tile_start;
   const uint32_t* blk_start;
-  const uint32_t* unit_start;
   int B;
 };
 
@@ -115,16 +116,17 @@ struct Plan {
   int64_t n, C, T, npix, cap, nbgblk;
   int B, chunk, raster_grid;
   int nblk_proj;
-  // binning: work units (bin block, tile slice) of all scenes and the size
-  // of the count matrix
-  int64_t bin_units, bin_cells;
+  // binning: LSD passes over the tile number and the digit width of each;
+  // emission blocks of emit_rounds rounds of kEmitRound spheres
+  int sort_passes, sort_digit, emit_rounds, nblk_emit;
   size_t off_status, off_counts, off_trect, off_rec;
   size_t off_partials, off_boff;
-  size_t off_bmat;    // [G, T] pairs per (bin block, tile), then their offsets inside the tile
-  size_t off_tcount;  // [T] pairs per tile
-  size_t off_gsum;    // [T / 64] sums over groups of 64 tiles (pairs, work-item counts)
+  size_t off_ebase;   // [nblk_emit + 1] first pair of each emission block (u64)
+  size_t off_mat;     // block x digit counts of the current pass, digit-major
+  size_t off_keys;    // [cap] tile of every pair, sorted (the final pass's output)
   size_t off_vals;    // [cap] sphere index of every pair, tile by tile
-  size_t off_ranges;  // [T + 1] first pair of each tile
+  size_t off_keys2, off_vals2;  // the other buffers of the ping-pong
+  size_t off_trange;  // [T] first and end pair of each tile (uint2)
   // raster work items: per tile uint4 (first partial-state slot, chunks, 0, 0);
   // the work list uint4 (tile | kFirstChunk, begin, end, slot or kNoSlot);
   // block sums of the chunk scan; the partial blend states; the per-pixel
@@ -229,7 +231,6 @@ inline SceneTable scene_table(const Plan& q, char* ws) {
   t.sph_start = st;
   t.tile_start = st + (q.B + 1);
   t.blk_start = st + 2 * (q.B + 1);
-  t.unit_start = st + 3 * (q.B + 1);
   t.B = q.B;
   return t;
 }

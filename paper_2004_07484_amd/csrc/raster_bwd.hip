@@ -29,6 +29,7 @@ struct BwdKernelArgs {
   SceneTable tab;
   Status* status;
   const uint4* desc;
+  uint32_t max_items;  // capacity of the work list (short items fill it from the back)
   const float4* rec;                // sphere records, 4 float4 per sphere
   const float* payload;             // the caller's payload rows [n, C]
   const unsigned long long* boff;   // first pair of each projection block
@@ -130,9 +131,9 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
   __shared__ uint32_t s_ik[kWave];
   const int tid = threadIdx.x;
   const int C = A.C;
-  const uint32_t nchunks = A.status->nchunks;
+  const uint32_t nchunks = item_count(A.status), nfull = A.status->nfull;
   for (uint32_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
-    const uint4 dsc = desc[chunk];
+    const uint4 dsc = desc[item_slot(chunk, nfull, A.max_items)];
     const uint32_t tile = dsc.x & ~kFirstChunk;
     const uint32_t beg = dsc.y, end = dsc.z;
     const TileScene ts = tile_scene(scenes, tile_start, A.tab.B, tile);
@@ -271,9 +272,9 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A,
   __shared__ uint32_t s_ik[kWave];
   const int lane = threadIdx.x;
   const int C = A.C;
-  const uint32_t nchunks = A.status->nchunks;
+  const uint32_t nchunks = item_count(A.status), nfull = A.status->nfull;
   for (uint32_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
-    const uint4 dsc = desc[chunk];
+    const uint4 dsc = desc[item_slot(chunk, nfull, A.max_items)];
     const uint32_t tile = dsc.x & ~kFirstChunk;
     const uint32_t beg = dsc.y, end = dsc.z;
     const TileScene ts = tile_scene(scenes, tile_start, A.tab.B, tile);
@@ -824,6 +825,7 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
   A.tab = tab;
   A.status = ws_ptr<Status>(ws, q.off_status);
   A.desc = ws_ptr<uint4>(ws, q.off_desc);
+  A.max_items = uint32_t(q.max_chunks);
   A.rec = ws_ptr<float4>(ws, q.off_rec);
   A.payload = a.payload;
   A.boff = ws_ptr<unsigned long long>(ws, q.off_boff);

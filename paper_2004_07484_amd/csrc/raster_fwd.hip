@@ -99,6 +99,7 @@ struct FwdKernelArgs {
   SceneTable tab;
   Status* status;
   const uint4* desc;
+  uint32_t max_items;  // capacity of the work list (short items fill it from the back)
   const uint4* tinfo;
   const uint32_t* mlist;
   const uint32_t* svals;            // sphere index of every sorted pair
@@ -219,9 +220,9 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM)) void k_fwd_chunk
 #pragma unroll
   for (int c = 0; c < CM; ++c)
     if (c >= A.cn) s_pay[c][lane] = 0.f;
-  const uint32_t nchunks = A.status->nchunks;
+  const uint32_t nchunks = item_count(A.status), nfull = A.status->nfull;
   for (uint32_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
-    const uint4 dsc = desc[chunk];
+    const uint4 dsc = desc[item_slot(chunk, nfull, A.max_items)];
     const uint32_t tile = dsc.x & ~kFirstChunk;
     const bool first = (dsc.x & kFirstChunk) != 0u;
     const uint32_t beg = dsc.y, end = dsc.z, slot = dsc.w;
@@ -412,7 +413,7 @@ __global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(
   constexpr int NF = 2 + CM + 2 * KM;  // m, D, numerator[CM], K-list t[KM], id[KM]
   __shared__ float s_state[kMergeWaves - 1][NF][kWave];
   const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
-  const uint32_t nmerge = A.status->nmerge;
+  const uint32_t nmerge = A.status->code == 0u ? A.status->nmerge : 0u;
   for (uint32_t mi = blockIdx.x; mi < nmerge; mi += gridDim.x) {
     const int tile = int(mlist[mi]);
     const uint4 ti = tinfo[tile];
@@ -531,6 +532,7 @@ static FwdKernelArgs raster_args(const Plan& q, const std::vector<SceneDev>& sce
   A.tab = scene_table(q, ws);
   A.status = ws_ptr<Status>(ws, q.off_status);
   A.desc = ws_ptr<uint4>(ws, q.off_desc);
+  A.max_items = uint32_t(q.max_chunks);
   A.tinfo = ws_ptr<uint4>(ws, q.off_tinfo);
   A.mlist = ws_ptr<uint32_t>(ws, q.off_mlist);
   A.svals = ws_ptr<uint32_t>(ws, q.off_vals);
