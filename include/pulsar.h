@@ -56,6 +56,9 @@ extern "C" {
 /* reported by pulsar_query_status only: the (tile, sphere) pairs of the last
  * forward did not fit into max_pairs; its outputs are invalid */
 #define PULSAR_ERR_CAPACITY (-5)
+/* pulsar_fwd_noalloc only: the call needs more workspace than its static
+ * scratch buffer holds (PULSAR_NOALLOC_SCRATCH_BYTES) */
+#define PULSAR_ERR_SCRATCH (-6)
 
 /* Pinhole camera (Sec. 3.2, Lst. 1: focal length f and sensor width s share
  * one unit). Host struct, passed by pointer. */
@@ -174,6 +177,28 @@ int pulsar_fwd(const float* pos, const float* radius, const float* opacity,
                const float* payload, int32_t n, int32_t C, const float* background,
                const pulsar_camera_t* cam, const pulsar_params_t* params, float* image,
                float* aux, void* ws, size_t ws_bytes, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * pulsar_fwd with no workspace argument. Every other argument, result and
+ * error is that of pulsar_fwd. The workspace is a static device array of
+ * PULSAR_NOALLOC_SCRATCH_BYTES that every GPU the library runs this call on
+ * holds until the process ends; the call allocates no device memory. A call
+ * whose pulsar_workspace_size exceeds it returns PULSAR_ERR_SCRATCH before
+ * anything is enqueued. All calls on one GPU share that GPU's array, which
+ * keeps the last call's contents (nothing in it needs clearing): calls whose
+ * work overlaps on one GPU (other streams, other threads) race and must be
+ * serialised by the caller, and a pulsar_bwd cannot reuse the state (use a
+ * workspace and PULSAR_REBIN for gradients). The device status of the call
+ * lives in that array and cannot be queried: a call whose (tile, sphere)
+ * pairs exceed params.max_pairs leaves invalid outputs, so size max_pairs
+ * for the scene (the default, 2 n + tiles + 65536, holds any scene whose
+ * spheres touch two tiles each on average). */
+#define PULSAR_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int pulsar_fwd_noalloc(const float* pos, const float* radius, const float* opacity,
+                       const float* payload, int32_t n, int32_t C, const float* background,
+                       const pulsar_camera_t* cam, const pulsar_params_t* params, float* image,
+                       float* aux, void* stream);
 
 /* Backward pass (App. B, "The Backward Pass"): given grad_image = dLoss/dF
  * [H,W,C], writes (overwrites, never accumulates)

@@ -21,12 +21,14 @@ PULSAR_ERR_WORKSPACE = -2
 PULSAR_ERR_UNSUPPORTED = -3
 PULSAR_ERR_HIP = -4
 PULSAR_ERR_CAPACITY = -5
+PULSAR_ERR_SCRATCH = -6
+PULSAR_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 EXPORTED = ("pulsar_workspace_size", "pulsar_fwd", "pulsar_bwd", "pulsar_batch_workspace_size",
             "pulsar_fwd_batched", "pulsar_bwd_batched", "pulsar_bwd_camera",
             "pulsar_bwd_camera_batched", "pulsar_query_status",
             "pulsar_status_string", "pulsar_last_hip_error", "pulsar_timing_enable",
-            "pulsar_timing_read", "pulsar_stage_name", "pulsar_version")
+            "pulsar_timing_read", "pulsar_stage_name", "pulsar_version", "pulsar_fwd_noalloc")
 
 PULSAR_NUM_STAGES = 7
 PULSAR_NO_BWD_AUX = 0x1   # forward keeps no backward state
@@ -89,6 +91,10 @@ def load():
     lib.pulsar_fwd.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp,
                                ctypes.POINTER(pulsar_camera_t), ctypes.POINTER(pulsar_params_t),
                                _vp, _vp, _vp, ctypes.c_size_t, _vp]
+    lib.pulsar_fwd_noalloc.restype = ctypes.c_int
+    lib.pulsar_fwd_noalloc.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp,
+                                       ctypes.POINTER(pulsar_camera_t),
+                                       ctypes.POINTER(pulsar_params_t), _vp, _vp, _vp]
     lib.pulsar_bwd.restype = ctypes.c_int
     lib.pulsar_bwd.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp,
                                ctypes.POINTER(pulsar_camera_t), ctypes.POINTER(pulsar_params_t),
@@ -245,6 +251,21 @@ def pulsar_fwd(pos, radius, opacity, payload, background, cam: pulsar_camera_t,
         _ws_ptr(ws), int(ws.numel()), _stream(stream))
     if rc != PULSAR_OK:
         raise PulsarError(rc, "pulsar_fwd")
+
+
+def pulsar_fwd_noalloc(pos, radius, opacity, payload, background, cam: pulsar_camera_t,
+                       params: pulsar_params_t, image, aux, stream=None) -> None:
+    """pulsar_fwd on the library's static scratch buffer (no workspace)."""
+    n, C = int(payload.shape[0]), int(payload.shape[1])
+    H, W = int(cam.height), int(cam.width)
+    rc = load().pulsar_fwd_noalloc(
+        _ptr(pos, "pos", n > 0, (n, 3)), _ptr(radius, "radius", n > 0, (n,)),
+        _ptr(opacity, "opacity", False, (n,)), _ptr(payload, "payload", n > 0, (n, C)), n, C,
+        _ptr(background, "background", True, (C,)), ctypes.byref(cam), ctypes.byref(params),
+        _ptr(image, "image", True, (H, W, C)), _ptr(aux, "aux", False, (H, W)),
+        _stream(stream))
+    if rc != PULSAR_OK:
+        raise PulsarError(rc, "pulsar_fwd_noalloc")
 
 
 def pulsar_bwd(pos, radius, opacity, payload, background, cam: pulsar_camera_t,

@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpulsar.so")
 
-SOURCES = ["capi.cpp", "project.hip", "binning.hip", "raster_fwd.hip", "raster_bwd.hip"]
+SOURCES = ["capi.cpp", "project.hip", "binning.hip", "raster_fwd.hip", "raster_bwd.hip",
+           "noalloc.hip"]
 HEADERS = ["pulsar_internal.h", "device_common.h"]
 
 HIPFLAGS = [

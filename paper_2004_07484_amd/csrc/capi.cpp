@@ -500,6 +500,9 @@ const char* pulsar_status_string(int code) {
       return "HIP launch or runtime error (see pulsar_last_hip_error)";
     case PULSAR_ERR_CAPACITY:
       return "tile-pair capacity exceeded: raise params.max_pairs and render again";
+    case PULSAR_ERR_SCRATCH:
+      return "the call needs more than the static scratch buffer of pulsar_fwd_noalloc holds: "
+             "use pulsar_fwd with a workspace";
     default:
       return "unknown status code";
   }

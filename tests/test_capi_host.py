@@ -44,7 +44,7 @@ def test_header_declarations_are_exported():
 def test_version_and_status_strings():
     _lib()
     assert _capi.pulsar_version() == 3
-    for code in [0, -1, -2, -3, -4, -5, -99]:
+    for code in [0, -1, -2, -3, -4, -5, -6, -99]:
         assert len(_capi.pulsar_status_string(code)) > 5
     assert "capacity" in _capi.pulsar_status_string(_capi.PULSAR_ERR_CAPACITY)
 
@@ -307,3 +307,22 @@ def test_flag_constants_mirror_the_header():
     preset = re.search(r"^#define PULSAR_MIN_RADIUS_PX_PAPER ([0-9.]+)f$", text, re.M)
     assert preset and abs(float(preset.group(1)) - _capi.PULSAR_MIN_RADIUS_PX_PAPER) < 1e-8
     assert abs(_capi.PULSAR_MIN_RADIUS_PX_PAPER - 0.5 * 2 ** 0.5) < 1e-8
+
+
+def test_noalloc_forward_rejects_what_its_scratch_cannot_hold():
+    """pulsar_fwd_noalloc checks its static scratch size on the host, before
+    any HIP call; invalid requests get pulsar_fwd's own validation error."""
+    lib = _lib()
+    p = _capi.make_params(K=8)
+    cam = _cam(width=4096, height=4096)
+    need = _capi.pulsar_workspace_size(2_000_000, 4096, 4096, 3, p)
+    assert need > _capi.PULSAR_NOALLOC_SCRATCH_BYTES
+    rc = lib.pulsar_fwd_noalloc(FAKE, FAKE, None, FAKE, 2_000_000, 3, FAKE, ctypes.byref(cam),
+                                ctypes.byref(p), FAKE, FAKE, None)
+    assert rc == _capi.PULSAR_ERR_SCRATCH
+    assert "scratch" in _capi.pulsar_status_string(rc)
+    rc = lib.pulsar_fwd_noalloc(FAKE, FAKE, None, FAKE, 10, 0, FAKE, ctypes.byref(_cam()),
+                                ctypes.byref(p), FAKE, FAKE, None)
+    assert rc == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    assert lib.pulsar_fwd_noalloc(FAKE, FAKE, None, FAKE, 10, 3, FAKE, None, ctypes.byref(p),
+                                  FAKE, FAKE, None) == _capi.PULSAR_ERR_INVALID_ARGUMENT
