@@ -149,7 +149,23 @@ typedef struct pulsar_params {
   int32_t raster_blocks;/* blocks of the persistent raster kernels: 0 = automatic
                            (4096), else in [256, 65536]. Never changes the image;
                            gradients only within float atomic reordering. */
-  int32_t reserved;     /* must be 0 */
+  float stop_share;     /* early ray termination (Sec. 3.2 and App. B, Step 2):
+                           0 = off (default; every hit blends). In (0, 1):
+                           each pixel takes its hits in ascending order of
+                           their sphere's earliest possible hit distance
+                           (float32 of |c| - R, c_z - R orthographic; ties by
+                           index) and stops before the first hit whose
+                           largest possible weight exp(z(that distance) /
+                           gamma) is below stop_share / (1 - stop_share) of
+                           the running denominator of Eq. 1 (opacity <= 1 is
+                           assumed for the bound): no farther sphere can then
+                           take that share of the pixel. Only the blended
+                           hits enter the image, the log-normaliser and the K
+                           nearest that pulsar_bwd differentiates. Every tile
+                           is then one work item (chunk is ignored) and its
+                           list is sorted by that distance. Combining it with
+                           PULSAR_BLEND_TOPK is PULSAR_ERR_UNSUPPORTED;
+                           pulsar_bwd must get the forward's value. */
 } pulsar_params_t;
 
 /* Bytes of device workspace one pulsar_fwd / pulsar_bwd pair needs for n

@@ -64,7 +64,7 @@ class pulsar_params_t(ctypes.Structure):
                 ("min_radius_px", ctypes.c_float), ("K", ctypes.c_int32),
                 ("flags", ctypes.c_uint32), ("max_pairs", ctypes.c_int32),
                 ("depth_bits", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("raster_blocks", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("raster_blocks", ctypes.c_int32), ("stop_share", ctypes.c_float)]
 
 
 class pulsar_scene_t(ctypes.Structure):
@@ -158,12 +158,13 @@ def make_camera(R, t, focal, sensor_width, znear, zfar, width, height) -> pulsar
 
 
 def make_params(gamma=0.1, eps=1e-5, min_radius_px=0.0, K=8, max_pairs=0,
-                depth_bits=0, chunk=0, raster_blocks=0, flags=0) -> pulsar_params_t:
+                depth_bits=0, chunk=0, raster_blocks=0, flags=0,
+                stop_share=0.0) -> pulsar_params_t:
     p = pulsar_params_t()
     p.gamma, p.eps, p.min_radius_px = float(gamma), float(eps), float(min_radius_px)
-    p.K, p.flags, p.max_pairs, p.depth_bits, p.reserved = int(K), int(flags), int(max_pairs), \
-        int(depth_bits), 0
-    p.chunk, p.raster_blocks = int(chunk), int(raster_blocks)
+    p.K, p.flags, p.max_pairs, p.depth_bits = int(K), int(flags), int(max_pairs), \
+        int(depth_bits)
+    p.chunk, p.raster_blocks, p.stop_share = int(chunk), int(raster_blocks), float(stop_share)
     return p
 
 

@@ -469,6 +469,87 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(uint32_t T, const uint2* 
   }
 }
 
+// ---------------------------------------------------------------- early termination
+// With early termination every tile's list is put in ascending order of
+// (earliest possible hit distance, sphere index): the order of the paper's
+// depth sort (App. B, Step 0), which the tile lists keep per tile. One block
+// per tile sorts 64-bit keys (distance bits above the index; distances are
+// positive, so their bits order like the floats) with a bitonic network whose
+// every compare-exchange puts the smaller key first: each merge of two
+// sorted runs of k/2 starts by comparing element i with its mirror
+// i ^ (k - 1), then halves. Positions past the list's end act as +infinity
+// keys; with every exchange ascending they never swap, so those compares are
+// skipped and a list of any length sorts in place. In LDS for up to
+// kTileSortLds keys, else on the list in global memory (each compare gathers
+// the two distances), which only extreme scenes need.
+constexpr int kTileSortThreads = 256;
+constexpr int kTileSortLds = 4096;
+
+__device__ __forceinline__ uint64_t depth_key(const float* __restrict__ tmin, uint32_t sph) {
+  return (uint64_t(__float_as_uint(tmin[sph])) << 32) | uint64_t(sph);
+}
+
+// One step of the network over L keys: partner of i is i ^ (k - 1) in the
+// first step of a merge (flip), i ^ j after it.
+template <typename Get, typename Put>
+__device__ __forceinline__ void bitonic_step(uint32_t L, uint32_t mask, bool flip, Get get,
+                                             Put put) {
+  for (uint32_t i = threadIdx.x; i < L; i += kTileSortThreads) {
+    const uint32_t ij = i ^ mask;
+    if (ij > i && ij < L) {
+      const uint64_t a = get(i), b = get(ij);
+      if (a > b) {
+        put(i, b);
+        put(ij, a);
+      }
+    }
+  }
+  (void)flip;
+}
+
+__global__ __launch_bounds__(kTileSortThreads) void k_tile_sort(
+    uint32_t T, const uint2* __restrict__ trange, const float* __restrict__ tmin,
+    const Status* __restrict__ status, uint32_t* __restrict__ vals) {
+  __shared__ uint64_t s_key[kTileSortLds];
+  if (status->code != 0u) return;
+  const uint32_t t = blockIdx.x;
+  if (t >= T) return;
+  const uint2 tr = trange[t];
+  const uint32_t L = tr.y - tr.x;
+  if (L < 2u) return;
+  uint32_t m = 2;
+  while (m < L) m <<= 1;
+  uint32_t* v = vals + tr.x;
+  if (L <= uint32_t(kTileSortLds)) {
+    for (uint32_t i = threadIdx.x; i < L; i += kTileSortThreads) s_key[i] = depth_key(tmin, v[i]);
+    __syncthreads();
+    auto get = [&](uint32_t i) { return s_key[i]; };
+    auto put = [&](uint32_t i, uint64_t x) { s_key[i] = x; };
+    for (uint32_t k = 2; k <= m; k <<= 1) {
+      bitonic_step(L, k - 1u, true, get, put);
+      __syncthreads();
+      for (uint32_t j = k >> 2; j > 0; j >>= 1) {
+        bitonic_step(L, j, false, get, put);
+        __syncthreads();
+      }
+    }
+    for (uint32_t i = threadIdx.x; i < L; i += kTileSortThreads) v[i] = uint32_t(s_key[i]);
+    return;
+  }
+  auto get = [&](uint32_t i) { return depth_key(tmin, v[i]); };
+  auto put = [&](uint32_t i, uint64_t x) { v[i] = uint32_t(x); };
+  for (uint32_t k = 2; k <= m; k <<= 1) {
+    bitonic_step(L, k - 1u, true, get, put);
+    __threadfence_block();
+    __syncthreads();
+    for (uint32_t j = k >> 2; j > 0; j >>= 1) {
+      bitonic_step(L, j, false, get, put);
+      __threadfence_block();
+      __syncthreads();
+    }
+  }
+}
+
 void launch_binning(const Plan& q, char* ws, hipStream_t stream) {
   Status* status = ws_ptr<Status>(ws, q.off_status);
   // pass p reads buffer p % 2 and writes the other; the last pass ends in
@@ -524,6 +605,10 @@ void launch_binning(const Plan& q, char* ws, hipStream_t stream) {
                      (long long)q.pcap, uint32_t(q.max_chunks), status,
                      ws_ptr<uint4>(ws, q.off_tinfo), ws_ptr<uint4>(ws, q.off_desc),
                      ws_ptr<uint32_t>(ws, q.off_mlist));
+  if (q.estop)
+    hipLaunchKernelGGL(k_tile_sort, dim3(unsigned(q.T)), dim3(kTileSortThreads), 0, stream,
+                       uint32_t(q.T), E.trange, ws_ptr<float>(ws, q.off_tmin), status,
+                       ws_ptr<uint32_t>(ws, q.off_vals));
 }
 
 }  // namespace pulsar

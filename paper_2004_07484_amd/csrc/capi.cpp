@@ -57,9 +57,12 @@ int check_params(const pulsar_params_t* p) {
   if (p->raster_blocks != 0 && (p->raster_blocks < 256 || p->raster_blocks > 65536))
     return PULSAR_ERR_INVALID_ARGUMENT;
   if ((p->flags & ~(PULSAR_NO_BWD_AUX | PULSAR_REBIN | PULSAR_GRAD_PAPER_NORM |
-                    PULSAR_BLEND_TOPK | PULSAR_ORTHO)) != 0u ||
-      p->reserved != 0)
+                    PULSAR_BLEND_TOPK | PULSAR_ORTHO)) != 0u)
     return PULSAR_ERR_UNSUPPORTED;
+  if (!std::isfinite(p->stop_share) || p->stop_share < 0.f || p->stop_share >= 1.f)
+    return PULSAR_ERR_INVALID_ARGUMENT;
+  // the top-K blend with early termination is not built
+  if (p->stop_share > 0.f && (p->flags & PULSAR_BLEND_TOPK) != 0u) return PULSAR_ERR_UNSUPPORTED;
   return PULSAR_OK;
 }
 
@@ -162,6 +165,10 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   q.npix = int64_t(last.pix_off) + lastpix;
   q.nbgblk = int64_t(last.bgblk_off) + (lastpix + kBgBlockPixels - 1) / kBgBlockPixels;
   q.chunk = p->chunk > 0 ? p->chunk : kChunkDefault;
+  // early termination walks each tile's whole list in order: one work item
+  // per tile (no partial states, no merge)
+  q.estop = p->stop_share > 0.f ? 1 : 0;
+  if (q.estop) q.chunk = 1 << 30;
   q.raster_grid = p->raster_blocks > 0 ? p->raster_blocks : kRasterGridDefault;
   const int64_t n = q.n;
   int64_t cap = p->max_pairs > 0 ? int64_t(p->max_pairs) : 2 * n + q.T + 65536;
@@ -204,6 +211,8 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   q.off_keys2 = take(size_t(q.sort_passes > 0 ? cap : 1) * 4);
   q.off_vals2 = take(size_t(q.sort_passes > 0 ? cap : 1) * 4);
   q.off_trange = take(size_t(q.T) * 8);
+  // early termination: every sphere's earliest possible hit distance
+  q.off_tmin = take(q.estop ? nn * 4 : 0);
   q.max_chunks = (cap + q.chunk - 1) / q.chunk + q.T;
   // partial blend states: a tile of L > chunk pairs needs ceil(L / chunk)
   // < 2 L / chunk of them, so 2 cap / chunk + 1 bounds their sum
@@ -222,6 +231,8 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   q.off_bgsum = take(bwd ? size_t(q.nbgblk) * size_t(C) * 4 : 0);
   q.off_pstate = take(size_t(q.pcap) * kWave * size_t(q.pstride) * 4);
   q.off_thr = take(thr ? size_t(q.npix) * 8 : 0);
+  // early termination: per pixel the first hit it skipped, for the backward
+  q.off_stop = take(q.estop ? size_t(q.npix) * 8 : 0);
   q.off_mlist = take(size_t(q.T) * 4);
   // the backward kernel instance keeps cm >= C channels, a power of two up to
   // 32; wider payloads keep only dL/dc, dL/dR | dL/do in the record
@@ -329,6 +340,7 @@ int pulsar_fwd_batched(const pulsar_scene_t* scenes, int32_t B, const float* pos
   a.min_radius_px = params->min_radius_px;
   a.track = aux != nullptr && (params->flags & PULSAR_NO_BWD_AUX) == 0u;
   a.topk = (params->flags & PULSAR_BLEND_TOPK) != 0u;
+  a.stop_share = params->stop_share;
   hipError_t e = launch_forward(q, sc, a, static_cast<char*>(ws),
                                 static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail_hip(e);
@@ -372,6 +384,7 @@ static int bwd_impl(const pulsar_scene_t* scenes, int32_t B, const float* pos,
     f.min_radius_px = params->min_radius_px;
     f.track = true;
     f.topk = false;
+    f.stop_share = params->stop_share;
     hipError_t e = launch_rebin(q, sc, f, static_cast<char*>(ws),
                                 static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail_hip(e);

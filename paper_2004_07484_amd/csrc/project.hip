@@ -84,7 +84,12 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
     const float* __restrict__ opacity, SceneTable tab, SceneUpload u, int inline_scenes,
     SceneDev* __restrict__ tab_out, uint32_t* __restrict__ starts_out, float min_radius_px,
     uint32_t* __restrict__ counts, ushort4* __restrict__ trect, float4* __restrict__ rec,
-    unsigned long long* __restrict__ partials) {
+    unsigned long long* __restrict__ partials, float* __restrict__ tmin_out) {
+  // no FMA contraction: the camera transform, the minimum size and the
+  // earliest hit distance are the IEEE double evaluations of the same
+  // expressions, term by term (early termination orders spheres by the
+  // float32 of that distance)
+#pragma clang fp contract(off)
   const int i = blockIdx.x * kProjectBlock + threadIdx.x;
   if (inline_scenes && blockIdx.x == 0 && threadIdx.x < kWave) {
     const int k = threadIdx.x;
@@ -139,6 +144,7 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
     // the nearest point any ray can reach
     const double tmin = ortho ? cz - R : sqrt(cx * cx + cy * cy + cz * cz) - R;
     ok = ok && (tmin <= double(cam.zfar));
+    if (tmin_out) tmin_out[i] = ok ? float(tmin) : INFINITY;
     if (ok) {
       // The cone of rays through the sphere lies between the two planes through
       // the camera centre tangent to it; on the plane z = f they bound
@@ -228,7 +234,8 @@ void launch_project(const Plan& q, const std::vector<SceneDev>& sc, const FwdArg
                      ws_ptr<uint32_t>(ws, q.off_starts), a.min_radius_px,
                      ws_ptr<uint32_t>(ws, q.off_counts), ws_ptr<ushort4>(ws, q.off_trect),
                      ws_ptr<float4>(ws, q.off_rec),
-                     ws_ptr<unsigned long long>(ws, q.off_partials));
+                     ws_ptr<unsigned long long>(ws, q.off_partials),
+                     q.estop ? ws_ptr<float>(ws, q.off_tmin) : nullptr);
 }
 
 }  // namespace pulsar

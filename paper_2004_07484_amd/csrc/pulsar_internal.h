@@ -119,6 +119,9 @@ struct Plan {
   // binning: LSD passes over the tile number and the digit width of each;
   // emission blocks of emit_rounds rounds of kEmitRound spheres
   int sort_passes, sort_digit, emit_rounds, nblk_emit;
+  int estop;          // early termination: tiles are sorted by earliest hit distance
+  size_t off_tmin;    // [n] float32 earliest possible hit distance (early termination)
+  size_t off_stop;    // [npix] (distance, pair position) of the first skipped hit
   size_t off_status, off_counts, off_trect, off_rec;
   size_t off_partials, off_boff;
   size_t off_ebase;   // [nblk_emit + 1] first pair of each emission block (u64)
@@ -173,6 +176,7 @@ struct FwdArgs {
   float min_radius_px;
   bool track;  // keep each pixel's K nearest hits for a following backward
   bool topk;   // blend only each pixel's K nearest hits
+  float stop_share;  // early termination share (0: off)
 };
 
 struct BwdArgs {

@@ -47,6 +47,10 @@ struct BwdKernelArgs {
   float* bgsum;       // background-gradient block sums, or null
   uint32_t nbgblk;
   float eps2;
+  // early termination: each sphere's earliest possible hit distance and per
+  // pixel the first hit the forward skipped (hits from it on take no part)
+  const float* tmin;
+  const float2* stop;
 };
 
 constexpr int kBgThreads = 256;
@@ -121,7 +125,8 @@ constexpr int kBwdWaves = 4;
 // instances keep the compiler's budget.
 constexpr int bwd_waves_per_simd(int CM) { return CM <= 4 ? 5 : (CM <= 8 ? 4 : 1); }
 
-template <int CM, bool CAM>
+// ES: early termination (hits from each pixel's first skipped one on take no part).
+template <int CM, bool CAM, bool ES>
 __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_bwd_items(
     BwdKernelArgs A, const SceneDev* __restrict__ scenes, const uint32_t* __restrict__ tile_start,
     const uint4* __restrict__ desc) {
@@ -129,6 +134,7 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
   __shared__ float s_G[CM][kWave];
   __shared__ float s_L2[kWave], s_GF[kWave], s_tk[kWave];
   __shared__ uint32_t s_ik[kWave];
+  __shared__ uint64_t s_sk[ES ? kWave : 1];  // early termination: first skipped hit
   const int tid = threadIdx.x;
   const int C = A.C;
   const uint32_t nchunks = item_count(A.status), nfull = A.status->nfull;
@@ -146,6 +152,7 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
     uint32_t j = beg + uint32_t(tid);
     float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra, rc = ra, rd = ra;
     uint32_t bo = 0;
+    float tmin = 0.f;
     float f[CM];
 #pragma unroll
     for (int c = 0; c < CM; ++c) f[c] = 0.f;
@@ -156,6 +163,7 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
       rb = rp[1];
       rc = rp[2];
       rd = rp[3];
+      if (ES) tmin = A.tmin[sph];
       bo = uint32_t(A.boff[sph / kProjectBlock]);
       const float* fp = A.payload + size_t(sph) * size_t(C);
       // unconditional loads (clamped to the row), so they issue together
@@ -177,6 +185,10 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
                                                           size_t(ts.tx0));
       const float aux = A.aux[p];
       const float2 th = A.thr[p];
+      if (ES) {
+        const float2 st = A.stop[p];
+        s_sk[tid] = inside ? (uint64_t(__float_as_uint(st.x)) << 32) | __float_as_uint(st.y) : 0ull;
+      }
       float gi[CM], fi[CM];
 #pragma unroll
       for (int c = 0; c < CM; ++c) {
@@ -210,12 +222,16 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
       float gcx = 0.f, gcy = 0.f, gcz = 0.f, gR = 0.f, go = 0.f, gk = 0.f;
       uint32_t nh = 0;
       const float tlo = front_bound(s);
+      // early termination: the sphere's place in the depth-sort order
+      const uint64_t dkey = ES ? (uint64_t(__float_as_uint(tmin)) << 32) | id : 0ull;
       for (int py = ya; py <= yb; ++py) {
         for (int px = xa; px <= xb; ++px) {
           const int pl = (py - ts.ty0) * kTileW + (px - ts.tx0);
           const float tk = s_tk[pl];
           // behind the pixel's K-th nearest hit: no gradient, no test needed
           if (tlo > tk) continue;
+          // at or after the hit where the pixel stopped: never blended
+          if (ES && dkey >= s_sk[pl]) continue;
           const PixelRay ray = load_ray(s_ray, pl, px, py);
           Hit h;
           if (!exact_hit(ray, s, bc.zfar, h)) continue;
@@ -270,6 +286,7 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A,
   __shared__ TileRays s_ray;
   __shared__ float s_L2[kWave], s_tk[kWave];
   __shared__ uint32_t s_ik[kWave];
+  __shared__ uint64_t s_sk[kWave];  // early termination: first skipped hit
   const int lane = threadIdx.x;
   const int C = A.C;
   const uint32_t nchunks = item_count(A.status), nfull = A.status->nfull;
@@ -292,6 +309,10 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A,
     const float2 th = inside ? A.thr[p] : make_float2(-INFINITY, 0.f);
     s_tk[lane] = th.x;
     s_ik[lane] = __float_as_uint(th.y);
+    if (A.stop) {
+      const float2 st = inside ? A.stop[p] : make_float2(0.f, 0.f);
+      s_sk[lane] = (uint64_t(__float_as_uint(st.x)) << 32) | __float_as_uint(st.y);
+    }
     __syncthreads();
     for (uint32_t b0 = beg; b0 < end; b0 += kWave) {
       const uint32_t j = b0 + uint32_t(lane);
@@ -309,11 +330,14 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A,
       const int xa = max(s.x0, tx0), xb = min(int(p1 & 0xffffu), tx0 + kTileW - 1);
       const int ya = max(s.y0, ty0), yb = min(int(p1 >> 16), ty0 + kTileH - 1);
       const float tlo = front_bound(s);
+      const uint64_t dkey =
+          A.stop ? (uint64_t(__float_as_uint(A.tmin[id])) << 32) | slot : 0ull;
       for (int iy = ya; iy <= yb; ++iy) {
         for (int ix = xa; ix <= xb; ++ix) {
           const int pl = (iy - ty0) * kTileW + (ix - tx0);
           const float tk = s_tk[pl];
           if (tlo > tk) continue;  // behind the K-th nearest hit
+          if (A.stop && dkey >= s_sk[pl]) continue;  // after the pixel's early stop
           const PixelRay ray = load_ray(s_ray, pl, ix, iy);
           Hit h;
           if (!exact_hit(ray, s, bc.zfar, h)) continue;
@@ -700,14 +724,22 @@ __global__ __launch_bounds__(kBgThreads) void k_bg_partial_wide(SceneTable tab,
   }
 }
 
-template <int CM>
-static void launch_items(const BwdKernelArgs& A, dim3 grid, dim3 block, hipStream_t stream) {
+template <int CM, bool ES>
+static void launch_items_es(const BwdKernelArgs& A, dim3 grid, dim3 block, hipStream_t stream) {
   if (A.need_cam)
-    hipLaunchKernelGGL((k_bwd_items<CM, true>), grid, block, 0, stream, A, A.tab.scenes,
+    hipLaunchKernelGGL((k_bwd_items<CM, true, ES>), grid, block, 0, stream, A, A.tab.scenes,
                        A.tab.tile_start, A.desc);
   else
-    hipLaunchKernelGGL((k_bwd_items<CM, false>), grid, block, 0, stream, A, A.tab.scenes,
+    hipLaunchKernelGGL((k_bwd_items<CM, false, ES>), grid, block, 0, stream, A, A.tab.scenes,
                        A.tab.tile_start, A.desc);
+}
+
+template <int CM>
+static void launch_items(const BwdKernelArgs& A, dim3 grid, dim3 block, hipStream_t stream) {
+  if (A.stop)
+    launch_items_es<CM, true>(A, grid, block, stream);
+  else
+    launch_items_es<CM, false>(A, grid, block, stream);
 }
 
 template <int CM>
@@ -847,6 +879,8 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
   A.bgsum = (a.grad_bg && !wide) ? ws_ptr<float>(ws, q.off_bgsum) : nullptr;
   A.nbgblk = uint32_t(q.nbgblk);
   A.eps2 = a.eps2;
+  A.tmin = q.estop ? ws_ptr<float>(ws, q.off_tmin) : nullptr;
+  A.stop = q.estop ? ws_ptr<float2>(ws, q.off_stop) : nullptr;
   float* bgsum = ws_ptr<float>(ws, q.off_bgsum);
   const uint32_t* counts = ws_ptr<uint32_t>(ws, q.off_counts);
   stage_begin(PULSAR_STAGE_ZERO, stream);

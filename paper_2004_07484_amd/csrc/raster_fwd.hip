@@ -23,6 +23,8 @@
 // leaves a partial state (m, D, numerator, K-list) and k_fwd_merge combines
 // them in chunk order, so the result is deterministic. After its work items
 // the same grid fills the tiles that no sphere touches.
+#include <cmath>
+
 #include "hit_geometry.h"
 
 namespace pulsar {
@@ -120,13 +122,20 @@ struct FwdKernelArgs {
   uint32_t T;                         // tiles of all scenes
   int fill_in_tail;                   // empty tiles filled by the work-item kernel
   float eps2;                         // background exponent (base 2)
+  // early termination: each sphere's earliest possible hit distance, the
+  // per-pixel first skipped hit (t_min, pair position), and log2 of
+  // share / (1 - share)
+  const float* tmin;
+  float2* stop;
+  float lrho2;
 };
 
 template <int CM, int KM>
 __device__ __forceinline__ void write_pixel(const FwdKernelArgs& A, const CamDev& cam,
                                             unsigned long long pix_off, int px, int py,
                                             float m2, float D, const float (&N)[CM],
-                                            const uint64_t (&kk)[KM]) {
+                                            const uint64_t (&kk)[KM],
+                                            uint64_t skey = kKeyNone) {
   if (px >= cam.W || py >= cam.H) return;
   const size_t p = size_t(pix_off) + size_t(py) * size_t(cam.W) + size_t(px);
   const float invD = 1.f / D;
@@ -140,6 +149,10 @@ __device__ __forceinline__ void write_pixel(const FwdKernelArgs& A, const CamDev
     A.thr[p] = k == kKeyNone ? make_float2(INFINITY, __uint_as_float(0xffffffffu))
                              : make_float2(__uint_as_float(uint32_t(k >> 32)),
                                            __uint_as_float(uint32_t(k)));
+    // early termination: the first hit the pixel skipped, or none
+    if (A.stop)
+      A.stop[p] = make_float2(__uint_as_float(uint32_t(skey >> 32)),
+                              __uint_as_float(uint32_t(skey)));
   }
 }
 
@@ -195,10 +208,15 @@ __global__ __launch_bounds__(256) void k_fwd_background(FwdKernelArgs A) {
 // Up to 8 channels and an 8-entry K-list the work-item kernel fits 128 VGPRs
 // (4 waves per SIMD, a few registers spilled outside the hit loop); wider
 // instances keep the compiler's own register budget.
-constexpr int fwd_waves_per_simd(int CM, int KM) { return (CM <= 8 && KM <= 8) ? 4 : 1; }
+// The early-termination instances carry the stop state on top and keep the
+// compiler's budget (they spilled at 128).
+constexpr int fwd_waves_per_simd(int CM, int KM, bool ES = false) {
+  return (!ES && CM <= 8 && KM <= 8) ? 4 : 1;
+}
 
-template <int CM, int KM>
-__global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM)) void k_fwd_chunks(
+// ES: early termination (tiles are single work items, in depth order).
+template <int CM, int KM, bool ES>
+__global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM, ES)) void k_fwd_chunks(
     FwdKernelArgs A, const SceneDev* __restrict__ scenes, const uint32_t* __restrict__ tile_start,
     const uint4* __restrict__ desc) {
   // the batch's records (part-major: s_rec[q][r] is float4 q of record r)
@@ -214,6 +232,7 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM)) void k_fwd_chunk
   // bit p % 64 of word p / 64 is set when a record's first pair is p (a
   // batch has at most 64 records of at most 64 pixels, so 64 words suffice)
   __shared__ unsigned long long s_start[kWave];
+  __shared__ float s_tmin[ES ? kWave : 1];  // early termination: the records' t_min
   const int lane = threadIdx.x;
   s_start[lane] = 0ull;
   // channels past this pass's width are never loaded: keep them zero
@@ -252,6 +271,10 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM)) void k_fwd_chunk
     for (int c = 0; c < CM; ++c) N[c] = (first && c < A.cn) ? bg[A.c0 + c] : 0.f;
     uint64_t kk[KM];
     klist_init(kk, A.K);
+    // early termination: whether this pixel has stopped, and at which hit
+    bool done = false;
+    uint64_t skey = kKeyNone;
+    const bool inside = ray.px < cam.W && ray.py < cam.H;
 
     const int ttx = tx0 / kTileW, tty = ty0 / kTileH;  // the tile, in tile units
     // the sorted pairs name their spheres, whose records and payload rows are
@@ -273,6 +296,7 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM)) void k_fwd_chunk
 #pragma unroll
       for (int c = 0; c < CM; ++c)
         if (c < A.cn) __builtin_amdgcn_global_load_lds(fp + c, &s_pay[c][0], 4, 0, 0);
+      if (ES) __builtin_amdgcn_global_load_lds(A.tmin + sph, &s_tmin[0], 4, 0, 0);
       const uint32_t bo = uint32_t(A.boff[sph / kProjectBlock]);
       __builtin_amdgcn_s_waitcnt(kWaitVmem0);
       __syncthreads();
@@ -302,6 +326,7 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM)) void k_fwd_chunk
       // number of records starting at or before it, minus one: a popcount of
       // the start bits, with no search.
       uint32_t before = 0;  // records starting in earlier blocks of 64 pairs
+      const uint64_t stopped = ES ? __ballot(done) : 0ull;  // pixels that take no more hits
       for (uint32_t pb = 0; pb < total; pb += kWave) {
         const unsigned long long starts = s_start[pb >> 6];
         const int r = int(before + uint32_t(__popcll(starts & ((2ull << lane) - 1ull)))) - 1;
@@ -319,7 +344,7 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM)) void k_fwd_chunk
         const float dy = float(ty0 + y - int(pk >> 16)) - ra.y;
         const float cr = rb.x * dy - rb.y * dx;
         const float r2 = ra.z * (dx * dx + dy * dy + cr * cr) * s_iv2[pl];
-        if (r2 < kRejectR2) atomicOr(&s_mask[pl], 1ull << r);
+        if (r2 < kRejectR2 && !((stopped >> pl) & 1ull)) atomicOr(&s_mask[pl], 1ull << r);
       }
       s_start[lane] = 0ull;  // for the next batch (this wave's reads above are issued first)
       __syncthreads();
@@ -339,8 +364,23 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM)) void k_fwd_chunk
         hits &= hits - 1ull;
         const SphereRec s = unpack_rec(s_rec[0][k], s_rec[1][k], s_rec[2][k], s_rec[3][k]);
         Hit h;
-        const bool hit = exact_hit(ray, s, bc.zfar, h) && act &&
-                         (h.t < tk || (h.t == tk && s_id[k] <= ik));
+        bool hit = exact_hit(ray, s, bc.zfar, h) && act &&
+                   (h.t < tk || (h.t == tk && s_id[k] <= ik));
+        if (ES) {
+          // early termination (Sec. 3.2, App. B Step 2): the hits come in
+          // depth-sort order; the first whose largest possible weight
+          // exp(z(t_min) / gamma) is below share / (1 - share) of the running
+          // denominator stops the pixel, and it and every later hit are
+          // skipped (base-2 exponents: D holds the sum over 2^m2)
+          if (hit && !done) {
+            const float bound2 = (bc.zfar - s_tmin[k]) * bc.kz;
+            if (bound2 < A.lrho2 + m2 + fast_log2(D)) {
+              done = true;
+              skey = hit_key(s_tmin[k], s_id[k]);
+            }
+          }
+          hit = hit && !done;
+        }
         const float s2 = s.o * (bc.zfar - h.t) * bc.kz;
         const bool grow = hit && s2 > m2;
         if (__ballot(grow) != 0ull) {
@@ -360,10 +400,12 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM)) void k_fwd_chunk
         for (int c = 0; c < CM; ++c) N[c] = hit ? fmaf(wgt, fv[c], N[c]) : N[c];
         if (A.track) klist_insert(kk, hit ? hit_key(h.t, s_id[k]) : kKeyNone);
       }
+      // early termination: the tile is done once every pixel has stopped
+      if (ES && __ballot(inside && !done) == 0ull) break;
     }
 
     if (slot == kNoSlot) {
-      write_pixel(A, cam, sc.pix_off, ray.px, ray.py, m2, D, N, kk);
+      write_pixel(A, cam, sc.pix_off, ray.px, ray.py, m2, D, N, kk, skey);
     } else {
       if ((long long)slot < A.pcap) {
         float* ps = A.pstate + size_t(slot) * size_t(kWave) * size_t(A.pstride);
@@ -495,8 +537,12 @@ void launch_binning(const Plan& q, char* ws, hipStream_t stream);
 template <int CM, int KM>
 static void launch_raster_fwd_cm(const Plan& q, const FwdKernelArgs& A, hipStream_t stream) {
   stage_begin(PULSAR_STAGE_RASTER_FWD, stream);
-  hipLaunchKernelGGL((k_fwd_chunks<CM, KM>), dim3(unsigned(q.raster_grid)), dim3(kWave), 0,
-                     stream, A, A.tab.scenes, A.tab.tile_start, A.desc);
+  if (q.estop)
+    hipLaunchKernelGGL((k_fwd_chunks<CM, KM, true>), dim3(unsigned(q.raster_grid)), dim3(kWave),
+                       0, stream, A, A.tab.scenes, A.tab.tile_start, A.desc);
+  else
+    hipLaunchKernelGGL((k_fwd_chunks<CM, KM, false>), dim3(unsigned(q.raster_grid)), dim3(kWave),
+                       0, stream, A, A.tab.scenes, A.tab.tile_start, A.desc);
   if (!A.fill_in_tail && A.image)
     hipLaunchKernelGGL(k_fwd_background, dim3(unsigned((q.T + 3) / 4)), dim3(256), 0, stream, A);
   stage_end(PULSAR_STAGE_RASTER_FWD, stream);
@@ -560,6 +606,9 @@ static FwdKernelArgs raster_args(const Plan& q, const std::vector<SceneDev>& sce
   A.track = 0;
   A.topk = 0;
   A.vec4 = 0;
+  A.tmin = q.estop ? ws_ptr<float>(ws, q.off_tmin) : nullptr;
+  A.stop = q.estop ? ws_ptr<float2>(ws, q.off_stop) : nullptr;
+  A.lrho2 = q.estop ? float(std::log2(double(a.stop_share) / (1.0 - double(a.stop_share)))) : 0.f;
   return A;
 }
 

@@ -32,10 +32,11 @@ def gpu_render(scene, cam, params, G=None, max_pairs=0, depth_bits=0, need=None,
     backward runs on."""
     import torch
     cs = cam_struct(cam)
+    share = float(getattr(params, "stop_share", 0.0))
     ps = _capi.make_params(params.gamma, params.eps, params.min_radius_px, params.K,
-                           max_pairs, depth_bits, chunk, raster_blocks, fwd_flags)
+                           max_pairs, depth_bits, chunk, raster_blocks, fwd_flags, share)
     pb = _capi.make_params(params.gamma, params.eps, params.min_radius_px, params.K,
-                           max_pairs, depth_bits, chunk, raster_blocks, bwd_flags)
+                           max_pairs, depth_bits, chunk, raster_blocks, bwd_flags, share)
     n, C = scene.payload.shape
     pos, rad, opa = to_dev(scene.pos), to_dev(scene.radius), to_dev(scene.opacity)
     pay, bg = to_dev(scene.payload), to_dev(scene.bg)
@@ -121,7 +122,8 @@ def gpu_render_batch(workloads, params, Gs=None, depth_bits=0, chunk=0, raster_b
     B = len(workloads)
     C = workloads[0].scene.payload.shape[1]
     ps = _capi.make_params(params.gamma, params.eps, params.min_radius_px, params.K, 0,
-                           depth_bits, chunk, raster_blocks, flags)
+                           depth_bits, chunk, raster_blocks, flags,
+                           float(getattr(params, "stop_share", 0.0)))
     scenes = _capi.make_scenes([cam_struct(w.camera) for w in workloads],
                                [w.scene.n for w in workloads])
     cat = lambda xs, shape: np.concatenate([np.asarray(x, np.float32).reshape(shape) for x in xs])

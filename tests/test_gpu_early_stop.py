@@ -1,0 +1,147 @@
+"""Early ray termination (params.stop_share > 0; Sec. 3.2 and App. B,
+Step 2) on the GPU against the oracle's early stop: each pixel takes its
+hits in ascending (float32 earliest hit distance, index) order and stops
+before the first one whose largest possible weight is below the share of
+the running denominator. Pixels the oracle flags as within rounding of a
+stop decision, or of a change of their K nearest, are left out of the image
+comparison and get no upstream gradient."""
+import copy
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import reference as ref
+from paper_2004_07484_amd import _capi
+from paper_2004_07484_amd import scenegen as sg
+from tests.gpu_helpers import (IMAGE_REL, assert_close, compare_grads, gpu_render,
+                               gpu_render_batch, masked_G)
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def stacked(seed=21, n=6000, W=64, H=48, C=3, share=0.01, gamma=0.05, K=8):
+    """Spheres spread over depth in front of the camera, about a dozen hits
+    per pixel: near ones outweigh far ones by up to exp(16), so pixels stop."""
+    rng = np.random.default_rng(seed)
+    z = rng.uniform(2.0, 9.0, n)
+    xy = rng.uniform(-1.0, 1.0, (n, 2)) * z[:, None] * 0.7
+    sc = sg.Scene(pos=sg._f32(np.column_stack([xy, z])),
+                  radius=sg._f32(rng.uniform(0.05, 0.3, n) * z / 3.0 * 0.4),
+                  opacity=sg._f32(rng.uniform(0.5, 1.0, n)),
+                  payload=sg._f32(rng.standard_normal((n, C))),
+                  bg=sg._f32(rng.uniform(-0.5, 0.5, C)))
+    cam = sg.identity_camera(W, H)
+    par = sg.Params(gamma=gamma, eps=1e-5, K=K, stop_share=share)
+    return sc, cam, par
+
+
+def _rotate(sc, cam, seed):
+    rng = np.random.default_rng(seed)
+    q, r = np.linalg.qr(rng.standard_normal((3, 3)))
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    tq = rng.uniform(-1, 1, 3)
+    sc.pos = ((sc.pos.astype(np.float64) - tq) @ q).astype(np.float32)
+    cam.R, cam.t = q.astype(np.float32), tq.astype(np.float32)
+
+
+def _check(sc, cam, par, what, rows=None, bwd_flags=0, fwd_flags=0, G_seed=700,
+           require_stop=True):
+    fwd = ref.forward(sc, cam, par, rows=rows)
+    exact = ref.forward(sc, cam, dataclass_replace(par, stop_share=0.0), rows=rows)
+    sel = slice(None) if rows is None else rows
+    stopped = (fwd["nhits"][sel] < exact["nhits"][sel]).sum()
+    _say(f"[early stop] {what}: {stopped} of {fwd['nhits'][sel].size} pixels stop early, "
+         f"{fwd['ambiguous'][sel].sum()} ambiguous")
+    assert stopped > 0 or not require_stop
+    G = sg.upstream_grad(G_seed, cam.height, cam.width, sc.C)
+    Gm = masked_G(G, rows, fwd["ambiguous"])
+    out = gpu_render(sc, cam, par, Gm, fwd_flags=fwd_flags, bwd_flags=bwd_flags)
+    assert out["status"] == _capi.PULSAR_OK
+    ok = ~fwd["ambiguous"][sel]
+    assert_close(out["F"][sel][ok], fwd["F"][sel][ok], IMAGE_REL, f"{what} image")
+    assert_close(out["L"][sel][ok], fwd["L"][sel][ok], IMAGE_REL, f"{what} log-normaliser")
+    g = ref.backward(sc, cam, par, Gm, fwd, rows=rows)
+    compare_grads(out, g, what)
+    return fwd, out
+
+
+def dataclass_replace(par, **kw):
+    p = copy.copy(par)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("case", ["plain", "rotated_rebin", "orthographic", "wide_payload",
+                                  "K1", "small_share"])
+def test_early_stop_matches_oracle(case):
+    sc, cam, par = stacked()
+    fwd_flags = bwd_flags = 0
+    if case == "rotated_rebin":
+        _rotate(sc, cam, 5)
+        bwd_flags = _capi.PULSAR_REBIN
+    if case == "orthographic":
+        cam.orthographic = True
+        cam.sensor_width = 4.0
+        fwd_flags = bwd_flags = _capi.PULSAR_ORTHO
+    if case == "wide_payload":
+        sc, cam, par = stacked(C=40)
+    if case == "K1":
+        par.K = 1
+    if case == "small_share":
+        par.stop_share = 1e-3
+    _check(sc, cam, par, case, fwd_flags=fwd_flags, bwd_flags=bwd_flags)
+
+
+def test_early_stop_config1():
+    """At gamma 0.1 these depths weigh within a factor exp(3.4) of each other,
+    so no pixel reaches the 1 % bound: the early-stop path (depth-sorted
+    whole-tile work items) must then give the plain blend."""
+    wl = sg.config1()
+    par = dataclass_replace(wl.params, stop_share=0.01)
+    _check(wl.scene, wl.camera, par, "1k spheres 64x64", require_stop=False)
+
+
+def test_early_stop_config2_rows():
+    wl = sg.config2()
+    par = dataclass_replace(wl.params, stop_share=0.01)
+    rows = sorted(np.random.default_rng(78).choice(512, 10, replace=False).tolist())
+    _check(wl.scene, wl.camera, par, "100k spheres 512x512", rows=rows, require_stop=False)
+
+
+def test_early_stop_is_deterministic():
+    sc, cam, par = stacked()
+    a = gpu_render(sc, cam, par)
+    b = gpu_render(sc, cam, par)
+    assert np.array_equal(a["F"], b["F"]) and np.array_equal(a["L"], b["L"])
+
+
+def test_early_stop_batched():
+    """Two scenes in one batched call, each against the oracle."""
+    wls = []
+    for seed, (W, H) in [(31, (64, 48)), (32, (40, 56))]:
+        sc, cam, par = stacked(seed=seed, W=W, H=H)
+        wls.append(sg.Workload(name=f"stacked{seed}", scene=sc, camera=cam, params=par,
+                               seed=seed))
+    par = wls[0].params
+    fwds, Gs = [], []
+    for w in wls:
+        f = ref.forward(w.scene, w.camera, par)
+        fwds.append(f)
+        Gs.append(masked_G(sg.upstream_grad(w.seed + 5, w.camera.height, w.camera.width, 3),
+                           None, f["ambiguous"]))
+    outs = gpu_render_batch(wls, par, Gs=Gs)
+    for w, f, G, o in zip(wls, fwds, Gs, outs):
+        assert o["status"] == _capi.PULSAR_OK
+        ok = ~f["ambiguous"]
+        assert_close(o["F"][ok], f["F"][ok], IMAGE_REL, f"batched {w.name} image")
+        g = ref.backward(w.scene, w.camera, par, G, f)
+        compare_grads(o, g, f"batched {w.name}")
