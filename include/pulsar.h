@@ -305,6 +305,27 @@ int pulsar_fwd_batched(const pulsar_scene_t* scenes, int32_t B, const float* pos
 
 /* Batched backward: pulsar_bwd for every scene; the same rules on NULL
  * outputs and on pairing with the preceding forward apply. */
+/* pulsar_fwd_batched with the cameras read from device memory when the work
+ * runs rather than when the call is made: d_cameras [B] pulsar_camera_t in
+ * device memory (caller-owned; read by this call's first kernels), while
+ * scenes[b].camera only gives the image sizes (and must be valid). A graph
+ * captured from this call renders, at each replay, with the cameras
+ * d_cameras then holds (image sizes and sphere counts stay those of the
+ * capture). The device computes the camera constants as the host does, so
+ * the results equal pulsar_fwd_batched with those cameras bitwise. Device
+ * cameras cannot be checked on the host: an invalid one (the checks
+ * pulsar_fwd makes) makes pulsar_query_status report
+ * PULSAR_ERR_INVALID_ARGUMENT, and the outputs are undefined. A
+ * pulsar_bwd_batched on the same workspace without PULSAR_REBIN uses the
+ * cameras this forward read; with PULSAR_REBIN it would use those of its
+ * own scenes argument. */
+int pulsar_fwd_batched_devcam(const pulsar_scene_t* scenes, int32_t B,
+                              const pulsar_camera_t* d_cameras, const float* pos,
+                              const float* radius, const float* opacity, const float* payload,
+                              int32_t C, const float* background, const pulsar_params_t* params,
+                              float* image, float* aux, void* ws, size_t ws_bytes,
+                              void* stream);
+
 int pulsar_bwd_batched(const pulsar_scene_t* scenes, int32_t B, const float* pos,
                        const float* radius, const float* opacity, const float* payload,
                        int32_t C, const float* background, const pulsar_params_t* params,
@@ -324,10 +345,19 @@ int pulsar_bwd_camera_batched(const pulsar_scene_t* scenes, int32_t B, const flo
                               void* ws, size_t ws_bytes, void* stream);
 
 /* Synchronises `stream` and reports the status the device wrote into the
- * workspace during the last pulsar_fwd: PULSAR_OK or PULSAR_ERR_CAPACITY.
- * If pairs is not NULL it receives the number of (tile, sphere) pairs that
- * forward produced. */
+ * workspace during the last pulsar_fwd: PULSAR_OK, PULSAR_ERR_CAPACITY, or
+ * PULSAR_ERR_INVALID_ARGUMENT when a camera pulsar_fwd_batched_devcam read
+ * from device memory was invalid. If pairs is not NULL it receives the
+ * number of (tile, sphere) pairs that forward produced. */
 int pulsar_query_status(const void* ws, size_t ws_bytes, void* stream, int64_t* pairs);
+
+/* The status without synchronising: once a forward's work has completed, the
+ * first PULSAR_STATUS_BYTES bytes of its workspace hold, little-endian,
+ * uint32 status (0: PULSAR_OK, else minus the PULSAR_ERR_* code), uint32
+ * pairs stored, uint64 pairs produced. A caller may copy them behind the
+ * forward on its stream (into pinned host memory, say) and read them later,
+ * which keeps the stream free of host synchronisation (graph capture). */
+#define PULSAR_STATUS_BYTES 16
 
 /* Static English description of a status code. Never NULL. */
 const char* pulsar_status_string(int code);

@@ -9,6 +9,7 @@ raises PulsarLibraryMissing.
 from __future__ import annotations
 
 import ctypes
+import struct
 import os
 from typing import Optional, Tuple
 
@@ -23,12 +24,14 @@ PULSAR_ERR_HIP = -4
 PULSAR_ERR_CAPACITY = -5
 PULSAR_ERR_SCRATCH = -6
 PULSAR_NOALLOC_SCRATCH_BYTES = 64 << 20
+PULSAR_STATUS_BYTES = 16
 
 EXPORTED = ("pulsar_workspace_size", "pulsar_fwd", "pulsar_bwd", "pulsar_batch_workspace_size",
             "pulsar_fwd_batched", "pulsar_bwd_batched", "pulsar_bwd_camera",
             "pulsar_bwd_camera_batched", "pulsar_query_status",
             "pulsar_status_string", "pulsar_last_hip_error", "pulsar_timing_enable",
-            "pulsar_timing_read", "pulsar_stage_name", "pulsar_version", "pulsar_fwd_noalloc")
+            "pulsar_timing_read", "pulsar_stage_name", "pulsar_version", "pulsar_fwd_noalloc",
+            "pulsar_fwd_batched_devcam")
 
 PULSAR_NUM_STAGES = 7
 PULSAR_NO_BWD_AUX = 0x1   # forward keeps no backward state
@@ -107,6 +110,11 @@ def load():
                                        _vp, _vp, ctypes.c_int32, _vp,
                                        ctypes.POINTER(pulsar_params_t), _vp, _vp, _vp,
                                        ctypes.c_size_t, _vp]
+    lib.pulsar_fwd_batched_devcam.restype = ctypes.c_int
+    lib.pulsar_fwd_batched_devcam.argtypes = [ctypes.POINTER(pulsar_scene_t), ctypes.c_int32,
+                                              _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp,
+                                              ctypes.POINTER(pulsar_params_t), _vp, _vp, _vp,
+                                              ctypes.c_size_t, _vp]
     lib.pulsar_bwd_batched.restype = ctypes.c_int
     lib.pulsar_bwd_batched.argtypes = [ctypes.POINTER(pulsar_scene_t), ctypes.c_int32, _vp, _vp,
                                        _vp, _vp, ctypes.c_int32, _vp,
@@ -333,6 +341,37 @@ def pulsar_fwd_batched(scenes, pos, radius, opacity, payload, background,
         raise PulsarError(rc, "pulsar_fwd_batched")
 
 
+def cameras_bytes(cameras) -> bytes:
+    """The bytes of B pulsar_camera_t structs, for a device camera array
+    (a uint8 tensor of B * sizeof(pulsar_camera_t) bytes)."""
+    cams = list(cameras)
+    arr = (pulsar_camera_t * len(cams))(*cams)
+    return ctypes.string_at(ctypes.addressof(arr), ctypes.sizeof(arr))
+
+
+def pulsar_fwd_batched_devcam(scenes, d_cameras, pos, radius, opacity, payload, background,
+                              params: pulsar_params_t, image, aux, ws, stream=None) -> None:
+    """pulsar_fwd_batched with the cameras read from d_cameras (a contiguous
+    uint8 device tensor holding B pulsar_camera_t, see cameras_bytes) when
+    the work runs; scenes give the image sizes and sphere counts."""
+    B = len(scenes)
+    N, P = batch_sizes(scenes)
+    C = int(payload.shape[1])
+    if (not d_cameras.is_cuda or d_cameras.element_size() != 1 or not d_cameras.is_contiguous()
+            or d_cameras.numel() != B * ctypes.sizeof(pulsar_camera_t)):
+        raise ValueError("d_cameras must hold B pulsar_camera_t in a contiguous uint8 device "
+                         "tensor")
+    rc = load().pulsar_fwd_batched_devcam(
+        scenes, B, d_cameras.data_ptr(), _ptr(pos, "pos", N > 0, (N, 3)),
+        _ptr(radius, "radius", N > 0, (N,)), _ptr(opacity, "opacity", False, (N,)),
+        _ptr(payload, "payload", N > 0, (N, C)), C,
+        _ptr(background, "background", True, (B, C)), ctypes.byref(params),
+        _ptr(image, "image", True, (P, C)), _ptr(aux, "aux", False, (P,)),
+        _ws_ptr(ws), int(ws.numel()), _stream(stream))
+    if rc != PULSAR_OK:
+        raise PulsarError(rc, "pulsar_fwd_batched_devcam")
+
+
 def pulsar_bwd_batched(scenes, pos, radius, opacity, payload, background,
                        params: pulsar_params_t, image, aux, grad_image, grad_pos, grad_radius,
                        grad_opacity, grad_payload, grad_background, ws, stream=None) -> None:
@@ -382,9 +421,16 @@ def pulsar_query_status(ws, stream=None) -> Tuple[int, int]:
     pairs = ctypes.c_int64(0)
     rc = load().pulsar_query_status(_ws_ptr(ws), int(ws.numel()), _stream(stream),
                                     ctypes.byref(pairs))
-    if rc not in (PULSAR_OK, PULSAR_ERR_CAPACITY):
+    if rc not in (PULSAR_OK, PULSAR_ERR_CAPACITY, PULSAR_ERR_INVALID_ARGUMENT):
         raise PulsarError(rc, "pulsar_query_status")
     return rc, int(pairs.value)
+
+
+def decode_status(raw: bytes) -> Tuple[int, int]:
+    """(status code, tile pairs) from the first PULSAR_STATUS_BYTES bytes of a
+    workspace (the layout the header documents)."""
+    flag, _stored, pairs = struct.unpack("<IIQ", bytes(raw[:PULSAR_STATUS_BYTES]))
+    return -int(flag), int(pairs)
 
 
 def _ws_ptr(ws) -> int:

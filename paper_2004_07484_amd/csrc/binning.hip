@@ -383,7 +383,9 @@ __global__ __launch_bounds__(1024) void k_ranges(uint32_t T, const uint32_t* __r
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     status->pairs = total;
     status->used = used;
-    status->code = total > (unsigned long long)cap ? uint32_t(-PULSAR_ERR_CAPACITY) : 0u;
+    status->code = total > (unsigned long long)cap ? uint32_t(-PULSAR_ERR_CAPACITY)
+                   : status->bad_cam != 0u            ? uint32_t(-PULSAR_ERR_INVALID_ARGUMENT)
+                                                      : 0u;
     status->nfull = 0u;
     status->nshort = 0u;
     status->npartials = 0u;

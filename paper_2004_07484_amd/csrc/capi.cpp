@@ -312,10 +312,11 @@ size_t pulsar_workspace_size(int32_t n, int32_t width, int32_t height, int32_t C
   return pulsar_batch_workspace_size(&sc, 1, C, params);
 }
 
-int pulsar_fwd_batched(const pulsar_scene_t* scenes, int32_t B, const float* pos,
-                       const float* radius, const float* opacity, const float* payload,
-                       int32_t C, const float* background, const pulsar_params_t* params,
-                       float* image, float* aux, void* ws, size_t ws_bytes, void* stream) {
+static int fwd_impl(const pulsar_scene_t* scenes, int32_t B, const pulsar_camera_t* d_cams,
+                    const float* pos, const float* radius, const float* opacity,
+                    const float* payload, int32_t C, const float* background,
+                    const pulsar_params_t* params, float* image, float* aux, void* ws,
+                    size_t ws_bytes, void* stream) {
   std::vector<SceneDev> sc;
   int rc = make_scenes(scenes, B, params, &sc);
   if (rc != PULSAR_OK) return rc;
@@ -341,10 +342,33 @@ int pulsar_fwd_batched(const pulsar_scene_t* scenes, int32_t B, const float* pos
   a.track = aux != nullptr && (params->flags & PULSAR_NO_BWD_AUX) == 0u;
   a.topk = (params->flags & PULSAR_BLEND_TOPK) != 0u;
   a.stop_share = params->stop_share;
+  a.d_cams = d_cams;
+  a.gamma = params->gamma;
+  a.eps = params->eps;
+  a.ortho = (params->flags & PULSAR_ORTHO) != 0u;
   hipError_t e = launch_forward(q, sc, a, static_cast<char*>(ws),
                                 static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail_hip(e);
   return PULSAR_OK;
+}
+
+int pulsar_fwd_batched(const pulsar_scene_t* scenes, int32_t B, const float* pos,
+                       const float* radius, const float* opacity, const float* payload,
+                       int32_t C, const float* background, const pulsar_params_t* params,
+                       float* image, float* aux, void* ws, size_t ws_bytes, void* stream) {
+  return fwd_impl(scenes, B, nullptr, pos, radius, opacity, payload, C, background, params,
+                  image, aux, ws, ws_bytes, stream);
+}
+
+int pulsar_fwd_batched_devcam(const pulsar_scene_t* scenes, int32_t B,
+                              const pulsar_camera_t* d_cameras, const float* pos,
+                              const float* radius, const float* opacity, const float* payload,
+                              int32_t C, const float* background, const pulsar_params_t* params,
+                              float* image, float* aux, void* ws, size_t ws_bytes,
+                              void* stream) {
+  if (!d_cameras) return PULSAR_ERR_INVALID_ARGUMENT;
+  return fwd_impl(scenes, B, d_cameras, pos, radius, opacity, payload, C, background, params,
+                  image, aux, ws, ws_bytes, stream);
 }
 
 static int bwd_impl(const pulsar_scene_t* scenes, int32_t B, const float* pos,
@@ -385,6 +409,10 @@ static int bwd_impl(const pulsar_scene_t* scenes, int32_t B, const float* pos,
     f.track = true;
     f.topk = false;
     f.stop_share = params->stop_share;
+    f.d_cams = nullptr;
+    f.gamma = params->gamma;
+    f.eps = params->eps;
+    f.ortho = (params->flags & PULSAR_ORTHO) != 0u;
     hipError_t e = launch_rebin(q, sc, f, static_cast<char*>(ws),
                                 static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return fail_hip(e);
@@ -496,7 +524,8 @@ int pulsar_query_status(const void* ws, size_t ws_bytes, void* stream, int64_t* 
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail_hip(e);
   if (pairs) *pairs = int64_t(st.pairs);
-  return st.code == 0u ? PULSAR_OK : PULSAR_ERR_CAPACITY;
+  // the device writes the negated code: capacity, or an invalid device camera
+  return st.code == 0u ? PULSAR_OK : -int(st.code);
 }
 
 const char* pulsar_status_string(int code) {

@@ -34,9 +34,11 @@ struct SceneUpload {
 };
 
 __global__ __launch_bounds__(64) void k_upload_scenes(SceneUpload u, SceneDev* __restrict__ scenes,
-                                                      uint32_t* __restrict__ starts) {
+                                                      uint32_t* __restrict__ starts,
+                                                      Status* __restrict__ status) {
   const int k = threadIdx.x;
   const int B1 = u.B + 1;
+  if (u.first == 0 && k == 0) status->bad_cam = 0u;
   if (k < u.count) {
     const int b = u.first + k;
     scenes[b] = u.s[k];
@@ -71,8 +73,59 @@ void launch_upload_scenes(const Plan& q, const std::vector<SceneDev>& sc, char* 
   uint32_t* starts = ws_ptr<uint32_t>(ws, q.off_starts);
   for (int first = 0; first < q.B; first += kUploadScenes) {
     const SceneUpload u = make_upload(q, sc, first);
-    hipLaunchKernelGGL(k_upload_scenes, dim3(1), dim3(64), 0, stream, u, scenes, starts);
+    hipLaunchKernelGGL(k_upload_scenes, dim3(1), dim3(64), 0, stream, u, scenes, starts,
+                       ws_ptr<Status>(ws, q.off_status));
   }
+}
+
+// Cameras from device memory: scene b's camera and blend constants are
+// rebuilt from d_cams[b] when the work runs, with the expressions the host
+// uses (IEEE double, no contraction), so the table equals what the host would
+// have uploaded for the same cameras. Image sizes, and with them the
+// workspace plan, stay those of the host's scene array. An invalid camera
+// (the checks pulsar_fwd makes on the host) is reported through the status;
+// the call's outputs are then undefined, but every access stays in bounds
+// (rectangles are clamped to the host's image sizes).
+__global__ __launch_bounds__(256) void k_device_cameras(const pulsar_camera_t* __restrict__ d_cams,
+                                                        int B, float gamma, float eps, int ortho,
+                                                        SceneDev* __restrict__ scenes,
+                                                        Status* __restrict__ status) {
+#pragma clang fp contract(off)
+  const int b = blockIdx.x * 256 + threadIdx.x;
+  if (b >= B) return;
+  const pulsar_camera_t c = d_cams[b];
+  bool ok = isfinite(c.focal) && c.focal > 0.f && isfinite(c.sensor_width) &&
+            c.sensor_width > 0.f && isfinite(c.znear) && c.znear > 0.f && isfinite(c.zfar) &&
+            c.zfar > c.znear;
+  for (int i = 0; i < 9; ++i) ok = ok && isfinite(c.R[i]);
+  for (int i = 0; i < 3; ++i) ok = ok && isfinite(c.t[i]);
+  if (!ok) atomicOr(&status->bad_cam, 1u);
+  SceneDev& sc = scenes[b];
+  CamDev d = sc.cam;  // width, height and tile counts of the plan
+  for (int i = 0; i < 9; ++i) d.R[i] = c.R[i];
+  for (int i = 0; i < 3; ++i) d.t[i] = c.t[i];
+  d.f = ortho ? 1.f : c.focal;
+  d.s = c.sensor_width;
+  d.znear = c.znear;
+  d.zfar = c.zfar;
+  const double W = double(d.W), H = double(d.H), s = double(c.sensor_width);
+  d.pitch = float(s / W);
+  d.sh = float(s * H / W);
+  d.dpitch = s / W;
+  d.dinv_pitch = W / s;
+  d.dsh = s * H / W;
+  d.dhalf_sh = 0.5 * s * H / W;
+  d.ortho = ortho;
+  sc.cam = d;
+  const double log2e = 1.4426950408889634;
+  const double span = double(c.zfar) - double(c.znear);
+  BlendConst bc;
+  bc.kz = float(log2e / (double(gamma) * span));
+  bc.eps2 = float(double(eps) / double(gamma) * log2e);
+  bc.zfar = c.zfar;
+  bc.inv_gamma = float(1.0 / double(gamma));
+  bc.inv_span = float(1.0 / span);
+  sc.bc = bc;
 }
 
 // When the whole scene table fits in the launch arguments (`inline_scenes`),
@@ -84,7 +137,8 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
     const float* __restrict__ opacity, SceneTable tab, SceneUpload u, int inline_scenes,
     SceneDev* __restrict__ tab_out, uint32_t* __restrict__ starts_out, float min_radius_px,
     uint32_t* __restrict__ counts, ushort4* __restrict__ trect, float4* __restrict__ rec,
-    unsigned long long* __restrict__ partials, float* __restrict__ tmin_out) {
+    unsigned long long* __restrict__ partials, float* __restrict__ tmin_out,
+    Status* __restrict__ status) {
   // no FMA contraction: the camera transform, the minimum size and the
   // earliest hit distance are the IEEE double evaluations of the same
   // expressions, term by term (early termination orders spheres by the
@@ -94,6 +148,7 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
   if (inline_scenes && blockIdx.x == 0 && threadIdx.x < kWave) {
     const int k = threadIdx.x;
     const int B1 = u.B + 1;
+    if (k == 0) status->bad_cam = 0u;
     if (k < u.count) {
       tab_out[k] = u.s[k];
       starts_out[k] = u.s[k].sph_off;
@@ -225,8 +280,14 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
 // The projection runs even with no sphere (it then only writes the scene table).
 void launch_project(const Plan& q, const std::vector<SceneDev>& sc, const FwdArgs& a, char* ws,
                     hipStream_t stream) {
-  const bool inline_scenes = q.B <= kUploadScenes;
+  // device cameras replace those of the uploaded table, so the projection
+  // reads the table from the workspace
+  const bool inline_scenes = q.B <= kUploadScenes && !a.d_cams;
   if (!inline_scenes) launch_upload_scenes(q, sc, ws, stream);
+  if (a.d_cams)
+    hipLaunchKernelGGL(k_device_cameras, dim3(unsigned((q.B + 255) / 256)), dim3(256), 0, stream,
+                       a.d_cams, q.B, a.gamma, a.eps, a.ortho ? 1 : 0,
+                       ws_ptr<SceneDev>(ws, q.off_scenes), ws_ptr<Status>(ws, q.off_status));
   const SceneUpload u = make_upload(q, sc, 0);
   hipLaunchKernelGGL(k_project, dim3(q.nblk_proj > 0 ? q.nblk_proj : 1), dim3(kProjectBlock), 0,
                      stream, int(q.n), a.pos, a.radius, a.opacity, scene_table(q, ws), u,
@@ -235,7 +296,8 @@ void launch_project(const Plan& q, const std::vector<SceneDev>& sc, const FwdArg
                      ws_ptr<uint32_t>(ws, q.off_counts), ws_ptr<ushort4>(ws, q.off_trect),
                      ws_ptr<float4>(ws, q.off_rec),
                      ws_ptr<unsigned long long>(ws, q.off_partials),
-                     q.estop ? ws_ptr<float>(ws, q.off_tmin) : nullptr);
+                     q.estop ? ws_ptr<float>(ws, q.off_tmin) : nullptr,
+                     ws_ptr<Status>(ws, q.off_status));
 }
 
 }  // namespace pulsar

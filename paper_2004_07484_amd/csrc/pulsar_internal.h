@@ -44,9 +44,12 @@ struct Status {
   uint32_t nshort;              // shorter work items (back of the list)
   uint32_t npartials;           // partial blend states needed by tiles with several work items
   uint32_t nmerge;              // tiles with several work items
-  uint32_t pad[56];
+  uint32_t bad_cam;             // a camera read from device memory was invalid
+  uint32_t pad[55];
 };
 static_assert(sizeof(Status) == 256, "status block");
+static_assert(offsetof(Status, pairs) + sizeof(unsigned long long) == PULSAR_STATUS_BYTES,
+              "the documented status prefix");
 
 // Raster work items: full chunks fill the list from the front, shorter ones
 // from the back (full chunks, the costlier items, are taken first).
@@ -177,6 +180,10 @@ struct FwdArgs {
   bool track;  // keep each pixel's K nearest hits for a following backward
   bool topk;   // blend only each pixel's K nearest hits
   float stop_share;  // early termination share (0: off)
+  // cameras read from device memory when the work runs (null: the host table)
+  const pulsar_camera_t* d_cams;
+  float gamma, eps;  // for the blend constants of device cameras
+  bool ortho;
 };
 
 struct BwdArgs {

@@ -4,10 +4,18 @@ PyTorch only provides device memory, the stream and autograd bookkeeping;
 every step of the rendering pass runs in the HIP kernels of libpulsar.so.
 The backward recomputes per-pixel hits from the workspace the forward filled
 (nothing per pixel is stored beyond the image and its log-normaliser).
+
+Pair capacity: a forward whose (tile, sphere) pairs exceed the capacity has
+invalid outputs. check_capacity="sync" waits for every forward and re-renders
+with a larger capacity; "lazy" (the default) never waits: the device status
+is copied to pinned host memory behind the forward and read once it has
+landed (by the backward, by the next call of the same Renderer, or by
+Renderer.check_status()), so a render step can be captured in a graph.
 """
 from __future__ import annotations
 
 import math
+import warnings
 from typing import Optional
 
 import torch
@@ -100,6 +108,30 @@ def camera_struct(cam, width: int, height: int, znear: float, zfar: float):
                      "[t(3), 6D rotation(6), focal, sensor_width]")
 
 
+class StatusProbe:
+    """A forward's device status (the first PULSAR_STATUS_BYTES bytes of its
+    workspace) copied into pinned host memory behind the forward's kernels on
+    the current stream, so nothing waits for it; read once it has landed."""
+
+    def __init__(self, ws: torch.Tensor, what: str):
+        self.what = what
+        self.host = torch.empty(_capi.PULSAR_STATUS_BYTES, dtype=torch.uint8, pin_memory=True)
+        self.host.copy_(ws[:_capi.PULSAR_STATUS_BYTES], non_blocking=True)
+        self.done = torch.cuda.Event()
+        self.done.record(torch.cuda.current_stream(ws.device))
+
+    def result(self, wait: bool = False):
+        """(code, pairs), or None while the copy is still in flight (wait=False)."""
+        if not wait and not self.done.query():
+            return None
+        self.done.synchronize()
+        return _capi.decode_status(self.host.numpy().tobytes())
+
+
+def _capturing() -> bool:
+    return torch.cuda.is_available() and torch.cuda.is_current_stream_capturing()
+
+
 def _forward_into(pos, radius, opacity, payload, bg, cam, params, check: bool):
     """Run pulsar_fwd into fresh outputs; grow the pair capacity and re-run
     if the device reports an overflow (only when check is set)."""
@@ -126,20 +158,37 @@ def _forward_into(pos, radius, opacity, payload, bg, cam, params, check: bool):
         params = grown
 
 
+def _raise_if_overflowed(probe) -> None:
+    """A backward whose forward overflowed the pair capacity has nothing
+    valid to differentiate; checked only if the status has already landed."""
+    if probe is None:
+        return
+    res = probe.result(wait=False)
+    if res is not None and res[0] != _capi.PULSAR_OK:
+        raise _capi.PulsarError(res[0], f"{probe.what} ({res[1]} tile pairs; raise max_pairs)")
+
+
 class PulsarFunction(torch.autograd.Function):
     """F = R(S, camera) with the hand-written backward of libpulsar.so."""
 
     @staticmethod
-    def forward(ctx, pos, radius, opacity, payload, bg, cam, params, check=True, cam_R=None,
-                cam_t=None, cam_f=None, cam_s=None):
+    def forward(ctx, pos, radius, opacity, payload, bg, cam, params, check="lazy", cam_R=None,
+                cam_t=None, cam_f=None, cam_s=None, probes=None):
         """cam is the pulsar_camera_t the kernels use; cam_R [3,3], cam_t [3],
         cam_f, cam_s, when given, are tensors holding the same values, and
         receive dLoss/dR (R as a free matrix), dLoss/dt, dLoss/dfocal and
-        dLoss/dsensor_width."""
+        dLoss/dsensor_width. check: "sync", "lazy" (a StatusProbe, appended
+        to the list `probes` when one is given) or False."""
         pos, radius, payload, bg = (t.contiguous() for t in (pos, radius, payload, bg))
         opacity = opacity.contiguous() if opacity is not None else None
+        sync = check in (True, "sync") and not _capturing()
         image, aux, ws, params = _forward_into(pos, radius, opacity, payload, bg, cam, params,
-                                               check)
+                                               sync)
+        ctx.probe = None
+        if check == "lazy" and not _capturing():
+            ctx.probe = StatusProbe(ws, "pulsar_fwd")
+            if isinstance(probes, list):
+                probes.append(ctx.probe)
         ctx.save_for_backward(pos, radius, opacity, payload, bg, image, aux, ws)
         ctx.cam, ctx.params = cam, params
         ctx.cam_shapes = [None if x is None else x.shape for x in (cam_R, cam_t, cam_f, cam_s)]
@@ -149,6 +198,7 @@ class PulsarFunction(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_image, grad_aux):
         pos, radius, opacity, payload, bg, image, aux, ws = ctx.saved_tensors
+        _raise_if_overflowed(ctx.probe)
         need = ctx.needs_input_grad
         n, C = payload.shape
 
@@ -174,7 +224,7 @@ class PulsarFunction(torch.autograd.Function):
         else:
             _capi.pulsar_bwd(pos, radius, opacity, payload, bg, ctx.cam, ctx.params, image, aux,
                              grad_image.contiguous(), gp, gr, go, gf, gb, ws)
-        return (gp, gr, go, gf, gb, None, None, None, *cam_grads)
+        return (gp, gr, go, gf, gb, None, None, None, *cam_grads, None)
 
 
 class PulsarBatchFunction(torch.autograd.Function):
@@ -182,7 +232,7 @@ class PulsarBatchFunction(torch.autograd.Function):
     pulsar_fwd_batched), with the batched hand-written backward."""
 
     @staticmethod
-    def forward(ctx, pos, radius, opacity, payload, bg, scenes, params):
+    def forward(ctx, pos, radius, opacity, payload, bg, scenes, params, check="lazy"):
         pos, radius, payload, bg = (t.contiguous() for t in (pos, radius, payload, bg))
         opacity = opacity.contiguous() if opacity is not None else None
         N, P = _capi.batch_sizes(scenes)
@@ -194,9 +244,13 @@ class PulsarBatchFunction(torch.autograd.Function):
                          dtype=torch.uint8)
         _capi.pulsar_fwd_batched(scenes, pos, radius, opacity, payload, bg, params, image, aux,
                                  ws)
-        code, _ = _capi.pulsar_query_status(ws)
-        if code != _capi.PULSAR_OK:
-            raise _capi.PulsarError(code, "pulsar_fwd_batched")
+        ctx.probe = None
+        if check in (True, "sync") and not _capturing():
+            code, _ = _capi.pulsar_query_status(ws)
+            if code != _capi.PULSAR_OK:
+                raise _capi.PulsarError(code, "pulsar_fwd_batched")
+        elif check == "lazy" and not _capturing():
+            ctx.probe = StatusProbe(ws, "pulsar_fwd_batched")
         ctx.save_for_backward(pos, radius, opacity, payload, bg, image, aux, ws)
         ctx.scenes, ctx.params = scenes, params
         ctx.mark_non_differentiable(aux)
@@ -205,6 +259,7 @@ class PulsarBatchFunction(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_image, grad_aux):
         pos, radius, opacity, payload, bg, image, aux, ws = ctx.saved_tensors
+        _raise_if_overflowed(ctx.probe)
         need = ctx.needs_input_grad
         N, C = payload.shape
         B = bg.shape[0]
@@ -220,13 +275,13 @@ class PulsarBatchFunction(torch.autograd.Function):
             grad_image = torch.zeros_like(image)
         _capi.pulsar_bwd_batched(ctx.scenes, pos, radius, opacity, payload, bg, ctx.params,
                                  image, aux, grad_image.contiguous(), gp, gr, go, gf, gb, ws)
-        return gp, gr, go, gf, gb, None, None
+        return gp, gr, go, gf, gb, None, None, None
 
 
 def render_batch(cams, counts, pos, radius, payload, opacity=None, bg=None, gamma=0.1,
                  K: int = 5, eps: float = 1e-5, min_radius_px: float = 0.0, widths=None,
                  heights=None, min_depth: float = 1.0, max_depth: float = 10.0,
-                 params=None):
+                 params=None, check_capacity="lazy"):
     """Renders B scenes in one batched call. cams: B cameras (pulsar_camera_t,
     objects with R/t or 8-vectors, the latter two with widths/heights given);
     counts: spheres per scene, the sphere tensors packed in scene order.
@@ -245,7 +300,8 @@ def render_batch(cams, counts, pos, radius, payload, opacity=None, bg=None, gamm
         bg = torch.zeros((B, C), device=payload.device, dtype=torch.float32)
     if params is None:
         params = _capi.make_params(gamma, eps, min_radius_px, K)
-    image, _ = PulsarBatchFunction.apply(pos, radius, opacity, payload, bg, scenes, params)
+    image, _ = PulsarBatchFunction.apply(pos, radius, opacity, payload, bg, scenes, params,
+                                         check_capacity)
     out, p0 = [], 0
     for s in structs:
         hw = int(s.width) * int(s.height)
@@ -267,19 +323,47 @@ class Renderer(torch.nn.Module):
     """
 
     def __init__(self, width: int, height: int, max_num_spheres: int, n_channels: int = 3,
-                 K: int = 5, max_pairs: int = 0, check_capacity: bool = True,
+                 K: int = 5, max_pairs: int = 0, check_capacity="lazy",
                  autotune: bool = False, tune_cache: Optional[str] = None):
         super().__init__()
         self.width, self.height = int(width), int(height)
         self.max_num_spheres, self.n_channels, self.K = int(max_num_spheres), int(n_channels), \
             int(K)
         self.max_pairs = int(max_pairs)
-        self.check_capacity = bool(check_capacity)
+        if check_capacity is True:
+            check_capacity = "sync"
+        if check_capacity not in ("sync", "lazy", False):
+            raise ValueError('check_capacity must be "sync", "lazy" or False')
+        self.check_capacity = check_capacity
+        self._probes = []  # status probes of calls not yet checked
         self.autotune = bool(autotune)
         self._tune_cache = None
         self._tune_path = tune_cache
         self._knobs = {}
         _capi.load()
+
+    def check_status(self, wait: bool = True) -> None:
+        """Reads the status of earlier lazy-checked calls (waiting for them
+        when wait is set). After an overflow the calls from then on use a
+        larger pair capacity; the overflowing call's outputs were invalid,
+        which a warning reports (or, with wait, an exception)."""
+        pending = []
+        for pr in self._probes:
+            res = pr.result(wait=wait)
+            if res is None:
+                pending.append(pr)
+                continue
+            code, pairs = res
+            if code != _capi.PULSAR_OK:
+                grown = max(pairs * 5 // 4 + 1024, 2 * self.max_pairs)
+                self.max_pairs = int(min(2**31 - 1, grown))
+                msg = (f"a render produced {pairs} tile pairs, more than its capacity; its "
+                       f"outputs were invalid. Later renders use max_pairs={self.max_pairs}.")
+                self._probes = pending
+                if wait:
+                    raise _capi.PulsarError(code, msg)
+                warnings.warn(msg, RuntimeWarning, stacklevel=3)
+        self._probes = pending[-64:]
 
     def _tuned(self, params, pos, radius, opacity, payload, bg, cs):
         """Knobs for this workload from the tuning cache, or measured now on
@@ -342,6 +426,8 @@ class Renderer(torch.nn.Module):
                                    self.height)
         else:
             cs = camera_struct(cam, self.width, self.height, min_depth, max_depth)
+        if self.check_capacity == "lazy" and self._probes and not _capturing():
+            self.check_status(wait=False)
         flags = ((_capi.PULSAR_ORTHO if orthographic else 0) |
                  (_capi.PULSAR_BLEND_TOPK if blend_topk else 0) |
                  (_capi.PULSAR_GRAD_PAPER_NORM if paper_gradients else 0))
@@ -358,5 +444,5 @@ class Renderer(torch.nn.Module):
             # no backward can follow: skip keeping its per-pixel state
             params.flags |= _capi.PULSAR_NO_BWD_AUX
         image, aux = PulsarFunction.apply(pos, radius, opacity, payload, bg, cs, params,
-                                          self.check_capacity, *cam_tensors)
+                                          self.check_capacity, *cam_tensors, self._probes)
         return (image, aux) if return_aux else image

@@ -261,3 +261,119 @@ def test_batched_variants_match_oracle(flags):
         assert_close(out["L"][ok], fwd["L"][ok], IMAGE_REL, f"scene {b} log-normaliser")
         g = ref.backward(wl.scene, wl.camera, PARAMS, G, fwd)
         compare_grads(out, g, f"scene {b}")
+
+
+def _packed(wls):
+    import torch
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(np.asarray(a, np.float32))).cuda()
+    C = wls[0].scene.C
+    return dict(pos=t(np.concatenate([w.scene.pos for w in wls])),
+                rad=t(np.concatenate([w.scene.radius for w in wls])),
+                opa=t(np.concatenate([w.scene.opacity for w in wls])),
+                pay=t(np.concatenate([w.scene.payload for w in wls])),
+                bg=t(np.stack([w.scene.bg for w in wls])),
+                G=t(np.concatenate([sg.upstream_grad(70 + b, w.camera.height, w.camera.width, C)
+                                    .reshape(-1, C) for b, w in enumerate(wls)])))
+
+
+def test_device_cameras_in_a_graph():
+    """pulsar_fwd_batched_devcam reads the cameras from device memory when the
+    work runs: a batched forward + backward captured once renders, at each
+    replay, with the cameras then in the array, bitwise equal to
+    pulsar_fwd_batched / pulsar_bwd_batched with those cameras on the host."""
+    import torch
+    wls = sorted(sg.config4_scenes(), key=lambda w: w.scene.n)[:3]
+    par = wls[0].params
+    C = wls[0].scene.C
+    B = len(wls)
+    _say(f"[batch] device cameras, {B} scenes {[w.scene.n for w in wls]}")
+    d = _packed(wls)
+    ps = _capi.make_params(par.gamma, par.eps, par.min_radius_px, par.K)
+    cams0 = [sg_cam(w) for w in wls]
+    scenes = _capi.make_scenes(cams0, [w.scene.n for w in wls])
+    N, P = _capi.batch_sizes(scenes)
+    ws = torch.empty(_capi.pulsar_batch_workspace_size(scenes, C, ps), dtype=torch.uint8,
+                     device="cuda:0")
+    d_cams = torch.from_numpy(np.frombuffer(_capi.cameras_bytes(cams0), np.uint8).copy()).cuda()
+
+    def outs():
+        return [torch.empty(s, device="cuda:0") for s in
+                ((P, C), (P,), (N, 3), (N,), (N,), (N, C), (B, C))]
+
+    og = outs()
+
+    def step(o, s, devcam):
+        if devcam:
+            _capi.pulsar_fwd_batched_devcam(scenes, d_cams, d["pos"], d["rad"], d["opa"],
+                                            d["pay"], d["bg"], ps, o[0], o[1], ws, s)
+        else:
+            _capi.pulsar_fwd_batched(host_scenes, d["pos"], d["rad"], d["opa"], d["pay"],
+                                     d["bg"], ps, o[0], o[1], ws, s)
+        _capi.pulsar_bwd_batched(scenes if devcam else host_scenes, d["pos"], d["rad"], d["opa"],
+                                 d["pay"], d["bg"], ps, o[0], o[1], d["G"], *o[2:], ws, s)
+
+    host_scenes = scenes
+    step(og, torch.cuda.current_stream(), True)  # warm-up outside the capture
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step(og, torch.cuda.current_stream(), True)
+    rng = np.random.default_rng(17)
+    oe = outs()
+    for k in range(4):
+        cams = []
+        for w in wls:
+            v = rng.standard_normal(3)
+            v /= np.linalg.norm(v)
+            c = sg.look_at_camera(4.0 * v, rng.uniform(-0.2, 0.2, 3), [0.0, 0.0, 1.0],
+                                  w.camera.width, w.camera.height,
+                                  focal=float(rng.uniform(0.8, 1.2)))
+            cams.append(sg_cam(types_ns(c)))
+        d_cams.copy_(torch.from_numpy(np.frombuffer(_capi.cameras_bytes(cams), np.uint8).copy()))
+        graph.replay()
+        torch.cuda.synchronize()
+        code, _ = _capi.pulsar_query_status(ws)
+        assert code == _capi.PULSAR_OK
+        got = [x.clone() for x in og]
+        # eager work between replays: the same cameras through the host table
+        host_scenes = _capi.make_scenes(cams, [w.scene.n for w in wls])
+        step(oe, torch.cuda.current_stream(), False)
+        torch.cuda.synchronize()
+        for name, a, b in zip(["image", "aux", "pos", "radius", "opacity", "payload", "bg"],
+                              got, oe):
+            assert torch.equal(a, b), f"replay {k}: {name} differs from the host-camera call"
+
+
+def types_ns(cam):
+    """A Workload-like holder for sg_cam."""
+    import types
+    return types.SimpleNamespace(camera=cam)
+
+
+def test_invalid_device_camera_is_reported():
+    import torch
+    wls = sorted(sg.config4_scenes(), key=lambda w: w.scene.n)[:2]
+    par = wls[0].params
+    C = wls[0].scene.C
+    d = _packed(wls)
+    ps = _capi.make_params(par.gamma, par.eps, par.min_radius_px, par.K)
+    cams = [sg_cam(w) for w in wls]
+    scenes = _capi.make_scenes(cams, [w.scene.n for w in wls])
+    N, P = _capi.batch_sizes(scenes)
+    bad = _capi.make_camera(cams[1].R, cams[1].t, -1.0, cams[1].sensor_width, cams[1].znear,
+                            cams[1].zfar, cams[1].width, cams[1].height)
+    d_cams = torch.from_numpy(np.frombuffer(_capi.cameras_bytes([cams[0], bad]),
+                                            np.uint8).copy()).cuda()
+    ws = torch.empty(_capi.pulsar_batch_workspace_size(scenes, C, ps), dtype=torch.uint8,
+                     device="cuda:0")
+    image, aux = torch.empty((P, C), device="cuda:0"), torch.empty((P,), device="cuda:0")
+    _capi.pulsar_fwd_batched_devcam(scenes, d_cams, d["pos"], d["rad"], d["opa"], d["pay"],
+                                    d["bg"], ps, image, aux, ws)
+    code, _ = _capi.pulsar_query_status(ws)
+    assert code == _capi.PULSAR_ERR_INVALID_ARGUMENT
+    # the same workspace with valid cameras is fine again
+    d_cams.copy_(torch.from_numpy(np.frombuffer(_capi.cameras_bytes(cams), np.uint8).copy()))
+    _capi.pulsar_fwd_batched_devcam(scenes, d_cams, d["pos"], d["rad"], d["opa"], d["pay"],
+                                    d["bg"], ps, image, aux, ws)
+    code, _ = _capi.pulsar_query_status(ws)
+    assert code == _capi.PULSAR_OK
