@@ -110,13 +110,25 @@ typedef struct pulsar_camera {
  *   plane and focal plays no part (it must still be valid). The minimum size
  *   becomes the constant radius min_radius_px * pitch. pulsar_bwd_camera
  *   returns PULSAR_ERR_UNSUPPORTED for it.
- * Storing per-pixel hit lists instead of recomputing them (App. B stores the
- * nearest hits per pixel) is not built: its bit is reserved. */
+ * PULSAR_STORE_HITS: the paper's preparation for the backward pass (App. B):
+ *   the forward also stores every pixel's K nearest hits (depth and sphere
+ *   index, 8 K bytes per pixel at the end of the workspace; pixels of tiles
+ *   that no sphere touches have none) and pulsar_bwd
+ *   takes them from there pixel by pixel, recomputing each stored hit's
+ *   geometry, instead of re-testing every (tile, sphere) pair against the
+ *   pixel's K-th nearest hit. The per-sphere sums are then gathered with
+ *   float atomics, so the gradients equal those of the default backward up
+ *   to summation order (they are not bitwise reproducible). Forward and
+ *   backward must both set it (with PULSAR_REBIN the backward stores them
+ *   itself); a backward on a workspace whose forward stored no hits writes
+ *   zero gradients and pulsar_query_status reports
+ *   PULSAR_ERR_INVALID_ARGUMENT. */
 #define PULSAR_NO_BWD_AUX 0x1u
 #define PULSAR_REBIN 0x2u
 #define PULSAR_GRAD_PAPER_NORM 0x4u
 #define PULSAR_BLEND_TOPK 0x8u
 #define PULSAR_ORTHO 0x10u
+#define PULSAR_STORE_HITS 0x20u
 
 /* min_radius_px preset for the paper's rule that every sphere is drawn at
  * least one pixel large, so none falls between the pixel rays (App. B,
@@ -133,9 +145,9 @@ typedef struct pulsar_params {
                            (App. B, Step 0). 0 = off. */
   int32_t K;            /* nearest hits per pixel that receive gradients, 1..32 */
   uint32_t flags;       /* OR of PULSAR_NO_BWD_AUX, PULSAR_REBIN,
-                           PULSAR_GRAD_PAPER_NORM, PULSAR_BLEND_TOPK and
-                           PULSAR_ORTHO; any other bit is reserved
-                           (PULSAR_ERR_UNSUPPORTED) */
+                           PULSAR_GRAD_PAPER_NORM, PULSAR_BLEND_TOPK,
+                           PULSAR_ORTHO and PULSAR_STORE_HITS; any other bit
+                           is reserved (PULSAR_ERR_UNSUPPORTED) */
   int32_t max_pairs;    /* capacity of (screen tile, sphere) pairs; 0 = default
                            (2 n + number of tiles + 65536) */
   int32_t depth_bits;   /* reserved, must be 0 (PULSAR_ERR_UNSUPPORTED

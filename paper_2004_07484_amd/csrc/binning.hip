@@ -375,12 +375,13 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortArgs A) {
 // counters for k_plan.
 __global__ __launch_bounds__(1024) void k_ranges(uint32_t T, const uint32_t* __restrict__ keys,
                                                  const unsigned long long* __restrict__ ebase,
-                                                 int nblk_emit, long long cap,
+                                                 int nblk_emit, long long cap, uint32_t hits_k,
                                                  Status* __restrict__ status,
                                                  uint2* __restrict__ trange) {
   const unsigned long long total = ebase[nblk_emit];
   const uint32_t used = stored_pairs(ebase, nblk_emit, cap);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
+    status->hits_k = hits_k;  // the raster pass that follows stores them
     status->pairs = total;
     status->used = used;
     status->code = total > (unsigned long long)cap ? uint32_t(-PULSAR_ERR_CAPACITY)
@@ -601,7 +602,7 @@ void launch_binning(const Plan& q, char* ws, hipStream_t stream) {
   const long long rg = (q.cap + 4095) / 4096;
   hipLaunchKernelGGL(k_ranges, dim3(unsigned(rg < 256 ? rg : 256)), dim3(1024), 0, stream,
                      uint32_t(q.T), ws_ptr<uint32_t>(ws, q.off_keys), E.ebase, q.nblk_emit,
-                     (long long)q.cap, status, E.trange);
+                     (long long)q.cap, q.store_hits ? uint32_t(q.K) : 0u, status, E.trange);
   hipLaunchKernelGGL(k_plan, dim3(unsigned((q.T + kPlanThreads - 1) / kPlanThreads)),
                      dim3(kPlanThreads), 0, stream, uint32_t(q.T), E.trange, uint32_t(q.chunk),
                      (long long)q.pcap, uint32_t(q.max_chunks), status,

@@ -57,7 +57,7 @@ int check_params(const pulsar_params_t* p) {
   if (p->raster_blocks != 0 && (p->raster_blocks < 256 || p->raster_blocks > 65536))
     return PULSAR_ERR_INVALID_ARGUMENT;
   if ((p->flags & ~(PULSAR_NO_BWD_AUX | PULSAR_REBIN | PULSAR_GRAD_PAPER_NORM |
-                    PULSAR_BLEND_TOPK | PULSAR_ORTHO)) != 0u)
+                    PULSAR_BLEND_TOPK | PULSAR_ORTHO | PULSAR_STORE_HITS)) != 0u)
     return PULSAR_ERR_UNSUPPORTED;
   if (!std::isfinite(p->stop_share) || p->stop_share < 0.f || p->stop_share >= 1.f)
     return PULSAR_ERR_INVALID_ARGUMENT;
@@ -243,6 +243,11 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   q.ncampart = int64_t(q.B) + n / kCamSpan + 1;
   q.off_camg = take(bwd ? nn * 16 : 0);
   q.off_campart = take(bwd ? size_t(q.ncampart) * 16 * 8 : 0);
+  // the stored per-pixel K nearest hits come last, so every other offset is
+  // the same with or without them
+  q.K = p->K;
+  q.store_hits = (p->flags & PULSAR_STORE_HITS) != 0u ? 1 : 0;
+  q.off_hits = take(q.store_hits ? size_t(q.npix) * size_t(p->K) * 8 : 0);
   q.total = o;
   *out = q;
   return PULSAR_OK;

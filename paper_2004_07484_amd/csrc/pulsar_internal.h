@@ -45,7 +45,8 @@ struct Status {
   uint32_t npartials;           // partial blend states needed by tiles with several work items
   uint32_t nmerge;              // tiles with several work items
   uint32_t bad_cam;             // a camera read from device memory was invalid
-  uint32_t pad[55];
+  uint32_t hits_k;              // the forward stored K nearest hits per pixel (0: none)
+  uint32_t pad[54];
 };
 static_assert(sizeof(Status) == 256, "status block");
 static_assert(offsetof(Status, pairs) + sizeof(unsigned long long) == PULSAR_STATUS_BYTES,
@@ -123,6 +124,8 @@ struct Plan {
   // emission blocks of emit_rounds rounds of kEmitRound spheres
   int sort_passes, sort_digit, emit_rounds, nblk_emit;
   int estop;          // early termination: tiles are sorted by earliest hit distance
+  int K, store_hits;  // stored per-pixel K nearest hits (PULSAR_STORE_HITS)
+  size_t off_hits;    // [npix][K] (t, sphere index), last in the workspace
   size_t off_tmin;    // [n] float32 earliest possible hit distance (early termination)
   size_t off_stop;    // [npix] (distance, pair position) of the first skipped hit
   size_t off_status, off_counts, off_trect, off_rec;

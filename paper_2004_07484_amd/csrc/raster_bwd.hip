@@ -51,6 +51,11 @@ struct BwdKernelArgs {
   // pixel the first hit the forward skipped (hits from it on take no part)
   const float* tmin;
   const float2* stop;
+  // PULSAR_STORE_HITS: per pixel the forward's K nearest (t bits, sphere index)
+  const uint2* hits;
+  const uint4* tinfo;  // per tile (first partial slot, work items)
+  int K;
+  uint32_t T;
 };
 
 constexpr int kBgThreads = 256;
@@ -151,13 +156,13 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
     // its sphere, whose record and payload row are read in place
     uint32_t j = beg + uint32_t(tid);
     float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra, rc = ra, rd = ra;
-    uint32_t bo = 0;
+    uint32_t bo = 0, sph = 0;
     float tmin = 0.f;
     float f[CM];
 #pragma unroll
     for (int c = 0; c < CM; ++c) f[c] = 0.f;
     auto load_record = [&](uint32_t jj) {
-      const uint32_t sph = min(A.svals[jj], A.last_sph);
+      sph = min(A.svals[jj], A.last_sph);
       const float4* rp = A.rec + 4 * size_t(sph);
       ra = rp[0];
       rb = rp[1];
@@ -212,7 +217,7 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
     for (; j < end; j += kWave * kBwdWaves) {
       if (j != beg + uint32_t(tid)) load_record(j);
       const SphereRec s = unpack_rec(ra, rb, rc, rd);
-      const uint32_t id = pair_position(ra, rd, bo, ttx, tty);  // tie-break and slot
+      const uint32_t id = pair_position(ra, rd, bo, ttx, tty);  // the pair's slot
       const uint32_t p1 = __float_as_uint(rd.z);
       const int xa = max(s.x0, ts.tx0), xb = min(int(p1 & 0xffffu), ts.tx0 + kTileW - 1);
       const int ya = max(s.y0, ts.ty0), yb = min(int(p1 >> 16), ts.ty0 + kTileH - 1);
@@ -223,7 +228,7 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
       uint32_t nh = 0;
       const float tlo = front_bound(s);
       // early termination: the sphere's place in the depth-sort order
-      const uint64_t dkey = ES ? (uint64_t(__float_as_uint(tmin)) << 32) | id : 0ull;
+      const uint64_t dkey = ES ? (uint64_t(__float_as_uint(tmin)) << 32) | sph : 0ull;
       for (int py = ya; py <= yb; ++py) {
         for (int px = xa; px <= xb; ++px) {
           const int pl = (py - ts.ty0) * kTileW + (px - ts.tx0);
@@ -235,8 +240,9 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
           const PixelRay ray = load_ray(s_ray, pl, px, py);
           Hit h;
           if (!exact_hit(ray, s, bc.zfar, h)) continue;
+          // among the pixel's K nearest: (t, sphere index) up to its K-th
           const uint32_t ik = s_ik[pl];
-          if (!(id == ik || h.t < tk || (h.t == tk && id < ik))) continue;
+          if (!(sph == ik || h.t < tk || (h.t == tk && sph < ik))) continue;
           float hs = -s_GF[pl];  // G . (f_k - F)
 #pragma unroll
           for (int c = 0; c < CM; ++c) hs += s_G[c][pl] * f[c];
@@ -321,7 +327,7 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A,
       const float4* rp = A.rec + 4 * size_t(id);
       const float4 a = rp[0], d = rp[3];
       const SphereRec s = unpack_rec(a, rp[1], rp[2], d);
-      // pair position (tie-break and slot)
+      // the pair's slot
       const uint32_t slot =
           pair_position(a, d, uint32_t(A.boff[id / kProjectBlock]), tx0 / kTileW, ty0 / kTileH);
       const uint32_t p1 = __float_as_uint(d.z);
@@ -331,7 +337,7 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A,
       const int ya = max(s.y0, ty0), yb = min(int(p1 >> 16), ty0 + kTileH - 1);
       const float tlo = front_bound(s);
       const uint64_t dkey =
-          A.stop ? (uint64_t(__float_as_uint(A.tmin[id])) << 32) | slot : 0ull;
+          A.stop ? (uint64_t(__float_as_uint(A.tmin[id])) << 32) | id : 0ull;
       for (int iy = ya; iy <= yb; ++iy) {
         for (int ix = xa; ix <= xb; ++ix) {
           const int pl = (iy - ty0) * kTileW + (ix - tx0);
@@ -342,7 +348,7 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A,
           Hit h;
           if (!exact_hit(ray, s, bc.zfar, h)) continue;
           const uint32_t ik = s_ik[pl];
-          if (!(slot == ik || h.t < tk || (h.t == tk && slot < ik))) continue;
+          if (!(id == ik || h.t < tk || (h.t == tk && id < ik))) continue;
           const size_t pp = size_t(sc.pix_off) + size_t(iy) * size_t(cam.W) + size_t(ix);
           const float* Gp = A.grad_image + pp * size_t(C);
           const float* Fp = A.image + pp * size_t(C);
@@ -724,6 +730,120 @@ __global__ __launch_bounds__(kBgThreads) void k_bg_partial_wide(SceneTable tab,
   }
 }
 
+// PULSAR_STORE_HITS: every slot of the call starts at zero (the hits add
+// into them).
+__global__ __launch_bounds__(256) void k_zero_slots(const Status* __restrict__ status,
+                                                    float4* __restrict__ pslot, int ps4) {
+  if (status->code != 0u) return;
+  const size_t total = size_t(status->used) * size_t(ps4);
+  for (size_t k = size_t(blockIdx.x) * 256 + threadIdx.x; k < total; k += size_t(gridDim.x) * 256)
+    pslot[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// PULSAR_STORE_HITS backward (App. B keeps each pixel's nearest hits from the
+// forward): one wave per non-empty tile, lane p = pixel p. Each of the pixel's stored K
+// nearest hits names its sphere; the hit's geometry is recomputed from the
+// sphere's record with the same hit test and gradient terms as k_bwd_items,
+// and its terms are added with float atomics into the slot of its (tile,
+// sphere) pair, which k_finalize then sums per sphere. CM = 0: payloads wider
+// than the register budget, whose terms go into the caller's rows (zeroed by
+// k_bwd_prep) and whose slots hold dL/dc, dL/dR | dL/do, dL/d(f/s), count.
+template <int CM, bool CAM>
+__global__ __launch_bounds__(kWave) void k_bwd_hits(BwdKernelArgs A,
+                                                    const SceneDev* __restrict__ scenes,
+                                                    const uint32_t* __restrict__ tile_start) {
+  constexpr int CS = CM > 0 ? CM : 1;
+  const int lane = threadIdx.x;
+  // a workspace whose forward stored no hits (or other ones): nothing is read
+  if (A.status->code != 0u) return;
+  if (A.status->hits_k != uint32_t(A.K)) {
+    if (blockIdx.x == 0 && lane == 0)
+      A.status->code = uint32_t(-PULSAR_ERR_INVALID_ARGUMENT);
+    return;
+  }
+  const int C = A.C;
+  for (uint32_t tile = blockIdx.x; tile < A.T; tile += gridDim.x) {
+    // a tile no sphere touches was filled with the background, and its
+    // pixels' hit entries were never written: nothing to read there
+    if (A.tinfo[tile].y == 0u) continue;
+    const TileScene ts = tile_scene(scenes, tile_start, A.tab.B, tile);
+    const SceneDev& sc = scenes[ts.b];
+    const CamDev cam = sc.cam;
+    const BlendConst bc = sc.bc;
+    const int px = ts.tx0 + lane % kTileW, py = ts.ty0 + lane / kTileW;
+    if (px >= cam.W || py >= cam.H) continue;
+    const size_t p = size_t(sc.pix_off) + size_t(py) * size_t(cam.W) + size_t(px);
+    const uint2* hp = A.hits + p * size_t(A.K);
+    if (hp[0].y == 0xffffffffu) continue;  // no hit at all
+    const int ttx = ts.tx0 / kTileW, tty = ts.ty0 / kTileH;
+    const PixelRay ray = make_ray(cam, px, py);
+    const float L2 = A.aux[p] * 1.4426950408889634f;
+    const float* Gp = A.grad_image + p * size_t(C);
+    const float* Fp = A.image + p * size_t(C);
+    float G[CS], gf0 = 0.f;
+    if (CM > 0) {
+#pragma unroll
+      for (int c = 0; c < CS; ++c) G[c] = c < C ? Gp[c] : 0.f;
+#pragma unroll
+      for (int c = 0; c < CS; ++c) gf0 += c < C ? G[c] * Fp[c] : 0.f;
+    }
+    for (int j = 0; j < A.K; ++j) {
+      const uint2 e = hp[j];
+      if (e.y == 0xffffffffu) break;  // fewer than K hits
+      const uint32_t sph = min(e.y, A.last_sph);
+      const float4* rp = A.rec + 4 * size_t(sph);
+      const float4 ra = rp[0], rd = rp[3];
+      const SphereRec s = unpack_rec(ra, rp[1], rp[2], rd);
+      Hit h;
+      if (!exact_hit(ray, s, bc.zfar, h)) continue;  // never, for a stored hit
+      const float* fk = A.payload + size_t(sph) * size_t(C);
+      float hs = 0.f;
+      if (CM > 0) {
+        hs = -gf0;
+#pragma unroll
+        for (int c = 0; c < CS; ++c) hs += c < C ? G[c] * fk[c] : 0.f;
+      } else {
+        for (int c = 0; c < C; ++c) hs += Gp[c] * (fk[c] - Fp[c]);
+      }
+      const HitGrad g = hit_grad(ray, s, h, cam, bc, L2, hs);
+      const float gk = CAM ? hit_grad_kappa(ray, s, h, cam, g) : 0.f;
+      const uint32_t slot =
+          pair_position(ra, rd, uint32_t(A.boff[sph / kProjectBlock]), ttx, tty);
+      float* sr = reinterpret_cast<float*>(A.pslot + size_t(slot) * size_t(A.ps4));
+      atomicAdd(sr + 0, g.gcx);
+      atomicAdd(sr + 1, g.gcy);
+      atomicAdd(sr + 2, g.gcz);
+      atomicAdd(sr + 3, g.gR);
+      if (CM > 0) {
+#pragma unroll
+        for (int c = 0; c < CS; ++c)
+          if (c < C) atomicAdd(sr + 4 + c, g.w * G[c]);
+        atomicAdd(sr + 4 + CM, g.go);
+        if (CAM) atomicAdd(sr + 5 + CM, gk);
+        atomicAdd(sr + 6 + CM, 1.f);
+      } else {
+        if (A.need_pay) {
+          float* gp = A.grad_payload + size_t(sph) * size_t(C);
+          for (int c = 0; c < C; ++c) atomicAdd(gp + c, g.w * Gp[c]);
+        }
+        atomicAdd(sr + 4, g.go);
+        if (CAM) atomicAdd(sr + 5, gk);
+        atomicAdd(sr + 6, 1.f);
+      }
+    }
+  }
+}
+
+template <int CM>
+static void launch_hits(const BwdKernelArgs& A, unsigned grid, hipStream_t stream) {
+  if (A.need_cam)
+    hipLaunchKernelGGL((k_bwd_hits<CM, true>), dim3(grid), dim3(kWave), 0, stream, A,
+                       A.tab.scenes, A.tab.tile_start);
+  else
+    hipLaunchKernelGGL((k_bwd_hits<CM, false>), dim3(grid), dim3(kWave), 0, stream, A,
+                       A.tab.scenes, A.tab.tile_start);
+}
+
 template <int CM, bool ES>
 static void launch_items_es(const BwdKernelArgs& A, dim3 grid, dim3 block, hipStream_t stream) {
   if (A.need_cam)
@@ -881,36 +1001,63 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
   A.eps2 = a.eps2;
   A.tmin = q.estop ? ws_ptr<float>(ws, q.off_tmin) : nullptr;
   A.stop = q.estop ? ws_ptr<float2>(ws, q.off_stop) : nullptr;
+  A.hits = q.store_hits ? ws_ptr<uint2>(ws, q.off_hits) : nullptr;
+  A.tinfo = ws_ptr<uint4>(ws, q.off_tinfo);
+  A.K = q.K;
+  A.T = uint32_t(q.T);
+  const bool store = q.store_hits != 0;
+  // the pair-parallel kernel also computes the background block sums
+  if (store) A.bgsum = nullptr;
   float* bgsum = ws_ptr<float>(ws, q.off_bgsum);
   const uint32_t* counts = ws_ptr<uint32_t>(ws, q.off_counts);
   stage_begin(PULSAR_STAGE_ZERO, stream);
   if (wide && a.grad_payload && q.n > 0)
     hipLaunchKernelGGL(k_bwd_prep, dim3(unsigned((q.n + 255) / 256)), dim3(256), 0, stream,
                        int(q.n), counts, a.C, a.grad_payload);
+  if (store)
+    hipLaunchKernelGGL(k_zero_slots, dim3(1024), dim3(256), 0, stream, A.status, A.pslot, A.ps4);
   stage_end(PULSAR_STAGE_ZERO, stream);
   stage_begin(PULSAR_STAGE_RASTER_BWD, stream);
-  // as many waves as the forward's grid of one-wave blocks: blocks past the
-  // work items would only be dispatched after them to find nothing to do
-  const long long bg = q.raster_grid / kBwdWaves > 0 ? q.raster_grid / kBwdWaves : 1;
-  const dim3 ig{unsigned(bg), 1u, 1u}, it{unsigned(kWave * kBwdWaves), 1u, 1u};
-  if (a.C <= 1)
-    launch_items<1>(A, ig, it, stream);
-  else if (a.C <= 2)
-    launch_items<2>(A, ig, it, stream);
-  else if (a.C <= 4)
-    launch_items<4>(A, ig, it, stream);
-  else if (a.C <= 8)
-    launch_items<8>(A, ig, it, stream);
-  else if (a.C <= 16)
-    launch_items<16>(A, ig, it, stream);
-  else if (!wide)
-    launch_items<32>(A, ig, it, stream);
-  else
-    hipLaunchKernelGGL(k_bwd_chunks_wide, dim3(unsigned(q.raster_grid)), dim3(kWave), 0, stream,
-                       A, A.tab.scenes, A.tab.tile_start, A.desc);
+  if (store) {
+    const unsigned hg = unsigned(q.T < q.raster_grid ? q.T : q.raster_grid);
+    if (a.C <= 1)
+      launch_hits<1>(A, hg, stream);
+    else if (a.C <= 2)
+      launch_hits<2>(A, hg, stream);
+    else if (a.C <= 4)
+      launch_hits<4>(A, hg, stream);
+    else if (a.C <= 8)
+      launch_hits<8>(A, hg, stream);
+    else if (a.C <= 16)
+      launch_hits<16>(A, hg, stream);
+    else if (!wide)
+      launch_hits<32>(A, hg, stream);
+    else
+      launch_hits<0>(A, hg, stream);
+  } else {
+    // as many waves as the forward's grid of one-wave blocks: blocks past the
+    // work items would only be dispatched after them to find nothing to do
+    const long long bg = q.raster_grid / kBwdWaves > 0 ? q.raster_grid / kBwdWaves : 1;
+    const dim3 ig{unsigned(bg), 1u, 1u}, it{unsigned(kWave * kBwdWaves), 1u, 1u};
+    if (a.C <= 1)
+      launch_items<1>(A, ig, it, stream);
+    else if (a.C <= 2)
+      launch_items<2>(A, ig, it, stream);
+    else if (a.C <= 4)
+      launch_items<4>(A, ig, it, stream);
+    else if (a.C <= 8)
+      launch_items<8>(A, ig, it, stream);
+    else if (a.C <= 16)
+      launch_items<16>(A, ig, it, stream);
+    else if (!wide)
+      launch_items<32>(A, ig, it, stream);
+    else
+      hipLaunchKernelGGL(k_bwd_chunks_wide, dim3(unsigned(q.raster_grid)), dim3(kWave), 0, stream,
+                         A, A.tab.scenes, A.tab.tile_start, A.desc);
+  }
   stage_end(PULSAR_STAGE_RASTER_BWD, stream);
   stage_begin(PULSAR_STAGE_FINALIZE, stream);
-  if (a.grad_bg && wide) {
+  if (a.grad_bg && (wide || store)) {
     if (q.C <= kBgMaxC)
       hipLaunchKernelGGL(k_bg_partial, dim3(unsigned(q.nbgblk)), dim3(kBgThreads), 0, stream,
                          tab, a.aux, a.grad_image, int(q.C), a.eps2, bgsum);

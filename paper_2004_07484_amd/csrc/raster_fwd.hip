@@ -16,9 +16,7 @@
 // running maximum m of the base-2 exponents and rescales when it grows, so
 // exp never overflows down to gamma = 1e-5; every hit enters the sum. When
 // a backward pass follows, lane p also keeps its K nearest hits, ordered by
-// (t, sphere index); the index is represented by the pair's emission
-// position, which orders spheres the same way. The K-th one becomes the
-// pixel's gradient threshold.
+// (t, sphere index). The K-th one becomes the pixel's gradient threshold.
 // A tile with one chunk writes its pixels directly; otherwise every chunk
 // leaves a partial state (m, D, numerator, K-list) and k_fwd_merge combines
 // them in chunk order, so the result is deterministic. After its work items
@@ -108,7 +106,6 @@ struct FwdKernelArgs {
   uint32_t last_sph;                 // n - 1: sorted indices are clamped to it
   const float4* rec;                 // sphere records, 4 float4 per sphere
   const float* payload;              // the caller's payload rows [n, C]
-  const unsigned long long* boff;    // first pair of each projection block
   const float* bg;      // [B, C]
   float* image;
   float* aux;
@@ -128,6 +125,7 @@ struct FwdKernelArgs {
   const float* tmin;
   float2* stop;
   float lrho2;
+  uint2* hits;  // PULSAR_STORE_HITS: per pixel the K nearest (t bits, sphere index)
 };
 
 template <int CM, int KM>
@@ -149,6 +147,14 @@ __device__ __forceinline__ void write_pixel(const FwdKernelArgs& A, const CamDev
     A.thr[p] = k == kKeyNone ? make_float2(INFINITY, __uint_as_float(0xffffffffu))
                              : make_float2(__uint_as_float(uint32_t(k >> 32)),
                                            __uint_as_float(uint32_t(k)));
+    // the stored K nearest hits, nearest first (kKeyNone where fewer)
+    if (A.hits) {
+      uint2* hp = A.hits + p * size_t(A.K);
+#pragma unroll
+      for (int i = 0; i < KM; ++i)
+        if (i >= KM - A.K)
+          hp[i - (KM - A.K)] = make_uint2(uint32_t(kk[i] >> 32), uint32_t(kk[i]));
+    }
     // early termination: the first hit the pixel skipped, or none
     if (A.stop)
       A.stop[p] = make_float2(__uint_as_float(uint32_t(skey >> 32)),
@@ -276,7 +282,6 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM, ES)) void k_fwd_c
     uint64_t skey = kKeyNone;
     const bool inside = ray.px < cam.W && ray.py < cam.H;
 
-    const int ttx = tx0 / kTileW, tty = ty0 / kTileH;  // the tile, in tile units
     // the sorted pairs name their spheres, whose records and payload rows are
     // read in place; lanes past the end repeat the last pair, so every load
     // is unconditional. The next batch's sphere indices are requested with
@@ -297,12 +302,11 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM, ES)) void k_fwd_c
       for (int c = 0; c < CM; ++c)
         if (c < A.cn) __builtin_amdgcn_global_load_lds(fp + c, &s_pay[c][0], 4, 0, 0);
       if (ES) __builtin_amdgcn_global_load_lds(A.tmin + sph, &s_tmin[0], 4, 0, 0);
-      const uint32_t bo = uint32_t(A.boff[sph / kProjectBlock]);
       __builtin_amdgcn_s_waitcnt(kWaitVmem0);
       __syncthreads();
       const float4 a = s_rec[0][lane], d = s_rec[3][lane];
-      // pair position: orders spheres like their index
-      const uint32_t id = valid ? pair_position(a, d, bo, ttx, tty) : 0u;
+      // the sphere index breaks ties of equal hit distances
+      const uint32_t id = valid ? sph : 0u;
       // the sphere's rectangle inside this tile, in tile coordinates; the
       // (sphere, pixel) pairs are flattened over the wave by a prefix sum
       const uint32_t p0 = __float_as_uint(a.w), p1 = __float_as_uint(d.z);
@@ -585,7 +589,6 @@ static FwdKernelArgs raster_args(const Plan& q, const std::vector<SceneDev>& sce
   A.last_sph = q.n > 0 ? uint32_t(q.n - 1) : 0u;
   A.rec = ws_ptr<float4>(ws, q.off_rec);
   A.payload = a.payload;
-  A.boff = ws_ptr<unsigned long long>(ws, q.off_boff);
   A.bg = a.bg;
   A.image = a.image;
   A.aux = a.aux;
@@ -608,6 +611,7 @@ static FwdKernelArgs raster_args(const Plan& q, const std::vector<SceneDev>& sce
   A.vec4 = 0;
   A.tmin = q.estop ? ws_ptr<float>(ws, q.off_tmin) : nullptr;
   A.stop = q.estop ? ws_ptr<float2>(ws, q.off_stop) : nullptr;
+  A.hits = q.store_hits ? ws_ptr<uint2>(ws, q.off_hits) : nullptr;
   A.lrho2 = q.estop ? float(std::log2(double(a.stop_share) / (1.0 - double(a.stop_share)))) : 0.f;
   return A;
 }

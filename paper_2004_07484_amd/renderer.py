@@ -396,12 +396,15 @@ class Renderer(torch.nn.Module):
                 bg: Optional[torch.Tensor] = None, eps: float = 1e-5,
                 min_radius_px: float = 0.0, return_aux: bool = False,
                 orthographic: bool = False, blend_topk: bool = False,
-                paper_gradients: bool = False):
+                paper_gradients: bool = False, store_hits: bool = False,
+                stop_share: float = 0.0):
         """orthographic: parallel rays along +z (PULSAR_ORTHO; no camera
         gradient). blend_topk: only each pixel's K nearest hits blend
         (PULSAR_BLEND_TOPK). paper_gradients: the paper's gradients for
         optimisation, averaged over each sphere's pixels with the 3-pixel
-        position gate (PULSAR_GRAD_PAPER_NORM)."""
+        position gate (PULSAR_GRAD_PAPER_NORM). store_hits: the forward keeps
+        each pixel's K nearest hits for the backward (PULSAR_STORE_HITS).
+        stop_share: early ray termination at that share (0 = off)."""
         if pos.shape[0] > self.max_num_spheres:
             raise ValueError("more spheres than the renderer was built for")
         C = payload.shape[1]
@@ -430,10 +433,12 @@ class Renderer(torch.nn.Module):
             self.check_status(wait=False)
         flags = ((_capi.PULSAR_ORTHO if orthographic else 0) |
                  (_capi.PULSAR_BLEND_TOPK if blend_topk else 0) |
-                 (_capi.PULSAR_GRAD_PAPER_NORM if paper_gradients else 0))
+                 (_capi.PULSAR_GRAD_PAPER_NORM if paper_gradients else 0) |
+                 (_capi.PULSAR_STORE_HITS if store_hits else 0))
         if orthographic and torch.is_tensor(cam) and cam.requires_grad:
             raise ValueError("camera gradients are not available for the orthographic projection")
-        params = _capi.make_params(gamma, eps, min_radius_px, self.K, self.max_pairs, flags=flags)
+        params = _capi.make_params(gamma, eps, min_radius_px, self.K, self.max_pairs, flags=flags,
+                                   stop_share=stop_share)
         if self.autotune:
             params = self._tuned(params, pos.detach().contiguous(), radius.detach().contiguous(),
                                  None if opacity is None else opacity.detach().contiguous(),
