@@ -106,6 +106,185 @@ def cpu_baseline(wl, G, rows_n: int):
     return base, dict(rows=rows, fwd=fwd, grads=grads, G=Gm)
 
 
+def at_knobs(p) -> dict:
+    from paper_2004_07484_amd import autotune as at
+    return at.knobs_of(p)
+
+
+def cpu_one_thread(wl, rows_n: int = 2) -> dict:
+    """The oracle on one thread, on a few seeded rows of the same workload,
+    extrapolated to the full frame (the per-core cost of the baseline)."""
+    from oracle import reference as ref
+    H, W, C = wl.camera.height, wl.camera.width, wl.scene.C
+    rows = sorted(np.random.default_rng(54321).choice(H, rows_n, replace=False).tolist())
+    t0 = time.perf_counter()
+    fwd = ref.forward(wl.scene, wl.camera, wl.params, rows=rows, n_threads=1)
+    G = np.zeros((H, W, C), np.float32)
+    G[rows] = 1.0
+    G[fwd["ambiguous"]] = 0.0
+    ref.backward(wl.scene, wl.camera, wl.params, G, fwd, rows=rows)
+    dt = time.perf_counter() - t0
+    return {"value": round(dt * 1e3 * H / rows_n, 1), "unit": "ms/frame (extrapolated)",
+            "cores": 1, "sample": f"{rows_n} of {H} seeded rows, {dt:.1f} s"}
+
+
+def graph_time(fn, steps: int, warmup: int, stream) -> float:
+    """Median ms of fn(s) captured once in a HIP graph (s: the capturing
+    stream) and replayed on `stream`."""
+    import torch
+    fn(stream)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        fn(torch.cuda.current_stream())
+    for _ in range(warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    for e0, e1 in evs:
+        e0.record(stream)
+        graph.replay()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    return float(np.median([a.elapsed_time(b) for a, b in evs]))
+
+
+def bench_small(args, dev, wl) -> dict:
+    """One fwd + bwd of a small workload: microseconds per frame, eager and
+    graph-replayed (launch latency dominates at these sizes)."""
+    import torch
+
+    from paper_2004_07484_amd import _capi
+    sc, cam, par = wl.scene, wl.camera, wl.params
+    n, C = sc.payload.shape
+    H, W = cam.height, cam.width
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    pos, rad, opa, pay, bg = t(sc.pos), t(sc.radius), t(sc.opacity), t(sc.payload), t(sc.bg)
+    G = t(np.random.default_rng(wl.seed + 1000).standard_normal((H, W, C)).astype(np.float32))
+    cs = _capi.make_camera(cam.R, cam.t, cam.focal, cam.sensor_width, cam.znear, cam.zfar, W, H)
+    ps = _capi.make_params(par.gamma, par.eps, par.min_radius_px, par.K)
+    ws = torch.empty(_capi.pulsar_workspace_size(n, W, H, C, ps), dtype=torch.uint8, device=dev)
+    image, aux = torch.empty((H, W, C), device=dev), torch.empty((H, W), device=dev)
+    gp, gr, go = torch.empty((n, 3), device=dev), torch.empty(n, device=dev), \
+        torch.empty(n, device=dev)
+    gf, gb = torch.empty((n, C), device=dev), torch.empty(C, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(s=stream):
+        _capi.pulsar_fwd(pos, rad, opa, pay, bg, cs, ps, image, aux, ws, s)
+        _capi.pulsar_bwd(pos, rad, opa, pay, bg, cs, ps, image, aux, G, gp, gr, go, gf, gb, ws, s)
+
+    step()
+    code, pairs = _capi.pulsar_query_status(ws, stream)
+    assert code == _capi.PULSAR_OK
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for e0, e1 in evs:
+        e0.record(stream)
+        step()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    eager = float(np.median([a.elapsed_time(b) for a, b in evs]))
+    graph = graph_time(step, args.steps, args.warmup, stream)
+    code, _ = _capi.pulsar_query_status(ws, stream)
+    assert code == _capi.PULSAR_OK
+    fb, bb = io_bytes(n, H, W, C)
+    return {"workload": wl.name, "spheres": int(n), "width": W, "height": H, "channels": int(C),
+            "K": int(par.K), "tile_pairs": int(pairs), "eager_us": round(eager * 1e3, 1),
+            "graph_us": round(graph * 1e3, 1),
+            "io_roofline_frac": round((fb + bb) / (graph * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+
+
+def bench_optimise(args, dev, steps: int = 100) -> dict:
+    """The optimisation workload (3M spheres on blobs, 1920x1080, C = 16,
+    K = 8): the renderer's fwd + bwd alone (C ABI, eager, HIP events), and
+    `steps` Adam steps through the autograd Renderer against a target from a
+    copy of the scene with N(0, 0.01^2) position noise (L1 loss), timed per
+    whole step (render, loss, backward, Adam) with the loss curve."""
+    import torch
+
+    from paper_2004_07484_amd import _capi
+    from paper_2004_07484_amd import scenegen as sg
+    from paper_2004_07484_amd.renderer import Renderer
+    wl = sg.config5()
+    sc, cam, par = wl.scene, wl.camera, wl.params
+    n, C = sc.payload.shape
+    H, W = cam.height, cam.width
+    log(f"[optimise] {n} spheres {W}x{H} C={C}")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    stream = torch.cuda.current_stream()
+    # renderer alone
+    pos, rad, opa, pay, bg = t(sc.pos), t(sc.radius), t(sc.opacity), t(sc.payload), t(sc.bg)
+    G = t(sg.upstream_grad(wl.seed + 1000, H, W, C))
+    cs = _capi.make_camera(cam.R, cam.t, cam.focal, cam.sensor_width, cam.znear, cam.zfar, W, H)
+    ps = _capi.make_params(par.gamma, par.eps, par.min_radius_px, par.K)
+    ws = torch.empty(_capi.pulsar_workspace_size(n, W, H, C, ps), dtype=torch.uint8, device=dev)
+    image, aux = torch.empty((H, W, C), device=dev), torch.empty((H, W), device=dev)
+    gp, gr, go = torch.empty((n, 3), device=dev), torch.empty(n, device=dev), \
+        torch.empty(n, device=dev)
+    gf, gb = torch.empty((n, C), device=dev), torch.empty(C, device=dev)
+
+    def step():
+        _capi.pulsar_fwd(pos, rad, opa, pay, bg, cs, ps, image, aux, ws, stream)
+        _capi.pulsar_bwd(pos, rad, opa, pay, bg, cs, ps, image, aux, G, gp, gr, go, gf, gb, ws,
+                         stream)
+
+    step()
+    code, pairs = _capi.pulsar_query_status(ws, stream)
+    assert code == _capi.PULSAR_OK
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    for e0, e1 in evs:
+        e0.record(stream)
+        step()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    render_ms = float(np.median([a.elapsed_time(b) for a, b in evs]))
+    del ws, gp, gr, go, gf, gb
+    # the optimisation loop
+    r = Renderer(W, H, n, n_channels=C, K=par.K)
+    noisy = (sc.pos.astype(np.float64) +
+             0.01 * np.random.default_rng(6).standard_normal(sc.pos.shape)).astype(np.float32)
+    with torch.no_grad():
+        target = r(t(noisy), pay, rad, cam, opacity=opa, gamma=par.gamma)
+    vp, vr, vo, vf = (x.clone().requires_grad_(True) for x in (pos, rad, opa, pay))
+    opt = torch.optim.Adam([{"params": [vp, vo, vf], "lr": 1e-3}, {"params": [vr], "lr": 1e-5}])
+    losses = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        opt.zero_grad(set_to_none=True)
+        img = r(vp, vf, vr, cam, opacity=vo, gamma=par.gamma)
+        loss = (img - target).abs().mean()
+        loss.backward()
+        opt.step()
+        with torch.no_grad():
+            vr.clamp_(min=1e-5)
+            vo.clamp_(0.0, 1.0)
+        losses.append(loss.detach())
+    torch.cuda.synchronize()
+    step_ms = (time.perf_counter() - t0) * 1e3 / steps
+    r.check_status(wait=True)
+    curve = torch.stack(losses).cpu().numpy()
+    log(f"[optimise] renderer {render_ms:.3f} ms, whole step {step_ms:.3f} ms, L1 "
+        f"{curve[0]:.5f} -> {curve[-1]:.5f}")
+    fb, bb = io_bytes(n, H, W, C)
+    return {"workload": wl.name, "spheres": int(n), "width": W, "height": H, "channels": int(C),
+            "K": int(par.K), "tile_pairs": int(pairs), "renderer_ms_per_step": round(render_ms, 4),
+            "renderer_io_roofline_frac": round((fb + bb) / (render_ms * 1e-3) /
+                                               (HBM_PEAK_GBS * 1e9), 4),
+            "whole_step_ms": round(step_ms, 4), "adam_steps": steps,
+            "loss_curve": {str(k): round(float(curve[k]), 6)
+                           for k in list(range(0, steps, 10)) + [steps - 1]}}
+
+
 def max_rel(got, want, floor=1e-2) -> float:
     """Largest |got - want| / max(|want|, floor max|want|) (the parity scale)."""
     got = np.asarray(got, np.float64)
@@ -271,7 +450,7 @@ def bench_batch(args, dev) -> dict:
         wss = {}
 
         def run(p):
-            key = (p.chunk, p.raster_blocks)
+            key = (p.chunk, p.raster_blocks, p.flags)
             if key not in wss:
                 wss[key] = torch.empty(_capi.pulsar_batch_workspace_size(scenes, C, p),
                                        dtype=torch.uint8, device=dev)
@@ -281,8 +460,8 @@ def bench_batch(args, dev) -> dict:
                                      gf, gb, w, stream)
 
         tuned, info = at.tune(run, ps, reps=5, warmup=2)
-        ps.chunk, ps.raster_blocks = tuned.chunk, tuned.raster_blocks
-        ws = wss[(ps.chunk, ps.raster_blocks)]
+        ps.chunk, ps.raster_blocks, ps.flags = tuned.chunk, tuned.raster_blocks, tuned.flags
+        ws = wss[(ps.chunk, ps.raster_blocks, ps.flags)]
         wss.clear()
         knobs = info["knobs"]
         log(f"[batch] tuned knobs {knobs}")
@@ -301,8 +480,11 @@ def bench_batch(args, dev) -> dict:
     bt = res.get("batched_graph_ms", res["batched_eager_ms"])
     lt = min(res.get("looped_graph_ms", np.inf), res["looped_eager_ms"])
     log(f"[batch] batched {bt:.3f} ms, looped {lt:.3f} ms per batch of {B}")
+    io = sum(sum(io_bytes(w.scene.n, w.camera.height, w.camera.width, C)) for w in wls)
     out = {"workload": "uneven32_c3_k5", "scenes": B, "spheres": int(N), "pixels": int(P),
-           "tile_pairs": int(pairs), "batched_frames_per_s": round(B / (bt * 1e-3), 1),
+           "tile_pairs": int(pairs), "io_bytes": int(io),
+           "io_roofline_frac": round(io / (bt * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+           "batched_frames_per_s": round(B / (bt * 1e-3), 1),
            "looped_frames_per_s": round(B / (lt * 1e-3), 1),
            "speedup": round(lt / bt, 3), "tuned_knobs": knobs}
     out.update({k: round(v, 4) for k, v in res.items()})
@@ -322,6 +504,10 @@ def main() -> int:
                     help="skip the batched-vs-looped measurement of 32 uneven scenes")
     ap.add_argument("--no-camera", action="store_true",
                     help="skip timing the backward that also returns camera gradients")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the latency of the 1k and 100k sphere workloads")
+    ap.add_argument("--no-optimise", action="store_true",
+                    help="skip the 3M-sphere optimisation workload")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the default launch knobs instead of autotuning them first")
     ap.add_argument("--knobs", default="", metavar="K=V,...",
@@ -397,20 +583,22 @@ def main() -> int:
     if args.knobs:
         for kv in args.knobs.split(","):
             k, v = kv.split("=")
-            if k not in ("raster_blocks", "chunk"):
+            if k not in ("raster_blocks", "chunk", "store_hits"):
                 raise SystemExit(f"unknown knob {k}")
-            setattr(ps, k, int(v))
+            from paper_2004_07484_amd import autotune as at
+            at.set_knob(ps, k, int(v))
         ws = torch.empty(_capi.pulsar_workspace_size(n, W, H, C, ps), dtype=torch.uint8,
                          device=dev)
         step()
-        tune_info = {"knobs": {k: int(getattr(ps, k)) for k in ("raster_blocks", "chunk")}}
+        from paper_2004_07484_amd import autotune as at
+        tune_info = {"knobs": at.knobs_of(ps)}
         log(f"[bench] fixed knobs {tune_info['knobs']}")
     elif not args.no_tune:
         from paper_2004_07484_amd import autotune as at
         wss = {}
 
         def run(p):
-            key = (p.chunk, p.raster_blocks)
+            key = (p.chunk, p.raster_blocks, p.flags)
             if key not in wss:
                 wss[key] = torch.empty(_capi.pulsar_workspace_size(n, W, H, C, p),
                                        dtype=torch.uint8, device=dev)
@@ -420,7 +608,7 @@ def main() -> int:
                              stream)
 
         ps, tune_info = at.tune(run, ps, reps=5, warmup=2)
-        ws = wss[(ps.chunk, ps.raster_blocks)]
+        ws = wss[(ps.chunk, ps.raster_blocks, ps.flags)]
         wss.clear()
         torch.cuda.synchronize()
         log(f"[bench] tuned knobs {tune_info['knobs']} ({tune_info['ms']:.3f} ms eager)")
@@ -552,10 +740,47 @@ def main() -> int:
                                  "bwd_paper_norm": round(bwd_norm, 4)}
         log(f"[bench] forward {fwd_plain:.3f} ms, top-K blend {fwd_topk:.3f} ms; backward with "
             f"the paper's normalisation {bwd_norm:.3f} ms")
+        # early ray termination at a 1 % share, and the stored-hits backward,
+        # each on a workspace of its own
+        for name, pv in (("early_stop_1pct",
+                          _capi.make_params(par.gamma, par.eps, par.min_radius_px, par.K,
+                                            ps.max_pairs, 0, 0, ps.raster_blocks, 0, 0.01)),
+                         ("store_hits",
+                          _capi.make_params(par.gamma, par.eps, par.min_radius_px, par.K,
+                                            ps.max_pairs, 0, ps.chunk, ps.raster_blocks,
+                                            _capi.PULSAR_STORE_HITS))):
+            wv = torch.empty(_capi.pulsar_workspace_size(n, W, H, C, pv), dtype=torch.uint8,
+                             device=dev)
+            fv = lambda pv=pv, wv=wv: _capi.pulsar_fwd(pos, rad, opa, pay, bg, cs, pv, image,
+                                                       aux, wv, stream)
+            t_f = timed(fv)
+            t_b = timed(lambda pv=pv, wv=wv: _capi.pulsar_bwd(pos, rad, opa, pay, bg, cs, pv,
+                                                              image, aux, G, gp, gr, go, gf, gb,
+                                                              wv, stream), fv)
+            code, _ = _capi.pulsar_query_status(wv, stream)
+            assert code == _capi.PULSAR_OK, name
+            camera["variants_ms"][f"fwd_{name}"] = round(t_f, 4)
+            camera["variants_ms"][f"bwd_{name}"] = round(t_b, 4)
+            log(f"[bench] {name}: forward {t_f:.3f} ms, backward {t_b:.3f} ms")
+            del wv
 
     batch = None
     if not args.no_batch:
         batch = bench_batch(args, dev)
+
+    small = None
+    if not args.no_small:
+        small = {}
+        for make in (sg.config1, sg.config2):
+            w = make()
+            log(f"[small] {w.name}")
+            small[w.name] = bench_small(args, dev, w)
+            log(f"[small] {w.name}: graph {small[w.name]['graph_us']} us, eager "
+                f"{small[w.name]['eager_us']} us per fwd+bwd")
+
+    optimise = None
+    if not args.no_optimise:
+        optimise = bench_optimise(args, dev)
 
     cpu = None
     parity = None
@@ -563,6 +788,8 @@ def main() -> int:
         log(f"[bench] CPU oracle baseline on {args.cpu_rows} rows")
         cpu, orc = cpu_baseline(wl, G_np, args.cpu_rows)
         log(f"[bench] oracle {cpu['value']} ms/frame on {cpu['cores']} threads")
+        cpu["one_thread"] = cpu_one_thread(wl)
+        log(f"[bench] oracle on one thread {cpu['one_thread']['value']} ms/frame")
         # parity of the timed configuration: one more fwd + bwd with the same
         # launch knobs and workspace, G restricted to the oracle's rows
         Gd = t(orc["G"].astype(np.float32))
@@ -584,7 +811,7 @@ def main() -> int:
                   "masked_pixels": int(orc["fwd"]["ambiguous"][rows].sum()),
                   "max_rel_image": rel_img, "max_rel_grad": max(rel_grad.values()),
                   "max_rel_grad_by_tensor": rel_grad, "tolerance": {"image": 1e-4, "grad": 1e-3},
-                  "knobs": {k: int(getattr(ps, k)) for k in ("raster_blocks", "chunk")}}
+                  "knobs": at_knobs(ps)}
         parity["pass"] = bool(rel_img <= 1e-4 and parity["max_rel_grad"] <= 1e-3)
         log(f"[bench] parity on {len(rows)} oracle rows: image {rel_img:.2e}, gradients "
             f"{parity['max_rel_grad']:.2e} ({'pass' if parity['pass'] else 'FAIL'})")
@@ -619,6 +846,8 @@ def main() -> int:
         "tuned_knobs": None if tune_info is None else tune_info["knobs"],
         "camera_gradients_and_variants": camera,
         "batched": batch,
+        "small_workloads": small,
+        "optimisation": optimise,
         "cpu_baseline": cpu,
         "parity": parity,
         "paper_context": "RTX 2080, 1M spheres at 1000^2: fwd 19 ms, bwd 4.7 ms (CUDA only)",

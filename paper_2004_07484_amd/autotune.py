@@ -7,6 +7,10 @@ computed are measured on the device instead:
   raster_blocks  size of the persistent raster grid (never changes the image)
   chunk          sphere records per raster work item (changes only the
                  summation order of the blend)
+  store_hits     keep each pixel's K nearest hits for the backward
+                 (PULSAR_STORE_HITS, the paper's choice) or recompute them
+                 from the tile lists (changes only the summation order of
+                 the gradients)
 
 The 8x8 tile is not a knob: one wave64 owns one tile, lane = pixel, which the
 kernels rely on for their LDS layouts and ballots.
@@ -32,7 +36,24 @@ from . import _capi
 KNOBS: Tuple[Tuple[str, Tuple[int, ...]], ...] = (
     ("raster_blocks", (1024, 2048, 4096, 8192, 16384)),
     ("chunk", (64, 128, 256, 512)),
+    ("store_hits", (0, 1)),
 )
+# knobs that are bits of params.flags rather than fields of their own
+FLAG_KNOBS = {"store_hits": _capi.PULSAR_STORE_HITS}
+
+
+def get_knob(params, name: str) -> int:
+    if name in FLAG_KNOBS:
+        return int(bool(int(params.flags) & FLAG_KNOBS[name]))
+    return int(getattr(params, name))
+
+
+def set_knob(params, name: str, value: int) -> None:
+    if name in FLAG_KNOBS:
+        bit = FLAG_KNOBS[name]
+        params.flags = (int(params.flags) | bit) if int(value) else (int(params.flags) & ~bit)
+    else:
+        setattr(params, name, int(value))
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "pulsar_amd_autotune.json")
 
@@ -47,7 +68,7 @@ def cache_key(arch: str, n: int, pixels: int, C: int, K: int, B: int = 1) -> str
 
 
 def knobs_of(params) -> Dict[str, int]:
-    return {name: int(getattr(params, name)) for name, _ in KNOBS}
+    return {name: get_knob(params, name) for name, _ in KNOBS}
 
 
 def with_knobs(params, knobs: Dict[str, int]):
@@ -55,7 +76,7 @@ def with_knobs(params, knobs: Dict[str, int]):
     p = _capi.pulsar_params_t()
     ctypes_copy(p, params)
     for k, v in knobs.items():
-        setattr(p, k, int(v))
+        set_knob(p, k, v)
     return p
 
 
