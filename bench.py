@@ -41,10 +41,15 @@ def io_bytes(n: int, H: int, W: int, C: int):
 COMMON_SOURCES = ["paper_2004_07484_amd/csrc/hit_geometry.h",
                   "paper_2004_07484_amd/csrc/device_common.h",
                   "paper_2004_07484_amd/csrc/pulsar_internal.h"]
+_BIN = ["paper_2004_07484_amd/csrc/binning.hip"] + COMMON_SOURCES
 TRAFFIC_SOURCES = {
-    "k_bwd_items": ["paper_2004_07484_amd/csrc/raster_bwd.hip"] + COMMON_SOURCES,
-    "k_fwd_chunks": ["paper_2004_07484_amd/csrc/raster_fwd.hip"] + COMMON_SOURCES,
     "k_project": ["paper_2004_07484_amd/csrc/project.hip"] + COMMON_SOURCES,
+    "k_emit": _BIN, "k_sort_hist": _BIN, "k_sort_scatter": _BIN, "k_ranges": _BIN,
+    "k_plan": _BIN,
+    "k_fwd_chunks": ["paper_2004_07484_amd/csrc/raster_fwd.hip"] + COMMON_SOURCES,
+    "k_fwd_merge": ["paper_2004_07484_amd/csrc/raster_fwd.hip"] + COMMON_SOURCES,
+    "k_bwd_items": ["paper_2004_07484_amd/csrc/raster_bwd.hip"] + COMMON_SOURCES,
+    "k_finalize": ["paper_2004_07484_amd/csrc/raster_bwd.hip"] + COMMON_SOURCES,
 }
 
 
@@ -58,7 +63,7 @@ def measured_traffic(kernel: str, workload: str):
     """HBM bytes per dispatch from the committed rocprofv3 summary (FETCH_SIZE
     and WRITE_SIZE scaled by the copy calibration), or None when the summary
     is missing or the kernel's sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
+    path = os.path.join(ROOT, "profiles", f"{workload}.md")
     if kernel not in TRAFFIC_SOURCES or not os.path.exists(path):
         return None
     rec = None

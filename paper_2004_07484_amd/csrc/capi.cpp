@@ -200,7 +200,13 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   q.off_starts = take(size_t(kStartArrays) * size_t(q.B + 1) * 4);
   q.off_counts = take(nn * 4);
   q.off_trect = take(nn * 8);
-  q.off_rec = take(nn * 64);
+  // records: 64 bytes of geometry. (Copying payload rows of up to
+  // kRecPayload channels behind them, so that a raster gather touches one
+  // 128-byte line, halved the raster kernels' fetched bytes but cost the
+  // projection more time than the latency-bound raster kernels saved;
+  // rec4 = 8 selects that layout.)
+  q.rec4 = 4;
+  q.off_rec = take(nn * size_t(q.rec4) * 16);
   q.off_partials = take(size_t(q.nblk_proj + 1) * 8);
   q.off_boff = take(size_t(q.nblk_proj + 1) * 8);
   q.off_ebase = take(size_t(q.nblk_emit + 1) * 8);

@@ -15,6 +15,8 @@
 //           the last pixel of its rectangle; first is the sum of the tile
 //           counts of the spheres before it in its projection block, so its
 //           first tile pair sits at (block offset + first) in emission order
+//     [4-7] for payloads of at most 16 channels: the payload row, so that the
+//           raster kernels' gather of a pair reads one 128-byte line
 // and the per-block sum of counts for the tile-pair scan. High + low FP32
 // parts carry the FP64 values to about 48 bits for the exact hit test.
 #include <cstring>
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
     SceneDev* __restrict__ tab_out, uint32_t* __restrict__ starts_out, float min_radius_px,
     uint32_t* __restrict__ counts, ushort4* __restrict__ trect, float4* __restrict__ rec,
     unsigned long long* __restrict__ partials, float* __restrict__ tmin_out,
-    Status* __restrict__ status) {
+    Status* __restrict__ status, const float* __restrict__ payload, int C, int rec4) {
   // no FMA contraction: the camera transform, the minimum size and the
   // earliest hit distance are the IEEE double evaluations of the same
   // expressions, term by term (early termination orders spheres by the
@@ -163,6 +165,27 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
   }
   uint32_t count = 0;
   float4 r0, r1, r2, r3;
+  // the payload row that goes into the record is requested first, so its
+  // latency overlaps the projection below (16-byte rows: float4 loads)
+  float4 pv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) pv[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (rec4 == 8 && i < n) {
+    const float* f = payload + size_t(i) * size_t(C);
+    if ((C & 3) == 0 && (reinterpret_cast<uintptr_t>(payload) & 15u) == 0u) {
+      const float4* f4 = reinterpret_cast<const float4*>(f);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (4 * q < C) pv[q] = f4[q];
+    } else {
+      float v[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) v[c] = c < C ? f[c] : 0.f;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        pv[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+    }
+  }
   if (i < n) {
     int b = 0;
     if (inline_scenes) {
@@ -267,11 +290,16 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
     // a prefix beyond 32 bits only belongs to pairs past any capacity
     const unsigned long long first = before + incl - count;
     r3.w = __uint_as_float(first < 0xffffffffull ? uint32_t(first) : 0xffffffffu);
-    float4* r4 = rec + 4 * size_t(i);
+    float4* r4 = rec + size_t(rec4) * size_t(i);
     r4[0] = r0;
     r4[1] = r1;
     r4[2] = r2;
     r4[3] = r3;
+    if (rec4 == 8) {
+      // the payload row after the geometry (unused channels zero)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) r4[4 + q] = pv[q];
+    }
   }
   if (threadIdx.x == 0) partials[blockIdx.x] = total;
 }
@@ -297,7 +325,7 @@ void launch_project(const Plan& q, const std::vector<SceneDev>& sc, const FwdArg
                      ws_ptr<float4>(ws, q.off_rec),
                      ws_ptr<unsigned long long>(ws, q.off_partials),
                      q.estop ? ws_ptr<float>(ws, q.off_tmin) : nullptr,
-                     ws_ptr<Status>(ws, q.off_status));
+                     ws_ptr<Status>(ws, q.off_status), a.payload, a.C, q.rec4);
 }
 
 }  // namespace pulsar

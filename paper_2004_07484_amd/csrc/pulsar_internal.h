@@ -32,6 +32,7 @@ constexpr int kRasterGridDefault = 4096;     // persistent raster grid (one wave
 constexpr int kUploadScenes = 12;            // scene descriptors per upload launch
 constexpr int kBgBlockPixels = 1024;         // pixels per background-gradient block
 constexpr int kCamSpan = 1024;               // spheres per camera-gradient partial sum
+constexpr int kRecPayload = 16;              // payload channels kept in the sphere record
 constexpr uint32_t kFirstChunk = 0x80000000u;  // work item flag: first chunk of its tile
 constexpr uint32_t kNoSlot = 0xffffffffu;      // work item writes final pixels, no partial state
 
@@ -123,6 +124,7 @@ struct Plan {
   // binning: LSD passes over the tile number and the digit width of each;
   // emission blocks of emit_rounds rounds of kEmitRound spheres
   int sort_passes, sort_digit, emit_rounds, nblk_emit;
+  int rec4;           // float4 per sphere record: 4 (geometry) or 8 (with the payload row)
   int estop;          // early termination: tiles are sorted by earliest hit distance
   int K, store_hits;  // stored per-pixel K nearest hits (PULSAR_STORE_HITS)
   size_t off_hits;    // [npix][K] (t, sphere index), last in the workspace

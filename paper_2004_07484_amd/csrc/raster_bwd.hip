@@ -30,7 +30,8 @@ struct BwdKernelArgs {
   Status* status;
   const uint4* desc;
   uint32_t max_items;  // capacity of the work list (short items fill it from the back)
-  const float4* rec;                // sphere records, 4 float4 per sphere
+  const float4* rec;                // sphere records, rec4 float4 per sphere
+  int rec4;                         // 8: the payload row follows the geometry
   const float* payload;             // the caller's payload rows [n, C]
   const unsigned long long* boff;   // first pair of each projection block
   const float* image;
@@ -163,14 +164,16 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
     for (int c = 0; c < CM; ++c) f[c] = 0.f;
     auto load_record = [&](uint32_t jj) {
       sph = min(A.svals[jj], A.last_sph);
-      const float4* rp = A.rec + 4 * size_t(sph);
+      const float4* rp = A.rec + size_t(A.rec4) * size_t(sph);
       ra = rp[0];
       rb = rp[1];
       rc = rp[2];
       rd = rp[3];
       if (ES) tmin = A.tmin[sph];
       bo = uint32_t(A.boff[sph / kProjectBlock]);
-      const float* fp = A.payload + size_t(sph) * size_t(C);
+      // the payload row: in the record's second half when it fits there
+      const float* fp = A.rec4 == 8 ? reinterpret_cast<const float*>(rp + 4)
+                                    : A.payload + size_t(sph) * size_t(C);
       // unconditional loads (clamped to the row), so they issue together
 #pragma unroll
       for (int c = 0; c < CM; ++c) f[c] = fp[min(c, C - 1)];
@@ -324,7 +327,7 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A,
       const uint32_t j = b0 + uint32_t(lane);
       if (j >= end) continue;
       const uint32_t id = min(A.svals[j], A.last_sph);  // sphere index
-      const float4* rp = A.rec + 4 * size_t(id);
+      const float4* rp = A.rec + size_t(A.rec4) * size_t(id);
       const float4 a = rp[0], d = rp[3];
       const SphereRec s = unpack_rec(a, rp[1], rp[2], d);
       // the pair's slot
@@ -414,8 +417,7 @@ __global__ void k_bwd_prep(int n, const uint32_t* __restrict__ counts, int C,
 constexpr int kFinThreads = 256;
 template <int CM>
 __global__ __launch_bounds__(kFinThreads) void k_finalize(
-    int n, const uint32_t* __restrict__ counts, const float4* __restrict__ rec,
-    const unsigned long long* __restrict__ boff, const Status* __restrict__ status, const float* __restrict__ pos,
+    int n, const uint32_t* __restrict__ counts, const unsigned long long* __restrict__ boff, const Status* __restrict__ status, const float* __restrict__ pos,
     const float* __restrict__ radius, SceneTable tab, float min_radius_px, int C,
     const float4* __restrict__ pslot, int ps4, float* __restrict__ grad_pos,
     float* __restrict__ grad_radius, float* __restrict__ grad_opacity,
@@ -447,11 +449,19 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
   const int nloc = min(kFinThreads, n - i0);
   const int i = i0 + t;
   // the first slot: the projection block's first emission position plus the
-  // in-block prefix in record word 3.w (a sphere without tiles has no record)
+  // tile counts of the block's spheres before this one (the in-block prefix
+  // the projection computed; a block here is a projection block)
+  static_assert(kFinThreads == kProjectBlock, "one finalize block per projection block");
   const uint32_t count = t < nloc ? counts[i] : 0u;
-  const uint32_t base =
-      count != 0u ? uint32_t(boff[i / kProjectBlock]) + __float_as_uint(rec[4 * size_t(i) + 3].w)
-                  : 0u;
+  __shared__ uint32_t s_wpre[kFinThreads / kWave];
+  const int lane = t & (kWave - 1), wv = t / kWave;
+  const uint32_t incl = wave_incl_scan_u32(count, lane);
+  if (lane == kWave - 1) s_wpre[wv] = incl;
+  __syncthreads();
+  uint32_t first = incl - count;
+#pragma unroll
+  for (int w = 0; w < kFinThreads / kWave; ++w) first += w < wv ? s_wpre[w] : 0u;
+  const uint32_t base = count != 0u ? uint32_t(boff[blockIdx.x]) + first : 0u;
   s_cnt[t] = count;
   float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
   float go = 0.f, gk = 0.f, npx = 0.f;
@@ -791,7 +801,7 @@ __global__ __launch_bounds__(kWave) void k_bwd_hits(BwdKernelArgs A,
       const uint2 e = hp[j];
       if (e.y == 0xffffffffu) break;  // fewer than K hits
       const uint32_t sph = min(e.y, A.last_sph);
-      const float4* rp = A.rec + 4 * size_t(sph);
+      const float4* rp = A.rec + size_t(A.rec4) * size_t(sph);
       const float4 ra = rp[0], rd = rp[3];
       const SphereRec s = unpack_rec(ra, rp[1], rp[2], rd);
       Hit h;
@@ -866,8 +876,7 @@ template <int CM>
 static void launch_finalize(const Plan& q, const BwdArgs& a, char* ws, hipStream_t stream,
                             uint32_t nfin, uint32_t nred) {
   hipLaunchKernelGGL((k_finalize<CM>), dim3(nfin + nred), dim3(kFinThreads), 0, stream, int(q.n),
-                     ws_ptr<uint32_t>(ws, q.off_counts), ws_ptr<float4>(ws, q.off_rec),
-                     ws_ptr<unsigned long long>(ws, q.off_boff), ws_ptr<Status>(ws, q.off_status), a.pos, a.radius, scene_table(q, ws),
+                     ws_ptr<uint32_t>(ws, q.off_counts), ws_ptr<unsigned long long>(ws, q.off_boff), ws_ptr<Status>(ws, q.off_status), a.pos, a.radius, scene_table(q, ws),
                      a.min_radius_px, a.C, ws_ptr<float4>(ws, q.off_pslot), q.bwd_ps4, a.grad_pos,
                      a.grad_radius, a.grad_opacity, a.grad_payload, nfin,
                      ws_ptr<float>(ws, q.off_bgsum), a.grad_bg,
@@ -979,6 +988,7 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
   A.desc = ws_ptr<uint4>(ws, q.off_desc);
   A.max_items = uint32_t(q.max_chunks);
   A.rec = ws_ptr<float4>(ws, q.off_rec);
+  A.rec4 = q.rec4;
   A.payload = a.payload;
   A.boff = ws_ptr<unsigned long long>(ws, q.off_boff);
   A.image = a.image;

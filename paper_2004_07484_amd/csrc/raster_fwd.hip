@@ -104,7 +104,8 @@ struct FwdKernelArgs {
   const uint32_t* mlist;
   const uint32_t* svals;            // sphere index of every sorted pair
   uint32_t last_sph;                 // n - 1: sorted indices are clamped to it
-  const float4* rec;                 // sphere records, 4 float4 per sphere
+  const float4* rec;                 // sphere records, rec4 float4 per sphere
+  int rec4;                          // 8: the payload row follows the geometry
   const float* payload;              // the caller's payload rows [n, C]
   const float* bg;      // [B, C]
   float* image;
@@ -294,10 +295,12 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM, ES)) void k_fwd_c
       if (b0 + kWave < end)
         sph_next = min(A.svals[min(j + uint32_t(kWave), end - 1u)], A.last_sph);
       __syncthreads();  // previous batch done with s_rec / s_pay / s_mask
-      const float4* rp = A.rec + 4 * size_t(sph);
+      const float4* rp = A.rec + size_t(A.rec4) * size_t(sph);
 #pragma unroll
       for (int q = 0; q < 4; ++q) __builtin_amdgcn_global_load_lds(rp + q, &s_rec[q][0], 16, 0, 0);
-      const float* fp = A.payload + size_t(sph) * size_t(A.C) + A.c0;
+      // the payload row: in the record's second half when it fits there
+      const float* fp = A.rec4 == 8 ? reinterpret_cast<const float*>(rp + 4) + A.c0
+                                    : A.payload + size_t(sph) * size_t(A.C) + A.c0;
 #pragma unroll
       for (int c = 0; c < CM; ++c)
         if (c < A.cn) __builtin_amdgcn_global_load_lds(fp + c, &s_pay[c][0], 4, 0, 0);
@@ -588,6 +591,7 @@ static FwdKernelArgs raster_args(const Plan& q, const std::vector<SceneDev>& sce
   A.svals = ws_ptr<uint32_t>(ws, q.off_vals);
   A.last_sph = q.n > 0 ? uint32_t(q.n - 1) : 0u;
   A.rec = ws_ptr<float4>(ws, q.off_rec);
+  A.rec4 = q.rec4;
   A.payload = a.payload;
   A.bg = a.bg;
   A.image = a.image;
