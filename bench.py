@@ -49,6 +49,7 @@ TRAFFIC_SOURCES = {
     "k_fwd_chunks": ["paper_2004_07484_amd/csrc/raster_fwd.hip"] + COMMON_SOURCES,
     "k_fwd_merge": ["paper_2004_07484_amd/csrc/raster_fwd.hip"] + COMMON_SOURCES,
     "k_bwd_items": ["paper_2004_07484_amd/csrc/raster_bwd.hip"] + COMMON_SOURCES,
+    "k_bwd_spheres": ["paper_2004_07484_amd/csrc/raster_bwd.hip"] + COMMON_SOURCES,
     "k_finalize": ["paper_2004_07484_amd/csrc/raster_bwd.hip"] + COMMON_SOURCES,
 }
 
@@ -300,12 +301,17 @@ def max_rel(got, want, floor=1e-2) -> float:
     return float((np.abs(got - want) / np.maximum(scale, 1e-300)).max())
 
 
-STAGE_KERNELS = {"project": "k_project", "binning": "binning (several kernels)",
-                 "raster_fwd": "k_fwd_chunks", "merge": "k_fwd_merge",
-                 "raster_bwd": "k_bwd_items", "finalize": "k_finalize"}
+def stage_kernels(by_sphere: bool = True) -> dict:
+    """The kernel that does each stage's work (the backward in sphere order
+    writes the sphere gradients itself; the tile-order one leaves them to
+    k_finalize)."""
+    return {"project": "k_project", "binning": "binning (several kernels)",
+            "raster_fwd": "k_fwd_chunks", "merge": "k_fwd_merge",
+            "raster_bwd": "k_bwd_spheres" if by_sphere else "k_bwd_items",
+            "finalize": "k_finalize"}
 
 
-def stage_bytes(n: int, H: int, W: int, C: int, pairs: int) -> dict:
+def stage_bytes(n: int, H: int, W: int, C: int, pairs: int, by_sphere: bool = True) -> dict:
     """Algorithmic bytes each stage must move whatever the implementation:
     the compulsory I/O of the frame that falls to it, and for binning the tile
     lists it must produce.
@@ -315,25 +321,29 @@ def stage_bytes(n: int, H: int, W: int, C: int, pairs: int) -> dict:
       raster_fwd  read the payload rows, write F and L: n 4C + HW (4C + 4)
                   (split tiles' pixels are written by the merge, counted here)
       merge       none beyond the forward's (intermediate partial blends)
-      raster_bwd  read G, F and L and the payload rows: HW (8C + 4) + n 4C
-      finalize    write every sphere gradient: n 4 (C + 5), and the background
-                  gradient 4C"""
+      raster_bwd  read G, F and L and the payload rows: HW (8C + 4) + n 4C;
+                  in sphere order it also writes every sphere gradient,
+                  n 4 (C + 5)
+      finalize    the background gradient 4C, and in tile order every sphere
+                  gradient n 4 (C + 5)"""
     T = ((W + 7) // 8) * ((H + 7) // 8)
+    grads = 4 * (C + 5) * n
     return {"project": 20 * n, "binning": 4 * pairs + 4 * (T + 1),
             "raster_fwd": 4 * C * n + H * W * (4 * C + 4), "merge": 0,
-            "raster_bwd": H * W * (8 * C + 4) + 4 * C * n,
-            "finalize": 4 * (C + 5) * n + 4 * C}
+            "raster_bwd": H * W * (8 * C + 4) + 4 * C * n + (grads if by_sphere else 0),
+            "finalize": 4 * C + (0 if by_sphere else grads)}
 
 
-def stage_roofline(stage_avg: dict, n, H, W, C, pairs, workload):
+def stage_roofline(stage_avg: dict, n, H, W, C, pairs, workload, by_sphere: bool = True):
     """roofline object for the stage that takes longest (its algorithmic bytes
     over its average duration against the HBM peak), and the same figures
     for every stage."""
-    sb = stage_bytes(n, H, W, C, pairs)
+    sb = stage_bytes(n, H, W, C, pairs, by_sphere)
+    names = stage_kernels(by_sphere)
     kernels = {}
     for st, nbytes in sb.items():
         ms = stage_avg.get(st, 0.0)
-        kernels[st] = {"kernel": STAGE_KERNELS[st], "avg_ms": round(ms, 4),
+        kernels[st] = {"kernel": names[st], "avg_ms": round(ms, 4),
                        "bytes_per_launch": nbytes,
                        "achieved_GBs": round(nbytes / (ms * 1e-3) / 1e9, 1) if ms > 0 else None,
                        "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
@@ -341,7 +351,7 @@ def stage_roofline(stage_avg: dict, n, H, W, C, pairs, workload):
     dom = max(sb, key=lambda k: stage_avg.get(k, 0.0))
     ms = stage_avg[dom]
     achieved = sb[dom] / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
-    kname = STAGE_KERNELS[dom]
+    kname = names[dom]
     roofline = {"kernel": kname, "stage": dom, "bound": "hbm", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(kname, workload), "avg_ms": round(ms, 4),
@@ -588,7 +598,7 @@ def main() -> int:
     if args.knobs:
         for kv in args.knobs.split(","):
             k, v = kv.split("=")
-            if k not in ("raster_blocks", "chunk", "store_hits"):
+            if k not in ("raster_blocks", "chunk", "store_hits", "bwd_tiles"):
                 raise SystemExit(f"unknown knob {k}")
             from paper_2004_07484_amd import autotune as at
             at.set_knob(ps, k, int(v))
@@ -674,7 +684,8 @@ def main() -> int:
 
     fwd_b, bwd_b = io_bytes(n, H, W, C)
     stage_avg = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
-    roofline, kernels = stage_roofline(stage_avg, n, H, W, C, int(pairs), wl.name)
+    by_sphere = not (int(ps.flags) & (_capi.PULSAR_BWD_TILES | _capi.PULSAR_STORE_HITS))
+    roofline, kernels = stage_roofline(stage_avg, n, H, W, C, int(pairs), wl.name, by_sphere)
     io_frac = (fwd_b + bwd_b) / (step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9)
 
     # the backward with camera gradients against the plain one, each timed
@@ -745,15 +756,19 @@ def main() -> int:
                                  "bwd_paper_norm": round(bwd_norm, 4)}
         log(f"[bench] forward {fwd_plain:.3f} ms, top-K blend {fwd_topk:.3f} ms; backward with "
             f"the paper's normalisation {bwd_norm:.3f} ms")
-        # early ray termination at a 1 % share, and the stored-hits backward,
-        # each on a workspace of its own
+        # early ray termination at a 1 % share, the stored-hits backward and
+        # the backward in tile order, each on a workspace of its own
         for name, pv in (("early_stop_1pct",
                           _capi.make_params(par.gamma, par.eps, par.min_radius_px, par.K,
                                             ps.max_pairs, 0, 0, ps.raster_blocks, 0, 0.01)),
                          ("store_hits",
                           _capi.make_params(par.gamma, par.eps, par.min_radius_px, par.K,
                                             ps.max_pairs, 0, ps.chunk, ps.raster_blocks,
-                                            _capi.PULSAR_STORE_HITS))):
+                                            _capi.PULSAR_STORE_HITS)),
+                         ("bwd_tiles",
+                          _capi.make_params(par.gamma, par.eps, par.min_radius_px, par.K,
+                                            ps.max_pairs, 0, ps.chunk, ps.raster_blocks,
+                                            _capi.PULSAR_BWD_TILES))):
             wv = torch.empty(_capi.pulsar_workspace_size(n, W, H, C, pv), dtype=torch.uint8,
                              device=dev)
             fv = lambda pv=pv, wv=wv: _capi.pulsar_fwd(pos, rad, opa, pay, bg, cs, pv, image,

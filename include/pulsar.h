@@ -122,13 +122,24 @@ typedef struct pulsar_camera {
  *   backward must both set it (with PULSAR_REBIN the backward stores them
  *   itself); a backward on a workspace whose forward stored no hits writes
  *   zero gradients and pulsar_query_status reports
- *   PULSAR_ERR_INVALID_ARGUMENT. */
+ *   PULSAR_ERR_INVALID_ARGUMENT.
+ * PULSAR_BWD_TILES: the backward walks the forward's tile lists (a block per
+ *   work item, one thread per (tile, sphere) pair, each pair's sums in a slot
+ *   of its own, then a pass per sphere over its slots) instead of the
+ *   default walk in sphere order (a thread per sphere whose pixels are
+ *   shared out over the lanes of its wave, which needs no slots and no
+ *   second pass). Both compute the same terms and differ only in summation
+ *   order; the tile walk suits scenes whose spheres cover very many pixels
+ *   each. Forward and backward must both set it (the workspace holds the
+ *   slots only then). The stored-hits backward and payloads of more than 32
+ *   channels always use slots. */
 #define PULSAR_NO_BWD_AUX 0x1u
 #define PULSAR_REBIN 0x2u
 #define PULSAR_GRAD_PAPER_NORM 0x4u
 #define PULSAR_BLEND_TOPK 0x8u
 #define PULSAR_ORTHO 0x10u
 #define PULSAR_STORE_HITS 0x20u
+#define PULSAR_BWD_TILES 0x40u
 
 /* min_radius_px preset for the paper's rule that every sphere is drawn at
  * least one pixel large, so none falls between the pixel rays (App. B,
@@ -146,7 +157,8 @@ typedef struct pulsar_params {
   int32_t K;            /* nearest hits per pixel that receive gradients, 1..32 */
   uint32_t flags;       /* OR of PULSAR_NO_BWD_AUX, PULSAR_REBIN,
                            PULSAR_GRAD_PAPER_NORM, PULSAR_BLEND_TOPK,
-                           PULSAR_ORTHO and PULSAR_STORE_HITS; any other bit
+                           PULSAR_ORTHO, PULSAR_STORE_HITS and
+                           PULSAR_BWD_TILES; any other bit
                            is reserved (PULSAR_ERR_UNSUPPORTED) */
   int32_t max_pairs;    /* capacity of (screen tile, sphere) pairs; 0 = default
                            (2 n + number of tiles + 65536) */

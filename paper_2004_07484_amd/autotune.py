@@ -9,8 +9,10 @@ computed are measured on the device instead:
                  summation order of the blend)
   store_hits     keep each pixel's K nearest hits for the backward
                  (PULSAR_STORE_HITS, the paper's choice) or recompute them
-                 from the tile lists (changes only the summation order of
-                 the gradients)
+                 (changes only the summation order of the gradients)
+  bwd_tiles      recompute them walking the tile lists (PULSAR_BWD_TILES)
+                 or walking the spheres (the default; changes only the
+                 summation order of the gradients)
 
 The 8x8 tile is not a knob: one wave64 owns one tile, lane = pixel, which the
 kernels rely on for their LDS layouts and ballots.
@@ -37,9 +39,10 @@ KNOBS: Tuple[Tuple[str, Tuple[int, ...]], ...] = (
     ("raster_blocks", (1024, 2048, 4096, 8192, 16384)),
     ("chunk", (64, 128, 256, 512)),
     ("store_hits", (0, 1)),
+    ("bwd_tiles", (0, 1)),
 )
 # knobs that are bits of params.flags rather than fields of their own
-FLAG_KNOBS = {"store_hits": _capi.PULSAR_STORE_HITS}
+FLAG_KNOBS = {"store_hits": _capi.PULSAR_STORE_HITS, "bwd_tiles": _capi.PULSAR_BWD_TILES}
 
 
 def get_knob(params, name: str) -> int:

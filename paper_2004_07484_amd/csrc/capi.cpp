@@ -57,7 +57,8 @@ int check_params(const pulsar_params_t* p) {
   if (p->raster_blocks != 0 && (p->raster_blocks < 256 || p->raster_blocks > 65536))
     return PULSAR_ERR_INVALID_ARGUMENT;
   if ((p->flags & ~(PULSAR_NO_BWD_AUX | PULSAR_REBIN | PULSAR_GRAD_PAPER_NORM |
-                    PULSAR_BLEND_TOPK | PULSAR_ORTHO | PULSAR_STORE_HITS)) != 0u)
+                    PULSAR_BLEND_TOPK | PULSAR_ORTHO | PULSAR_STORE_HITS |
+                    PULSAR_BWD_TILES)) != 0u)
     return PULSAR_ERR_UNSUPPORTED;
   if (!std::isfinite(p->stop_share) || p->stop_share < 0.f || p->stop_share >= 1.f)
     return PULSAR_ERR_INVALID_ARGUMENT;
@@ -245,10 +246,17 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   int bcm = 1;
   while (bcm < C && bcm < kBwdChannels) bcm *= 2;
   q.bwd_ps4 = C <= kBwdChannels ? 1 + (bcm + 6) / 4 : 2;
-  q.off_pslot = take(bwd ? size_t(cap) * size_t(q.bwd_ps4) * 16 : 0);
   q.ncampart = int64_t(q.B) + n / kCamSpan + 1;
   q.off_camg = take(bwd ? nn * 16 : 0);
   q.off_campart = take(bwd ? size_t(q.ncampart) * 16 * 8 : 0);
+  // per-pair slots: only the backward passes that gather through them (the
+  // tile walk, the stored hits, wide payloads) need them. They come after
+  // everything the forward writes, so a forward planned without them leaves
+  // the same state for a backward that has them (given the larger workspace).
+  q.bwd_tiles = (p->flags & PULSAR_BWD_TILES) != 0u ? 1 : 0;
+  const bool slots = bwd && (q.bwd_tiles || (p->flags & PULSAR_STORE_HITS) != 0u ||
+                             C > kBwdChannels);
+  q.off_pslot = take(slots ? size_t(cap) * size_t(q.bwd_ps4) * 16 : 0);
   // the stored per-pixel K nearest hits come last, so every other offset is
   // the same with or without them
   q.K = p->K;

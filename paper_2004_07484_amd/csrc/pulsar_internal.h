@@ -127,6 +127,7 @@ struct Plan {
   int rec4;           // float4 per sphere record: 4 (geometry) or 8 (with the payload row)
   int estop;          // early termination: tiles are sorted by earliest hit distance
   int K, store_hits;  // stored per-pixel K nearest hits (PULSAR_STORE_HITS)
+  int bwd_tiles;      // the backward walks the tile lists (PULSAR_BWD_TILES)
   size_t off_hits;    // [npix][K] (t, sphere index), last in the workspace
   size_t off_tmin;    // [n] float32 earliest possible hit distance (early termination)
   size_t off_stop;    // [npix] (distance, pair position) of the first skipped hit

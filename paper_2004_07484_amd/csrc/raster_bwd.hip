@@ -405,107 +405,27 @@ __global__ void k_bwd_prep(int n, const uint32_t* __restrict__ counts, int C,
   for (int c = 0; c < C; ++c) grad_payload[size_t(i) * size_t(C) + c] = 0.f;
 }
 
-// K8: per sphere, in sphere order, kFinThreads spheres per block. The
-// camera-space sums are the sum of the sphere's pair slots sfirst ..
-// sfirst + count - 1 (in that order; none when it touches no tile). Position
-// and radius gradients follow c = R p + t and the min-size clamp; opacity and
-// payload gradients are copied out (CM > 0; with CM = 0, the wide path, the
-// payload gradient was added in place). Rows wider than one float (positions,
-// payloads) are staged per block and written as one contiguous run, so every
-// store instruction covers consecutive addresses. Blocks past the spheres sum
-// the background block sums, one block per (scene, channel).
+// The outputs of a block's spheres i0 .. i0 + nloc - 1 from their
+// camera-space sums, thread t holding sphere i0 + t (count: the tiles it
+// touches, 0 when it is not visible; npx: the pixels it received gradients
+// from). Position and radius gradients follow c = R p + t and the min-size
+// clamp; opacity and payload gradients are copied out (CM > 0; with CM = 0,
+// the wide path, the payload gradient was added in place). Rows wider than
+// one float (positions, payloads) are staged in s_gp [3 kFinThreads] and
+// s_pay [kFinThreads CS] and written as one contiguous run, so every store
+// instruction covers consecutive addresses. Every thread of the block calls
+// it (it holds a barrier).
 constexpr int kFinThreads = 256;
 template <int CM>
-__global__ __launch_bounds__(kFinThreads) void k_finalize(
-    int n, const uint32_t* __restrict__ counts, const unsigned long long* __restrict__ boff, const Status* __restrict__ status, const float* __restrict__ pos,
-    const float* __restrict__ radius, SceneTable tab, float min_radius_px, int C,
-    const float4* __restrict__ pslot, int ps4, float* __restrict__ grad_pos,
+__device__ __forceinline__ void write_sphere_grads(
+    int t, int i0, int nloc, uint32_t count, float4 g, float go, float gk, float npx,
+    const float (&gf)[CM > 0 ? CM : 1], const CamDev& cam, const float* __restrict__ pos,
+    const float* __restrict__ radius, float min_radius_px, int C, float* __restrict__ grad_pos,
     float* __restrict__ grad_radius, float* __restrict__ grad_opacity,
-    float* __restrict__ grad_payload, uint32_t nfin, const float* __restrict__ bgsum,
-    float* __restrict__ grad_bg, float4* __restrict__ camg, int paper_norm) {
+    float* __restrict__ grad_payload, float4* __restrict__ camg, int paper_norm,
+    float* __restrict__ s_gp, float* __restrict__ s_pay) {
   constexpr int CS = CM > 0 ? CM : 1;
-  __shared__ uint32_t s_cnt[kFinThreads];
-  __shared__ float s_gp[3 * kFinThreads];
-  __shared__ float s_pay[kFinThreads * CS];
-  const int t = threadIdx.x;
-  if (blockIdx.x >= nfin) {
-    const uint32_t k = blockIdx.x - nfin;
-    const int c = int(k % uint32_t(C)), b = int(k / uint32_t(C));
-    const uint32_t k0 = tab.blk_start[b], k1 = tab.blk_start[b + 1];
-    float acc = 0.f;
-    for (uint32_t j = k0 + t; j < k1; j += kFinThreads) acc += bgsum[size_t(j) * size_t(C) + c];
-    acc = wave_sum(acc);
-    __shared__ float s_red[kFinThreads / kWave];
-    if ((t & (kWave - 1)) == 0) s_red[t / kWave] = acc;
-    __syncthreads();
-    if (t == 0) {
-      float tsum = 0.f;
-      for (int w = 0; w < kFinThreads / kWave; ++w) tsum += s_red[w];
-      grad_bg[size_t(b) * size_t(C) + c] = tsum;
-    }
-    return;
-  }
-  const int i0 = blockIdx.x * kFinThreads;
-  const int nloc = min(kFinThreads, n - i0);
   const int i = i0 + t;
-  // the first slot: the projection block's first emission position plus the
-  // tile counts of the block's spheres before this one (the in-block prefix
-  // the projection computed; a block here is a projection block)
-  static_assert(kFinThreads == kProjectBlock, "one finalize block per projection block");
-  const uint32_t count = t < nloc ? counts[i] : 0u;
-  __shared__ uint32_t s_wpre[kFinThreads / kWave];
-  const int lane = t & (kWave - 1), wv = t / kWave;
-  const uint32_t incl = wave_incl_scan_u32(count, lane);
-  if (lane == kWave - 1) s_wpre[wv] = incl;
-  __syncthreads();
-  uint32_t first = incl - count;
-#pragma unroll
-  for (int w = 0; w < kFinThreads / kWave; ++w) first += w < wv ? s_wpre[w] : 0u;
-  const uint32_t base = count != 0u ? uint32_t(boff[blockIdx.x]) + first : 0u;
-  s_cnt[t] = count;
-  float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
-  float go = 0.f, gk = 0.f, npx = 0.f;
-  float gf[CS];
-#pragma unroll
-  for (int c = 0; c < CS; ++c) gf[c] = 0.f;
-  if (count != 0u) {
-    // after a capacity overflow (outputs invalid) the slots may be missing
-    if (size_t(base) + count <= size_t(status->used)) {
-      for (uint32_t k = 0; k < count; ++k) {
-        const float4* sr = pslot + size_t(base + k) * size_t(ps4);
-        const float4 a = sr[0];
-        g.x += a.x;
-        g.y += a.y;
-        g.z += a.z;
-        g.w += a.w;
-        if (CM > 0) {
-          constexpr int NT = (CM + 6) / 4;
-#pragma unroll
-          for (int q = 0; q < NT; ++q) {
-            const float4 v = sr[1 + q];
-            const float vv[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const int kk = 4 * q + u;
-              if (kk < CM)
-                gf[kk < CS ? kk : 0] += vv[u];
-              else if (kk == CM)
-                go += vv[u];
-              else if (kk == CM + 1)
-                gk += vv[u];
-              else if (kk == CM + 2)
-                npx += vv[u];
-            }
-          }
-        } else {
-          const float4 v = sr[1];
-          go += v.x;
-          gk += v.y;
-          npx += v.z;
-        }
-      }
-    }
-  }
   // the paper's optimisation-friendly variant (App. B normalisation, Sec. 7
   // limitation 1): every gradient of a sphere divided by the number of
   // pixels it received gradients from; position and radius gradients only
@@ -517,7 +437,6 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
       float gx = g.x, gy = g.y, gz = g.z, gR = g.w;
       bool clamped = false, gated = false;
       float cam_scale = 1.f;  // the paper's camera-gradient normalisation
-      const CamDev cam = tab.scenes[find_scene(tab.sph_start, tab.B, uint32_t(i))].cam;
       if (count != 0u && (min_radius_px > 0.f || paper_norm)) {
         const float px = pos[3 * i + 0], py = pos[3 * i + 1], pz = pos[3 * i + 2];
         const double cz = double(cam.R[6]) * px + double(cam.R[7]) * py +
@@ -582,6 +501,406 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
     // ... and its per-hit sums take the pixel-count average here
     for (int c = 0; c < C; ++c) grad_payload[size_t(i) * size_t(C) + c] *= scale;
   }
+}
+
+// K8 after the slot-based backward passes (the wide, stored-hits and
+// tile-order ones): per sphere, in sphere order, kFinThreads spheres per
+// block (a block is a projection block). The camera-space sums are the sum
+// of the sphere's pair slots sfirst .. sfirst + count - 1 (in that order;
+// none when it touches no tile). Blocks past the spheres sum the background
+// block sums, one block per (scene, channel); with nfin = 0 that is all the
+// launch does.
+template <int CM>
+__global__ __launch_bounds__(kFinThreads) void k_finalize(
+    int n, const uint32_t* __restrict__ counts, const unsigned long long* __restrict__ boff,
+    const Status* __restrict__ status, const float* __restrict__ pos,
+    const float* __restrict__ radius, SceneTable tab, float min_radius_px, int C,
+    const float4* __restrict__ pslot, int ps4, float* __restrict__ grad_pos,
+    float* __restrict__ grad_radius, float* __restrict__ grad_opacity,
+    float* __restrict__ grad_payload, uint32_t nfin, const float* __restrict__ bgsum,
+    float* __restrict__ grad_bg, float4* __restrict__ camg, int paper_norm) {
+  constexpr int CS = CM > 0 ? CM : 1;
+  __shared__ float s_gp[3 * kFinThreads];
+  __shared__ float s_pay[kFinThreads * CS];
+  const int t = threadIdx.x;
+  if (blockIdx.x >= nfin) {
+    const uint32_t k = blockIdx.x - nfin;
+    const int c = int(k % uint32_t(C)), b = int(k / uint32_t(C));
+    const uint32_t k0 = tab.blk_start[b], k1 = tab.blk_start[b + 1];
+    float acc = 0.f;
+    for (uint32_t j = k0 + t; j < k1; j += kFinThreads) acc += bgsum[size_t(j) * size_t(C) + c];
+    acc = wave_sum(acc);
+    __shared__ float s_red[kFinThreads / kWave];
+    if ((t & (kWave - 1)) == 0) s_red[t / kWave] = acc;
+    __syncthreads();
+    if (t == 0) {
+      float tsum = 0.f;
+      for (int w = 0; w < kFinThreads / kWave; ++w) tsum += s_red[w];
+      grad_bg[size_t(b) * size_t(C) + c] = tsum;
+    }
+    return;
+  }
+  const int i0 = blockIdx.x * kFinThreads;
+  const int nloc = min(kFinThreads, n - i0);
+  const int i = i0 + t;
+  // the first slot: the projection block's first emission position plus the
+  // tile counts of the block's spheres before this one (the in-block prefix
+  // the projection computed; a block here is a projection block)
+  static_assert(kFinThreads == kProjectBlock, "one finalize block per projection block");
+  const uint32_t count = t < nloc ? counts[i] : 0u;
+  __shared__ uint32_t s_wpre[kFinThreads / kWave];
+  const int lane = t & (kWave - 1), wv = t / kWave;
+  const uint32_t incl = wave_incl_scan_u32(count, lane);
+  if (lane == kWave - 1) s_wpre[wv] = incl;
+  __syncthreads();
+  uint32_t first = incl - count;
+#pragma unroll
+  for (int w = 0; w < kFinThreads / kWave; ++w) first += w < wv ? s_wpre[w] : 0u;
+  const uint32_t base = count != 0u ? uint32_t(boff[blockIdx.x]) + first : 0u;
+  float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+  float go = 0.f, gk = 0.f, npx = 0.f;
+  float gf[CS];
+#pragma unroll
+  for (int c = 0; c < CS; ++c) gf[c] = 0.f;
+  if (count != 0u) {
+    // after a capacity overflow (outputs invalid) the slots may be missing
+    if (size_t(base) + count <= size_t(status->used)) {
+      for (uint32_t k = 0; k < count; ++k) {
+        const float4* sr = pslot + size_t(base + k) * size_t(ps4);
+        const float4 a = sr[0];
+        g.x += a.x;
+        g.y += a.y;
+        g.z += a.z;
+        g.w += a.w;
+        if (CM > 0) {
+          constexpr int NT = (CM + 6) / 4;
+#pragma unroll
+          for (int q = 0; q < NT; ++q) {
+            const float4 v = sr[1 + q];
+            const float vv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int kk = 4 * q + u;
+              if (kk < CM)
+                gf[kk < CS ? kk : 0] += vv[u];
+              else if (kk == CM)
+                go += vv[u];
+              else if (kk == CM + 1)
+                gk += vv[u];
+              else if (kk == CM + 2)
+                npx += vv[u];
+            }
+          }
+        } else {
+          const float4 v = sr[1];
+          go += v.x;
+          gk += v.y;
+          npx += v.z;
+        }
+      }
+    }
+  }
+  // the sphere's own camera (a projection block may hold spheres of several scenes)
+  const CamDev cam = tab.scenes[find_scene(tab.sph_start, tab.B, uint32_t(t < nloc ? i : i0))].cam;
+  write_sphere_grads<CM>(t, i0, nloc, count, g, go, gk, npx, gf, cam, pos, radius, min_radius_px,
+                         C, grad_pos, grad_radius, grad_opacity, grad_payload, camg, paper_norm,
+                         s_gp, s_pay);
+}
+
+// ---------------------------------------------------------------- K7 by sphere
+// The default backward (up to kBwdChannels channels): one thread per sphere,
+// in sphere order, kSphThreads spheres of one scene per block. A sphere's
+// record, payload row and every output row are read and written as
+// contiguous runs, and its gradient never goes through per-pair slots: the
+// thread ends with the sphere's sums and writes its outputs itself.
+//
+// The (sphere, pixel of its rectangle) pairs of a wave are flattened over its
+// lanes, 64 at a time, by a prefix sum over rectangle sizes (a pair's sphere
+// is found by binary search in that sum), so a wave takes as many rounds as
+// its spheres have pixels in all / 64, whatever the size of each. A lane
+// gathers its pixel's L, K-th nearest hit and (for a hit among the K
+// nearest) G and F, recomputes the hit exactly as the forward did and forms
+// its terms; a segmented scan over the lanes adds the terms of each sphere's
+// pixels in a fixed order, and the sphere's own lane takes the sum. No
+// atomics: the gradients are reproducible bit for bit. The pixels that
+// spheres touch lie in the non-empty tiles, which stay in cache. Blocks past
+// the spheres compute the background-gradient block sums.
+struct BwdSphArgs {
+  const Status* status;
+  const uint32_t* counts;  // tiles per sphere (0: not visible)
+  const float4* rec;       // sphere records, rec4 float4 each
+  int rec4;
+  const float* payload;
+  int C;
+  int vec4;  // C % 4 == 0 and 16-byte aligned image rows: float4 row loads
+  int pay4;  // the same for the payload rows
+  const float* pos;
+  const float* radius;
+  const float* image;
+  const float* aux;
+  const float* grad_image;
+  const float2* thr;
+  // early termination: each sphere's earliest possible hit distance and per
+  // pixel the first hit the forward skipped (hits from it on take no part)
+  const float* tmin;
+  const float2* stop;
+  float* grad_pos;
+  float* grad_radius;
+  float* grad_opacity;
+  float* grad_payload;
+  float4* camg;
+  float min_radius_px;
+  int paper_norm;
+  int B;
+  uint32_t nsph_blocks;  // blocks of spheres; the blocks after them sum the background
+  SceneTable tab;
+  float* bgsum;  // background-gradient block sums, or null
+  float eps2;
+};
+
+constexpr int kSphThreads = kFinThreads;
+static_assert(kSphThreads == kBgThreads, "the background blocks share the launch");
+
+// Scene b owns blocks b + sph_off_b / kSphThreads onwards, as many as its
+// spheres need, so a block never spans two scenes (a block right after a
+// scene's last may have nothing to do).
+__device__ __forceinline__ uint32_t sph_first_block(const SceneDev& sc, int b) {
+  return uint32_t(b) + sc.sph_off / uint32_t(kSphThreads);
+}
+
+// The terms of one (sphere, pixel) pair, added into v = (dL/dc, dL/dR, dL/do,
+// dL/dkappa, pixel count, dL/df[CM]) when the pixel's ray hits the sphere
+// among its K nearest hits (the same tests, in the same precision, as every
+// other raster kernel).
+template <int CM, bool CAM, bool ES>
+__device__ __forceinline__ void sphere_pixel_terms(const BwdSphArgs& A, const CamDev& cam,
+                                                   const BlendConst& bc,
+                                                   unsigned long long pix_off,
+                                                   const SphereRec& s, const float (&f)[CM],
+                                                   uint32_t sph, float tmin, int px, int py,
+                                                   float (&v)[7 + CM]) {
+  const size_t p = size_t(pix_off) + size_t(py) * size_t(cam.W) + size_t(px);
+  const float2 th = A.thr[p];
+  const float aux = A.aux[p];
+  float2 st = make_float2(0.f, 0.f);
+  if (ES) st = A.stop[p];
+  // behind the pixel's K-th nearest hit: no gradient, no test needed
+  if (front_bound(s) > th.x) return;
+  // at or after the hit where the pixel stopped: never blended
+  if (ES) {
+    const uint64_t sk = (uint64_t(__float_as_uint(st.x)) << 32) | __float_as_uint(st.y);
+    if (((uint64_t(__float_as_uint(tmin)) << 32) | sph) >= sk) return;
+  }
+  const PixelRay ray = make_ray(cam, px, py);
+  Hit h;
+  if (!exact_hit(ray, s, bc.zfar, h)) return;
+  // among the pixel's K nearest: (t, sphere index) up to its K-th
+  const uint32_t ik = __float_as_uint(th.y);
+  if (!(sph == ik || h.t < th.x || (h.t == th.x && sph < ik))) return;
+  const int C = A.C;
+  float G[CM], F[CM];
+  if (A.vec4) {
+    const float4* g4 = reinterpret_cast<const float4*>(A.grad_image + p * size_t(C));
+    const float4* f4 = reinterpret_cast<const float4*>(A.image + p * size_t(C));
+#pragma unroll
+    for (int q = 0; q < (CM + 3) / 4; ++q) {
+      const int qq = min(q, C / 4 - 1);  // rows hold C / 4 float4
+      const float4 a = g4[qq], b = f4[qq];
+      const float ga[4] = {a.x, a.y, a.z, a.w}, fa[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (4 * q + u < CM) {
+          G[4 * q + u] = 4 * q + u < C ? ga[u] : 0.f;
+          F[4 * q + u] = 4 * q + u < C ? fa[u] : 0.f;
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < CM; ++c) {
+      G[c] = A.grad_image[p * size_t(C) + size_t(min(c, C - 1))];
+      F[c] = A.image[p * size_t(C) + size_t(min(c, C - 1))];
+    }
+#pragma unroll
+    for (int c = 0; c < CM; ++c) {
+      G[c] = c < C ? G[c] : 0.f;
+      F[c] = c < C ? F[c] : 0.f;
+    }
+  }
+  // G . (f_k - F), as G . f_k - G . F
+  float gfp = 0.f;
+#pragma unroll
+  for (int c = 0; c < CM; ++c) gfp += G[c] * F[c];
+  float hs = -gfp;
+#pragma unroll
+  for (int c = 0; c < CM; ++c) hs += G[c] * f[c];
+  const HitGrad g = hit_grad(ray, s, h, cam, bc, aux * 1.4426950408889634f, hs);
+  v[0] += g.gcx;
+  v[1] += g.gcy;
+  v[2] += g.gcz;
+  v[3] += g.gR;
+  v[4] += g.go;
+  if (CAM) v[5] += hit_grad_kappa(ray, s, h, cam, g);
+  v[6] += 1.f;
+#pragma unroll
+  for (int c = 0; c < CM; ++c) v[7 + c] += g.w * G[c];
+}
+
+template <int CM, bool CAM, bool ES>
+__global__ __launch_bounds__(kSphThreads) void k_bwd_spheres(BwdSphArgs A,
+                                                             const SceneDev* __restrict__ scenes) {
+  constexpr int NV = 7 + CM;                   // dL/dc (3), dL/dR, dL/do, dL/dkappa, count, dL/df
+  constexpr int RW = 16 + CM + (ES ? 1 : 0);   // staged words per sphere: record, payload, t_min
+  constexpr int RS = (RW + 3) & ~3;            // row stride in floats (16-byte rows)
+  static_assert(RS * kSphThreads >= 3 * kFinThreads + kFinThreads * CM, "output staging fits");
+  __shared__ float4 s_stage4[RS / 4 * kSphThreads];
+  float* s_stage = reinterpret_cast<float*>(s_stage4);
+  const int t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
+  const uint32_t g = blockIdx.x;
+  if (g >= A.nsph_blocks) {
+    if (A.bgsum) bg_partial_block(A.tab, A.aux, A.grad_image, A.C, A.eps2, A.bgsum,
+                                  g - A.nsph_blocks);
+    return;
+  }
+  // the block's scene (uniform: its camera comes in through scalar loads)
+  int lo = 0, hi = A.B - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (sph_first_block(scenes[mid], mid) <= g)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const SceneDev& sc = scenes[lo];
+  const uint32_t local = g - sph_first_block(sc, lo);
+  if (local >= (sc.n + uint32_t(kSphThreads) - 1u) / uint32_t(kSphThreads)) return;  // whole block
+  const int i0 = int(sc.sph_off + local * uint32_t(kSphThreads));
+  const int nloc = int(min(uint32_t(kSphThreads), sc.sph_off + sc.n - uint32_t(i0)));
+  const bool valid = t < nloc;
+  const int i = valid ? i0 + t : i0;  // loads stay inside the arrays
+  const CamDev cam = sc.cam;
+  const BlendConst bc = sc.bc;
+  const unsigned long long pix_off = sc.pix_off;
+  const int C = A.C;
+  // the sphere: its tile count (none after a capacity overflow, whose
+  // outputs are invalid anyway), then the record and payload row of a
+  // visible sphere (an invisible one has no record; most spheres of a
+  // scene can be invisible, and skipping their reads saves more than the
+  // extra round trip costs)
+  uint32_t count = A.counts[i];
+  count = (valid && A.status->code == 0u) ? count : 0u;
+  float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra, rc = ra, rd = ra;
+  float f[CM];
+#pragma unroll
+  for (int c = 0; c < CM; ++c) f[c] = 0.f;
+  float tm = 0.f;
+  if (count != 0u) {
+    const float4* rp = A.rec + size_t(A.rec4) * size_t(i);
+    ra = rp[0];
+    rb = rp[1];
+    rc = rp[2];
+    rd = rp[3];
+    if (A.pay4) {
+      const float4* f4 = reinterpret_cast<const float4*>(A.payload + size_t(i) * size_t(C));
+#pragma unroll
+      for (int q = 0; q < (CM + 3) / 4; ++q) {
+        const float4 v = f4[min(q, C / 4 - 1)];
+        const float va[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (4 * q + u < CM) f[4 * q + u] = va[u];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < CM; ++c) f[c] = A.payload[size_t(i) * size_t(C) + size_t(min(c, C - 1))];
+    }
+    if (ES) tm = A.tmin[i];
+  }
+  float* my = s_stage + t * RS;
+  reinterpret_cast<float4*>(my)[0] = ra;
+  reinterpret_cast<float4*>(my)[1] = rb;
+  reinterpret_cast<float4*>(my)[2] = rc;
+  reinterpret_cast<float4*>(my)[3] = rd;
+#pragma unroll
+  for (int c = 0; c < CM; ++c) my[16 + c] = c < C ? f[c] : 0.f;
+  if (ES) my[16 + CM] = tm;
+  const uint32_t p0 = __float_as_uint(ra.w), p1 = __float_as_uint(rd.z);
+  const uint32_t npx = count != 0u ? ((p1 & 0xffffu) - (p0 & 0xffffu) + 1u) *
+                                         ((p1 >> 16) - (p0 >> 16) + 1u)
+                                   : 0u;
+  __syncthreads();  // the stage is complete
+  // this wave's pairs: lane l's sphere owns pairs start .. start + npx - 1
+  const uint32_t incl = wave_incl_scan_u32(npx, lane);
+  const uint32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
+  const uint32_t start = incl - npx;
+  const float* wstage = s_stage + size_t(wv) * kWave * RS;
+  float acc[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) acc[q] = 0.f;
+  for (uint32_t pb = 0; pb < total; pb += kWave) {
+    const uint32_t j = pb + uint32_t(lane);
+    const bool act = j < total;
+    // the pair's sphere: the number of lanes whose pairs end at or before it
+    int o = 0;
+#pragma unroll
+    for (int step = kWave / 2; step > 0; step >>= 1) {
+      const uint32_t e = __shfl(incl, o + step - 1, kWave);
+      if (e <= j) o += step;
+    }
+    o = min(o, kWave - 1);  // lanes past the end
+    const uint32_t ostart = __shfl(start, o, kWave);
+    float v[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) v[q] = 0.f;
+    if (act) {
+      const float* r = wstage + o * RS;
+      const float4 a = reinterpret_cast<const float4*>(r)[0];
+      const float4 b = reinterpret_cast<const float4*>(r)[1];
+      const float4 c = reinterpret_cast<const float4*>(r)[2];
+      const float4 d = reinterpret_cast<const float4*>(r)[3];
+      float fo[CM];
+#pragma unroll
+      for (int q = 0; q < CM; ++q) fo[q] = r[16 + q];
+      const float to = ES ? r[16 + CM] : 0.f;
+      const SphereRec s = unpack_rec(a, b, c, d);
+      const uint32_t q1 = __float_as_uint(d.z);
+      const uint32_t w = (q1 & 0xffffu) - uint32_t(s.x0) + 1u;
+      const uint32_t k = j - ostart;
+      const uint32_t yy = k / w;
+      const int px = s.x0 + int(k - yy * w), py = s.y0 + int(yy);
+      sphere_pixel_terms<CM, CAM, ES>(A, cam, bc, pix_off, s, fo,
+                                      uint32_t(i0 + wv * kWave + o), to, px, py, v);
+    }
+    // segmented inclusive scan over the lanes: a lane adds the partial sum of
+    // the lane `off` below while both belong to the same sphere
+    const uint32_t key = act ? uint32_t(o) : uint32_t(kWave + lane);
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const uint32_t ku = __shfl_up(key, off, kWave);
+      const bool add = lane >= off && ku == key;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const float x = __shfl_up(v[q], off, kWave);
+        v[q] = add ? v[q] + x : v[q];
+      }
+    }
+    // each sphere takes the sum at the last lane of its run in this round
+    const bool has = npx != 0u && start < pb + kWave && start + npx > pb;
+    const int tail = has ? int(min(start + npx, pb + kWave) - 1u - pb) : lane;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const float x = __shfl(v[q], tail, kWave);
+      acc[q] = has ? acc[q] + x : acc[q];
+    }
+  }
+  __syncthreads();  // every wave is done with the stage; it now stages the outputs
+  float gf[CM];
+#pragma unroll
+  for (int c = 0; c < CM; ++c) gf[c] = acc[7 + c];
+  write_sphere_grads<CM>(t, i0, nloc, count, make_float4(acc[0], acc[1], acc[2], acc[3]), acc[4],
+                         acc[5], acc[6], gf, cam, A.pos, A.radius, A.min_radius_px, C, A.grad_pos,
+                         A.grad_radius, A.grad_opacity, A.grad_payload, A.camg, A.paper_norm,
+                         s_stage, s_stage + 3 * kFinThreads);
 }
 
 // The block sum for background block `blk`, by a whole block of kBgThreads
@@ -872,6 +1191,26 @@ static void launch_items(const BwdKernelArgs& A, dim3 grid, dim3 block, hipStrea
     launch_items_es<CM, false>(A, grid, block, stream);
 }
 
+template <int CM, bool CAM>
+static void launch_spheres_cam(const BwdSphArgs& S, unsigned grid, const SceneDev* scenes,
+                               hipStream_t stream) {
+  if (S.stop)
+    hipLaunchKernelGGL((k_bwd_spheres<CM, CAM, true>), dim3(grid), dim3(kSphThreads), 0, stream,
+                       S, scenes);
+  else
+    hipLaunchKernelGGL((k_bwd_spheres<CM, CAM, false>), dim3(grid), dim3(kSphThreads), 0, stream,
+                       S, scenes);
+}
+
+template <int CM>
+static void launch_spheres(const BwdSphArgs& S, bool cam, unsigned grid, const SceneDev* scenes,
+                           hipStream_t stream) {
+  if (cam)
+    launch_spheres_cam<CM, true>(S, grid, scenes, stream);
+  else
+    launch_spheres_cam<CM, false>(S, grid, scenes, stream);
+}
+
 template <int CM>
 static void launch_finalize(const Plan& q, const BwdArgs& a, char* ws, hipStream_t stream,
                             uint32_t nfin, uint32_t nred) {
@@ -1016,6 +1355,8 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
   A.K = q.K;
   A.T = uint32_t(q.T);
   const bool store = q.store_hits != 0;
+  // the default: the walk in sphere order, which writes the outputs itself
+  const bool by_sphere = !wide && !store && !q.bwd_tiles;
   // the pair-parallel kernel also computes the background block sums
   if (store) A.bgsum = nullptr;
   float* bgsum = ws_ptr<float>(ws, q.off_bgsum);
@@ -1044,6 +1385,53 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
       launch_hits<32>(A, hg, stream);
     else
       launch_hits<0>(A, hg, stream);
+  } else if (by_sphere) {
+    BwdSphArgs S;
+    S.status = A.status;
+    S.counts = counts;
+    S.rec = A.rec;
+    S.rec4 = q.rec4;
+    S.payload = a.payload;
+    S.C = a.C;
+    S.vec4 = (a.C % 4 == 0 && (reinterpret_cast<uintptr_t>(a.image) & 15u) == 0u &&
+              (reinterpret_cast<uintptr_t>(a.grad_image) & 15u) == 0u)
+                 ? 1
+                 : 0;
+    S.pay4 = (a.C % 4 == 0 && (reinterpret_cast<uintptr_t>(a.payload) & 15u) == 0u) ? 1 : 0;
+    S.pos = a.pos;
+    S.radius = a.radius;
+    S.image = a.image;
+    S.aux = a.aux;
+    S.grad_image = a.grad_image;
+    S.thr = A.thr;
+    S.tmin = A.tmin;
+    S.stop = A.stop;
+    S.grad_pos = a.grad_pos;
+    S.grad_radius = a.grad_radius;
+    S.grad_opacity = a.grad_opacity;
+    S.grad_payload = a.grad_payload;
+    S.camg = a.grad_cam ? ws_ptr<float4>(ws, q.off_camg) : nullptr;
+    S.min_radius_px = a.min_radius_px;
+    S.paper_norm = a.paper_norm ? 1 : 0;
+    S.B = q.B;
+    // scene b's blocks start at b + sph_off_b / kSphThreads
+    S.nsph_blocks = uint32_t(q.B + (q.n + kSphThreads - 1) / kSphThreads);
+    S.tab = tab;
+    S.bgsum = a.grad_bg ? bgsum : nullptr;
+    S.eps2 = a.eps2;
+    const unsigned grid = unsigned(S.nsph_blocks + (a.grad_bg ? uint32_t(q.nbgblk) : 0u));
+    if (a.C <= 1)
+      launch_spheres<1>(S, a.grad_cam != nullptr, grid, tab.scenes, stream);
+    else if (a.C <= 2)
+      launch_spheres<2>(S, a.grad_cam != nullptr, grid, tab.scenes, stream);
+    else if (a.C <= 4)
+      launch_spheres<4>(S, a.grad_cam != nullptr, grid, tab.scenes, stream);
+    else if (a.C <= 8)
+      launch_spheres<8>(S, a.grad_cam != nullptr, grid, tab.scenes, stream);
+    else if (a.C <= 16)
+      launch_spheres<16>(S, a.grad_cam != nullptr, grid, tab.scenes, stream);
+    else
+      launch_spheres<32>(S, a.grad_cam != nullptr, grid, tab.scenes, stream);
   } else {
     // as many waves as the forward's grid of one-wave blocks: blocks past the
     // work items would only be dispatched after them to find nothing to do
@@ -1075,7 +1463,8 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
       hipLaunchKernelGGL(k_bg_partial_wide, dim3(unsigned(q.nbgblk)), dim3(kBgThreads), 0,
                          stream, tab, a.aux, a.grad_image, int(q.C), a.eps2, bgsum);
   }
-  const uint32_t nfin = uint32_t((q.n + kFinThreads - 1) / kFinThreads);
+  // after the walk in sphere order only the per-scene background sums remain
+  const uint32_t nfin = by_sphere ? 0u : uint32_t((q.n + kFinThreads - 1) / kFinThreads);
   const uint32_t nred = a.grad_bg ? uint32_t(q.C) * uint32_t(q.B) : 0u;
   if (nfin + nred > 0) {
     if (a.C <= 1)

@@ -103,7 +103,7 @@ static void invalid_params() {
       {"eps -1", [](pulsar_params_t* p) { p->eps = -1.0f; }},
       {"eps inf", [](pulsar_params_t* p) { p->eps = INFINITY; }},
       {"min radius -1", [](pulsar_params_t* p) { p->min_radius_px = -1.0f; }},
-      {"reserved flag", [](pulsar_params_t* p) { p->flags = 0x40u; }},
+      {"reserved flag", [](pulsar_params_t* p) { p->flags = 0x80u; }},
       {"top bit", [](pulsar_params_t* p) { p->flags = 0x80000000u; }},
       {"depth bits", [](pulsar_params_t* p) { p->depth_bits = 1; }},
       {"chunk 65", [](pulsar_params_t* p) { p->chunk = 65; }},

@@ -35,7 +35,8 @@ def test_with_knobs_keeps_other_fields():
     q = at.with_knobs(p, {"chunk": 256, "raster_blocks": 8192})
     assert (q.gamma, q.eps, q.K, q.max_pairs) == (p.gamma, p.eps, p.K, p.max_pairs)
     assert (q.chunk, q.raster_blocks, p.chunk, p.raster_blocks) == (256, 8192, 0, 0)
-    assert at.knobs_of(q) == {"raster_blocks": 8192, "chunk": 256, "store_hits": 0}
+    assert at.knobs_of(q) == {"raster_blocks": 8192, "chunk": 256, "store_hits": 0,
+                             "bwd_tiles": 0}
     r = at.with_knobs(p, {"store_hits": 1})
     assert r.flags & _capi.PULSAR_STORE_HITS and at.knobs_of(r)["store_hits"] == 1
     assert at.with_knobs(r, {"store_hits": 0}).flags == p.flags

@@ -114,7 +114,7 @@ def test_bad_params_are_rejected(par_kw, code):
 
 
 def test_reserved_flags_are_unsupported():
-    for bit in [0x40, 0x80, 0x80000000]:
+    for bit in [0x80, 0x100, 0x80000000]:
         p = _capi.make_params(flags=bit | _capi.PULSAR_REBIN)
         assert _call_fwd(_cam(), p) == _capi.PULSAR_ERR_UNSUPPORTED
 
@@ -129,6 +129,24 @@ def test_known_flags_pass_validation():
         # flags change no workspace size
         assert _capi.pulsar_workspace_size(10, 64, 64, 3, p) == \
             _capi.pulsar_workspace_size(10, 64, 64, 3, _capi.make_params())
+
+
+def test_pair_slots_only_for_the_backwards_that_use_them():
+    """The default backward (in sphere order) needs no per-pair slots; the
+    tile-order and stored-hits backwards and payloads wider than 32 channels
+    do, 16 bytes per float4 of a slot and pair."""
+    _lib()
+    cap = 10**5
+    plain = _capi.pulsar_workspace_size(1000, 64, 64, 3, _capi.make_params(max_pairs=cap))
+    tiles = _capi.pulsar_workspace_size(1000, 64, 64, 3, _capi.make_params(
+        max_pairs=cap, flags=_capi.PULSAR_BWD_TILES))
+    store = _capi.pulsar_workspace_size(1000, 64, 64, 3, _capi.make_params(
+        max_pairs=cap, flags=_capi.PULSAR_STORE_HITS))
+    # C = 3: a slot of two float4 (dL/dc, dL/dR | dL/df[4], dL/do, ...)
+    assert tiles - plain >= 32 * cap
+    assert store > tiles
+    p = _capi.make_params(flags=_capi.PULSAR_BWD_TILES)
+    assert _call_fwd(_cam(), p, ws_bytes=1024) == _capi.PULSAR_ERR_WORKSPACE
 
 
 def test_missing_pointers_and_small_workspace():

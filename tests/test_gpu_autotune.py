@@ -41,7 +41,7 @@ def test_renderer_autotune_matches_untuned(tmp_path):
     data = json.load(open(path))
     assert len(data) == 1
     entry = next(iter(data.values()))
-    assert set(entry["knobs"]) == {"raster_blocks", "chunk", "store_hits"}
+    assert set(entry["knobs"]) == {"raster_blocks", "chunk", "store_hits", "bwd_tiles"}
     assert entry["ms"] > 0
     # a second renderer reads the cached choice instead of measuring again
     again = Renderer(cam.width, cam.height, n, n_channels=C, K=par.K, autotune=True,

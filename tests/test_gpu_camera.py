@@ -34,12 +34,12 @@ def _rotated(wl, seed):
     return sc, cam
 
 
-def _check(sc, cam, par, what, rows=None, G_seed=500):
+def _check(sc, cam, par, what, rows=None, G_seed=500, flags=0):
     _say(f"[camera] {what} n={sc.n} {cam.width}x{cam.height} C={sc.C} K={par.K}")
     fwd = ref.forward(sc, cam, par, rows=rows)
     G = sg.upstream_grad(G_seed, cam.height, cam.width, sc.C)
     Gm = masked_G(G, rows, fwd["ambiguous"])
-    out = gpu_render(sc, cam, par, Gm, camera_grad=True)
+    out = gpu_render(sc, cam, par, Gm, camera_grad=True, fwd_flags=flags, bwd_flags=flags)
     assert out["status"] == _capi.PULSAR_OK
     g = ref.backward(sc, cam, par, Gm, fwd, rows=rows)
     assert np.isfinite(out["grad_camera"]).all()
@@ -53,6 +53,13 @@ def test_camera_gradients_small_rotated(seed):
     wl = sg.config1()
     sc, cam = _rotated(wl, seed)
     _check(sc, cam, wl.params, f"1k spheres, pose {seed}")
+
+
+def test_camera_gradients_tile_order():
+    """The same through the backward that walks the tile lists."""
+    wl = sg.config1()
+    sc, cam = _rotated(wl, 3)
+    _check(sc, cam, wl.params, "1k spheres, tile order", flags=_capi.PULSAR_BWD_TILES)
 
 
 def test_camera_gradients_identity_pose():

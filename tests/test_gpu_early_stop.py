@@ -81,10 +81,12 @@ def dataclass_replace(par, **kw):
 
 
 @pytest.mark.parametrize("case", ["plain", "rotated_rebin", "orthographic", "wide_payload",
-                                  "K1", "small_share"])
+                                  "K1", "small_share", "tile_order"])
 def test_early_stop_matches_oracle(case):
     sc, cam, par = stacked()
     fwd_flags = bwd_flags = 0
+    if case == "tile_order":
+        fwd_flags = bwd_flags = _capi.PULSAR_BWD_TILES
     if case == "rotated_rebin":
         _rotate(sc, cam, 5)
         bwd_flags = _capi.PULSAR_REBIN
