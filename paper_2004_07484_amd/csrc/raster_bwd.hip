@@ -61,9 +61,12 @@ struct BwdKernelArgs {
 
 constexpr int kBgThreads = 256;
 constexpr int kBgMaxC = kBgThreads;  // wider images use k_bg_partial_wide
+// LDS floats a background block sum works in (the caller's, so a kernel that
+// also does other work can share it)
+constexpr int kBgScratch = kBgBlockPixels + kBgThreads + 4 * kBgThreads;
 __device__ void bg_partial_block(const SceneTable& tab, const float* __restrict__ aux,
                                  const float* __restrict__ grad_image, int C, float eps2,
-                                 float* __restrict__ bgsum, uint32_t blk);
+                                 float* __restrict__ bgsum, uint32_t blk, float* scratch);
 
 // Gradient terms of one hit (pixel ray, sphere s) that belongs to the K
 // nearest: derivatives of Eq. 1 through t (depth), 1 - q/R (distance), o and f.
@@ -141,6 +144,7 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
   __shared__ float s_L2[kWave], s_GF[kWave], s_tk[kWave];
   __shared__ uint32_t s_ik[kWave];
   __shared__ uint64_t s_sk[ES ? kWave : 1];  // early termination: first skipped hit
+  __shared__ float s_bg[kBgScratch];           // the background block sums at the end
   const int tid = threadIdx.x;
   const int C = A.C;
   const uint32_t nchunks = item_count(A.status), nfull = A.status->nfull;
@@ -283,7 +287,7 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
   // overlap the uneven end of the work-item loop)
   if (A.bgsum)
     for (uint32_t blk = blockIdx.x; blk < A.nbgblk; blk += gridDim.x)
-      bg_partial_block(A.tab, A.aux, A.grad_image, C, A.eps2, A.bgsum, blk);
+      bg_partial_block(A.tab, A.aux, A.grad_image, C, A.eps2, A.bgsum, blk, s_bg);
 }
 
 // Channels beyond the register budget: same walk, the pixel terms read from
@@ -405,16 +409,77 @@ __global__ void k_bwd_prep(int n, const uint32_t* __restrict__ counts, int C,
   for (int c = 0; c < C; ++c) grad_payload[size_t(i) * size_t(C) + c] = 0.f;
 }
 
-// The outputs of a block's spheres i0 .. i0 + nloc - 1 from their
-// camera-space sums, thread t holding sphere i0 + t (count: the tiles it
-// touches, 0 when it is not visible; npx: the pixels it received gradients
-// from). Position and radius gradients follow c = R p + t and the min-size
-// clamp; opacity and payload gradients are copied out (CM > 0; with CM = 0,
-// the wide path, the payload gradient was added in place). Rows wider than
-// one float (positions, payloads) are staged in s_gp [3 kFinThreads] and
-// s_pay [kFinThreads CS] and written as one contiguous run, so every store
-// instruction covers consecutive addresses. Every thread of the block calls
-// it (it holds a barrier).
+// A sphere's gradients from its camera-space sums g = (dL/dc, dL/dR), go =
+// dL/do, gk = dL/dkappa (count: the tiles it touches, 0 when it is not
+// visible; npx: the pixels it received gradients from). Writes its opacity,
+// radius and camera-space camera terms and returns its position gradient
+// (dL/dp = R^T dL/dc with the min-size clamp) and the factor of its payload
+// gradient.
+struct SphereGrad {
+  float gx, gy, gz;  // dL/dp
+  float scale;       // payload-gradient factor (the paper's per-pixel average)
+};
+
+__device__ __forceinline__ SphereGrad sphere_grad(int i, uint32_t count, float4 g, float go,
+                                                  float gk, float npx, const CamDev& cam,
+                                                  const float* __restrict__ pos,
+                                                  const float* __restrict__ radius,
+                                                  float min_radius_px,
+                                                  float* __restrict__ grad_radius,
+                                                  float* __restrict__ grad_opacity,
+                                                  float4* __restrict__ camg, int paper_norm,
+                                                  bool need_pos) {
+  SphereGrad o;
+  // the paper's optimisation-friendly variant (App. B normalisation, Sec. 7
+  // limitation 1): every gradient of a sphere divided by the number of
+  // pixels it received gradients from; position and radius gradients only
+  // for spheres wider than 3 pixels in radius (R f / (c_z pitch))
+  o.scale = (paper_norm && npx > 0.f) ? 1.f / npx : 1.f;
+  o.gx = o.gy = o.gz = 0.f;
+  if (grad_opacity) grad_opacity[i] = go * o.scale;
+  if (!(need_pos || grad_radius || camg)) return o;
+  float gx = g.x, gy = g.y, gz = g.z, gR = g.w;
+  bool clamped = false, gated = false;
+  float cam_scale = 1.f;  // the paper's camera-gradient normalisation
+  if (count != 0u && (min_radius_px > 0.f || paper_norm)) {
+    const float px = pos[3 * i + 0], py = pos[3 * i + 1], pz = pos[3 * i + 2];
+    const double cz = double(cam.R[6]) * px + double(cam.R[7]) * py + double(cam.R[8]) * pz +
+                      double(cam.t[2]);
+    const double pitch = double(cam.s) / double(cam.W);
+    // orthographic: the minimum radius min_radius_px pitch is constant
+    const double k = cam.ortho ? 0.0 : double(min_radius_px) * pitch / double(cam.f);
+    const double rmin = cam.ortho ? double(min_radius_px) * pitch : k * cz;
+    clamped = min_radius_px > 0.f && rmin > double(radius[i]);
+    if (clamped && !cam.ortho) {
+      gz += float(double(gR) * k);  // R = k c_z depends on depth only
+      // and on the camera through k = min_radius_px / (W kappa):
+      // dR/dkappa = -R / kappa
+      gk -= float(double(gR) * k * cz * double(cam.s) / double(cam.f));
+    }
+    const double reff = clamped ? rmin : double(radius[i]);
+    const double rpx = cam.ortho ? reff / pitch : reff * double(cam.f) / (cz * pitch);
+    gated = paper_norm && !(rpx > 3.0);
+    // camera gradients: each sphere's part over its projected disk area
+    // in pixels, times 1e-3 (App. B, normalisation)
+    if (paper_norm) cam_scale = float(1e-3 / (3.141592653589793 * rpx * rpx));
+  }
+  if (camg) camg[i] = make_float4(gx * cam_scale, gy * cam_scale, gz * cam_scale, gk * cam_scale);
+  if (grad_radius) grad_radius[i] = (clamped || gated) ? 0.f : gR * o.scale;
+  // c = R p + t  =>  dL/dp = R^T dL/dc
+  const float ps = gated ? 0.f : o.scale;
+  o.gx = (cam.R[0] * gx + cam.R[3] * gy + cam.R[6] * gz) * ps;
+  o.gy = (cam.R[1] * gx + cam.R[4] * gy + cam.R[7] * gz) * ps;
+  o.gz = (cam.R[2] * gx + cam.R[5] * gy + cam.R[8] * gz) * ps;
+  return o;
+}
+
+// The outputs of a block's spheres i0 .. i0 + nloc - 1, thread t holding
+// sphere i0 + t (see sphere_grad). Opacity and payload gradients are copied
+// out (CM > 0; with CM = 0, the wide path, the payload gradient was added in
+// place). Rows wider than one float (positions, payloads) are staged in s_gp
+// [3 kFinThreads] and s_pay [kFinThreads CS] and written as one contiguous
+// run, so every store instruction covers consecutive addresses. Every thread
+// of the block calls it (it holds a barrier).
 constexpr int kFinThreads = 256;
 template <int CM>
 __device__ __forceinline__ void write_sphere_grads(
@@ -426,48 +491,15 @@ __device__ __forceinline__ void write_sphere_grads(
     float* __restrict__ s_gp, float* __restrict__ s_pay) {
   constexpr int CS = CM > 0 ? CM : 1;
   const int i = i0 + t;
-  // the paper's optimisation-friendly variant (App. B normalisation, Sec. 7
-  // limitation 1): every gradient of a sphere divided by the number of
-  // pixels it received gradients from; position and radius gradients only
-  // for spheres wider than 3 pixels in radius (R f / (c_z pitch))
-  const float scale = (paper_norm && npx > 0.f) ? 1.f / npx : 1.f;
+  float scale = 1.f;
   if (t < nloc) {
-    if (grad_opacity) grad_opacity[i] = go * scale;
-    if (grad_pos || grad_radius || camg) {
-      float gx = g.x, gy = g.y, gz = g.z, gR = g.w;
-      bool clamped = false, gated = false;
-      float cam_scale = 1.f;  // the paper's camera-gradient normalisation
-      if (count != 0u && (min_radius_px > 0.f || paper_norm)) {
-        const float px = pos[3 * i + 0], py = pos[3 * i + 1], pz = pos[3 * i + 2];
-        const double cz = double(cam.R[6]) * px + double(cam.R[7]) * py +
-                          double(cam.R[8]) * pz + double(cam.t[2]);
-        const double pitch = double(cam.s) / double(cam.W);
-        // orthographic: the minimum radius min_radius_px pitch is constant
-        const double k = cam.ortho ? 0.0 : double(min_radius_px) * pitch / double(cam.f);
-        const double rmin = cam.ortho ? double(min_radius_px) * pitch : k * cz;
-        clamped = min_radius_px > 0.f && rmin > double(radius[i]);
-        if (clamped && !cam.ortho) {
-          gz += float(double(gR) * k);  // R = k c_z depends on depth only
-          // and on the camera through k = min_radius_px / (W kappa):
-          // dR/dkappa = -R / kappa
-          gk -= float(double(gR) * k * cz * double(cam.s) / double(cam.f));
-        }
-        const double reff = clamped ? rmin : double(radius[i]);
-        const double rpx = cam.ortho ? reff / pitch : reff * double(cam.f) / (cz * pitch);
-        gated = paper_norm && !(rpx > 3.0);
-        // camera gradients: each sphere's part over its projected disk area
-        // in pixels, times 1e-3 (App. B, normalisation)
-        if (paper_norm) cam_scale = float(1e-3 / (3.141592653589793 * rpx * rpx));
-      }
-      if (camg)
-        camg[i] = make_float4(gx * cam_scale, gy * cam_scale, gz * cam_scale, gk * cam_scale);
-      if (grad_radius) grad_radius[i] = (clamped || gated) ? 0.f : gR * scale;
-      // c = R p + t  =>  dL/dp = R^T dL/dc
-      const float ps = gated ? 0.f : scale;
-      s_gp[3 * t + 0] = (cam.R[0] * gx + cam.R[3] * gy + cam.R[6] * gz) * ps;
-      s_gp[3 * t + 1] = (cam.R[1] * gx + cam.R[4] * gy + cam.R[7] * gz) * ps;
-      s_gp[3 * t + 2] = (cam.R[2] * gx + cam.R[5] * gy + cam.R[8] * gz) * ps;
-    }
+    const SphereGrad o = sphere_grad(i, count, g, go, gk, npx, cam, pos, radius, min_radius_px,
+                                     grad_radius, grad_opacity, camg, paper_norm,
+                                     grad_pos != nullptr);
+    scale = o.scale;
+    s_gp[3 * t + 0] = o.gx;
+    s_gp[3 * t + 1] = o.gy;
+    s_gp[3 * t + 2] = o.gz;
   }
   if (CM > 0) {
 #pragma unroll
@@ -634,6 +666,7 @@ struct BwdSphArgs {
   int C;
   int vec4;  // C % 4 == 0 and 16-byte aligned image rows: float4 row loads
   int pay4;  // the same for the payload rows
+  int gpay4;  // ... and for the payload-gradient rows
   const float* pos;
   const float* radius;
   const float* image;
@@ -752,14 +785,14 @@ __global__ __launch_bounds__(kSphThreads) void k_bwd_spheres(BwdSphArgs A,
   constexpr int NV = 7 + CM;                   // dL/dc (3), dL/dR, dL/do, dL/dkappa, count, dL/df
   constexpr int RW = 16 + CM + (ES ? 1 : 0);   // staged words per sphere: record, payload, t_min
   constexpr int RS = (RW + 3) & ~3;            // row stride in floats (16-byte rows)
-  static_assert(RS * kSphThreads >= 3 * kFinThreads + kFinThreads * CM, "output staging fits");
+  static_assert(RS * kSphThreads >= kBgScratch, "the background sums fit the stage");
   __shared__ float4 s_stage4[RS / 4 * kSphThreads];
   float* s_stage = reinterpret_cast<float*>(s_stage4);
   const int t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
   const uint32_t g = blockIdx.x;
   if (g >= A.nsph_blocks) {
     if (A.bgsum) bg_partial_block(A.tab, A.aux, A.grad_image, A.C, A.eps2, A.bgsum,
-                                  g - A.nsph_blocks);
+                                  g - A.nsph_blocks, s_stage);
     return;
   }
   // the block's scene (uniform: its camera comes in through scalar loads)
@@ -828,7 +861,11 @@ __global__ __launch_bounds__(kSphThreads) void k_bwd_spheres(BwdSphArgs A,
   const uint32_t npx = count != 0u ? ((p1 & 0xffffu) - (p0 & 0xffffu) + 1u) *
                                          ((p1 >> 16) - (p0 >> 16) + 1u)
                                    : 0u;
-  __syncthreads();  // the stage is complete
+  // each wave reads only its own rows of the stage: a wave-level barrier
+  // (LDS operations of one wave complete in order)
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   // this wave's pairs: lane l's sphere owns pairs start .. start + npx - 1
   const uint32_t incl = wave_incl_scan_u32(npx, lane);
   const uint32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
@@ -893,14 +930,35 @@ __global__ __launch_bounds__(kSphThreads) void k_bwd_spheres(BwdSphArgs A,
       acc[q] = has ? acc[q] + x : acc[q];
     }
   }
-  __syncthreads();  // every wave is done with the stage; it now stages the outputs
-  float gf[CM];
+  // the sphere's outputs, each lane its own rows (a wave's position rows are
+  // one run of 768 bytes, its payload rows one of 256 C bytes)
+  if (!valid) return;
+  const SphereGrad o = sphere_grad(i, count, make_float4(acc[0], acc[1], acc[2], acc[3]), acc[4],
+                                   acc[5], acc[6], cam, A.pos, A.radius, A.min_radius_px,
+                                   A.grad_radius, A.grad_opacity, A.camg, A.paper_norm,
+                                   A.grad_pos != nullptr);
+  if (A.grad_pos) {
+    A.grad_pos[3 * size_t(i) + 0] = o.gx;
+    A.grad_pos[3 * size_t(i) + 1] = o.gy;
+    A.grad_pos[3 * size_t(i) + 2] = o.gz;
+  }
+  if (A.grad_payload) {
+    float* gp = A.grad_payload + size_t(i) * size_t(C);
+    if (A.gpay4) {
 #pragma unroll
-  for (int c = 0; c < CM; ++c) gf[c] = acc[7 + c];
-  write_sphere_grads<CM>(t, i0, nloc, count, make_float4(acc[0], acc[1], acc[2], acc[3]), acc[4],
-                         acc[5], acc[6], gf, cam, A.pos, A.radius, A.min_radius_px, C, A.grad_pos,
-                         A.grad_radius, A.grad_opacity, A.grad_payload, A.camg, A.paper_norm,
-                         s_stage, s_stage + 3 * kFinThreads);
+      for (int q = 0; q < (CM + 3) / 4; ++q)
+        if (4 * q < C)
+          reinterpret_cast<float4*>(gp)[q] =
+              make_float4(acc[7 + min(4 * q, CM - 1)] * o.scale,
+                          acc[7 + min(4 * q + 1, CM - 1)] * o.scale,
+                          acc[7 + min(4 * q + 2, CM - 1)] * o.scale,
+                          acc[7 + min(4 * q + 3, CM - 1)] * o.scale);
+    } else {
+#pragma unroll
+      for (int c = 0; c < CM; ++c)
+        if (c < C) gp[c] = acc[7 + c] * o.scale;
+    }
+  }
 }
 
 // The block sum for background block `blk`, by a whole block of kBgThreads
@@ -908,10 +966,10 @@ __global__ __launch_bounds__(kSphThreads) void k_bwd_spheres(BwdSphArgs A,
 // for several blocks in a row).
 __device__ void bg_partial_block(const SceneTable& tab, const float* __restrict__ aux,
                                  const float* __restrict__ grad_image, int C, float eps2,
-                                 float* __restrict__ bgsum, uint32_t blk) {
-  __shared__ float s_w[kBgBlockPixels];
-  __shared__ float s_acc[kBgThreads];
-  __shared__ float s_acc4_buf[4 * kBgThreads];
+                                 float* __restrict__ bgsum, uint32_t blk, float* scratch) {
+  float* s_w = scratch;                          // [kBgBlockPixels]
+  float* s_acc = scratch + kBgBlockPixels;       // [kBgThreads]
+  float* s_acc4_buf = s_acc + kBgThreads;        // [4 kBgThreads]
   const int tid = threadIdx.x;
   __syncthreads();  // the previous call's readers are done with the LDS
   const int b = find_scene(tab.blk_start, tab.B, blk);
@@ -1025,7 +1083,8 @@ __global__ __launch_bounds__(kBgThreads) void k_bg_partial(SceneTable tab,
                                                            const float* __restrict__ grad_image,
                                                            int C, float eps2,
                                                            float* __restrict__ bgsum) {
-  bg_partial_block(tab, aux, grad_image, C, eps2, bgsum, blockIdx.x);
+  __shared__ float s_bg[kBgScratch];
+  bg_partial_block(tab, aux, grad_image, C, eps2, bgsum, blockIdx.x, s_bg);
 }
 
 // The same sums for C > kBgMaxC: one pixel per thread and a loop over channels.
@@ -1398,6 +1457,8 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
                  ? 1
                  : 0;
     S.pay4 = (a.C % 4 == 0 && (reinterpret_cast<uintptr_t>(a.payload) & 15u) == 0u) ? 1 : 0;
+    S.gpay4 =
+        (a.C % 4 == 0 && (reinterpret_cast<uintptr_t>(a.grad_payload) & 15u) == 0u) ? 1 : 0;
     S.pos = a.pos;
     S.radius = a.radius;
     S.image = a.image;
