@@ -348,7 +348,12 @@ def stage_roofline(stage_avg: dict, n, H, W, C, pairs, workload, by_sphere: bool
                        "achieved_GBs": round(nbytes / (ms * 1e-3) / 1e9, 1) if ms > 0 else None,
                        "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
                        if ms > 0 else None}
-    dom = max(sb, key=lambda k: stage_avg.get(k, 0.0))
+    # the dominant kernel: the longest stage that is a single kernel, so its
+    # average duration can be checked against the rocprofv3 kernel trace
+    # (binning is six kernels; its own figures are in `kernels` and in
+    # `longest_stage` when it takes longest)
+    single = [k for k in sb if k != "binning"]
+    dom = max(single, key=lambda k: stage_avg.get(k, 0.0))
     ms = stage_avg[dom]
     achieved = sb[dom] / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     kname = names[dom]
@@ -356,6 +361,10 @@ def stage_roofline(stage_avg: dict, n, H, W, C, pairs, workload, by_sphere: bool
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic(kname, workload), "avg_ms": round(ms, 4),
                 "bytes_per_launch": sb[dom]}
+    longest = max(sb, key=lambda k: stage_avg.get(k, 0.0))
+    roofline["longest_stage"] = {"stage": longest, "kernel": names[longest],
+                                 "avg_ms": round(stage_avg.get(longest, 0.0), 4),
+                                 "frac": kernels[longest]["frac"]}
     return roofline, kernels
 
 
