@@ -237,7 +237,7 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   const bool thr = bwd || (p->flags & PULSAR_BLEND_TOPK) != 0u;
   q.off_bgsum = take(bwd ? size_t(q.nbgblk) * size_t(C) * 4 : 0);
   q.off_pstate = take(size_t(q.pcap) * kWave * size_t(q.pstride) * 4);
-  q.off_thr = take(thr ? size_t(q.npix) * 8 : 0);
+  q.off_thr = take(thr ? size_t(q.npix) * 16 : 0);
   // early termination: per pixel the first hit it skipped, for the backward
   q.off_stop = take(q.estop ? size_t(q.npix) * 8 : 0);
   q.off_mlist = take(size_t(q.T) * 4);
@@ -456,6 +456,7 @@ static int bwd_impl(const pulsar_scene_t* scenes, int32_t B, const float* pos,
   a.paper_norm = paper_norm;
   a.min_radius_px = params->min_radius_px;
   a.eps2 = sc[0].bc.eps2;
+  a.rebinned = rebin;
   hipError_t e = launch_backward(q, a, static_cast<char*>(ws), static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return fail_hip(e);
   return PULSAR_OK;

@@ -143,7 +143,7 @@ struct Plan {
   // the work list uint4 (tile | kFirstChunk, begin, end, slot or kNoSlot);
   // block sums of the chunk scan; the partial blend states; the per-pixel
   // K-th nearest hit (t, sphere id); background-gradient block sums
-  size_t off_tinfo, off_desc, off_pstate, off_thr, off_bgsum;
+  size_t off_tinfo, off_desc, off_pstate, off_thr, off_bgsum;  // off_thr: [npix] float4
   size_t off_mlist;  // tiles with several work items, for the merge kernel
   size_t off_scenes, off_starts;  // scene table and its start arrays
   // backward: one sum slot per (tile, sphere) pair at its emission position,
@@ -210,6 +210,9 @@ struct BwdArgs {
   bool paper_norm;  // per-pixel averaging and the 3-pixel position gate
   float min_radius_px;
   float eps2;  // eps / gamma * log2(e), the background exponent (camera independent)
+  // the thresholds were rebuilt by the backward (their stored L is that of
+  // the full blend, which differs from the caller's under the top-K blend)
+  bool rebinned;
 };
 
 // Enqueue the forward / backward pipelines. The forward first copies the

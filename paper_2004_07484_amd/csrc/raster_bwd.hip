@@ -37,7 +37,7 @@ struct BwdKernelArgs {
   const float* image;
   const float* aux;
   const float* grad_image;
-  const float2* thr;
+  const float4* thr;  // per pixel: K-th nearest hit (t, sphere index), L, 0
   float4* pslot;        // per-pair sum slots at emission positions, ps4 float4 each
   int ps4;
   const uint32_t* svals;  // sphere index of every sorted pair
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
                                                     : size_t(ts.ty0) * size_t(cam.W) +
                                                           size_t(ts.tx0));
       const float aux = A.aux[p];
-      const float2 th = A.thr[p];
+      const float4 th = A.thr[p];
       if (ES) {
         const float2 st = A.stop[p];
         s_sk[tid] = inside ? (uint64_t(__float_as_uint(st.x)) << 32) | __float_as_uint(st.y) : 0ull;
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(kWave) void k_bwd_chunks_wide(BwdKernelArgs A,
     __syncthreads();
     store_ray(s_ray, lane, make_ray(cam, px, py));
     s_L2[lane] = L2;
-    const float2 th = inside ? A.thr[p] : make_float2(-INFINITY, 0.f);
+    const float4 th = inside ? A.thr[p] : make_float4(-INFINITY, 0.f, 0.f, 0.f);
     s_tk[lane] = th.x;
     s_ik[lane] = __float_as_uint(th.y);
     if (A.stop) {
@@ -672,7 +672,8 @@ struct BwdSphArgs {
   const float* image;
   const float* aux;
   const float* grad_image;
-  const float2* thr;
+  const float4* thr;  // per pixel: K-th nearest hit (t, sphere index), L, 0
+  int l_in_thr;       // thr holds the image's L (else it is read from aux)
   // early termination: each sphere's earliest possible hit distance and per
   // pixel the first hit the forward skipped (hits from it on take no part)
   const float* tmin;
@@ -713,8 +714,10 @@ __device__ __forceinline__ void sphere_pixel_terms(const BwdSphArgs& A, const Ca
                                                    uint32_t sph, float tmin, int px, int py,
                                                    float (&v)[7 + CM]) {
   const size_t p = size_t(pix_off) + size_t(py) * size_t(cam.W) + size_t(px);
-  const float2 th = A.thr[p];
-  const float aux = A.aux[p];
+  // the K-th nearest hit and L in one record (after a rebuild of the
+  // thresholds, L from the caller's image)
+  const float4 th = A.thr[p];
+  const float aux = A.l_in_thr ? th.z : A.aux[p];
   float2 st = make_float2(0.f, 0.f);
   if (ES) st = A.stop[p];
   // behind the pixel's K-th nearest hit: no gradient, no test needed
@@ -1392,7 +1395,7 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
   A.image = a.image;
   A.aux = a.aux;
   A.grad_image = a.grad_image;
-  A.thr = ws_ptr<float2>(ws, q.off_thr);
+  A.thr = ws_ptr<float4>(ws, q.off_thr);
   A.pslot = ws_ptr<float4>(ws, q.off_pslot);
   A.ps4 = q.bwd_ps4;
   A.svals = ws_ptr<uint32_t>(ws, q.off_vals);
@@ -1465,6 +1468,7 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
     S.aux = a.aux;
     S.grad_image = a.grad_image;
     S.thr = A.thr;
+    S.l_in_thr = a.rebinned ? 0 : 1;
     S.tmin = A.tmin;
     S.stop = A.stop;
     S.grad_pos = a.grad_pos;

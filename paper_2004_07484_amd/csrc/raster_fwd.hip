@@ -110,7 +110,7 @@ struct FwdKernelArgs {
   const float* bg;      // [B, C]
   float* image;
   float* aux;
-  float2* thr;
+  float4* thr;  // per pixel: K-th nearest hit (t, sphere index), L of the image, 0
   float* pstate;
   long long pcap;
   int C, c0, cn, K, pstride, kfield;  // kfield: first K-list field of a partial state
@@ -141,13 +141,18 @@ __device__ __forceinline__ void write_pixel(const FwdKernelArgs& A, const CamDev
 #pragma unroll
   for (int c = 0; c < CM; ++c)
     if (c < A.cn) A.image[p * size_t(A.C) + A.c0 + c] = N[c] * invD;
-  if (A.c0 == 0 && A.aux) A.aux[p] = (m2 + fast_log2(D)) * 0.69314718055994531f;
+  const float L = (m2 + fast_log2(D)) * 0.69314718055994531f;
+  if (A.c0 == 0 && A.aux) A.aux[p] = L;
+  // the top-K blend's own L goes beside the thresholds its first pass left,
+  // so the record always holds the L of the image
+  if (A.c0 == 0 && A.topk && !A.track) reinterpret_cast<float*>(A.thr + p)[2] = L;
   if (A.track) {
-    // the K-th nearest hit, or (+inf, none) when the pixel has fewer than K
+    // the K-th nearest hit, or (+inf, none) when the pixel has fewer than K,
+    // with L: one 16-byte record per pixel for the backward's gathers
     const uint64_t k = kk[KM - 1];
-    A.thr[p] = k == kKeyNone ? make_float2(INFINITY, __uint_as_float(0xffffffffu))
-                             : make_float2(__uint_as_float(uint32_t(k >> 32)),
-                                           __uint_as_float(uint32_t(k)));
+    A.thr[p] = k == kKeyNone ? make_float4(INFINITY, __uint_as_float(0xffffffffu), L, 0.f)
+                             : make_float4(__uint_as_float(uint32_t(k >> 32)),
+                                           __uint_as_float(uint32_t(k)), L, 0.f);
     // the stored K nearest hits, nearest first (kKeyNone where fewer)
     if (A.hits) {
       uint2* hp = A.hits + p * size_t(A.K);
@@ -263,7 +268,7 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM, ES)) void k_fwd_c
     float tk = INFINITY;
     uint32_t ik = 0xffffffffu;
     if (A.topk && ray.px < cam.W && ray.py < cam.H) {
-      const float2 th = A.thr[size_t(sc.pix_off) + size_t(ray.py) * size_t(cam.W) +
+      const float4 th = A.thr[size_t(sc.pix_off) + size_t(ray.py) * size_t(cam.W) +
                               size_t(ray.px)];
       tk = th.x;
       ik = __float_as_uint(th.y);
@@ -596,7 +601,7 @@ static FwdKernelArgs raster_args(const Plan& q, const std::vector<SceneDev>& sce
   A.bg = a.bg;
   A.image = a.image;
   A.aux = a.aux;
-  A.thr = ws_ptr<float2>(ws, q.off_thr);
+  A.thr = ws_ptr<float4>(ws, q.off_thr);
   A.pstate = ws_ptr<float>(ws, q.off_pstate);
   A.pcap = q.pcap;
   A.C = a.C;

@@ -237,10 +237,12 @@ def test_tuning_knobs_keep_results(knob):
 
 
 @pytest.mark.parametrize("flags", [_capi.PULSAR_ORTHO, _capi.PULSAR_BLEND_TOPK,
-                                   _capi.PULSAR_ORTHO | _capi.PULSAR_BLEND_TOPK])
+                                   _capi.PULSAR_ORTHO | _capi.PULSAR_BLEND_TOPK,
+                                   _capi.PULSAR_BWD_TILES])
 def test_batched_variants_match_oracle(flags):
-    """The orthographic projection and the top-K blend in a batched call of
-    small scenes, against the oracle per scene."""
+    """The orthographic projection, the top-K blend and the tile-order
+    backward in a batched call of small scenes, against the oracle per
+    scene."""
     import copy
     ortho = bool(flags & _capi.PULSAR_ORTHO)
     topk = bool(flags & _capi.PULSAR_BLEND_TOPK)
