@@ -693,13 +693,14 @@ struct BwdSphArgs {
 };
 
 constexpr int kSphThreads = kFinThreads;
+constexpr int kSphPerLane = 1;  // spheres per lane of the sphere-order backward
 static_assert(kSphThreads == kBgThreads, "the background blocks share the launch");
 
-// Scene b owns blocks b + sph_off_b / kSphThreads onwards, as many as its
-// spheres need, so a block never spans two scenes (a block right after a
-// scene's last may have nothing to do).
-__device__ __forceinline__ uint32_t sph_first_block(const SceneDev& sc, int b) {
-  return uint32_t(b) + sc.sph_off / uint32_t(kSphThreads);
+// With `span` spheres per block, scene b owns blocks b + sph_off_b / span
+// onwards, as many as its spheres need, so a block never spans two scenes (a
+// block right after a scene's last may have nothing to do).
+__device__ __forceinline__ uint32_t sph_first_block(const SceneDev& sc, int b, uint32_t span) {
+  return uint32_t(b) + sc.sph_off / span;
 }
 
 // The terms of one (sphere, pixel) pair, added into v = (dL/dc, dL/dR, dL/do,
@@ -782,14 +783,19 @@ __device__ __forceinline__ void sphere_pixel_terms(const BwdSphArgs& A, const Ca
   for (int c = 0; c < CM; ++c) v[7 + c] += g.w * G[c];
 }
 
-template <int CM, bool CAM, bool ES>
+// SPL spheres per lane: a block covers SPL kSphThreads spheres, lane t of
+// wave w taking spheres t, t + kSphThreads, ... of it, and a wave's pairs are
+// flattened over its SPL 64 spheres at once.
+template <int CM, bool CAM, bool ES, int SPL>
 __global__ __launch_bounds__(kSphThreads) void k_bwd_spheres(BwdSphArgs A,
                                                              const SceneDev* __restrict__ scenes) {
   constexpr int NV = 7 + CM;                   // dL/dc (3), dL/dR, dL/do, dL/dkappa, count, dL/df
   constexpr int RW = 16 + CM + (ES ? 1 : 0);   // staged words per sphere: record, payload, t_min
   constexpr int RS = (RW + 3) & ~3;            // row stride in floats (16-byte rows)
-  static_assert(RS * kSphThreads >= kBgScratch, "the background sums fit the stage");
-  __shared__ float4 s_stage4[RS / 4 * kSphThreads];
+  constexpr int SB = SPL * kSphThreads;        // spheres per block
+  constexpr int NVL = SPL * kWave;             // a wave's spheres
+  static_assert(RS * SB >= kBgScratch, "the background sums fit the stage");
+  __shared__ float4 s_stage4[RS / 4 * SB];
   float* s_stage = reinterpret_cast<float*>(s_stage4);
   const int t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
   const uint32_t g = blockIdx.x;
@@ -802,98 +808,127 @@ __global__ __launch_bounds__(kSphThreads) void k_bwd_spheres(BwdSphArgs A,
   int lo = 0, hi = A.B - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (sph_first_block(scenes[mid], mid) <= g)
+    if (sph_first_block(scenes[mid], mid, SB) <= g)
       lo = mid;
     else
       hi = mid - 1;
   }
   const SceneDev& sc = scenes[lo];
-  const uint32_t local = g - sph_first_block(sc, lo);
-  if (local >= (sc.n + uint32_t(kSphThreads) - 1u) / uint32_t(kSphThreads)) return;  // whole block
-  const int i0 = int(sc.sph_off + local * uint32_t(kSphThreads));
-  const int nloc = int(min(uint32_t(kSphThreads), sc.sph_off + sc.n - uint32_t(i0)));
-  const bool valid = t < nloc;
-  const int i = valid ? i0 + t : i0;  // loads stay inside the arrays
+  const uint32_t local = g - sph_first_block(sc, lo, SB);
+  if (local >= (sc.n + uint32_t(SB) - 1u) / uint32_t(SB)) return;  // the whole block
+  const int i0 = int(sc.sph_off + local * uint32_t(SB));
+  const int nloc = int(min(uint32_t(SB), sc.sph_off + sc.n - uint32_t(i0)));
   const CamDev cam = sc.cam;
   const BlendConst bc = sc.bc;
   const unsigned long long pix_off = sc.pix_off;
   const int C = A.C;
-  // the sphere: its tile count (none after a capacity overflow, whose
-  // outputs are invalid anyway), then the record and payload row of a
-  // visible sphere (an invisible one has no record; most spheres of a
-  // scene can be invisible, and skipping their reads saves more than the
-  // extra round trip costs)
-  uint32_t count = A.counts[i];
-  count = (valid && A.status->code == 0u) ? count : 0u;
-  float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra, rc = ra, rd = ra;
-  float f[CM];
+  const bool ok = A.status->code == 0u;
+  // the spheres: their tile counts (none after a capacity overflow, whose
+  // outputs are invalid anyway), then the record and payload row of each
+  // visible one (an invisible sphere has no record; most spheres of a scene
+  // can be invisible, and skipping their reads saves more than the extra
+  // round trip costs), staged in LDS
+  uint32_t count[SPL];
 #pragma unroll
-  for (int c = 0; c < CM; ++c) f[c] = 0.f;
-  float tm = 0.f;
-  if (count != 0u) {
-    const float4* rp = A.rec + size_t(A.rec4) * size_t(i);
-    ra = rp[0];
-    rb = rp[1];
-    rc = rp[2];
-    rd = rp[3];
-    if (A.pay4) {
-      const float4* f4 = reinterpret_cast<const float4*>(A.payload + size_t(i) * size_t(C));
-#pragma unroll
-      for (int q = 0; q < (CM + 3) / 4; ++q) {
-        const float4 v = f4[min(q, C / 4 - 1)];
-        const float va[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          if (4 * q + u < CM) f[4 * q + u] = va[u];
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < CM; ++c) f[c] = A.payload[size_t(i) * size_t(C) + size_t(min(c, C - 1))];
-    }
-    if (ES) tm = A.tmin[i];
+  for (int u = 0; u < SPL; ++u) {
+    const int ts = u * kSphThreads + t;
+    count[u] = A.counts[ts < nloc ? i0 + ts : i0];
+    count[u] = (ts < nloc && ok) ? count[u] : 0u;
   }
-  float* my = s_stage + t * RS;
-  reinterpret_cast<float4*>(my)[0] = ra;
-  reinterpret_cast<float4*>(my)[1] = rb;
-  reinterpret_cast<float4*>(my)[2] = rc;
-  reinterpret_cast<float4*>(my)[3] = rd;
+  uint32_t npx[SPL];
 #pragma unroll
-  for (int c = 0; c < CM; ++c) my[16 + c] = c < C ? f[c] : 0.f;
-  if (ES) my[16 + CM] = tm;
-  const uint32_t p0 = __float_as_uint(ra.w), p1 = __float_as_uint(rd.z);
-  const uint32_t npx = count != 0u ? ((p1 & 0xffffu) - (p0 & 0xffffu) + 1u) *
-                                         ((p1 >> 16) - (p0 >> 16) + 1u)
-                                   : 0u;
+  for (int u = 0; u < SPL; ++u) {
+    const int ts = u * kSphThreads + t;
+    const int i = ts < nloc ? i0 + ts : i0;
+    float4 ra = make_float4(0.f, 0.f, 0.f, 0.f), rb = ra, rc = ra, rd = ra;
+    float f[CM];
+#pragma unroll
+    for (int c = 0; c < CM; ++c) f[c] = 0.f;
+    float tm = 0.f;
+    if (count[u] != 0u) {
+      const float4* rp = A.rec + size_t(A.rec4) * size_t(i);
+      ra = rp[0];
+      rb = rp[1];
+      rc = rp[2];
+      rd = rp[3];
+      if (A.pay4) {
+        const float4* f4 = reinterpret_cast<const float4*>(A.payload + size_t(i) * size_t(C));
+#pragma unroll
+        for (int q = 0; q < (CM + 3) / 4; ++q) {
+          const float4 v = f4[min(q, C / 4 - 1)];
+          const float va[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+          for (int w = 0; w < 4; ++w)
+            if (4 * q + w < CM) f[4 * q + w] = va[w];
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < CM; ++c)
+          f[c] = A.payload[size_t(i) * size_t(C) + size_t(min(c, C - 1))];
+      }
+      if (ES) tm = A.tmin[i];
+    }
+    float* my = s_stage + ts * RS;
+    reinterpret_cast<float4*>(my)[0] = ra;
+    reinterpret_cast<float4*>(my)[1] = rb;
+    reinterpret_cast<float4*>(my)[2] = rc;
+    reinterpret_cast<float4*>(my)[3] = rd;
+#pragma unroll
+    for (int c = 0; c < CM; ++c) my[16 + c] = c < C ? f[c] : 0.f;
+    if (ES) my[16 + CM] = tm;
+    const uint32_t p0 = __float_as_uint(ra.w), p1 = __float_as_uint(rd.z);
+    npx[u] = count[u] != 0u ? ((p1 & 0xffffu) - (p0 & 0xffffu) + 1u) *
+                                  ((p1 >> 16) - (p0 >> 16) + 1u)
+                            : 0u;
+  }
   // each wave reads only its own rows of the stage: a wave-level barrier
   // (LDS operations of one wave complete in order)
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  // this wave's pairs: lane l's sphere owns pairs start .. start + npx - 1
-  const uint32_t incl = wave_incl_scan_u32(npx, lane);
-  const uint32_t total = __builtin_amdgcn_readlane(incl, kWave - 1);
-  const uint32_t start = incl - npx;
-  const float* wstage = s_stage + size_t(wv) * kWave * RS;
-  float acc[NV];
+  // this wave's pairs: sphere v = u 64 + lane owns pairs start[u] ..
+  // start[u] + npx[u] - 1 (all of slot 0's spheres, then slot 1's, ...)
+  uint32_t incl[SPL], start[SPL];
+  uint32_t total = 0;
 #pragma unroll
-  for (int q = 0; q < NV; ++q) acc[q] = 0.f;
+  for (int u = 0; u < SPL; ++u) {
+    incl[u] = total + wave_incl_scan_u32(npx[u], lane);
+    start[u] = incl[u] - npx[u];
+    total = __builtin_amdgcn_readlane(incl[u], kWave - 1);
+  }
+  // a wave-level value of sphere v (v < NVL) from its lane
+  auto at_sphere = [&](const uint32_t (&x)[SPL], int v) {
+    uint32_t r = 0;
+#pragma unroll
+    for (int u = 0; u < SPL; ++u) {
+      const uint32_t y = __shfl(x[u], v & (kWave - 1), kWave);
+      r = (v >> 6) == u ? y : r;
+    }
+    return r;
+  };
+  float acc[SPL][NV];
+#pragma unroll
+  for (int u = 0; u < SPL; ++u)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[u][q] = 0.f;
   for (uint32_t pb = 0; pb < total; pb += kWave) {
     const uint32_t j = pb + uint32_t(lane);
     const bool act = j < total;
-    // the pair's sphere: the number of lanes whose pairs end at or before it
+    // the pair's sphere: the number of spheres whose pairs end at or before it
     int o = 0;
 #pragma unroll
-    for (int step = kWave / 2; step > 0; step >>= 1) {
-      const uint32_t e = __shfl(incl, o + step - 1, kWave);
+    for (int step = NVL / 2; step > 0; step >>= 1) {
+      const uint32_t e = at_sphere(incl, o + step - 1);
       if (e <= j) o += step;
     }
-    o = min(o, kWave - 1);  // lanes past the end
-    const uint32_t ostart = __shfl(start, o, kWave);
+    o = min(o, NVL - 1);  // lanes past the end
+    const uint32_t ostart = at_sphere(start, o);
+    const int orow = (o >> 6) * kSphThreads + wv * kWave + (o & (kWave - 1));
     float v[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) v[q] = 0.f;
     if (act) {
-      const float* r = wstage + o * RS;
+      const float* r = s_stage + orow * RS;
       const float4 a = reinterpret_cast<const float4*>(r)[0];
       const float4 b = reinterpret_cast<const float4*>(r)[1];
       const float4 c = reinterpret_cast<const float4*>(r)[2];
@@ -908,12 +943,12 @@ __global__ __launch_bounds__(kSphThreads) void k_bwd_spheres(BwdSphArgs A,
       const uint32_t k = j - ostart;
       const uint32_t yy = k / w;
       const int px = s.x0 + int(k - yy * w), py = s.y0 + int(yy);
-      sphere_pixel_terms<CM, CAM, ES>(A, cam, bc, pix_off, s, fo,
-                                      uint32_t(i0 + wv * kWave + o), to, px, py, v);
+      sphere_pixel_terms<CM, CAM, ES>(A, cam, bc, pix_off, s, fo, uint32_t(i0 + orow), to, px,
+                                      py, v);
     }
     // segmented inclusive scan over the lanes: a lane adds the partial sum of
     // the lane `off` below while both belong to the same sphere
-    const uint32_t key = act ? uint32_t(o) : uint32_t(kWave + lane);
+    const uint32_t key = act ? uint32_t(o) : uint32_t(NVL + lane);
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
       const uint32_t ku = __shfl_up(key, off, kWave);
@@ -925,41 +960,50 @@ __global__ __launch_bounds__(kSphThreads) void k_bwd_spheres(BwdSphArgs A,
       }
     }
     // each sphere takes the sum at the last lane of its run in this round
-    const bool has = npx != 0u && start < pb + kWave && start + npx > pb;
-    const int tail = has ? int(min(start + npx, pb + kWave) - 1u - pb) : lane;
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      const float x = __shfl(v[q], tail, kWave);
-      acc[q] = has ? acc[q] + x : acc[q];
+    for (int u = 0; u < SPL; ++u) {
+      const bool has = npx[u] != 0u && start[u] < pb + kWave && start[u] + npx[u] > pb;
+      const int tail = has ? int(min(start[u] + npx[u], pb + kWave) - 1u - pb) : lane;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const float x = __shfl(v[q], tail, kWave);
+        acc[u][q] = has ? acc[u][q] + x : acc[u][q];
+      }
     }
   }
-  // the sphere's outputs, each lane its own rows (a wave's position rows are
+  // the spheres' outputs, each lane its own rows (a wave's position rows are
   // one run of 768 bytes, its payload rows one of 256 C bytes)
-  if (!valid) return;
-  const SphereGrad o = sphere_grad(i, count, make_float4(acc[0], acc[1], acc[2], acc[3]), acc[4],
-                                   acc[5], acc[6], cam, A.pos, A.radius, A.min_radius_px,
-                                   A.grad_radius, A.grad_opacity, A.camg, A.paper_norm,
-                                   A.grad_pos != nullptr);
-  if (A.grad_pos) {
-    A.grad_pos[3 * size_t(i) + 0] = o.gx;
-    A.grad_pos[3 * size_t(i) + 1] = o.gy;
-    A.grad_pos[3 * size_t(i) + 2] = o.gz;
-  }
-  if (A.grad_payload) {
-    float* gp = A.grad_payload + size_t(i) * size_t(C);
-    if (A.gpay4) {
 #pragma unroll
-      for (int q = 0; q < (CM + 3) / 4; ++q)
-        if (4 * q < C)
-          reinterpret_cast<float4*>(gp)[q] =
-              make_float4(acc[7 + min(4 * q, CM - 1)] * o.scale,
-                          acc[7 + min(4 * q + 1, CM - 1)] * o.scale,
-                          acc[7 + min(4 * q + 2, CM - 1)] * o.scale,
-                          acc[7 + min(4 * q + 3, CM - 1)] * o.scale);
-    } else {
+  for (int u = 0; u < SPL; ++u) {
+    const int ts = u * kSphThreads + t;
+    if (ts >= nloc) continue;
+    const int i = i0 + ts;
+    const SphereGrad o = sphere_grad(i, count[u], make_float4(acc[u][0], acc[u][1], acc[u][2],
+                                                              acc[u][3]),
+                                     acc[u][4], acc[u][5], acc[u][6], cam, A.pos, A.radius,
+                                     A.min_radius_px, A.grad_radius, A.grad_opacity, A.camg,
+                                     A.paper_norm, A.grad_pos != nullptr);
+    if (A.grad_pos) {
+      A.grad_pos[3 * size_t(i) + 0] = o.gx;
+      A.grad_pos[3 * size_t(i) + 1] = o.gy;
+      A.grad_pos[3 * size_t(i) + 2] = o.gz;
+    }
+    if (A.grad_payload) {
+      float* gp = A.grad_payload + size_t(i) * size_t(C);
+      if (A.gpay4) {
 #pragma unroll
-      for (int c = 0; c < CM; ++c)
-        if (c < C) gp[c] = acc[7 + c] * o.scale;
+        for (int q = 0; q < (CM + 3) / 4; ++q)
+          if (4 * q < C)
+            reinterpret_cast<float4*>(gp)[q] =
+                make_float4(acc[u][7 + min(4 * q, CM - 1)] * o.scale,
+                            acc[u][7 + min(4 * q + 1, CM - 1)] * o.scale,
+                            acc[u][7 + min(4 * q + 2, CM - 1)] * o.scale,
+                            acc[u][7 + min(4 * q + 3, CM - 1)] * o.scale);
+      } else {
+#pragma unroll
+        for (int c = 0; c < CM; ++c)
+          if (c < C) gp[c] = acc[u][7 + c] * o.scale;
+      }
     }
   }
 }
@@ -1257,11 +1301,11 @@ template <int CM, bool CAM>
 static void launch_spheres_cam(const BwdSphArgs& S, unsigned grid, const SceneDev* scenes,
                                hipStream_t stream) {
   if (S.stop)
-    hipLaunchKernelGGL((k_bwd_spheres<CM, CAM, true>), dim3(grid), dim3(kSphThreads), 0, stream,
-                       S, scenes);
+    hipLaunchKernelGGL((k_bwd_spheres<CM, CAM, true, kSphPerLane>), dim3(grid),
+                       dim3(kSphThreads), 0, stream, S, scenes);
   else
-    hipLaunchKernelGGL((k_bwd_spheres<CM, CAM, false>), dim3(grid), dim3(kSphThreads), 0, stream,
-                       S, scenes);
+    hipLaunchKernelGGL((k_bwd_spheres<CM, CAM, false, kSphPerLane>), dim3(grid),
+                       dim3(kSphThreads), 0, stream, S, scenes);
 }
 
 template <int CM>
@@ -1479,8 +1523,9 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
     S.min_radius_px = a.min_radius_px;
     S.paper_norm = a.paper_norm ? 1 : 0;
     S.B = q.B;
-    // scene b's blocks start at b + sph_off_b / kSphThreads
-    S.nsph_blocks = uint32_t(q.B + (q.n + kSphThreads - 1) / kSphThreads);
+    // scene b's blocks start at b + sph_off_b / (spheres per block)
+    constexpr int64_t sb = int64_t(kSphPerLane) * kSphThreads;
+    S.nsph_blocks = uint32_t(q.B + (q.n + sb - 1) / sb);
     S.tab = tab;
     S.bgsum = a.grad_bg ? bgsum : nullptr;
     S.eps2 = a.eps2;
