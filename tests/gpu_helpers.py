@@ -166,12 +166,18 @@ def gpu_render_batch(workloads, params, Gs=None, depth_bits=0, chunk=0, raster_b
     return outs
 
 
+# Camera gradients are sums over every hit of terms of both signs (the
+# derivative of the image with respect to the camera, Sec. 3.1, adds each
+# hit's dL/dc p^T, dL/dc and dL/dkappa): a value can cancel to far below its
+# terms, so its scale is the larger of |ref| and this fraction of the sum of
+# the absolute values of its terms.
+CAMERA_FLOOR = 1e-4
+
+
 def assert_camera_close(got, ref, ref_abs, what, rel=GRAD_REL):
-    """Camera gradients are sums over every hit of terms of both signs: the
-    scale of each value is the larger of |ref| and 1e-2 of the sum of the
-    absolute values of its terms."""
+    """|got - ref| <= rel max(|ref|, CAMERA_FLOOR sum of |terms|), per value."""
     got = np.asarray(got, np.float64)
-    scale = np.maximum(np.abs(ref), FLOOR * np.asarray(ref_abs, np.float64))
+    scale = np.maximum(np.abs(ref), CAMERA_FLOOR * np.asarray(ref_abs, np.float64))
     err = np.abs(got - ref) / np.maximum(scale, 1e-300)
     assert np.all(err <= rel), f"{what}: worst {err.max():.3g} at {int(err.argmax())}: " \
         f"got {got.tolist()} ref {np.asarray(ref).tolist()}"
