@@ -211,10 +211,41 @@ __device__ __forceinline__ void fill_background_tile(const FwdKernelArgs& A, uin
         A.eps2 * 0.69314718055994531f;
 }
 
-// Empty-tile fill as a launch of its own: one wave per tile.
-__global__ __launch_bounds__(256) void k_fwd_background(FwdKernelArgs A) {
-  const uint32_t tile = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
-  if (tile < A.T && A.tinfo[tile].y == 0u) fill_background_tile(A, tile, threadIdx.x % kWave);
+// Empty-tile fill as a launch of its own (when the work-item grid has more
+// than a few tiles per block, as in large batches): a block per
+// kBgBlockPixels consecutive pixels of one scene (the background-gradient
+// blocks), a thread per pixel, so consecutive threads write consecutive
+// pixels; a pixel is written when its tile holds no pair.
+constexpr int kBgFillThreads = 256;
+__global__ __launch_bounds__(kBgFillThreads) void k_fwd_background(FwdKernelArgs A) {
+  const uint32_t blk = blockIdx.x;
+  const int b = find_scene(A.tab.blk_start, A.tab.B, blk);
+  const SceneDev& sc = A.tab.scenes[b];
+  const uint32_t W = uint32_t(sc.cam.W);
+  const uint32_t npix = W * uint32_t(sc.cam.H);  // at most 65535^2 < 2^32
+  const uint32_t p0 = (blk - sc.bgblk_off) * uint32_t(kBgBlockPixels);
+  const uint32_t np = min(uint32_t(kBgBlockPixels), npix - p0);
+  // the block's first pixel's row and column; each thread then steps along
+  // the row (a division by W once per block, not per pixel)
+  const uint32_t y0 = p0 / W, x0 = p0 - y0 * W;
+  const float inv_w = 1.f / float(W);
+  const uint32_t tiles_x = uint32_t(sc.cam.tiles_x);
+  const int C = A.C;
+  const float* bg = A.bg + size_t(b) * size_t(C);
+  for (uint32_t k = threadIdx.x; k < np; k += kBgFillThreads) {
+    // row offset of pixel p0 + k: floor((x0 + k) / W), exact after one correction
+    const uint32_t xk = x0 + k;
+    uint32_t dy = uint32_t(float(xk) * inv_w);
+    if (dy * W > xk) --dy;
+    if ((dy + 1u) * W <= xk) ++dy;
+    const uint32_t x = xk - dy * W, y = y0 + dy;
+    const uint32_t tile = sc.tile_off + (y / kTileH) * tiles_x + x / kTileW;
+    if (A.tinfo[tile].y != 0u) continue;
+    const size_t p = size_t(sc.pix_off) + size_t(p0 + k);
+    float* row = A.image + p * size_t(C);
+    for (int c = A.c0; c < A.c0 + A.cn; ++c) row[c] = bg[c];
+    if (A.c0 == 0 && A.aux) A.aux[p] = A.eps2 * 0.69314718055994531f;
+  }
 }
 
 // Up to 8 channels and an 8-entry K-list the work-item kernel fits 128 VGPRs
@@ -556,7 +587,8 @@ static void launch_raster_fwd_cm(const Plan& q, const FwdKernelArgs& A, hipStrea
     hipLaunchKernelGGL((k_fwd_chunks<CM, KM, false>), dim3(unsigned(q.raster_grid)), dim3(kWave),
                        0, stream, A, A.tab.scenes, A.tab.tile_start, A.desc);
   if (!A.fill_in_tail && A.image)
-    hipLaunchKernelGGL(k_fwd_background, dim3(unsigned((q.T + 3) / 4)), dim3(256), 0, stream, A);
+    hipLaunchKernelGGL(k_fwd_background, dim3(unsigned(q.nbgblk)), dim3(kBgFillThreads), 0,
+                       stream, A);
   stage_end(PULSAR_STAGE_RASTER_FWD, stream);
   stage_begin(PULSAR_STAGE_MERGE, stream);
   // merge tiles are a minority of the tiles; a grid of at most kMergeGrid
