@@ -125,14 +125,15 @@ typedef struct pulsar_camera {
  *   PULSAR_ERR_INVALID_ARGUMENT.
  * PULSAR_BWD_TILES: the backward walks the forward's tile lists (a block per
  *   work item, one thread per (tile, sphere) pair, each pair's sums in a slot
- *   of its own, then a pass per sphere over its slots) instead of the
- *   default walk in sphere order (a thread per sphere whose pixels are
- *   shared out over the lanes of its wave, which needs no slots and no
- *   second pass). Both compute the same terms and differ only in summation
- *   order; the tile walk suits scenes whose spheres cover very many pixels
- *   each. Forward and backward must both set it (the workspace holds the
- *   slots only then). The stored-hits backward and payloads of more than 32
- *   channels always use slots. */
+ *   of its own, then a pass per sphere over its slots). Without it the
+ *   backward walks the spheres in index order (a thread per sphere whose
+ *   pixels are shared out over the lanes of its wave, no slots, no second
+ *   pass), unless the forward met a sphere touching more than 16 tiles:
+ *   that decision is taken on the device and the tile walk runs instead, as
+ *   the walk in sphere order would give all of that sphere's pixels to one
+ *   wave. Both walks compute the same terms and differ only in summation
+ *   order. The stored-hits backward and payloads of more than 32 channels
+ *   always use slots. */
 #define PULSAR_NO_BWD_AUX 0x1u
 #define PULSAR_REBIN 0x2u
 #define PULSAR_GRAD_PAPER_NORM 0x4u

@@ -40,7 +40,7 @@ PULSAR_GRAD_PAPER_NORM = 0x4  # per-pixel averaged gradients, 3-pixel position g
 PULSAR_BLEND_TOPK = 0x8   # blend only each pixel's K nearest hits
 PULSAR_ORTHO = 0x10       # orthographic projection
 PULSAR_STORE_HITS = 0x20  # forward stores each pixel's K nearest hits for the backward
-PULSAR_BWD_TILES = 0x40   # backward walks the tile lists (per-pair slots) instead of the spheres
+PULSAR_BWD_TILES = 0x40   # backward always walks the tile lists (per-pair slots)
 PULSAR_MIN_RADIUS_PX_PAPER = 0.70710678  # every sphere covers a pixel centre
 PULSAR_MAX_SCENES = 4096
 

@@ -84,6 +84,7 @@ struct EmitArgs {
   unsigned long long* ebase;  // [nblk + 1] first pair of each emission block
   uint32_t* mat;              // [2^digit_bits][nblk] first digit's counts
   uint2* trange;              // [T] cleared here for k_ranges
+  Status* status;             // big_spheres set here
 };
 
 // Block b covers spheres b S .. b S + S - 1 (S = rounds kEmitRound) in rounds
@@ -129,6 +130,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs A) {
       c[2] = i0 + 2 < A.n ? c4.z : 0u;
       c[3] = i0 + 3 < A.n ? c4.w : 0u;
     }
+    if (max(max(c[0], c[1]), max(c[2], c[3])) > kBigTiles) atomicOr(&A.status->big_spheres, 1u);
     if (r == 0) {
       // the pairs of every projection block before this emission block
       unsigned long long pre = 0;
@@ -580,6 +582,7 @@ void launch_binning(const Plan& q, char* ws, hipStream_t stream) {
   E.ebase = ws_ptr<unsigned long long>(ws, q.off_ebase);
   E.mat = ws_ptr<uint32_t>(ws, q.off_mat);
   E.trange = ws_ptr<uint2>(ws, q.off_trange);
+  E.status = status;
   hipLaunchKernelGGL(k_emit, dim3(unsigned(q.nblk_emit)), dim3(kEmitThreads), 0, stream, E);
   for (int p = 0; p < q.sort_passes; ++p) {
     SortArgs S;

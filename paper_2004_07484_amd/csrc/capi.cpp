@@ -249,14 +249,12 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   q.ncampart = int64_t(q.B) + n / kCamSpan + 1;
   q.off_camg = take(bwd ? nn * 16 : 0);
   q.off_campart = take(bwd ? size_t(q.ncampart) * 16 * 8 : 0);
-  // per-pair slots: only the backward passes that gather through them (the
-  // tile walk, the stored hits, wide payloads) need them. They come after
-  // everything the forward writes, so a forward planned without them leaves
-  // the same state for a backward that has them (given the larger workspace).
+  // per-pair slots for the backward passes that gather through them (the
+  // tile walk, which the default backward also takes for scenes with very
+  // large spheres, the stored hits, wide payloads). They come after
+  // everything the forward writes.
   q.bwd_tiles = (p->flags & PULSAR_BWD_TILES) != 0u ? 1 : 0;
-  const bool slots = bwd && (q.bwd_tiles || (p->flags & PULSAR_STORE_HITS) != 0u ||
-                             C > kBwdChannels);
-  q.off_pslot = take(slots ? size_t(cap) * size_t(q.bwd_ps4) * 16 : 0);
+  q.off_pslot = take(bwd ? size_t(cap) * size_t(q.bwd_ps4) * 16 : 0);
   // the stored per-pixel K nearest hits come last, so every other offset is
   // the same with or without them
   q.K = p->K;

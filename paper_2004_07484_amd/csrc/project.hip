@@ -147,6 +147,8 @@ __global__ __launch_bounds__(kProjectBlock) void k_project(
   // float32 of that distance)
 #pragma clang fp contract(off)
   const int i = blockIdx.x * kProjectBlock + threadIdx.x;
+  // the emission that follows flags spheres wider than kBigTiles tiles
+  if (blockIdx.x == 0 && threadIdx.x == 0) status->big_spheres = 0u;
   if (inline_scenes && blockIdx.x == 0 && threadIdx.x < kWave) {
     const int k = threadIdx.x;
     const int B1 = u.B + 1;

@@ -33,6 +33,10 @@ constexpr int kUploadScenes = 12;            // scene descriptors per upload lau
 constexpr int kBgBlockPixels = 1024;         // pixels per background-gradient block
 constexpr int kCamSpan = 1024;               // spheres per camera-gradient partial sum
 constexpr int kRecPayload = 16;              // payload channels kept in the sphere record
+// a sphere touching more tiles than this sends the default backward to the
+// walk over the tile lists (the walk in sphere order would give all of its
+// pixels to one wave)
+constexpr uint32_t kBigTiles = 16;
 constexpr uint32_t kFirstChunk = 0x80000000u;  // work item flag: first chunk of its tile
 constexpr uint32_t kNoSlot = 0xffffffffu;      // work item writes final pixels, no partial state
 
@@ -47,7 +51,8 @@ struct Status {
   uint32_t nmerge;              // tiles with several work items
   uint32_t bad_cam;             // a camera read from device memory was invalid
   uint32_t hits_k;              // the forward stored K nearest hits per pixel (0: none)
-  uint32_t pad[54];
+  uint32_t big_spheres;         // a sphere touches more than kBigTiles tiles
+  uint32_t pad[53];
 };
 static_assert(sizeof(Status) == 256, "status block");
 static_assert(offsetof(Status, pairs) + sizeof(unsigned long long) == PULSAR_STATUS_BYTES,

@@ -57,6 +57,7 @@ struct BwdKernelArgs {
   const uint4* tinfo;  // per tile (first partial slot, work items)
   int K;
   uint32_t T;
+  int only_if_big;  // the tile walk runs only when the emission flagged a very large sphere
 };
 
 constexpr int kBgThreads = 256;
@@ -136,9 +137,10 @@ constexpr int bwd_waves_per_simd(int CM) { return CM <= 4 ? 5 : (CM <= 8 ? 4 : 1
 
 // ES: early termination (hits from each pixel's first skipped one on take no part).
 template <int CM, bool CAM, bool ES>
-__global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_bwd_items(
-    BwdKernelArgs A, const SceneDev* __restrict__ scenes, const uint32_t* __restrict__ tile_start,
-    const uint4* __restrict__ desc) {
+__device__ __forceinline__ void bwd_items_body(const BwdKernelArgs& A,
+                                               const SceneDev* __restrict__ scenes,
+                                               const uint32_t* __restrict__ tile_start,
+                                               const uint4* __restrict__ desc) {
   __shared__ TileRays s_ray;
   __shared__ float s_G[CM][kWave];
   __shared__ float s_L2[kWave], s_GF[kWave], s_tk[kWave];
@@ -288,6 +290,15 @@ __global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_b
   if (A.bgsum)
     for (uint32_t blk = blockIdx.x; blk < A.nbgblk; blk += gridDim.x)
       bg_partial_block(A.tab, A.aux, A.grad_image, C, A.eps2, A.bgsum, blk, s_bg);
+}
+
+template <int CM, bool CAM, bool ES>
+__global__ __launch_bounds__(kWave * kBwdWaves, bwd_waves_per_simd(CM)) void k_bwd_items(
+    BwdKernelArgs A, const SceneDev* __restrict__ scenes, const uint32_t* __restrict__ tile_start,
+    const uint4* __restrict__ desc) {
+  // beside the walk in sphere order: only for scenes with a very large sphere
+  if (A.only_if_big && A.status->big_spheres == 0u) return;
+  bwd_items_body<CM, CAM, ES>(A, scenes, tile_start, desc);
 }
 
 // Channels beyond the register budget: same walk, the pixel terms read from
@@ -535,49 +546,24 @@ __device__ __forceinline__ void write_sphere_grads(
   }
 }
 
-// K8 after the slot-based backward passes (the wide, stored-hits and
-// tile-order ones): per sphere, in sphere order, kFinThreads spheres per
-// block (a block is a projection block). The camera-space sums are the sum
-// of the sphere's pair slots sfirst .. sfirst + count - 1 (in that order;
-// none when it touches no tile). Blocks past the spheres sum the background
-// block sums, one block per (scene, channel); with nfin = 0 that is all the
-// launch does.
+// One projection block of K8 (every thread of the block calls it).
 template <int CM>
-__global__ __launch_bounds__(kFinThreads) void k_finalize(
-    int n, const uint32_t* __restrict__ counts, const unsigned long long* __restrict__ boff,
-    const Status* __restrict__ status, const float* __restrict__ pos,
-    const float* __restrict__ radius, SceneTable tab, float min_radius_px, int C,
-    const float4* __restrict__ pslot, int ps4, float* __restrict__ grad_pos,
-    float* __restrict__ grad_radius, float* __restrict__ grad_opacity,
-    float* __restrict__ grad_payload, uint32_t nfin, const float* __restrict__ bgsum,
-    float* __restrict__ grad_bg, float4* __restrict__ camg, int paper_norm) {
+__device__ __forceinline__ void finalize_block(
+    uint32_t sb, int t, int n, const uint32_t* __restrict__ counts,
+    const unsigned long long* __restrict__ boff, const Status* __restrict__ status,
+    const float* __restrict__ pos, const float* __restrict__ radius, const SceneTable& tab,
+    float min_radius_px, int C, const float4* __restrict__ pslot, int ps4,
+    float* __restrict__ grad_pos, float* __restrict__ grad_radius,
+    float* __restrict__ grad_opacity, float* __restrict__ grad_payload,
+    float4* __restrict__ camg, int paper_norm, float* s_gp, float* s_pay) {
   constexpr int CS = CM > 0 ? CM : 1;
-  __shared__ float s_gp[3 * kFinThreads];
-  __shared__ float s_pay[kFinThreads * CS];
-  const int t = threadIdx.x;
-  if (blockIdx.x >= nfin) {
-    const uint32_t k = blockIdx.x - nfin;
-    const int c = int(k % uint32_t(C)), b = int(k / uint32_t(C));
-    const uint32_t k0 = tab.blk_start[b], k1 = tab.blk_start[b + 1];
-    float acc = 0.f;
-    for (uint32_t j = k0 + t; j < k1; j += kFinThreads) acc += bgsum[size_t(j) * size_t(C) + c];
-    acc = wave_sum(acc);
-    __shared__ float s_red[kFinThreads / kWave];
-    if ((t & (kWave - 1)) == 0) s_red[t / kWave] = acc;
-    __syncthreads();
-    if (t == 0) {
-      float tsum = 0.f;
-      for (int w = 0; w < kFinThreads / kWave; ++w) tsum += s_red[w];
-      grad_bg[size_t(b) * size_t(C) + c] = tsum;
-    }
-    return;
-  }
-  const int i0 = blockIdx.x * kFinThreads;
+  __syncthreads();  // the previous block's readers of the LDS are done
+  const int i0 = int(sb) * kFinThreads;
   const int nloc = min(kFinThreads, n - i0);
   const int i = i0 + t;
   // the first slot: the projection block's first emission position plus the
-  // tile counts of the block's spheres before this one (the in-block prefix
-  // the projection computed; a block here is a projection block)
+  // tile counts of the block's spheres before this one (a block here is a
+  // projection block)
   static_assert(kFinThreads == kProjectBlock, "one finalize block per projection block");
   const uint32_t count = t < nloc ? counts[i] : 0u;
   __shared__ uint32_t s_wpre[kFinThreads / kWave];
@@ -588,7 +574,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
   uint32_t first = incl - count;
 #pragma unroll
   for (int w = 0; w < kFinThreads / kWave; ++w) first += w < wv ? s_wpre[w] : 0u;
-  const uint32_t base = count != 0u ? uint32_t(boff[blockIdx.x]) + first : 0u;
+  const uint32_t base = count != 0u ? uint32_t(boff[sb]) + first : 0u;
   float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
   float go = 0.f, gk = 0.f, npx = 0.f;
   float gf[CS];
@@ -639,6 +625,53 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(
                          s_gp, s_pay);
 }
 
+// K8 after the slot-based backward passes (the wide, stored-hits and
+// tile-order ones): per sphere, in sphere order, kFinThreads spheres (a
+// projection block) at a time, the first fin_grid blocks walking the nfin
+// projection blocks. The camera-space sums are the sum of the sphere's pair
+// slots sfirst .. sfirst + count - 1 (in that order; none when it touches no
+// tile). With only_if_big those blocks do nothing unless the backward took
+// the tile walk (a very large sphere). Blocks past them sum the background block
+// sums, one block per (scene, channel).
+template <int CM>
+__global__ __launch_bounds__(kFinThreads) void k_finalize(
+    int n, const uint32_t* __restrict__ counts, const unsigned long long* __restrict__ boff,
+    const Status* __restrict__ status, const float* __restrict__ pos,
+    const float* __restrict__ radius, SceneTable tab, float min_radius_px, int C,
+    const float4* __restrict__ pslot, int ps4, float* __restrict__ grad_pos,
+    float* __restrict__ grad_radius, float* __restrict__ grad_opacity,
+    float* __restrict__ grad_payload, uint32_t nfin, uint32_t fin_grid, int only_if_big,
+    const float* __restrict__ bgsum, float* __restrict__ grad_bg, float4* __restrict__ camg,
+    int paper_norm) {
+  constexpr int CS = CM > 0 ? CM : 1;
+  __shared__ float s_gp[3 * kFinThreads];
+  __shared__ float s_pay[kFinThreads * CS];
+  const int t = threadIdx.x;
+  if (blockIdx.x >= fin_grid) {
+    const uint32_t k = blockIdx.x - fin_grid;
+    const int c = int(k % uint32_t(C)), b = int(k / uint32_t(C));
+    const uint32_t k0 = tab.blk_start[b], k1 = tab.blk_start[b + 1];
+    float acc = 0.f;
+    for (uint32_t j = k0 + t; j < k1; j += kFinThreads) acc += bgsum[size_t(j) * size_t(C) + c];
+    acc = wave_sum(acc);
+    __shared__ float s_red[kFinThreads / kWave];
+    if ((t & (kWave - 1)) == 0) s_red[t / kWave] = acc;
+    __syncthreads();
+    if (t == 0) {
+      float tsum = 0.f;
+      for (int w = 0; w < kFinThreads / kWave; ++w) tsum += s_red[w];
+      grad_bg[size_t(b) * size_t(C) + c] = tsum;
+    }
+    return;
+  }
+  if (only_if_big && status->big_spheres == 0u) return;
+  for (uint32_t sb = blockIdx.x; sb < nfin; sb += fin_grid)
+    finalize_block<CM>(sb, t, n, counts, boff, status, pos, radius, tab, min_radius_px, C, pslot,
+                       ps4, grad_pos, grad_radius, grad_opacity, grad_payload, camg, paper_norm,
+                       s_gp, s_pay);
+}
+
+
 // ---------------------------------------------------------------- K7 by sphere
 // The default backward (up to kBwdChannels channels): one thread per sphere,
 // in sphere order, kSphThreads spheres of one scene per block. A sphere's
@@ -687,6 +720,7 @@ struct BwdSphArgs {
   int paper_norm;
   int B;
   uint32_t nsph_blocks;  // blocks of spheres; the blocks after them sum the background
+  uint32_t nbgblk;       // background-gradient blocks
   SceneTable tab;
   float* bgsum;  // background-gradient block sums, or null
   float eps2;
@@ -694,6 +728,8 @@ struct BwdSphArgs {
 
 constexpr int kSphThreads = kFinThreads;
 constexpr int kSphPerLane = 1;  // spheres per lane of the sphere-order backward
+constexpr uint32_t kFinGridAuto = 1024;  // K8 blocks for the tile walk beside the sphere walk
+constexpr long long kBwdGridAuto = 1024;  // tile-walk blocks beside the sphere walk
 static_assert(kSphThreads == kBgThreads, "the background blocks share the launch");
 
 // With `span` spheres per block, scene b owns blocks b + sph_off_b / span
@@ -787,8 +823,8 @@ __device__ __forceinline__ void sphere_pixel_terms(const BwdSphArgs& A, const Ca
 // wave w taking spheres t, t + kSphThreads, ... of it, and a wave's pairs are
 // flattened over its SPL 64 spheres at once.
 template <int CM, bool CAM, bool ES, int SPL>
-__global__ __launch_bounds__(kSphThreads) void k_bwd_spheres(BwdSphArgs A,
-                                                             const SceneDev* __restrict__ scenes) {
+__device__ __forceinline__ void bwd_spheres_body(const BwdSphArgs& A,
+                                                 const SceneDev* __restrict__ scenes) {
   constexpr int NV = 7 + CM;                   // dL/dc (3), dL/dR, dL/do, dL/dkappa, count, dL/df
   constexpr int RW = 16 + CM + (ES ? 1 : 0);   // staged words per sphere: record, payload, t_min
   constexpr int RS = (RW + 3) & ~3;            // row stride in floats (16-byte rows)
@@ -800,8 +836,9 @@ __global__ __launch_bounds__(kSphThreads) void k_bwd_spheres(BwdSphArgs A,
   const int t = threadIdx.x, lane = t & (kWave - 1), wv = t / kWave;
   const uint32_t g = blockIdx.x;
   if (g >= A.nsph_blocks) {
-    if (A.bgsum) bg_partial_block(A.tab, A.aux, A.grad_image, A.C, A.eps2, A.bgsum,
-                                  g - A.nsph_blocks, s_stage);
+    if (A.bgsum && g - A.nsph_blocks < A.nbgblk)
+      bg_partial_block(A.tab, A.aux, A.grad_image, A.C, A.eps2, A.bgsum, g - A.nsph_blocks,
+                       s_stage);
     return;
   }
   // the block's scene (uniform: its camera comes in through scalar loads)
@@ -1006,6 +1043,19 @@ __global__ __launch_bounds__(kSphThreads) void k_bwd_spheres(BwdSphArgs A,
       }
     }
   }
+}
+
+// The default backward launches both walks; each reads on the device whether
+// the emission found a sphere wider than kBigTiles tiles (whose pixels the
+// walk in sphere order would all give to one wave) and returns at once when
+// the other walk is the one to run, so one launch sequence (and one graph)
+// serves every scene. With such a sphere the walk over the tile lists runs,
+// and k_finalize adds its per-pair slots.
+template <int CM, bool CAM, bool ES, int SPL>
+__global__ __launch_bounds__(kSphThreads) void k_bwd_spheres(BwdSphArgs A,
+                                                             const SceneDev* __restrict__ scenes) {
+  if (A.status->big_spheres != 0u) return;
+  bwd_spheres_body<CM, CAM, ES, SPL>(A, scenes);
 }
 
 // The block sum for background block `blk`, by a whole block of kBgThreads
@@ -1297,6 +1347,19 @@ static void launch_items(const BwdKernelArgs& A, dim3 grid, dim3 block, hipStrea
     launch_items_es<CM, false>(A, grid, block, stream);
 }
 
+template <int CM>
+static void launch_finalize(const Plan& q, const BwdArgs& a, char* ws, hipStream_t stream,
+                            uint32_t nfin, uint32_t fin_grid, int only_if_big, uint32_t nred) {
+  hipLaunchKernelGGL((k_finalize<CM>), dim3(fin_grid + nred), dim3(kFinThreads), 0, stream,
+                     int(q.n), ws_ptr<uint32_t>(ws, q.off_counts),
+                     ws_ptr<unsigned long long>(ws, q.off_boff), ws_ptr<Status>(ws, q.off_status),
+                     a.pos, a.radius, scene_table(q, ws), a.min_radius_px, a.C,
+                     ws_ptr<float4>(ws, q.off_pslot), q.bwd_ps4, a.grad_pos, a.grad_radius,
+                     a.grad_opacity, a.grad_payload, nfin, fin_grid, only_if_big,
+                     ws_ptr<float>(ws, q.off_bgsum), a.grad_bg,
+                     a.grad_cam ? ws_ptr<float4>(ws, q.off_camg) : nullptr, a.paper_norm ? 1 : 0);
+}
+
 template <int CM, bool CAM>
 static void launch_spheres_cam(const BwdSphArgs& S, unsigned grid, const SceneDev* scenes,
                                hipStream_t stream) {
@@ -1315,17 +1378,6 @@ static void launch_spheres(const BwdSphArgs& S, bool cam, unsigned grid, const S
     launch_spheres_cam<CM, true>(S, grid, scenes, stream);
   else
     launch_spheres_cam<CM, false>(S, grid, scenes, stream);
-}
-
-template <int CM>
-static void launch_finalize(const Plan& q, const BwdArgs& a, char* ws, hipStream_t stream,
-                            uint32_t nfin, uint32_t nred) {
-  hipLaunchKernelGGL((k_finalize<CM>), dim3(nfin + nred), dim3(kFinThreads), 0, stream, int(q.n),
-                     ws_ptr<uint32_t>(ws, q.off_counts), ws_ptr<unsigned long long>(ws, q.off_boff), ws_ptr<Status>(ws, q.off_status), a.pos, a.radius, scene_table(q, ws),
-                     a.min_radius_px, a.C, ws_ptr<float4>(ws, q.off_pslot), q.bwd_ps4, a.grad_pos,
-                     a.grad_radius, a.grad_opacity, a.grad_payload, nfin,
-                     ws_ptr<float>(ws, q.off_bgsum), a.grad_bg,
-                     a.grad_cam ? ws_ptr<float4>(ws, q.off_camg) : nullptr, a.paper_norm ? 1 : 0);
 }
 
 // Camera gradients: dL/dR = sum_i dL/dc_i p_i^T, dL/dt = sum_i dL/dc_i and
@@ -1428,6 +1480,7 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
   const bool wide = a.C > kBwdChannels;
   const SceneTable tab = scene_table(q, ws);
   BwdKernelArgs A;
+  A.only_if_big = 0;
   A.tab = tab;
   A.status = ws_ptr<Status>(ws, q.off_status);
   A.desc = ws_ptr<uint4>(ws, q.off_desc);
@@ -1526,22 +1579,43 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
     // scene b's blocks start at b + sph_off_b / (spheres per block)
     constexpr int64_t sb = int64_t(kSphPerLane) * kSphThreads;
     S.nsph_blocks = uint32_t(q.B + (q.n + sb - 1) / sb);
+    S.nbgblk = uint32_t(q.nbgblk);
     S.tab = tab;
     S.bgsum = a.grad_bg ? bgsum : nullptr;
     S.eps2 = a.eps2;
     const unsigned grid = unsigned(S.nsph_blocks + (a.grad_bg ? uint32_t(q.nbgblk) : 0u));
+    const bool cam = a.grad_cam != nullptr;
     if (a.C <= 1)
-      launch_spheres<1>(S, a.grad_cam != nullptr, grid, tab.scenes, stream);
+      launch_spheres<1>(S, cam, grid, tab.scenes, stream);
     else if (a.C <= 2)
-      launch_spheres<2>(S, a.grad_cam != nullptr, grid, tab.scenes, stream);
+      launch_spheres<2>(S, cam, grid, tab.scenes, stream);
     else if (a.C <= 4)
-      launch_spheres<4>(S, a.grad_cam != nullptr, grid, tab.scenes, stream);
+      launch_spheres<4>(S, cam, grid, tab.scenes, stream);
     else if (a.C <= 8)
-      launch_spheres<8>(S, a.grad_cam != nullptr, grid, tab.scenes, stream);
+      launch_spheres<8>(S, cam, grid, tab.scenes, stream);
     else if (a.C <= 16)
-      launch_spheres<16>(S, a.grad_cam != nullptr, grid, tab.scenes, stream);
+      launch_spheres<16>(S, cam, grid, tab.scenes, stream);
     else
-      launch_spheres<32>(S, a.grad_cam != nullptr, grid, tab.scenes, stream);
+      launch_spheres<32>(S, cam, grid, tab.scenes, stream);
+    // the tile walk beside it, on a small persistent grid (it returns at once
+    // unless a very large sphere needs it)
+    BwdKernelArgs Ab = A;
+    Ab.only_if_big = 1;
+    const long long ig = q.raster_grid / kBwdWaves < kBwdGridAuto ? q.raster_grid / kBwdWaves
+                                                                    : kBwdGridAuto;
+    const dim3 igrid{unsigned(ig > 0 ? ig : 1), 1u, 1u}, iblock{unsigned(kWave * kBwdWaves), 1u, 1u};
+    if (a.C <= 1)
+      launch_items<1>(Ab, igrid, iblock, stream);
+    else if (a.C <= 2)
+      launch_items<2>(Ab, igrid, iblock, stream);
+    else if (a.C <= 4)
+      launch_items<4>(Ab, igrid, iblock, stream);
+    else if (a.C <= 8)
+      launch_items<8>(Ab, igrid, iblock, stream);
+    else if (a.C <= 16)
+      launch_items<16>(Ab, igrid, iblock, stream);
+    else
+      launch_items<32>(Ab, igrid, iblock, stream);
   } else {
     // as many waves as the forward's grid of one-wave blocks: blocks past the
     // work items would only be dispatched after them to find nothing to do
@@ -1573,24 +1647,27 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
       hipLaunchKernelGGL(k_bg_partial_wide, dim3(unsigned(q.nbgblk)), dim3(kBgThreads), 0,
                          stream, tab, a.aux, a.grad_image, int(q.C), a.eps2, bgsum);
   }
-  // after the walk in sphere order only the per-scene background sums remain
-  const uint32_t nfin = by_sphere ? 0u : uint32_t((q.n + kFinThreads - 1) / kFinThreads);
+  // after the walk in sphere order only the per-scene background sums remain;
+  // its per-sphere blocks (a grid of at most kFinGridAuto walking the
+  // spheres) then return at once
+  const uint32_t nfin = uint32_t((q.n + kFinThreads - 1) / kFinThreads);
+  const uint32_t fin_grid = by_sphere ? (nfin < kFinGridAuto ? nfin : kFinGridAuto) : nfin;
   const uint32_t nred = a.grad_bg ? uint32_t(q.C) * uint32_t(q.B) : 0u;
-  if (nfin + nred > 0) {
+  if (fin_grid + nred > 0) {
     if (a.C <= 1)
-      launch_finalize<1>(q, a, ws, stream, nfin, nred);
+      launch_finalize<1>(q, a, ws, stream, nfin, fin_grid, by_sphere ? 1 : 0, nred);
     else if (a.C <= 2)
-      launch_finalize<2>(q, a, ws, stream, nfin, nred);
+      launch_finalize<2>(q, a, ws, stream, nfin, fin_grid, by_sphere ? 1 : 0, nred);
     else if (a.C <= 4)
-      launch_finalize<4>(q, a, ws, stream, nfin, nred);
+      launch_finalize<4>(q, a, ws, stream, nfin, fin_grid, by_sphere ? 1 : 0, nred);
     else if (a.C <= 8)
-      launch_finalize<8>(q, a, ws, stream, nfin, nred);
+      launch_finalize<8>(q, a, ws, stream, nfin, fin_grid, by_sphere ? 1 : 0, nred);
     else if (a.C <= 16)
-      launch_finalize<16>(q, a, ws, stream, nfin, nred);
+      launch_finalize<16>(q, a, ws, stream, nfin, fin_grid, by_sphere ? 1 : 0, nred);
     else if (!wide)
-      launch_finalize<32>(q, a, ws, stream, nfin, nred);
+      launch_finalize<32>(q, a, ws, stream, nfin, fin_grid, by_sphere ? 1 : 0, nred);
     else
-      launch_finalize<0>(q, a, ws, stream, nfin, nred);
+      launch_finalize<0>(q, a, ws, stream, nfin, fin_grid, by_sphere ? 1 : 0, nred);
   }
   if (a.grad_cam) {
     hipLaunchKernelGGL(k_cam_partial, dim3(unsigned(q.ncampart)), dim3(kCamThreads), 0, stream,

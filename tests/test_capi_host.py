@@ -131,20 +131,24 @@ def test_known_flags_pass_validation():
             _capi.pulsar_workspace_size(10, 64, 64, 3, _capi.make_params())
 
 
-def test_pair_slots_only_for_the_backwards_that_use_them():
-    """The default backward (in sphere order) needs no per-pair slots; the
-    tile-order and stored-hits backwards and payloads wider than 32 channels
-    do, 16 bytes per float4 of a slot and pair."""
+def test_pair_slots_are_planned_for_every_backward():
+    """Every plan with backward state holds one gradient slot per pair (the
+    default backward may take the tile walk for scenes with very large
+    spheres, decided on the device), 16 bytes per float4 of a slot; the
+    stored hits come on top of that."""
     _lib()
     cap = 10**5
     plain = _capi.pulsar_workspace_size(1000, 64, 64, 3, _capi.make_params(max_pairs=cap))
+    small = _capi.pulsar_workspace_size(1000, 64, 64, 3, _capi.make_params(max_pairs=cap // 2))
     tiles = _capi.pulsar_workspace_size(1000, 64, 64, 3, _capi.make_params(
         max_pairs=cap, flags=_capi.PULSAR_BWD_TILES))
     store = _capi.pulsar_workspace_size(1000, 64, 64, 3, _capi.make_params(
         max_pairs=cap, flags=_capi.PULSAR_STORE_HITS))
-    # C = 3: a slot of two float4 (dL/dc, dL/dR | dL/df[4], dL/do, ...)
-    assert tiles - plain >= 32 * cap
-    assert store > tiles
+    # per pair: tile and sphere index twice (16 bytes) and a slot of two
+    # float4 at C = 3 (dL/dc, dL/dR | dL/df[4], dL/do, ...)
+    assert plain - small >= (16 + 32) * (cap - cap // 2)
+    assert tiles == plain
+    assert store > plain
     p = _capi.make_params(flags=_capi.PULSAR_BWD_TILES)
     assert _call_fwd(_cam(), p, ws_bytes=1024) == _capi.PULSAR_ERR_WORKSPACE
 

@@ -130,6 +130,27 @@ def test_tile_order_backward(case):
         _parity(wl, what=f"tiles: {case}", knobs=knobs)
 
 
+def test_large_spheres_take_the_tile_walk():
+    """Spheres wider than 16 tiles (their pixels would all fall to one wave
+    of the walk in sphere order): the default backward takes the walk over
+    the tile lists, decided on the device, so it gives bit for bit what
+    asking for that walk gives, and the oracle's gradients."""
+    wl = sg.tiny_scene(141, n=30, C=3, W=96, H=80, r_lo=0.3, r_hi=0.9)
+    wl.params = sg.Params(gamma=0.3, eps=1e-5, K=6)
+    sc, cam, par = wl.scene, wl.camera, wl.params
+    _say("[parity] large spheres (up to 11x11 tiles), default vs tile-order backward")
+    fwd = ref.forward(sc, cam, par)
+    G = masked_G(sg.upstream_grad(1411, cam.height, cam.width, sc.C), None, fwd["ambiguous"])
+    g = ref.backward(sc, cam, par, G, fwd)
+    a = gpu_render(sc, cam, par, G)
+    b = gpu_render(sc, cam, par, G, **TILES)
+    assert a["status"] == _capi.PULSAR_OK and b["status"] == _capi.PULSAR_OK
+    assert_close(a["F"], fwd["F"], IMAGE_REL, "large spheres image")
+    compare_grads(a, g, "large spheres")
+    for key in ["grad_pos", "grad_radius", "grad_opacity", "grad_payload", "grad_bg"]:
+        assert np.array_equal(a[key], b[key]), key
+
+
 def test_sphere_and_tile_order_backwards_agree():
     """Both backward walks compute the same per-(pixel, sphere) terms and only
     add them in another order: on the 100k-sphere workload (every pixel) they
