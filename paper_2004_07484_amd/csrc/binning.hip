@@ -448,7 +448,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(uint32_t T, const uint2* 
                                                         uint32_t max_items, Status* status,
                                                         uint4* __restrict__ tinfo,
                                                         uint4* __restrict__ desc,
-                                                        uint32_t* __restrict__ mlist) {
+                                                        uint4* __restrict__ mlist) {
   const uint32_t t = blockIdx.x * kPlanThreads + threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1);
   const bool ok = status->code == 0u;
@@ -464,7 +464,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(uint32_t T, const uint2* 
   if (!fits) atomicMax(&status->code, uint32_t(-PULSAR_ERR_CAPACITY));
   tinfo[t] = make_uint4(sl, fits ? nch : 0u, 0u, 0u);
   if (!fits) return;
-  if (c.nm) mlist[m] = t;
+  if (c.nm) mlist[m] = make_uint4(t, sl, nch, 0u);
   for (uint32_t ci = 0; ci < nch; ++ci) {
     const uint32_t b = tr.x + ci * chunk;
     const uint32_t e = min(tr.y, b + chunk);
@@ -610,7 +610,7 @@ void launch_binning(const Plan& q, char* ws, hipStream_t stream) {
                      dim3(kPlanThreads), 0, stream, uint32_t(q.T), E.trange, uint32_t(q.chunk),
                      (long long)q.pcap, uint32_t(q.max_chunks), status,
                      ws_ptr<uint4>(ws, q.off_tinfo), ws_ptr<uint4>(ws, q.off_desc),
-                     ws_ptr<uint32_t>(ws, q.off_mlist));
+                     ws_ptr<uint4>(ws, q.off_mlist));
   if (q.estop)
     hipLaunchKernelGGL(k_tile_sort, dim3(unsigned(q.T)), dim3(kTileSortThreads), 0, stream,
                        uint32_t(q.T), E.trange, ws_ptr<float>(ws, q.off_tmin), status,

@@ -240,7 +240,7 @@ int make_plan(const std::vector<SceneDev>& sc, int C, const pulsar_params_t* p, 
   q.off_thr = take(thr ? size_t(q.npix) * 16 : 0);
   // early termination: per pixel the first hit it skipped, for the backward
   q.off_stop = take(q.estop ? size_t(q.npix) * 8 : 0);
-  q.off_mlist = take(size_t(q.T) * 4);
+  q.off_mlist = take(size_t(q.T) * 16);
   // the backward kernel instance keeps cm >= C channels, a power of two up to
   // 32; wider payloads keep only dL/dc, dL/dR | dL/do in the record
   int bcm = 1;

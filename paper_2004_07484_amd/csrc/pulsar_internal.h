@@ -149,7 +149,7 @@ struct Plan {
   // block sums of the chunk scan; the partial blend states; the per-pixel
   // K-th nearest hit (t, sphere id); background-gradient block sums
   size_t off_tinfo, off_desc, off_pstate, off_thr, off_bgsum;  // off_thr: [npix] float4
-  size_t off_mlist;  // tiles with several work items, for the merge kernel
+  size_t off_mlist;  // tiles with several work items (tile, first slot, items), for the merge
   size_t off_scenes, off_starts;  // scene table and its start arrays
   // backward: one sum slot per (tile, sphere) pair at its emission position,
   // bwd_ps4 float4 each (dL/dc, dL/dR | dL/df[cm] | dL/do, dL/d(f/s), pixel

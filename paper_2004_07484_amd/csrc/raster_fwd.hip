@@ -101,7 +101,7 @@ struct FwdKernelArgs {
   const uint4* desc;
   uint32_t max_items;  // capacity of the work list (short items fill it from the back)
   const uint4* tinfo;
-  const uint32_t* mlist;
+  const uint4* mlist;  // (tile, first partial slot, work items) of each tile to merge
   const uint32_t* svals;            // sphere index of every sorted pair
   uint32_t last_sph;                 // n - 1: sorted indices are clamped to it
   const float4* rec;                 // sphere records, rec4 float4 per sphere
@@ -282,9 +282,14 @@ __global__ __launch_bounds__(kWave, fwd_waves_per_simd(CM, KM, ES)) void k_fwd_c
 #pragma unroll
   for (int c = 0; c < CM; ++c)
     if (c >= A.cn) s_pay[c][lane] = 0.f;
+  // the block's first work item is requested with the status: full chunks
+  // fill the list from the front, so for the blocks that take them (the
+  // costliest items) slot blockIdx.x is the one
+  const uint4 dsc0 = desc[min(blockIdx.x, A.max_items - 1u)];
   const uint32_t nchunks = item_count(A.status), nfull = A.status->nfull;
   for (uint32_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
-    const uint4 dsc = desc[item_slot(chunk, nfull, A.max_items)];
+    const uint4 dsc =
+        (chunk == blockIdx.x && chunk < nfull) ? dsc0 : desc[item_slot(chunk, nfull, A.max_items)];
     const uint32_t tile = dsc.x & ~kFirstChunk;
     const bool first = (dsc.x & kFirstChunk) != 0u;
     const uint32_t beg = dsc.y, end = dsc.z, slot = dsc.w;
@@ -494,14 +499,18 @@ constexpr long long kMergeGrid = 2048;
 template <int CM, int KM>
 __global__ __launch_bounds__(kWave * kMergeWaves) void k_fwd_merge(
     FwdKernelArgs A, const SceneDev* __restrict__ scenes, const uint32_t* __restrict__ tile_start,
-    const uint4* __restrict__ tinfo, const uint32_t* __restrict__ mlist) {
+    const uint4* __restrict__ tinfo, const uint4* __restrict__ mlist) {
   constexpr int NF = 2 + CM + 2 * KM;  // m, D, numerator[CM], K-list t[KM], id[KM]
   __shared__ float s_state[kMergeWaves - 1][NF][kWave];
   const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+  // the block's first entry is requested with the status (the list holds
+  // T entries, so the read stays inside it whatever the count)
+  const uint4 first = mlist[min(blockIdx.x, A.T - 1u)];
   const uint32_t nmerge = A.status->code == 0u ? A.status->nmerge : 0u;
   for (uint32_t mi = blockIdx.x; mi < nmerge; mi += gridDim.x) {
-    const int tile = int(mlist[mi]);
-    const uint4 ti = tinfo[tile];
+    const uint4 me = mi == blockIdx.x ? first : mlist[mi];
+    const int tile = int(me.x);
+    const uint4 ti = make_uint4(me.y, me.z, 0u, 0u);  // first slot, partial states
     if ((long long)ti.x + ti.y > A.pcap) continue;  // capacity exceeded (reported)
     float m2 = -INFINITY, D = 0.f, N[CM];
     uint64_t kk[KM];
@@ -624,7 +633,7 @@ static FwdKernelArgs raster_args(const Plan& q, const std::vector<SceneDev>& sce
   A.desc = ws_ptr<uint4>(ws, q.off_desc);
   A.max_items = uint32_t(q.max_chunks);
   A.tinfo = ws_ptr<uint4>(ws, q.off_tinfo);
-  A.mlist = ws_ptr<uint32_t>(ws, q.off_mlist);
+  A.mlist = ws_ptr<uint4>(ws, q.off_mlist);
   A.svals = ws_ptr<uint32_t>(ws, q.off_vals);
   A.last_sph = q.n > 0 ? uint32_t(q.n - 1) : 0u;
   A.rec = ws_ptr<float4>(ws, q.off_rec);
