@@ -1520,13 +1520,18 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
   if (store) A.bgsum = nullptr;
   float* bgsum = ws_ptr<float>(ws, q.off_bgsum);
   const uint32_t* counts = ws_ptr<uint32_t>(ws, q.off_counts);
-  stage_begin(PULSAR_STAGE_ZERO, stream);
-  if (wide && a.grad_payload && q.n > 0)
-    hipLaunchKernelGGL(k_bwd_prep, dim3(unsigned((q.n + 255) / 256)), dim3(256), 0, stream,
-                       int(q.n), counts, a.C, a.grad_payload);
-  if (store)
-    hipLaunchKernelGGL(k_zero_slots, dim3(1024), dim3(256), 0, stream, A.status, A.pslot, A.ps4);
-  stage_end(PULSAR_STAGE_ZERO, stream);
+  // clearing before the raster pass (only the wide and stored-hits passes add into memory)
+  const bool prep = wide && a.grad_payload && q.n > 0;
+  if (prep || store) {
+    stage_begin(PULSAR_STAGE_ZERO, stream);
+    if (prep)
+      hipLaunchKernelGGL(k_bwd_prep, dim3(unsigned((q.n + 255) / 256)), dim3(256), 0, stream,
+                         int(q.n), counts, a.C, a.grad_payload);
+    if (store)
+      hipLaunchKernelGGL(k_zero_slots, dim3(1024), dim3(256), 0, stream, A.status, A.pslot,
+                         A.ps4);
+    stage_end(PULSAR_STAGE_ZERO, stream);
+  }
   stage_begin(PULSAR_STAGE_RASTER_BWD, stream);
   if (store) {
     const unsigned hg = unsigned(q.T < q.raster_grid ? q.T : q.raster_grid);

@@ -62,6 +62,15 @@ def test_camera_gradients_tile_order():
     _check(sc, cam, wl.params, "1k spheres, tile order", flags=_capi.PULSAR_BWD_TILES)
 
 
+def test_camera_gradients_large_spheres():
+    """Spheres wider than 16 tiles send the default backward to the tile walk
+    (decided on the device); its camera terms go through the per-pair slots."""
+    wl = sg.tiny_scene(142, n=24, C=3, W=96, H=80, r_lo=0.3, r_hi=0.9)
+    wl.params = sg.Params(gamma=0.3, eps=1e-5, K=6)
+    sc, cam = _rotated(wl, 4)
+    _check(sc, cam, wl.params, "large spheres, tile walk chosen on the device")
+
+
 def test_camera_gradients_identity_pose():
     wl = sg.config1()
     _check(wl.scene, wl.camera, wl.params, "1k spheres, identity pose")
