@@ -401,10 +401,13 @@ const char* pulsar_last_hip_error(void);
 #define PULSAR_STAGE_BINNING 1    /* K2-K5: pair scan, emission, radix sort, tile ranges */
 #define PULSAR_STAGE_RASTER_FWD 2 /* K6: per-tile forward blend (and empty-tile fill) */
 #define PULSAR_STAGE_ZERO 3       /* clearing of the gradient outputs */
-#define PULSAR_STAGE_RASTER_BWD 4 /* K7: per-tile backward with recomputed hits */
+#define PULSAR_STAGE_RASTER_BWD 4 /* K7: backward with recomputed hits (sphere walk, or the
+                                     tile walk when asked for with PULSAR_BWD_TILES) */
 #define PULSAR_STAGE_FINALIZE 5   /* K8: world-space gradients, background sum */
 #define PULSAR_STAGE_MERGE 6      /* K6b: merge of split tiles' partial blends */
-#define PULSAR_NUM_STAGES 7
+#define PULSAR_STAGE_RASTER_BWD_TILES 7 /* K7 tile walk beside the default sphere walk
+                                           (returns at once unless a sphere is very large) */
+#define PULSAR_NUM_STAGES 8
 int pulsar_timing_enable(int on);
 int pulsar_timing_read(double* total_ms, int64_t* counts);
 const char* pulsar_stage_name(int stage);

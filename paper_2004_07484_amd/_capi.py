@@ -33,7 +33,7 @@ EXPORTED = ("pulsar_workspace_size", "pulsar_fwd", "pulsar_bwd", "pulsar_batch_w
             "pulsar_timing_read", "pulsar_stage_name", "pulsar_version", "pulsar_fwd_noalloc",
             "pulsar_fwd_batched_devcam")
 
-PULSAR_NUM_STAGES = 7
+PULSAR_NUM_STAGES = 8
 PULSAR_NO_BWD_AUX = 0x1   # forward keeps no backward state
 PULSAR_REBIN = 0x2        # backward rebuilds its tile lists and thresholds
 PULSAR_GRAD_PAPER_NORM = 0x4  # per-pixel averaged gradients, 3-pixel position gate

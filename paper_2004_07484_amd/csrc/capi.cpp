@@ -595,7 +595,7 @@ int pulsar_timing_read(double* total_ms, int64_t* counts) {
 const char* pulsar_stage_name(int stage) {
   static const char* names[PULSAR_NUM_STAGES] = {"project",    "binning",  "raster_fwd",
                                                  "zero",       "raster_bwd", "finalize",
-                                                 "merge"};
+                                                 "merge",      "raster_bwd_tiles"};
   return (stage >= 0 && stage < PULSAR_NUM_STAGES) ? names[stage] : "unknown";
 }
 

@@ -1603,7 +1603,9 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
     else
       launch_spheres<32>(S, cam, grid, tab.scenes, stream);
     // the tile walk beside it, on a small persistent grid (it returns at once
-    // unless a very large sphere needs it)
+    // unless a very large sphere needs it), timed as a stage of its own
+    stage_end(PULSAR_STAGE_RASTER_BWD, stream);
+    stage_begin(PULSAR_STAGE_RASTER_BWD_TILES, stream);
     BwdKernelArgs Ab = A;
     Ab.only_if_big = 1;
     const long long ig = q.raster_grid / kBwdWaves < kBwdGridAuto ? q.raster_grid / kBwdWaves
@@ -1621,6 +1623,7 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
       launch_items<16>(Ab, igrid, iblock, stream);
     else
       launch_items<32>(Ab, igrid, iblock, stream);
+    stage_end(PULSAR_STAGE_RASTER_BWD_TILES, stream);
   } else {
     // as many waves as the forward's grid of one-wave blocks: blocks past the
     // work items would only be dispatched after them to find nothing to do
@@ -1642,7 +1645,7 @@ hipError_t launch_backward(const Plan& q, const BwdArgs& a, char* ws, hipStream_
       hipLaunchKernelGGL(k_bwd_chunks_wide, dim3(unsigned(q.raster_grid)), dim3(kWave), 0, stream,
                          A, A.tab.scenes, A.tab.tile_start, A.desc);
   }
-  stage_end(PULSAR_STAGE_RASTER_BWD, stream);
+  if (!by_sphere) stage_end(PULSAR_STAGE_RASTER_BWD, stream);
   stage_begin(PULSAR_STAGE_FINALIZE, stream);
   if (a.grad_bg && (wide || store)) {
     if (q.C <= kBgMaxC)
