@@ -37,7 +37,7 @@ from . import _capi
 
 KNOBS: Tuple[Tuple[str, Tuple[int, ...]], ...] = (
     ("raster_blocks", (1024, 2048, 4096, 8192, 16384)),
-    ("chunk", (64, 128, 256, 512)),
+    ("chunk", (64, 128, 192, 256, 320, 512)),
     ("store_hits", (0, 1)),
     ("bwd_tiles", (0, 1)),
 )

@@ -128,8 +128,11 @@ def _cfg4_oracle_rows():
     return _CFG4
 
 
-# the default launch and the benchmark's tuned batch configuration
-@pytest.mark.parametrize("knobs", [{}, dict(chunk=512, raster_blocks=16384),
+# the default launch and the batch configurations the autotuner picks at
+# the largest grid
+@pytest.mark.parametrize("knobs", [{}, dict(chunk=192, raster_blocks=16384),
+                                   dict(chunk=320, raster_blocks=16384),
+                                   dict(chunk=512, raster_blocks=16384),
                                    dict(chunk=64, raster_blocks=4096)])
 def test_batched_default_key_width_and_oracle_rows(knobs):
     """Default depth key width (the batch has other tile numbers, so the key

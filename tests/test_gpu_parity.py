@@ -79,7 +79,8 @@ def _config3_oracle():
 # the default launch and every configuration the autotuner can pick at this
 # workload, the benchmark's among them (knob ranges of autotune.KNOBS)
 @pytest.mark.parametrize("knobs", [
-    {}, dict(chunk=256, raster_blocks=16384), dict(chunk=512, raster_blocks=16384),
+    {}, dict(chunk=192, raster_blocks=16384), dict(chunk=256, raster_blocks=16384),
+    dict(chunk=320, raster_blocks=16384), dict(chunk=512, raster_blocks=16384),
     dict(chunk=64, raster_blocks=1024), dict(chunk=256, raster_blocks=8192)])
 def test_config3_full_size_row_subset(knobs):
     """1M spheres at 1024x1024, C=8, K=8: the benchmark workload, in the
