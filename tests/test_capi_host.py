@@ -348,3 +348,18 @@ def test_noalloc_forward_rejects_what_its_scratch_cannot_hold():
     assert rc == _capi.PULSAR_ERR_INVALID_ARGUMENT
     assert lib.pulsar_fwd_noalloc(FAKE, FAKE, None, FAKE, 10, 3, FAKE, None, ctypes.byref(p),
                                   FAKE, FAKE, None) == _capi.PULSAR_ERR_INVALID_ARGUMENT
+
+
+def test_stage_names_match_the_header():
+    """Every timing stage the header defines has its own name, and the binding
+    reads as many stages as the header declares."""
+    _lib()
+    text = open(HEADER).read()
+    stages = {m[0]: int(m[1]) for m in re.findall(r"#define PULSAR_STAGE_(\w+) (\d+)", text)}
+    n = int(re.search(r"#define PULSAR_NUM_STAGES (\d+)", text).group(1))
+    assert n == _capi.PULSAR_NUM_STAGES
+    assert sorted(stages.values()) == list(range(n))
+    for name, i in stages.items():
+        assert _capi.pulsar_stage_name(i) == name.lower(), (name, i)
+    assert _capi.pulsar_stage_name(n) == "unknown"
+    assert _capi.pulsar_stage_name(-1) == "unknown"
