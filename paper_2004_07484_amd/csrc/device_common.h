@@ -7,14 +7,6 @@
 
 namespace pulsar {
 
-// Broadcast lane `k` (wave-uniform) of v to the whole wave (v_readlane_b32).
-__device__ __forceinline__ float rl(float v, int k) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), k));
-}
-__device__ __forceinline__ uint32_t rlu(uint32_t v, int k) {
-  return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), k));
-}
-
 // Hardware transcendental approximations (about 1 ulp on normal inputs).
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float fast_log2(float x) { return __builtin_amdgcn_logf(x); }

@@ -70,16 +70,6 @@ struct SphereRec {
   float xl, yl, kl, axl, ayl;  // low parts
 };
 
-// Cheap FP32 rejection. Returns r2 (only meaningful when < kRejectR2).
-__device__ __forceinline__ float coarse_r2(const PixelRay& ray, int x0, int y0, float xh,
-                                           float yh, float kh, float axh, float ayh) {
-#pragma clang fp contract(off)
-  const float dx = float(ray.px - x0) - xh;
-  const float dy = float(ray.py - y0) - yh;
-  const float cr = axh * dy - ayh * dx;
-  return kh * (dx * dx + dy * dy + cr * cr) * ray.inv_v2;
-}
-
 struct Hit {
   float e;      // 1 - q^2/R^2, accurate to FP64 rounding
   float delta;  // 1 - q/R
