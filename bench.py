@@ -335,12 +335,13 @@ def stage_bytes(n: int, H: int, W: int, C: int, pairs: int, by_sphere: bool = Tr
                   (split tiles' pixels are written by the merge, counted here)
       merge       none beyond the forward's (intermediate partial blends)
       raster_bwd  read G, F and L and the payload rows: HW (8C + 4) + n 4C;
-                  in sphere order it also writes every sphere gradient,
-                  n 4 (C + 5)
-      finalize    the background gradient 4C, and in tile order every sphere
-                  gradient n 4 (C + 5)"""
+                  in sphere order it also re-reads the scene for the chain
+                  rule, n 20, and writes every sphere gradient, n 4 (C + 5)
+      finalize    the background gradient 4C, and in tile order the scene
+                  re-read and every sphere gradient, n 20 + n 4 (C + 5)
+    The stages add up to io_bytes() plus the tile lists."""
     T = ((W + 7) // 8) * ((H + 7) // 8)
-    grads = 4 * (C + 5) * n
+    grads = 20 * n + 4 * (C + 5) * n  # the scene re-read and every gradient
     return {"project": 20 * n, "binning": 4 * pairs + 4 * (T + 1),
             "raster_fwd": 4 * C * n + H * W * (4 * C + 4), "merge": 0,
             "raster_bwd": H * W * (8 * C + 4) + 4 * C * n + (grads if by_sphere else 0),
