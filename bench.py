@@ -483,7 +483,19 @@ def bench_batch(args, dev) -> dict:
     code, pairs = _capi.pulsar_query_status(ws, stream)
     assert code == _capi.PULSAR_OK, "batched tile-pair capacity"
     knobs = None
-    if not args.no_tune:
+    if args.batch_knobs:
+        from paper_2004_07484_amd import autotune as at
+        for k, v in parse_knobs(args.batch_knobs):
+            at.set_knob(ps, k, v)
+        ws = torch.empty(_capi.pulsar_batch_workspace_size(scenes, C, ps), dtype=torch.uint8,
+                         device=dev)
+        knobs = at.knobs_of(ps)
+        log(f"[batch] fixed knobs {knobs}")
+        ws1 = torch.empty(max(_capi.pulsar_workspace_size(w.scene.n, w.camera.width,
+                                                          w.camera.height, C, ps) for w in wls),
+                          dtype=torch.uint8, device=dev)
+        batched(stream)
+    elif not args.no_tune:
         from paper_2004_07484_amd import autotune as at
         wss = {}
 
@@ -529,6 +541,20 @@ def bench_batch(args, dev) -> dict:
     return out
 
 
+KNOB_NAMES = ("raster_blocks", "chunk", "store_hits", "bwd_tiles")
+
+
+def parse_knobs(text: str):
+    """[(knob, value)] from "k=v,k=v" (launch knobs only)."""
+    out = []
+    for kv in text.split(","):
+        k, v = kv.split("=")
+        if k not in KNOB_NAMES:
+            raise SystemExit(f"unknown knob {k}")
+        out.append((k, int(v)))
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -551,6 +577,11 @@ def main() -> int:
     ap.add_argument("--knobs", default="", metavar="K=V,...",
                     help="fixed launch knobs for the single-scene workload, e.g. "
                          "raster_blocks=4096,chunk=128 (implies no tuning)")
+    ap.add_argument("--batch-knobs", default="", metavar="K=V,...",
+                    help="fixed launch knobs for the 32-scene batch (implies no tuning there)")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="only run the batched-vs-looped measurement and print its JSON object "
+                         "(for profiling the batch on its own; not the bench line)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (5 times) and exit; "
                          "calibrates the FETCH_SIZE / WRITE_SIZE counters")
@@ -579,6 +610,9 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     dev = torch.device("cuda:0")
+    if args.only_batch:
+        print(json.dumps(bench_batch(args, dev)), flush=True)
+        return 0
     log(f"[bench] generating workload ({args.spheres} spheres)")
     wl = sg.config3(args.spheres)
     sc, cam, par = wl.scene, wl.camera, wl.params
@@ -619,12 +653,9 @@ def main() -> int:
         assert code == _capi.PULSAR_OK
     tune_info = None
     if args.knobs:
-        for kv in args.knobs.split(","):
-            k, v = kv.split("=")
-            if k not in ("raster_blocks", "chunk", "store_hits", "bwd_tiles"):
-                raise SystemExit(f"unknown knob {k}")
-            from paper_2004_07484_amd import autotune as at
-            at.set_knob(ps, k, int(v))
+        from paper_2004_07484_amd import autotune as at
+        for k, v in parse_knobs(args.knobs):
+            at.set_knob(ps, k, v)
         ws = torch.empty(_capi.pulsar_workspace_size(n, W, H, C, ps), dtype=torch.uint8,
                          device=dev)
         step()
