@@ -60,10 +60,11 @@ def sources_hash(kernel: str) -> str:
                                    for p in TRAFFIC_SOURCES[kernel])).hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per dispatch from the committed rocprofv3 summary (FETCH_SIZE
-    and WRITE_SIZE scaled by the copy calibration), or None when the summary
-    is missing or the kernel's sources changed since it was taken."""
+def measured_record(kernel: str, workload: str):
+    """The kernel's record in the committed rocprofv3 summary (HBM bytes per
+    dispatch from FETCH_SIZE and WRITE_SIZE scaled by the copy calibration,
+    and its VALU-active share of wave cycles), or None when the summary is
+    missing or the kernel's sources changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"{workload}.md")
     if kernel not in TRAFFIC_SOURCES or not os.path.exists(path):
         return None
@@ -73,9 +74,25 @@ def measured_traffic(kernel: str, workload: str):
             r = json.loads(line.strip()[len("TRAFFIC "):])
             if r.get("kernel") == kernel:
                 rec = r
-    if rec is None:
+    if rec is None or sources_hash(kernel) != rec.get("sources_sha256_16"):
         return None
-    return int(rec["bytes"]) if sources_hash(kernel) == rec.get("sources_sha256_16") else None
+    return rec
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per dispatch from the committed rocprofv3 summary, or None."""
+    rec = measured_record(kernel, workload)
+    return None if rec is None else int(rec["bytes"])
+
+
+def binning_launches(T: int) -> dict:
+    """Launches of each binning kernel for T tiles: the emission, then LSD
+    passes of at most 8-bit digits (a histogram before every pass but the
+    first), the tile ranges and the work items."""
+    bits = max(0, (T - 1).bit_length())
+    passes = (bits + 7) // 8
+    return {"k_emit": 1, "k_sort_scatter": passes, "k_sort_hist": max(0, passes - 1),
+            "k_ranges": 1, "k_plan": 1}
 
 
 def cpu_baseline(wl, G, rows_n: int):
@@ -354,6 +371,7 @@ def stage_roofline(stage_avg: dict, n, H, W, C, pairs, workload, by_sphere: bool
     for every stage."""
     sb = stage_bytes(n, H, W, C, pairs, by_sphere)
     names = stage_kernels(by_sphere)
+    T = ((W + 7) // 8) * ((H + 7) // 8)
     kernels = {}
     for st, nbytes in sb.items():
         ms = stage_avg.get(st, 0.0)
@@ -362,6 +380,21 @@ def stage_roofline(stage_avg: dict, n, H, W, C, pairs, workload, by_sphere: bool
                        "achieved_GBs": round(nbytes / (ms * 1e-3) / 1e9, 1) if ms > 0 else None,
                        "frac": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
                        if ms > 0 else None}
+        # counter traffic (over the compulsory bytes) and VALU-active share
+        # from the committed profile of this workload, while it is current
+        if st == "binning":
+            recs = [(measured_record(k, workload), c) for k, c in binning_launches(T).items()]
+            traffic = (sum(int(r["bytes"]) * c for r, c in recs)
+                       if all(r is not None for r, _ in recs) else None)
+            valu = None
+        else:
+            rec = measured_record(names[st], workload)
+            traffic = None if rec is None else int(rec["bytes"])
+            valu = None if rec is None else rec.get("valu_active")
+        kernels[st]["traffic"] = traffic
+        kernels[st]["traffic_ratio"] = (round(traffic / nbytes, 3)
+                                        if traffic is not None and nbytes > 0 else None)
+        kernels[st]["valu_active"] = valu
     # the dominant kernel: the longest stage that is a single kernel, so its
     # average duration can be checked against the rocprofv3 kernel trace
     # (binning is six kernels; its own figures are in `kernels` and in

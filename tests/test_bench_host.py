@@ -57,13 +57,26 @@ def _fake_profile(tmp_path, monkeypatch, kernel, nbytes, digest):
         p.parent.mkdir(parents=True, exist_ok=True)
         p.write_text(f"source of {rel}\n")
     (tmp_path / "profiles").mkdir()
-    rec = {"kernel": kernel, "bytes": nbytes, "sources_sha256_16": digest or bench.sources_hash(kernel)}
+    rec = {"kernel": kernel, "bytes": nbytes, "sources_sha256_16": digest or bench.sources_hash(kernel),
+           "valu_active": 0.25}
     (tmp_path / "profiles" / "wl.md").write_text("# summary\n\n    TRAFFIC " + json.dumps(rec) + "\n")
 
 
 def test_traffic_is_reported_while_the_sources_match(tmp_path, monkeypatch):
     _fake_profile(tmp_path, monkeypatch, "k_bwd_spheres", 123456, None)
     assert bench.measured_traffic("k_bwd_spheres", "wl") == 123456
+    assert bench.measured_record("k_bwd_spheres", "wl")["valu_active"] == 0.25
+    # the stage of that kernel carries the traffic, its ratio to the
+    # compulsory bytes and the VALU share
+    n, H, W, C = 1000, 64, 64, 3
+    avg = {"project": 0.01, "binning": 0.01, "raster_fwd": 0.01, "merge": 0.01,
+           "raster_bwd": 0.02, "finalize": 0.01}
+    _, kernels = bench.stage_roofline(avg, n, H, W, C, 500, "wl")
+    k = kernels["raster_bwd"]
+    assert k["traffic"] == 123456 and k["valu_active"] == 0.25
+    assert k["traffic_ratio"] == pytest.approx(123456 / k["bytes_per_launch"], rel=1e-3)
+    assert kernels["raster_fwd"]["traffic"] is None  # no record for it
+    assert kernels["binning"]["traffic"] is None  # its kernels have none
     assert bench.measured_traffic("k_fwd_chunks", "wl") is None  # no record for it
     assert bench.measured_traffic("k_bwd_spheres", "other") is None  # no summary
     assert bench.measured_traffic("no_such_kernel", "wl") is None
@@ -71,6 +84,18 @@ def test_traffic_is_reported_while_the_sources_match(tmp_path, monkeypatch):
     first = bench.TRAFFIC_SOURCES["k_bwd_spheres"][0]
     (tmp_path / first).write_text("changed\n")
     assert bench.measured_traffic("k_bwd_spheres", "wl") is None
+
+
+def test_binning_launch_counts_follow_the_tile_bits():
+    # a single tile: nothing to sort; 2^14 tiles: two 7-bit passes; the
+    # 32-scene batch's 258,048 tiles: three 6-bit passes
+    assert bench.binning_launches(1)["k_sort_scatter"] == 0
+    one = bench.binning_launches(256)
+    assert (one["k_sort_scatter"], one["k_sort_hist"]) == (1, 0)
+    two = bench.binning_launches(16384)
+    assert (two["k_sort_scatter"], two["k_sort_hist"]) == (2, 1)
+    assert bench.binning_launches(258048)["k_sort_scatter"] == 3
+    assert all(two[k] == 1 for k in ("k_emit", "k_ranges", "k_plan"))
 
 
 def test_more_than_one_gpu_is_refused():
